@@ -1,0 +1,334 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: the generator's independent
+coding of the visibility model (Section 2), closed forms (the Z least squares of Section 3, the
+sufficient-statistics expansion of the cost), finite differences of the oracle's own objective,
+textbook library routines (Cholesky, least squares, SVD polar factor, SciPy's trust-region least
+squares), invariances (the unitary ambiguity of Section 3) and the special cases the method has
+(noise-free data, truth inside the basis span, rho = 0 = normal calibration).
+"""
+import numpy as np
+import pytest
+
+from conftest import rand_jones, tiny_cfg
+
+
+def _unitary(rng):
+    A = rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2))
+    Q, R = np.linalg.qr(A)
+    return Q * (np.diag(R) / np.abs(np.diag(R)))
+
+
+def _noise_pair(synth, cfg):
+    """Same seed with and without noise: everything but the noise draws is identical."""
+    import dataclasses
+    clean = synth.generate(dataclasses.replace(cfg, snr=None), seed=12345)
+    noisy = synth.generate(cfg, seed=12345)
+    return clean, noisy
+
+
+def test_predict_matches_generator_model(oracle_mod, synth_mod):
+    cfg = tiny_cfg(synth_mod, N=6, P=3, K=3, snr=None)
+    d = synth_mod.generate(cfg)
+    pb = oracle_mod.Problem(d)
+    model = pb.predict(d["jones_true"])
+    assert np.max(np.abs(model - d["vis"])) <= 1e-13 * np.max(np.abs(d["vis"]))
+
+
+def test_cost_zero_noise_free_and_noise_energy(oracle_mod, synth_mod):
+    cfg = tiny_cfg(synth_mod, N=6, P=3, K=2)
+    clean, noisy = _noise_pair(synth_mod, cfg)
+    g0 = oracle_mod.Problem(clean).subband_cost(clean["jones_true"])
+    assert np.all(g0 <= 1e-24 * np.sum(np.abs(clean["vis"]) ** 2))
+    g = oracle_mod.Problem(noisy).subband_cost(noisy["jones_true"])
+    noise = (noisy["vis"] - clean["vis"]).reshape(-1, 4)
+    off = noisy["vis_off"]
+    energy = [np.sum(np.abs(noise[off[f]:off[f + 1]]) ** 2) for f in range(cfg.P)]
+    np.testing.assert_allclose(g, energy, rtol=1e-12)
+
+
+def test_cost_gauge_invariance(oracle_mod, synth_mod):
+    rng = np.random.default_rng(1)
+    cfg = tiny_cfg(synth_mod, N=5, P=3, K=2)
+    d = synth_mod.generate(cfg)
+    pb = oracle_mod.Problem(d)
+    J = rand_jones(rng, cfg.P, cfg.K, cfg.N)
+    JU = J.copy()
+    for f in range(cfg.P):
+        for k in range(cfg.K):
+            JU[f, k] = J[f, k] @ _unitary(rng)
+    np.testing.assert_allclose(pb.subband_cost(JU), pb.subband_cost(J), rtol=1e-13)
+
+
+def test_cost_sufficient_statistics_identity(oracle_mod, synth_mod):
+    """For one direction, sum_s ||V - c M||^2 = E_b - 2 Re tr(M^H D_b) + S_b ||M||^2 per baseline,
+    with E_b = sum ||V||^2, D_b = sum conj(c) V, S_b = sum |c|^2 (C = c I2, J time invariant)."""
+    rng = np.random.default_rng(2)
+    cfg = tiny_cfg(synth_mod, N=6, P=2, K=1, n_chan=3)
+    d = synth_mod.generate(cfg)
+    pb = oracle_mod.Problem(d)
+    J = rand_jones(rng, cfg.P, 1, cfg.N)
+    g = pb.subband_cost(J)
+    p, q = synth_mod.baseline_pairs(cfg.N)
+    spb = cfg.T * 3
+    for f in range(cfg.P):
+        V = d["vis"][d["vis_off"][f]:d["vis_off"][f + 1]].reshape(cfg.B, spb, 2, 2)
+        c = d["coh"][d["coh_off"][f]:d["coh_off"][f + 1]].reshape(cfg.B, spb)
+        M = J[f, 0, p] @ np.conj(np.swapaxes(J[f, 0, q], -1, -2))
+        E = np.sum(np.abs(V) ** 2, axis=(1, 2, 3))
+        D = np.einsum("bs,bsij->bij", np.conj(c), V)
+        S = np.sum(np.abs(c) ** 2, axis=1)
+        ref = np.sum(E - 2 * np.real(np.einsum("bij,bij->b", np.conj(M), D))
+                     + S * np.sum(np.abs(M) ** 2, axis=(1, 2)))
+        assert abs(g[f] - ref) <= 1e-11 * abs(ref)
+
+
+def test_gradient_finite_differences(oracle_mod, synth_mod):
+    rng = np.random.default_rng(3)
+    cfg = tiny_cfg(synth_mod, N=4, P=2, K=2, rho=3.0)
+    d = synth_mod.generate(cfg)
+    pb = oracle_mod.Problem(d)
+    J = rand_jones(rng, cfg.P, cfg.K, cfg.N)
+    Y = 0.3 * (rng.normal(size=J.shape) + 1j * rng.normal(size=J.shape))
+    BZ = rand_jones(rng, cfg.P, cfg.K, cfg.N)
+    f, k = 1, 1
+    L0, G = pb.dir_objective(J, Y, BZ, f, k)
+    h = 1e-5
+    fd = np.zeros(8 * cfg.N)
+    for i in range(4 * cfg.N):
+        for ri, step in enumerate((h, 1j * h)):
+            Jp = J[f, k].copy().reshape(-1)
+            Jm = Jp.copy()
+            Jp[i] += step
+            Jm[i] -= step
+            fd[2 * i + ri] = (pb.dir_objective(J, Y, BZ, f, k, Jp.reshape(cfg.N, 2, 2), grad=False)
+                              - pb.dir_objective(J, Y, BZ, f, k, Jm.reshape(cfg.N, 2, 2), grad=False)) / (2 * h)
+    g = np.stack([G.reshape(-1).real, G.reshape(-1).imag], axis=1).reshape(-1)
+    assert np.linalg.norm(g - fd) <= 1e-7 * np.linalg.norm(fd)
+
+
+def _fd_jacobian(pb, d, J, f, h=1e-6):
+    """Central-difference Jacobian of the real/imag parts of the model of subband f with respect to
+    the real parameters of direction 0 (one direction, so model = c J_p J_q^H)."""
+    N = J.shape[2]
+    o0, o1 = d["vis_off"][f], d["vis_off"][f + 1]
+    cols = []
+    for i in range(4 * N):
+        for step in (h, 1j * h):
+            Jp, Jm = J.copy(), J.copy()
+            Jp[f, 0].reshape(-1)[i] += step
+            Jm[f, 0].reshape(-1)[i] -= step
+            dm = (pb.predict(Jp)[o0:o1] - pb.predict(Jm)[o0:o1]).reshape(-1) / (2 * h)
+            cols.append(np.concatenate([dm.real, dm.imag]))
+    return np.stack(cols, axis=1)
+
+
+def test_gauss_newton_matches_fd_jacobian(oracle_mod, synth_mod):
+    rng = np.random.default_rng(4)
+    cfg = tiny_cfg(synth_mod, N=4, P=2, K=1)
+    d = synth_mod.generate(cfg)
+    pb = oracle_mod.Problem(d)
+    J = rand_jones(rng, cfg.P, 1, cfg.N)
+    f = 1
+    Jac = _fd_jacobian(pb, d, J, f)
+    H = pb.dir_gn_hessian(f, 0, J[f, 0])
+    ref = 2 * Jac.T @ Jac
+    assert np.linalg.norm(H - ref) <= 1e-8 * np.linalg.norm(ref)
+    # the unitary ambiguity leaves a 4-dimensional null space
+    ev = np.linalg.eigvalsh(H)
+    assert np.sum(ev < 1e-9 * ev[-1]) == 4
+
+
+def test_full_hessian_equals_gn_at_zero_residual(oracle_mod, synth_mod):
+    cfg = tiny_cfg(synth_mod, N=4, P=2, K=1, snr=None, rho=0.0)
+    d = synth_mod.generate(cfg)
+    pb = oracle_mod.Problem(d, rho=np.zeros(1))
+    J = d["jones_true"].copy()
+    Y = np.zeros_like(J)
+    f = 0
+    H = pb.dir_gn_hessian(f, 0, J[f, 0])
+    h = 1e-6
+    n = 8 * cfg.N
+    Hfd = np.zeros((n, n))
+    for i in range(4 * cfg.N):
+        for ri, step in enumerate((h, 1j * h)):
+            Jp, Jm = J[f, 0].copy().reshape(-1), J[f, 0].copy().reshape(-1)
+            Jp[i] += step
+            Jm[i] -= step
+            gp = pb.dir_objective(J, Y, Y, f, 0, Jp.reshape(-1, 2, 2))[1].reshape(-1)
+            gm = pb.dir_objective(J, Y, Y, f, 0, Jm.reshape(-1, 2, 2))[1].reshape(-1)
+            dg = (gp - gm) / (2 * h)
+            Hfd[:, 2 * i + ri] = np.stack([dg.real, dg.imag], axis=1).reshape(-1)
+    assert np.linalg.norm(H - Hfd) <= 1e-6 * np.linalg.norm(H)
+
+
+def test_textbook_helpers(oracle_mod):
+    rng = np.random.default_rng(5)
+    A = rng.normal(size=(30, 30))
+    A = A @ A.T + 30 * np.eye(30)
+    np.testing.assert_allclose(oracle_mod.cholesky(A), np.linalg.cholesky(A), rtol=1e-12, atol=1e-12)
+    assert oracle_mod.cholesky(-np.eye(3)) is None
+    M = rng.normal(size=(9, 4))
+    X = rng.normal(size=(9, 5)) + 1j * rng.normal(size=(9, 5))
+    np.testing.assert_allclose(oracle_mod.lstsq(M, X), np.linalg.lstsq(M, X, rcond=None)[0],
+                               rtol=1e-12, atol=1e-12)
+    assert oracle_mod.lstsq(np.ones((5, 2)), X[:5]) is None
+    for _ in range(20):
+        B = rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2))
+        W, s, Vh = np.linalg.svd(B)
+        np.testing.assert_allclose(oracle_mod.polar2(B), W @ Vh, atol=1e-13)
+
+
+def _vander(d, Q, fsel=None):
+    x = (np.asarray(d["freq"]) - d["f0"]) / d["f0"]
+    if fsel is not None:
+        x = x[fsel]
+    return np.vander(x, Q, increasing=True)
+
+
+def test_z_update_closed_form_and_invariants(oracle_mod, synth_mod):
+    rng = np.random.default_rng(6)
+    cfg = tiny_cfg(synth_mod, N=3, P=6, Q=3, K=2, rho=2.5)
+    d = synth_mod.generate(cfg)
+    pb = oracle_mod.Problem(d)
+    J = rand_jones(rng, cfg.P, cfg.K, cfg.N)
+    Y0 = 0.1 * (rng.normal(size=J.shape) + 1j * rng.normal(size=J.shape))
+    Zold = np.zeros(pb.zshape(), np.complex128)
+    Y, Z, BZ, pr, du = pb.consensus(J, Y0, Zold)
+    Bv = _vander(d, cfg.Q)
+    rho = 2.5
+    for k in range(cfg.K):
+        # the paper's closed form: Z = (1/rho) ((sum b b^T)^+ kron I) sum_f b_f kron (Y_f + rho J_f)
+        R = np.einsum("fl,fx->lx", Bv, (Y0[:, k] + rho * J[:, k]).reshape(cfg.P, -1))
+        Zref = (np.linalg.pinv(Bv.T @ Bv) @ R) / rho
+        np.testing.assert_allclose(Z[k].reshape(cfg.Q, -1), Zref, rtol=1e-10, atol=1e-12)
+        # stationarity of M2: sum_f b_f (-Y_f - rho (J_f - B_f Z)) = 0
+        grad = np.einsum("fl,fx->lx", Bv, (-Y0[:, k] - rho * (J[:, k] - BZ[:, k])).reshape(cfg.P, -1))
+        assert np.max(np.abs(grad)) < 1e-12 * np.max(np.abs(R))
+        # after the dual update the multipliers are orthogonal to the basis
+        inv = np.einsum("fl,fx->lx", Bv, Y[:, k].reshape(cfg.P, -1))
+        assert np.max(np.abs(inv)) < 1e-12 * (1 + np.max(np.abs(Y)))
+    # residual definitions of Section 4
+    ref_pr = np.mean([np.linalg.norm(J[f, k] - BZ[f, k]) / np.sqrt(4 * cfg.N)
+                      for f in range(cfg.P) for k in range(cfg.K)])
+    assert abs(pr - ref_pr) < 1e-12
+    ref_du = np.mean([np.linalg.norm(Z[k]) / np.sqrt(4 * cfg.Q * cfg.N) for k in range(cfg.K)])
+    assert abs(du - ref_du) < 1e-12
+
+
+def test_rank_condition(oracle_mod, synth_mod):
+    cfg = tiny_cfg(synth_mod, N=3, P=2, Q=3, K=1)
+    d = synth_mod.generate(cfg)
+    pb = oracle_mod.Problem(d)
+    J = synth_mod.identity_jones(2, 1, 3)
+    with pytest.raises(ValueError):
+        pb.consensus(J, np.zeros_like(J), np.zeros(pb.zshape(), np.complex128))
+
+
+def test_truth_in_span_is_fixed_point(oracle_mod, synth_mod):
+    cfg = tiny_cfg(synth_mod, N=6, P=5, Q=3, K=2, snr=None, lm_iters=5)
+    d = synth_mod.generate(cfg, truth_in_span=True)
+    pb = oracle_mod.Problem(d)
+    Jt = d["jones_true"]
+    Y = np.zeros_like(Jt)
+    J1 = pb.local_step(Jt, Y, Jt)
+    assert np.max(np.abs(J1 - Jt)) < 1e-10
+    Y1, Z, BZ, pr, du = pb.consensus(J1, Y, np.zeros(pb.zshape(), np.complex128))
+    assert pr < 1e-12 and np.max(np.abs(Y1)) < 1e-10
+    np.testing.assert_allclose(BZ, Jt, atol=1e-12)
+
+
+def test_admm_noise_free_reaches_zero_cost(oracle_mod, synth_mod):
+    cfg = tiny_cfg(synth_mod, N=6, P=5, Q=3, K=2, snr=None, lm_iters=10)
+    d = synth_mod.generate(cfg, truth_in_span=True)
+    pb = oracle_mod.Problem(d)
+    out = pb.admm_solve(synth_mod.identity_jones(cfg.P, cfg.K, cfg.N), 12)
+    tr = out["trace"]
+    # the consensus penalty keeps a small per-subband gauge mismatch, so the data cost falls by
+    # five to six orders of magnitude rather than to rounding level within a dozen iterations
+    assert tr[-1, 0] < 1e-4 * tr[0, 0]
+    assert tr[-1, 2] < 2e-2 * tr[0, 2]
+
+
+def test_rho_zero_is_normal_calibration(oracle_mod, synth_mod):
+    cfg = tiny_cfg(synth_mod, N=5, P=4, Q=2, K=2, rho=0.0, lm_iters=6)
+    d = synth_mod.generate(cfg)
+    pb = oracle_mod.Problem(d, options=0)
+    J0 = synth_mod.identity_jones(cfg.P, cfg.K, cfg.N)
+    out = pb.admm_solve(J0, 3)
+    J = J0.copy()
+    zero = np.zeros_like(J0)
+    for _ in range(3):
+        J = pb.local_step(J, zero, zero)
+    np.testing.assert_allclose(out["J"], J, rtol=0, atol=1e-13)
+    assert np.max(np.abs(out["Y"])) == 0.0
+
+
+def test_lm_converges_noise_free(oracle_mod, synth_mod):
+    cfg = tiny_cfg(synth_mod, N=5, P=1, Q=1, K=1, snr=None, rho=0.0, lm_iters=30)
+    d = synth_mod.generate(cfg)
+    pb = oracle_mod.Problem(d, rho=np.zeros(1))
+    rng = np.random.default_rng(7)
+    J0 = d["jones_true"] + 0.05 * (rng.normal(size=d["jones_true"].shape)
+                                   + 1j * rng.normal(size=d["jones_true"].shape))
+    z = np.zeros_like(J0)
+    J, tr = pb.local_step(J0, z, z, trace=True)
+    g0 = pb.subband_cost(J0)[0]
+    assert pb.subband_cost(J)[0] < 1e-20 * g0
+    objective = tr[0, 0, 0, :, 0]
+    assert np.all(np.diff(objective) <= 0)
+
+
+def test_lm_matches_scipy_least_squares(oracle_mod, synth_mod):
+    scipy_opt = pytest.importorskip("scipy.optimize")
+    cfg = tiny_cfg(synth_mod, N=4, P=1, Q=1, K=1, rho=0.0, lm_iters=60)
+    d = synth_mod.generate(cfg)
+    pb = oracle_mod.Problem(d, rho=np.zeros(1))
+    J0 = synth_mod.identity_jones(1, 1, cfg.N)
+    z = np.zeros_like(J0)
+    J = pb.local_step(J0, z, z)
+    V = d["vis"].reshape(-1)
+
+    def resid(theta):
+        Jt = (theta[0::2] + 1j * theta[1::2]).reshape(1, 1, cfg.N, 2, 2)
+        r = V - pb.predict(Jt).reshape(-1)
+        return np.concatenate([r.real, r.imag])
+
+    th0 = np.stack([J0.reshape(-1).real, J0.reshape(-1).imag], 1).reshape(-1)
+    sol = scipy_opt.least_squares(resid, th0, xtol=1e-15, ftol=1e-15, gtol=1e-15, max_nfev=2000)
+    ref = np.sum(sol.fun ** 2)
+    assert abs(pb.subband_cost(J)[0] - ref) <= 1e-9 * ref
+
+
+def test_gpa_alignment(oracle_mod, synth_mod):
+    rng = np.random.default_rng(8)
+    cfg = tiny_cfg(synth_mod, N=5, P=5, K=1)
+    d = synth_mod.generate(cfg)
+    pb = oracle_mod.Problem(d)
+    base = rand_jones(rng, 1, 1, cfg.N)[0, 0]
+    J = np.zeros((cfg.P, 1, cfg.N, 2, 2), np.complex128)
+    for f in range(cfg.P):
+        J[f, 0] = (base + 0.01 * rng.normal(size=base.shape)) @ _unitary(rng)
+    Ja = pb.gpa(J, rounds=3)
+    np.testing.assert_allclose(pb.subband_cost(Ja), pb.subband_cost(J), rtol=1e-12)
+    spread_before = np.mean([np.linalg.norm(J[f, 0] - J[0, 0]) for f in range(cfg.P)])
+    spread_after = np.mean([np.linalg.norm(Ja[f, 0] - Ja[0, 0]) for f in range(cfg.P)])
+    assert spread_after < 0.1 * spread_before
+    # Procrustes optimality: J_f^H mean is Hermitian positive semi-definite after alignment
+    mean = Ja[:, 0].mean(axis=0)
+    for f in range(cfg.P):
+        A = np.einsum("pji,pjk->ik", np.conj(Ja[f, 0]), mean)
+        np.testing.assert_allclose(A, A.conj().T, atol=1e-3 * np.abs(A).max())
+
+
+def test_admm_trends_with_rho(oracle_mod, synth_mod):
+    """Section 4.1 trends: the primal residual falls with iterations and is lower for larger rho."""
+    cfg = tiny_cfg(synth_mod, N=8, P=6, Q=3, K=1, T=4, n_chan=1, lm_iters=6)
+    d = synth_mod.generate(cfg)
+    J0 = synth_mod.identity_jones(cfg.P, 1, cfg.N)
+    res = {}
+    for rho in (0.5, 50.0):
+        pb = oracle_mod.Problem(d, rho=np.array([rho]))
+        res[rho] = pb.admm_solve(J0, 15)["trace"]
+    assert res[50.0][-1, 2] < res[50.0][1, 2]
+    assert res[50.0][-1, 2] < res[0.5][-1, 2]
