@@ -1,0 +1,161 @@
+/* calib.h - C ABI of the MI355X consensus-ADMM calibration library.
+ *
+ * The library solves the distributed calibration problem of Yatawatta (2015), "Distributed
+ * radio interferometric calibration": for every subband f (one compute agent of the paper) and
+ * direction k it estimates 2x2 complex Jones matrices J_fkp of N stations such that the model
+ * visibilities sum_k J_fkp C_fkpq J_fkq^H (Section 2, visibility model) fit the observed
+ * V_fpq in least squares (Section 2, cost), while the Jones matrices of all subbands are tied
+ * to a polynomial in frequency J_fk = B_f Z_k (Section 3, smoothness constraint) by consensus
+ * ADMM (Section 3, minimisations M1-M3 and steps D1-D3).  All subbands live on one GPU; the
+ * paper's network exchange becomes a device-wide reduction over subbands.
+ *
+ * Local step (M1): per direction a SAGE expectation (Section 3) and a Levenberg-Marquardt
+ * minimisation of the augmented Lagrangian
+ *     L_fk(J) = sum ||V_fk - c J_p J_q^H||^2 + Re tr(Y_fk^H (J - B_f Z_k)) + rho_k/2 ||J - B_f Z_k||^2
+ * (the linear term in the trace form of Appendix A).  The paper minimises M1 with a Riemannian
+ * trust region; this library uses Levenberg-Marquardt with Nielsen's damping rule on the
+ * Gauss-Newton normal equations, solved by a batched FP64 Cholesky factorisation.
+ *
+ * Data conventions
+ *   - Baselines b enumerate station pairs p<q row-major (no autocorrelations); 2x2 matrices are
+ *     row-major complex, interleaved (re, im).
+ *   - Visibilities: per subband, sample s = (b*T + t)*n_chan[f] + ch; vis holds
+ *     sum_f B*T*n_chan[f] samples of 2x2 complex (8 reals).
+ *   - Coherencies: the paper's C = c * I2 for an unpolarised point source (Section 2), so one
+ *     complex scalar per sample and direction; per subband laid out [k][b][t][ch] for
+ *     k < n_dirs[f]; coh holds sum_f n_dirs[f]*B*T*n_chan[f] complex scalars.
+ *   - Element type of vis/coh: double for CALIB_FP64, float for CALIB_FP32_MIXED.  J, Z, Y and
+ *     B_f Z are always double complex: J/Y/BZ [P][K][N][2][2], Z [K][Q][N][2][2] (monomial basis
+ *     b_l(f) = ((f - f0)/f0)^(l-1), Section 3).
+ *   - Flags: one byte per (subband, baseline), 1 = baseline flagged in that subband; flagged
+ *     baselines are excluded from every sum and never read after calib_init.
+ *
+ * Ownership and execution
+ *   - Pointers marked "device" are GPU memory owned by the caller; calib_init copies and repacks
+ *     them, so the caller may release them once the stream has synchronised.  Pointers marked
+ *     "host" are read during the call only.
+ *   - All work is enqueued on the stream given to calib_init (a hipStream_t, NULL = default
+ *     stream).  Entry points return once the work is enqueued, except where stated.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *
+ * Errors: every entry point returns a calib_status; nothing aborts or throws across the ABI.
+ * calib_last_error gives a message for the last failure of a context (or of calib_init, with a
+ * NULL context).
+ */
+#ifndef CALIB_MI355X_H
+#define CALIB_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct calib_ctx calib_ctx;
+
+typedef enum {
+  CALIB_OK = 0,
+  CALIB_E_INVAL = 1,    /* bad argument or configuration                                      */
+  CALIB_E_NOMEM = 2,    /* device allocation failed                                           */
+  CALIB_E_DEVICE = 3,   /* a HIP call failed                                                  */
+  CALIB_E_RANK = 4,     /* fewer than Q distinct subband frequencies carry a direction (the
+                           rank condition P >= F of the Z update, Section 3)                  */
+  CALIB_E_NUMERIC = 5,  /* non-finite values in the inputs                                     */
+  CALIB_E_STATE = 6     /* entry point called out of order                                    */
+} calib_status;
+
+typedef enum { CALIB_FP64 = 0, CALIB_FP32_MIXED = 1 } calib_precision;
+
+/* options */
+#define CALIB_OPT_GPA_FIRST_ITER 1u  /* align the unitary ambiguity across subbands after the first
+                                        local step (Section 3, initialisation)                  */
+#define CALIB_OPT_UNREG_FIRST 2u     /* first local step without the consensus terms            */
+
+typedef struct {
+  int32_t n_stations;      /* N >= 2                                                           */
+  int32_t n_subbands;      /* P >= 1 (the paper's compute agents)                              */
+  int32_t n_basis;         /* Q >= 1 polynomial terms (the paper's F)                          */
+  int32_t n_dirs_max;      /* K >= 1                                                           */
+  int32_t n_times;         /* T >= 1 time slots of the solution interval                       */
+  const int32_t *n_chan;   /* host [P], channels per subband, >= 1                             */
+  const int32_t *n_dirs;   /* host [P], directions per subband 1..K (nested 0..K_f-1); NULL = K */
+  const double *freq_hz;   /* host [P], subband frequency at which b_f is evaluated             */
+  double f0_hz;            /* basis reference frequency (> 0)                                  */
+  const double *rho;       /* host [K], per-direction rho >= 0 (0 = normal calibration)        */
+  calib_precision precision;
+  int32_t lm_iters;        /* LM iterations per direction per local step, >= 1                  */
+  int32_t sage_sweeps;     /* SAGE sweeps over the directions per local step, >= 1              */
+  uint32_t options;        /* CALIB_OPT_* bits                                                  */
+} calib_config;
+
+/* Field selectors for calib_get. */
+#define CALIB_FIELD_J 0          /* double complex [P][K][N][2][2]                              */
+#define CALIB_FIELD_Z 1          /* double complex [K][Q][N][2][2]                              */
+#define CALIB_FIELD_BZ 2         /* double complex [P][K][N][2][2], B_f Z_k                     */
+#define CALIB_FIELD_Y 3          /* double complex [P][K][N][2][2], Lagrange multipliers        */
+#define CALIB_FIELD_MODEL_VIS 4  /* vis layout and element type: sum_k c J_p J_q^H, zero on
+                                    flagged baselines (Section 2, visibility model)           */
+#define CALIB_FIELD_COST 5       /* double [P]: data cost g_f at the current J (Section 2)     */
+#define CALIB_FIELD_TRACE 6      /* double [admm iterations run][4]: data cost after the local
+                                    step, augmented Lagrangian, primal, dual residual         */
+#define CALIB_FIELD_LM_TRACE 7   /* double [P][K][lm_iters][3] of the last SAGE sweep of the last
+                                    local step: objective after each LM iteration, damping
+                                    lambda, 1 if the step was accepted                        */
+#define CALIB_FIELD_LM_STEP 8    /* double [P][2][8N]: gradient G and solution delta of
+                                    (H_GN + (rho + lambda) I) delta = -G of the last LM
+                                    iteration (real parameters p*8 + (i*2+j)*2 + re/im)       */
+
+/* Validate the configuration, pack the inputs into the library's baseline-major layout (dropping
+ * flagged baselines, converting nothing: the element type must match cfg->precision), compute
+ * the per-baseline coherency energies S_b = sum |c|^2, set J to jones0 (or identity blocks,
+ * Section 3 initialisation) and Z = Y = 0.
+ *   vis    device, see layout above;       coh    device, see layout above
+ *   flags  device [P*B] or NULL;           jones0 device double complex [P][K][N][2][2] or NULL
+ *   hip_stream  hipStream_t or NULL;       out    receives the new context
+ * Returns CALIB_E_RANK when some direction has fewer than Q subbands or the basis matrix of its
+ * subband frequencies is rank deficient. */
+calib_status calib_init(const calib_config *cfg, const void *vis, const void *coh,
+                        const uint8_t *flags, const void *jones0, void *hip_stream,
+                        calib_ctx **out);
+
+/* Step D1/S1 for all subbands at ADMM iteration admm_iter (minimisation M1): refresh the full
+ * residual, then for each SAGE sweep and direction run lm_iters Levenberg-Marquardt iterations
+ * on L_fk with Y and B_f Z from the previous consensus update.  At admm_iter 0 with
+ * CALIB_OPT_UNREG_FIRST the consensus terms are left out. */
+calib_status admm_local_step(calib_ctx *ctx, int32_t admm_iter);
+
+/* Steps D2 and D3 (minimisations M2 and M3): at admm_iter 0 with CALIB_OPT_GPA_FIRST_ITER first
+ * align the unitary ambiguity of each direction across subbands; then per direction
+ * Z_k = argmin sum_f ||J_fk + Y_fk/rho_k - B_f Z_k||^2 (the closed-form Z of Section 3, solved by
+ * QR of the basis matrix), B_f Z_k, Y_fk += rho_k (J_fk - B_f Z_k), and the primal and dual
+ * residuals of Section 4.1 into the trace row of admm_iter. */
+calib_status admm_consensus_update(calib_ctx *ctx, int32_t admm_iter);
+
+/* The whole C-ADMM loop: iterations 0..max_iters-1 of local step + consensus update.  When
+ * rel_cost_tol > 0 it stops after an iteration whose data cost changed by less than
+ * rel_cost_tol relative to the previous one (this check synchronises the stream each
+ * iteration).  trace_out (host, may be NULL) receives [iters][4] as CALIB_FIELD_TRACE;
+ * iters_done (host, may be NULL) the number of iterations run.  Synchronises the stream. */
+calib_status admm_solve(calib_ctx *ctx, int32_t max_iters, double rel_cost_tol, double *trace_out,
+                        int32_t *iters_done);
+
+/* Copy a field into caller memory.  dst is device memory for every field except
+ * CALIB_FIELD_TRACE (host).  Enqueued on the context's stream. */
+calib_status calib_get(calib_ctx *ctx, int32_t field, void *dst);
+
+/* Overwrite J (device double complex [P][K][N][2][2]) - a warm start for a new solve on the
+ * same data, e.g. the previous solution interval's J (Section 3) or a learned prediction -
+ * and reset Y, Z and B_f Z to zero. */
+calib_status calib_set_jones(calib_ctx *ctx, const void *jones);
+
+/* Free every device buffer of the context (synchronises its stream). NULL is accepted. */
+void calib_destroy(calib_ctx *ctx);
+
+/* Message of the last failure on ctx, or of the last calib_init failure when ctx is NULL. */
+const char *calib_last_error(const calib_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CALIB_MI355X_H */

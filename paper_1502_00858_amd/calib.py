@@ -1,0 +1,169 @@
+"""Python binding of the C ABI in include/calib.h (argument marshalling only).
+
+Device buffers are torch tensors on the GPU; every step of the computation runs in the HIP
+library libcalib_mi355x.so.  There is no fallback: if the library is missing, loading fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+from .build import LIB_PATH
+
+CALIB_FP64 = 0
+CALIB_FP32_MIXED = 1
+OPT_GPA_FIRST_ITER = 1
+OPT_UNREG_FIRST = 2
+(FIELD_J, FIELD_Z, FIELD_BZ, FIELD_Y, FIELD_MODEL_VIS, FIELD_COST, FIELD_TRACE, FIELD_LM_TRACE,
+ FIELD_LM_STEP) = range(9)
+STATUS = {0: "CALIB_OK", 1: "CALIB_E_INVAL", 2: "CALIB_E_NOMEM", 3: "CALIB_E_DEVICE",
+          4: "CALIB_E_RANK", 5: "CALIB_E_NUMERIC", 6: "CALIB_E_STATE"}
+EXPORTS = ["calib_init", "admm_local_step", "admm_consensus_update", "admm_solve", "calib_get",
+           "calib_set_jones", "calib_destroy", "calib_last_error"]
+
+
+class CalibError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Config(C.Structure):
+    _fields_ = [("n_stations", C.c_int32), ("n_subbands", C.c_int32), ("n_basis", C.c_int32),
+                ("n_dirs_max", C.c_int32), ("n_times", C.c_int32),
+                ("n_chan", C.POINTER(C.c_int32)), ("n_dirs", C.POINTER(C.c_int32)),
+                ("freq_hz", C.POINTER(C.c_double)), ("f0_hz", C.c_double),
+                ("rho", C.POINTER(C.c_double)), ("precision", C.c_int),
+                ("lm_iters", C.c_int32), ("sage_sweeps", C.c_int32), ("options", C.c_uint32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with paper_1502_00858_amd.build.build()")
+        lib = C.CDLL(path)
+        vp, i32, dbl = C.c_void_p, C.c_int32, C.c_double
+        lib.calib_init.argtypes = [C.POINTER(_Config), vp, vp, vp, vp, vp, C.POINTER(vp)]
+        lib.admm_local_step.argtypes = [vp, i32]
+        lib.admm_consensus_update.argtypes = [vp, i32]
+        lib.admm_solve.argtypes = [vp, i32, dbl, vp, C.POINTER(i32)]
+        lib.calib_get.argtypes = [vp, i32, vp]
+        lib.calib_set_jones.argtypes = [vp, vp]
+        lib.calib_destroy.argtypes = [vp]
+        lib.calib_destroy.restype = None
+        lib.calib_last_error.argtypes = [vp]
+        lib.calib_last_error.restype = C.c_char_p
+        for name in ("calib_init", "admm_local_step", "admm_consensus_update", "admm_solve",
+                     "calib_get", "calib_set_jones"):
+            getattr(lib, name).restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(t) -> C.c_void_p:
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def device_inputs(data: dict, precision: int = CALIB_FP64, device: str = "cuda"):
+    """Move the generator's arrays to the GPU in the element type of the precision mode."""
+    import torch
+    cdt = torch.complex128 if precision == CALIB_FP64 else torch.complex64
+    vis = torch.from_numpy(np.ascontiguousarray(data["vis"])).to(device=device, dtype=cdt)
+    coh = torch.from_numpy(np.ascontiguousarray(data["coh"])).to(device=device, dtype=cdt)
+    flags = torch.from_numpy(np.ascontiguousarray(data["flags"], np.uint8)).to(device)
+    return vis, coh, flags
+
+
+class Calib:
+    """One calibration context (calib_init ... calib_destroy)."""
+
+    def __init__(self, data: dict, vis, coh, flags=None, jones0=None, precision: int = CALIB_FP64,
+                 lm_iters: Optional[int] = None, sage_sweeps: int = 1,
+                 options: int = OPT_GPA_FIRST_ITER, rho=None, stream=None):
+        import torch
+        self.lib = load()
+        self.N, self.P, self.Q, self.K, self.T = (int(data[k]) for k in ("N", "P", "Q", "K", "T"))
+        self.precision = precision
+        self.lm_iters = int(data.get("lm_iters", 10) if lm_iters is None else lm_iters)
+        self._n_chan = np.ascontiguousarray(data["n_chan"], np.int32)
+        self._n_dirs = np.ascontiguousarray(data["n_dirs"], np.int32)
+        self._freq = np.ascontiguousarray(data["freq"], np.float64)
+        self._rho = np.ascontiguousarray(data["rho"] if rho is None else rho, np.float64)
+        self._vis_shape = tuple(vis.shape)
+        self._vis_dtype = vis.dtype
+        cfg = _Config(self.N, self.P, self.Q, self.K, self.T,
+                      self._n_chan.ctypes.data_as(C.POINTER(C.c_int32)),
+                      self._n_dirs.ctypes.data_as(C.POINTER(C.c_int32)),
+                      self._freq.ctypes.data_as(C.POINTER(C.c_double)), float(data["f0"]),
+                      self._rho.ctypes.data_as(C.POINTER(C.c_double)), int(precision),
+                      self.lm_iters, int(sage_sweeps), int(options))
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        ctx = C.c_void_p()
+        st = self.lib.calib_init(C.byref(cfg), _ptr(vis), _ptr(coh), _ptr(flags), _ptr(jones0),
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
+        if st != 0:
+            raise CalibError(st, self.lib.calib_last_error(None).decode())
+        self.ctx = ctx
+
+    def _check(self, st):
+        if st != 0:
+            raise CalibError(st, self.lib.calib_last_error(self.ctx).decode())
+
+    def local_step(self, admm_iter: int):
+        self._check(self.lib.admm_local_step(self.ctx, admm_iter))
+
+    def consensus_update(self, admm_iter: int):
+        self._check(self.lib.admm_consensus_update(self.ctx, admm_iter))
+
+    def solve(self, max_iters: int, rel_cost_tol: float = 0.0):
+        tr = np.zeros((max(max_iters, 1), 4))
+        done = C.c_int32(0)
+        self._check(self.lib.admm_solve(self.ctx, max_iters, rel_cost_tol,
+                                        C.c_void_p(tr.ctypes.data), C.byref(done)))
+        return tr[:done.value]
+
+    def get(self, field: int):
+        import torch
+        if field == FIELD_TRACE:
+            n = 4096
+            tr = np.zeros((n, 4))
+            self._check(self.lib.calib_get(self.ctx, field, C.c_void_p(tr.ctypes.data)))
+            return tr
+        shapes = {FIELD_J: (self.P, self.K, self.N, 2, 2), FIELD_Y: (self.P, self.K, self.N, 2, 2),
+                  FIELD_BZ: (self.P, self.K, self.N, 2, 2), FIELD_Z: (self.K, self.Q, self.N, 2, 2)}
+        if field in shapes:
+            out = torch.empty(shapes[field], dtype=torch.complex128, device="cuda")
+        elif field == FIELD_MODEL_VIS:
+            out = torch.empty(self._vis_shape, dtype=self._vis_dtype, device="cuda")
+        elif field == FIELD_COST:
+            out = torch.empty(self.P, dtype=torch.float64, device="cuda")
+        elif field == FIELD_LM_STEP:
+            out = torch.empty((self.P, 2, 8 * self.N), dtype=torch.float64, device="cuda")
+        elif field == FIELD_LM_TRACE:
+            out = torch.empty((self.P, self.K, self.lm_iters, 3), dtype=torch.float64, device="cuda")
+        else:
+            raise ValueError(field)
+        self._check(self.lib.calib_get(self.ctx, field, _ptr(out)))
+        return out
+
+    def set_jones(self, J):
+        self._check(self.lib.calib_set_jones(self.ctx, _ptr(J)))
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.calib_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

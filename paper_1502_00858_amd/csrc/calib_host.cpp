@@ -1,0 +1,480 @@
+// Host side of the C ABI: validation, packing, workspace management and the launch sequence of
+// the consensus-ADMM iteration (Section 3, steps D1-D3).  Every arithmetic step of the method
+// runs in the HIP kernels; this file only prepares index tables and enqueues work.
+#include "calib.h"
+#include "calib_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace calib;
+
+namespace {
+constexpr int kMaxTrace = 4096;
+thread_local std::string g_init_error;
+
+struct DevAlloc {
+  std::vector<void *> ptrs;
+  hipError_t alloc(void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) ptrs.push_back(*p);
+    return e;
+  }
+  void release() {
+    for (void *p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+}  // namespace
+
+struct calib_ctx {
+  int N = 0, P = 0, Q = 0, K = 0, T = 0;
+  calib_precision precision = CALIB_FP64;
+  int lm_iters = 1, sage_sweeps = 1;
+  uint32_t options = 0;
+  double f0 = 0.0;
+  std::vector<int32_t> n_chan, n_dirs;
+  std::vector<double> freq, rho;
+  hipStream_t stream = nullptr;
+  Problem pb{};
+  Layout L{};
+  Buffers B{};
+  DevAlloc mem;
+  int64_t total_full_samples = 0;
+  int64_t *d_full_off = nullptr;
+  int32_t *d_full_bmap = nullptr;
+  int32_t *d_ndir = nullptr;
+  double *lm_trace = nullptr;
+  int iters_done = 0;
+  std::string err;
+};
+
+namespace {
+
+calib_status fail(calib_ctx *ctx, calib_status st, const std::string &msg) {
+  if (ctx) ctx->err = msg; else g_init_error = msg;
+  return st;
+}
+
+#define HIPCHK(ctx, expr)                                                                      \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(ctx, CALIB_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+#define ALLOC(ctx, ptr, bytes)                                                                 \
+  do {                                                                                         \
+    void *p_ = nullptr;                                                                        \
+    if ((ctx)->mem.alloc(&p_, (bytes)) != hipSuccess)                                          \
+      return fail(ctx, CALIB_E_NOMEM, "hipMalloc failed for " #ptr);                           \
+    ptr = reinterpret_cast<decltype(ptr)>(p_);                                                 \
+  } while (0)
+
+template <typename V>
+calib_status upload(calib_ctx *ctx, V **dst, const std::vector<V> &src) {
+  ALLOC(ctx, *dst, sizeof(V) * std::max<size_t>(src.size(), 1));
+  if (!src.empty())
+    HIPCHK(ctx, hipMemcpyAsync(*dst, src.data(), sizeof(V) * src.size(), hipMemcpyHostToDevice,
+                               ctx->stream));
+  return CALIB_OK;
+}
+
+// lanes per baseline for the streaming kernels: fewest idle lane-iterations over the subbands,
+// ties to the larger group; CALIB_GROUP overrides (used by the tile-shape tuner)
+int choose_group(const std::vector<int32_t> &spb, const std::vector<int32_t> &nb) {
+  if (const char *env = std::getenv("CALIB_GROUP")) {
+    const int g = std::atoi(env);
+    if (g == 8 || g == 16 || g == 32 || g == 64) return g;
+  }
+  int best = 16;
+  double best_w = 1e300;
+  for (int g : {64, 32, 16, 8}) {
+    double w = 0.0;
+    for (size_t f = 0; f < spb.size(); ++f) {
+      const int it = (spb[f] + g - 1) / g;
+      w += (double)nb[f] * (double)(it * g - spb[f]);
+    }
+    if (w < best_w) { best_w = w; best = g; }
+  }
+  return best;
+}
+
+template <typename T>
+calib_status run_local_step(calib_ctx *c, int admm_iter) {
+  const int unreg = (admm_iter == 0 && (c->options & CALIB_OPT_UNREG_FIRST)) ? 1 : 0;
+  hipStream_t s = c->stream;
+  HIPCHK(c, launch_refresh<T>(c->pb, c->L, c->B, s));
+  for (int sw = 0; sw < c->sage_sweeps; ++sw)
+    for (int k = 0; k < c->K; ++k) {
+      HIPCHK(c, launch_lm_begin(c->pb, c->L, c->B, k, unreg, s));
+      for (int it = 0; it < c->lm_iters; ++it) {
+        HIPCHK(c, launch_assemble(c->pb, c->L, c->B, k, unreg, s));
+        HIPCHK(c, launch_chol_solve_nd(c->pb, c->B, k, c->d_ndir, s));
+        HIPCHK(c, launch_trial<T>(c->pb, c->L, c->B, k, s));
+        HIPCHK(c, launch_lm_update_tr(c->pb, c->L, c->B, k, unreg, c->lm_trace, it, c->lm_iters, s));
+      }
+      HIPCHK(c, launch_commit<T>(c->pb, c->L, c->B, k, s));
+    }
+  return CALIB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *calib_last_error(const calib_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+void calib_destroy(calib_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->mem.release();
+  delete ctx;
+}
+
+calib_status calib_init(const calib_config *cfg, const void *vis, const void *coh,
+                        const uint8_t *flags, const void *jones0, void *hip_stream,
+                        calib_ctx **out) {
+  g_init_error.clear();
+  if (!out) return fail(nullptr, CALIB_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfg || !vis || !coh) return fail(nullptr, CALIB_E_INVAL, "cfg, vis and coh are required");
+  const int N = cfg->n_stations, P = cfg->n_subbands, Q = cfg->n_basis, K = cfg->n_dirs_max,
+            T = cfg->n_times;
+  if (N < 2 || N > 4096) return fail(nullptr, CALIB_E_INVAL, "n_stations must be in [2, 4096]");
+  if (P < 1) return fail(nullptr, CALIB_E_INVAL, "n_subbands must be >= 1");
+  if (Q < 1 || Q > 8) return fail(nullptr, CALIB_E_INVAL, "n_basis must be in [1, 8]");
+  if (K < 1 || K > kMaxDirs) return fail(nullptr, CALIB_E_INVAL, "n_dirs_max must be in [1, 16]");
+  if (T < 1) return fail(nullptr, CALIB_E_INVAL, "n_times must be >= 1");
+  if (!cfg->n_chan || !cfg->freq_hz || !cfg->rho)
+    return fail(nullptr, CALIB_E_INVAL, "n_chan, freq_hz and rho are required");
+  if (!(cfg->f0_hz > 0.0) || !std::isfinite(cfg->f0_hz))
+    return fail(nullptr, CALIB_E_INVAL, "f0_hz must be positive");
+  if (cfg->precision != CALIB_FP64 && cfg->precision != CALIB_FP32_MIXED)
+    return fail(nullptr, CALIB_E_INVAL, "unknown precision");
+  if (cfg->lm_iters < 1 || cfg->sage_sweeps < 1)
+    return fail(nullptr, CALIB_E_INVAL, "lm_iters and sage_sweeps must be >= 1");
+
+  calib_ctx *c = new calib_ctx();
+  c->N = N; c->P = P; c->Q = Q; c->K = K; c->T = T;
+  c->precision = cfg->precision;
+  c->lm_iters = cfg->lm_iters;
+  c->sage_sweeps = cfg->sage_sweeps;
+  c->options = cfg->options;
+  c->f0 = cfg->f0_hz;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->n_chan.assign(cfg->n_chan, cfg->n_chan + P);
+  c->freq.assign(cfg->freq_hz, cfg->freq_hz + P);
+  c->rho.assign(cfg->rho, cfg->rho + K);
+  if (cfg->n_dirs) c->n_dirs.assign(cfg->n_dirs, cfg->n_dirs + P);
+  else c->n_dirs.assign(P, K);
+  auto bail = [&](calib_status st, const std::string &m) {
+    g_init_error = m;
+    calib_destroy(c);
+    return st;
+  };
+  for (int f = 0; f < P; ++f) {
+    if (c->n_chan[f] < 1) return bail(CALIB_E_INVAL, "n_chan entries must be >= 1");
+    if (c->n_dirs[f] < 1 || c->n_dirs[f] > K) return bail(CALIB_E_INVAL, "n_dirs entries must be in [1, K]");
+    if (!std::isfinite(c->freq[f])) return bail(CALIB_E_INVAL, "freq_hz must be finite");
+  }
+  for (int k = 0; k < K; ++k)
+    if (!(c->rho[k] >= 0.0) || !std::isfinite(c->rho[k])) return bail(CALIB_E_INVAL, "rho must be finite and >= 0");
+  for (int k = 0; k < K; ++k) {
+    std::vector<double> fr;
+    for (int f = 0; f < P; ++f)
+      if (c->n_dirs[f] > k) fr.push_back(c->freq[f]);
+    std::sort(fr.begin(), fr.end());
+    const size_t distinct = std::unique(fr.begin(), fr.end()) - fr.begin();
+    if ((int)distinct < Q)
+      return bail(CALIB_E_RANK, "direction " + std::to_string(k) + " is carried by fewer than Q distinct subband frequencies");
+  }
+
+  const int Bfull = N * (N - 1) / 2;
+  std::vector<uint8_t> hflags((size_t)P * Bfull, 0);
+  if (flags) {
+    hipError_t e = hipMemcpyAsync(hflags.data(), flags, hflags.size(), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return bail(CALIB_E_DEVICE, std::string("reading flags: ") + hipGetErrorString(e));
+  }
+  std::vector<int32_t> pair_p(Bfull), pair_q(Bfull);
+  for (int a = 0, b = 0; a < N; ++a)
+    for (int q = a + 1; q < N; ++q, ++b) { pair_p[b] = a; pair_q[b] = q; }
+
+  std::vector<int64_t> samp_off(P), coh_off(P), sb_off(P), in_vis_off(P), in_coh_off(P), full_off(P);
+  std::vector<int32_t> bl_off(P), nb(P), spb(P), bl_p, bl_q, comp2full, comp_f;
+  std::vector<int32_t> full_bmap((size_t)P * Bfull, -1), bidx((size_t)P * N * N, -1);
+  int64_t so = 0, co = 0, sbo = 0, ivo = 0, ico = 0;
+  for (int f = 0; f < P; ++f) {
+    spb[f] = T * c->n_chan[f];
+    bl_off[f] = (int32_t)bl_p.size();
+    samp_off[f] = so; coh_off[f] = co; sb_off[f] = sbo;
+    in_vis_off[f] = ivo; in_coh_off[f] = ico; full_off[f] = ivo;
+    int cnt = 0;
+    for (int b = 0; b < Bfull; ++b) {
+      if (hflags[(size_t)f * Bfull + b]) continue;
+      const int gb = (int)bl_p.size();
+      full_bmap[(size_t)f * Bfull + b] = gb;
+      bidx[((size_t)f * N + pair_p[b]) * N + pair_q[b]] = gb;
+      bidx[((size_t)f * N + pair_q[b]) * N + pair_p[b]] = gb;
+      bl_p.push_back(pair_p[b]);
+      bl_q.push_back(pair_q[b]);
+      comp2full.push_back(b);
+      comp_f.push_back(f);
+      ++cnt;
+    }
+    nb[f] = cnt;
+    so += (int64_t)cnt * spb[f];
+    co += (int64_t)c->n_dirs[f] * cnt * spb[f];
+    sbo += (int64_t)c->n_dirs[f] * cnt;
+    ivo += (int64_t)Bfull * spb[f];
+    ico += (int64_t)c->n_dirs[f] * Bfull * spb[f];
+  }
+  const int nb_total = (int)bl_p.size();
+  c->total_full_samples = ivo;
+  std::vector<int32_t> comp_tab(comp2full);
+  comp_tab.insert(comp_tab.end(), comp_f.begin(), comp_f.end());
+
+  const int group = choose_group(spb, nb);
+  const int bpt = kBlock / group;
+  std::vector<int32_t> tile_f, tile_b0, tile_off(P + 1);
+  for (int f = 0; f < P; ++f) {
+    tile_off[f] = (int32_t)tile_f.size();
+    for (int b0 = 0; b0 < nb[f]; b0 += bpt) { tile_f.push_back(f); tile_b0.push_back(b0); }
+  }
+  tile_off[P] = (int32_t)tile_f.size();
+  std::vector<int32_t> adj_off((size_t)P * N + 1), adj_b, adj_o;
+  for (int f = 0; f < P; ++f)
+    for (int p = 0; p < N; ++p) {
+      adj_off[(size_t)f * N + p] = (int32_t)adj_b.size();
+      for (int o = 0; o < N; ++o) {
+        if (o == p) continue;
+        const int gb = bidx[((size_t)f * N + p) * N + o];
+        if (gb < 0) continue;
+        adj_b.push_back(gb);
+        adj_o.push_back(o > p ? o : -1 - o);
+      }
+    }
+  adj_off[(size_t)P * N] = (int32_t)adj_b.size();
+
+  Problem &pb = c->pb;
+  pb.N = N; pb.P = P; pb.Q = Q; pb.K = K;
+  pb.nf = ((8 * N + 15) / 16) * 16;
+  pb.npad = pb.nf + 16;
+  pb.ntiles = (int)tile_f.size();
+  pb.group = group;
+  pb.bpt = bpt;
+
+  calib_status st = CALIB_OK;
+#define UPL(dst, src)                                                                          \
+  do {                                                                                         \
+    st = upload(c, &dst, src);                                                                 \
+    if (st != CALIB_OK) { g_init_error = c->err; calib_destroy(c); return st; }                \
+  } while (0)
+  int64_t *d_samp, *d_coh, *d_sb, *d_ivo, *d_ico;
+  int32_t *d_bl_off, *d_nb, *d_spb, *d_ndir, *d_blp, *d_blq, *d_tf, *d_tb, *d_to, *d_ao, *d_ab, *d_aoth,
+      *d_bidx, *d_comp;
+  UPL(d_samp, samp_off); UPL(d_coh, coh_off); UPL(d_sb, sb_off); UPL(d_ivo, in_vis_off);
+  UPL(d_ico, in_coh_off); UPL(d_bl_off, bl_off); UPL(d_nb, nb); UPL(d_spb, spb);
+  UPL(d_ndir, c->n_dirs); UPL(d_blp, bl_p); UPL(d_blq, bl_q); UPL(d_tf, tile_f); UPL(d_tb, tile_b0);
+  UPL(d_to, tile_off); UPL(d_ao, adj_off); UPL(d_ab, adj_b); UPL(d_aoth, adj_o); UPL(d_bidx, bidx);
+  UPL(d_comp, comp_tab); UPL(c->d_full_off, full_off); UPL(c->d_full_bmap, full_bmap);
+  double *d_rho, *d_freq;
+  UPL(d_rho, c->rho); UPL(d_freq, c->freq);
+  c->d_ndir = d_ndir;
+  Layout &L = c->L;
+  L.samp_off = d_samp; L.coh_off = d_coh; L.bl_off = d_bl_off; L.nb = d_nb; L.spb = d_spb;
+  L.ndir = d_ndir; L.bl_p = d_blp; L.bl_q = d_blq; L.tile_f = d_tf; L.tile_b0 = d_tb;
+  L.tile_off = d_to; L.adj_off = d_ao; L.adj_b = d_ab; L.adj_o = d_aoth; L.bidx = d_bidx;
+  L.sb_off = d_sb;
+
+  const size_t elt = (c->precision == CALIB_FP64) ? sizeof(double) : sizeof(float);
+  Buffers &B = c->B;
+  auto fail_alloc = [&](const char *what) {
+    g_init_error = std::string("hipMalloc failed for ") + what;
+    calib_destroy(c);
+    return CALIB_E_NOMEM;
+  };
+#define DALLOC(ptr, bytes)                                                                     \
+  do {                                                                                         \
+    void *p_ = nullptr;                                                                        \
+    if (c->mem.alloc(&p_, (bytes)) != hipSuccess) return fail_alloc(#ptr);                     \
+    ptr = reinterpret_cast<decltype(ptr)>(p_);                                                 \
+  } while (0)
+  void *Vp, *Cp, *R;
+  double *Sb;
+  DALLOC(Vp, (size_t)so * 8 * elt);
+  DALLOC(R, (size_t)so * 8 * elt);
+  DALLOC(Cp, (size_t)co * 2 * elt);
+  DALLOC(Sb, (size_t)sbo * sizeof(double));
+  const size_t nj = (size_t)P * K * N * 8, nz = (size_t)K * Q * N * 8;
+  DALLOC(B.J, nj * 8); DALLOC(B.Y, nj * 8); DALLOC(B.BZ, nj * 8);
+  DALLOC(B.Z, nz * 8); B.Zold = nullptr;
+  DALLOC(B.Jstart, (size_t)P * N * 8 * 8); DALLOC(B.Jtrial, (size_t)P * N * 8 * 8);
+  DALLOC(B.Dcur, (size_t)nb_total * 8 * 8); DALLOC(B.Dtrial, (size_t)nb_total * 8 * 8);
+  DALLOC(B.H, (size_t)P * pb.npad * pb.nf * 8);
+  DALLOC(B.G, (size_t)P * pb.nf * 8); DALLOC(B.delta, (size_t)P * pb.nf * 8);
+  DALLOC(B.cost_part, (size_t)std::max(pb.ntiles, 1) * 8);
+  DALLOC(B.lm, (size_t)P * sizeof(LmState));
+  double *basis, *fitw;
+  DALLOC(basis, (size_t)P * Q * 8);
+  DALLOC(fitw, (size_t)K * Q * P * 8);
+  DALLOC(B.trace, (size_t)kMaxTrace * 4 * 8);
+  DALLOC(B.scratch, ((size_t)P * K + K) * 8);
+  DALLOC(c->lm_trace, (size_t)P * K * c->lm_iters * 3 * 8);
+  int *flagbuf;
+  DALLOC(flagbuf, 2 * sizeof(int));
+  B.V = Vp; B.R = R; B.C = Cp; B.Sb = Sb; B.rho = d_rho; B.basis = basis; B.fitw = fitw;
+
+  hipStream_t s = c->stream;
+  auto dev = [&](hipError_t e, const char *what) -> bool {
+    if (e == hipSuccess) return true;
+    g_init_error = std::string(what) + ": " + hipGetErrorString(e);
+    return false;
+  };
+  const bool ok =
+      dev(hipMemsetAsync(flagbuf, 0, 2 * sizeof(int), s), "clear flags") &&
+      dev(c->precision == CALIB_FP64
+              ? launch_pack<double>(pb, L, vis, coh, Vp, Cp, Sb, d_ivo, d_ico, d_comp, nb_total, flagbuf, s)
+              : launch_pack<float>(pb, L, vis, coh, Vp, Cp, Sb, d_ivo, d_ico, d_comp, nb_total, flagbuf, s),
+          "pack") &&
+      dev(launch_basis_setup(pb, d_freq, c->f0, d_ndir, basis, fitw, flagbuf + 1, s), "basis setup") &&
+      dev(launch_zero(B.H, (int64_t)P * pb.npad * pb.nf, s), "zero H") &&
+      dev(launch_zero(B.Y, (int64_t)nj, s), "zero Y") && dev(launch_zero(B.BZ, (int64_t)nj, s), "zero BZ") &&
+      dev(launch_zero(B.Z, (int64_t)nz, s), "zero Z") &&
+      dev(launch_zero(B.trace, (int64_t)kMaxTrace * 4, s), "zero trace") &&
+      dev(launch_zero(c->lm_trace, (int64_t)P * K * c->lm_iters * 3, s), "zero lm trace") &&
+      dev(jones0 ? hipMemcpyAsync(B.J, jones0, nj * 8, hipMemcpyDeviceToDevice, s)
+                 : launch_fill_identity(B.J, (int64_t)P * K * N, s),
+          "initial jones");
+  if (!ok) { calib_destroy(c); return CALIB_E_DEVICE; }
+  int hflag[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(hflag, flagbuf, sizeof hflag, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return bail(CALIB_E_DEVICE, std::string("init: ") + hipGetErrorString(e));
+  if (hflag[0]) return bail(CALIB_E_NUMERIC, "non-finite values in vis or coh");
+  if (hflag[1]) return bail(CALIB_E_RANK, "basis matrix of the subband frequencies is rank deficient");
+  *out = c;
+  return CALIB_OK;
+}
+
+calib_status admm_local_step(calib_ctx *ctx, int32_t admm_iter) {
+  if (!ctx) return CALIB_E_INVAL;
+  if (admm_iter < 0 || admm_iter >= kMaxTrace) return fail(ctx, CALIB_E_INVAL, "admm_iter out of range");
+  return ctx->precision == CALIB_FP64 ? run_local_step<double>(ctx, admm_iter)
+                                      : run_local_step<float>(ctx, admm_iter);
+}
+
+calib_status admm_consensus_update(calib_ctx *ctx, int32_t admm_iter) {
+  if (!ctx) return CALIB_E_INVAL;
+  if (admm_iter < 0 || admm_iter >= kMaxTrace) return fail(ctx, CALIB_E_INVAL, "admm_iter out of range");
+  hipStream_t s = ctx->stream;
+  HIPCHK(ctx, launch_penalty_trace(ctx->pb, ctx->L, ctx->B, admm_iter, s));
+  if (admm_iter == 0 && (ctx->options & CALIB_OPT_GPA_FIRST_ITER))
+    HIPCHK(ctx, launch_gpa(ctx->pb, ctx->L, ctx->B, 3, s));
+  HIPCHK(ctx, launch_consensus(ctx->pb, ctx->L, ctx->B, admm_iter, s));
+  ctx->iters_done = std::max(ctx->iters_done, admm_iter + 1);
+  return CALIB_OK;
+}
+
+calib_status admm_solve(calib_ctx *ctx, int32_t max_iters, double rel_cost_tol, double *trace_out,
+                        int32_t *iters_done) {
+  if (!ctx) return CALIB_E_INVAL;
+  if (max_iters < 0 || max_iters > kMaxTrace) return fail(ctx, CALIB_E_INVAL, "max_iters out of range");
+  int n = 0;
+  double prev = 0.0;
+  for (; n < max_iters; ++n) {
+    calib_status st = admm_local_step(ctx, n);
+    if (st != CALIB_OK) return st;
+    st = admm_consensus_update(ctx, n);
+    if (st != CALIB_OK) return st;
+    if (rel_cost_tol > 0.0) {
+      double cur = 0.0;
+      HIPCHK(ctx, hipMemcpyAsync(&cur, ctx->B.trace + 4 * n, sizeof(double), hipMemcpyDeviceToHost,
+                                 ctx->stream));
+      HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+      if (n > 0 && std::fabs(cur - prev) <= rel_cost_tol * std::fabs(prev)) { ++n; break; }
+      prev = cur;
+    }
+  }
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+  if (trace_out && n > 0)
+    HIPCHK(ctx, hipMemcpy(trace_out, ctx->B.trace, sizeof(double) * 4 * n, hipMemcpyDeviceToHost));
+  if (iters_done) *iters_done = n;
+  return CALIB_OK;
+}
+
+calib_status calib_get(calib_ctx *ctx, int32_t field, void *dst) {
+  if (!ctx) return CALIB_E_INVAL;
+  if (!dst) return fail(ctx, CALIB_E_INVAL, "dst is NULL");
+  hipStream_t s = ctx->stream;
+  const size_t nj = (size_t)ctx->P * ctx->K * ctx->N * 8 * sizeof(double);
+  switch (field) {
+    case CALIB_FIELD_J:
+      HIPCHK(ctx, hipMemcpyAsync(dst, ctx->B.J, nj, hipMemcpyDeviceToDevice, s));
+      return CALIB_OK;
+    case CALIB_FIELD_Y:
+      HIPCHK(ctx, hipMemcpyAsync(dst, ctx->B.Y, nj, hipMemcpyDeviceToDevice, s));
+      return CALIB_OK;
+    case CALIB_FIELD_BZ:
+      HIPCHK(ctx, hipMemcpyAsync(dst, ctx->B.BZ, nj, hipMemcpyDeviceToDevice, s));
+      return CALIB_OK;
+    case CALIB_FIELD_Z:
+      HIPCHK(ctx, hipMemcpyAsync(dst, ctx->B.Z, (size_t)ctx->K * ctx->Q * ctx->N * 8 * sizeof(double),
+                                 hipMemcpyDeviceToDevice, s));
+      return CALIB_OK;
+    case CALIB_FIELD_MODEL_VIS:
+      HIPCHK(ctx, ctx->precision == CALIB_FP64
+                      ? launch_model<double>(ctx->pb, ctx->L, ctx->B, dst, ctx->d_full_off, ctx->d_full_bmap, s)
+                      : launch_model<float>(ctx->pb, ctx->L, ctx->B, dst, ctx->d_full_off, ctx->d_full_bmap, s));
+      return CALIB_OK;
+    case CALIB_FIELD_COST:
+      HIPCHK(ctx, ctx->precision == CALIB_FP64 ? launch_refresh<double>(ctx->pb, ctx->L, ctx->B, s)
+                                               : launch_refresh<float>(ctx->pb, ctx->L, ctx->B, s));
+      HIPCHK(ctx, launch_subband_cost(ctx->pb, ctx->L, ctx->B, static_cast<double *>(dst), s));
+      return CALIB_OK;
+    case CALIB_FIELD_TRACE:
+      HIPCHK(ctx, hipStreamSynchronize(s));
+      if (ctx->iters_done > 0)
+        HIPCHK(ctx, hipMemcpy(dst, ctx->B.trace, sizeof(double) * 4 * ctx->iters_done, hipMemcpyDeviceToHost));
+      return CALIB_OK;
+    case CALIB_FIELD_LM_TRACE:
+      HIPCHK(ctx, hipMemcpyAsync(dst, ctx->lm_trace,
+                                 sizeof(double) * 3 * (size_t)ctx->P * ctx->K * ctx->lm_iters,
+                                 hipMemcpyDeviceToDevice, s));
+      return CALIB_OK;
+    case CALIB_FIELD_LM_STEP: {
+      const size_t w = (size_t)8 * ctx->N * sizeof(double), sp = (size_t)ctx->pb.nf * sizeof(double);
+      char *d = static_cast<char *>(dst);
+      HIPCHK(ctx, hipMemcpy2DAsync(d, 2 * w, ctx->B.G, sp, w, ctx->P, hipMemcpyDeviceToDevice, s));
+      HIPCHK(ctx, hipMemcpy2DAsync(d + w, 2 * w, ctx->B.delta, sp, w, ctx->P, hipMemcpyDeviceToDevice, s));
+      return CALIB_OK;
+    }
+    default:
+      return fail(ctx, CALIB_E_INVAL, "unknown field");
+  }
+}
+
+calib_status calib_set_jones(calib_ctx *ctx, const void *jones) {
+  if (!ctx) return CALIB_E_INVAL;
+  if (!jones) return fail(ctx, CALIB_E_INVAL, "jones is NULL");
+  hipStream_t s = ctx->stream;
+  const int64_t nj = (int64_t)ctx->P * ctx->K * ctx->N * 8;
+  HIPCHK(ctx, hipMemcpyAsync(ctx->B.J, jones, nj * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(ctx, launch_zero(ctx->B.Y, nj, s));
+  HIPCHK(ctx, launch_zero(ctx->B.BZ, nj, s));
+  HIPCHK(ctx, launch_zero(ctx->B.Z, (int64_t)ctx->K * ctx->Q * ctx->N * 8, s));
+  ctx->iters_done = 0;
+  return CALIB_OK;
+}
+
+}  // extern "C"

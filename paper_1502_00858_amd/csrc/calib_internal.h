@@ -1,0 +1,115 @@
+// Internal declarations shared by the host code and the HIP kernels of the calibration library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace calib {
+
+constexpr int kBlock = 256;        // threads per workgroup of every kernel (4 wave64)
+constexpr int kMaxDirs = 16;       // directions per subband
+constexpr double kLmTau = 1e-3;    // Nielsen's initial damping factor
+
+// Per-subband tables of the packed, baseline-major layout.  Flagged baselines are dropped at
+// init, so "baseline index" below always means the compact index of an unflagged baseline.
+struct Layout {
+  const int64_t *samp_off;   // [P] first sample of subband f in V and R
+  const int64_t *coh_off;    // [P] first coherency of subband f (directions outermost)
+  const int32_t *bl_off;     // [P] first compact baseline of subband f
+  const int32_t *nb;         // [P] unflagged baselines
+  const int32_t *spb;        // [P] samples per baseline = T * n_chan
+  const int32_t *ndir;       // [P] directions K_f
+  const int32_t *bl_p;       // [sum nb] first station of each compact baseline
+  const int32_t *bl_q;       // [sum nb] second station
+  const int32_t *tile_f;     // [ntiles] subband of a streaming tile
+  const int32_t *tile_b0;    // [ntiles] first compact baseline of the tile
+  const int32_t *tile_off;   // [P+1] first tile of subband f
+  const int32_t *adj_off;    // [P*N+1] adjacency list of (subband, station)
+  const int32_t *adj_b;      // compact baseline index (global, i.e. including bl_off)
+  const int32_t *adj_o;      // other station; negative-encoded (-1-q) when the station is second
+  const int32_t *bidx;       // [P][N][N] compact baseline (global) of pair a<b or -1
+  const int64_t *sb_off;     // [P] first S_b entry of subband f (directions outermost)
+};
+
+// State of the Levenberg-Marquardt iteration of the active direction of each subband.
+struct LmState {
+  double F;        // objective at the accepted point
+  double lambda;   // damping
+  double nu;       // damping growth factor
+  double ell;      // predicted decrease of the last step
+  double Fnew;     // objective at the last trial point
+  int32_t chol_ok; // last factorisation succeeded
+  int32_t accepted;// accepted steps in this LM run
+  int32_t active;  // subband carries the active direction
+  int32_t pad;
+};
+
+struct Problem {
+  int N, P, Q, K;
+  int nf;          // factor columns = round_up(8N, 16)
+  int npad;        // rows of the augmented matrix = nf + 16 (row nf holds the right-hand side)
+  int ntiles;
+  int group;       // lanes per baseline in the streaming kernels
+  int bpt;         // baselines per tile = kBlock / group
+};
+
+struct Buffers {
+  const void *V;   // packed visibilities (stream type)
+  void *R;         // residual V - model (stream type)
+  const void *C;   // packed coherencies (stream type)
+  const double *Sb;
+  double *J, *Y, *BZ, *Z, *Zold;        // FP64 master state
+  double *Jstart, *Jtrial;              // [P][N][8] active direction
+  double *Dcur, *Dtrial;                // [sum nb][8]
+  double *H;                            // [P][npad][nf]
+  double *G, *delta;                    // [P][nf]
+  double *cost_part;                    // [ntiles]
+  LmState *lm;                          // [P]
+  const double *rho;                    // [K]
+  const double *basis;                  // [P][Q] b_l(f)
+  const double *fitw;                   // [K][Q][P] least-squares operator per direction
+  double *trace;                        // [iters][4]
+  double *scratch;                      // [P*K*2 + K] residual partials
+};
+
+// streaming kernels (templated on the stream element type float or double)
+template <typename T>
+hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
+template <typename T>
+hipError_t launch_trial(const Problem &pb, const Layout &L, const Buffers &B, int k, hipStream_t s);
+template <typename T>
+hipError_t launch_commit(const Problem &pb, const Layout &L, const Buffers &B, int k, hipStream_t s);
+template <typename T>
+hipError_t launch_model(const Problem &pb, const Layout &L, const Buffers &B, void *model_out,
+                        const int64_t *full_off, const int32_t *full_bmap, hipStream_t s);
+template <typename T>
+hipError_t launch_pack(const Problem &pb, const Layout &L, const void *vis, const void *coh,
+                       void *Vp, void *Cp, double *Sb, const int64_t *in_vis_off,
+                       const int64_t *in_coh_off, const int32_t *comp2full, int nb_total,
+                       int *bad_flag, hipStream_t s);
+
+// LM kernels
+hipError_t launch_lm_begin(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
+                           hipStream_t s);
+hipError_t launch_assemble(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
+                           hipStream_t s);
+int chol_panel_width(const Problem &pb);
+hipError_t launch_chol_solve_nd(const Problem &pb, const Buffers &B, int k, const int32_t *ndir,
+                                hipStream_t s);
+hipError_t launch_lm_update_tr(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
+                               double *lm_trace, int it, int lm_iters, hipStream_t s);
+
+// consensus kernels
+hipError_t launch_basis_setup(const Problem &pb, const double *freq, double f0, const int32_t *ndir,
+                              double *basis, double *fitw, int *rank_fail, hipStream_t s);
+hipError_t launch_penalty_trace(const Problem &pb, const Layout &L, const Buffers &B, int iter,
+                                hipStream_t s);
+hipError_t launch_gpa(const Problem &pb, const Layout &L, const Buffers &B, int rounds, hipStream_t s);
+hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, int iter,
+                            hipStream_t s);
+hipError_t launch_subband_cost(const Problem &pb, const Layout &L, const Buffers &B, double *out,
+                               hipStream_t s);
+hipError_t launch_fill_identity(double *J, int64_t nblocks, hipStream_t s);
+hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
+
+}  // namespace calib

@@ -1,0 +1,341 @@
+// Fusion-centre kernels (steps D2/D3 of Section 3) and bookkeeping, all FP64.
+//
+//   basis_setup : b_l(f) = ((f - f0)/f0)^(l-1) (the example polynomial of Section 3) and, per
+//                 direction, the least-squares operator W_k = R^-1 Q^T of the basis matrix of the
+//                 subbands that carry the direction (thin QR by twice-iterated classical
+//                 Gram-Schmidt).  Z_k = W_k (J + Y/rho) equals the closed-form minimiser
+//                 (sum b b^T)^+ sum b kron (Y + rho J) / rho of Section 3 when the basis matrix
+//                 has full column rank (the paper's condition P >= F).
+//   gpa         : first-iteration alignment of the unitary ambiguity (Section 3,
+//                 initialisation): generalised Procrustes to the mean over subbands.
+//   z_fit       : Z_k per direction and the dual-residual partials.
+//   y_update    : B_f Z_k, Y_fk += rho_k (J_fk - B_f Z_k) (minimisation M3) and primal partials.
+//   residuals   : primal and dual residuals of Section 4.1 averaged over (f, k) and k.
+#include "calib_internal.h"
+
+namespace calib {
+
+namespace {
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int NV>
+__device__ inline void block_sum_vec(double *v, double (*red)[kBlock / 64]) {
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double s = wave_sum(v[i]);
+    if ((threadIdx.x & 63) == 0) red[i][w] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < kBlock / 64; ++j) s += red[i][j];
+    v[i] = s;
+  }
+  __syncthreads();
+}
+
+// one thread per direction
+__global__ void k_basis_setup(int P, int Q, int K, const double *freq, double f0,
+                              const int32_t *ndir, double *basis, double *fitw, int *rank_fail) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0)
+    for (int f = 0; f < P; ++f) {
+      const double x = (freq[f] - f0) / f0;
+      double v = 1.0;
+      for (int l = 0; l < Q; ++l) { basis[f * Q + l] = v; v *= x; }
+    }
+  if (k >= K) return;
+  double *W = fitw + (int64_t)k * Q * P;   // row l = column l of the basis matrix, then of Q
+  double R[8][8];
+  for (int i = 0; i < 8; ++i)
+    for (int j = 0; j < 8; ++j) R[i][j] = 0.0;
+  for (int l = 0; l < Q; ++l)
+    for (int f = 0; f < P; ++f) {
+      const double x = (freq[f] - f0) / f0;
+      double v = 1.0;
+      for (int e = 0; e < l; ++e) v *= x;
+      W[l * P + f] = (ndir[f] > k) ? v : 0.0;
+    }
+  for (int l = 0; l < Q; ++l) {
+    double n0 = 0.0;
+    for (int f = 0; f < P; ++f) n0 += W[l * P + f] * W[l * P + f];
+    n0 = sqrt(n0);
+    for (int pass = 0; pass < 2; ++pass)
+      for (int j = 0; j < l; ++j) {
+        double r = 0.0;
+        for (int f = 0; f < P; ++f) r += W[j * P + f] * W[l * P + f];
+        R[j][l] += r;
+        for (int f = 0; f < P; ++f) W[l * P + f] -= r * W[j * P + f];
+      }
+    double nrm = 0.0;
+    for (int f = 0; f < P; ++f) nrm += W[l * P + f] * W[l * P + f];
+    nrm = sqrt(nrm);
+    if (!(nrm > 1e-12 * n0)) { atomicOr(rank_fail, 1); return; }
+    R[l][l] = nrm;
+    for (int f = 0; f < P; ++f) W[l * P + f] /= nrm;
+  }
+  for (int f = 0; f < P; ++f) {
+    double w[8];
+    for (int l = Q - 1; l >= 0; --l) {
+      double s = W[l * P + f];
+      for (int j = l + 1; j < Q; ++j) s -= R[l][j] * w[j];
+      w[l] = s / R[l][l];
+    }
+    for (int l = 0; l < Q; ++l) W[l * P + f] = w[l];
+  }
+}
+
+// data cost sum_f g_f (from the tile partials of the final residual) and the augmented
+// Lagrangian sum_f [g_f + sum_k Re tr(Y^H (J - BZ)) + rho_k/2 ||J - BZ||^2]
+__global__ __launch_bounds__(kBlock) void k_penalty_trace(Problem pb, Layout L, Buffers B, int iter) {
+  __shared__ double red[2][kBlock / 64];
+  double v[2] = {0.0, 0.0};
+  for (int t = threadIdx.x; t < pb.ntiles; t += kBlock) v[0] += B.cost_part[t];
+  const int64_t n = (int64_t)pb.P * pb.K * pb.N * 8;
+  for (int64_t e = threadIdx.x; e < n; e += kBlock) {
+    const int k = (int)((e / ((int64_t)pb.N * 8)) % pb.K);
+    const int f = (int)(e / ((int64_t)pb.K * pb.N * 8));
+    if (k >= L.ndir[f]) continue;
+    const double d = B.J[e] - B.BZ[e];
+    v[1] += B.Y[e] * d + 0.5 * B.rho[k] * d * d;
+  }
+  block_sum_vec<2>(v, red);
+  if (threadIdx.x == 0) {
+    B.trace[4 * iter] = v[0];
+    B.trace[4 * iter + 1] = v[0] + v[1];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_subband_cost(Problem pb, Layout L, Buffers B, double *out) {
+  __shared__ double red[1][kBlock / 64];
+  const int f = blockIdx.x;
+  double v[1] = {0.0};
+  for (int t = L.tile_off[f] + threadIdx.x; t < L.tile_off[f + 1]; t += kBlock) v[0] += B.cost_part[t];
+  block_sum_vec<1>(v, red);
+  if (threadIdx.x == 0) out[f] = v[0];
+}
+
+// Unitary polar factor of a 2x2 complex matrix in closed form: with A = W S V^H and
+// e^{i phi} = det A / |det A|, A + e^{i phi} adj(A)^H = (s1 + s2) W V^H.
+__device__ void polar2(const double *a, double *u) {
+  const double ar = a[0], ai = a[1], br = a[2], bi = a[3], cr = a[4], ci = a[5], dr = a[6], di = a[7];
+  double detr = ar * dr - ai * di - (br * cr - bi * ci);
+  double deti = ar * di + ai * dr - (br * ci + bi * cr);
+  const double dn = sqrt(detr * detr + deti * deti);
+  double er = 1.0, ei = 0.0;
+  if (dn > 0.0) { er = detr / dn; ei = deti / dn; }
+  // adj(A)^H = [[conj d, -conj c], [-conj b, conj a]]
+  const double hr[4] = {dr, -cr, -br, ar}, hi[4] = {-di, ci, bi, -ai};
+  double m[8];
+  const double src[8] = {ar, ai, br, bi, cr, ci, dr, di};
+  double s = 0.0;
+  for (int e = 0; e < 4; ++e) {
+    m[2 * e] = src[2 * e] + er * hr[e] - ei * hi[e];
+    m[2 * e + 1] = src[2 * e + 1] + er * hi[e] + ei * hr[e];
+    s += m[2 * e] * m[2 * e] + m[2 * e + 1] * m[2 * e + 1];
+  }
+  const double scale = (s > 0.0) ? sqrt(2.0 / s) : 0.0;
+  for (int e = 0; e < 8; ++e) u[e] = m[e] * scale;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gpa(Problem pb, Layout L, Buffers B, int rounds) {
+  extern __shared__ double ref[];   // [N*8]
+  __shared__ double red[8][kBlock / 64];
+  __shared__ double U[8];
+  const int k = blockIdx.x, N = pb.N, P = pb.P;
+  int cnt = 0, mid = -1;
+  for (int f = 0; f < P; ++f) cnt += (L.ndir[f] > k);
+  if (cnt == 0) return;
+  for (int f = 0, c = 0; f < P; ++f)
+    if (L.ndir[f] > k) { if (c == cnt / 2) mid = f; ++c; }
+  for (int e = threadIdx.x; e < 8 * N; e += kBlock)
+    ref[e] = B.J[((int64_t)mid * pb.K + k) * N * 8 + e];
+  __syncthreads();
+  for (int r = 0; r < rounds; ++r) {
+    for (int f = 0; f < P; ++f) {
+      if (L.ndir[f] <= k) continue;
+      double *Jf = B.J + ((int64_t)f * pb.K + k) * N * 8;
+      // A = J_f^H ref = sum_p J_fp^H ref_p
+      double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int p = threadIdx.x; p < N; p += kBlock) {
+        const double *x = Jf + 8 * p, *y = ref + 8 * p;
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j)
+            for (int t = 0; t < 2; ++t) {
+              const double xr = x[(t * 2 + i) * 2], xi = -x[(t * 2 + i) * 2 + 1];
+              const double yr = y[(t * 2 + j) * 2], yi = y[(t * 2 + j) * 2 + 1];
+              v[(i * 2 + j) * 2] += xr * yr - xi * yi;
+              v[(i * 2 + j) * 2 + 1] += xr * yi + xi * yr;
+            }
+      }
+      block_sum_vec<8>(v, red);
+      if (threadIdx.x == 0) polar2(v, U);
+      __syncthreads();
+      for (int p = threadIdx.x; p < N; p += kBlock) {
+        double x[8], y[8];
+        for (int e = 0; e < 8; ++e) x[e] = Jf[8 * p + e];
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) {
+            double re = 0.0, im = 0.0;
+            for (int t = 0; t < 2; ++t) {
+              const double xr = x[(i * 2 + t) * 2], xi = x[(i * 2 + t) * 2 + 1];
+              const double ur = U[(t * 2 + j) * 2], ui = U[(t * 2 + j) * 2 + 1];
+              re += xr * ur - xi * ui;
+              im += xr * ui + xi * ur;
+            }
+            y[(i * 2 + j) * 2] = re;
+            y[(i * 2 + j) * 2 + 1] = im;
+          }
+        for (int e = 0; e < 8; ++e) Jf[8 * p + e] = y[e];
+      }
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < 8 * N; e += kBlock) {
+      double s = 0.0;
+      for (int f = 0; f < P; ++f)
+        if (L.ndir[f] > k) s += B.J[((int64_t)f * pb.K + k) * N * 8 + e] / cnt;
+      ref[e] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// one workgroup per direction: Z_k = W_k (J + Y/rho); dual partial ||Z_new - Z_old||^2
+__global__ __launch_bounds__(kBlock) void k_z_fit(Problem pb, Layout L, Buffers B) {
+  __shared__ double red[1][kBlock / 64];
+  const int k = blockIdx.x, N = pb.N, P = pb.P, Q = pb.Q;
+  const double rho = B.rho[k];
+  const double *W = B.fitw + (int64_t)k * Q * P;
+  double dz = 0.0;
+  for (int e = threadIdx.x; e < 8 * N; e += kBlock) {
+    double z[8];
+    for (int l = 0; l < Q; ++l) z[l] = 0.0;
+    for (int f = 0; f < P; ++f) {
+      if (L.ndir[f] <= k) continue;
+      const int64_t o = ((int64_t)f * pb.K + k) * N * 8 + e;
+      const double x = (rho > 0.0) ? B.J[o] + B.Y[o] / rho : B.J[o];
+      for (int l = 0; l < Q; ++l) z[l] += W[l * P + f] * x;
+    }
+    for (int l = 0; l < Q; ++l) {
+      const int64_t o = ((int64_t)k * Q + l) * N * 8 + e;
+      const double d = z[l] - B.Z[o];
+      dz += d * d;
+      B.Z[o] = z[l];
+    }
+  }
+  double v[1] = {dz};
+  block_sum_vec<1>(v, red);
+  if (threadIdx.x == 0) B.scratch[(int64_t)pb.P * pb.K + k] = v[0];
+}
+
+// grid (P, K): B_f Z_k, dual ascent, primal partial ||J - BZ||^2
+__global__ __launch_bounds__(kBlock) void k_y_update(Problem pb, Layout L, Buffers B) {
+  __shared__ double red[1][kBlock / 64];
+  const int f = blockIdx.x, k = blockIdx.y, N = pb.N, Q = pb.Q;
+  const int64_t slot = (int64_t)f * pb.K + k;
+  if (k >= L.ndir[f]) {
+    if (threadIdx.x == 0) B.scratch[slot] = -1.0;
+    return;
+  }
+  const double rho = B.rho[k];
+  double pr = 0.0;
+  for (int e = threadIdx.x; e < 8 * N; e += kBlock) {
+    double bz = 0.0;
+    for (int l = 0; l < Q; ++l) bz += B.basis[f * Q + l] * B.Z[((int64_t)k * Q + l) * N * 8 + e];
+    const int64_t o = slot * N * 8 + e;
+    B.BZ[o] = bz;
+    const double t = B.J[o] - bz;
+    B.Y[o] += rho * t;
+    pr += t * t;
+  }
+  double v[1] = {pr};
+  block_sum_vec<1>(v, red);
+  if (threadIdx.x == 0) B.scratch[slot] = v[0];
+}
+
+__global__ void k_residuals(Problem pb, Buffers B, int iter) {
+  if (threadIdx.x != 0) return;
+  double ps = 0.0, ds = 0.0;
+  int pc = 0, dc = 0;
+  for (int64_t i = 0; i < (int64_t)pb.P * pb.K; ++i)
+    if (B.scratch[i] >= 0.0) { ps += sqrt(B.scratch[i]) / sqrt(4.0 * pb.N); ++pc; }
+  for (int k = 0; k < pb.K; ++k) {
+    ds += sqrt(B.scratch[(int64_t)pb.P * pb.K + k]) / sqrt(4.0 * pb.Q * pb.N);
+    ++dc;
+  }
+  B.trace[4 * iter + 2] = pc ? ps / pc : 0.0;
+  B.trace[4 * iter + 3] = dc ? ds / dc : 0.0;
+}
+
+__global__ void k_fill_identity(double *J, int64_t nblocks) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nblocks) return;
+  double *b = J + 8 * i;
+  b[0] = 1.0; b[1] = 0.0; b[2] = 0.0; b[3] = 0.0;
+  b[4] = 0.0; b[5] = 0.0; b[6] = 1.0; b[7] = 0.0;
+}
+
+__global__ void k_zero(double *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+}  // namespace
+
+hipError_t launch_basis_setup(const Problem &pb, const double *freq, double f0, const int32_t *ndir,
+                              double *basis, double *fitw, int *rank_fail, hipStream_t s) {
+  hipLaunchKernelGGL(k_basis_setup, dim3(1), dim3(64), 0, s, pb.P, pb.Q, pb.K, freq, f0, ndir, basis,
+                     fitw, rank_fail);
+  return hipGetLastError();
+}
+
+hipError_t launch_penalty_trace(const Problem &pb, const Layout &L, const Buffers &B, int iter,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_penalty_trace, dim3(1), dim3(kBlock), 0, s, pb, L, B, iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_subband_cost(const Problem &pb, const Layout &L, const Buffers &B, double *out,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_subband_cost, dim3(pb.P), dim3(kBlock), 0, s, pb, L, B, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gpa(const Problem &pb, const Layout &L, const Buffers &B, int rounds, hipStream_t s) {
+  const size_t lds = (size_t)pb.N * 8 * sizeof(double);
+  hipLaunchKernelGGL(k_gpa, dim3(pb.K), dim3(kBlock), lds, s, pb, L, B, rounds);
+  return hipGetLastError();
+}
+
+hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, int iter,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_z_fit, dim3(pb.K), dim3(kBlock), 0, s, pb, L, B);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_y_update, dim3(pb.P, pb.K), dim3(kBlock), 0, s, pb, L, B);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_residuals, dim3(1), dim3(64), 0, s, pb, B, iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_identity(double *J, int64_t nblocks, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_identity, dim3((unsigned)((nblocks + 255) / 256)), dim3(256), 0, s, J, nblocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(double *p, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace calib

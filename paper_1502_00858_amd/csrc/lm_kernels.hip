@@ -1,0 +1,490 @@
+// Levenberg-Marquardt kernels of the local step (minimisation M1 of Section 3), one subband per
+// workgroup except where stated, all in FP64.
+//
+// Real parameters of one direction: theta[p*8 + (i*2+j)*2 + {0:Re,1:Im}] for the entries
+// J_p[i][j].  The objective is the augmented Lagrangian
+//   L(J) = sum_b sum_s ||V_k - c_s J_p J_q^H||^2 + Re tr(Y^H (J - BZ)) + rho/2 ||J - BZ||^2
+// (linear term as in the trace form of Appendix A).  Its Euclidean gradient, packed as
+// d/dRe + i d/dIm per entry, is
+//   G_p = -2 sum_{q>p} D_pq J_q - 2 sum_{c<p} D_cp^H J_c + Y_p + rho (J_p - BZ_p),
+// with D_b = sum_s conj(c_s) r_s from the streaming pass.  Because the coherency is a scalar
+// times I2 (Section 2) and J is time invariant, the Gauss-Newton matrix 2 Jac^T Jac depends on
+// the data only through S_b = sum_s |c_s|^2:
+//   diagonal block of station p: for each row i of J_p, the real 4x4 form of
+//       2 Q_p,  Q_p = sum_{c adjacent p} S_pc J_c^H J_c
+//   off-diagonal block of baseline (a,b), a<b, entry (u of J_a, v of J_b):
+//       2 S_ab * [[Re w, Im w], [Im w, -Re w]][ri_u][ri_v],  w = J_a[i_u][j_v] J_b[i_v][j_u].
+// The damped system (H + (rho + lambda) I) delta = -G is solved by a Cholesky factorisation
+// of the matrix augmented with -G^T as an extra row (so the forward substitution falls out of
+// the factorisation), followed by a blocked back substitution.
+#include "calib_internal.h"
+
+namespace calib {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Reduce NV values per thread over the workgroup in a fixed order; result in out[] of every
+// thread (broadcast through LDS).
+template <int NV>
+__device__ inline void block_sum_vec(double *v, double (*red)[kBlock / 64]) {
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double s = wave_sum(v[i]);
+    if ((threadIdx.x & 63) == 0) red[i][w] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < kBlock / 64; ++j) s += red[i][j];
+    v[i] = s;
+  }
+  __syncthreads();
+}
+
+__device__ inline double readlane_d(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ inline const double *jdir(const Buffers &B, const Problem &pb, int f, int k) {
+  return B.J + ((int64_t)f * pb.K + k) * pb.N * 8;
+}
+
+// data cost of subband f from its tiles' partials (fixed order) + consensus terms at Jx
+__device__ inline double objective(const Problem &pb, const Layout &L, const Buffers &B, int f,
+                                   int k, int unreg, const double *Jx, double (*red)[kBlock / 64]) {
+  double acc[1] = {0.0};
+  for (int t = L.tile_off[f] + threadIdx.x; t < L.tile_off[f + 1]; t += kBlock) acc[0] += B.cost_part[t];
+  double pen = 0.0;
+  if (!unreg) {
+    const double rho = B.rho[k];
+    const int64_t o = ((int64_t)f * pb.K + k) * pb.N * 8;
+    for (int e = threadIdx.x; e < 8 * pb.N; e += kBlock) {
+      const double d = Jx[e] - B.BZ[o + e];
+      pen += B.Y[o + e] * d + 0.5 * rho * d * d;
+    }
+  }
+  double v[2] = {acc[0], pen};
+  block_sum_vec<2>(v, red);
+  return v[0] + v[1];
+}
+
+__global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffers B, int k, int unreg) {
+  __shared__ double red[2][kBlock / 64];
+  const int f = blockIdx.x;
+  LmState *st = B.lm + f;
+  if (k >= L.ndir[f]) {
+    if (threadIdx.x == 0) st->active = 0;
+    return;
+  }
+  const double *J = jdir(B, pb, f, k);
+  const double F = objective(pb, L, B, f, k, unreg, J, red);
+  // largest diagonal entry of H_GN + rho I: 2 sum_c S_pc (|J_c[0][j]|^2 + |J_c[1][j]|^2) + rho
+  const int nb = L.nb[f];
+  double dmax = 0.0;
+  for (int p = threadIdx.x; p < pb.N; p += kBlock) {
+    double d0 = 0.0, d1 = 0.0;
+    for (int a = L.adj_off[f * pb.N + p]; a < L.adj_off[f * pb.N + p + 1]; ++a) {
+      const int gb = L.adj_b[a];
+      const int o = L.adj_o[a] >= 0 ? L.adj_o[a] : -1 - L.adj_o[a];
+      const double S = B.Sb[L.sb_off[f] + (int64_t)k * nb + (gb - L.bl_off[f])];
+      const double *Jo = J + 8 * o;
+      d0 += S * (Jo[0] * Jo[0] + Jo[1] * Jo[1] + Jo[4] * Jo[4] + Jo[5] * Jo[5]);
+      d1 += S * (Jo[2] * Jo[2] + Jo[3] * Jo[3] + Jo[6] * Jo[6] + Jo[7] * Jo[7]);
+    }
+    dmax = fmax(dmax, 2.0 * fmax(d0, d1));
+  }
+  __shared__ double mx[kBlock / 64];
+  dmax = wave_max(dmax);
+  if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = dmax;
+  for (int e = threadIdx.x; e < 8 * pb.N; e += kBlock) B.Jstart[(int64_t)f * pb.N * 8 + e] = J[e];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int i = 0; i < kBlock / 64; ++i) m = fmax(m, mx[i]);
+    m += unreg ? 0.0 : B.rho[k];
+    st->F = F;
+    st->lambda = kLmTau * m;
+    st->nu = 2.0;
+    st->accepted = 0;
+    st->active = 1;
+    st->chol_ok = 0;
+    st->ell = 0.0;
+  }
+}
+
+// One workgroup per (subband, station row-block); blockIdx.y == N writes the padding rows.
+__global__ __launch_bounds__(kBlock) void k_assemble(Problem pb, Layout L, Buffers B, int k, int unreg) {
+  __shared__ double red[12][kBlock / 64];
+  __shared__ double qg[12];
+  const int f = blockIdx.x, p = blockIdx.y;
+  if (k >= L.ndir[f]) return;
+  const int N = pb.N, nf = pb.nf, npad = pb.npad;
+  double *A = B.H + (int64_t)f * npad * nf;
+  const double lam = B.lm[f].lambda;
+  const double rho = unreg ? 0.0 : B.rho[k];
+  if (p == N) {
+    // identity on padded factor columns, zero padding rows below the right-hand side row
+    for (int r = 8 * N; r < nf; ++r)
+      for (int c = threadIdx.x; c < nf; c += kBlock) A[(int64_t)r * nf + c] = (c == r) ? 1.0 : 0.0;
+    for (int c = 8 * N + threadIdx.x; c < nf; c += kBlock) A[(int64_t)nf * nf + c] = 0.0;
+    for (int r = nf + 1; r < npad; ++r)
+      for (int c = threadIdx.x; c < nf; c += kBlock) A[(int64_t)r * nf + c] = 0.0;
+    return;
+  }
+  const double *J = jdir(B, pb, f, k);
+  const int nb = L.nb[f];
+  const double *Sb = B.Sb + L.sb_off[f] + (int64_t)k * nb - L.bl_off[f];   // indexed by global gb
+  // Q_p (q00, q11, Re q01, Im q01) and the data part of the gradient of station p
+  double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int a = L.adj_off[f * N + p] + threadIdx.x; a < L.adj_off[f * N + p + 1]; a += kBlock) {
+    const int gb = L.adj_b[a];
+    const bool first = L.adj_o[a] >= 0;
+    const int o = first ? L.adj_o[a] : -1 - L.adj_o[a];
+    const double S = Sb[gb];
+    const double *Jo = J + 8 * o;
+    v[0] += S * (Jo[0] * Jo[0] + Jo[1] * Jo[1] + Jo[4] * Jo[4] + Jo[5] * Jo[5]);
+    v[1] += S * (Jo[2] * Jo[2] + Jo[3] * Jo[3] + Jo[6] * Jo[6] + Jo[7] * Jo[7]);
+    // (J^H J)[0][1] = conj(J00) J01 + conj(J10) J11
+    v[2] += S * (Jo[0] * Jo[2] + Jo[1] * Jo[3] + Jo[4] * Jo[6] + Jo[5] * Jo[7]);
+    v[3] += S * (Jo[0] * Jo[3] - Jo[1] * Jo[2] + Jo[4] * Jo[7] - Jo[5] * Jo[6]);
+    const double *D = B.Dcur + 8 * (int64_t)gb;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          if (first) {   // (D J_o)[i][j] = sum_t D[i][t] J_o[t][j]
+            const double dr = D[(i * 2 + t) * 2], di = D[(i * 2 + t) * 2 + 1];
+            const double jr = Jo[(t * 2 + j) * 2], ji = Jo[(t * 2 + j) * 2 + 1];
+            re += dr * jr - di * ji;
+            im += dr * ji + di * jr;
+          } else {       // (D^H J_o)[i][j] = sum_t conj(D[t][i]) J_o[t][j]
+            const double dr = D[(t * 2 + i) * 2], di = -D[(t * 2 + i) * 2 + 1];
+            const double jr = Jo[(t * 2 + j) * 2], ji = Jo[(t * 2 + j) * 2 + 1];
+            re += dr * jr - di * ji;
+            im += dr * ji + di * jr;
+          }
+        }
+        v[4 + (i * 2 + j) * 2] += -2.0 * re;
+        v[4 + (i * 2 + j) * 2 + 1] += -2.0 * im;
+      }
+  }
+  block_sum_vec<12>(v, red);
+  if (threadIdx.x < 12) {
+    double x = v[threadIdx.x];
+    if (threadIdx.x >= 4 && !unreg) {
+      const int e = threadIdx.x - 4;
+      const int64_t o = ((int64_t)f * pb.K + k) * N * 8 + 8 * p;
+      x += B.Y[o + e] + rho * (J[8 * p + e] - B.BZ[o + e]);
+    }
+    qg[threadIdx.x] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    B.G[(int64_t)f * nf + 8 * p + threadIdx.x] = qg[4 + threadIdx.x];
+    A[(int64_t)nf * nf + 8 * p + threadIdx.x] = -qg[4 + threadIdx.x];
+  }
+  const double q00 = qg[0], q11 = qg[1], q01r = qg[2], q01i = qg[3];
+  const int ncol = 8 * p + 8;
+  const double *Jp = J + 8 * p;
+  const int32_t *bidx = L.bidx + (int64_t)f * N * N;
+  for (int idx = threadIdx.x; idx < 8 * ncol; idx += kBlock) {
+    const int v8 = idx / ncol, c = idx - v8 * ncol;
+    const int iv = v8 >> 2, jv = (v8 >> 1) & 1, rv = v8 & 1;
+    double val;
+    if (c < 8 * p) {
+      const int a = c >> 3, u = c & 7;
+      const int iu = u >> 2, ju = (u >> 1) & 1, ru = u & 1;
+      const int gb = bidx[a * N + p];
+      if (gb < 0) {
+        val = 0.0;
+      } else {
+        const double *Ja = J + 8 * a;
+        const double ar = Ja[(iu * 2 + jv) * 2], ai = Ja[(iu * 2 + jv) * 2 + 1];
+        const double br = Jp[(iv * 2 + ju) * 2], bi = Jp[(iv * 2 + ju) * 2 + 1];
+        const double wr = ar * br - ai * bi, wi = ar * bi + ai * br;
+        const double g = (ru == 0) ? (rv == 0 ? wr : wi) : (rv == 0 ? wi : -wr);
+        val = 2.0 * Sb[gb] * g;
+      }
+    } else {
+      const int u = c - 8 * p;
+      const int iu = u >> 2, ju = (u >> 1) & 1, ru = u & 1;
+      if (iu != iv) {
+        val = 0.0;
+      } else {
+        // g' = Q[jv][ju] (row index v, column index u)
+        double gr, gi;
+        if (jv == ju) { gr = (jv == 0) ? q00 : q11; gi = 0.0; }
+        else if (jv == 0) { gr = q01r; gi = q01i; }      // Q[0][1]
+        else { gr = q01r; gi = -q01i; }                  // Q[1][0] = conj(Q[0][1])
+        val = 2.0 * ((rv == 0) ? (ru == 0 ? gr : gi) : (ru == 0 ? -gi : gr));
+        if (u == v8) val += rho + lam;
+      }
+    }
+    A[(int64_t)(8 * p + v8) * nf + c] = val;
+  }
+}
+
+// Factor the jb x jb diagonal block held column-major in LDS (leading dimension ld) with one
+// wavefront; lane i keeps row i in registers.  Returns false on a non-positive pivot.
+template <int JB>
+__device__ bool factor_diag(double *Pn, int ld) {
+  const int lane = threadIdx.x & 63;
+  double a[JB];
+#pragma unroll
+  for (int c = 0; c < JB; ++c) a[c] = (lane < JB && c <= lane) ? Pn[c * ld + lane] : 0.0;
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < JB; ++c) {
+    const double d = readlane_d(a[c], c);
+    if (!(d > 0.0) || !isfinite(d)) { ok = false; break; }
+    const double lc = sqrt(d);
+    const double li = (lane == c) ? lc : (lane > c ? a[c] / lc : 0.0);
+    a[c] = li;
+#pragma unroll
+    for (int c2 = c + 1; c2 < JB; ++c2) {
+      const double l2 = readlane_d(li, c2);
+      if (lane >= c2) a[c2] -= li * l2;
+    }
+  }
+  if (ok && lane < JB) {
+#pragma unroll
+    for (int c = 0; c < JB; ++c)
+      if (c <= lane) Pn[c * ld + lane] = a[c];
+  }
+  return ok;
+}
+
+// Rows below the diagonal block: x L11^T = a by forward substitution (thread per row).
+template <int JB>
+__device__ void trsm_rows(double *Pn, int ld, int m) {
+  for (int r = JB + threadIdx.x; r < m; r += kBlock) {
+    double x[JB];
+#pragma unroll
+    for (int c = 0; c < JB; ++c) x[c] = Pn[c * ld + r];
+#pragma unroll
+    for (int c = 0; c < JB; ++c) {
+      x[c] /= Pn[c * ld + c];
+#pragma unroll
+      for (int c2 = c + 1; c2 < JB; ++c2) x[c2] -= x[c] * Pn[c * ld + c2];
+    }
+#pragma unroll
+    for (int c = 0; c < JB; ++c) Pn[c * ld + r] = x[c];
+  }
+}
+
+// Cholesky factorisation + solve, one workgroup per subband.  The panel (rows j0..npad-1,
+// NB columns) is staged column-major in LDS; the trailing update A22 -= L21 L21^T runs on
+// v_mfma_f64_16x16x4f64 over 16x16 tiles of the lower triangle.
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_chol_solve(Problem pb, Buffers B, int k, const int32_t *ndir) {
+  extern __shared__ double Pn[];   // [NB][npad] panel, then reused as [nf] solution vector
+  __shared__ int fail;
+  __shared__ double red[2][kBlock / 64];
+  const int f = blockIdx.x;
+  if (k >= ndir[f]) return;
+  const int nf = pb.nf, npad = pb.npad;
+  double *A = B.H + (int64_t)f * npad * nf;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) fail = 0;
+  __syncthreads();
+
+  for (int j0 = 0; j0 < nf; j0 += NB) {
+    const int jb = (nf - j0 < NB) ? (nf - j0) : NB;   // NB or 16
+    const int m = npad - j0;
+    for (int idx = threadIdx.x; idx < m * jb; idx += kBlock) {
+      const int r = idx / jb, c = idx - r * jb;
+      Pn[c * npad + r] = A[(int64_t)(j0 + r) * nf + j0 + c];
+    }
+    __syncthreads();
+    if (wave == 0) {
+      const bool ok = (jb == NB) ? factor_diag<NB>(Pn, npad) : factor_diag<16>(Pn, npad);
+      if (!ok && lane == 0) fail = 1;
+    }
+    __syncthreads();
+    if (fail) break;
+    if (jb == NB) trsm_rows<NB>(Pn, npad, m); else trsm_rows<16>(Pn, npad, m);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < m * jb; idx += kBlock) {
+      const int r = idx / jb, c = idx - r * jb;
+      if (r >= c) A[(int64_t)(j0 + r) * nf + j0 + c] = Pn[c * npad + r];
+    }
+    // trailing update over 16x16 tiles (row tile I >= column tile Jt)
+    const int jt0 = (j0 + jb) >> 4, nct = nf >> 4, nrt = npad >> 4;
+    int cnt = 0;
+    for (int Jt = jt0; Jt < nct; ++Jt) {
+      for (int I = Jt; I < nrt; ++I, ++cnt) {
+        if ((cnt & 3) != wave) continue;
+        // accumulator element r of lane l holds D[4r + l/16][l%16] (v_mfma_f64_16x16x4f64)
+        const int row = I * 16 + (lane >> 4), col = Jt * 16 + (lane & 15);
+        d4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = A[(int64_t)(row + 4 * r) * nf + col];
+        const int ia = I * 16 - j0 + (lane & 15), ib = Jt * 16 - j0 + (lane & 15);
+        for (int kk = 0; kk < jb; kk += 4) {
+          const int kc = kk + (lane >> 4);
+          const double av = -Pn[kc * npad + ia];
+          const double bv = Pn[kc * npad + ib];
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) A[(int64_t)(row + 4 * r) * nf + col] = acc[r];
+      }
+    }
+    __syncthreads();
+  }
+  LmState *st = B.lm + f;
+  if (fail) {
+    if (threadIdx.x == 0) st->chol_ok = 0;
+    return;
+  }
+  // back substitution L^T x = y, y = row nf of the factor; 16-column blocks from the end
+  double *t = Pn;   // [nf]
+  for (int c = threadIdx.x; c < nf; c += kBlock) t[c] = A[(int64_t)nf * nf + c];
+  __syncthreads();
+  for (int j0 = nf - 16; j0 >= 0; j0 -= 16) {
+    if (wave == 0) {
+      // lane i < 16 owns t[j0+i]; L11^T x = t (upper triangular) solved bottom-up
+      double ti = lane < 16 ? t[j0 + lane] : 0.0;
+      for (int c = 15; c >= 0; --c) {
+        const double xc = readlane_d(ti, c) / A[(int64_t)(j0 + c) * nf + j0 + c];
+        if (lane == c) ti = xc;
+        if (lane < c) ti -= A[(int64_t)(j0 + c) * nf + j0 + lane] * xc;
+      }
+      if (lane < 16) t[j0 + lane] = ti;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < j0; c += kBlock) {
+      double s = t[c];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s -= A[(int64_t)(j0 + r) * nf + c] * t[j0 + r];
+      t[c] = s;
+    }
+    __syncthreads();
+  }
+  // delta, predicted decrease ell = delta.(lambda delta - G)/2, trial point
+  const double lam = st->lambda;
+  const int n8 = 8 * pb.N;
+  double ell = 0.0;
+  const double *G = B.G + (int64_t)f * nf;
+  const double *J = B.J + ((int64_t)f * pb.K + k) * pb.N * 8;
+  for (int e = threadIdx.x; e < n8; e += kBlock) {
+    const double d = t[e];
+    ell += d * (lam * d - G[e]);
+    B.delta[(int64_t)f * nf + e] = d;
+    B.Jtrial[(int64_t)f * n8 + e] = J[e] + d;
+  }
+  double v[1] = {ell};
+  block_sum_vec<1>(v, red);
+  if (threadIdx.x == 0) {
+    st->ell = 0.5 * v[0];
+    st->chol_ok = 1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_lm_update(Problem pb, Layout L, Buffers B, int k, int unreg,
+                                                      double *lm_trace, int it, int lm_iters) {
+  __shared__ double red[2][kBlock / 64];
+  __shared__ int acc;
+  const int f = blockIdx.x;
+  if (k >= L.ndir[f]) return;
+  LmState *st = B.lm + f;
+  int ok = st->chol_ok;
+  double Fn = 0.0;
+  if (ok) Fn = objective(pb, L, B, f, k, unreg, B.Jtrial + (int64_t)f * pb.N * 8, red);
+  if (threadIdx.x == 0) {
+    int a = 0;
+    if (ok) {
+      const double ell = st->ell, F = st->F;
+      if (ell > 0.0 && F - Fn > 0.0) {
+        const double gain = (F - Fn) / ell;
+        const double t = 2.0 * gain - 1.0;
+        st->lambda *= fmax(1.0 / 3.0, 1.0 - t * t * t);
+        st->nu = 2.0;
+        st->F = Fn;
+        st->accepted += 1;
+        a = 1;
+      }
+    }
+    if (!a) {
+      st->lambda *= st->nu;
+      st->nu *= 2.0;
+    }
+    st->Fnew = Fn;
+    acc = a;
+    if (lm_trace) {
+      double *tr = lm_trace + 3 * ((int64_t)(f * pb.K + k) * lm_iters + it);
+      tr[0] = st->F;
+      tr[1] = st->lambda;
+      tr[2] = a;
+    }
+  }
+  __syncthreads();
+  if (acc) {
+    double *J = B.J + ((int64_t)f * pb.K + k) * pb.N * 8;
+    for (int e = threadIdx.x; e < 8 * pb.N; e += kBlock) J[e] = B.Jtrial[(int64_t)f * pb.N * 8 + e];
+    const int64_t b0 = 8 * (int64_t)L.bl_off[f], b1 = b0 + 8 * (int64_t)L.nb[f];
+    for (int64_t e = b0 + threadIdx.x; e < b1; e += kBlock) B.Dcur[e] = B.Dtrial[e];
+  }
+}
+
+}  // namespace
+
+hipError_t launch_lm_begin(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_lm_begin, dim3(pb.P), dim3(kBlock), 0, s, pb, L, B, k, unreg);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_assemble, dim3(pb.P, pb.N + 1), dim3(kBlock), 0, s, pb, L, B, k, unreg);
+  return hipGetLastError();
+}
+
+int chol_panel_width(const Problem &pb) {
+  return (32 * pb.npad * 8 <= 150 * 1024) ? 32 : 16;
+}
+
+hipError_t launch_chol_solve_nd(const Problem &pb, const Buffers &B, int k, const int32_t *ndir,
+                                hipStream_t s) {
+  const int nb = chol_panel_width(pb);
+  size_t lds = (size_t)nb * pb.npad * sizeof(double);
+  if (lds < (size_t)pb.nf * sizeof(double)) lds = (size_t)pb.nf * sizeof(double);
+  if (nb == 32) {
+    hipFuncSetAttribute((const void *)k_chol_solve<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_chol_solve<32>, dim3(pb.P), dim3(kBlock), lds, s, pb, B, k, ndir);
+  } else {
+    hipFuncSetAttribute((const void *)k_chol_solve<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_chol_solve<16>, dim3(pb.P), dim3(kBlock), lds, s, pb, B, k, ndir);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_lm_update_tr(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
+                               double *lm_trace, int it, int lm_iters, hipStream_t s) {
+  hipLaunchKernelGGL(k_lm_update, dim3(pb.P), dim3(kBlock), 0, s, pb, L, B, k, unreg, lm_trace, it,
+                     lm_iters);
+  return hipGetLastError();
+}
+
+}  // namespace calib

@@ -1,0 +1,359 @@
+// Streaming kernels of the local step: they read the packed visibilities / residuals and
+// coherencies once per pass, in the baseline-major layout, and reduce per-baseline statistics.
+//
+//   refresh : R = V - sum_k c_k J_kp J_kq^H            (Section 2 visibility model; the full
+//             residual at the start of a local step), plus the statistics of direction 0
+//   trial   : r = R - c_k (M_trial - M_start)          (one Levenberg-Marquardt trial point of
+//             direction k: the SAGE expectation V_k = R + c_k M_start of Section 3 minus the
+//             trial model), accumulating sum ||r||^2 and D_b = sum conj(c_k) r
+//   commit  : R <- R - c_k (M_final - M_start)         (end of direction k), plus the statistics
+//             of the next direction
+//
+// The coherency of an unpolarised source is a scalar times I2 (Section 2), so one complex value
+// per sample and direction is streamed.  The Jones matrices are time invariant over the interval
+// (Section 2), so the 2x2 products M = J_p J_q^H are formed once per baseline in FP64.
+//
+// Work decomposition: a tile is a run of kBlock/G consecutive baselines of one subband; G lanes
+// of a wavefront share a baseline and stride over its T*n_chan samples, so consecutive lanes
+// read consecutive 32-byte (float) or 64-byte (double) samples.  Per-baseline sums are reduced
+// across the G lanes with cross-lane shuffles in FP64; the per-tile cost is reduced through LDS
+// into one FP64 partial per tile, summed later in a fixed order (run-to-run deterministic).
+#include "calib_internal.h"
+
+namespace calib {
+
+namespace {
+
+enum { SM_REFRESH = 0, SM_TRIAL = 1, SM_COMMIT = 2 };
+
+__device__ inline void jjh(const double *__restrict__ a, const double *__restrict__ b, double *m) {
+  // m = a b^H for 2x2 complex matrices stored as 8 doubles (row-major, re/im interleaved)
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const double ar = a[(i * 2 + t) * 2], ai = a[(i * 2 + t) * 2 + 1];
+        const double br = b[(j * 2 + t) * 2], bi = b[(j * 2 + t) * 2 + 1];
+        re += ar * br + ai * bi;
+        im += ai * br - ar * bi;
+      }
+      m[(i * 2 + j) * 2] = re;
+      m[(i * 2 + j) * 2 + 1] = im;
+    }
+}
+
+template <typename T>
+__device__ inline void load8(const T *__restrict__ p, T *v);
+template <>
+__device__ inline void load8<float>(const float *__restrict__ p, float *v) {
+  const float4 a = reinterpret_cast<const float4 *>(p)[0];
+  const float4 b = reinterpret_cast<const float4 *>(p)[1];
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+}
+template <>
+__device__ inline void load8<double>(const double *__restrict__ p, double *v) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double2 a = reinterpret_cast<const double2 *>(p)[i];
+    v[2 * i] = a.x; v[2 * i + 1] = a.y;
+  }
+}
+template <typename T>
+__device__ inline void store8(T *__restrict__ p, const T *v);
+template <>
+__device__ inline void store8<float>(float *__restrict__ p, const float *v) {
+  reinterpret_cast<float4 *>(p)[0] = make_float4(v[0], v[1], v[2], v[3]);
+  reinterpret_cast<float4 *>(p)[1] = make_float4(v[4], v[5], v[6], v[7]);
+}
+template <>
+__device__ inline void store8<double>(double *__restrict__ p, const double *v) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) reinterpret_cast<double2 *>(p)[i] = make_double2(v[2 * i], v[2 * i + 1]);
+}
+
+template <typename T>
+__device__ inline void load2(const T *__restrict__ p, T &re, T &im) {
+  re = p[0];
+  im = p[1];
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the workgroup in a fixed order; the result is valid in thread 0.
+__device__ inline double block_sum(double v, double *red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < kBlock / 64; ++i) s += red[i];
+  return s;
+}
+
+template <typename T, int G, int MODE>
+__global__ __launch_bounds__(kBlock) void k_stream(Problem pb, Layout L, Buffers B, int k) {
+  constexpr int BPT = kBlock / G;
+  constexpr int MD = (MODE == SM_REFRESH) ? kMaxDirs : 1;
+  __shared__ T Msh[BPT][MD][8];
+  __shared__ double red[kBlock / 64];
+
+  const int tile = blockIdx.x;
+  const int f = L.tile_f[tile];
+  const int Kf = L.ndir[f];
+  if (MODE == SM_TRIAL && (k >= Kf || !B.lm[f].chol_ok)) return;   // uniform per workgroup
+  if (MODE == SM_COMMIT && k >= Kf) return;
+
+  const int nb = L.nb[f], spb = L.spb[f];
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+  const int bi = L.tile_b0[tile] + grp;
+  const bool live = bi < nb;
+  const int N = pb.N, K = pb.K;
+  const int kst = (MODE == SM_REFRESH) ? 0 : (MODE == SM_TRIAL ? k : (k + 1 < Kf ? k + 1 : 0));
+  const int64_t gb = (int64_t)L.bl_off[f] + bi;
+  const int64_t s0 = L.samp_off[f] + (int64_t)bi * spb;
+  const T *C = static_cast<const T *>(B.C);
+  const T *cst = C + 2 * (L.coh_off[f] + ((int64_t)kst * nb + bi) * spb);
+
+  T dM[8];
+  if (MODE == SM_REFRESH) {
+    if (live) {
+      const int p = L.bl_p[gb], q = L.bl_q[gb];
+      for (int l = lane; l < Kf; l += G) {
+        double m[8];
+        const double *Jl = B.J + ((int64_t)f * K + l) * N * 8;
+        jjh(Jl + 8 * p, Jl + 8 * q, m);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Msh[grp][l][e] = (T)m[e];
+      }
+    }
+    __syncthreads();
+  } else if (live) {
+    const int p = L.bl_p[gb], q = L.bl_q[gb];
+    const double *J1 = (MODE == SM_TRIAL) ? B.Jtrial + (int64_t)f * N * 8
+                                          : B.J + ((int64_t)f * K + k) * N * 8;
+    const double *J0 = B.Jstart + (int64_t)f * N * 8;
+    double m1[8], m0[8];
+    jjh(J1 + 8 * p, J1 + 8 * q, m1);
+    jjh(J0 + 8 * p, J0 + 8 * q, m0);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dM[e] = (T)(m1[e] - m0[e]);
+  }
+
+  double cost = 0.0;
+  double D[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (live) {
+    const T *V = static_cast<const T *>(B.V);
+    T *R = static_cast<T *>(B.R);
+    const T *ck = C + 2 * (L.coh_off[f] + ((int64_t)k * nb + bi) * spb);
+    for (int s = lane; s < spb; s += G) {
+      T r[8];
+      if (MODE == SM_REFRESH) {
+        load8<T>(V + 8 * (s0 + s), r);
+        for (int l = 0; l < Kf; ++l) {
+          T cr, ci;
+          load2<T>(C + 2 * (L.coh_off[f] + ((int64_t)l * nb + bi) * spb + s), cr, ci);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const T mr = Msh[grp][l][2 * e], mi = Msh[grp][l][2 * e + 1];
+            r[2 * e] -= cr * mr - ci * mi;
+            r[2 * e + 1] -= cr * mi + ci * mr;
+          }
+        }
+        store8<T>(R + 8 * (s0 + s), r);
+      } else {
+        load8<T>(R + 8 * (s0 + s), r);
+        T cr, ci;
+        load2<T>(ck + 2 * s, cr, ci);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          r[2 * e] -= cr * dM[2 * e] - ci * dM[2 * e + 1];
+          r[2 * e + 1] -= cr * dM[2 * e + 1] + ci * dM[2 * e];
+        }
+        if (MODE == SM_COMMIT) store8<T>(R + 8 * (s0 + s), r);
+      }
+      T ss = 0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ss += r[e] * r[e];
+      cost += (double)ss;
+      T cr, ci;
+      load2<T>(cst + 2 * s, cr, ci);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        // conj(c) * r
+        D[2 * e] += (double)(cr * r[2 * e] + ci * r[2 * e + 1]);
+        D[2 * e + 1] += (double)(cr * r[2 * e + 1] - ci * r[2 * e]);
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) D[e] += __shfl_xor(D[e], o, G);
+  }
+  if (live && lane == 0) {
+    double *Dout = (MODE == SM_TRIAL ? B.Dtrial : B.Dcur) + 8 * gb;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) Dout[e] = D[e];
+  }
+  const double tot = block_sum(cost, red);
+  if (threadIdx.x == 0) B.cost_part[tile] = tot;
+}
+
+template <typename T, int MODE>
+hipError_t launch_mode(const Problem &pb, const Layout &L, const Buffers &B, int k, hipStream_t s) {
+  dim3 grid(pb.ntiles), block(kBlock);
+  switch (pb.group) {
+    case 8: hipLaunchKernelGGL((k_stream<T, 8, MODE>), grid, block, 0, s, pb, L, B, k); break;
+    case 16: hipLaunchKernelGGL((k_stream<T, 16, MODE>), grid, block, 0, s, pb, L, B, k); break;
+    case 32: hipLaunchKernelGGL((k_stream<T, 32, MODE>), grid, block, 0, s, pb, L, B, k); break;
+    case 64: hipLaunchKernelGGL((k_stream<T, 64, MODE>), grid, block, 0, s, pb, L, B, k); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Pack one compact baseline per workgroup: copy its samples of V and of each direction's
+// coherencies from the caller's layout, and reduce S_b = sum_s |c_s|^2 per direction.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pack(Problem pb, Layout L, const T *vis, const T *coh,
+                                                 T *Vp, T *Cp, double *Sb, const int64_t *in_vis_off,
+                                                 const int64_t *in_coh_off, const int32_t *comp2full,
+                                                 const int32_t *comp_f, int *bad) {
+  __shared__ double red[kBlock / 64];
+  const int64_t gb = blockIdx.x;
+  const int f = comp_f[gb];
+  const int bi = (int)(gb - L.bl_off[f]);
+  const int bfull = comp2full[gb];
+  const int spb = L.spb[f], nb = L.nb[f], Kf = L.ndir[f];
+  const int B = pb.N * (pb.N - 1) / 2;
+  bool finite = true;
+  for (int s = threadIdx.x; s < spb; s += kBlock) {
+    T v[8];
+    load8<T>(vis + 8 * (in_vis_off[f] + (int64_t)bfull * spb + s), v);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) finite &= isfinite((double)v[e]);
+    store8<T>(Vp + 8 * (L.samp_off[f] + (int64_t)bi * spb + s), v);
+  }
+  for (int k = 0; k < Kf; ++k) {
+    double acc = 0.0;
+    for (int s = threadIdx.x; s < spb; s += kBlock) {
+      const T *src = coh + 2 * (in_coh_off[f] + ((int64_t)k * B + bfull) * spb + s);
+      const T cr = src[0], ci = src[1];
+      finite &= isfinite((double)cr) && isfinite((double)ci);
+      T *dst = Cp + 2 * (L.coh_off[f] + ((int64_t)k * nb + bi) * spb + s);
+      dst[0] = cr;
+      dst[1] = ci;
+      acc += (double)cr * (double)cr + (double)ci * (double)ci;
+    }
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) Sb[L.sb_off[f] + (int64_t)k * nb + bi] = tot;
+    __syncthreads();
+  }
+  if (!finite) atomicOr(bad, 1);
+}
+
+// Model visibilities in the caller's full layout (zero on flagged baselines).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_model(Problem pb, Layout L, Buffers B, T *out,
+                                                  const int64_t *full_off, const int32_t *full_bmap) {
+  __shared__ double Msh[kMaxDirs][8];
+  const int f = blockIdx.y;
+  const int b = blockIdx.x;
+  const int Bfull = pb.N * (pb.N - 1) / 2;
+  if (b >= Bfull) return;
+  const int spb = L.spb[f], Kf = L.ndir[f], nb = L.nb[f];
+  const int gb = full_bmap[(int64_t)f * Bfull + b];
+  T *o = out + 8 * (full_off[f] + (int64_t)b * spb);
+  if (gb < 0) {
+    for (int i = threadIdx.x; i < 8 * spb; i += kBlock) o[i] = (T)0;
+    return;
+  }
+  const int bi = gb - L.bl_off[f];
+  if (threadIdx.x < Kf) {
+    const int l = threadIdx.x;
+    const double *Jl = B.J + ((int64_t)f * pb.K + l) * pb.N * 8;
+    jjh(Jl + 8 * L.bl_p[gb], Jl + 8 * L.bl_q[gb], Msh[l]);
+  }
+  __syncthreads();
+  const T *C = static_cast<const T *>(B.C);
+  for (int s = threadIdx.x; s < spb; s += kBlock) {
+    double m[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int l = 0; l < Kf; ++l) {
+      const T *c = C + 2 * (L.coh_off[f] + ((int64_t)l * nb + bi) * spb + s);
+      const double cr = c[0], ci = c[1];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        m[2 * e] += cr * Msh[l][2 * e] - ci * Msh[l][2 * e + 1];
+        m[2 * e + 1] += cr * Msh[l][2 * e + 1] + ci * Msh[l][2 * e];
+      }
+    }
+    T v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (T)m[e];
+    store8<T>(o + 8 * s, v);
+  }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
+  return launch_mode<T, SM_REFRESH>(pb, L, B, 0, s);
+}
+template <typename T>
+hipError_t launch_trial(const Problem &pb, const Layout &L, const Buffers &B, int k, hipStream_t s) {
+  return launch_mode<T, SM_TRIAL>(pb, L, B, k, s);
+}
+template <typename T>
+hipError_t launch_commit(const Problem &pb, const Layout &L, const Buffers &B, int k, hipStream_t s) {
+  return launch_mode<T, SM_COMMIT>(pb, L, B, k, s);
+}
+template <typename T>
+hipError_t launch_model(const Problem &pb, const Layout &L, const Buffers &B, void *model_out,
+                        const int64_t *full_off, const int32_t *full_bmap, hipStream_t s) {
+  const int Bfull = pb.N * (pb.N - 1) / 2;
+  hipLaunchKernelGGL(k_model<T>, dim3(Bfull, pb.P), dim3(kBlock), 0, s, pb, L, B,
+                     static_cast<T *>(model_out), full_off, full_bmap);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_pack(const Problem &pb, const Layout &L, const void *vis, const void *coh,
+                       void *Vp, void *Cp, double *Sb, const int64_t *in_vis_off,
+                       const int64_t *in_coh_off, const int32_t *comp2full, int nb_total,
+                       int *bad_flag, hipStream_t s) {
+  if (nb_total == 0) return hipSuccess;
+  // comp_f is stored right after comp2full (see host packing)
+  hipLaunchKernelGGL(k_pack<T>, dim3(nb_total), dim3(kBlock), 0, s, pb, L,
+                     static_cast<const T *>(vis), static_cast<const T *>(coh), static_cast<T *>(Vp),
+                     static_cast<T *>(Cp), Sb, in_vis_off, in_coh_off, comp2full,
+                     comp2full + nb_total, bad_flag);
+  return hipGetLastError();
+}
+
+template hipError_t launch_refresh<float>(const Problem &, const Layout &, const Buffers &, hipStream_t);
+template hipError_t launch_refresh<double>(const Problem &, const Layout &, const Buffers &, hipStream_t);
+template hipError_t launch_trial<float>(const Problem &, const Layout &, const Buffers &, int, hipStream_t);
+template hipError_t launch_trial<double>(const Problem &, const Layout &, const Buffers &, int, hipStream_t);
+template hipError_t launch_commit<float>(const Problem &, const Layout &, const Buffers &, int, hipStream_t);
+template hipError_t launch_commit<double>(const Problem &, const Layout &, const Buffers &, int, hipStream_t);
+template hipError_t launch_model<float>(const Problem &, const Layout &, const Buffers &, void *,
+                                        const int64_t *, const int32_t *, hipStream_t);
+template hipError_t launch_model<double>(const Problem &, const Layout &, const Buffers &, void *,
+                                         const int64_t *, const int32_t *, hipStream_t);
+template hipError_t launch_pack<float>(const Problem &, const Layout &, const void *, const void *,
+                                       void *, void *, double *, const int64_t *, const int64_t *,
+                                       const int32_t *, int, int *, hipStream_t);
+template hipError_t launch_pack<double>(const Problem &, const Layout &, const void *, const void *,
+                                        void *, void *, double *, const int64_t *, const int64_t *,
+                                        const int32_t *, int, int *, hipStream_t);
+
+}  // namespace calib

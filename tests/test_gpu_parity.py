@@ -1,0 +1,189 @@
+"""GPU library against the FP64 CPU oracle on identical seeded inputs.
+
+Tolerances: FP64 path 1e-10 relative on predicted visibilities and per-iteration cost; the
+FP32-streaming path 1e-5 relative, compared with the oracle run on the FP32-rounded inputs.
+"""
+import numpy as np
+import pytest
+
+from conftest import rand_jones, tiny_cfg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cal():
+    from paper_1502_00858_amd import calib
+    calib.load()
+    return calib
+
+
+def _ctx(cal, d, precision=0, jones0=None, **kw):
+    vis, coh, flags = cal.device_inputs(d, precision)
+    J0 = None if jones0 is None else torch.from_numpy(np.ascontiguousarray(jones0)).cuda()
+    return cal.Calib(d, vis, coh, flags, J0, precision=precision, **kw)
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def test_model_vis_and_cost_fp64(cal, oracle_mod, synth_mod):
+    cfg = tiny_cfg(synth_mod, N=7, P=3, K=3, T=4, n_chan=3)
+    d = synth_mod.generate(cfg)
+    J = rand_jones(np.random.default_rng(11), cfg.P, cfg.K, cfg.N)
+    c = _ctx(cal, d, 0, jones0=J)
+    pb = oracle_mod.Problem(d)
+    model = c.get(cal.FIELD_MODEL_VIS).cpu().numpy()
+    assert _rel(model, pb.predict(J)) < 1e-12
+    cost = c.get(cal.FIELD_COST).cpu().numpy()
+    np.testing.assert_allclose(cost, pb.subband_cost(J), rtol=1e-11)
+
+
+def test_local_step_lm_trace_fp64(cal, oracle_mod, synth_mod):
+    cfg = tiny_cfg(synth_mod, N=6, P=3, K=2, T=3, n_chan=2, lm_iters=6)
+    d = synth_mod.generate(cfg)
+    J0 = synth_mod.identity_jones(cfg.P, cfg.K, cfg.N)
+    c = _ctx(cal, d, 0, lm_iters=6)
+    c.local_step(0)
+    Jg = c.get(cal.FIELD_J).cpu().numpy()
+    trg = c.get(cal.FIELD_LM_TRACE).cpu().numpy()
+    pb = oracle_mod.Problem(d, lm_iters=6)
+    z = np.zeros_like(J0)
+    Jo, tro = pb.local_step(J0, z, z, trace=True)
+    # per LM iteration: objective, damping, accept decision
+    np.testing.assert_array_equal(trg[..., 2], tro[:, 0, :, :, 2])
+    np.testing.assert_allclose(trg[..., 0], tro[:, 0, :, :, 0], rtol=1e-10)
+    # lambda is scaled by a function of the gain ratio (F - F_new)/ell, a quotient of the difference
+    # of two nearly equal objectives: its rounding is amplified by F/(F - F_new) (up to ~1e6 here)
+    np.testing.assert_allclose(trg[..., 1], tro[:, 0, :, :, 1], rtol=1e-5)
+    assert _rel(pb.predict(Jg), pb.predict(Jo)) < 1e-9
+
+
+def test_consensus_step_fp64(cal, oracle_mod, synth_mod):
+    cfg = tiny_cfg(synth_mod, N=5, P=6, Q=3, K=2, rho=2.0)
+    d = synth_mod.generate(cfg)
+    J = rand_jones(np.random.default_rng(12), cfg.P, cfg.K, cfg.N)
+    c = _ctx(cal, d, 0, jones0=J)
+    c.consensus_update(1)     # not the first iteration: no alignment
+    pb = oracle_mod.Problem(d)
+    Y, Z, BZ, pr, du = pb.consensus(J, np.zeros_like(J), np.zeros(pb.zshape(), np.complex128))
+    assert _rel(c.get(cal.FIELD_BZ).cpu().numpy(), BZ) < 1e-12
+    assert _rel(c.get(cal.FIELD_Y).cpu().numpy(), Y) < 1e-11
+    assert _rel(c.get(cal.FIELD_Z).cpu().numpy(), Z) < 1e-9
+    tr = c.get(cal.FIELD_TRACE)
+    assert abs(tr[1, 2] - pr) < 1e-12 * max(pr, 1) and abs(tr[1, 3] - du) < 1e-12 * max(du, 1)
+
+
+def test_gpa_first_iteration_fp64(cal, oracle_mod, synth_mod):
+    cfg = tiny_cfg(synth_mod, N=5, P=5, Q=2, K=2)
+    d = synth_mod.generate(cfg)
+    J = rand_jones(np.random.default_rng(13), cfg.P, cfg.K, cfg.N, scale=0.5)
+    c = _ctx(cal, d, 0, jones0=J)
+    c.consensus_update(0)
+    pb = oracle_mod.Problem(d)
+    Ja = pb.gpa(J, rounds=3)
+    assert _rel(c.get(cal.FIELD_J).cpu().numpy(), Ja) < 1e-11
+
+
+def test_admm_c1_fp64(cal, oracle_mod, synth_mod):
+    cfg = synth_mod.named_config("c1")
+    d = synth_mod.generate(cfg)
+    c = _ctx(cal, d, 0, lm_iters=cfg.lm_iters)
+    trg = c.solve(cfg.admm_iters)
+    pb = oracle_mod.Problem(d, lm_iters=cfg.lm_iters)
+    out = pb.admm_solve(synth_mod.identity_jones(cfg.P, cfg.K, cfg.N), cfg.admm_iters)
+    tro = out["trace"]
+    np.testing.assert_allclose(trg[:, 0], tro[:, 0], rtol=1e-10)
+    np.testing.assert_allclose(trg[:, 1], tro[:, 1], rtol=1e-10)
+    model_g = c.get(cal.FIELD_MODEL_VIS).cpu().numpy()
+    assert _rel(model_g, pb.predict(out["J"])) < 1e-9
+
+
+def test_admm_fp32_mixed(cal, oracle_mod, synth_mod):
+    cfg = tiny_cfg(synth_mod, N=10, P=6, Q=3, K=3, T=5, n_chan=4, lm_iters=8)
+    d = synth_mod.generate(cfg)
+    c = _ctx(cal, d, 1, lm_iters=8)
+    trg = c.solve(6)
+    pb = oracle_mod.Problem(synth_mod.as_fp32_inputs(d), lm_iters=8)
+    tro = pb.admm_solve(synth_mod.identity_jones(cfg.P, cfg.K, cfg.N), 6)["trace"]
+    np.testing.assert_allclose(trg[:, 0], tro[:, 0], rtol=1e-5)
+    np.testing.assert_allclose(trg[:, 1], tro[:, 1], rtol=1e-5)
+
+
+def test_ragged_flags_fp64(cal, oracle_mod, synth_mod):
+    cfg = synth_mod.SynthConfig("rag", N=9, P=7, Q=3, K=4, T=3, n_chan=[1, 3, 2, 5, 1, 4, 2],
+                                n_dirs=[4, 3, 4, 2, 4, 3, 4], flag_frac_max=0.3, lm_iters=5,
+                                config_index=8)
+    d = synth_mod.generate(cfg)
+    assert d["flags"].sum() > 0
+    c = _ctx(cal, d, 0, lm_iters=5)
+    trg = c.solve(4)
+    pb = oracle_mod.Problem(d, lm_iters=5)
+    out = pb.admm_solve(synth_mod.identity_jones(cfg.P, cfg.K, cfg.N), 4)
+    np.testing.assert_allclose(trg[:, 0], out["trace"][:, 0], rtol=1e-10)
+    model_g = c.get(cal.FIELD_MODEL_VIS).cpu().numpy()
+    assert _rel(model_g, pb.predict(out["J"])) < 1e-9
+
+
+def test_rank_and_numeric_errors(cal, synth_mod):
+    cfg = tiny_cfg(synth_mod, N=4, P=2, Q=3, K=1)
+    d = synth_mod.generate(cfg)
+    with pytest.raises(cal.CalibError) as e:
+        _ctx(cal, d, 0)
+    assert e.value.status == 4
+    cfg = tiny_cfg(synth_mod, N=4, P=3, Q=2, K=1)
+    d = synth_mod.generate(cfg)
+    d["vis"] = d["vis"].copy()
+    d["vis"][5, 0, 1] = np.nan
+    with pytest.raises(cal.CalibError) as e:
+        _ctx(cal, d, 0)
+    assert e.value.status == 5
+
+
+def test_flagged_samples_never_read(cal, synth_mod):
+    cfg = tiny_cfg(synth_mod, N=6, P=3, Q=2, K=2, flag_frac_max=0.4)
+    d = synth_mod.generate(cfg)
+    B, spb = cfg.B, cfg.T * 2
+    vis = d["vis"].copy()
+    for f in range(cfg.P):
+        for b in np.nonzero(d["flags"][f * B:(f + 1) * B])[0]:
+            s0 = d["vis_off"][f] + b * spb
+            vis[s0:s0 + spb] = np.nan
+    d2 = dict(d, vis=vis)
+    tr1 = _ctx(cal, d, 0).solve(2)
+    tr2 = _ctx(cal, d2, 0).solve(2)
+    np.testing.assert_array_equal(tr1, tr2)
+
+
+def test_run_to_run_bitwise(cal, synth_mod):
+    cfg = tiny_cfg(synth_mod, N=8, P=4, Q=2, K=2, T=3, n_chan=3)
+    d = synth_mod.generate(cfg)
+    a = _ctx(cal, d, 1)
+    b = _ctx(cal, d, 1)
+    np.testing.assert_array_equal(a.solve(3), b.solve(3))
+    np.testing.assert_array_equal(a.get(cal.FIELD_J).cpu().numpy(), b.get(cal.FIELD_J).cpu().numpy())
+
+
+def test_normal_equation_solve_fp64(cal, oracle_mod, synth_mod):
+    """One LM iteration from a random state: the GPU step solves (H_GN + (rho+lambda) I) delta = -G
+    with the oracle's Gauss-Newton matrix (both odd and even station counts: padded factor)."""
+    for N in (6, 9):
+        cfg = tiny_cfg(synth_mod, N=N, P=2, Q=1, K=1, T=3, n_chan=2, rho=3.0, lm_iters=1)
+        d = synth_mod.generate(cfg)
+        J = rand_jones(np.random.default_rng(14), cfg.P, 1, N)
+        c = _ctx(cal, d, 0, jones0=J, lm_iters=1, options=0)
+        c.local_step(1)
+        step = c.get(cal.FIELD_LM_STEP).cpu().numpy()
+        pb = oracle_mod.Problem(d, lm_iters=1)
+        z = np.zeros_like(J)
+        for f in range(cfg.P):
+            _, G = pb.dir_objective(J, z, z, f, 0)
+            g = np.stack([G.reshape(-1).real, G.reshape(-1).imag], 1).reshape(-1)
+            np.testing.assert_allclose(step[f, 0], g, rtol=1e-10, atol=1e-10 * np.abs(g).max())
+            H = pb.dir_gn_hessian(f, 0, J[f, 0]) + 3.0 * np.eye(8 * N)
+            lam = 1e-3 * np.max(np.diag(H))
+            delta = np.linalg.solve(H + lam * np.eye(8 * N), -g)
+            np.testing.assert_allclose(step[f, 1], delta, rtol=1e-9, atol=1e-9 * np.abs(delta).max())
