@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Benchmark: subband consensus-ADMM solves per second on one MI355X.
+
+Workload (default): N=62 stations (1891 baselines), K=5 directions, T=10 slots, 32 subbands x 4
+channels over 115-185 MHz, 4-term polynomial basis, rho=5, 30 ADMM iterations x 10 LM iterations,
+FP32 streaming with FP64 normal-equation solve / cost / Z.  One step = one full ADMM solve of all
+32 subbands from the identity initialisation, with the inputs already resident in HBM.
+value = subbands x steps / wall time of the timed steps (subband-solves per second).
+
+Also reported: the per-kernel time breakdown and the roofline of the dominant kernel (HIP events
+on the library's stream around every launch, in a separate untimed pass), the FP32-vs-FP64
+accuracy of the final data cost, the iteration where the data cost reaches 1e-6 of its final
+value, and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+
+
+def kernel_work(name, data, K_active_total, n_chol_launch_subbands, elt):
+    """Algorithmic bytes or FLOPs of one launch of a kernel class."""
+    N = int(data["N"])
+    n = 8 * N
+    nb = data["nb_live"]
+    spb = data["T"] * data["n_chan"]
+    S = float(np.sum(nb * spb))                  # samples over all subbands
+    if name == "chol_solve":
+        return ("mfma", n_chol_launch_subbands * (n ** 3 / 3.0 + 2.0 * n ** 2), "TFLOP/s")
+    if name == "trial":
+        return ("hbm", S * (8 * elt + 2 * elt) + np.sum(nb) * 64.0, "GB/s")
+    if name == "commit":
+        return ("hbm", S * (8 * elt * 2 + 2 * 2 * elt) + np.sum(nb) * 64.0, "GB/s")
+    if name == "refresh":
+        kbar = K_active_total / max(int(data["P"]), 1)
+        return ("hbm", S * (8 * elt * 2 + 2 * elt * kbar) + np.sum(nb) * 64.0, "GB/s")
+    if name == "assemble":
+        return ("hbm", n_chol_launch_subbands * (n * (n + 1) / 2.0) * 8.0, "GB/s")
+    return (None, None, None)
+
+
+def cpu_baseline(data, iters_sample, admm_iters, lm_iters):
+    import oracle
+    pb = oracle.Problem(__import__("paper_1502_00858_amd.synth", fromlist=["x"]).as_fp32_inputs(data),
+                        lm_iters=lm_iters)
+    P, K, N = int(data["P"]), int(data["K"]), int(data["N"])
+    J0 = np.zeros((P, K, N, 2, 2), np.complex128)
+    J0[..., 0, 0] = 1
+    J0[..., 1, 1] = 1
+    t0 = time.perf_counter()
+    pb.admm_solve(J0, iters_sample)
+    el = time.perf_counter() - t0
+    per_solve = el * admm_iters / iters_sample
+    return {"value": P / per_solve, "unit": "subband-solves/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{iters_sample} of {admm_iters} ADMM iterations of the same workload "
+                      f"(all {P} subbands, FP64 oracle on the FP32-rounded inputs), "
+                      f"{el:.1f} s, scaled x{admm_iters / iters_sample:g} to one solve"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--admm-iters", type=int, default=None)
+    ap.add_argument("--lm-iters", type=int, default=None)
+    ap.add_argument("--cpu-sample-iters", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the method's cross-subband exchange is a device-wide "
+              "reduction here; multi-GPU sharding is not built (see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1502_00858_amd import calib, synth
+
+    cfg = synth.named_config(args.config)
+    admm_iters = args.admm_iters or cfg.admm_iters
+    lm_iters = args.lm_iters or cfg.lm_iters
+    data = synth.generate(cfg)
+    P = int(data["P"])
+    B = cfg.B
+    data["nb_live"] = np.array([B - int(data["flags"][f * B:(f + 1) * B].sum()) for f in range(P)])
+    prec = calib.CALIB_FP64 if args.config == "c1" else calib.CALIB_FP32_MIXED
+    elt = 8 if prec == calib.CALIB_FP64 else 4
+    vis, coh, flags = calib.device_inputs(data, prec)
+    J0 = torch.zeros((P, cfg.K, cfg.N, 2, 2), dtype=torch.complex128, device="cuda")
+    J0[..., 0, 0] = 1
+    J0[..., 1, 1] = 1
+    ctx = calib.Calib(data, vis, coh, flags, J0, precision=prec, lm_iters=lm_iters)
+
+    def step():
+        ctx.set_jones(J0)
+        return ctx.solve(admm_iters)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        trace = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = P * args.steps / elapsed
+
+    out = {"metric": "subband ADMM solves/s (N=62,K=5) at 1e-6 rel cost, learned vs plain; HBM GB/s",
+           "value": value, "unit": "subband-solves/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if prec == calib.CALIB_FP64 else "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": f"{args.config}: N={cfg.N} K={cfg.K} T={cfg.T} P={P} "
+                                  f"n_chan={cfg.n_chan} Q={cfg.Q} rho={cfg.rho} "
+                                  f"admm={admm_iters} lm={lm_iters}",
+                      "global_batch": P, "parallelism": "none (1 GPU)"}}
+
+    g = trace[:, 0]
+    tgt = np.nonzero(np.abs(g - g[-1]) <= 1e-6 * g[-1])[0]
+    out["iters_to_1e-6_rel_cost"] = int(tgt[0]) + 1 if len(tgt) else None
+    if len(tgt):
+        out["solves_per_s_to_1e-6_rel_cost"] = value * admm_iters / (int(tgt[0]) + 1)
+
+    if prec == calib.CALIB_FP32_MIXED:
+        v64, c64, f64 = calib.device_inputs(data, calib.CALIB_FP64)
+        ref = calib.Calib(data, v64, c64, f64, J0, precision=calib.CALIB_FP64, lm_iters=lm_iters)
+        tr64 = ref.solve(admm_iters)
+        out["fp32_vs_fp64_rel_cost"] = float(abs(g[-1] - tr64[-1, 0]) / tr64[-1, 0])
+        ref.close()
+        del v64, c64, f64
+
+    if not args.no_profile:
+        ctx.set_kernel_timing(True)
+        step()
+        kt = ctx.get(calib.FIELD_KERNEL_TIMES)
+        ctx.set_kernel_timing(False)
+        total = sum(v[1] for v in kt.values())
+        out["kernel_ms_per_step"] = {k: round(v[1], 3) for k, v in kt.items()}
+        dom = max(kt, key=lambda k: kt[k][1])
+        launches, ms = kt[dom]
+        avg_s = ms / launches / 1e3
+        bound, work, unit = kernel_work(dom, data, int(np.sum(data["n_dirs"])), P, elt)
+        if bound is not None:
+            achieved = work / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
+            peak = FP64_PEAK_TFS if unit == "TFLOP/s" else HBM_PEAK_GBS
+            out["roofline"] = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak,
+                               "unit": unit, "frac": achieved / peak, "traffic": None,
+                               "avg_launch_us": avg_s * 1e6, "share_of_step": ms / total}
+        # the streaming pass at the LM trial point: achieved HBM bandwidth
+        tl, tms = kt["trial"]
+        _, tb, _ = kernel_work("trial", data, 0, P, elt)
+        out["trial_pass_GBs"] = tb / (tms / tl / 1e3) / 1e9
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(data, args.cpu_sample_iters, admm_iters, lm_iters)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

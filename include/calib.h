@@ -148,6 +148,24 @@ calib_status calib_get(calib_ctx *ctx, int32_t field, void *dst);
  * and reset Y, Z and B_f Z to zero. */
 calib_status calib_set_jones(calib_ctx *ctx, const void *jones);
 
+/* Kernel classes reported by CALIB_FIELD_KERNEL_TIMES. */
+#define CALIB_KERNEL_REFRESH 0      /* full residual + statistics of the first direction        */
+#define CALIB_KERNEL_LM_BEGIN 1     /* initial objective and damping of a direction            */
+#define CALIB_KERNEL_ASSEMBLE 2     /* gradient and Gauss-Newton normal equations              */
+#define CALIB_KERNEL_CHOL_SOLVE 3   /* batched FP64 Cholesky factorisation and solve           */
+#define CALIB_KERNEL_TRIAL 4        /* streaming pass at the LM trial point                     */
+#define CALIB_KERNEL_LM_UPDATE 5    /* gain ratio, accept/reject, damping update                */
+#define CALIB_KERNEL_COMMIT 6       /* SAGE residual commit + statistics of the next direction  */
+#define CALIB_KERNEL_CONSENSUS 7    /* Lagrangian trace, alignment, Z, B_f Z, Y, residuals      */
+#define CALIB_NUM_KERNELS 8
+#define CALIB_FIELD_KERNEL_TIMES 9  /* host double [CALIB_NUM_KERNELS][2]: launches and total
+                                       milliseconds since timing was enabled (synchronises)     */
+
+/* Measurement aid: when enable != 0, every kernel launch of the context is bracketed by a pair
+ * of HIP events recorded on the context's stream, and CALIB_FIELD_KERNEL_TIMES accumulates the
+ * launch count and elapsed time per kernel class.  Enabling resets the counters. */
+calib_status calib_set_kernel_timing(calib_ctx *ctx, int32_t enable);
+
 /* Free every device buffer of the context (synchronises its stream). NULL is accepted. */
 void calib_destroy(calib_ctx *ctx);
 

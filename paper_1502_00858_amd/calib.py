@@ -18,11 +18,13 @@ CALIB_FP32_MIXED = 1
 OPT_GPA_FIRST_ITER = 1
 OPT_UNREG_FIRST = 2
 (FIELD_J, FIELD_Z, FIELD_BZ, FIELD_Y, FIELD_MODEL_VIS, FIELD_COST, FIELD_TRACE, FIELD_LM_TRACE,
- FIELD_LM_STEP) = range(9)
+ FIELD_LM_STEP, FIELD_KERNEL_TIMES) = range(10)
+KERNELS = ["refresh", "lm_begin", "assemble", "chol_solve", "trial", "lm_update", "commit",
+           "consensus"]
 STATUS = {0: "CALIB_OK", 1: "CALIB_E_INVAL", 2: "CALIB_E_NOMEM", 3: "CALIB_E_DEVICE",
           4: "CALIB_E_RANK", 5: "CALIB_E_NUMERIC", 6: "CALIB_E_STATE"}
 EXPORTS = ["calib_init", "admm_local_step", "admm_consensus_update", "admm_solve", "calib_get",
-           "calib_set_jones", "calib_destroy", "calib_last_error"]
+           "calib_set_jones", "calib_set_kernel_timing", "calib_destroy", "calib_last_error"]
 
 
 class CalibError(RuntimeError):
@@ -57,12 +59,13 @@ def load(path: str = LIB_PATH):
         lib.admm_solve.argtypes = [vp, i32, dbl, vp, C.POINTER(i32)]
         lib.calib_get.argtypes = [vp, i32, vp]
         lib.calib_set_jones.argtypes = [vp, vp]
+        lib.calib_set_kernel_timing.argtypes = [vp, i32]
         lib.calib_destroy.argtypes = [vp]
         lib.calib_destroy.restype = None
         lib.calib_last_error.argtypes = [vp]
         lib.calib_last_error.restype = C.c_char_p
         for name in ("calib_init", "admm_local_step", "admm_consensus_update", "admm_solve",
-                     "calib_get", "calib_set_jones"):
+                     "calib_get", "calib_set_jones", "calib_set_kernel_timing"):
             getattr(lib, name).restype = C.c_int
         _lib = lib
     return _lib
@@ -132,6 +135,10 @@ class Calib:
 
     def get(self, field: int):
         import torch
+        if field == FIELD_KERNEL_TIMES:
+            kt = np.zeros((len(KERNELS), 2))
+            self._check(self.lib.calib_get(self.ctx, field, C.c_void_p(kt.ctypes.data)))
+            return {name: (int(kt[i, 0]), float(kt[i, 1])) for i, name in enumerate(KERNELS)}
         if field == FIELD_TRACE:
             n = 4096
             tr = np.zeros((n, 4))
@@ -153,6 +160,9 @@ class Calib:
             raise ValueError(field)
         self._check(self.lib.calib_get(self.ctx, field, _ptr(out)))
         return out
+
+    def set_kernel_timing(self, enable: bool):
+        self._check(self.lib.calib_set_kernel_timing(self.ctx, int(bool(enable))))
 
     def set_jones(self, J):
         self._check(self.lib.calib_set_jones(self.ctx, _ptr(J)))

@@ -54,9 +54,59 @@ struct calib_ctx {
   double *lm_trace = nullptr;
   int iters_done = 0;
   std::string err;
+  // per-kernel event timing (measurement aid)
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  std::vector<std::pair<int, size_t>> pending;
+  size_t next_event = 0;
+  double kms[CALIB_NUM_KERNELS] = {0};
+  double kcount[CALIB_NUM_KERNELS] = {0};
 };
 
 namespace {
+
+constexpr size_t kMaxPendingEvents = 4096;
+
+hipError_t flush_timing(calib_ctx *c) {
+  if (c->pending.empty()) return hipSuccess;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return e;
+  for (auto &pr : c->pending) {
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, c->events[pr.second], c->events[pr.second + 1]);
+    if (e != hipSuccess) return e;
+    c->kms[pr.first] += ms;
+    c->kcount[pr.first] += 1.0;
+  }
+  c->pending.clear();
+  c->next_event = 0;
+  return hipSuccess;
+}
+
+// Launch through `launch`, bracketed by an event pair on the context stream when timing is on.
+template <typename F>
+hipError_t timed(calib_ctx *c, int id, F &&launch) {
+  if (!c->timing) return launch();
+  if (c->pending.size() >= kMaxPendingEvents) {
+    hipError_t e = flush_timing(c);
+    if (e != hipSuccess) return e;
+  }
+  while (c->next_event + 2 > c->events.size()) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return e;
+    c->events.push_back(ev);
+  }
+  const size_t i = c->next_event;
+  c->next_event += 2;
+  hipError_t e = hipEventRecord(c->events[i], c->stream);
+  if (e != hipSuccess) return e;
+  e = launch();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(c->events[i + 1], c->stream);
+  c->pending.emplace_back(id, i);
+  return e;
+}
 
 calib_status fail(calib_ctx *ctx, calib_status st, const std::string &msg) {
   if (ctx) ctx->err = msg; else g_init_error = msg;
@@ -111,17 +161,22 @@ template <typename T>
 calib_status run_local_step(calib_ctx *c, int admm_iter) {
   const int unreg = (admm_iter == 0 && (c->options & CALIB_OPT_UNREG_FIRST)) ? 1 : 0;
   hipStream_t s = c->stream;
-  HIPCHK(c, launch_refresh<T>(c->pb, c->L, c->B, s));
+  const Problem &pb = c->pb;
+  const Layout &L = c->L;
+  const Buffers &B = c->B;
+  HIPCHK(c, timed(c, CALIB_KERNEL_REFRESH, [&] { return launch_refresh<T>(pb, L, B, s); }));
   for (int sw = 0; sw < c->sage_sweeps; ++sw)
     for (int k = 0; k < c->K; ++k) {
-      HIPCHK(c, launch_lm_begin(c->pb, c->L, c->B, k, unreg, s));
+      HIPCHK(c, timed(c, CALIB_KERNEL_LM_BEGIN, [&] { return launch_lm_begin(pb, L, B, k, unreg, s); }));
       for (int it = 0; it < c->lm_iters; ++it) {
-        HIPCHK(c, launch_assemble(c->pb, c->L, c->B, k, unreg, s));
-        HIPCHK(c, launch_chol_solve_nd(c->pb, c->B, k, c->d_ndir, s));
-        HIPCHK(c, launch_trial<T>(c->pb, c->L, c->B, k, s));
-        HIPCHK(c, launch_lm_update_tr(c->pb, c->L, c->B, k, unreg, c->lm_trace, it, c->lm_iters, s));
+        HIPCHK(c, timed(c, CALIB_KERNEL_ASSEMBLE, [&] { return launch_assemble(pb, L, B, k, unreg, s); }));
+        HIPCHK(c, timed(c, CALIB_KERNEL_CHOL_SOLVE, [&] { return launch_chol_solve_nd(pb, B, k, c->d_ndir, s); }));
+        HIPCHK(c, timed(c, CALIB_KERNEL_TRIAL, [&] { return launch_trial<T>(pb, L, B, k, s); }));
+        HIPCHK(c, timed(c, CALIB_KERNEL_LM_UPDATE, [&] {
+          return launch_lm_update_tr(pb, L, B, k, unreg, c->lm_trace, it, c->lm_iters, s);
+        }));
       }
-      HIPCHK(c, launch_commit<T>(c->pb, c->L, c->B, k, s));
+      HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, k, s); }));
     }
   return CALIB_OK;
 }
@@ -137,6 +192,7 @@ const char *calib_last_error(const calib_ctx *ctx) {
 void calib_destroy(calib_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
+  for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
   ctx->mem.release();
   delete ctx;
 }
@@ -378,10 +434,13 @@ calib_status admm_consensus_update(calib_ctx *ctx, int32_t admm_iter) {
   if (!ctx) return CALIB_E_INVAL;
   if (admm_iter < 0 || admm_iter >= kMaxTrace) return fail(ctx, CALIB_E_INVAL, "admm_iter out of range");
   hipStream_t s = ctx->stream;
-  HIPCHK(ctx, launch_penalty_trace(ctx->pb, ctx->L, ctx->B, admm_iter, s));
-  if (admm_iter == 0 && (ctx->options & CALIB_OPT_GPA_FIRST_ITER))
-    HIPCHK(ctx, launch_gpa(ctx->pb, ctx->L, ctx->B, 3, s));
-  HIPCHK(ctx, launch_consensus(ctx->pb, ctx->L, ctx->B, admm_iter, s));
+  const bool gpa = admm_iter == 0 && (ctx->options & CALIB_OPT_GPA_FIRST_ITER);
+  HIPCHK(ctx, timed(ctx, CALIB_KERNEL_CONSENSUS, [&] {
+    hipError_t e = launch_penalty_trace(ctx->pb, ctx->L, ctx->B, admm_iter, s);
+    if (e == hipSuccess && gpa) e = launch_gpa(ctx->pb, ctx->L, ctx->B, 3, s);
+    if (e == hipSuccess) e = launch_consensus(ctx->pb, ctx->L, ctx->B, admm_iter, s);
+    return e;
+  }));
   ctx->iters_done = std::max(ctx->iters_done, admm_iter + 1);
   return CALIB_OK;
 }
@@ -452,6 +511,12 @@ calib_status calib_get(calib_ctx *ctx, int32_t field, void *dst) {
                                  sizeof(double) * 3 * (size_t)ctx->P * ctx->K * ctx->lm_iters,
                                  hipMemcpyDeviceToDevice, s));
       return CALIB_OK;
+    case CALIB_FIELD_KERNEL_TIMES: {
+      HIPCHK(ctx, flush_timing(ctx));
+      double *o = static_cast<double *>(dst);
+      for (int i = 0; i < CALIB_NUM_KERNELS; ++i) { o[2 * i] = ctx->kcount[i]; o[2 * i + 1] = ctx->kms[i]; }
+      return CALIB_OK;
+    }
     case CALIB_FIELD_LM_STEP: {
       const size_t w = (size_t)8 * ctx->N * sizeof(double), sp = (size_t)ctx->pb.nf * sizeof(double);
       char *d = static_cast<char *>(dst);
@@ -462,6 +527,14 @@ calib_status calib_get(calib_ctx *ctx, int32_t field, void *dst) {
     default:
       return fail(ctx, CALIB_E_INVAL, "unknown field");
   }
+}
+
+calib_status calib_set_kernel_timing(calib_ctx *ctx, int32_t enable) {
+  if (!ctx) return CALIB_E_INVAL;
+  HIPCHK(ctx, flush_timing(ctx));
+  ctx->timing = enable != 0;
+  for (int i = 0; i < CALIB_NUM_KERNELS; ++i) ctx->kms[i] = ctx->kcount[i] = 0.0;
+  return CALIB_OK;
 }
 
 calib_status calib_set_jones(calib_ctx *ctx, const void *jones) {
