@@ -206,7 +206,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   if (!cfg || !vis || !coh) return fail(nullptr, CALIB_E_INVAL, "cfg, vis and coh are required");
   const int N = cfg->n_stations, P = cfg->n_subbands, Q = cfg->n_basis, K = cfg->n_dirs_max,
             T = cfg->n_times;
-  if (N < 2 || N > 4096) return fail(nullptr, CALIB_E_INVAL, "n_stations must be in [2, 4096]");
+  if (N < 2 || N > kMaxStations) return fail(nullptr, CALIB_E_INVAL, "n_stations must be in [2, 128]");
   if (P < 1) return fail(nullptr, CALIB_E_INVAL, "n_subbands must be >= 1");
   if (Q < 1 || Q > 8) return fail(nullptr, CALIB_E_INVAL, "n_basis must be in [1, 8]");
   if (K < 1 || K > kMaxDirs) return fail(nullptr, CALIB_E_INVAL, "n_dirs_max must be in [1, 16]");
@@ -378,6 +378,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   DALLOC(B.Jstart, (size_t)P * N * 8 * 8); DALLOC(B.Jtrial, (size_t)P * N * 8 * 8);
   DALLOC(B.Dcur, (size_t)nb_total * 8 * 8); DALLOC(B.Dtrial, (size_t)nb_total * 8 * 8);
   DALLOC(B.H, (size_t)P * pb.npad * pb.nf * 8);
+  DALLOC(B.Linv, (size_t)P * (pb.nf / 16) * 256 * 8);
   DALLOC(B.G, (size_t)P * pb.nf * 8); DALLOC(B.delta, (size_t)P * pb.nf * 8);
   DALLOC(B.cost_part, (size_t)std::max(pb.ntiles, 1) * 8);
   DALLOC(B.lm, (size_t)P * sizeof(LmState));

@@ -9,6 +9,8 @@ namespace calib {
 constexpr int kBlock = 256;        // threads per workgroup of every kernel (4 wave64)
 constexpr int kMaxDirs = 16;       // directions per subband
 constexpr double kLmTau = 1e-3;    // Nielsen's initial damping factor
+constexpr int kCholMaxTilesPerWave = 9;   // 16-row tiles per wavefront in one Cholesky panel
+constexpr int kMaxStations = 128;         // the solve keeps one column of 8N per thread
 
 // Per-subband tables of the packed, baseline-major layout.  Flagged baselines are dropped at
 // init, so "baseline index" below always means the compact index of an unflagged baseline.
@@ -62,6 +64,7 @@ struct Buffers {
   double *Jstart, *Jtrial;              // [P][N][8] active direction
   double *Dcur, *Dtrial;                // [sum nb][8]
   double *H;                            // [P][npad][nf]
+  double *Linv;                         // [P][nf/16][16*16] inverses of the diagonal tiles
   double *G, *delta;                    // [P][nf]
   double *cost_part;                    // [ntiles]
   LmState *lm;                          // [P]
@@ -93,7 +96,6 @@ hipError_t launch_lm_begin(const Problem &pb, const Layout &L, const Buffers &B,
                            hipStream_t s);
 hipError_t launch_assemble(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
                            hipStream_t s);
-int chol_panel_width(const Problem &pb);
 hipError_t launch_chol_solve_nd(const Problem &pb, const Buffers &B, int k, const int32_t *ndir,
                                 hipStream_t s);
 hipError_t launch_lm_update_tr(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,

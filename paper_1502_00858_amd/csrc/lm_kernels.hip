@@ -244,163 +244,6 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Problem pb, Layout L, Buffe
   }
 }
 
-// Factor the jb x jb diagonal block held column-major in LDS (leading dimension ld) with one
-// wavefront; lane i keeps row i in registers.  Returns false on a non-positive pivot.
-template <int JB>
-__device__ bool factor_diag(double *Pn, int ld) {
-  const int lane = threadIdx.x & 63;
-  double a[JB];
-#pragma unroll
-  for (int c = 0; c < JB; ++c) a[c] = (lane < JB && c <= lane) ? Pn[c * ld + lane] : 0.0;
-  bool ok = true;
-#pragma unroll
-  for (int c = 0; c < JB; ++c) {
-    const double d = readlane_d(a[c], c);
-    if (!(d > 0.0) || !isfinite(d)) { ok = false; break; }
-    const double lc = sqrt(d);
-    const double li = (lane == c) ? lc : (lane > c ? a[c] / lc : 0.0);
-    a[c] = li;
-#pragma unroll
-    for (int c2 = c + 1; c2 < JB; ++c2) {
-      const double l2 = readlane_d(li, c2);
-      if (lane >= c2) a[c2] -= li * l2;
-    }
-  }
-  if (ok && lane < JB) {
-#pragma unroll
-    for (int c = 0; c < JB; ++c)
-      if (c <= lane) Pn[c * ld + lane] = a[c];
-  }
-  return ok;
-}
-
-// Rows below the diagonal block: x L11^T = a by forward substitution (thread per row).
-template <int JB>
-__device__ void trsm_rows(double *Pn, int ld, int m) {
-  for (int r = JB + threadIdx.x; r < m; r += kBlock) {
-    double x[JB];
-#pragma unroll
-    for (int c = 0; c < JB; ++c) x[c] = Pn[c * ld + r];
-#pragma unroll
-    for (int c = 0; c < JB; ++c) {
-      x[c] /= Pn[c * ld + c];
-#pragma unroll
-      for (int c2 = c + 1; c2 < JB; ++c2) x[c2] -= x[c] * Pn[c * ld + c2];
-    }
-#pragma unroll
-    for (int c = 0; c < JB; ++c) Pn[c * ld + r] = x[c];
-  }
-}
-
-// Cholesky factorisation + solve, one workgroup per subband.  The panel (rows j0..npad-1,
-// NB columns) is staged column-major in LDS; the trailing update A22 -= L21 L21^T runs on
-// v_mfma_f64_16x16x4f64 over 16x16 tiles of the lower triangle.
-template <int NB>
-__global__ __launch_bounds__(kBlock) void k_chol_solve(Problem pb, Buffers B, int k, const int32_t *ndir) {
-  extern __shared__ double Pn[];   // [NB][npad] panel, then reused as [nf] solution vector
-  __shared__ int fail;
-  __shared__ double red[2][kBlock / 64];
-  const int f = blockIdx.x;
-  if (k >= ndir[f]) return;
-  const int nf = pb.nf, npad = pb.npad;
-  double *A = B.H + (int64_t)f * npad * nf;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (threadIdx.x == 0) fail = 0;
-  __syncthreads();
-
-  for (int j0 = 0; j0 < nf; j0 += NB) {
-    const int jb = (nf - j0 < NB) ? (nf - j0) : NB;   // NB or 16
-    const int m = npad - j0;
-    for (int idx = threadIdx.x; idx < m * jb; idx += kBlock) {
-      const int r = idx / jb, c = idx - r * jb;
-      Pn[c * npad + r] = A[(int64_t)(j0 + r) * nf + j0 + c];
-    }
-    __syncthreads();
-    if (wave == 0) {
-      const bool ok = (jb == NB) ? factor_diag<NB>(Pn, npad) : factor_diag<16>(Pn, npad);
-      if (!ok && lane == 0) fail = 1;
-    }
-    __syncthreads();
-    if (fail) break;
-    if (jb == NB) trsm_rows<NB>(Pn, npad, m); else trsm_rows<16>(Pn, npad, m);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < m * jb; idx += kBlock) {
-      const int r = idx / jb, c = idx - r * jb;
-      if (r >= c) A[(int64_t)(j0 + r) * nf + j0 + c] = Pn[c * npad + r];
-    }
-    // trailing update over 16x16 tiles (row tile I >= column tile Jt)
-    const int jt0 = (j0 + jb) >> 4, nct = nf >> 4, nrt = npad >> 4;
-    int cnt = 0;
-    for (int Jt = jt0; Jt < nct; ++Jt) {
-      for (int I = Jt; I < nrt; ++I, ++cnt) {
-        if ((cnt & 3) != wave) continue;
-        // accumulator element r of lane l holds D[4r + l/16][l%16] (v_mfma_f64_16x16x4f64)
-        const int row = I * 16 + (lane >> 4), col = Jt * 16 + (lane & 15);
-        d4 acc;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r] = A[(int64_t)(row + 4 * r) * nf + col];
-        const int ia = I * 16 - j0 + (lane & 15), ib = Jt * 16 - j0 + (lane & 15);
-        for (int kk = 0; kk < jb; kk += 4) {
-          const int kc = kk + (lane >> 4);
-          const double av = -Pn[kc * npad + ia];
-          const double bv = Pn[kc * npad + ib];
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) A[(int64_t)(row + 4 * r) * nf + col] = acc[r];
-      }
-    }
-    __syncthreads();
-  }
-  LmState *st = B.lm + f;
-  if (fail) {
-    if (threadIdx.x == 0) st->chol_ok = 0;
-    return;
-  }
-  // back substitution L^T x = y, y = row nf of the factor; 16-column blocks from the end
-  double *t = Pn;   // [nf]
-  for (int c = threadIdx.x; c < nf; c += kBlock) t[c] = A[(int64_t)nf * nf + c];
-  __syncthreads();
-  for (int j0 = nf - 16; j0 >= 0; j0 -= 16) {
-    if (wave == 0) {
-      // lane i < 16 owns t[j0+i]; L11^T x = t (upper triangular) solved bottom-up
-      double ti = lane < 16 ? t[j0 + lane] : 0.0;
-      for (int c = 15; c >= 0; --c) {
-        const double xc = readlane_d(ti, c) / A[(int64_t)(j0 + c) * nf + j0 + c];
-        if (lane == c) ti = xc;
-        if (lane < c) ti -= A[(int64_t)(j0 + c) * nf + j0 + lane] * xc;
-      }
-      if (lane < 16) t[j0 + lane] = ti;
-    }
-    __syncthreads();
-    for (int c = threadIdx.x; c < j0; c += kBlock) {
-      double s = t[c];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) s -= A[(int64_t)(j0 + r) * nf + c] * t[j0 + r];
-      t[c] = s;
-    }
-    __syncthreads();
-  }
-  // delta, predicted decrease ell = delta.(lambda delta - G)/2, trial point
-  const double lam = st->lambda;
-  const int n8 = 8 * pb.N;
-  double ell = 0.0;
-  const double *G = B.G + (int64_t)f * nf;
-  const double *J = B.J + ((int64_t)f * pb.K + k) * pb.N * 8;
-  for (int e = threadIdx.x; e < n8; e += kBlock) {
-    const double d = t[e];
-    ell += d * (lam * d - G[e]);
-    B.delta[(int64_t)f * nf + e] = d;
-    B.Jtrial[(int64_t)f * n8 + e] = J[e] + d;
-  }
-  double v[1] = {ell};
-  block_sum_vec<1>(v, red);
-  if (threadIdx.x == 0) {
-    st->ell = 0.5 * v[0];
-    st->chol_ok = 1;
-  }
-}
-
 __global__ __launch_bounds__(kBlock) void k_lm_update(Problem pb, Layout L, Buffers B, int k, int unreg,
                                                       double *lm_trace, int it, int lm_iters) {
   __shared__ double red[2][kBlock / 64];
@@ -458,25 +301,6 @@ hipError_t launch_lm_begin(const Problem &pb, const Layout &L, const Buffers &B,
 hipError_t launch_assemble(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_assemble, dim3(pb.P, pb.N + 1), dim3(kBlock), 0, s, pb, L, B, k, unreg);
-  return hipGetLastError();
-}
-
-int chol_panel_width(const Problem &pb) {
-  return (32 * pb.npad * 8 <= 150 * 1024) ? 32 : 16;
-}
-
-hipError_t launch_chol_solve_nd(const Problem &pb, const Buffers &B, int k, const int32_t *ndir,
-                                hipStream_t s) {
-  const int nb = chol_panel_width(pb);
-  size_t lds = (size_t)nb * pb.npad * sizeof(double);
-  if (lds < (size_t)pb.nf * sizeof(double)) lds = (size_t)pb.nf * sizeof(double);
-  if (nb == 32) {
-    hipFuncSetAttribute((const void *)k_chol_solve<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_chol_solve<32>, dim3(pb.P), dim3(kBlock), lds, s, pb, B, k, ndir);
-  } else {
-    hipFuncSetAttribute((const void *)k_chol_solve<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_chol_solve<16>, dim3(pb.P), dim3(kBlock), lds, s, pb, B, k, ndir);
-  }
   return hipGetLastError();
 }
 
