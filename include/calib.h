@@ -86,6 +86,10 @@ typedef struct {
   int32_t lm_iters;        /* LM iterations per direction per local step, >= 1                  */
   int32_t sage_sweeps;     /* SAGE sweeps over the directions per local step, >= 1              */
   uint32_t options;        /* CALIB_OPT_* bits                                                  */
+  int32_t tile_group;      /* lanes per baseline in the streaming passes: 8, 16, 32 or 64; 0 =
+                              chosen from the samples per baseline (tile-shape tuner output)   */
+  int32_t stream_grid;     /* workgroups of the streaming passes: 0 = one per tile, > 0 = a
+                              persistent grid striding over the tiles                          */
 } calib_config;
 
 /* Field selectors for calib_get. */
@@ -131,7 +135,9 @@ calib_status admm_local_step(calib_ctx *ctx, int32_t admm_iter);
  * residuals of Section 4.1 into the trace row of admm_iter. */
 calib_status admm_consensus_update(calib_ctx *ctx, int32_t admm_iter);
 
-/* The whole C-ADMM loop: iterations 0..max_iters-1 of local step + consensus update.  When
+/* The whole C-ADMM loop: iterations 0..max_iters-1 of local step + consensus update.  Iteration
+ * 0 is enqueued kernel by kernel; the launch sequence of the later iterations is identical, so it
+ * is captured once into a HIP graph and replayed (not while kernel timing is enabled).  When
  * rel_cost_tol > 0 it stops after an iteration whose data cost changed by less than
  * rel_cost_tol relative to the previous one (this check synchronises the stream each
  * iteration).  trace_out (host, may be NULL) receives [iters][4] as CALIB_FIELD_TRACE;

@@ -39,7 +39,8 @@ class _Config(C.Structure):
                 ("n_chan", C.POINTER(C.c_int32)), ("n_dirs", C.POINTER(C.c_int32)),
                 ("freq_hz", C.POINTER(C.c_double)), ("f0_hz", C.c_double),
                 ("rho", C.POINTER(C.c_double)), ("precision", C.c_int),
-                ("lm_iters", C.c_int32), ("sage_sweeps", C.c_int32), ("options", C.c_uint32)]
+                ("lm_iters", C.c_int32), ("sage_sweeps", C.c_int32), ("options", C.c_uint32),
+                ("tile_group", C.c_int32), ("stream_grid", C.c_int32)]
 
 
 _lib = None
@@ -90,7 +91,8 @@ class Calib:
 
     def __init__(self, data: dict, vis, coh, flags=None, jones0=None, precision: int = CALIB_FP64,
                  lm_iters: Optional[int] = None, sage_sweeps: int = 1,
-                 options: int = OPT_GPA_FIRST_ITER, rho=None, stream=None):
+                 options: int = OPT_GPA_FIRST_ITER, rho=None, stream=None, tile_group: int = 0,
+                 stream_grid: int = 0):
         import torch
         self.lib = load()
         self.N, self.P, self.Q, self.K, self.T = (int(data[k]) for k in ("N", "P", "Q", "K", "T"))
@@ -107,7 +109,8 @@ class Calib:
                       self._n_dirs.ctypes.data_as(C.POINTER(C.c_int32)),
                       self._freq.ctypes.data_as(C.POINTER(C.c_double)), float(data["f0"]),
                       self._rho.ctypes.data_as(C.POINTER(C.c_double)), int(precision),
-                      self.lm_iters, int(sage_sweeps), int(options))
+                      self.lm_iters, int(sage_sweeps), int(options), int(tile_group),
+                      int(stream_grid))
         self.stream = torch.cuda.current_stream() if stream is None else stream
         ctx = C.c_void_p()
         st = self.lib.calib_init(C.byref(cfg), _ptr(vis), _ptr(coh), _ptr(flags), _ptr(jones0),

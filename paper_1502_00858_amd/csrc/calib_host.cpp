@@ -61,6 +61,10 @@ struct calib_ctx {
   size_t next_event = 0;
   double kms[CALIB_NUM_KERNELS] = {0};
   double kcount[CALIB_NUM_KERNELS] = {0};
+  // one captured ADMM iteration (iterations >= 1 share their launch sequence)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
 };
 
 namespace {
@@ -137,13 +141,10 @@ calib_status upload(calib_ctx *ctx, V **dst, const std::vector<V> &src) {
   return CALIB_OK;
 }
 
-// lanes per baseline for the streaming kernels: fewest idle lane-iterations over the subbands,
-// ties to the larger group; CALIB_GROUP overrides (used by the tile-shape tuner)
-int choose_group(const std::vector<int32_t> &spb, const std::vector<int32_t> &nb) {
-  if (const char *env = std::getenv("CALIB_GROUP")) {
-    const int g = std::atoi(env);
-    if (g == 8 || g == 16 || g == 32 || g == 64) return g;
-  }
+// lanes per baseline for the streaming kernels: the configured value, else the fewest idle
+// lane-iterations over the subbands, ties to the larger group
+int choose_group(const std::vector<int32_t> &spb, const std::vector<int32_t> &nb, int requested) {
+  if (requested == 8 || requested == 16 || requested == 32 || requested == 64) return requested;
   int best = 16;
   double best_w = 1e300;
   for (int g : {64, 32, 16, 8}) {
@@ -158,9 +159,8 @@ int choose_group(const std::vector<int32_t> &spb, const std::vector<int32_t> &nb
 }
 
 template <typename T>
-calib_status run_local_step(calib_ctx *c, int admm_iter) {
+calib_status run_local_step(calib_ctx *c, int admm_iter, hipStream_t s) {
   const int unreg = (admm_iter == 0 && (c->options & CALIB_OPT_UNREG_FIRST)) ? 1 : 0;
-  hipStream_t s = c->stream;
   const Problem &pb = c->pb;
   const Layout &L = c->L;
   const Buffers &B = c->B;
@@ -181,6 +181,41 @@ calib_status run_local_step(calib_ctx *c, int admm_iter) {
   return CALIB_OK;
 }
 
+calib_status local_step_on(calib_ctx *c, int admm_iter, hipStream_t s) {
+  return c->precision == CALIB_FP64 ? run_local_step<double>(c, admm_iter, s)
+                                    : run_local_step<float>(c, admm_iter, s);
+}
+
+// Lagrangian trace row, first-iteration alignment, Z, B_f Z, Y and residuals; the trace row is
+// the device iteration counter, which the last kernel advances
+calib_status consensus_on(calib_ctx *c, bool gpa, hipStream_t s) {
+  HIPCHK(c, timed(c, CALIB_KERNEL_CONSENSUS, [&] {
+    hipError_t e = launch_penalty_trace(c->pb, c->L, c->B, s);
+    if (e == hipSuccess && gpa) e = launch_gpa(c->pb, c->L, c->B, 3, s);
+    if (e == hipSuccess) e = launch_consensus(c->pb, c->L, c->B, s);
+    return e;
+  }));
+  return CALIB_OK;
+}
+
+// capture the launch sequence of one ADMM iteration >= 1 into a graph (recorded, not run)
+calib_status build_iteration_graph(calib_ctx *c) {
+  if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+  calib_status st = local_step_on(c, 1, c->cap_stream);
+  if (st == CALIB_OK) st = consensus_on(c, false, c->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+  if (st != CALIB_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(c, CALIB_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+  c->graph = g;
+  HIPCHK(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+  return CALIB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -192,6 +227,9 @@ const char *calib_last_error(const calib_ctx *ctx) {
 void calib_destroy(calib_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   for (hipEvent_t ev : ctx->events) (void)hipEventDestroy(ev);
   ctx->mem.release();
   delete ctx;
@@ -300,7 +338,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   std::vector<int32_t> comp_tab(comp2full);
   comp_tab.insert(comp_tab.end(), comp_f.begin(), comp_f.end());
 
-  const int group = choose_group(spb, nb);
+  const int group = choose_group(spb, nb, cfg->tile_group);
   const int bpt = kBlock / group;
   std::vector<int32_t> tile_f, tile_b0, tile_off(P + 1);
   for (int f = 0; f < P; ++f) {
@@ -329,6 +367,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   pb.ntiles = (int)tile_f.size();
   pb.group = group;
   pb.bpt = bpt;
+  pb.stream_grid = cfg->stream_grid > 0 ? cfg->stream_grid : 0;
 
   calib_status st = CALIB_OK;
 #define UPL(dst, src)                                                                          \
@@ -387,6 +426,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   DALLOC(fitw, (size_t)K * Q * P * 8);
   DALLOC(B.trace, (size_t)kMaxTrace * 4 * 8);
   DALLOC(B.scratch, ((size_t)P * K + K) * 8);
+  DALLOC(B.iter, sizeof(int));
   DALLOC(c->lm_trace, (size_t)P * K * c->lm_iters * 3 * 8);
   int *flagbuf;
   DALLOC(flagbuf, 2 * sizeof(int));
@@ -409,6 +449,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
       dev(launch_zero(B.Y, (int64_t)nj, s), "zero Y") && dev(launch_zero(B.BZ, (int64_t)nj, s), "zero BZ") &&
       dev(launch_zero(B.Z, (int64_t)nz, s), "zero Z") &&
       dev(launch_zero(B.trace, (int64_t)kMaxTrace * 4, s), "zero trace") &&
+      dev(launch_set_iter(B, 0, s), "iteration counter") &&
       dev(launch_zero(c->lm_trace, (int64_t)P * K * c->lm_iters * 3, s), "zero lm trace") &&
       dev(jones0 ? hipMemcpyAsync(B.J, jones0, nj * 8, hipMemcpyDeviceToDevice, s)
                  : launch_fill_identity(B.J, (int64_t)P * K * N, s),
@@ -427,21 +468,16 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
 calib_status admm_local_step(calib_ctx *ctx, int32_t admm_iter) {
   if (!ctx) return CALIB_E_INVAL;
   if (admm_iter < 0 || admm_iter >= kMaxTrace) return fail(ctx, CALIB_E_INVAL, "admm_iter out of range");
-  return ctx->precision == CALIB_FP64 ? run_local_step<double>(ctx, admm_iter)
-                                      : run_local_step<float>(ctx, admm_iter);
+  return local_step_on(ctx, admm_iter, ctx->stream);
 }
 
 calib_status admm_consensus_update(calib_ctx *ctx, int32_t admm_iter) {
   if (!ctx) return CALIB_E_INVAL;
   if (admm_iter < 0 || admm_iter >= kMaxTrace) return fail(ctx, CALIB_E_INVAL, "admm_iter out of range");
-  hipStream_t s = ctx->stream;
-  const bool gpa = admm_iter == 0 && (ctx->options & CALIB_OPT_GPA_FIRST_ITER);
-  HIPCHK(ctx, timed(ctx, CALIB_KERNEL_CONSENSUS, [&] {
-    hipError_t e = launch_penalty_trace(ctx->pb, ctx->L, ctx->B, admm_iter, s);
-    if (e == hipSuccess && gpa) e = launch_gpa(ctx->pb, ctx->L, ctx->B, 3, s);
-    if (e == hipSuccess) e = launch_consensus(ctx->pb, ctx->L, ctx->B, admm_iter, s);
-    return e;
-  }));
+  HIPCHK(ctx, launch_set_iter(ctx->B, admm_iter, ctx->stream));
+  const calib_status st =
+      consensus_on(ctx, admm_iter == 0 && (ctx->options & CALIB_OPT_GPA_FIRST_ITER), ctx->stream);
+  if (st != CALIB_OK) return st;
   ctx->iters_done = std::max(ctx->iters_done, admm_iter + 1);
   return CALIB_OK;
 }
@@ -453,9 +489,17 @@ calib_status admm_solve(calib_ctx *ctx, int32_t max_iters, double rel_cost_tol, 
   int n = 0;
   double prev = 0.0;
   for (; n < max_iters; ++n) {
-    calib_status st = admm_local_step(ctx, n);
-    if (st != CALIB_OK) return st;
-    st = admm_consensus_update(ctx, n);
+    calib_status st = CALIB_OK;
+    if (n == 0 || ctx->timing) {
+      st = admm_local_step(ctx, n);
+      if (st == CALIB_OK) st = admm_consensus_update(ctx, n);
+    } else {
+      // iterations >= 1: replay the captured iteration; the device counter (set by iteration 0)
+      // selects the trace row
+      if (!ctx->graph_exec) st = build_iteration_graph(ctx);
+      if (st == CALIB_OK) HIPCHK(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
+      ctx->iters_done = std::max(ctx->iters_done, n + 1);
+    }
     if (st != CALIB_OK) return st;
     if (rel_cost_tol > 0.0) {
       double cur = 0.0;
@@ -472,6 +516,7 @@ calib_status admm_solve(calib_ctx *ctx, int32_t max_iters, double rel_cost_tol, 
   if (iters_done) *iters_done = n;
   return CALIB_OK;
 }
+
 
 calib_status calib_get(calib_ctx *ctx, int32_t field, void *dst) {
   if (!ctx) return CALIB_E_INVAL;

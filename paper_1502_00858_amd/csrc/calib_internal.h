@@ -53,6 +53,7 @@ struct Problem {
   int ntiles;
   int group;       // lanes per baseline in the streaming kernels
   int bpt;         // baselines per tile = kBlock / group
+  int stream_grid; // 0 = one workgroup per tile, else persistent grid size
 };
 
 struct Buffers {
@@ -73,6 +74,7 @@ struct Buffers {
   const double *fitw;                   // [K][Q][P] least-squares operator per direction
   double *trace;                        // [iters][4]
   double *scratch;                      // [P*K*2 + K] residual partials
+  int *iter;                            // ADMM iteration whose trace row is being written
 };
 
 // streaming kernels (templated on the stream element type float or double)
@@ -104,11 +106,10 @@ hipError_t launch_lm_update_tr(const Problem &pb, const Layout &L, const Buffers
 // consensus kernels
 hipError_t launch_basis_setup(const Problem &pb, const double *freq, double f0, const int32_t *ndir,
                               double *basis, double *fitw, int *rank_fail, hipStream_t s);
-hipError_t launch_penalty_trace(const Problem &pb, const Layout &L, const Buffers &B, int iter,
-                                hipStream_t s);
+hipError_t launch_set_iter(const Buffers &B, int iter, hipStream_t s);
+hipError_t launch_penalty_trace(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
 hipError_t launch_gpa(const Problem &pb, const Layout &L, const Buffers &B, int rounds, hipStream_t s);
-hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, int iter,
-                            hipStream_t s);
+hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
 hipError_t launch_subband_cost(const Problem &pb, const Layout &L, const Buffers &B, double *out,
                                hipStream_t s);
 hipError_t launch_fill_identity(double *J, int64_t nblocks, hipStream_t s);

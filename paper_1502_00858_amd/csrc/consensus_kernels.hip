@@ -94,7 +94,7 @@ __global__ void k_basis_setup(int P, int Q, int K, const double *freq, double f0
 
 // data cost sum_f g_f (from the tile partials of the final residual) and the augmented
 // Lagrangian sum_f [g_f + sum_k Re tr(Y^H (J - BZ)) + rho_k/2 ||J - BZ||^2]
-__global__ __launch_bounds__(kBlock) void k_penalty_trace(Problem pb, Layout L, Buffers B, int iter) {
+__global__ __launch_bounds__(kBlock) void k_penalty_trace(Problem pb, Layout L, Buffers B) {
   __shared__ double red[2][kBlock / 64];
   double v[2] = {0.0, 0.0};
   for (int t = threadIdx.x; t < pb.ntiles; t += kBlock) v[0] += B.cost_part[t];
@@ -108,6 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_penalty_trace(Problem pb, Layout L, 
   }
   block_sum_vec<2>(v, red);
   if (threadIdx.x == 0) {
+    const int iter = B.iter[0];
     B.trace[4 * iter] = v[0];
     B.trace[4 * iter + 1] = v[0] + v[1];
   }
@@ -260,8 +261,11 @@ __global__ __launch_bounds__(kBlock) void k_y_update(Problem pb, Layout L, Buffe
   if (threadIdx.x == 0) B.scratch[slot] = v[0];
 }
 
-__global__ void k_residuals(Problem pb, Buffers B, int iter) {
+// averages the residual partials into the trace row of the current iteration and advances the
+// iteration counter (so that a replayed graph writes the next row)
+__global__ void k_residuals(Problem pb, Buffers B) {
   if (threadIdx.x != 0) return;
+  const int iter = B.iter[0];
   double ps = 0.0, ds = 0.0;
   int pc = 0, dc = 0;
   for (int64_t i = 0; i < (int64_t)pb.P * pb.K; ++i)
@@ -272,6 +276,11 @@ __global__ void k_residuals(Problem pb, Buffers B, int iter) {
   }
   B.trace[4 * iter + 2] = pc ? ps / pc : 0.0;
   B.trace[4 * iter + 3] = dc ? ds / dc : 0.0;
+  B.iter[0] = iter + 1;
+}
+
+__global__ void k_set_iter(int *p, int v) {
+  if (threadIdx.x == 0) p[0] = v;
 }
 
 __global__ void k_fill_identity(double *J, int64_t nblocks) {
@@ -296,9 +305,13 @@ hipError_t launch_basis_setup(const Problem &pb, const double *freq, double f0, 
   return hipGetLastError();
 }
 
-hipError_t launch_penalty_trace(const Problem &pb, const Layout &L, const Buffers &B, int iter,
-                                hipStream_t s) {
-  hipLaunchKernelGGL(k_penalty_trace, dim3(1), dim3(kBlock), 0, s, pb, L, B, iter);
+hipError_t launch_set_iter(const Buffers &B, int iter, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_iter, dim3(1), dim3(64), 0, s, B.iter, iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_penalty_trace(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
+  hipLaunchKernelGGL(k_penalty_trace, dim3(1), dim3(kBlock), 0, s, pb, L, B);
   return hipGetLastError();
 }
 
@@ -314,15 +327,14 @@ hipError_t launch_gpa(const Problem &pb, const Layout &L, const Buffers &B, int 
   return hipGetLastError();
 }
 
-hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, int iter,
-                            hipStream_t s) {
+hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
   hipLaunchKernelGGL(k_z_fit, dim3(pb.K), dim3(kBlock), 0, s, pb, L, B);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_y_update, dim3(pb.P, pb.K), dim3(kBlock), 0, s, pb, L, B);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_residuals, dim3(1), dim3(64), 0, s, pb, B, iter);
+  hipLaunchKernelGGL(k_residuals, dim3(1), dim3(64), 0, s, pb, B);
   return hipGetLastError();
 }
 

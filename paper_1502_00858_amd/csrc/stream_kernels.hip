@@ -100,13 +100,9 @@ __device__ inline double block_sum(double v, double *red) {
 }
 
 template <typename T, int G, int MODE>
-__global__ __launch_bounds__(kBlock) void k_stream(Problem pb, Layout L, Buffers B, int k) {
-  constexpr int BPT = kBlock / G;
-  constexpr int MD = (MODE == SM_REFRESH) ? kMaxDirs : 1;
-  __shared__ T Msh[BPT][MD][8];
-  __shared__ double red[kBlock / 64];
-
-  const int tile = blockIdx.x;
+__device__ inline void stream_tile(const Problem &pb, const Layout &L, const Buffers &B, int k,
+                                   int tile, T (*Msh)[(MODE == SM_REFRESH) ? kMaxDirs : 1][8],
+                                   double *red) {
   const int f = L.tile_f[tile];
   const int Kf = L.ndir[f];
   if (MODE == SM_TRIAL && (k >= Kf || !B.lm[f].chol_ok)) return;   // uniform per workgroup
@@ -208,9 +204,23 @@ __global__ __launch_bounds__(kBlock) void k_stream(Problem pb, Layout L, Buffers
   if (threadIdx.x == 0) B.cost_part[tile] = tot;
 }
 
+// One workgroup per tile (grid = ntiles), or a persistent grid that strides over the tiles.
+template <typename T, int G, int MODE>
+__global__ __launch_bounds__(kBlock) void k_stream(Problem pb, Layout L, Buffers B, int k) {
+  constexpr int BPT = kBlock / G;
+  constexpr int MD = (MODE == SM_REFRESH) ? kMaxDirs : 1;
+  __shared__ T Msh[BPT][MD][8];
+  __shared__ double red[kBlock / 64];
+  for (int tile = blockIdx.x; tile < pb.ntiles; tile += gridDim.x) {
+    stream_tile<T, G, MODE>(pb, L, B, k, tile, Msh, red);
+    __syncthreads();
+  }
+}
+
 template <typename T, int MODE>
 hipError_t launch_mode(const Problem &pb, const Layout &L, const Buffers &B, int k, hipStream_t s) {
-  dim3 grid(pb.ntiles), block(kBlock);
+  if (pb.ntiles == 0) return hipSuccess;
+  dim3 grid(pb.stream_grid > 0 && pb.stream_grid < pb.ntiles ? pb.stream_grid : pb.ntiles), block(kBlock);
   switch (pb.group) {
     case 8: hipLaunchKernelGGL((k_stream<T, 8, MODE>), grid, block, 0, s, pb, L, B, k); break;
     case 16: hipLaunchKernelGGL((k_stream<T, 16, MODE>), grid, block, 0, s, pb, L, B, k); break;

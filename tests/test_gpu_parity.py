@@ -193,3 +193,34 @@ def test_normal_equation_solve_fp64(cal, oracle_mod, synth_mod):
             lam = 1e-3 * np.max(np.diag(H))
             delta = np.linalg.solve(H + lam * np.eye(8 * N), -g)
             np.testing.assert_allclose(step[f, 1], delta, rtol=1e-9, atol=1e-9 * np.abs(delta).max())
+
+
+def test_graph_replay_equals_eager(cal, synth_mod):
+    """Iterations >= 1 replay a captured graph; with kernel timing on every launch is eager."""
+    cfg = synth_mod.SynthConfig("g", N=9, P=6, Q=3, K=3, T=3, n_chan=[2, 1, 3, 2, 4, 1],
+                                n_dirs=[3, 2, 3, 3, 1, 3], flag_frac_max=0.2, lm_iters=4,
+                                config_index=9)
+    d = synth_mod.generate(cfg)
+    for prec in (0, 1):
+        a = _ctx(cal, d, prec, lm_iters=4)
+        b = _ctx(cal, d, prec, lm_iters=4)
+        b.set_kernel_timing(True)
+        ta, tb = a.solve(5), b.solve(5)
+        np.testing.assert_array_equal(ta, tb)
+        np.testing.assert_array_equal(a.get(cal.FIELD_J).cpu().numpy(), b.get(cal.FIELD_J).cpu().numpy())
+        # a second solve on the same context replays the same graph from a reset state
+        J0 = torch.from_numpy(synth_mod.identity_jones(cfg.P, cfg.K, cfg.N)).cuda()
+        a.set_jones(J0)
+        np.testing.assert_array_equal(a.solve(5), ta)
+
+
+def test_tile_shapes_and_persistent_grid(cal, synth_mod):
+    """Every lanes-per-baseline choice and a persistent streaming grid give the same numbers
+    (the per-tile reduction order does not depend on the grid)."""
+    cfg = tiny_cfg(synth_mod, N=8, P=4, Q=2, K=2, T=5, n_chan=3)
+    d = synth_mod.generate(cfg)
+    ref = _ctx(cal, d, 1).solve(3)
+    np.testing.assert_array_equal(_ctx(cal, d, 1, stream_grid=3).solve(3), ref)
+    for g in (8, 16, 32, 64):
+        tr = _ctx(cal, d, 1, tile_group=g).solve(3)
+        np.testing.assert_allclose(tr, ref, rtol=1e-6)
