@@ -28,6 +28,24 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 
+# HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a 256 MiB copy) of the kernels as they
+# were when the counters were taken (profiles/hbm_counters_c2.md); reported only while the
+# kernel source is unchanged (sha256 of the file).
+MEASURED_TRAFFIC = {
+    "chol_solve": ("paper_1502_00858_amd/csrc/chol_kernel.hip",
+                   "594706b86df67b8a700c59d4388c0a03a8e5dc83afc85f4c158c8cca38594b96",
+                   (40.39 + 36.83) * 1e6),
+}
+
+
+def measured_traffic(kernel):
+    import hashlib
+    if kernel not in MEASURED_TRAFFIC:
+        return None
+    path, sha, nbytes = MEASURED_TRAFFIC[kernel]
+    with open(os.path.join(ROOT, path), "rb") as fh:
+        return nbytes if hashlib.sha256(fh.read()).hexdigest() == sha else None
+
 
 def kernel_work(name, data, K_active_total, n_chol_launch_subbands, elt):
     """Algorithmic bytes or FLOPs of one launch of a kernel class."""
@@ -80,6 +98,10 @@ def main():
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--no-reference", action="store_true", help="skip the FP64 accuracy run")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with one 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--tile-group", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the method's cross-subband exchange is a device-wide "
@@ -102,7 +124,8 @@ def main():
     J0 = torch.zeros((P, cfg.K, cfg.N, 2, 2), dtype=torch.complex128, device="cuda")
     J0[..., 0, 0] = 1
     J0[..., 1, 1] = 1
-    ctx = calib.Calib(data, vis, coh, flags, J0, precision=prec, lm_iters=lm_iters)
+    ctx = calib.Calib(data, vis, coh, flags, J0, precision=prec, lm_iters=lm_iters,
+                      tile_group=args.tile_group)
 
     def step():
         ctx.set_jones(J0)
@@ -136,7 +159,7 @@ def main():
     if len(tgt):
         out["solves_per_s_to_1e-6_rel_cost"] = value * admm_iters / (int(tgt[0]) + 1)
 
-    if prec == calib.CALIB_FP32_MIXED:
+    if prec == calib.CALIB_FP32_MIXED and not args.no_reference:
         v64, c64, f64 = calib.device_inputs(data, calib.CALIB_FP64)
         ref = calib.Calib(data, v64, c64, f64, J0, precision=calib.CALIB_FP64, lm_iters=lm_iters)
         tr64 = ref.solve(admm_iters)
@@ -159,7 +182,7 @@ def main():
             achieved = work / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
             peak = FP64_PEAK_TFS if unit == "TFLOP/s" else HBM_PEAK_GBS
             out["roofline"] = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak,
-                               "unit": unit, "frac": achieved / peak, "traffic": None,
+                               "unit": unit, "frac": achieved / peak, "traffic": measured_traffic(dom),
                                "avg_launch_us": avg_s * 1e6, "share_of_step": ms / total}
         # the streaming pass at the LM trial point: achieved HBM bandwidth
         tl, tms = kt["trial"]
@@ -169,6 +192,12 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(data, args.cpu_sample_iters, admm_iters, lm_iters)
     ctx.close()
+    if args.copy_calibration:
+        src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
     print(json.dumps(out))
 
 
