@@ -1,16 +1,29 @@
 #!/usr/bin/env python3
-"""Benchmark: subband consensus-ADMM solves per second on one MI355X.
+"""Benchmark: subband consensus-ADMM solves per second on one MI355X, to a fixed cost target,
+learned warm start against the plain starts.
 
-Workload (default): N=62 stations (1891 baselines), K=5 directions, T=10 slots, 32 subbands x 4
-channels over 115-185 MHz, 4-term polynomial basis, rho=5, 30 ADMM iterations x 10 LM iterations,
-FP32 streaming with FP64 normal-equation solve / cost / Z.  One step = one full ADMM solve of all
-32 subbands from the identity initialisation, with the inputs already resident in HBM.
-value = subbands x steps / wall time of the timed steps (subband-solves per second).
+Workload (default c2): N=62 stations (1891 baselines), K=5 directions, T=10 slots, 32 subbands x 4
+channels over 115-185 MHz, 4-term polynomial basis, rho=5, 10 LM iterations per direction, FP32
+streaming with FP64 normal-equation solve / cost / Z.  The data are consecutive solution
+intervals of a drifting observation (synth.episode_interval); the measured interval is interval 3
+of a held-out episode, whose predecessors were solved (30 ADMM iterations each) to give the
+previous C-ADMM state (J, Y, Z, B_f Z).
 
-Also reported: the per-kernel time breakdown and the roofline of the dominant kernel (HIP events
-on the library's stream around every launch, in a separate untimed pass), the FP32-vs-FP64
-accuracy of the final data cost, the iteration where the data cost reaches 1e-6 of its final
-value, and the FP64 CPU oracle timed on a bounded sample of the same workload.
+Target: g_inf, the median data cost over iterations 50-99 of a 100-iteration run from the
+previous state; a start "reaches" the target at the first ADMM iteration whose data cost is within
+1e-6 relative of g_inf (iterations counted in untimed reference runs of each start).
+
+One timed step = one solve of all 32 subbands from a start, run for exactly the iterations that
+start needs to reach the target, with the inputs resident in HBM:
+  learned : previous state, features, network forward, per-subband cost fallback, then ADMM
+  plain   : previous state (the paper's warm start, J and the dual variables), then ADMM
+  identity: identity Jones matrices, Y = Z = 0, first-iteration gauge alignment, then ADMM
+value = subbands x steps / wall time of the learned steps (subband-solves per second).
+
+Also reported: training cost of the network (pairs, epochs, seconds), per-kernel time breakdown and
+the roofline of the dominant kernel (HIP events on the library's stream around every launch, in a
+separate untimed pass), the FP32-vs-FP64 accuracy of the data cost, and the FP64 CPU oracle timed
+on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -68,23 +81,37 @@ def kernel_work(name, data, K_active_total, n_chol_launch_subbands, elt):
     return (None, None, None)
 
 
-def cpu_baseline(data, iters_sample, admm_iters, lm_iters):
+def cpu_baseline(data, iters_sample, iters_to_target, lm_iters):
+    """The FP64 oracle's plain C-ADMM on the same interval (FP32-rounded inputs): the time of
+    iters_sample iterations, scaled to the iterations the plain start needs to reach the target
+    (an iteration costs the same from any start)."""
     import oracle
-    pb = oracle.Problem(__import__("paper_1502_00858_amd.synth", fromlist=["x"]).as_fp32_inputs(data),
-                        lm_iters=lm_iters)
+    from paper_1502_00858_amd import synth
+    pb = oracle.Problem(synth.as_fp32_inputs(data), lm_iters=lm_iters, options=0)
     P, K, N = int(data["P"]), int(data["K"]), int(data["N"])
-    J0 = np.zeros((P, K, N, 2, 2), np.complex128)
-    J0[..., 0, 0] = 1
-    J0[..., 1, 1] = 1
+    J0 = synth.identity_jones(P, K, N)
     t0 = time.perf_counter()
     pb.admm_solve(J0, iters_sample)
     el = time.perf_counter() - t0
-    per_solve = el * admm_iters / iters_sample
+    per_solve = el * iters_to_target / iters_sample
     return {"value": P / per_solve, "unit": "subband-solves/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{iters_sample} of {admm_iters} ADMM iterations of the same workload "
-                      f"(all {P} subbands, FP64 oracle on the FP32-rounded inputs), "
-                      f"{el:.1f} s, scaled x{admm_iters / iters_sample:g} to one solve"}
+            "sample": f"{iters_sample} ADMM iterations over all {P} subbands of the measured "
+                      f"interval (FP64 oracle on the FP32-rounded inputs), {el:.1f} s, scaled "
+                      f"x{iters_to_target / iters_sample:g} to the {iters_to_target} iterations "
+                      f"the plain start needs to reach the target"}
+
+
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
 
 
 def main():
@@ -93,8 +120,14 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--admm-iters", type=int, default=None)
     ap.add_argument("--lm-iters", type=int, default=None)
+    ap.add_argument("--chain-iters", type=int, default=30,
+                    help="ADMM iterations per interval when solving the episodes")
+    ap.add_argument("--ref-iters", type=int, default=100,
+                    help="iterations of the reference runs that fix the target")
+    ap.add_argument("--train-episodes", type=int, default=2)
+    ap.add_argument("--episode-intervals", type=int, default=6)
+    ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--cpu-sample-iters", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -109,67 +142,119 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1502_00858_amd import calib, synth
+    from paper_1502_00858_amd import calib, synth, warmstart
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     cfg = synth.named_config(args.config)
-    admm_iters = args.admm_iters or cfg.admm_iters
     lm_iters = args.lm_iters or cfg.lm_iters
-    data = synth.generate(cfg)
-    P = int(data["P"])
-    B = cfg.B
-    data["nb_live"] = np.array([B - int(data["flags"][f * B:(f + 1) * B].sum()) for f in range(P)])
     prec = calib.CALIB_FP64 if args.config == "c1" else calib.CALIB_FP32_MIXED
     elt = 8 if prec == calib.CALIB_FP64 else 4
-    vis, coh, flags = calib.device_inputs(data, prec)
-    J0 = torch.zeros((P, cfg.K, cfg.N, 2, 2), dtype=torch.complex128, device="cuda")
-    J0[..., 0, 0] = 1
-    J0[..., 1, 1] = 1
-    ctx = calib.Calib(data, vis, coh, flags, J0, precision=prec, lm_iters=lm_iters,
-                      tile_group=args.tile_group)
+    TEST_EPISODE, J_EVAL = 9, 3
 
-    def step():
-        ctx.set_jones(J0)
-        return ctx.solve(admm_iters)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+    # ---- training pairs and the network (untimed; reported as training cost) ----------------------
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        trace = step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = P * args.steps / elapsed
+    train_iv = []
+    for e in range(args.train_episodes):
+        train_iv += warmstart.solve_episode(cfg, e, args.episode_intervals, prec, args.chain_iters,
+                                            lm_iters)
+        log(f"training episode {e} solved ({time.perf_counter() - t0:.1f} s)")
+    gen_s = time.perf_counter() - t0
+    X, Y = warmstart.stack_rows(train_iv)
+    del train_iv
+    net = warmstart.WarmStartNet(max_rows=max(4096, int(cfg.P * cfg.K * cfg.N)))
+    train_s = net.train(X, Y, epochs=args.epochs, batch=512, lr=2e-3, lr_final=2e-4)
+    log(f"trained on {X.shape[0]} rows in {train_s:.1f} s, loss {net.history[-1]:.3e}")
+
+    # ---- the measured interval and its predecessors (untimed) -----------------------------------
+    chain = warmstart.solve_episode(cfg, TEST_EPISODE, args.episode_intervals, prec,
+                                    args.chain_iters, lm_iters, count=J_EVAL)
+    prev, prev2 = chain[-1], chain[-2]
+    data = synth.episode_interval(cfg, TEST_EPISODE, J_EVAL, args.episode_intervals)
+    P, B = int(data["P"]), cfg.B
+    data["nb_live"] = np.array([B - int(data["flags"][f * B:(f + 1) * B].sum()) for f in range(P)])
+    vis, coh, flags = calib.device_inputs(data, prec)
+    ctx = calib.Calib(data, vis, coh, flags, precision=prec, lm_iters=lm_iters, options=0,
+                      tile_group=args.tile_group)
+    ctx_id = calib.Calib(data, vis, coh, flags, precision=prec, lm_iters=lm_iters,
+                         options=calib.OPT_GPA_FIRST_ITER, tile_group=args.tile_group)
+    J_id = torch.from_numpy(synth.identity_jones(P, cfg.K, cfg.N)).cuda()
+
+    def start_plain():
+        ctx.set_state(prev.J, prev.Y, prev.Z, prev.BZ)
+
+    def start_learned():
+        ctx.set_state(prev.J, prev.Y, prev.Z, prev.BZ)
+        feats = ctx.warmstart_features(prev2.J, prev.BZ)
+        return ctx.warmstart_apply(net.predict(feats))
+
+    def start_identity():
+        ctx_id.set_jones(J_id)
+
+    starts = {"learned": (ctx, start_learned), "plain": (ctx, start_plain),
+              "identity": (ctx_id, start_identity)}
+    ref = {}
+    for name, (c, st) in starts.items():
+        st()
+        ref[name] = c.solve(args.ref_iters)
+    g_inf = float(np.median(ref["plain"][args.ref_iters // 2:, 0]))
+    iters = {k: warmstart.iters_to_target(tr, g_inf) for k, tr in ref.items()}
+    log(f"target {g_inf:.9e}; iterations to it: {iters}")
+
+    # ---- timed steps ----------------------------------------------------------------------------
+    sec, final = {}, {}
+    for name, (c, st) in starts.items():
+        n_it = iters[name] or args.ref_iters
+
+        def step():
+            st()
+            final[name] = c.solve(n_it)
+        sec[name] = timed(step, args.steps, args.warmup)
+    kept = start_learned().cpu().numpy()
+    ws_s = timed(start_learned, max(args.steps, 3), 1) - timed(start_plain, max(args.steps, 3), 1)
+    value = P / sec["learned"]
 
     out = {"metric": "subband ADMM solves/s (N=62,K=5) at 1e-6 rel cost, learned vs plain; HBM GB/s",
            "value": value, "unit": "subband-solves/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+           "warmup": args.warmup, "ms_per_step": 1e3 * sec["learned"], "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if prec == calib.CALIB_FP64 else "f32+f64",
+           "dtype": "f64+bf16" if prec == calib.CALIB_FP64 else "f32+f64+bf16",
            "data": "synthetic",
            "config": {"workload": f"{args.config}: N={cfg.N} K={cfg.K} T={cfg.T} P={P} "
-                                  f"n_chan={cfg.n_chan} Q={cfg.Q} rho={cfg.rho} "
-                                  f"admm={admm_iters} lm={lm_iters}",
+                                  f"n_chan={cfg.n_chan} Q={cfg.Q} rho={cfg.rho} lm={lm_iters}, "
+                                  f"interval {J_EVAL} of a drifting episode, learned warm start",
                       "global_batch": P, "parallelism": "none (1 GPU)"}}
-
-    g = trace[:, 0]
-    tgt = np.nonzero(np.abs(g - g[-1]) <= 1e-6 * g[-1])[0]
-    out["iters_to_1e-6_rel_cost"] = int(tgt[0]) + 1 if len(tgt) else None
-    if len(tgt):
-        out["solves_per_s_to_1e-6_rel_cost"] = value * admm_iters / (int(tgt[0]) + 1)
+    out["target_cost"] = g_inf
+    out["iters_to_target"] = iters
+    out["solves_per_s"] = {k: P / v for k, v in sec.items()}
+    out["speedup_learned_vs_plain"] = sec["plain"] / sec["learned"]
+    out["speedup_learned_vs_identity"] = sec["identity"] / sec["learned"]
+    out["final_rel_cost"] = {k: float((v[-1, 0] - g_inf) / g_inf) for k, v in final.items()}
+    out["final_primal_residual"] = {k: float(v[-1, 2]) for k, v in final.items()}
+    out["warm_start_ms"] = 1e3 * ws_s
+    out["learned_kept_subbands"] = int(kept.sum())
+    out["training"] = {"rows": int(X.shape[0]), "epochs": args.epochs, "batch": 512,
+                       "pair_generation_s": round(gen_s, 2), "train_s": round(train_s, 2),
+                       "final_loss": net.history[-1],
+                       "zero_predictor_loss": float(np.mean(Y.astype(np.float64) ** 2))}
 
     if prec == calib.CALIB_FP32_MIXED and not args.no_reference:
+        # FP64 solve from the same previous state, same iterations as the timed plain step
         v64, c64, f64 = calib.device_inputs(data, calib.CALIB_FP64)
-        ref = calib.Calib(data, v64, c64, f64, J0, precision=calib.CALIB_FP64, lm_iters=lm_iters)
-        tr64 = ref.solve(admm_iters)
-        out["fp32_vs_fp64_rel_cost"] = float(abs(g[-1] - tr64[-1, 0]) / tr64[-1, 0])
-        ref.close()
+        r64 = calib.Calib(data, v64, c64, f64, precision=calib.CALIB_FP64, lm_iters=lm_iters,
+                          options=0)
+        r64.set_state(prev.J, prev.Y, prev.Z, prev.BZ)
+        tr64 = r64.solve(iters["plain"] or args.ref_iters)
+        g32 = final["plain"][-1, 0]
+        out["fp32_vs_fp64_rel_cost"] = float(abs(g32 - tr64[-1, 0]) / tr64[-1, 0])
+        r64.close()
         del v64, c64, f64
 
     if not args.no_profile:
         ctx.set_kernel_timing(True)
-        step()
+        start_learned()
+        ctx.solve(iters["learned"] or args.ref_iters)
         kt = ctx.get(calib.FIELD_KERNEL_TIMES)
         ctx.set_kernel_timing(False)
         total = sum(v[1] for v in kt.values())
@@ -190,8 +275,11 @@ def main():
         out["trial_pass_GBs"] = tb / (tms / tl / 1e3) / 1e9
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(data, args.cpu_sample_iters, admm_iters, lm_iters)
+        out["cpu_baseline"] = cpu_baseline(data, args.cpu_sample_iters,
+                                           iters["plain"] or args.ref_iters, lm_iters)
     ctx.close()
+    ctx_id.close()
+    net.close()
     if args.copy_calibration:
         src = torch.empty(32 * 1024 * 1024, dtype=torch.float64, device="cuda").fill_(1.0)
         dst = torch.empty_like(src)

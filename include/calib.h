@@ -154,6 +154,14 @@ calib_status calib_get(calib_ctx *ctx, int32_t field, void *dst);
  * and reset Y, Z and B_f Z to zero. */
 calib_status calib_set_jones(calib_ctx *ctx, const void *jones);
 
+/* Overwrite the whole C-ADMM state for a warm start that carries the dual variables as well:
+ * J (required), Y, Z and B_f Z (each may be NULL = zero), device double complex in the layouts
+ * above (Z [K][Q][N][2][2]).  bz must equal B_f Z for this context's frequencies, e.g. the previous
+ * solution interval's.  The next admm_solve or admm_local_step(0) continues the iteration from
+ * this state; a context initialised without CALIB_OPT_GPA_FIRST_ITER keeps its gauge. */
+calib_status calib_set_state(calib_ctx *ctx, const void *jones, const void *y, const void *z,
+                             const void *bz);
+
 /* Kernel classes reported by CALIB_FIELD_KERNEL_TIMES. */
 #define CALIB_KERNEL_REFRESH 0      /* full residual + statistics of the first direction        */
 #define CALIB_KERNEL_LM_BEGIN 1     /* initial objective and damping of a direction            */
@@ -171,6 +179,81 @@ calib_status calib_set_jones(calib_ctx *ctx, const void *jones);
  * of HIP events recorded on the context's stream, and CALIB_FIELD_KERNEL_TIMES accumulates the
  * launch count and elapsed time per kernel class.  Enabling resets the counters. */
 calib_status calib_set_kernel_timing(calib_ctx *ctx, int32_t enable);
+
+/* ---- Warm start of a new solution interval ----------------------------------------------------
+ * Section 3 initialises a new interval's C-ADMM iteration from the previous interval's solution.
+ * The learned warm start refines that: a small network maps per-station features of the new
+ * data at the previous solution to a correction of each station's Jones matrix, and a per-subband
+ * cost comparison keeps the correction only where it does not raise the data cost.  The features
+ * and the fallback run here; the network is the calib_mlp API below.
+ *
+ * Rows r = (f*K + k)*N + p; a row of a direction the subband does not carry is zero. */
+#define CALIB_WS_FEATURES 32   /* features per row                                             */
+#define CALIB_WS_OUTPUTS 8     /* network outputs per row                                      */
+#define CALIB_WS_SCALE 10.0    /* scale s of the difference features and of the outputs        */
+
+/* Features at the context's current J (the previous interval's solution, set by calib_set_jones
+ * with the new interval's data loaded by calib_init), device float [P*K*N][32]:
+ *   [0,8)   J_p
+ *   [8,16)  s (J_p - J2_p)            J2 = jones_prev2 (the interval before; device double
+ *                                     [P][K][N][2][2]) or zero when jones_prev2 is NULL
+ *   [16,24) s (-1/2) G_p Q_p^-1       per-station Gauss-Newton step of the new data with the other
+ *                                     stations held (G_p: gradient of the data cost of direction k
+ *                                     after the SAGE expectation of Section 3; Q_p = sum_q S_pq
+ *                                     J_q^H J_q); zero if Q_p is singular
+ *   [24,32) s (BZ_p - J_p)            BZ = bz_prev (previous interval's B_f Z_k, device double
+ *                                     [P][K][N][2][2]) or zero when bz_prev is NULL
+ * J is unchanged on return. */
+calib_status calib_warmstart_features(calib_ctx *ctx, const void *jones_prev2, const void *bz_prev,
+                                      float *features);
+
+/* Training target of the network for the interval whose converged J the context holds:
+ * device float [P*K*N][8], row (f, k, p) = s (J_p U - Jprev_p) with U the unitary polar factor of
+ * sum_p J_p^H Jprev_p, so that the target is free of the unitary ambiguity of the solution
+ * (Section 3).  jones_prev: device double [P][K][N][2][2], the previous interval's solution. */
+calib_status calib_warmstart_target(calib_ctx *ctx, const void *jones_prev, float *target);
+
+/* J_learned = J + delta / s (delta: device float [P*K*N][8], the network output), then per
+ * subband keep J_learned if its data cost is finite and not above that of the current J, else
+ * restore the current J.  kept (device int32 [P], may be NULL) receives 1 where the learned value
+ * was kept.  Y, Z and B_f Z are left as they are (set them first with calib_set_state to carry
+ * the previous interval's dual variables, or calib_set_jones to start them at zero); the next
+ * admm_solve starts at iteration 0 from this state. */
+calib_status calib_warmstart_apply(calib_ctx *ctx, const float *delta, int32_t *kept);
+
+/* ---- Warm-start network ------------------------------------------------------------------------
+ * A fully connected network y = W_L^T(... GELU(W_1^T x + b_1) ...) + b_L with GELU(x) =
+ * x Phi(x) between layers.  GEMM operands (inputs, activations, weights, output gradients) are
+ * rounded to BF16 (round to nearest even) and multiplied on the matrix cores with FP32
+ * accumulation; master weights, biases, pre-activations, gradients and the Adam moments are FP32.
+ * Parameters are packed per layer l as W_l [dims[l]][dims[l+1]] row-major followed by
+ * b_l [dims[l+1]]. */
+typedef struct calib_mlp calib_mlp;
+
+/* n_layers >= 1 layers of widths dims[0..n_layers] (host); params host FP32 (copied); max_rows
+ * bounds the rows of every later call; work is enqueued on hip_stream.  Adam state starts at 0. */
+calib_status calib_mlp_create(int32_t n_layers, const int32_t *dims, const float *params,
+                              int64_t max_rows, void *hip_stream, calib_mlp **out);
+
+/* y (device float [rows][dims[L]]) = network(x) (device float [rows][dims[0]]), 1 <= rows <=
+ * max_rows. */
+calib_status calib_mlp_forward(calib_mlp *m, const float *x, int64_t rows, float *y);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with the 1-based step) on the
+ * mean square error mean((y - target)^2) over rows x dims[L] values; loss (device float [1], may
+ * be NULL) receives the loss before the step.  lr = 0 computes the gradients only. */
+calib_status calib_mlp_train_step(calib_mlp *m, const float *x, const float *target, int64_t rows,
+                                  float lr, int32_t step, float *loss);
+
+/* Copy the FP32 parameters (what = 0) or the last gradients (what = 1) into host memory in the
+ * packed layout.  Synchronises the stream. */
+calib_status calib_mlp_get(calib_mlp *m, int32_t what, float *dst);
+
+/* Free the network's device memory (synchronises its stream). NULL is accepted. */
+void calib_mlp_destroy(calib_mlp *m);
+
+/* Message of the last failure on m, or of the last calib_mlp_create failure when m is NULL. */
+const char *calib_mlp_last_error(const calib_mlp *m);
 
 /* Free every device buffer of the context (synchronises its stream). NULL is accepted. */
 void calib_destroy(calib_ctx *ctx);

@@ -24,7 +24,13 @@ KERNELS = ["refresh", "lm_begin", "assemble", "chol_solve", "trial", "lm_update"
 STATUS = {0: "CALIB_OK", 1: "CALIB_E_INVAL", 2: "CALIB_E_NOMEM", 3: "CALIB_E_DEVICE",
           4: "CALIB_E_RANK", 5: "CALIB_E_NUMERIC", 6: "CALIB_E_STATE"}
 EXPORTS = ["calib_init", "admm_local_step", "admm_consensus_update", "admm_solve", "calib_get",
-           "calib_set_jones", "calib_set_kernel_timing", "calib_destroy", "calib_last_error"]
+           "calib_set_jones", "calib_set_state", "calib_warmstart_features", "calib_warmstart_target",
+           "calib_warmstart_apply", "calib_mlp_create", "calib_mlp_forward", "calib_mlp_train_step", "calib_mlp_get",
+           "calib_mlp_destroy", "calib_mlp_last_error", "calib_set_kernel_timing",
+           "calib_destroy", "calib_last_error"]
+WS_FEATURES = 32
+WS_OUTPUTS = 8
+WS_SCALE = 10.0
 
 
 class CalibError(RuntimeError):
@@ -60,13 +66,28 @@ def load(path: str = LIB_PATH):
         lib.admm_solve.argtypes = [vp, i32, dbl, vp, C.POINTER(i32)]
         lib.calib_get.argtypes = [vp, i32, vp]
         lib.calib_set_jones.argtypes = [vp, vp]
+        lib.calib_set_state.argtypes = [vp, vp, vp, vp, vp]
         lib.calib_set_kernel_timing.argtypes = [vp, i32]
         lib.calib_destroy.argtypes = [vp]
         lib.calib_destroy.restype = None
         lib.calib_last_error.argtypes = [vp]
         lib.calib_last_error.restype = C.c_char_p
+        lib.calib_warmstart_features.argtypes = [vp, vp, vp, vp]
+        lib.calib_warmstart_apply.argtypes = [vp, vp, vp]
+        lib.calib_warmstart_target.argtypes = [vp, vp, vp]
+        lib.calib_mlp_create.argtypes = [i32, vp, vp, C.c_int64, vp, C.POINTER(vp)]
+        lib.calib_mlp_forward.argtypes = [vp, vp, C.c_int64, vp]
+        lib.calib_mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, i32, vp]
+        lib.calib_mlp_get.argtypes = [vp, i32, vp]
+        lib.calib_mlp_destroy.argtypes = [vp]
+        lib.calib_mlp_destroy.restype = None
+        lib.calib_mlp_last_error.argtypes = [vp]
+        lib.calib_mlp_last_error.restype = C.c_char_p
         for name in ("calib_init", "admm_local_step", "admm_consensus_update", "admm_solve",
-                     "calib_get", "calib_set_jones", "calib_set_kernel_timing"):
+                     "calib_get", "calib_set_jones", "calib_set_state", "calib_set_kernel_timing",
+                     "calib_warmstart_features", "calib_warmstart_target", "calib_warmstart_apply",
+                     "calib_mlp_create",
+                     "calib_mlp_forward", "calib_mlp_train_step", "calib_mlp_get"):
             getattr(lib, name).restype = C.c_int
         _lib = lib
     return _lib
@@ -170,6 +191,33 @@ class Calib:
     def set_jones(self, J):
         self._check(self.lib.calib_set_jones(self.ctx, _ptr(J)))
 
+    def set_state(self, J, Y=None, Z=None, BZ=None):
+        self._check(self.lib.calib_set_state(self.ctx, _ptr(J), _ptr(Y), _ptr(Z), _ptr(BZ)))
+
+    def warmstart_features(self, jones_prev2=None, bz_prev=None):
+        """Features [P*K*N][32] (float32, device) at the current J."""
+        import torch
+        out = torch.empty((self.P * self.K * self.N, WS_FEATURES), dtype=torch.float32,
+                          device="cuda")
+        self._check(self.lib.calib_warmstart_features(self.ctx, _ptr(jones_prev2), _ptr(bz_prev),
+                                                      _ptr(out)))
+        return out
+
+    def warmstart_target(self, jones_prev):
+        """Gauge-aligned training target [P*K*N][8] of the current J against jones_prev."""
+        import torch
+        out = torch.empty((self.P * self.K * self.N, WS_OUTPUTS), dtype=torch.float32,
+                          device="cuda")
+        self._check(self.lib.calib_warmstart_target(self.ctx, _ptr(jones_prev), _ptr(out)))
+        return out
+
+    def warmstart_apply(self, delta):
+        """J += delta / s where that lowers each subband's cost; returns the kept flags [P]."""
+        import torch
+        kept = torch.empty(self.P, dtype=torch.int32, device="cuda")
+        self._check(self.lib.calib_warmstart_apply(self.ctx, _ptr(delta), _ptr(kept)))
+        return kept
+
     def close(self):
         if getattr(self, "ctx", None):
             self.lib.calib_destroy(self.ctx)
@@ -180,3 +228,68 @@ class Calib:
             self.close()
         except Exception:
             pass
+
+
+class MLP:
+    """The warm-start network (calib_mlp_create ... calib_mlp_destroy)."""
+
+    def __init__(self, dims, params: np.ndarray, max_rows: int, stream=None):
+        import torch
+        self.lib = load()
+        self.dims = [int(d) for d in dims]
+        self._dims = np.ascontiguousarray(self.dims, np.int32)
+        p = np.ascontiguousarray(params, np.float32)
+        if p.size != n_params(self.dims):
+            raise ValueError(f"expected {n_params(self.dims)} parameters, got {p.size}")
+        self.max_rows = int(max_rows)
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        h = C.c_void_p()
+        st = self.lib.calib_mlp_create(len(self.dims) - 1, C.c_void_p(self._dims.ctypes.data),
+                                       C.c_void_p(p.ctypes.data), self.max_rows,
+                                       C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if st != 0:
+            raise CalibError(st, self.lib.calib_mlp_last_error(None).decode())
+        self.h = h
+        self.step = 0
+
+    def _check(self, st):
+        if st != 0:
+            raise CalibError(st, self.lib.calib_mlp_last_error(self.h).decode())
+
+    def forward(self, x):
+        import torch
+        y = torch.empty((x.shape[0], self.dims[-1]), dtype=torch.float32, device="cuda")
+        self._check(self.lib.calib_mlp_forward(self.h, _ptr(x), int(x.shape[0]), _ptr(y)))
+        return y
+
+    def train_step(self, x, target, lr: float, loss=None):
+        """One Adam step (lr = 0: gradients only); loss: optional device float32 [1]."""
+        if lr > 0:
+            self.step += 1
+        self._check(self.lib.calib_mlp_train_step(self.h, _ptr(x), _ptr(target), int(x.shape[0]),
+                                                  float(lr), max(self.step, 1), _ptr(loss)))
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(n_params(self.dims), np.float32)
+        self._check(self.lib.calib_mlp_get(self.h, 0, C.c_void_p(out.ctypes.data)))
+        return out
+
+    def grads(self) -> np.ndarray:
+        out = np.zeros(n_params(self.dims), np.float32)
+        self._check(self.lib.calib_mlp_get(self.h, 1, C.c_void_p(out.ctypes.data)))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.calib_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def n_params(dims) -> int:
+    return int(sum(dims[i] * dims[i + 1] + dims[i + 1] for i in range(len(dims) - 1)))

@@ -14,6 +14,9 @@
 
 using namespace calib;
 
+static_assert(CALIB_WS_FEATURES == kWsFeatures && CALIB_WS_OUTPUTS == kWsOutputs,
+              "warm-start row widths of the ABI and the kernels differ");
+
 namespace {
 constexpr int kMaxTrace = 4096;
 thread_local std::string g_init_error;
@@ -65,6 +68,9 @@ struct calib_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  // warm start
+  double *ws_jsave = nullptr;   // [P][K][N][8]
+  double *ws_cost = nullptr;    // [2][P]
 };
 
 namespace {
@@ -427,6 +433,8 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   DALLOC(B.trace, (size_t)kMaxTrace * 4 * 8);
   DALLOC(B.scratch, ((size_t)P * K + K) * 8);
   DALLOC(B.iter, sizeof(int));
+  DALLOC(c->ws_jsave, nj * 8);
+  DALLOC(c->ws_cost, (size_t)2 * P * 8);
   DALLOC(c->lm_trace, (size_t)P * K * c->lm_iters * 3 * 8);
   int *flagbuf;
   DALLOC(flagbuf, 2 * sizeof(int));
@@ -575,11 +583,81 @@ calib_status calib_get(calib_ctx *ctx, int32_t field, void *dst) {
   }
 }
 
+calib_status calib_warmstart_features(calib_ctx *ctx, const void *jones_prev2, const void *bz_prev,
+                                      float *features) {
+  if (!ctx) return CALIB_E_INVAL;
+  if (!features) return fail(ctx, CALIB_E_INVAL, "features is NULL");
+  hipStream_t s = ctx->stream;
+  const Problem &pb = ctx->pb;
+  const Layout &L = ctx->L;
+  const Buffers &B = ctx->B;
+  const double *J2 = static_cast<const double *>(jones_prev2);
+  const double *BZp = static_cast<const double *>(bz_prev);
+  // residual at the current J and the per-baseline sums of direction 0; each direction's
+  // statistics follow from a commit with an unchanged J (start point = current point)
+  HIPCHK(ctx, ctx->precision == CALIB_FP64 ? launch_refresh<double>(pb, L, B, s)
+                                           : launch_refresh<float>(pb, L, B, s));
+  for (int k = 0; k < ctx->K; ++k) {
+    HIPCHK(ctx, launch_lm_begin(pb, L, B, k, 1, s));
+    HIPCHK(ctx, launch_ws_features(pb, L, B, k, J2, BZp, features, s));
+    HIPCHK(ctx, ctx->precision == CALIB_FP64 ? launch_commit<double>(pb, L, B, k, s)
+                                             : launch_commit<float>(pb, L, B, k, s));
+  }
+  return CALIB_OK;
+}
+
+calib_status calib_warmstart_target(calib_ctx *ctx, const void *jones_prev, float *target) {
+  if (!ctx) return CALIB_E_INVAL;
+  if (!jones_prev || !target) return fail(ctx, CALIB_E_INVAL, "jones_prev or target is NULL");
+  HIPCHK(ctx, launch_ws_target(ctx->pb, ctx->L, ctx->B, static_cast<const double *>(jones_prev),
+                               target, ctx->stream));
+  return CALIB_OK;
+}
+
+calib_status calib_warmstart_apply(calib_ctx *ctx, const float *delta, int32_t *kept) {
+  if (!ctx) return CALIB_E_INVAL;
+  if (!delta) return fail(ctx, CALIB_E_INVAL, "delta is NULL");
+  hipStream_t s = ctx->stream;
+  const Problem &pb = ctx->pb;
+  const Layout &L = ctx->L;
+  const Buffers &B = ctx->B;
+  double *cost0 = ctx->ws_cost, *cost1 = ctx->ws_cost + ctx->P;
+  auto cost = [&](double *out) -> hipError_t {
+    hipError_t e = ctx->precision == CALIB_FP64 ? launch_refresh<double>(pb, L, B, s)
+                                                : launch_refresh<float>(pb, L, B, s);
+    return e == hipSuccess ? launch_subband_cost(pb, L, B, out, s) : e;
+  };
+  HIPCHK(ctx, cost(cost0));
+  HIPCHK(ctx, launch_ws_add(pb, L, B, delta, ctx->ws_jsave, s));
+  HIPCHK(ctx, cost(cost1));
+  HIPCHK(ctx, launch_ws_choose(pb, B, cost0, cost1, ctx->ws_jsave, kept, s));
+  ctx->iters_done = 0;
+  return CALIB_OK;
+}
+
 calib_status calib_set_kernel_timing(calib_ctx *ctx, int32_t enable) {
   if (!ctx) return CALIB_E_INVAL;
   HIPCHK(ctx, flush_timing(ctx));
   ctx->timing = enable != 0;
   for (int i = 0; i < CALIB_NUM_KERNELS; ++i) ctx->kms[i] = ctx->kcount[i] = 0.0;
+  return CALIB_OK;
+}
+
+calib_status calib_set_state(calib_ctx *ctx, const void *jones, const void *y, const void *z,
+                             const void *bz) {
+  if (!ctx) return CALIB_E_INVAL;
+  if (!jones) return fail(ctx, CALIB_E_INVAL, "jones is NULL");
+  hipStream_t s = ctx->stream;
+  const int64_t nj = (int64_t)ctx->P * ctx->K * ctx->N * 8;
+  const int64_t nz = (int64_t)ctx->K * ctx->Q * ctx->N * 8;
+  HIPCHK(ctx, hipMemcpyAsync(ctx->B.J, jones, nj * 8, hipMemcpyDeviceToDevice, s));
+  if (y) HIPCHK(ctx, hipMemcpyAsync(ctx->B.Y, y, nj * 8, hipMemcpyDeviceToDevice, s));
+  else HIPCHK(ctx, launch_zero(ctx->B.Y, nj, s));
+  if (z) HIPCHK(ctx, hipMemcpyAsync(ctx->B.Z, z, nz * 8, hipMemcpyDeviceToDevice, s));
+  else HIPCHK(ctx, launch_zero(ctx->B.Z, nz, s));
+  if (bz) HIPCHK(ctx, hipMemcpyAsync(ctx->B.BZ, bz, nj * 8, hipMemcpyDeviceToDevice, s));
+  else HIPCHK(ctx, launch_zero(ctx->B.BZ, nj, s));
+  ctx->iters_done = 0;
   return CALIB_OK;
 }
 

@@ -112,6 +112,19 @@ hipError_t launch_gpa(const Problem &pb, const Layout &L, const Buffers &B, int 
 hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
 hipError_t launch_subband_cost(const Problem &pb, const Layout &L, const Buffers &B, double *out,
                                hipStream_t s);
+// warm start (warmstart_kernels.hip)
+constexpr int kWsFeatures = 32;     // network inputs per (subband, direction, station)
+constexpr int kWsOutputs = 8;       // network outputs: scaled change of the station's Jones
+constexpr double kWsScale = 10.0;   // scale of the difference features and of the outputs
+hipError_t launch_ws_features(const Problem &pb, const Layout &L, const Buffers &B, int k,
+                              const double *J2, const double *BZp, float *feat, hipStream_t s);
+hipError_t launch_ws_add(const Problem &pb, const Layout &L, const Buffers &B, const float *delta,
+                         double *Jsave, hipStream_t s);
+hipError_t launch_ws_target(const Problem &pb, const Layout &L, const Buffers &B, const double *Jprev,
+                            float *target, hipStream_t s);
+hipError_t launch_ws_choose(const Problem &pb, const Buffers &B, const double *cost0,
+                            const double *cost1, const double *Jsave, int32_t *kept, hipStream_t s);
+
 hipError_t launch_fill_identity(double *J, int64_t nblocks, hipStream_t s);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 

@@ -1,0 +1,213 @@
+// Kernels of the warm-start network: a fully connected GELU network trained and evaluated on the
+// GPU.  GEMMs run on v_mfma_f32_16x16x16bf16_1k (BF16 operands, FP32 accumulation); master
+// weights, biases, Adam moments, pre-activations and gradients are FP32.
+#include "calib_internal.h"
+#include "mlp_internal.h"
+
+#include <cmath>
+
+namespace calib {
+
+namespace {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTM = 64, kTN = 64, kTK = 16;   // output tile and k step of one workgroup
+
+__device__ inline unsigned short bf16_rne(float x) {
+  unsigned int u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+// C[M][N] = A'[M][K] B'[K][N] (FP32 out).  A' = A (stored [M][K]) or A^T (A stored [K][M]);
+// B' = B (stored [K][N]) or B^T (B stored [N][K]).  Out-of-range elements load as zero.
+// MFMA layouts (16x16x16 bf16): A lane l holds A[l%16][4(l/16)+e], B lane l holds
+// B[4(l/16)+e][l%16], accumulator element r of lane l is D[4(l/16)+r][l%16].
+template <bool TA, bool TB>
+__global__ __launch_bounds__(kBlock) void k_gemm_bf16(const unsigned short *A, const unsigned short *B,
+                                                      float *C, int M, int N, int K) {
+  __shared__ unsigned short As[kTM][kTK + 4];   // [m][k]
+  __shared__ unsigned short Bs[kTN][kTK + 4];   // [n][k]
+  const int m0 = blockIdx.x * kTM, n0 = blockIdx.y * kTN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;   // 2x2 waves, 32x32 each
+  f4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += kTK) {
+    for (int idx = tid; idx < kTM * kTK; idx += kBlock) {
+      const int mm = idx / kTK, kk = idx % kTK, gm = m0 + mm, gk = k0 + kk;
+      unsigned short v = 0;
+      if (gm < M && gk < K) v = TA ? A[(int64_t)gk * M + gm] : A[(int64_t)gm * K + gk];
+      As[mm][kk] = v;
+    }
+    for (int idx = tid; idx < kTN * kTK; idx += kBlock) {
+      const int nn = idx / kTK, kk = idx % kTK, gn = n0 + nn, gk = k0 + kk;
+      unsigned short v = 0;
+      if (gn < N && gk < K) v = TB ? B[(int64_t)gn * K + gk] : B[(int64_t)gk * N + gn];
+      Bs[nn][kk] = v;
+    }
+    __syncthreads();
+    s4 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        a[i][e] = (short)As[wm + i * 16 + (lane & 15)][4 * (lane >> 4) + e];
+        b[i][e] = (short)Bs[wn + i * 16 + (lane & 15)][4 * (lane >> 4) + e];
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + i * 16 + 4 * (lane >> 4) + r, gn = n0 + wn + j * 16 + (lane & 15);
+        if (gm < M && gn < N) C[(int64_t)gm * N + gn] = acc[i][j][r];
+      }
+}
+
+__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ inline float gelu_grad(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+// Z = C + b (kept), out = BF16(GELU(Z)) or, for the last layer, Y = Z
+__global__ void k_bias_act(const float *C, const float *b, float *Z, unsigned short *Hb, float *Y,
+                           int64_t rows, int n, int act) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * n) return;
+  const float z = C[i] + b[i % n];
+  if (act) {
+    Z[i] = z;
+    Hb[i] = bf16_rne(gelu(z));
+  } else {
+    Y[i] = z;
+  }
+}
+
+__global__ void k_to_bf16(const float *x, unsigned short *y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = bf16_rne(x[i]);
+}
+
+// mean-square error loss: dY = 2 (Y - T) / (rows n) as BF16, per-block loss partials (FP64)
+__global__ __launch_bounds__(kBlock) void k_mse(const float *Y, const float *T, unsigned short *dYb,
+                                                double *part, int64_t total) {
+  __shared__ double red[kBlock / 64];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+    const float d = Y[i] - T[i];
+    s += (double)d * d;
+    dYb[i] = bf16_rne(2.0f * d / (float)total);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_loss_final(const double *part, int nparts, int64_t total, float *loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < nparts; ++i) s += part[i];
+  loss[0] = (float)(s / (double)total);
+}
+
+// gb[j] = sum over rows of dZ[r][j] (dZ stored BF16), fixed order per column
+__global__ void k_colsum(const unsigned short *dZb, float *gb, int64_t rows, int n) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int64_t r = 0; r < rows; ++r) s += bf16_to_f(dZb[r * n + j]);
+  gb[j] = (float)s;
+}
+
+// dZ = dA * GELU'(Z) stored BF16
+__global__ void k_gelu_back(const float *dA, const float *Z, unsigned short *dZb, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dZb[i] = bf16_rne(dA[i] * gelu_grad(Z[i]));
+}
+
+// Adam on FP32 master parameters; refreshes the BF16 copy of the weights
+__global__ void k_adam(float *p, const float *g, float *m, float *v, unsigned short *pb, int64_t n,
+                       float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float upd = lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  const float np = p[i] - upd;
+  p[i] = np;
+  if (pb) pb[i] = bf16_rne(np);
+}
+
+inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t mlp_gemm(const unsigned short *A, bool ta, const unsigned short *B, bool tb, float *C,
+                    int M, int N, int K, hipStream_t s) {
+  dim3 grid((M + kTM - 1) / kTM, (N + kTN - 1) / kTN), block(kBlock);
+  if (!ta && !tb) hipLaunchKernelGGL((k_gemm_bf16<false, false>), grid, block, 0, s, A, B, C, M, N, K);
+  else if (ta && !tb) hipLaunchKernelGGL((k_gemm_bf16<true, false>), grid, block, 0, s, A, B, C, M, N, K);
+  else if (!ta && tb) hipLaunchKernelGGL((k_gemm_bf16<false, true>), grid, block, 0, s, A, B, C, M, N, K);
+  else hipLaunchKernelGGL((k_gemm_bf16<true, true>), grid, block, 0, s, A, B, C, M, N, K);
+  return hipGetLastError();
+}
+
+hipError_t mlp_bias_act(const float *C, const float *b, float *Z, unsigned short *Hb, float *Y,
+                        int64_t rows, int n, bool act, hipStream_t s) {
+  hipLaunchKernelGGL(k_bias_act, dim3(blocks(rows * n)), dim3(256), 0, s, C, b, Z, Hb, Y, rows, n, act ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t mlp_to_bf16(const float *x, unsigned short *y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(blocks(n)), dim3(256), 0, s, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t mlp_mse(const float *Y, const float *T, unsigned short *dYb, double *part, int nparts,
+                   int64_t total, float *loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_mse, dim3(nparts), dim3(kBlock), 0, s, Y, T, dYb, part, total);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !loss) return e;
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, part, nparts, total, loss);
+  return hipGetLastError();
+}
+
+hipError_t mlp_colsum(const unsigned short *dZb, float *gb, int64_t rows, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_colsum, dim3(blocks(n, 64)), dim3(64), 0, s, dZb, gb, rows, n);
+  return hipGetLastError();
+}
+
+hipError_t mlp_gelu_back(const float *dA, const float *Z, unsigned short *dZb, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_gelu_back, dim3(blocks(n)), dim3(256), 0, s, dA, Z, dZb, n);
+  return hipGetLastError();
+}
+
+hipError_t mlp_adam(float *p, const float *g, float *m, float *v, unsigned short *pb, int64_t n,
+                    float lr, int step, hipStream_t s) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(blocks(n)), dim3(256), 0, s, p, g, m, v, pb, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+}  // namespace calib

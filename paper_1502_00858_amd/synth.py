@@ -36,6 +36,7 @@ CHAN_WIDTH_HZ = 0.2e6
 BAND_HZ = (115e6, 185e6)
 LATITUDE_RAD = np.deg2rad(52.9)
 SEED_BASE = 150200858
+INTERVAL_SLOT_RAD = 2 * np.pi / 1440   # hour angle of one time slot of an episode (1 minute)
 
 
 @dataclasses.dataclass
@@ -112,13 +113,18 @@ def _uvw(enu_b, hour_angles):
 
 def generate(cfg: SynthConfig, seed: Optional[int] = None, episode: int = 0,
              dtype=np.complex128, truth_in_span: bool = False,
-             jones_time_factor: Optional[np.ndarray] = None) -> dict:
+             jones_time_factor: Optional[np.ndarray] = None,
+             interval: Optional[int] = None) -> dict:
     """Draw one seeded solution interval.
 
     ``truth_in_span``: true Jones = I + polynomial of degree Q-1 in x=(f-f0)/f0, so that it lies
     exactly in the span of the calibration basis (used for fixed-point checks).
     ``jones_time_factor``: optional complex [N, K] multiplier of the perturbation (solution
     intervals that drift in time).
+    ``interval``: index of the solution interval within a longer observation.  Everything drawn
+    from ``seed`` (stations, sky, Jones polynomial, flags) stays fixed; the T time slots become
+    consecutive slots of INTERVAL_SLOT_RAD hour angle starting at interval*T, and the noise is
+    drawn from a generator seeded by (seed, interval).
     """
     if seed is None:
         seed = SEED_BASE + 1000 * cfg.config_index + episode
@@ -145,6 +151,8 @@ def generate(cfg: SynthConfig, seed: Optional[int] = None, episode: int = 0,
     st = _stations(rng, N, cfg.disk_radius_m)
     enu_b = st[q_idx] - st[p_idx]
     hour = np.sort(rng.uniform(-np.pi / 3, np.pi / 3, T))   # +-4 h
+    if interval is not None:
+        hour = -np.pi / 3 + (interval * T + np.arange(T)) * INTERVAL_SLOT_RAD
     uu, vv, ww = _uvw(enu_b, hour)                            # [B, T]
 
     l = rng.uniform(-cfg.lm_box, cfg.lm_box, K)
@@ -180,6 +188,7 @@ def generate(cfg: SynthConfig, seed: Optional[int] = None, episode: int = 0,
     vis = np.empty((int(vis_off[-1]), 2, 2), dtype)
     coh = np.empty(int(coh_off[-1]), dtype)
     noise_power = np.zeros(P)
+    nrng = rng if interval is None else np.random.default_rng([seed, interval])
 
     for f in range(P):
         nch = int(n_chan[f])
@@ -200,8 +209,8 @@ def generate(cfg: SynthConfig, seed: Optional[int] = None, episode: int = 0,
             live = flags[f] == 0
             spow = np.mean(np.abs(sig[live]) ** 2) if live.any() else 0.0
             npow = spow / cfg.snr                    # per complex entry
-            noise = (rng.normal(0, np.sqrt(npow / 2), sig.shape)
-                     + 1j * rng.normal(0, np.sqrt(npow / 2), sig.shape))
+            noise = (nrng.normal(0, np.sqrt(npow / 2), sig.shape)
+                     + 1j * nrng.normal(0, np.sqrt(npow / 2), sig.shape))
             noise[flags[f] == 1] = 0.0
             sig = sig + noise
             noise_power[f] = npow
@@ -216,6 +225,38 @@ def generate(cfg: SynthConfig, seed: Optional[int] = None, episode: int = 0,
         vis_off=vis_off, coh_off=coh_off, noise_power=noise_power,
         sources=dict(l=l, m=m, flux=flux, alpha=alpha), seed=seed,
     )
+
+
+def time_factor(cfg: SynthConfig, episode: int, interval: int, n_intervals: int) -> np.ndarray:
+    """Complex [N, K] drift of the Jones perturbation over the solution intervals of an episode:
+    sin(a1 tau + 2 pi b1) + j sin(a2 tau + 2 pi b2) with a, b ~ U(0, 1) per station and direction
+    (the time variation of the simulated gains in Section 4), tau = pi * interval / n_intervals so
+    that an episode covers about half a period."""
+    rng = np.random.default_rng([SEED_BASE, 7, cfg.config_index, episode])
+    a1, b1, a2, b2 = rng.uniform(0.0, 1.0, (4, cfg.N, cfg.K))
+    tau = np.pi * interval / max(n_intervals, 1)
+    return np.sin(a1 * tau + 2 * np.pi * b1) + 1j * np.sin(a2 * tau + 2 * np.pi * b2)
+
+
+def episode_interval(cfg: SynthConfig, episode: int, interval: int, n_intervals: int,
+                     dtype=np.complex128) -> dict:
+    """Solution interval ``interval`` of episode ``episode``: one sky, array and Jones polynomial
+    per episode, perturbation scaled by the episode's time factor, consecutive time slots."""
+    seed = SEED_BASE + 1000 * cfg.config_index + 100 * (episode + 1)
+    return generate(cfg, seed=seed, dtype=dtype,
+                    jones_time_factor=time_factor(cfg, episode, interval, n_intervals),
+                    interval=interval)
+
+
+def mlp_init_params(dims: Sequence[int], seed: int = SEED_BASE) -> np.ndarray:
+    """Seeded initial parameters of a fully connected network, float32, packed per layer as
+    W [dims[l]][dims[l+1]] then b [dims[l+1]]: W ~ N(0, 1/dims[l]), b = 0."""
+    rng = np.random.default_rng([seed, 11])
+    parts = []
+    for i in range(len(dims) - 1):
+        parts.append(rng.normal(0.0, 1.0 / np.sqrt(dims[i]), dims[i] * dims[i + 1]))
+        parts.append(np.zeros(dims[i + 1]))
+    return np.concatenate(parts).astype(np.float32)
 
 
 def identity_jones(P: int, K: int, N: int) -> np.ndarray:
