@@ -60,24 +60,26 @@ def measured_traffic(kernel):
         return nbytes if hashlib.sha256(fh.read()).hexdigest() == sha else None
 
 
-def kernel_work(name, data, K_active_total, n_chol_launch_subbands, elt):
-    """Algorithmic bytes or FLOPs of one launch of a kernel class."""
+def kernel_work(name, data, elt):
+    """Algorithmic bytes or FLOPs of one launch of a kernel class, averaged over the directions
+    (a direction's LM launches cover only the subbands that carry it)."""
     N = int(data["N"])
+    K = int(data["K"])
     n = 8 * N
-    nb = data["nb_live"]
-    spb = data["T"] * data["n_chan"]
-    S = float(np.sum(nb * spb))                  # samples over all subbands
+    nb = data["nb_live"].astype(np.float64)
+    Kf = np.asarray(data["n_dirs"], np.float64)
+    S_f = nb * data["T"] * np.asarray(data["n_chan"], np.float64)   # samples per subband
+    w = Kf / K                                   # share of a class's launches that cover f
     if name == "chol_solve":
-        return ("mfma", n_chol_launch_subbands * (n ** 3 / 3.0 + 2.0 * n ** 2), "TFLOP/s")
+        return ("mfma", float(np.sum(w)) * (n ** 3 / 3.0 + 2.0 * n ** 2), "TFLOP/s")
     if name == "trial":
-        return ("hbm", S * (8 * elt + 2 * elt) + np.sum(nb) * 64.0, "GB/s")
+        return ("hbm", float(np.sum(w * (S_f * (8 + 2) * elt + nb * 64.0))), "GB/s")
     if name == "commit":
-        return ("hbm", S * (8 * elt * 2 + 2 * 2 * elt) + np.sum(nb) * 64.0, "GB/s")
+        return ("hbm", float(np.sum(w * (S_f * (8 * 2 + 2 * 2) * elt + nb * 64.0))), "GB/s")
     if name == "refresh":
-        kbar = K_active_total / max(int(data["P"]), 1)
-        return ("hbm", S * (8 * elt * 2 + 2 * elt * kbar) + np.sum(nb) * 64.0, "GB/s")
+        return ("hbm", float(np.sum(S_f * (8 * 2 + 2 * Kf) * elt + nb * 64.0)), "GB/s")
     if name == "assemble":
-        return ("hbm", n_chol_launch_subbands * (n * (n + 1) / 2.0) * 8.0, "GB/s")
+        return ("hbm", float(np.sum(w)) * (n * (n + 1) / 2.0) * 8.0, "GB/s")
     return (None, None, None)
 
 
@@ -135,6 +137,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--tile-group", type=int, default=0)
+    ap.add_argument("--stream-grid", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="choose tile_group / stream_grid with paper_1502_00858_amd.autotune")
+    ap.add_argument("--batch", type=int, default=512, help="training minibatch rows")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the method's cross-subband exchange is a device-wide "
@@ -163,8 +169,8 @@ def main():
     gen_s = time.perf_counter() - t0
     X, Y = warmstart.stack_rows(train_iv)
     del train_iv
-    net = warmstart.WarmStartNet(max_rows=max(4096, int(cfg.P * cfg.K * cfg.N)))
-    train_s = net.train(X, Y, epochs=args.epochs, batch=512, lr=2e-3, lr_final=2e-4)
+    net = warmstart.WarmStartNet(max_rows=max(args.batch, int(cfg.P * cfg.K * cfg.N)))
+    train_s = net.train(X, Y, epochs=args.epochs, batch=args.batch, lr=2e-3, lr_final=2e-4)
     log(f"trained on {X.shape[0]} rows in {train_s:.1f} s, loss {net.history[-1]:.3e}")
 
     # ---- the measured interval and its predecessors (untimed) -----------------------------------
@@ -175,10 +181,19 @@ def main():
     P, B = int(data["P"]), cfg.B
     data["nb_live"] = np.array([B - int(data["flags"][f * B:(f + 1) * B].sum()) for f in range(P)])
     vis, coh, flags = calib.device_inputs(data, prec)
+    shape = {"tile_group": args.tile_group, "stream_grid": args.stream_grid, "source": "flags"}
+    if args.autotune:
+        from paper_1502_00858_amd import autotune
+        tuned = autotune.tune(data, vis, coh, flags, prec, refresh=True)
+        shape = {"tile_group": tuned["tile_group"], "stream_grid": tuned["stream_grid"],
+                 "source": "autotune", "stream_ms_per_local_step": round(tuned["ms"], 3),
+                 "worst_candidate_ms": round(max(c["ms"] for c in tuned["candidates"]), 3)}
+        log(f"autotune: {shape}")
     ctx = calib.Calib(data, vis, coh, flags, precision=prec, lm_iters=lm_iters, options=0,
-                      tile_group=args.tile_group)
+                      tile_group=shape["tile_group"], stream_grid=shape["stream_grid"])
     ctx_id = calib.Calib(data, vis, coh, flags, precision=prec, lm_iters=lm_iters,
-                         options=calib.OPT_GPA_FIRST_ITER, tile_group=args.tile_group)
+                         options=calib.OPT_GPA_FIRST_ITER, tile_group=shape["tile_group"],
+                         stream_grid=shape["stream_grid"])
     J_id = torch.from_numpy(synth.identity_jones(P, cfg.K, cfg.N)).cuda()
 
     def start_plain():
@@ -214,6 +229,9 @@ def main():
     kept = start_learned().cpu().numpy()
     ws_s = timed(start_learned, max(args.steps, 3), 1) - timed(start_plain, max(args.steps, 3), 1)
     value = P / sec["learned"]
+    kdesc = cfg.K if cfg.n_dirs is None and cfg.name != "c3" else f"{cfg.K} (K_f ~ U{{3..10}})"
+    cdesc = cfg.n_chan if cfg.n_chan > 0 else "U{1..16}"
+    fdesc = f" flagged ~U(0,{cfg.flag_frac_max})" if cfg.flag_frac_max > 0 else ""
 
     out = {"metric": "subband ADMM solves/s (N=62,K=5) at 1e-6 rel cost, learned vs plain; HBM GB/s",
            "value": value, "unit": "subband-solves/s", "n_gpus": 1, "steps": args.steps,
@@ -221,8 +239,8 @@ def main():
            "scaling": "weak", "vs_baseline": None,
            "dtype": "f64+bf16" if prec == calib.CALIB_FP64 else "f32+f64+bf16",
            "data": "synthetic",
-           "config": {"workload": f"{args.config}: N={cfg.N} K={cfg.K} T={cfg.T} P={P} "
-                                  f"n_chan={cfg.n_chan} Q={cfg.Q} rho={cfg.rho} lm={lm_iters}, "
+           "config": {"workload": f"{args.config}: N={cfg.N} K={kdesc} T={cfg.T} P={P} "
+                                  f"n_chan={cdesc} Q={cfg.Q} rho={cfg.rho} lm={lm_iters}{fdesc}, "
                                   f"interval {J_EVAL} of a drifting episode, learned warm start",
                       "global_batch": P, "parallelism": "none (1 GPU)"}}
     out["target_cost"] = g_inf
@@ -234,7 +252,8 @@ def main():
     out["final_primal_residual"] = {k: float(v[-1, 2]) for k, v in final.items()}
     out["warm_start_ms"] = 1e3 * ws_s
     out["learned_kept_subbands"] = int(kept.sum())
-    out["training"] = {"rows": int(X.shape[0]), "epochs": args.epochs, "batch": 512,
+    out["tile_shape"] = shape
+    out["training"] = {"rows": int(X.shape[0]), "epochs": args.epochs, "batch": args.batch,
                        "pair_generation_s": round(gen_s, 2), "train_s": round(train_s, 2),
                        "final_loss": net.history[-1],
                        "zero_predictor_loss": float(np.mean(Y.astype(np.float64) ** 2))}
@@ -262,7 +281,7 @@ def main():
         dom = max(kt, key=lambda k: kt[k][1])
         launches, ms = kt[dom]
         avg_s = ms / launches / 1e3
-        bound, work, unit = kernel_work(dom, data, int(np.sum(data["n_dirs"])), P, elt)
+        bound, work, unit = kernel_work(dom, data, elt)
         if bound is not None:
             achieved = work / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
             peak = FP64_PEAK_TFS if unit == "TFLOP/s" else HBM_PEAK_GBS
@@ -271,7 +290,7 @@ def main():
                                "avg_launch_us": avg_s * 1e6, "share_of_step": ms / total}
         # the streaming pass at the LM trial point: achieved HBM bandwidth
         tl, tms = kt["trial"]
-        _, tb, _ = kernel_work("trial", data, 0, P, elt)
+        _, tb, _ = kernel_work("trial", data, elt)
         out["trial_pass_GBs"] = tb / (tms / tl / 1e3) / 1e9
 
     if not args.no_cpu_baseline:
