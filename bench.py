@@ -83,25 +83,29 @@ def kernel_work(name, data, elt):
     return (None, None, None)
 
 
-def cpu_baseline(data, iters_sample, iters_to_target, lm_iters):
-    """The FP64 oracle's plain C-ADMM on the same interval (FP32-rounded inputs): the time of
-    iters_sample iterations, scaled to the iterations the plain start needs to reach the target
-    (an iteration costs the same from any start)."""
+def cpu_baseline(data, iters_sample, iters_to_target, lm_iters, lm_tol):
+    """The FP64 oracle's plain C-ADMM on the same interval (FP32-rounded inputs).  Per-iteration
+    time = (time of 2 + iters_sample iterations - time of 2 iterations) / iters_sample, i.e. the
+    cost of iterations after the first two (where the LM stopping rule acts as it does in the
+    timed GPU runs), scaled to the iterations the plain start needs to reach the target."""
     import oracle
     from paper_1502_00858_amd import synth
-    pb = oracle.Problem(synth.as_fp32_inputs(data), lm_iters=lm_iters, options=0)
+    pb = oracle.Problem(synth.as_fp32_inputs(data), lm_iters=lm_iters, options=0, lm_tol=lm_tol)
     P, K, N = int(data["P"]), int(data["K"]), int(data["N"])
     J0 = synth.identity_jones(P, K, N)
     t0 = time.perf_counter()
-    pb.admm_solve(J0, iters_sample)
-    el = time.perf_counter() - t0
-    per_solve = el * iters_to_target / iters_sample
+    pb.admm_solve(J0, 2)
+    t1 = time.perf_counter()
+    pb.admm_solve(J0, 2 + iters_sample)
+    t2 = time.perf_counter()
+    per_iter = ((t2 - t1) - (t1 - t0)) / iters_sample
+    per_solve = per_iter * iters_to_target
     return {"value": P / per_solve, "unit": "subband-solves/s", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"{iters_sample} ADMM iterations over all {P} subbands of the measured "
-                      f"interval (FP64 oracle on the FP32-rounded inputs), {el:.1f} s, scaled "
-                      f"x{iters_to_target / iters_sample:g} to the {iters_to_target} iterations "
-                      f"the plain start needs to reach the target"}
+            "sample": f"ADMM iterations 3-{2 + iters_sample} over all {P} subbands of the measured "
+                      f"interval (FP64 oracle on the FP32-rounded inputs, same LM stopping rule), "
+                      f"{per_iter:.2f} s per iteration ({t2 - t0:.1f} s of runs), scaled to the "
+                      f"{iters_to_target} iterations the plain start needs to reach the target"}
 
 
 def timed(fn, steps, warmup):
@@ -123,6 +127,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--lm-iters", type=int, default=None)
+    ap.add_argument("--lm-tol", type=float, default=1e-10,
+                    help="LM stopping rule: predicted decrease <= lm_tol * objective (0 = off)")
     ap.add_argument("--chain-iters", type=int, default=30,
                     help="ADMM iterations per interval when solving the episodes")
     ap.add_argument("--ref-iters", type=int, default=100,
@@ -164,7 +170,7 @@ def main():
     train_iv = []
     for e in range(args.train_episodes):
         train_iv += warmstart.solve_episode(cfg, e, args.episode_intervals, prec, args.chain_iters,
-                                            lm_iters)
+                                            lm_iters, lm_tol=args.lm_tol)
         log(f"training episode {e} solved ({time.perf_counter() - t0:.1f} s)")
     gen_s = time.perf_counter() - t0
     X, Y = warmstart.stack_rows(train_iv)
@@ -175,7 +181,7 @@ def main():
 
     # ---- the measured interval and its predecessors (untimed) -----------------------------------
     chain = warmstart.solve_episode(cfg, TEST_EPISODE, args.episode_intervals, prec,
-                                    args.chain_iters, lm_iters, count=J_EVAL)
+                                    args.chain_iters, lm_iters, count=J_EVAL, lm_tol=args.lm_tol)
     prev, prev2 = chain[-1], chain[-2]
     data = synth.episode_interval(cfg, TEST_EPISODE, J_EVAL, args.episode_intervals)
     P, B = int(data["P"]), cfg.B
@@ -190,10 +196,11 @@ def main():
                  "worst_candidate_ms": round(max(c["ms"] for c in tuned["candidates"]), 3)}
         log(f"autotune: {shape}")
     ctx = calib.Calib(data, vis, coh, flags, precision=prec, lm_iters=lm_iters, options=0,
-                      tile_group=shape["tile_group"], stream_grid=shape["stream_grid"])
+                      tile_group=shape["tile_group"], stream_grid=shape["stream_grid"],
+                      lm_tol=args.lm_tol)
     ctx_id = calib.Calib(data, vis, coh, flags, precision=prec, lm_iters=lm_iters,
                          options=calib.OPT_GPA_FIRST_ITER, tile_group=shape["tile_group"],
-                         stream_grid=shape["stream_grid"])
+                         stream_grid=shape["stream_grid"], lm_tol=args.lm_tol)
     J_id = torch.from_numpy(synth.identity_jones(P, cfg.K, cfg.N)).cuda()
 
     def start_plain():
@@ -240,7 +247,7 @@ def main():
            "dtype": "f64+bf16" if prec == calib.CALIB_FP64 else "f32+f64+bf16",
            "data": "synthetic",
            "config": {"workload": f"{args.config}: N={cfg.N} K={kdesc} T={cfg.T} P={P} "
-                                  f"n_chan={cdesc} Q={cfg.Q} rho={cfg.rho} lm={lm_iters}{fdesc}, "
+                                  f"n_chan={cdesc} Q={cfg.Q} rho={cfg.rho} lm<={lm_iters} lm_tol={args.lm_tol:g}{fdesc}, "
                                   f"interval {J_EVAL} of a drifting episode, learned warm start",
                       "global_batch": P, "parallelism": "none (1 GPU)"}}
     out["target_cost"] = g_inf
@@ -262,7 +269,7 @@ def main():
         # FP64 solve from the same previous state, same iterations as the timed plain step
         v64, c64, f64 = calib.device_inputs(data, calib.CALIB_FP64)
         r64 = calib.Calib(data, v64, c64, f64, precision=calib.CALIB_FP64, lm_iters=lm_iters,
-                          options=0)
+                          options=0, lm_tol=args.lm_tol)
         r64.set_state(prev.J, prev.Y, prev.Z, prev.BZ)
         tr64 = r64.solve(iters["plain"] or args.ref_iters)
         g32 = final["plain"][-1, 0]
@@ -271,11 +278,21 @@ def main():
         del v64, c64, f64
 
     if not args.no_profile:
-        ctx.set_kernel_timing(True)
-        start_learned()
-        ctx.solve(iters["learned"] or args.ref_iters)
-        kt = ctx.get(calib.FIELD_KERNEL_TIMES)
-        ctx.set_kernel_timing(False)
+        # per-launch work is only well defined when every launch covers every subband that
+        # carries the direction: the profiled solve runs with the stopping rule off
+        pctx = ctx
+        if args.lm_tol > 0:
+            pctx = calib.Calib(data, vis, coh, flags, precision=prec, lm_iters=lm_iters, options=0,
+                               tile_group=shape["tile_group"], stream_grid=shape["stream_grid"])
+        pctx.set_kernel_timing(True)
+        pctx.set_state(prev.J, prev.Y, prev.Z, prev.BZ)
+        pctx.warmstart_apply(net.predict(pctx.warmstart_features(prev2.J, prev.BZ)))
+        pctx.solve(iters["learned"] or args.ref_iters)
+        kt = pctx.get(calib.FIELD_KERNEL_TIMES)
+        pctx.set_kernel_timing(False)
+        if pctx is not ctx:
+            pctx.close()
+        out["profiled_solve"] = "learned start, stopping rule off (every LM launch full)"
         total = sum(v[1] for v in kt.values())
         out["kernel_ms_per_step"] = {k: round(v[1], 3) for k, v in kt.items()}
         dom = max(kt, key=lambda k: kt[k][1])
@@ -295,7 +312,8 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(data, args.cpu_sample_iters,
-                                           iters["plain"] or args.ref_iters, lm_iters)
+                                           iters["plain"] or args.ref_iters, lm_iters,
+                                           args.lm_tol)
     ctx.close()
     ctx_id.close()
     net.close()

@@ -90,6 +90,15 @@ typedef struct {
                               chosen from the samples per baseline (tile-shape tuner output)   */
   int32_t stream_grid;     /* workgroups of the streaming passes: 0 = one per tile, > 0 = a
                               persistent grid striding over the tiles                          */
+  double lm_tol;           /* LM stopping rule: a direction's LM run ends after an iteration whose
+                              step predicts a decrease ell <= lm_tol * F (F the objective before
+                              the step); 0 = always lm_iters iterations.  Skipped iterations
+                              launch nothing for that subband; their CALIB_FIELD_LM_TRACE rows
+                              repeat (F, lambda) with accepted = 0                             */
+  int32_t solver;          /* Cholesky solver of the damped normal equations: 1 = one workgroup
+                              per subband matrix, 2 = 64-column panels spread over many
+                              workgroups per matrix (for batches that leave compute units idle),
+                              0 = chosen from the number of subbands                           */
 } calib_config;
 
 /* Field selectors for calib_get. */

@@ -31,7 +31,7 @@ class _Cfg(C.Structure):
                 ("n_chan", C.POINTER(C.c_int32)), ("n_dirs", C.POINTER(C.c_int32)),
                 ("freq", C.POINTER(C.c_double)), ("f0", C.c_double),
                 ("rho", C.POINTER(C.c_double)), ("lm_iters", C.c_int),
-                ("sage_sweeps", C.c_int), ("options", C.c_uint32)]
+                ("sage_sweeps", C.c_int), ("options", C.c_uint32), ("lm_tol", C.c_double)]
 
 
 class _Data(C.Structure):
@@ -78,7 +78,7 @@ class Problem:
     """Holds one interval's arrays in the layout the C oracle expects (contiguous copies)."""
 
     def __init__(self, data: dict, lm_iters: int | None = None, sage_sweeps: int = 1,
-                 options: int = OPT_GPA_FIRST, rho=None):
+                 options: int = OPT_GPA_FIRST, rho=None, lm_tol: float = 0.0):
         self.N, self.P, self.Q, self.K, self.T = (int(data[k]) for k in ("N", "P", "Q", "K", "T"))
         self.n_chan = np.ascontiguousarray(data["n_chan"], np.int32)
         self.n_dirs = np.ascontiguousarray(data["n_dirs"], np.int32)
@@ -93,7 +93,7 @@ class Problem:
                         self.n_dirs.ctypes.data_as(C.POINTER(C.c_int32)),
                         self.freq.ctypes.data_as(C.POINTER(C.c_double)), float(data["f0"]),
                         self.rho.ctypes.data_as(C.POINTER(C.c_double)), self.lm_iters,
-                        int(sage_sweeps), int(options))
+                        int(sage_sweeps), int(options), float(lm_tol))
         self.dat = _Data(self.vis.ctypes.data, self.coh.ctypes.data, self.flags.ctypes.data)
         self.sage_sweeps = int(sage_sweeps)
 

@@ -304,8 +304,12 @@ static void chol_solve(int n, const double *L, const double *b, double *x) {
 /* Levenberg-Marquardt on one direction's augmented Lagrangian (minimisation M1).
  * Damping follows Nielsen's rule (Madsen, Nielsen & Tingleff 2004, Sec. 3.2): lambda_0 =
  * tau * max diag(A), A = H_GN + rho I; step (A + lambda I) delta = -G; predicted decrease
- * ell = delta.(lambda delta - G)/2; accept iff ell > 0 and the objective decreases. */
-static void lm_dir(const dir_problem *P, double complex *Jd, int iters, double *trace) {
+ * ell = delta.(lambda delta - G)/2; accept iff ell > 0 and the objective decreases.
+ * Stopping: after an iteration whose step predicts ell <= lm_tol * F (F the objective before
+ * the step) the run ends, the trace rows of the iterations not run repeating (F, lambda) with
+ * accepted = 0; lm_tol = 0 runs all iterations. */
+static void lm_dir(const dir_problem *P, double complex *Jd, int iters, double lm_tol,
+                   double *trace) {
   const int N = P->N, n = 8 * N;
   double complex *D = malloc(sizeof(double complex) * 4 * P->B);
   double complex *G = malloc(sizeof(double complex) * 4 * N);
@@ -323,7 +327,8 @@ static void lm_dir(const dir_problem *P, double complex *Jd, int iters, double *
   double lambda = LM_TAU * dmax, nu = 2.0;
 
   for (int it = 0; it < iters; ++it) {
-    int accepted = 0;
+    int accepted = 0, stop = 0;
+    const double F_before = F;
     memcpy(Mw, A, sizeof(double) * n * n);
     for (int i = 0; i < n; ++i) Mw[(int64_t)i * n + i] += lambda;
     if (or_cholesky(n, Mw, L) != 0) {
@@ -336,6 +341,7 @@ static void lm_dir(const dir_problem *P, double complex *Jd, int iters, double *
         ell += delta[2 * i] * (lambda * delta[2 * i] - creal(G[i]))
              + delta[2 * i + 1] * (lambda * delta[2 * i + 1] - cimag(G[i]));
       ell *= 0.5;
+      stop = lm_tol > 0.0 && ell <= lm_tol * F_before;
       for (int i = 0; i < 4 * N; ++i) Jt[i] = Jd[i] + delta[2 * i] + I * delta[2 * i + 1];
       const double Fn = dir_data_cost(P, Jt, NULL) + dir_penalty(P, Jt);
       if (ell > 0.0 && F - Fn > 0.0) {
@@ -354,6 +360,12 @@ static void lm_dir(const dir_problem *P, double complex *Jd, int iters, double *
       }
     }
     if (trace) { trace[3 * it] = F; trace[3 * it + 1] = lambda; trace[3 * it + 2] = accepted; }
+    if (stop) {
+      for (int r = it + 1; trace && r < iters; ++r) {
+        trace[3 * r] = F; trace[3 * r + 1] = lambda; trace[3 * r + 2] = 0;
+      }
+      break;
+    }
   }
   free(D); free(G); free(Jt); free(A); free(Mw); free(L); free(rhs); free(delta);
 }
@@ -416,7 +428,7 @@ int or_local_step(const or_cfg *c, const or_data *d, double complex *J, const do
         double *tr = lm_trace
             ? lm_trace + 3 * (int64_t)c->lm_iters * ((int64_t)(f * c->sage_sweeps + sw) * K + k)
             : NULL;
-        lm_dir(&P, J + o, c->lm_iters, tr);
+        lm_dir(&P, J + o, c->lm_iters, c->lm_tol, tr);
       }
     free(Vk);
   }

@@ -32,6 +32,7 @@ typedef struct {
   const double *rho;       /* [K] */
   int lm_iters, sage_sweeps;
   uint32_t options;
+  double lm_tol;           /* stop a direction's LM once a step's predicted decrease <= lm_tol*F */
 } or_cfg;
 
 typedef struct {

@@ -46,7 +46,8 @@ class _Config(C.Structure):
                 ("freq_hz", C.POINTER(C.c_double)), ("f0_hz", C.c_double),
                 ("rho", C.POINTER(C.c_double)), ("precision", C.c_int),
                 ("lm_iters", C.c_int32), ("sage_sweeps", C.c_int32), ("options", C.c_uint32),
-                ("tile_group", C.c_int32), ("stream_grid", C.c_int32)]
+                ("tile_group", C.c_int32), ("stream_grid", C.c_int32), ("lm_tol", C.c_double),
+                ("solver", C.c_int32)]
 
 
 _lib = None
@@ -56,6 +57,9 @@ def load(path: str = LIB_PATH):
     """Load the HIP library (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch's HIP runtime must be the process's HIP runtime: load it before the library
+        # (whose libamdhip64 dependency then resolves to the already-loaded copy)
+        import torch  # noqa: F401
         if not os.path.exists(path):
             raise RuntimeError(f"{path} is missing: build it with paper_1502_00858_amd.build.build()")
         lib = C.CDLL(path)
@@ -113,7 +117,7 @@ class Calib:
     def __init__(self, data: dict, vis, coh, flags=None, jones0=None, precision: int = CALIB_FP64,
                  lm_iters: Optional[int] = None, sage_sweeps: int = 1,
                  options: int = OPT_GPA_FIRST_ITER, rho=None, stream=None, tile_group: int = 0,
-                 stream_grid: int = 0):
+                 stream_grid: int = 0, lm_tol: float = 0.0, solver: int = 0):
         import torch
         self.lib = load()
         self.N, self.P, self.Q, self.K, self.T = (int(data[k]) for k in ("N", "P", "Q", "K", "T"))
@@ -131,7 +135,7 @@ class Calib:
                       self._freq.ctypes.data_as(C.POINTER(C.c_double)), float(data["f0"]),
                       self._rho.ctypes.data_as(C.POINTER(C.c_double)), int(precision),
                       self.lm_iters, int(sage_sweeps), int(options), int(tile_group),
-                      int(stream_grid))
+                      int(stream_grid), float(lm_tol), int(solver))
         self.stream = torch.cuda.current_stream() if stream is None else stream
         ctx = C.c_void_p()
         st = self.lib.calib_init(C.byref(cfg), _ptr(vis), _ptr(coh), _ptr(flags), _ptr(jones0),

@@ -176,7 +176,11 @@ calib_status run_local_step(calib_ctx *c, int admm_iter, hipStream_t s) {
       HIPCHK(c, timed(c, CALIB_KERNEL_LM_BEGIN, [&] { return launch_lm_begin(pb, L, B, k, unreg, s); }));
       for (int it = 0; it < c->lm_iters; ++it) {
         HIPCHK(c, timed(c, CALIB_KERNEL_ASSEMBLE, [&] { return launch_assemble(pb, L, B, k, unreg, s); }));
-        HIPCHK(c, timed(c, CALIB_KERNEL_CHOL_SOLVE, [&] { return launch_chol_solve_nd(pb, B, k, c->d_ndir, s); }));
+        HIPCHK(c, timed(c, CALIB_KERNEL_CHOL_SOLVE, [&] {
+          return pb.solver == kSolverBlocked
+                     ? launch_chol_blocked(pb, B, k, c->d_ndir, B.chol_ld, B.chol_fail, s)
+                     : launch_chol_solve_nd(pb, B, k, c->d_ndir, s);
+        }));
         HIPCHK(c, timed(c, CALIB_KERNEL_TRIAL, [&] { return launch_trial<T>(pb, L, B, k, s); }));
         HIPCHK(c, timed(c, CALIB_KERNEL_LM_UPDATE, [&] {
           return launch_lm_update_tr(pb, L, B, k, unreg, c->lm_trace, it, c->lm_iters, s);
@@ -263,6 +267,9 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
     return fail(nullptr, CALIB_E_INVAL, "unknown precision");
   if (cfg->lm_iters < 1 || cfg->sage_sweeps < 1)
     return fail(nullptr, CALIB_E_INVAL, "lm_iters and sage_sweeps must be >= 1");
+  if (!(cfg->lm_tol >= 0.0) || !std::isfinite(cfg->lm_tol))
+    return fail(nullptr, CALIB_E_INVAL, "lm_tol must be finite and >= 0");
+  if (cfg->solver < 0 || cfg->solver > 2) return fail(nullptr, CALIB_E_INVAL, "solver must be 0, 1 or 2");
 
   calib_ctx *c = new calib_ctx();
   c->N = N; c->P = P; c->Q = Q; c->K = K; c->T = T;
@@ -374,6 +381,10 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   pb.group = group;
   pb.bpt = bpt;
   pb.stream_grid = cfg->stream_grid > 0 ? cfg->stream_grid : 0;
+  pb.lm_tol = cfg->lm_tol;
+  pb.solver = cfg->solver == 1 ? kSolverSingle
+              : cfg->solver == 2 ? kSolverBlocked
+              : (P < kBlockedSolverMaxSubbands ? kSolverBlocked : kSolverSingle);
 
   calib_status st = CALIB_OK;
 #define UPL(dst, src)                                                                          \
@@ -433,6 +444,12 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   DALLOC(B.trace, (size_t)kMaxTrace * 4 * 8);
   DALLOC(B.scratch, ((size_t)P * K + K) * 8);
   DALLOC(B.iter, sizeof(int));
+  B.chol_fail = nullptr;
+  B.chol_ld = nullptr;
+  if (pb.solver == kSolverBlocked) {
+    DALLOC(B.chol_fail, (size_t)P * sizeof(int));
+    DALLOC(B.chol_ld, (size_t)P * chol_blocked_panels(pb) * 64 * 64 * 8);
+  }
   DALLOC(c->ws_jsave, nj * 8);
   DALLOC(c->ws_cost, (size_t)2 * P * 8);
   DALLOC(c->lm_trace, (size_t)P * K * c->lm_iters * 3 * 8);
@@ -454,6 +471,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
           "pack") &&
       dev(launch_basis_setup(pb, d_freq, c->f0, d_ndir, basis, fitw, flagbuf + 1, s), "basis setup") &&
       dev(launch_zero(B.H, (int64_t)P * pb.npad * pb.nf, s), "zero H") &&
+      (!B.chol_fail || dev(hipMemsetAsync(B.chol_fail, 0, (size_t)P * sizeof(int), s), "zero flags")) &&
       dev(launch_zero(B.Y, (int64_t)nj, s), "zero Y") && dev(launch_zero(B.BZ, (int64_t)nj, s), "zero BZ") &&
       dev(launch_zero(B.Z, (int64_t)nz, s), "zero Z") &&
       dev(launch_zero(B.trace, (int64_t)kMaxTrace * 4, s), "zero trace") &&

@@ -43,7 +43,7 @@ struct LmState {
   int32_t chol_ok; // last factorisation succeeded
   int32_t accepted;// accepted steps in this LM run
   int32_t active;  // subband carries the active direction
-  int32_t pad;
+  int32_t done;    // the LM run of the active direction has met its stopping rule
 };
 
 struct Problem {
@@ -54,7 +54,13 @@ struct Problem {
   int group;       // lanes per baseline in the streaming kernels
   int bpt;         // baselines per tile = kBlock / group
   int stream_grid; // 0 = one workgroup per tile, else persistent grid size
+  double lm_tol;   // LM stops once a step's predicted decrease <= lm_tol * F (0 = never)
+  int solver;      // normal-equation solver: kSolverSingle or kSolverBlocked
 };
+
+constexpr int kSolverSingle = 1;    // one workgroup per matrix (chol_kernel.hip)
+constexpr int kSolverBlocked = 2;   // 64-column panels over many workgroups (chol_blocked.hip)
+constexpr int kBlockedSolverMaxSubbands = 128;   // automatic choice: blocked below this batch
 
 struct Buffers {
   const void *V;   // packed visibilities (stream type)
@@ -75,6 +81,8 @@ struct Buffers {
   double *trace;                        // [iters][4]
   double *scratch;                      // [P*K*2 + K] residual partials
   int *iter;                            // ADMM iteration whose trace row is being written
+  int *chol_fail;                       // [P] blocked solver: a pivot failed in this solve
+  double *chol_ld;                      // [P][panels][64*64] blocked solver: diagonal blocks' L
 };
 
 // streaming kernels (templated on the stream element type float or double)
@@ -100,6 +108,9 @@ hipError_t launch_assemble(const Problem &pb, const Layout &L, const Buffers &B,
                            hipStream_t s);
 hipError_t launch_chol_solve_nd(const Problem &pb, const Buffers &B, int k, const int32_t *ndir,
                                 hipStream_t s);
+hipError_t launch_chol_blocked(const Problem &pb, const Buffers &B, int k, const int32_t *ndir,
+                               double *Ld, int *cfail, hipStream_t s);
+int chol_blocked_panels(const Problem &pb);
 hipError_t launch_lm_update_tr(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
                                double *lm_trace, int it, int lm_iters, hipStream_t s);
 

@@ -14,53 +14,29 @@
 //   3. the tiles below are finished as L[I,j] = A'[I,j] L_jj^-T (an MFMA product).
 // The back substitution L^T delta = y runs 16 rows at a time with the stored L_jj^-1, two
 // columns per thread, the next block of L prefetched into registers.
-#include "calib_internal.h"
+#include "chol_common.h"
 
 namespace calib {
 
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-constexpr int kCholWaves = 8;
-constexpr int kColsPerThread = 2;   // back substitution: nf <= kColsPerThread * kCholThreads
-constexpr int kCholThreads = 64 * kCholWaves;
+using namespace chol;
+constexpr int kCholWaves = kWaves;
+constexpr int kCholThreads = kThreads;
 constexpr int kGroup = 3;           // panel tiles a wavefront updates together
-
-__device__ inline double readlane_d(double x, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
-  return __hiloint2double(hi, lo);
-}
-
-// The accumulator element r of lane l of v_mfma_f64_16x16x4f64 holds D[4r + l/16][l%16].
-__device__ inline d4 load_tile(const double *A, int ld, int I, int J, int lane) {
-  d4 v;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) v[r] = A[(int64_t)(I * 16 + 4 * r + (lane >> 4)) * ld + J * 16 + (lane & 15)];
-  return v;
-}
-__device__ inline void store_tile(double *A, int ld, int I, int J, int lane, d4 v) {
-#pragma unroll
-  for (int r = 0; r < 4; ++r) A[(int64_t)(I * 16 + 4 * r + (lane >> 4)) * ld + J * 16 + (lane & 15)] = v[r];
-}
-
-__device__ inline void load4(const double *p, double &a0, double &a1, double &a2, double &a3) {
-  const double2 x = reinterpret_cast<const double2 *>(p)[0];
-  const double2 y = reinterpret_cast<const double2 *>(p)[1];
-  a0 = x.x; a1 = x.y; a2 = y.x; a3 = y.y;
-}
 
 __global__ __launch_bounds__(kCholThreads) void k_chol_solve(Problem pb, Buffers B, int k,
                                                              const int32_t *ndir) {
   __shared__ double part[kCholWaves][256];
   __shared__ double diag[256];
   __shared__ double inv[256];
+  __shared__ double xch[32];
   __shared__ double tb[16];
   __shared__ double xb[16];
   __shared__ double red[kCholWaves];
   __shared__ int fail;
   const int f = blockIdx.x;
-  if (k >= ndir[f]) return;
+  if (k >= ndir[f] || B.lm[f].done) return;
   const int nf = pb.nf, npad = pb.npad, nct = nf >> 4, nrt = npad >> 4;
   double *A = B.H + (int64_t)f * npad * nf;
   double *Li = B.Linv + (int64_t)f * nct * 256;
@@ -187,50 +163,10 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_solve(Problem pb, Buffers
       }
     }
     __syncthreads();
-    // diagonal tile: one wavefront factors it (lane i < 16 keeps row i, one reciprocal per
-    // column) and inverts it right-looking (lane c < 16 forms column c of L_jj^-1)
+    // diagonal tile: one wavefront factors and inverts it
     if (w == 0) {
-      double a[16], rinv[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) a[c] = (lane < 16 && c <= lane) ? diag[lane * 16 + c] : 0.0;
-      // straight-line (no early exit) so that the loops unroll; a non-positive pivot only
-      // marks the factorisation as failed
-      bool ok = true;
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        const double d = readlane_d(a[c], c);
-        ok = ok && (d > 0.0) && isfinite(d);
-        const double lc = sqrt(fmax(d, 1e-300));
-        const double rl = 1.0 / lc;
-        rinv[c] = rl;
-        const double lv = (lane == c) ? lc : (lane > c ? a[c] * rl : 0.0);
-        a[c] = lv;
-#pragma unroll
-        for (int c2 = c + 1; c2 < 16; ++c2) {
-          const double l2 = readlane_d(lv, c2);
-          a[c2] = (lane >= c2) ? a[c2] - lv * l2 : a[c2];
-        }
-      }
-      if (ok) {
-        double x[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) x[i] = (i == lane) ? 1.0 : 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          x[q] *= rinv[q];
-#pragma unroll
-          for (int i = q + 1; i < 16; ++i) x[i] -= readlane_d(a[q], i) * x[q];
-        }
-        if (lane < 16) {
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            inv[i * 16 + lane] = x[i];
-            Li[j * 256 + i * 16 + lane] = x[i];
-          }
-        }
-      } else if (lane == 0) {
-        fail = 1;
-      }
+      const bool ok = factor16(diag, 16, inv, xch, Li + j * 256, lane);
+      if (!ok && lane == 0) fail = 1;
     }
     __syncthreads();
     if (fail) break;
@@ -258,84 +194,7 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_solve(Problem pb, Buffers
     if (tid == 0) st->chol_ok = 0;
     return;
   }
-  // back substitution L^T x = y; thread tid owns columns tid + u * kCholThreads
-  double t[kColsPerThread], lc[kColsPerThread][16], ln[kColsPerThread][16];
-#pragma unroll
-  for (int u = 0; u < kColsPerThread; ++u) {
-    const int c = tid + u * kCholThreads;
-    t[u] = (c < nf) ? A[(int64_t)nf * nf + c] : 0.0;
-    const int j0 = nf - 16;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) ln[u][r] = (c < j0) ? A[(int64_t)(j0 + r) * nf + c] : 0.0;
-  }
-  double lin[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) lin[i] = (tid < 16) ? Li[(nct - 1) * 256 + i * 16 + tid] : 0.0;
-  for (int jb = nct - 1; jb >= 0; --jb) {
-    const int j0 = jb * 16;
-#pragma unroll
-    for (int u = 0; u < kColsPerThread; ++u) {
-      const int c = tid + u * kCholThreads;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) lc[u][r] = ln[u][r];
-      if (jb > 0) {
-        const int j1 = j0 - 16;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) ln[u][r] = (c < j1) ? A[(int64_t)(j1 + r) * nf + c] : 0.0;
-      }
-      if (c >= j0 && c < j0 + 16) tb[c - j0] = t[u];
-    }
-    __syncthreads();
-    if (tid < 16) {
-      // x = L_jj^-T t_blk: x_r = sum_i (L_jj^-1)[i][r] t_i; the next block's column prefetched
-      double lic[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) lic[i] = lin[i];
-      if (jb > 0) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) lin[i] = Li[(jb - 1) * 256 + i * 16 + tid];
-      }
-      double x = 0.0;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) x += lic[i] * tb[i];
-      xb[tid] = x;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kColsPerThread; ++u) {
-      const int c = tid + u * kCholThreads;
-      if (c < j0) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) t[u] -= lc[u][r] * xb[r];
-      } else if (c < j0 + 16) {
-        t[u] = xb[c - j0];
-      }
-    }
-  }
-  // delta, predicted decrease ell = delta.(lambda delta - G)/2, trial point
-  const double lam = st->lambda;
-  const int n8 = 8 * pb.N;
-  double ell = 0.0;
-#pragma unroll
-  for (int u = 0; u < kColsPerThread; ++u) {
-    const int c = tid + u * kCholThreads;
-    if (c < n8) {
-      const double g = B.G[(int64_t)f * nf + c];
-      ell += t[u] * (lam * t[u] - g);
-      B.delta[(int64_t)f * nf + c] = t[u];
-      B.Jtrial[(int64_t)f * n8 + c] = B.J[((int64_t)f * pb.K + k) * n8 + c] + t[u];
-    }
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) ell += __shfl_xor(ell, o, 64);
-  if (lane == 0) red[w] = ell;
-  __syncthreads();
-  if (tid == 0) {
-    double sum = 0.0;
-    for (int i = 0; i < kCholWaves; ++i) sum += red[i];
-    st->ell = 0.5 * sum;
-    st->chol_ok = 1;
-  }
+  backsub_tail(pb, B, f, k, A, Li, tb, xb, red);
 }
 
 }  // namespace

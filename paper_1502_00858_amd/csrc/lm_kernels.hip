@@ -126,6 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffe
     st->active = 1;
     st->chol_ok = 0;
     st->ell = 0.0;
+    st->done = 0;
   }
 }
 
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Problem pb, Layout L, Buffe
   __shared__ double red[12][kBlock / 64];
   __shared__ double qg[12];
   const int f = blockIdx.x, p = blockIdx.y;
-  if (k >= L.ndir[f]) return;
+  if (k >= L.ndir[f] || B.lm[f].done) return;
   const int N = pb.N, nf = pb.nf, npad = pb.npad;
   double *A = B.H + (int64_t)f * npad * nf;
   const double lam = B.lm[f].lambda;
@@ -251,6 +252,16 @@ __global__ __launch_bounds__(kBlock) void k_lm_update(Problem pb, Layout L, Buff
   const int f = blockIdx.x;
   if (k >= L.ndir[f]) return;
   LmState *st = B.lm + f;
+  if (st->done) {
+    // the run has stopped: the trace repeats the final objective and damping
+    if (threadIdx.x == 0 && lm_trace) {
+      double *tr = lm_trace + 3 * ((int64_t)(f * pb.K + k) * lm_iters + it);
+      tr[0] = st->F;
+      tr[1] = st->lambda;
+      tr[2] = 0;
+    }
+    return;
+  }
   int ok = st->chol_ok;
   double Fn = 0.0;
   if (ok) Fn = objective(pb, L, B, f, k, unreg, B.Jtrial + (int64_t)f * pb.N * 8, red);
@@ -258,6 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_lm_update(Problem pb, Layout L, Buff
     int a = 0;
     if (ok) {
       const double ell = st->ell, F = st->F;
+      if (pb.lm_tol > 0.0 && ell <= pb.lm_tol * F) st->done = 1;
       if (ell > 0.0 && F - Fn > 0.0) {
         const double gain = (F - Fn) / ell;
         const double t = 2.0 * gain - 1.0;

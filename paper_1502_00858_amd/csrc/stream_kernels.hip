@@ -105,7 +105,7 @@ __device__ inline void stream_tile(const Problem &pb, const Layout &L, const Buf
                                    double *red) {
   const int f = L.tile_f[tile];
   const int Kf = L.ndir[f];
-  if (MODE == SM_TRIAL && (k >= Kf || !B.lm[f].chol_ok)) return;   // uniform per workgroup
+  if (MODE == SM_TRIAL && (k >= Kf || !B.lm[f].chol_ok || B.lm[f].done)) return;   // uniform
   if (MODE == SM_COMMIT && k >= Kf) return;
 
   const int nb = L.nb[f], spb = L.spb[f];

@@ -173,14 +173,18 @@ def test_run_to_run_bitwise(cal, synth_mod):
     np.testing.assert_array_equal(a.get(cal.FIELD_J).cpu().numpy(), b.get(cal.FIELD_J).cpu().numpy())
 
 
-def test_normal_equation_solve_fp64(cal, oracle_mod, synth_mod):
+@pytest.mark.parametrize("solver", [1, 2])
+def test_normal_equation_solve_fp64(cal, oracle_mod, synth_mod, solver):
     """One LM iteration from a random state: the GPU step solves (H_GN + (rho+lambda) I) delta = -G
-    with the oracle's Gauss-Newton matrix (both odd and even station counts: padded factor)."""
-    for N in (6, 9):
+    with the oracle's Gauss-Newton matrix, for both Cholesky solvers (one workgroup per matrix;
+    64-column panels over many workgroups) and station counts that give padded factors and
+    partial last panels (8N = 48, 72, 136, 264 columns)."""
+    for N in (6, 9, 17, 33):
+        print(f"solver {solver} N {N}", flush=True)
         cfg = tiny_cfg(synth_mod, N=N, P=2, Q=1, K=1, T=3, n_chan=2, rho=3.0, lm_iters=1)
         d = synth_mod.generate(cfg)
         J = rand_jones(np.random.default_rng(14), cfg.P, 1, N)
-        c = _ctx(cal, d, 0, jones0=J, lm_iters=1, options=0)
+        c = _ctx(cal, d, 0, jones0=J, lm_iters=1, options=0, solver=solver)
         c.local_step(1)
         step = c.get(cal.FIELD_LM_STEP).cpu().numpy()
         pb = oracle_mod.Problem(d, lm_iters=1)
@@ -224,3 +228,38 @@ def test_tile_shapes_and_persistent_grid(cal, synth_mod):
     for g in (8, 16, 32, 64):
         tr = _ctx(cal, d, 1, tile_group=g).solve(3)
         np.testing.assert_allclose(tr, ref, rtol=1e-6)
+
+
+def test_lm_stopping_rule_fp64(cal, oracle_mod, synth_mod):
+    """With the LM stopping rule on, the GPU stops each (subband, direction) at the same iteration
+    as the oracle and the whole C-ADMM trajectory still agrees."""
+    cfg = tiny_cfg(synth_mod, N=7, P=4, Q=2, K=2, T=3, n_chan=2, lm_iters=10)
+    d = synth_mod.generate(cfg)
+    J0 = synth_mod.identity_jones(cfg.P, cfg.K, cfg.N)
+    z = np.zeros_like(J0)
+    c = _ctx(cal, d, 0, lm_iters=10, lm_tol=1e-7)
+    c.local_step(0)
+    trg = c.get(cal.FIELD_LM_TRACE).cpu().numpy()
+    pb = oracle_mod.Problem(d, lm_iters=10, lm_tol=1e-7)
+    _, tro = pb.local_step(J0, z, z, trace=True)
+    np.testing.assert_array_equal(trg[..., 2], tro[:, 0, :, :, 2])
+    np.testing.assert_allclose(trg[..., 0], tro[:, 0, :, :, 0], rtol=1e-10)
+    assert np.sum(trg[..., 2] == 0) > 0
+    c2 = _ctx(cal, d, 0, lm_iters=10, lm_tol=1e-7)
+    tr = c2.solve(5)
+    ref = pb.admm_solve(J0, 5)["trace"]
+    np.testing.assert_allclose(tr[:, 0], ref[:, 0], rtol=1e-10)
+    np.testing.assert_allclose(tr[:, 1], ref[:, 1], rtol=1e-10)
+
+
+def test_solvers_agree_on_a_local_step(cal, synth_mod):
+    """The two Cholesky solvers sum in different orders: whole local steps agree to rounding."""
+    cfg = tiny_cfg(synth_mod, N=20, P=5, Q=2, K=3, T=3, n_chan=2, lm_iters=6, flag_frac_max=0.2)
+    d = synth_mod.generate(cfg)
+    tr = []
+    for solver in (1, 2):
+        c = _ctx(cal, d, 0, lm_iters=6, solver=solver)
+        c.local_step(0)
+        tr.append(c.get(cal.FIELD_LM_TRACE).cpu().numpy())
+    np.testing.assert_array_equal(tr[0][..., 2], tr[1][..., 2])
+    np.testing.assert_allclose(tr[0][..., 0], tr[1][..., 0], rtol=1e-11)

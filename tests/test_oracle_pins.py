@@ -332,3 +332,34 @@ def test_admm_trends_with_rho(oracle_mod, synth_mod):
         res[rho] = pb.admm_solve(J0, 15)["trace"]
     assert res[50.0][-1, 2] < res[50.0][1, 2]
     assert res[50.0][-1, 2] < res[0.5][-1, 2]
+
+
+def test_lm_stopping_rule_truncates_the_run(oracle_mod, synth_mod):
+    # the stopping rule only ends the run: the trace up to the stop equals the fixed-iteration
+    # trace, the rows after it repeat (F, lambda) with no accepted step, and a tolerance no step
+    # can meet (the predicted decrease of a step is positive) changes nothing
+    cfg = tiny_cfg(synth_mod, N=6, P=3, K=2, T=3, n_chan=2, lm_iters=12)
+    d = synth_mod.generate(cfg)
+    J0 = synth_mod.identity_jones(cfg.P, cfg.K, cfg.N)
+    z = np.zeros_like(J0)
+    _, t0 = oracle_mod.Problem(d, lm_iters=12).local_step(J0, z, z, trace=True)
+    _, tn = oracle_mod.Problem(d, lm_iters=12, lm_tol=1e-300).local_step(J0, z, z, trace=True)
+    np.testing.assert_array_equal(tn, t0)
+    _, ts = oracle_mod.Problem(d, lm_iters=12, lm_tol=1e-7).local_step(J0, z, z, trace=True)
+    # direction 0 of every subband starts from the same state in both runs (later directions
+    # start from whatever the earlier directions' runs left)
+    stopped = 0
+    for f in range(cfg.P):
+        for k in (0,):
+            a, b = t0[f, 0, k], ts[f, 0, k]
+            # first row where the runs differ: the stop happened in the row before it
+            diff = np.nonzero(np.any(a != b, axis=1))[0]
+            if len(diff) == 0:
+                continue
+            s = diff[0]
+            assert s >= 1
+            np.testing.assert_array_equal(b[:s], a[:s])
+            assert np.all(b[s:, 0] == b[s - 1, 0]) and np.all(b[s:, 1] == b[s - 1, 1])
+            assert np.all(b[s:, 2] == 0)
+            stopped += 1
+    assert stopped >= 2
