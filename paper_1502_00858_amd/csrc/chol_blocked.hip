@@ -3,21 +3,25 @@
 // on 256 compute units).  Same augmented matrix as chol_kernel.hip (row nf holds -G^T, so the
 // factorisation also performs the forward substitution) and the same back substitution.
 //
-// Right-looking over 64-column panels p (tile columns 4p .. 4p+wp-1), two launches per panel:
-//   panel  (grid: subband x 64-row chunk below the panel's diagonal block)
-//          every workgroup loads the panel's diagonal block into LDS and factors it (left-looking
+// Right-looking over 64-column panels p (tile columns 4p .. 4p+wp-1), one launch per panel
+// (grid: subband x (64-row chunks below the panel's diagonal block + 64x64 blocks of the trailing
+// lower triangle)):
+//   panel workgroups load the panel's diagonal block and their chunk of rows into LDS, apply the
+//          pending rank-64 update of the previous panel there, and factor the block (left-looking
 //          over its 16x16 tiles: diagonal tile factor + inverse on one wavefront, the tiles below
-//          as MFMA products with the inverse, then the rank-16 update of the block's later
-//          tile columns) - redundantly, so that no workgroup waits for another - and applies the
-//          same steps to its own chunk of rows: L[I, panel] = A[I, panel] L_pp^-T.  The
-//          workgroup of chunk 0 also keeps the diagonal tiles' inverses (for the back
-//          substitution) and the block's strictly-lower tiles (in a side buffer: the other
-//          workgroups are still reading the block from the matrix).
-//   trail  (grid: subband x 64x64 block of the trailing lower triangle, right-hand-side row
-//          included) A[I,K] -= sum_{t in panel} L[I,t] L[K,t]^T on v_mfma_f64_16x16x4f64.
-// The launch boundaries order the panels; nothing spins.  A non-positive pivot sets a per-subband
-// flag that makes the later launches skip the subband and the back substitution report
-// chol_ok = 0 (and clear the flag).
+//          as MFMA products with the inverse, then the rank-16 update of the block's later tile
+//          columns) - redundantly, so that no workgroup waits for another - applying the same
+//          steps to their own rows: L[I, panel] = A[I, panel] L_pp^-T.  The workgroup of chunk 0
+//          also keeps the diagonal tiles' inverses (for the back substitution) and the block's
+//          strictly-lower tiles (in a side buffer: the other workgroups are still reading the
+//          block from the matrix);
+//   trailing workgroups apply the previous panel's update to the lower triangle right of the
+//          panel (right-hand-side row included): A[I,K] -= sum_t L[I,t] L[K,t]^T on
+//          v_mfma_f64_16x16x4f64.
+// Both roles read only the previous panel's L and write disjoint regions; launch boundaries order
+// the panels and nothing spins.  A 1024-thread back substitution follows.  A non-positive pivot
+// sets a per-subband flag that makes the later launches skip the subband and the back
+// substitution report chol_ok = 0 (and clear the flag).
 #include "chol_common.h"
 
 namespace calib {
@@ -57,27 +61,119 @@ __device__ inline void tile_update_lds(double *T, const double *X, const double 
   for (int r = 0; r < 4; ++r) T[(4 * r + lq) * kLd + li] = acc[r];
 }
 
+// Trailing update of one 4x4-tile block (rb, kb) of the lower triangle that starts at tile rs:
+// A[I,K] -= sum_{t in panel src} L[I,t] L[K,t]^T; each wavefront owns 2x2 tiles and has all
+// operands of the panel in flight at once.
+__device__ __attribute__((always_inline)) inline void trail_block(double *A, int nf, int nct, int nrt, const PanelGeom &src, int rs,
+                                   int rb, int kb, int w, int lane) {
+  const int li = lane & 15, lq = lane >> 4;
+  const int i0 = rs + kPanelTiles * rb + 2 * (w >> 1);
+  const int k0 = rs + kPanelTiles * kb + 2 * (w & 1);
+  bool valid[2][2];
+  d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int I = i0 + a, K = k0 + b;
+      valid[a][b] = I < nrt && K < nct && K <= I;
+      acc[a][b] = valid[a][b] ? load_tile(A, nf, I, K, lane) : d4{0.0, 0.0, 0.0, 0.0};
+    }
+  const bool rowok[2] = {i0 < nrt, i0 + 1 < nrt};
+  const bool colok[2] = {k0 < nct, k0 + 1 < nct};
+  double x[kPanelTiles][2][4], y[kPanelTiles][2][4];
+#pragma unroll
+  for (int t = 0; t < kPanelTiles; ++t) {
+    const int tc = (src.c0 + t) * 16 + 4 * lq;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      if (t < src.wp && rowok[a]) load4(A + (int64_t)((i0 + a) * 16 + li) * nf + tc, x[t][a][0], x[t][a][1], x[t][a][2], x[t][a][3]);
+      else x[t][a][0] = x[t][a][1] = x[t][a][2] = x[t][a][3] = 0.0;
+      if (t < src.wp && colok[a]) load4(A + (int64_t)((k0 + a) * 16 + li) * nf + tc, y[t][a][0], y[t][a][1], y[t][a][2], y[t][a][3]);
+      else y[t][a][0] = y[t][a][1] = y[t][a][2] = y[t][a][3] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kPanelTiles; ++t) {
+    if (t < src.wp) {
+#pragma unroll
+      for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[t][a][qq], y[t][b][qq], acc[a][b], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+      if (valid[a][b]) store_tile(A, nf, i0 + a, k0 + b, lane, acc[a][b]);
+}
+
+// T (16x16 tile in LDS, stride kLd) <- T - sum_{t < wsrc} X_t Y_t^T with X_t, Y_t the 16x16 tiles
+// at column offset 16t of the LDS row blocks X and Y
+__device__ __attribute__((always_inline)) inline void tile_update_lds_panel(double *T, const double *X, const double *Y, int wsrc,
+                                             int li, int lq) {
+  d4 acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = T[(4 * r + lq) * kLd + li];
+#pragma unroll
+  for (int t = 0; t < kPanelTiles; ++t) {
+    if (t < wsrc) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-X[li * kLd + 16 * t + 4 * lq + q],
+                                                   Y[li * kLd + 16 * t + 4 * lq + q], acc, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) T[(4 * r + lq) * kLd + li] = acc[r];
+}
+
+// One step p of the blocked factorisation (grid: subband x (nchunk panel workgroups + trailing
+// workgroups)).  Panel workgroups (blockIdx.y < nchunk, dispatched first) apply the pending
+// rank-64 update of panel p-1 to their LDS copies of panel p's diagonal block and of their chunk
+// of rows, then factor panel p.  Trailing workgroups apply the same update of panel p-1 to the
+// lower triangle right of panel p.  Both roles only read panel p-1's L and write disjoint regions,
+// so one launch per panel suffices and nothing waits across workgroups.
 __global__ __launch_bounds__(kBThreads) void k_chol_panel(Problem pb, Buffers B, int k,
                                                           const int32_t *ndir, int p, double *Ld,
                                                           int *cfail) {
   __shared__ double Dl[kPB * kLd];    // the panel's diagonal block
   __shared__ double Xl[kPB * kLd];    // this workgroup's rows of the panel
+  __shared__ double Pd[kPB * kLd];    // L of panel p-1 at the diagonal block's rows
+  __shared__ double Px[kPB * kLd];    // L of panel p-1 at this workgroup's rows
   __shared__ double inv[256];
   __shared__ double xch[32];
   __shared__ int bad;
-  const int f = blockIdx.x, q = blockIdx.y;
+  const int f = blockIdx.x;
   if (k >= ndir[f] || B.lm[f].done || cfail[f]) return;
   const int nf = pb.nf, nct = nf >> 4, nrt = pb.npad >> 4;
   const PanelGeom g = panel_geom(p, nct);
-  const int r0 = g.c1 + kPanelTiles * q;            // first row tile of this chunk
-  const int nr = min(kPanelTiles, nrt - r0);
-  const int wcol = 16 * g.wp;
   double *A = B.H + (int64_t)f * pb.npad * nf;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 15, lq = lane >> 4;
+  const PanelGeom gs = panel_geom(p > 0 ? p - 1 : 0, nct);   // source of the pending update
+  const int nchunk = (nrt - g.c1 + kPanelTiles - 1) / kPanelTiles;
+  if ((int)blockIdx.y >= nchunk) {
+    // trailing role: the region right of panel p, rows and columns from tile g.c1
+    const int bb = blockIdx.y - nchunk;
+    const int nkb = (nct - g.c1 + kPanelTiles - 1) / kPanelTiles;
+    const int rb = bb / nkb, kb = bb % nkb;
+    if (kb > rb) return;
+    trail_block(A, nf, nct, nrt, gs, g.c1, rb, kb, w, lane);
+    return;
+  }
+  const int q = blockIdx.y;
+  const int r0 = g.c1 + kPanelTiles * q;            // first row tile of this chunk
+  const int nr = min(kPanelTiles, nrt - r0);
+  const int wcol = 16 * g.wp, wsrc = (p > 0) ? 16 * gs.wp : 0;
 
-  // fixed-count loops over the 64x64 footprint: every load is issued before the first LDS store
+  // fixed-count loops over the 64x64 footprints: each block pair's loads are all issued before
+  // its first LDS store
   {
     double dv[kPB * kPB / kBThreads], xv[kPB * kPB / kBThreads];
 #pragma unroll
@@ -94,9 +190,38 @@ __global__ __launch_bounds__(kBThreads) void k_chol_panel(Problem pb, Buffers B,
       Xl[row * kLd + col] = xv[it];
     }
   }
+  if (p > 0) {
+    double dv[kPB * kPB / kBThreads], xv[kPB * kPB / kBThreads];
+#pragma unroll
+    for (int it = 0; it < kPB * kPB / kBThreads; ++it) {
+      const int e = tid + it * kBThreads, row = e >> 6, col = e & 63;
+      dv[it] = (row < wcol && col < wsrc) ? A[(int64_t)(g.c0 * 16 + row) * nf + gs.c0 * 16 + col] : 0.0;
+      xv[it] = (row < 16 * nr && col < wsrc) ? A[(int64_t)(r0 * 16 + row) * nf + gs.c0 * 16 + col] : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < kPB * kPB / kBThreads; ++it) {
+      const int e = tid + it * kBThreads, row = e >> 6, col = e & 63;
+      Pd[row * kLd + col] = dv[it];
+      Px[row * kLd + col] = xv[it];
+    }
+  }
   if (tid == 0) bad = 0;
   __syncthreads();
-
+  if (p > 0) {
+    // pending rank-64 update of panel p-1: the diagonal block's lower tiles, then the chunk's
+    int cnt = 0;
+    for (int s2 = 0; s2 < g.wp; ++s2)
+      for (int t2 = 0; t2 <= s2; ++t2, ++cnt)
+        if ((cnt & 3) == w)
+          tile_update_lds_panel(Dl + s2 * 16 * kLd + t2 * 16, Pd + s2 * 16 * kLd, Pd + t2 * 16 * kLd,
+                                gs.wp, li, lq);
+    for (int r = 0; r < nr; ++r)
+      for (int t2 = 0; t2 < g.wp; ++t2, ++cnt)
+        if ((cnt & 3) == w)
+          tile_update_lds_panel(Xl + r * 16 * kLd + t2 * 16, Px + r * 16 * kLd, Pd + t2 * 16 * kLd,
+                                gs.wp, li, lq);
+    __syncthreads();
+  }
   for (int t = 0; t < g.wp; ++t) {
     if (w == 0) {
       double *Li = (q == 0) ? B.Linv + ((int64_t)f * nct + g.c0 + t) * 256 : nullptr;
@@ -159,65 +284,6 @@ __global__ __launch_bounds__(kBThreads) void k_chol_panel(Problem pb, Buffers B,
   }
 }
 
-__global__ __launch_bounds__(kBThreads) void k_chol_trail(Problem pb, Buffers B, int k,
-                                                          const int32_t *ndir, int p, const int *cfail) {
-  const int f = blockIdx.x;
-  if (k >= ndir[f] || B.lm[f].done || cfail[f]) return;
-  const int nf = pb.nf, nct = nf >> 4, nrt = pb.npad >> 4;
-  const PanelGeom g = panel_geom(p, nct);
-  const int nkb = (nct - g.c1 + kPanelTiles - 1) / kPanelTiles;
-  const int rb = blockIdx.y / nkb, kb = blockIdx.y % nkb;
-  if (kb > rb) return;
-  double *A = B.H + (int64_t)f * pb.npad * nf;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int li = lane & 15, lq = lane >> 4;
-  // this wavefront's 2x2 tiles of the 4x4-tile block
-  const int i0 = g.c1 + kPanelTiles * rb + 2 * (w >> 1);
-  const int k0 = g.c1 + kPanelTiles * kb + 2 * (w & 1);
-  bool valid[2][2];
-  d4 acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int I = i0 + a, K = k0 + b;
-      valid[a][b] = I < nrt && K < nct && K <= I;
-      acc[a][b] = valid[a][b] ? load_tile(A, nf, I, K, lane) : d4{0.0, 0.0, 0.0, 0.0};
-    }
-  const bool rowok[2] = {i0 < nrt, i0 + 1 < nrt};
-  const bool colok[2] = {k0 < nct, k0 + 1 < nct};
-  // all operands of the panel in flight at once (one memory latency instead of one per tile)
-  double x[kPanelTiles][2][4], y[kPanelTiles][2][4];
-#pragma unroll
-  for (int t = 0; t < kPanelTiles; ++t) {
-    const int tc = (g.c0 + t) * 16 + 4 * lq;
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      if (t < g.wp && rowok[a]) load4(A + (int64_t)((i0 + a) * 16 + li) * nf + tc, x[t][a][0], x[t][a][1], x[t][a][2], x[t][a][3]);
-      else x[t][a][0] = x[t][a][1] = x[t][a][2] = x[t][a][3] = 0.0;
-      if (t < g.wp && colok[a]) load4(A + (int64_t)((k0 + a) * 16 + li) * nf + tc, y[t][a][0], y[t][a][1], y[t][a][2], y[t][a][3]);
-      else y[t][a][0] = y[t][a][1] = y[t][a][2] = y[t][a][3] = 0.0;
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < kPanelTiles; ++t) {
-    if (t < g.wp) {
-#pragma unroll
-      for (int qq = 0; qq < 4; ++qq)
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[t][a][qq], y[t][b][qq], acc[a][b], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-      if (valid[a][b]) store_tile(A, nf, i0 + a, k0 + b, lane, acc[a][b]);
-}
 
 // Back substitution L^T delta = y with one thread per column (nf <= 1024): per 16-row block,
 // from the last, x_J = (L_JJ^-1)^T t_J on 16 threads, then t -= L_J^T x_J on every column left
@@ -363,18 +429,13 @@ hipError_t launch_chol_blocked(const Problem &pb, const Buffers &B, int k, const
   for (int p = 0; p < np; ++p) {
     const int c1 = min(kPanelTiles * (p + 1), nct);
     const int nchunk = (nrt - c1 + kPanelTiles - 1) / kPanelTiles;
-    hipLaunchKernelGGL(k_chol_panel, dim3(pb.P, nchunk), dim3(kBThreads), 0, s, pb, B, k, ndir, p,
-                       Ld, cfail);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     const int nrb = (nrt - c1 + kPanelTiles - 1) / kPanelTiles;
     const int nkb = (nct - c1 + kPanelTiles - 1) / kPanelTiles;
-    if (nkb > 0) {
-      hipLaunchKernelGGL(k_chol_trail, dim3(pb.P, nrb * nkb), dim3(kBThreads), 0, s, pb, B, k,
-                         ndir, p, cfail);
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
+    const int ntrail = (p > 0) ? nrb * nkb : 0;
+    hipLaunchKernelGGL(k_chol_panel, dim3(pb.P, nchunk + ntrail), dim3(kBThreads), 0, s, pb, B, k,
+                       ndir, p, Ld, cfail);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_chol_backsub, dim3(pb.P), dim3(kBsThreads), 0, s, pb, B, k, ndir, Ld, cfail);
   return hipGetLastError();
