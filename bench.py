@@ -41,23 +41,28 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 
-# HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a 256 MiB copy) of the kernels as they
-# were when the counters were taken (profiles/hbm_counters_c2.md); reported only while the
-# kernel source is unchanged (sha256 of the file).
+# HBM bytes per launch of a kernel class (FETCH_SIZE + WRITE_SIZE, scaled by a 256 MiB copy) as
+# measured for a workload (profiles/hbm_counters_c2.md); reported only while the kernel sources
+# are unchanged (sha256 over the listed files) and for that workload and solver.
 MEASURED_TRAFFIC = {
-    "chol_solve": ("paper_1502_00858_amd/csrc/chol_kernel.hip",
-                   "594706b86df67b8a700c59d4388c0a03a8e5dc83afc85f4c158c8cca38594b96",
-                   (40.39 + 36.83) * 1e6),
+    ("chol_solve", "c2", "blocked"): (
+        ("paper_1502_00858_amd/csrc/chol_blocked.hip", "paper_1502_00858_amd/csrc/chol_common.h"),
+        "fd342625a7b1e884633703c13a70e2a586d7e2d5528fb929c61115ecc7633255",
+        (153.56 + 87.81) * 1e6),
 }
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, config, solver):
     import hashlib
-    if kernel not in MEASURED_TRAFFIC:
+    key = (kernel, config, solver)
+    if key not in MEASURED_TRAFFIC:
         return None
-    path, sha, nbytes = MEASURED_TRAFFIC[kernel]
-    with open(os.path.join(ROOT, path), "rb") as fh:
-        return nbytes if hashlib.sha256(fh.read()).hexdigest() == sha else None
+    paths, sha, nbytes = MEASURED_TRAFFIC[key]
+    h = hashlib.sha256()
+    for path in paths:
+        with open(os.path.join(ROOT, path), "rb") as fh:
+            h.update(fh.read())
+    return nbytes if h.hexdigest() == sha else None
 
 
 def kernel_work(name, data, elt):
@@ -313,11 +318,14 @@ def main():
         launches, ms = kt[dom]
         avg_s = ms / launches / 1e3
         bound, work, unit = kernel_work(dom, data, elt)
+        solver_name = ("blocked" if (args.solver == 2 or (args.solver == 0 and P < 128))
+                       else "single")
         if bound is not None:
             achieved = work / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
             peak = FP64_PEAK_TFS if unit == "TFLOP/s" else HBM_PEAK_GBS
             out["roofline"] = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak,
-                               "unit": unit, "frac": achieved / peak, "traffic": measured_traffic(dom),
+                               "unit": unit, "frac": achieved / peak,
+                               "traffic": measured_traffic(dom, args.config, solver_name),
                                "avg_launch_us": avg_s * 1e6, "share_of_step": ms / total}
         # the streaming pass at the LM trial point: achieved HBM bandwidth
         tl, tms = kt["trial"]
