@@ -27,6 +27,7 @@ struct calib_mlp {
   float *C = nullptr, *Y = nullptr, *dA = nullptr;
   unsigned short *dZ0 = nullptr, *dZ1 = nullptr;
   double *part = nullptr;
+  double *cpart = nullptr;   // column-sum partials
   std::string err;
 
   template <typename T>
@@ -130,7 +131,7 @@ calib_status calib_mlp_create(int32_t n_layers, const int32_t *dims, const float
   const size_t big = (size_t)max_rows * m->maxd;
   if (m->alloc(&m->C, big) || m->alloc(&m->Y, (size_t)max_rows * m->dims[m->L]) ||
       m->alloc(&m->dA, big) || m->alloc(&m->dZ0, big) || m->alloc(&m->dZ1, big) ||
-      m->alloc(&m->part, kLossParts))
+      m->alloc(&m->part, kLossParts) || m->alloc(&m->cpart, (size_t)mlp_colsum_scratch(m->maxd)))
     return oom();
   if (hipStreamSynchronize(m->stream) != hipSuccess) {
     calib_mlp_destroy(m);
@@ -161,7 +162,7 @@ calib_status calib_mlp_train_step(calib_mlp *m, const float *x, const float *tar
     const int in = m->dims[l], out = m->dims[l + 1];
     // dW_l = X_l^T dZ_l, db_l = column sums of dZ_l
     MCHK(m, mlp_gemm(m->Xb[l], true, dz, false, m->gW[l], in, out, (int)rows, s));
-    MCHK(m, mlp_colsum(dz, m->gb[l], rows, out, s));
+    MCHK(m, mlp_colsum(dz, m->gb[l], m->cpart, rows, out, s));
     if (l > 0) {
       // dX_l = dZ_l W_l^T, then through the GELU of layer l-1
       MCHK(m, mlp_gemm(dz, false, m->Wb[l], true, m->dA, (int)rows, in, out, s));

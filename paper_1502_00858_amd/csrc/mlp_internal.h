@@ -13,7 +13,9 @@ hipError_t mlp_bias_act(const float *C, const float *b, float *Z, unsigned short
 hipError_t mlp_to_bf16(const float *x, unsigned short *y, int64_t n, hipStream_t s);
 hipError_t mlp_mse(const float *Y, const float *T, unsigned short *dYb, double *part, int nparts,
                    int64_t total, float *loss, hipStream_t s);
-hipError_t mlp_colsum(const unsigned short *dZb, float *gb, int64_t rows, int n, hipStream_t s);
+int mlp_colsum_scratch(int n);   // doubles of partial sums mlp_colsum needs for n columns
+hipError_t mlp_colsum(const unsigned short *dZb, float *gb, double *part, int64_t rows, int n,
+                      hipStream_t s);
 hipError_t mlp_gelu_back(const float *dA, const float *Z, unsigned short *dZb, int64_t n, hipStream_t s);
 hipError_t mlp_adam(float *p, const float *g, float *m, float *v, unsigned short *pb, int64_t n,
                     float lr, int step, hipStream_t s);

@@ -40,14 +40,17 @@ __global__ __launch_bounds__(kBlock) void k_gemm_bf16(const unsigned short *A, c
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < K; k0 += kTK) {
+    // consecutive threads walk the operand's contiguous dimension (coalesced loads)
     for (int idx = tid; idx < kTM * kTK; idx += kBlock) {
-      const int mm = idx / kTK, kk = idx % kTK, gm = m0 + mm, gk = k0 + kk;
+      const int mm = TA ? idx % kTM : idx / kTK, kk = TA ? idx / kTM : idx % kTK;
+      const int gm = m0 + mm, gk = k0 + kk;
       unsigned short v = 0;
       if (gm < M && gk < K) v = TA ? A[(int64_t)gk * M + gm] : A[(int64_t)gm * K + gk];
       As[mm][kk] = v;
     }
     for (int idx = tid; idx < kTN * kTK; idx += kBlock) {
-      const int nn = idx / kTK, kk = idx % kTK, gn = n0 + nn, gk = k0 + kk;
+      const int nn = TB ? idx / kTK : idx % kTN, kk = TB ? idx % kTK : idx / kTN;
+      const int gn = n0 + nn, gk = k0 + kk;
       unsigned short v = 0;
       if (gn < N && gk < K) v = TB ? B[(int64_t)gn * K + gk] : B[(int64_t)gk * N + gn];
       Bs[nn][kk] = v;
@@ -127,12 +130,29 @@ __global__ void k_loss_final(const double *part, int nparts, int64_t total, floa
   loss[0] = (float)(s / (double)total);
 }
 
-// gb[j] = sum over rows of dZ[r][j] (dZ stored BF16), fixed order per column
-__global__ void k_colsum(const unsigned short *dZb, float *gb, int64_t rows, int n) {
+// gb[j] = sum over rows of dZ[r][j] (dZ stored BF16) in two fixed-order stages: workgroup
+// (x, y) sums columns 64x..64x+63 over the rows r = 4y + g + 4*kColsumGroups*i (g: wavefront),
+// the four wavefronts combine in LDS, then k_colsum_final adds the kColsumGroups partials
+constexpr int kColsumGroups = 16;
+__global__ __launch_bounds__(kBlock) void k_colsum(const unsigned short *dZb, double *part,
+                                                   int64_t rows, int n) {
+  __shared__ double red[4][64];
+  const int j = blockIdx.x * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
+  double s = 0.0;
+  if (j < n)
+    for (int64_t r = 4 * blockIdx.y + g; r < rows; r += 4 * kColsumGroups) s += bf16_to_f(dZb[r * n + j]);
+  red[g][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (g == 0 && j < n)
+    part[(int64_t)blockIdx.y * n + j] = (red[0][threadIdx.x] + red[1][threadIdx.x]) +
+                                        (red[2][threadIdx.x] + red[3][threadIdx.x]);
+}
+
+__global__ void k_colsum_final(const double *part, float *gb, int n) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
   double s = 0.0;
-  for (int64_t r = 0; r < rows; ++r) s += bf16_to_f(dZb[r * n + j]);
+  for (int y = 0; y < kColsumGroups; ++y) s += part[(int64_t)y * n + j];
   gb[j] = (float)s;
 }
 
@@ -192,8 +212,14 @@ hipError_t mlp_mse(const float *Y, const float *T, unsigned short *dYb, double *
   return hipGetLastError();
 }
 
-hipError_t mlp_colsum(const unsigned short *dZb, float *gb, int64_t rows, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum, dim3(blocks(n, 64)), dim3(64), 0, s, dZb, gb, rows, n);
+int mlp_colsum_scratch(int n) { return kColsumGroups * n; }
+
+hipError_t mlp_colsum(const unsigned short *dZb, float *gb, double *part, int64_t rows, int n,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_colsum, dim3(blocks(n, 64), kColsumGroups), dim3(kBlock), 0, s, dZb, part, rows, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colsum_final, dim3(blocks(n, 64)), dim3(64), 0, s, part, gb, n);
   return hipGetLastError();
 }
 
