@@ -132,7 +132,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--lm-iters", type=int, default=None)
-    ap.add_argument("--lm-tol", type=float, default=1e-8,
+    ap.add_argument("--lm-tol", type=float, default=1e-7,
                     help="LM stopping rule: predicted decrease <= lm_tol * objective (0 = off)")
     ap.add_argument("--chain-iters", type=int, default=30,
                     help="ADMM iterations per interval when solving the episodes")

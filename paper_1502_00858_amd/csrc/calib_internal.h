@@ -79,7 +79,7 @@ struct Buffers {
   const double *basis;                  // [P][Q] b_l(f)
   const double *fitw;                   // [K][Q][P] least-squares operator per direction
   double *trace;                        // [iters][4]
-  double *scratch;                      // [P*K*2 + K] residual partials
+  double *scratch;                      // [P*K + K] residual partials, [2P] cost/penalty partials
   int *iter;                            // ADMM iteration whose trace row is being written
   int *chol_fail;                       // [P] blocked solver: a pivot failed in this solve
   double *chol_ld;                      // [P][panels][64*64] blocked solver: diagonal blocks' L

@@ -95,17 +95,35 @@ __global__ void k_basis_setup(int P, int Q, int K, const double *freq, double f0
 
 // data cost sum_f g_f (from the tile partials of the final residual) and the augmented
 // Lagrangian sum_f [g_f + sum_k Re tr(Y^H (J - BZ)) + rho_k/2 ||J - BZ||^2]
-__global__ __launch_bounds__(kBlock) void k_penalty_trace(Problem pb, Layout L, Buffers B) {
+// Data cost and augmented Lagrangian for the trace row: per-subband partials (one workgroup per
+// subband), then one workgroup adds them in subband order (run-to-run deterministic).
+__global__ __launch_bounds__(kBlock) void k_penalty_part(Problem pb, Layout L, Buffers B) {
   __shared__ double red[2][kBlock / 64];
+  const int f = blockIdx.x;
   double v[2] = {0.0, 0.0};
-  for (int t = threadIdx.x; t < pb.ntiles; t += kBlock) v[0] += B.cost_part[t];
-  const int64_t n = (int64_t)pb.P * pb.K * pb.N * 8;
-  for (int64_t e = threadIdx.x; e < n; e += kBlock) {
-    const int k = (int)((e / ((int64_t)pb.N * 8)) % pb.K);
-    const int f = (int)(e / ((int64_t)pb.K * pb.N * 8));
-    if (k >= L.ndir[f]) continue;
-    const double d = B.J[e] - B.BZ[e];
-    v[1] += B.Y[e] * d + 0.5 * B.rho[k] * d * d;
+  for (int t = L.tile_off[f] + threadIdx.x; t < L.tile_off[f + 1]; t += kBlock) v[0] += B.cost_part[t];
+  const int n8 = 8 * pb.N;
+  const int64_t o = (int64_t)f * pb.K * n8;
+  for (int e = threadIdx.x; e < pb.K * n8; e += kBlock) {
+    const int k = e / n8;
+    const double d = B.J[o + e] - B.BZ[o + e];
+    v[1] += B.Y[o + e] * d + 0.5 * B.rho[k] * d * d;
+  }
+  block_sum_vec<2>(v, red);
+  if (threadIdx.x == 0) {
+    double *part = B.scratch + (int64_t)pb.P * pb.K + pb.K;
+    part[2 * f] = v[0];
+    part[2 * f + 1] = v[1];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_penalty_trace(Problem pb, Buffers B) {
+  __shared__ double red[2][kBlock / 64];
+  const double *part = B.scratch + (int64_t)pb.P * pb.K + pb.K;
+  double v[2] = {0.0, 0.0};
+  for (int f = threadIdx.x; f < pb.P; f += kBlock) {
+    v[0] += part[2 * f];
+    v[1] += part[2 * f + 1];
   }
   block_sum_vec<2>(v, red);
   if (threadIdx.x == 0) {
@@ -289,7 +307,10 @@ hipError_t launch_set_iter(const Buffers &B, int iter, hipStream_t s) {
 }
 
 hipError_t launch_penalty_trace(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
-  hipLaunchKernelGGL(k_penalty_trace, dim3(1), dim3(kBlock), 0, s, pb, L, B);
+  hipLaunchKernelGGL(k_penalty_part, dim3(pb.P), dim3(kBlock), 0, s, pb, L, B);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_penalty_trace, dim3(1), dim3(kBlock), 0, s, pb, B);
   return hipGetLastError();
 }
 

@@ -97,10 +97,12 @@ __global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffe
   const double F = objective(pb, L, B, f, k, unreg, J, red);
   // largest diagonal entry of H_GN + rho I: 2 sum_c S_pc (|J_c[0][j]|^2 + |J_c[1][j]|^2) + rho
   const int nb = L.nb[f];
+  // one wavefront per station at a time, its lanes over the station's baselines
   double dmax = 0.0;
-  for (int p = threadIdx.x; p < pb.N; p += kBlock) {
+  const int lane = threadIdx.x & 63;
+  for (int p = threadIdx.x >> 6; p < pb.N; p += kBlock / 64) {
     double d0 = 0.0, d1 = 0.0;
-    for (int a = L.adj_off[f * pb.N + p]; a < L.adj_off[f * pb.N + p + 1]; ++a) {
+    for (int a = L.adj_off[f * pb.N + p] + lane; a < L.adj_off[f * pb.N + p + 1]; a += 64) {
       const int gb = L.adj_b[a];
       const int o = L.adj_o[a] >= 0 ? L.adj_o[a] : -1 - L.adj_o[a];
       const double S = B.Sb[L.sb_off[f] + (int64_t)k * nb + (gb - L.bl_off[f])];
@@ -108,6 +110,8 @@ __global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffe
       d0 += S * (Jo[0] * Jo[0] + Jo[1] * Jo[1] + Jo[4] * Jo[4] + Jo[5] * Jo[5]);
       d1 += S * (Jo[2] * Jo[2] + Jo[3] * Jo[3] + Jo[6] * Jo[6] + Jo[7] * Jo[7]);
     }
+    d0 = wave_sum(d0);
+    d1 = wave_sum(d1);
     dmax = fmax(dmax, 2.0 * fmax(d0, d1));
   }
   __shared__ double mx[kBlock / 64];
