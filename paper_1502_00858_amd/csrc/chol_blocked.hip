@@ -6,15 +6,17 @@
 // Right-looking over 64-column panels p (tile columns 4p .. 4p+wp-1), one launch per panel
 // (grid: subband x (64-row chunks below the panel's diagonal block + 64x64 blocks of the trailing
 // lower triangle)):
-//   panel workgroups load the panel's diagonal block and their chunk of rows into LDS, apply the
-//          pending rank-64 update of the previous panel there, and factor the block (left-looking
-//          over its 16x16 tiles: diagonal tile factor + inverse on one wavefront, the tiles below
-//          as MFMA products with the inverse, then the rank-16 update of the block's later tile
-//          columns) - redundantly, so that no workgroup waits for another - applying the same
-//          steps to their own rows: L[I, panel] = A[I, panel] L_pp^-T.  The workgroup of chunk 0
-//          also keeps the diagonal tiles' inverses (for the back substitution) and the block's
-//          strictly-lower tiles (in a side buffer: the other workgroups are still reading the
-//          block from the matrix);
+//   panel workgroups hold the panel's diagonal block and their chunk of rows (a 128x64 stack) in
+//          registers, apply the pending rank-64 update of the previous panel on MFMA, and
+//          eliminate the panel's columns two at a time across the whole workgroup: the stack's
+//          values of the next two columns are published in LDS, every lane forms the 2x2 pivot
+//          block's elimination itself, the owners of the following pair update it first and
+//          publish it, one barrier per pair, the rest of the update after the barrier.  Every
+//          panel workgroup factors the diagonal block redundantly, so none waits for another; the
+//          chunk rows come out as L[I, panel] = A[I, panel] L_pp^-T.  The workgroup of chunk 0
+//          also inverts the diagonal 16x16 tiles (for the back substitution) and keeps the
+//          block's strictly-lower tiles in a side buffer (the other workgroups are still reading
+//          the block from the matrix);
 //   trailing workgroups apply the previous panel's update to the lower triangle right of the
 //          panel (right-hand-side row included): A[I,K] -= sum_t L[I,t] L[K,t]^T on
 //          v_mfma_f64_16x16x4f64.
@@ -32,8 +34,9 @@ using namespace chol;
 
 constexpr int kPanelTiles = 4;            // 16-column tiles per panel
 constexpr int kPB = 64;                   // panel width in columns
-constexpr int kLd = kPB + 1;              // LDS row stride of a 64x64 block (doubles)
-constexpr int kBThreads = 256;            // panel and trail workgroups: 4 wavefronts
+constexpr int kPs = kPB + 2;              // LDS row stride of the previous panel's L (16-byte rows)
+constexpr int kStack = 2 * kPB;           // rows of a panel workgroup's stack: diagonal block + chunk
+constexpr int kBThreads = 512;            // panel and trailing workgroups: 8 wavefronts
 
 struct PanelGeom {
   int c0, wp, c1;                         // first tile column, tile columns, first trailing tile
@@ -45,20 +48,6 @@ __device__ inline PanelGeom panel_geom(int p, int nct) {
   g.wp = min(kPanelTiles, nct - g.c0);
   g.c1 = g.c0 + g.wp;
   return g;
-}
-
-// T (16x16 tile in LDS, stride kLd) <- T - X Y^T, X and Y 16x16 tiles in LDS (v_mfma operands:
-// lane l supplies row l%16, columns 4(l/16)..4(l/16)+3 of X and of Y)
-__device__ inline void tile_update_lds(double *T, const double *X, const double *Y, int li, int lq) {
-  d4 acc;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) acc[r] = T[(4 * r + lq) * kLd + li];
-#pragma unroll
-  for (int q = 0; q < 4; ++q)
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-X[li * kLd + 4 * lq + q], Y[li * kLd + 4 * lq + q],
-                                               acc, 0, 0, 0);
-#pragma unroll
-  for (int r = 0; r < 4; ++r) T[(4 * r + lq) * kLd + li] = acc[r];
 }
 
 // Trailing update of one 4x4-tile block (rb, kb) of the lower triangle that starts at tile rs:
@@ -112,42 +101,157 @@ __device__ __attribute__((always_inline)) inline void trail_block(double *A, int
       if (valid[a][b]) store_tile(A, nf, i0 + a, k0 + b, lane, acc[a][b]);
 }
 
-// T (16x16 tile in LDS, stride kLd) <- T - sum_{t < wsrc} X_t Y_t^T with X_t, Y_t the 16x16 tiles
-// at column offset 16t of the LDS row blocks X and Y
-__device__ __attribute__((always_inline)) inline void tile_update_lds_panel(double *T, const double *X, const double *Y, int wsrc,
-                                             int li, int lq) {
-  d4 acc;
+// A panel workgroup's stack: wavefront w owns stack tile row w (0-3: the panel's diagonal block,
+// 4-7: the chunk rows) across the panel's four tile columns, in the v_mfma_f64_16x16x4f64
+// accumulator layout: element r of lane l of tile J is stack row 16w + 4r + l/16 at panel column
+// 16J + l%16.
+typedef d4 Stack[kPanelTiles];
+
+__device__ inline int stack_row(int w, int r, int lq) { return 16 * w + 4 * r + lq; }
+
+__device__ inline double2 lds2(const double *p) { return *reinterpret_cast<const double2 *>(p); }
+
+// 1/d: the v_rcp_f64 estimate (relative error below 2^-24) refined by one third-order step
+// y (1 + e + e^2), e = 1 - d y, which cubes the relative error.
+__device__ inline double rcp3(double d) {
+  const double y = __builtin_amdgcn_rcp(d);
+  const double e = fma(-d, y, 1.0);
+  return fma(y, fma(e, e, e), y);
+}
+
+// What a pair's elimination leaves for the next step: this lane's v_mfma operands of the pair's
+// rank-2 update of the tile columns right of its priority tile (A: the pair's column k = l/16 at
+// stack row 16w + l%16, zero for k > 1; B, formed in the next step: row k of
+// M^-1 [a[j][c] a[j][c+1]]^T at column j = 16J + l%16, from the carried coefficients al, be and
+// the pair's values v0, v1 at row j).
+struct PairCarry {
+  double aval, al, be, v0[kPanelTiles], v1[kPanelTiles];
+};
+
+// The pair's update of tile columns JD.. on v_mfma_f64_16x16x4f64 (k = 0, 1 carry the pair; the
+// tile columns past the panel's width hold padding that is never read).  The empty asm emits
+// nothing; it keeps the products ahead of the publication that follows in the same step.
+template <int JD>
+__device__ __attribute__((always_inline)) inline void pair_rest(Stack &acc, const PairCarry &cy) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r) acc[r] = T[(4 * r + lq) * kLd + li];
+  for (int j2 = JD; j2 < kPanelTiles; ++j2) {
+    const double bval = fma(cy.al, cy.v0[j2], cy.be * cy.v1[j2]);
+    acc[j2] = __builtin_amdgcn_mfma_f64_16x16x4f64(-cy.aval, bval, acc[j2], 0, 0, 0);
 #pragma unroll
-  for (int t = 0; t < kPanelTiles; ++t) {
-    if (t < wsrc) {
+    for (int r = 0; r < 4; ++r) __asm__ __volatile__("" : "+v"(acc[j2][r]));
+  }
+}
+
+// Elimination of the column pair c, c+1 (c even, in tile column J; JP = (c+2)/16 holds the next
+// pair).  hist[c/2]: the stack's values of columns c and c+1 ([row][2], updated through column
+// c-1); hist[c/2 + 1]: where the next pair goes.  With the pivot block M = [a00 a10; a10 a11]
+// (a00 = a[c][c], a10 = a[c+1][c], a11 = a[c+1][c+1]) and d = det M, two steps of the
+// right-looking Cholesky update of column j > c+1 are
+//     a[i][j] -= [a[i][c] a[i][c+1]] M^-1 [a[j][c] a[j][c+1]]^T
+//              = (a[i][c] (a11 a[j][c] - a10 a[j][c+1]) + a[i][c+1] (a00 a[j][c+1] - a10 a[j][c])) / d,
+// and every lane forms it from hist itself.  The step: this pair's reads, d and the hardware
+// estimate of 1/d, the previous pair's update of the tile columns right of J on MFMA (independent
+// of this pair's pivots, it runs inside the estimate's latency), the refinement of 1/d, this
+// pair's update of tile JP on the vector unit and the publication of the pair c+2, c+3, the
+// carry, the barrier (sched_barrier keeps the compiler from interleaving the groups otherwise).
+// Columns stay unscaled: L is formed from hist after the last pair.  Entries above the diagonal
+// block's diagonal are carried along and never read; finished columns are left alone (their
+// lanes add zero).
+template <int J, int JP, bool kPrev>
+__device__ __attribute__((always_inline)) inline void elim_pair(Stack &acc, double *hist,
+                                                                PairCarry &cy, int c, int wcol,
+                                                                int w, int lane) {
+  const int li = lane & 15, lq = lane >> 4;
+  const double *cb = hist + (c >> 1) * 2 * kStack;
+  double *cn = hist + ((c >> 1) + 1) * 2 * kStack;
+  const double a00 = cb[2 * c];
+  const double2 p1 = lds2(cb + 2 * (c + 1));
+  const double a10 = p1.x, a11 = p1.y;
+  double u0[4], u1[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-X[li * kLd + 16 * t + 4 * lq + q],
-                                                   Y[li * kLd + 16 * t + 4 * lq + q], acc, 0, 0, 0);
+  for (int r = 0; r < 4; ++r) {
+    const double2 v = lds2(cb + 2 * stack_row(w, r, lq));
+    u0[r] = v.x;
+    u1[r] = v.y;
+  }
+  const double arow = cb[2 * (16 * w + li) + (lq & 1)];
+  double v0[kPanelTiles], v1[kPanelTiles];
+#pragma unroll
+  for (int j2 = 0; j2 < kPanelTiles; ++j2) {
+    if (j2 >= JP) {
+      const double2 v = lds2(cb + 2 * (16 * j2 + li));
+      v0[j2] = v.x;
+      v1[j2] = v.y;
+    } else {
+      v0[j2] = v1[j2] = 0.0;
     }
   }
+  const double det = fma(a00, a11, -(a10 * a10));
+  double y0 = __builtin_amdgcn_rcp(det);
+  __asm__ __volatile__("" : "+v"(y0));
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (kPrev) pair_rest<J + 1>(acc, cy);
+  __builtin_amdgcn_sched_barrier(0);
+  const double e0 = fma(-det, y0, 1.0);
+  const double rdet = fma(y0, fma(e0, e0, e0), y0);   // third-order refinement, as in rcp3
+  if constexpr (JP < kPanelTiles) {
+    const bool upd = 16 * JP + li > c + 1;
+    const double pn = upd ? fma(a11, v0[JP], -(a10 * v1[JP])) : 0.0;
+    const double qn = upd ? fma(a00, v1[JP], -(a10 * v0[JP])) : 0.0;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) T[(4 * r + lq) * kLd + li] = acc[r];
+    for (int r = 0; r < 4; ++r) acc[JP][r] = fma(-fma(u0[r], pn, u1[r] * qn), rdet, acc[JP][r]);
+    const int cc = (c + 2) & 15;
+    if (c + 2 < wcol && (li == cc || li == cc + 1)) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cn[2 * stack_row(w, r, lq) + (li - cc)] = acc[JP][r];
+    }
+  }
+  cy.aval = lq < 2 ? arow : 0.0;
+  cy.al = (lq == 0 ? a11 : (lq == 1 ? -a10 : 0.0)) * rdet;
+  cy.be = (lq == 0 ? -a10 : (lq == 1 ? a00 : 0.0)) * rdet;
+#pragma unroll
+  for (int j2 = 0; j2 < kPanelTiles; ++j2) {
+    cy.v0[j2] = v0[j2];
+    cy.v1[j2] = v1[j2];
+  }
+  __syncthreads();
+}
+
+// The eight column pairs of tile column J
+template <int J>
+__device__ __attribute__((always_inline)) inline void elim_tile(Stack &acc, double *hist,
+                                                                PairCarry &cy, int wcol, int w,
+                                                                int lane) {
+  elim_pair<J, J, (J > 0)>(acc, hist, cy, 16 * J, wcol, w, lane);
+#pragma unroll 1
+  for (int s = 1; s < 7; ++s) elim_pair<J, J, true>(acc, hist, cy, 16 * J + 2 * s, wcol, w, lane);
+  elim_pair<J, J + 1, true>(acc, hist, cy, 16 * J + 14, wcol, w, lane);
+}
+
+// Lower-triangle 64x64 blocks of the trailing region right of a panel: block rows rb < nrb (the
+// last may hold the right-hand-side row), block columns kb <= rb and kb < nkb.
+__host__ __device__ inline int trail_blocks(int nrb, int nkb) {
+  int n = 0;
+  for (int rb = 0; rb < nrb; ++rb) n += min(rb + 1, nkb);
+  return n;
 }
 
 // One step p of the blocked factorisation (grid: subband x (nchunk panel workgroups + trailing
 // workgroups)).  Panel workgroups (blockIdx.y < nchunk, dispatched first) apply the pending
-// rank-64 update of panel p-1 to their LDS copies of panel p's diagonal block and of their chunk
-// of rows, then factor panel p.  Trailing workgroups apply the same update of panel p-1 to the
-// lower triangle right of panel p.  Both roles only read panel p-1's L and write disjoint regions,
-// so one launch per panel suffices and nothing waits across workgroups.
+// rank-64 update of panel p-1 to their stack (panel p's diagonal block and their chunk of rows),
+// then factor panel p.  Trailing workgroups apply the same update of panel p-1 to the lower
+// triangle right of panel p, two 64x64 blocks each (four wavefronts per block).  Both roles only
+// read panel p-1's L and write disjoint regions, so one launch per panel suffices and nothing
+// waits across workgroups.
 __global__ __launch_bounds__(kBThreads) void k_chol_panel(Problem pb, Buffers B, int k,
                                                           const int32_t *ndir, int p, double *Ld,
                                                           int *cfail) {
-  __shared__ double Dl[kPB * kLd];    // the panel's diagonal block
-  __shared__ double Xl[kPB * kLd];    // this workgroup's rows of the panel
-  __shared__ double Pd[kPB * kLd];    // L of panel p-1 at the diagonal block's rows
-  __shared__ double Px[kPB * kLd];    // L of panel p-1 at this workgroup's rows
-  __shared__ double inv[256];
-  __shared__ double xch[32];
-  __shared__ int bad;
+  // L of panel p-1 at the diagonal block's rows (Pd) and at this workgroup's rows (Px); after the
+  // pending update, the history of published column pairs (hist, [pair][row][2]); at the end, the
+  // diagonal tiles to invert
+  __shared__ __align__(16) double lds[2 * kPB * kPs];
+  static_assert(kPB / 2 * 2 * kStack <= 2 * kPB * kPs, "column history fits");
+  double *Pd = lds, *Px = lds + kPB * kPs, *hist = lds;
   const int f = blockIdx.x;
   if (k >= ndir[f] || B.lm[f].done || cfail[f]) return;
   const int nf = pb.nf, nct = nf >> 4, nrt = pb.npad >> 4;
@@ -160,37 +264,40 @@ __global__ __launch_bounds__(kBThreads) void k_chol_panel(Problem pb, Buffers B,
   const int nchunk = (nrt - g.c1 + kPanelTiles - 1) / kPanelTiles;
   if ((int)blockIdx.y >= nchunk) {
     // trailing role: the region right of panel p, rows and columns from tile g.c1
-    const int bb = blockIdx.y - nchunk;
+    const int nrb = (nrt - g.c1 + kPanelTiles - 1) / kPanelTiles;
     const int nkb = (nct - g.c1 + kPanelTiles - 1) / kPanelTiles;
-    const int rb = bb / nkb, kb = bb % nkb;
-    if (kb > rb) return;
-    trail_block(A, nf, nct, nrt, gs, g.c1, rb, kb, w, lane);
+    int rem = 2 * ((int)blockIdx.y - nchunk) + (w >> 2);
+    if (rem >= trail_blocks(nrb, nkb)) return;
+    int rb = 0;
+    while (rem >= min(rb + 1, nkb)) {
+      rem -= min(rb + 1, nkb);
+      ++rb;
+    }
+    trail_block(A, nf, nct, nrt, gs, g.c1, rb, rem, w & 3, lane);
     return;
   }
   const int q = blockIdx.y;
   const int r0 = g.c1 + kPanelTiles * q;            // first row tile of this chunk
   const int nr = min(kPanelTiles, nrt - r0);
-  const int wcol = 16 * g.wp, wsrc = (p > 0) ? 16 * gs.wp : 0;
+  const int wp = g.wp, wcol = 16 * wp, wsrc = (p > 0) ? 16 * gs.wp : 0;
+  // this wavefront's stack tile row: its first matrix row, and whether it holds rows of the
+  // block or the chunk
+  const bool in_block = w < kPanelTiles;
+  const bool live = in_block ? w < wp : w - kPanelTiles < nr;
+  const int64_t row0 = in_block ? 16 * (g.c0 + w) : 16 * (r0 + w - kPanelTiles);
 
-  // fixed-count loops over the 64x64 footprints: each block pair's loads are all issued before
-  // its first LDS store
-  {
-    double dv[kPB * kPB / kBThreads], xv[kPB * kPB / kBThreads];
+  Stack acc;
 #pragma unroll
-    for (int it = 0; it < kPB * kPB / kBThreads; ++it) {
-      const int e = tid + it * kBThreads, row = e >> 6, col = e & 63;
-      dv[it] = (row < wcol && col < wcol && (col >> 4) <= (row >> 4))
-                   ? A[(int64_t)(g.c0 * 16 + row) * nf + g.c0 * 16 + col] : 0.0;
-      xv[it] = (row < 16 * nr && col < wcol) ? A[(int64_t)(r0 * 16 + row) * nf + g.c0 * 16 + col] : 0.0;
-    }
+  for (int J = 0; J < kPanelTiles; ++J)
 #pragma unroll
-    for (int it = 0; it < kPB * kPB / kBThreads; ++it) {
-      const int e = tid + it * kBThreads, row = e >> 6, col = e & 63;
-      Dl[row * kLd + col] = dv[it];
-      Xl[row * kLd + col] = xv[it];
+    for (int r = 0; r < 4; ++r) {
+      const int rr = 4 * r + lq;
+      const bool v = live && J < wp && (!in_block || J < w || (J == w && li <= rr));
+      acc[J][r] = v ? A[(row0 + rr) * nf + 16 * (g.c0 + J) + li] : 0.0;
     }
-  }
   if (p > 0) {
+    // L of panel p-1 at the block's rows and at the chunk's rows (fixed-count loops: each pair's
+    // loads are all issued before its first LDS store)
     double dv[kPB * kPB / kBThreads], xv[kPB * kPB / kBThreads];
 #pragma unroll
     for (int it = 0; it < kPB * kPB / kBThreads; ++it) {
@@ -201,86 +308,105 @@ __global__ __launch_bounds__(kBThreads) void k_chol_panel(Problem pb, Buffers B,
 #pragma unroll
     for (int it = 0; it < kPB * kPB / kBThreads; ++it) {
       const int e = tid + it * kBThreads, row = e >> 6, col = e & 63;
-      Pd[row * kLd + col] = dv[it];
-      Px[row * kLd + col] = xv[it];
-    }
-  }
-  if (tid == 0) bad = 0;
-  __syncthreads();
-  if (p > 0) {
-    // pending rank-64 update of panel p-1: the diagonal block's lower tiles, then the chunk's
-    int cnt = 0;
-    for (int s2 = 0; s2 < g.wp; ++s2)
-      for (int t2 = 0; t2 <= s2; ++t2, ++cnt)
-        if ((cnt & 3) == w)
-          tile_update_lds_panel(Dl + s2 * 16 * kLd + t2 * 16, Pd + s2 * 16 * kLd, Pd + t2 * 16 * kLd,
-                                gs.wp, li, lq);
-    for (int r = 0; r < nr; ++r)
-      for (int t2 = 0; t2 < g.wp; ++t2, ++cnt)
-        if ((cnt & 3) == w)
-          tile_update_lds_panel(Xl + r * 16 * kLd + t2 * 16, Px + r * 16 * kLd, Pd + t2 * 16 * kLd,
-                                gs.wp, li, lq);
-    __syncthreads();
-  }
-  for (int t = 0; t < g.wp; ++t) {
-    if (w == 0) {
-      double *Li = (q == 0) ? B.Linv + ((int64_t)f * nct + g.c0 + t) * 256 : nullptr;
-      const bool ok = factor16(Dl + t * 16 * kLd + t * 16, kLd, inv, xch, Li, lane);
-      if (!ok && lane == 0) bad = 1;
+      Pd[row * kPs + col] = dv[it];
+      Px[row * kPs + col] = xv[it];
     }
     __syncthreads();
-    if (bad) {
-      if (tid == 0) cfail[f] = 1;
-      return;
-    }
-    // tiles below diagonal tile t: the block's tiles (s, t), s > t, then the chunk's tiles
-    const double iv0 = inv[li * 16 + 4 * lq], iv1 = inv[li * 16 + 4 * lq + 1];
-    const double iv2 = inv[li * 16 + 4 * lq + 2], iv3 = inv[li * 16 + 4 * lq + 3];
-    const int nbelow = g.wp - 1 - t;
-    for (int m = w; m < nbelow + nr; m += 4) {
-      double *T = (m < nbelow) ? Dl + (t + 1 + m) * 16 * kLd + t * 16 : Xl + (m - nbelow) * 16 * kLd + t * 16;
-      const double x0 = T[li * kLd + 4 * lq], x1 = T[li * kLd + 4 * lq + 1];
-      const double x2 = T[li * kLd + 4 * lq + 2], x3 = T[li * kLd + 4 * lq + 3];
-      d4 d = {0.0, 0.0, 0.0, 0.0};
-      d = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, iv0, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, iv1, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f64_16x16x4f64(x2, iv2, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f64_16x16x4f64(x3, iv3, d, 0, 0, 0);
+    // pending rank-64 update: stack tile (w, J) -= P_w P_J^T, P_w the previous panel's L at the
+    // tile's rows (v_mfma operands: lane l supplies row l%16, columns 16t + 4(l/16) + qq)
+    const double *xrow = (in_block ? Pd + (16 * w + li) * kPs : Px + (16 * (w - kPanelTiles) + li) * kPs) + 4 * lq;
+    // (every tile of the row: those above the block's diagonal, past the panel's width or in
+    // padding rows hold values that are never read; gs.wp = 4 for every source panel)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) T[(4 * r + lq) * kLd + li] = d[r];
+    for (int t = 0; t < kPanelTiles; ++t) {
+      {
+        double xa[4], yb[kPanelTiles][4];
+        {
+          const double2 a = lds2(xrow + 16 * t), b = lds2(xrow + 16 * t + 2);
+          xa[0] = a.x; xa[1] = a.y; xa[2] = b.x; xa[3] = b.y;
+        }
+#pragma unroll
+        for (int J = 0; J < kPanelTiles; ++J) {
+          const double *src = Pd + (16 * J + li) * kPs + 16 * t + 4 * lq;
+          const double2 a = lds2(src), b = lds2(src + 2);
+          yb[J][0] = a.x; yb[J][1] = a.y; yb[J][2] = b.x; yb[J][3] = b.y;
+        }
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq)
+#pragma unroll
+          for (int J = 0; J < kPanelTiles; ++J)
+            acc[J] = __builtin_amdgcn_mfma_f64_16x16x4f64(-xa[qq], yb[J][qq], acc[J], 0, 0, 0);
+      }
     }
-    __syncthreads();
-    // rank-16 update of the later tile columns t' > t: the block's tiles (s, t'), s >= t', then
-    // the chunk's tiles
-    int cnt = 0;
-    for (int tp = t + 1; tp < g.wp; ++tp)
-      for (int s = tp; s < g.wp; ++s, ++cnt)
-        if ((cnt & 3) == w)
-          tile_update_lds(Dl + s * 16 * kLd + tp * 16, Dl + s * 16 * kLd + t * 16,
-                          Dl + tp * 16 * kLd + t * 16, li, lq);
-    for (int r = 0; r < nr; ++r)
-      for (int tp = t + 1; tp < g.wp; ++tp, ++cnt)
-        if ((cnt & 3) == w)
-          tile_update_lds(Xl + r * 16 * kLd + tp * 16, Xl + r * 16 * kLd + t * 16,
-                          Dl + tp * 16 * kLd + t * 16, li, lq);
-    __syncthreads();
+  }
+  __syncthreads();   // the pending update's reads of Pd and Px are done
+  // columns 0 and 1 published, then the pairs
+  if (li < 2) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) hist[2 * stack_row(w, r, lq) + li] = acc[0][r];
+  }
+  __syncthreads();
+  PairCarry cy;
+  elim_tile<0>(acc, hist, cy, wcol, w, lane);
+  if (wp > 1) elim_tile<1>(acc, hist, cy, wcol, w, lane);
+  if (wp > 2) elim_tile<2>(acc, hist, cy, wcol, w, lane);
+  if (wp > 3) elim_tile<3>(acc, hist, cy, wcol, w, lane);
+
+  // L from the history: column c of pair (c, c+1) is L[.][c] sqrt(a00), column c+1 is
+  // (a[.][c+1] - a[.][c] a10 / a00) / sqrt(det / a00); 1/L_jj in the diagonal slots.  Each lane
+  // checks the pivots of its columns' pairs (all pairs are covered).
+  int okv = 1;
+#pragma unroll
+  for (int J = 0; J < kPanelTiles; ++J) {
+    const int cpair = 16 * J + (li & ~1);
+    const double *h = hist + (cpair >> 1) * 2 * kStack;
+    const double a00 = J < wp ? h[2 * cpair] : 1.0;
+    const double2 p1 = lds2(h + 2 * (cpair + 1));
+    const double a10 = J < wp ? p1.x : 0.0, a11 = J < wp ? p1.y : 1.0;
+    const double det = fma(a00, a11, -(a10 * a10));
+    okv &= (a00 > 0.0 && det > 0.0 && isfinite(a00) && isfinite(det)) ? 1 : 0;
+    const double inv0 = rcp3(a00);
+    const double l10 = a10 * inv0;
+    const bool odd = li & 1;
+    const double rs = rsqrt_nr(odd ? det * inv0 : a00);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double2 x = lds2(h + 2 * stack_row(w, r, lq));
+      const double v = odd ? fma(-x.x, l10, x.y) : x.x;
+      acc[J][r] = (in_block && stack_row(w, r, lq) == 16 * J + li) ? rs : v * rs;
+    }
+  }
+  if (!__syncthreads_and(okv)) {
+    if (tid == 0) cfail[f] = 1;
+    return;
   }
 
-  {
+  // the chunk's rows of L go back into the matrix
+  if (!in_block && live) {
+#pragma unroll
+    for (int J = 0; J < kPanelTiles; ++J)
+      if (J < wp) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) A[(row0 + 4 * r + lq) * nf + 16 * (g.c0 + J) + li] = acc[J][r];
+      }
+  }
+  if (q == 0) {
+    // the block's strictly-lower tiles to the side buffer, its diagonal tiles inverted
     double *dst = Ld + ((int64_t)f * ((nct + kPanelTiles - 1) / kPanelTiles) + p) * kPB * kPB;
-    double xv[kPB * kPB / kBThreads], dv[kPB * kPB / kBThreads];
+    if (in_block && live) {
 #pragma unroll
-    for (int it = 0; it < kPB * kPB / kBThreads; ++it) {
-      const int e = tid + it * kBThreads, row = e >> 6, col = e & 63;
-      xv[it] = Xl[row * kLd + col];
-      dv[it] = Dl[row * kLd + col];
-    }
+      for (int J = 0; J < kPanelTiles; ++J) {
+        if (J < w) {
 #pragma unroll
-    for (int it = 0; it < kPB * kPB / kBThreads; ++it) {
-      const int e = tid + it * kBThreads, row = e >> 6, col = e & 63;
-      if (row < 16 * nr && col < wcol) A[(int64_t)(r0 * 16 + row) * nf + g.c0 * 16 + col] = xv[it];
-      if (q == 0 && row < wcol && col < wcol && (col >> 4) < (row >> 4)) dst[row * kPB + col] = dv[it];
+          for (int r = 0; r < 4; ++r) dst[(16 * w + 4 * r + lq) * kPB + 16 * J + li] = acc[J][r];
+        } else if (J == w) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) lds[w * 256 + (4 * r + lq) * 16 + li] = acc[J][r];
+        }
+      }
     }
+    __syncthreads();
+    if (w < wp) tri_inverse16(lds + w * 256, nullptr, B.Linv + ((int64_t)f * nct + g.c0 + w) * 256, lane);
   }
 }
 
@@ -431,7 +557,7 @@ hipError_t launch_chol_blocked(const Problem &pb, const Buffers &B, int k, const
     const int nchunk = (nrt - c1 + kPanelTiles - 1) / kPanelTiles;
     const int nrb = (nrt - c1 + kPanelTiles - 1) / kPanelTiles;
     const int nkb = (nct - c1 + kPanelTiles - 1) / kPanelTiles;
-    const int ntrail = (p > 0) ? nrb * nkb : 0;
+    const int ntrail = (p > 0) ? (trail_blocks(nrb, nkb) + 1) / 2 : 0;
     hipLaunchKernelGGL(k_chol_panel, dim3(pb.P, nchunk + ntrail), dim3(kBThreads), 0, s, pb, B, k,
                        ndir, p, Ld, cfail);
     const hipError_t e = hipGetLastError();

@@ -50,18 +50,59 @@ __device__ inline double rsqrt_nr(double d) {
   return y;
 }
 
+// 1/d for d != 0: the hardware estimate v_rcp_f64 refined by two Newton-Raphson steps
+// y <- y + y (1 - d y), which square the relative error each time.
+__device__ inline double rcp_nr(double d) {
+  double y = __builtin_amdgcn_rcp(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(y, fma(-d, y, 1.0), y);
+  return y;
+}
+
+// Inverse of a 16x16 lower-triangular tile T (row-major in LDS, leading dimension 16, 1/T_ii in
+// the diagonal slots, entries above the diagonal never read) by forward substitution on one
+// wavefront: lane c < 16 solves T x = e_c with four partial sums per row, the next row of T
+// prefetched while the current one is used.  The inverse (row-major) goes to out_lds (which may
+// be T itself: every read of T precedes the first write) and to out_global, each when not null.
+__device__ inline void tri_inverse16(const double *T, double *out_lds, double *out_global, int lane) {
+  double x[16], row[16], nxt[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) row[m] = (m == 0) ? T[0] : 0.0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    if (i + 1 < 16) {
+#pragma unroll
+      for (int m = 0; m <= i + 1; ++m) nxt[m] = T[(i + 1) * 16 + m];
+    }
+    double p[4] = {(i == lane) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < i; ++m) p[m & 3] -= row[m] * x[m];
+    x[i] = ((p[0] + p[1]) + (p[2] + p[3])) * row[i];
+    __asm__ __volatile__("" : "+v"(x[i]) :: "memory");
+#pragma unroll
+    for (int m = 0; m < 16; ++m) row[m] = nxt[m];
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane < 16) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (out_lds) out_lds[i * 16 + lane] = x[i];
+      if (out_global) out_global[i * 16 + lane] = x[i];
+    }
+  }
+}
+
 // One full wavefront factors the 16x16 SPD tile D (row-major, leading dimension ld, lower
 // triangle read) and inverts the factor.  Lane i < 16 keeps row i of the reduced matrix; every
 // lane also keeps the whole reduced diagonal (dg, identical in all lanes), so the pivot of each
 // column is at hand without an exchange.  Column c of L is exchanged through the LDS scratch
 // xch (32 doubles; a wavefront's LDS accesses complete in order), no value goes through scalar
 // registers, and each finished column goes to inv at once with 1/L_ii in the diagonal slot of
-// row i.  The inverse is formed by forward substitution (lane c < 16 forms column c of L^-1, the
-// next row of L prefetched while the current one is used) and written to inv (16x16 row-major,
-// LDS) and, when Li_out is not null, to Li_out.  Straight-line code (no early exit); a
-// non-positive or non-finite pivot only makes the result false (wave-uniform).  The empty asm
-// statements emit no instruction: they pin values and LDS accesses to their column or row so
-// that the unrolled loops keep few registers live.
+// row i.  The inverse (tri_inverse16) is written to inv (16x16 row-major, LDS) and, when Li_out
+// is not null, to Li_out.  Straight-line code (no early exit); a non-positive or non-finite pivot
+// only makes the result false (wave-uniform).  The empty asm statements emit no instruction:
+// they pin values and LDS accesses to their column so that the unrolled loop keeps few registers
+// live.
 __device__ inline bool factor16(const double *D, int ld, double *inv, double *xch, double *Li_out,
                                 int lane) {
   double a[16], dg[16];
@@ -96,32 +137,7 @@ __device__ inline bool factor16(const double *D, int ld, double *inv, double *xc
   const bool ok = okv != 0;
   if (ok) {
     __builtin_amdgcn_wave_barrier();
-    // forward substitution L x = e_lane with four partial sums per row
-    double x[16], row[16], nxt[16];
-#pragma unroll
-    for (int m = 0; m < 16; ++m) row[m] = (m == 0) ? inv[0] : 0.0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      if (i + 1 < 16) {
-#pragma unroll
-        for (int m = 0; m <= i + 1; ++m) nxt[m] = inv[(i + 1) * 16 + m];
-      }
-      double p[4] = {(i == lane) ? 1.0 : 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int m = 0; m < i; ++m) p[m & 3] -= row[m] * x[m];
-      x[i] = ((p[0] + p[1]) + (p[2] + p[3])) * row[i];
-      __asm__ __volatile__("" : "+v"(x[i]) :: "memory");
-#pragma unroll
-      for (int m = 0; m < 16; ++m) row[m] = nxt[m];
-    }
-    __builtin_amdgcn_wave_barrier();
-    if (lane < 16) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        inv[i * 16 + lane] = x[i];
-        if (Li_out) Li_out[i * 16 + lane] = x[i];
-      }
-    }
+    tri_inverse16(inv, inv, Li_out, lane);
   }
   return ok;
 }
