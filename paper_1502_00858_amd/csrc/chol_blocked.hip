@@ -236,8 +236,9 @@ __host__ __device__ inline int trail_blocks(int nrb, int nkb) {
   return n;
 }
 
-// One step p of the blocked factorisation (grid: subband x (nchunk panel workgroups + trailing
-// workgroups)).  Panel workgroups (blockIdx.y < nchunk, dispatched first) apply the pending
+// One step p of the blocked factorisation (grid: subband x (nchunk panel workgroups, for p > 0 one
+// workgroup for panel p-1's diagonal block, trailing workgroups)).  Panel workgroups
+// (blockIdx.y < nchunk, dispatched first) apply the pending
 // rank-64 update of panel p-1 to their stack (panel p's diagonal block and their chunk of rows),
 // then factor panel p.  Trailing workgroups apply the same update of panel p-1 to the lower
 // triangle right of panel p, two 64x64 blocks each (four wavefronts per block).  Both roles only
@@ -261,12 +262,37 @@ __global__ __launch_bounds__(kBThreads) void k_chol_panel(Problem pb, Buffers B,
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 15, lq = lane >> 4;
   const PanelGeom gs = panel_geom(p > 0 ? p - 1 : 0, nct);   // source of the pending update
+  const int np = (nct + kPanelTiles - 1) / kPanelTiles;
   const int nchunk = (nrt - g.c1 + kPanelTiles - 1) / kPanelTiles;
-  if ((int)blockIdx.y >= nchunk) {
+  if (p > 0 && (int)blockIdx.y == nchunk) {
+    // panel p-1's diagonal block: its strictly-lower tiles from the side buffer into the matrix
+    // (no workgroup of this launch reads them there) and its diagonal tiles inverted for the back
+    // substitution, one wavefront per tile
+    const PanelGeom gp = panel_geom(p - 1, nct);
+    const double *src = Ld + ((int64_t)f * np + p - 1) * kPB * kPB;
+#pragma unroll 4
+    for (int e = tid; e < kPB * kPB; e += kBThreads) {
+      const int row = e >> 6, col = e & 63, ti = row >> 4, tj = col >> 4;
+      if (ti < gp.wp && tj < ti) A[(int64_t)(gp.c0 * 16 + row) * nf + gp.c0 * 16 + col] = src[e];
+    }
+    if (w < gp.wp) {
+      double *T = lds + w * 256;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = lane + 64 * u;
+        T[e] = src[(16 * w + (e >> 4)) * kPB + 16 * w + (e & 15)];
+      }
+      __builtin_amdgcn_wave_barrier();
+      tri_inverse16(T, nullptr, B.Linv + ((int64_t)f * nct + gp.c0 + w) * 256, lane);
+    }
+    return;
+  }
+  const int side = (p > 0) ? 1 : 0;
+  if ((int)blockIdx.y >= nchunk + side) {
     // trailing role: the region right of panel p, rows and columns from tile g.c1
     const int nrb = (nrt - g.c1 + kPanelTiles - 1) / kPanelTiles;
     const int nkb = (nct - g.c1 + kPanelTiles - 1) / kPanelTiles;
-    int rem = 2 * ((int)blockIdx.y - nchunk) + (w >> 2);
+    int rem = 2 * ((int)blockIdx.y - nchunk - side) + (w >> 2);
     if (rem >= trail_blocks(nrb, nkb)) return;
     int rb = 0;
     while (rem >= min(rb + 1, nkb)) {
@@ -390,15 +416,27 @@ __global__ __launch_bounds__(kBThreads) void k_chol_panel(Problem pb, Buffers B,
         for (int r = 0; r < 4; ++r) A[(row0 + 4 * r + lq) * nf + 16 * (g.c0 + J) + li] = acc[J][r];
       }
   }
-  if (q == 0) {
-    // the block's strictly-lower tiles to the side buffer, its diagonal tiles inverted
-    double *dst = Ld + ((int64_t)f * ((nct + kPanelTiles - 1) / kPanelTiles) + p) * kPB * kPB;
+  if (q == 0 && p < np - 1 && in_block && live) {
+    // the block's lower tiles (diagonal tiles included) to the side buffer: the other workgroups
+    // are still reading the block from the matrix (the next launch moves them and inverts the
+    // diagonal tiles)
+    double *dst = Ld + ((int64_t)f * np + p) * kPB * kPB;
+#pragma unroll
+    for (int J = 0; J < kPanelTiles; ++J)
+      if (J <= w) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[(16 * w + 4 * r + lq) * kPB + 16 * J + li] = acc[J][r];
+      }
+  }
+  if (p == np - 1) {
+    // the last panel has one workgroup, chunk 0 (its chunk is the right-hand-side row): the
+    // block's strictly-lower tiles go straight into the matrix, its diagonal tiles are inverted
     if (in_block && live) {
 #pragma unroll
       for (int J = 0; J < kPanelTiles; ++J) {
         if (J < w) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) dst[(16 * w + 4 * r + lq) * kPB + 16 * J + li] = acc[J][r];
+          for (int r = 0; r < 4; ++r) A[(row0 + 4 * r + lq) * nf + 16 * (g.c0 + J) + li] = acc[J][r];
         } else if (J == w) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) lds[w * 256 + (4 * r + lq) * 16 + li] = acc[J][r];
@@ -410,7 +448,6 @@ __global__ __launch_bounds__(kBThreads) void k_chol_panel(Problem pb, Buffers B,
   }
 }
 
-
 // Back substitution L^T delta = y with one thread per column (nf <= 1024): per 16-row block,
 // from the last, x_J = (L_JJ^-1)^T t_J on 16 threads, then t -= L_J^T x_J on every column left
 // of the block.  The rows of L of the next block are in flight while a block is used (the
@@ -419,8 +456,7 @@ constexpr int kBsThreads = 1024;
 constexpr int kBsWaves = kBsThreads / 64;
 
 __global__ __launch_bounds__(kBsThreads) void k_chol_backsub(Problem pb, Buffers B, int k,
-                                                             const int32_t *ndir, const double *Ld,
-                                                             int *cfail) {
+                                                             const int32_t *ndir, int *cfail) {
   __shared__ double tb[2][16];
   __shared__ double xb[2][16];
   __shared__ double liS[2][256];   // L_JJ^-1 of the current and the next block
@@ -441,18 +477,8 @@ __global__ __launch_bounds__(kBsThreads) void k_chol_backsub(Problem pb, Buffers
     return;
   }
   const int nf = pb.nf, nct = nf >> 4;
-  const int np = (nct + kPanelTiles - 1) / kPanelTiles;
   double *A = B.H + (int64_t)f * pb.npad * nf;
   const double *Li = B.Linv + (int64_t)f * nct * 256;
-  // the diagonal blocks' strictly-lower tiles go back into the matrix
-  const double *src = Ld + (int64_t)f * np * kPB * kPB;
-  for (int e = tid; e < np * kPB * kPB; e += kBsThreads) {
-    const int p = e / (kPB * kPB), row = (e / kPB) % kPB, col = e % kPB;
-    const PanelGeom g = panel_geom(p, nct);
-    if ((col >> 4) < (row >> 4) && (row >> 4) < g.wp)
-      A[(int64_t)(g.c0 * 16 + row) * nf + g.c0 * 16 + col] = src[e];
-  }
-  __syncthreads();
 
   const int c = tid;
   double t = (c < nf) ? A[(int64_t)nf * nf + c] : 0.0;
@@ -543,6 +569,98 @@ __global__ __launch_bounds__(kBsThreads) void k_chol_backsub(Problem pb, Buffers
   }
 }
 
+// Back substitution L^T delta = y for nf <= 512, one thread per column: per 16-row block J, from
+// the last, the 16 lanes that own the block's columns form x_J = (L_JJ^-1)^T t_J inside their
+// wavefront (t_J exchanged through LDS; each lane holds its column of L_JJ^-1 from the start) and
+// publish it; after one barrier every column left of the block takes t -= L_J^T x_J.  The rows of
+// L stream from memory once, up to kBsAhead blocks ahead of their use, in a ring of register
+// buffers indexed at compile time (the block loop is unrolled by kBsAhead).  Only lanes whose
+// column is left of a block load its rows, so wavefronts right of it issue no loads: the step is
+// bound by the vector-memory instructions the compute unit issues, not by their latency.
+constexpr int kBrThreads = 512;
+constexpr int kBrWaves = kBrThreads / 64;
+constexpr int kBsAhead = 4;
+
+__global__ __launch_bounds__(kBrThreads) void k_chol_backsub_ring(Problem pb, Buffers B, int k,
+                                                                  const int32_t *ndir, int *cfail) {
+  __shared__ double tx[kBrWaves][16];   // per wavefront: the right-hand side of its block
+  __shared__ double xs[2][16];          // the current block's solution
+  __shared__ double red[kBrWaves];
+  __shared__ int failed;
+  const int f = blockIdx.x;
+  if (k >= ndir[f] || B.lm[f].done) return;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  if (tid == 0) failed = cfail[f];
+  __syncthreads();
+  LmState *st = B.lm + f;
+  if (failed) {
+    if (tid == 0) {
+      st->chol_ok = 0;
+      cfail[f] = 0;
+    }
+    return;
+  }
+  const int nf = pb.nf, nct = nf >> 4;
+  const double *A = B.H + (int64_t)f * pb.npad * nf;
+  const int c = tid, myblk = c >> 4, r16 = c & 15;
+  double t = (c < nf) ? A[(int64_t)nf * nf + c] : 0.0;
+  double lic[16];   // column r16 of L_JJ^-1, J = this lane's block
+#pragma unroll
+  for (int i = 0; i < 16; ++i) lic[i] = (c < nf) ? B.Linv[((int64_t)f * nct + myblk) * 256 + i * 16 + r16] : 0.0;
+  auto load_rows = [&](int jb, double (&dst)[16]) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) dst[r] = (jb >= 0 && c < 16 * jb) ? A[(int64_t)(16 * jb + r) * nf + c] : 0.0;
+  };
+  double ring[kBsAhead][16];
+#pragma unroll
+  for (int u = 0; u < kBsAhead; ++u) load_rows(nct - 1 - u, ring[u]);
+  auto step = [&](int jb, double (&use)[16]) {
+    if (myblk == jb) {
+      tx[w][r16] = t;
+      __builtin_amdgcn_wave_barrier();
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < 16; ++i) s4[i & 3] = fma(lic[i], tx[w][i], s4[i & 3]);
+      t = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+      xs[jb & 1][r16] = t;
+    }
+    __syncthreads();
+    if (c < 16 * jb) {
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < 16; ++r) s4[r & 3] = fma(use[r], xs[jb & 1][r], s4[r & 3]);
+      t -= (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    }
+    load_rows(jb - kBsAhead, use);
+  };
+  for (int jb = nct - 1; jb >= 0; jb -= kBsAhead) {
+#pragma unroll
+    for (int u = 0; u < kBsAhead; ++u)
+      if (jb - u >= 0) step(jb - u, ring[u]);
+  }
+  // delta, predicted decrease ell = delta.(lambda delta - G)/2, trial point
+  const double lam = st->lambda;
+  const int n8 = 8 * pb.N;
+  double ell = 0.0;
+  if (c < n8) {
+    const double gc = B.G[(int64_t)f * nf + c];
+    ell = t * (lam * t - gc);
+    B.delta[(int64_t)f * nf + c] = t;
+    B.Jtrial[(int64_t)f * n8 + c] = B.J[((int64_t)f * pb.K + k) * n8 + c] + t;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) ell += __shfl_xor(ell, o, 64);
+  if (lane == 0) red[w] = ell;
+  __syncthreads();
+  if (tid == 0) {
+    double sum = 0.0;
+    for (int i = 0; i < kBrWaves; ++i) sum += red[i];
+    st->ell = 0.5 * sum;
+    st->chol_ok = 1;
+  }
+}
+
 }  // namespace
 
 int chol_blocked_panels(const Problem &pb) { return (pb.nf / 16 + kPanelTiles - 1) / kPanelTiles; }
@@ -557,13 +675,16 @@ hipError_t launch_chol_blocked(const Problem &pb, const Buffers &B, int k, const
     const int nchunk = (nrt - c1 + kPanelTiles - 1) / kPanelTiles;
     const int nrb = (nrt - c1 + kPanelTiles - 1) / kPanelTiles;
     const int nkb = (nct - c1 + kPanelTiles - 1) / kPanelTiles;
-    const int ntrail = (p > 0) ? (trail_blocks(nrb, nkb) + 1) / 2 : 0;
-    hipLaunchKernelGGL(k_chol_panel, dim3(pb.P, nchunk + ntrail), dim3(kBThreads), 0, s, pb, B, k,
+    const int nextra = (p > 0) ? 1 + (trail_blocks(nrb, nkb) + 1) / 2 : 0;   // side + trailing
+    hipLaunchKernelGGL(k_chol_panel, dim3(pb.P, nchunk + nextra), dim3(kBThreads), 0, s, pb, B, k,
                        ndir, p, Ld, cfail);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_chol_backsub, dim3(pb.P), dim3(kBsThreads), 0, s, pb, B, k, ndir, Ld, cfail);
+  if (pb.nf <= kBrThreads)
+    hipLaunchKernelGGL(k_chol_backsub_ring, dim3(pb.P), dim3(kBrThreads), 0, s, pb, B, k, ndir, cfail);
+  else
+    hipLaunchKernelGGL(k_chol_backsub, dim3(pb.P), dim3(kBsThreads), 0, s, pb, B, k, ndir, cfail);
   return hipGetLastError();
 }
 

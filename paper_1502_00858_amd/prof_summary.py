@@ -6,7 +6,7 @@
 `trace` prints, per kernel, calls, total and average time and the average over dispatches longer
 than 5 us (launches whose subbands all stopped their LM runs exit at once), and, for the Cholesky
 solve, the wall time of each full solve: from the first kernel of a solve to the end of its last
-one (blocked solver: 8 panel launches + back substitution; one-workgroup solver: one launch).
+one (blocked solver: the panel launches + back substitution; one-workgroup solver: one launch).
 `pmc` prints per-dispatch FETCH_SIZE / WRITE_SIZE per kernel in MB, scaled by what the counters
 read for the 256 MiB device copy that profile_run ends with, and per-solve sums for the Cholesky.
 Output is markdown on stdout.
@@ -61,7 +61,7 @@ def trace(dirname: str):
                 start = (s, d)
             elif d > FULL_US and start[1] <= FULL_US:
                 start = (s, d)
-        elif n == "k_chol_backsub" and start is not None:
+        elif n in ("k_chol_backsub", "k_chol_backsub_ring") and start is not None:
             if d > FULL_US:
                 solves.append((e - start[0]) / 1e3)
             start = None
@@ -99,10 +99,11 @@ def pmc(fetch_dir: str, write_dir: str):
         f = sum(fv[n]) / len(fv[n]) * 1024 * fscale / 1e6
         w = (sum(wv[n]) / len(wv[n]) * 1024 * wscale / 1e6) if n in wv else float("nan")
         print(f"| {n} | {len(fv[n])} | {f:.2f} | {w:.2f} |")
-    solves = len(fv.get("k_chol_backsub", fv.get("k_chol_solve", [])))
+    names = ("k_chol_panel", "k_chol_backsub", "k_chol_backsub_ring", "k_chol_solve")
+    solves = sum(len(fv.get(n, [])) for n in names[1:])
     if solves:
-        tf = sum(sum(fv.get(n, [])) for n in ("k_chol_panel", "k_chol_backsub", "k_chol_solve"))
-        tw = sum(sum(wv.get(n, [])) for n in ("k_chol_panel", "k_chol_backsub", "k_chol_solve"))
+        tf = sum(sum(fv.get(n, [])) for n in names)
+        tw = sum(sum(wv.get(n, [])) for n in names)
         print(f"\nCholesky solve ({solves} solves): fetch {tf / solves * 1024 * fscale / 1e6:.2f} MB + "
               f"write {tw / solves * 1024 * wscale / 1e6:.2f} MB per solve")
 

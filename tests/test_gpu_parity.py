@@ -178,8 +178,9 @@ def test_normal_equation_solve_fp64(cal, oracle_mod, synth_mod, solver):
     """One LM iteration from a random state: the GPU step solves (H_GN + (rho+lambda) I) delta = -G
     with the oracle's Gauss-Newton matrix, for both Cholesky solvers (one workgroup per matrix;
     64-column panels over many workgroups) and station counts that give padded factors and
-    partial last panels (8N = 48, 72, 136, 264 columns)."""
-    for N in (6, 9, 17, 33):
+    partial last panels (8N = 48, 72, 136, 264 columns), and 8N = 528 (past the 512 columns of
+    the panel solver's register-ring back substitution: its 1024-thread back substitution)."""
+    for N in (6, 9, 17, 33, 66):
         print(f"solver {solver} N {N}", flush=True)
         cfg = tiny_cfg(synth_mod, N=N, P=2, Q=1, K=1, T=3, n_chan=2, rho=3.0, lm_iters=1)
         d = synth_mod.generate(cfg)
