@@ -68,6 +68,13 @@ struct calib_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  // LM runs under the stopping rule: each direction's run in chunks of kLmChunk iterations, one
+  // captured graph per (direction, chunk) that ends by writing whether every run has stopped; the
+  // host skips the rest of a direction once it has (those iterations would change nothing but
+  // trace rows, which one small launch writes instead)
+  int *stop_flag = nullptr;                 // pinned host memory
+  std::vector<hipGraph_t> chunk_graphs;     // [K][chunks]
+  std::vector<hipGraphExec_t> chunk_execs;
   // warm start
   double *ws_jsave = nullptr;   // [P][K][N][8]
   double *ws_cost = nullptr;    // [2][P]
@@ -164,6 +171,25 @@ int choose_group(const std::vector<int32_t> &spb, const std::vector<int32_t> &nb
   return best;
 }
 
+// one LM iteration of direction k: normal equations, solve, trial point, accept / damping
+template <typename T>
+calib_status lm_iteration(calib_ctx *c, int k, int it, int unreg, hipStream_t s) {
+  const Problem &pb = c->pb;
+  const Layout &L = c->L;
+  const Buffers &B = c->B;
+  HIPCHK(c, timed(c, CALIB_KERNEL_ASSEMBLE, [&] { return launch_assemble(pb, L, B, k, unreg, s); }));
+  HIPCHK(c, timed(c, CALIB_KERNEL_CHOL_SOLVE, [&] {
+    return pb.solver == kSolverBlocked
+               ? launch_chol_blocked(pb, B, k, c->d_ndir, B.chol_ld, B.chol_fail, s)
+               : launch_chol_solve_nd(pb, B, k, c->d_ndir, s);
+  }));
+  HIPCHK(c, timed(c, CALIB_KERNEL_TRIAL, [&] { return launch_trial<T>(pb, L, B, k, s); }));
+  HIPCHK(c, timed(c, CALIB_KERNEL_LM_UPDATE, [&] {
+    return launch_lm_update_tr(pb, L, B, k, unreg, c->lm_trace, it, c->lm_iters, s);
+  }));
+  return CALIB_OK;
+}
+
 template <typename T>
 calib_status run_local_step(calib_ctx *c, int admm_iter, hipStream_t s) {
   const int unreg = (admm_iter == 0 && (c->options & CALIB_OPT_UNREG_FIRST)) ? 1 : 0;
@@ -175,16 +201,8 @@ calib_status run_local_step(calib_ctx *c, int admm_iter, hipStream_t s) {
     for (int k = 0; k < c->K; ++k) {
       HIPCHK(c, timed(c, CALIB_KERNEL_LM_BEGIN, [&] { return launch_lm_begin(pb, L, B, k, unreg, s); }));
       for (int it = 0; it < c->lm_iters; ++it) {
-        HIPCHK(c, timed(c, CALIB_KERNEL_ASSEMBLE, [&] { return launch_assemble(pb, L, B, k, unreg, s); }));
-        HIPCHK(c, timed(c, CALIB_KERNEL_CHOL_SOLVE, [&] {
-          return pb.solver == kSolverBlocked
-                     ? launch_chol_blocked(pb, B, k, c->d_ndir, B.chol_ld, B.chol_fail, s)
-                     : launch_chol_solve_nd(pb, B, k, c->d_ndir, s);
-        }));
-        HIPCHK(c, timed(c, CALIB_KERNEL_TRIAL, [&] { return launch_trial<T>(pb, L, B, k, s); }));
-        HIPCHK(c, timed(c, CALIB_KERNEL_LM_UPDATE, [&] {
-          return launch_lm_update_tr(pb, L, B, k, unreg, c->lm_trace, it, c->lm_iters, s);
-        }));
+        const calib_status st = lm_iteration<T>(c, k, it, unreg, s);
+        if (st != CALIB_OK) return st;
       }
       HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, k, s); }));
     }
@@ -194,6 +212,91 @@ calib_status run_local_step(calib_ctx *c, int admm_iter, hipStream_t s) {
 calib_status local_step_on(calib_ctx *c, int admm_iter, hipStream_t s) {
   return c->precision == CALIB_FP64 ? run_local_step<double>(c, admm_iter, s)
                                     : run_local_step<float>(c, admm_iter, s);
+}
+
+constexpr int kLmChunk = 1;   // LM iterations between the host's looks at the stop flag
+
+// chunk ch of direction k's LM run (its first chunk opens the run), then the stop flag
+template <typename T>
+calib_status lm_chunk(calib_ctx *c, int k, int ch, int unreg, hipStream_t s) {
+  const int it0 = ch * kLmChunk, it1 = std::min(it0 + kLmChunk, c->lm_iters);
+  if (ch == 0)
+    HIPCHK(c, timed(c, CALIB_KERNEL_LM_BEGIN, [&] { return launch_lm_begin(c->pb, c->L, c->B, k, unreg, s); }));
+  for (int it = it0; it < it1; ++it) {
+    const calib_status st = lm_iteration<T>(c, k, it, unreg, s);
+    if (st != CALIB_OK) return st;
+  }
+  HIPCHK(c, launch_lm_stopped(c->pb, c->L, c->B, k, c->stop_flag, s));
+  return CALIB_OK;
+}
+
+calib_status chunk_graph(calib_ctx *c, int k, int ch, hipGraphExec_t *out) {
+  const int nch = (c->lm_iters + kLmChunk - 1) / kLmChunk;
+  const size_t idx = (size_t)k * nch + ch;
+  if (c->chunk_execs.empty()) {
+    c->chunk_graphs.assign((size_t)c->K * nch, nullptr);
+    c->chunk_execs.assign((size_t)c->K * nch, nullptr);
+  }
+  if (!c->chunk_execs[idx]) {
+    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    calib_status st = c->precision == CALIB_FP64 ? lm_chunk<double>(c, k, ch, 0, c->cap_stream)
+                                                 : lm_chunk<float>(c, k, ch, 0, c->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    if (st != CALIB_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(c, CALIB_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    c->chunk_graphs[idx] = g;
+    HIPCHK(c, hipGraphInstantiate(&c->chunk_execs[idx], g, nullptr, nullptr, 0));
+  }
+  *out = c->chunk_execs[idx];
+  return CALIB_OK;
+}
+
+// The local step under the LM stopping rule (same results as run_local_step): after each chunk
+// but the last the stream synchronises and, once every run of the direction has stopped, the
+// remaining iterations are skipped and their trace rows written.  Chunks run from captured graphs
+// (admm_iter >= 1, no kernel timing) or as direct launches.
+template <typename T>
+calib_status run_local_step_chunked(calib_ctx *c, int admm_iter, bool graphs, hipStream_t s) {
+  const int unreg = (admm_iter == 0 && (c->options & CALIB_OPT_UNREG_FIRST)) ? 1 : 0;
+  const Problem &pb = c->pb;
+  const Layout &L = c->L;
+  const Buffers &B = c->B;
+  const int nch = (c->lm_iters + kLmChunk - 1) / kLmChunk;
+  HIPCHK(c, timed(c, CALIB_KERNEL_REFRESH, [&] { return launch_refresh<T>(pb, L, B, s); }));
+  for (int sw = 0; sw < c->sage_sweeps; ++sw)
+    for (int k = 0; k < c->K; ++k) {
+      for (int ch = 0; ch < nch; ++ch) {
+        if (graphs) {
+          hipGraphExec_t ge = nullptr;
+          const calib_status st = chunk_graph(c, k, ch, &ge);
+          if (st != CALIB_OK) return st;
+          HIPCHK(c, hipGraphLaunch(ge, s));
+        } else {
+          const calib_status st = lm_chunk<T>(c, k, ch, unreg, s);
+          if (st != CALIB_OK) return st;
+        }
+        const int it1 = std::min((ch + 1) * kLmChunk, c->lm_iters);
+        if (it1 < c->lm_iters) {
+          HIPCHK(c, hipStreamSynchronize(s));
+          if (*reinterpret_cast<volatile int *>(c->stop_flag)) {
+            HIPCHK(c, launch_lm_fill_trace(pb, L, B, k, c->lm_trace, it1, c->lm_iters, s));
+            break;
+          }
+        }
+      }
+      HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, k, s); }));
+    }
+  return CALIB_OK;
+}
+
+calib_status local_step_chunked_on(calib_ctx *c, int admm_iter, bool graphs, hipStream_t s) {
+  return c->precision == CALIB_FP64 ? run_local_step_chunked<double>(c, admm_iter, graphs, s)
+                                    : run_local_step_chunked<float>(c, admm_iter, graphs, s);
 }
 
 // Lagrangian trace row, first-iteration alignment, Z, B_f Z, Y and residuals; the trace row is
@@ -237,6 +340,11 @@ const char *calib_last_error(const calib_ctx *ctx) {
 void calib_destroy(calib_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
+  for (hipGraphExec_t ge : ctx->chunk_execs)
+    if (ge) (void)hipGraphExecDestroy(ge);
+  for (hipGraph_t g : ctx->chunk_graphs)
+    if (g) (void)hipGraphDestroy(g);
+  if (ctx->stop_flag) (void)hipHostFree(ctx->stop_flag);
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
   if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -453,6 +561,12 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   DALLOC(c->ws_jsave, nj * 8);
   DALLOC(c->ws_cost, (size_t)2 * P * 8);
   DALLOC(c->lm_trace, (size_t)P * K * c->lm_iters * 3 * 8);
+  {
+    const hipError_t he = hipHostMalloc(reinterpret_cast<void **>(&c->stop_flag), sizeof(int),
+                                        hipHostMallocCoherent);
+    if (he != hipSuccess) return bail(CALIB_E_DEVICE, std::string("pinned flag: ") + hipGetErrorString(he));
+    *c->stop_flag = 0;
+  }
   int *flagbuf;
   DALLOC(flagbuf, 2 * sizeof(int));
   B.V = Vp; B.R = R; B.C = Cp; B.Sb = Sb; B.rho = d_rho; B.basis = basis; B.fitw = fitw;
@@ -514,9 +628,22 @@ calib_status admm_solve(calib_ctx *ctx, int32_t max_iters, double rel_cost_tol, 
   if (max_iters < 0 || max_iters > kMaxTrace) return fail(ctx, CALIB_E_INVAL, "max_iters out of range");
   int n = 0;
   double prev = 0.0;
+  const bool chunked = ctx->pb.lm_tol > 0.0;
   for (; n < max_iters; ++n) {
     calib_status st = CALIB_OK;
-    if (n == 0 || ctx->timing) {
+    if (chunked) {
+      const bool eager = n == 0 || ctx->timing;
+      st = local_step_chunked_on(ctx, n, !eager, ctx->stream);
+      if (st == CALIB_OK) {
+        if (eager) {
+          st = admm_consensus_update(ctx, n);
+        } else {
+          // the device counter (set by iteration 0) selects the trace row
+          st = consensus_on(ctx, false, ctx->stream);
+          ctx->iters_done = std::max(ctx->iters_done, n + 1);
+        }
+      }
+    } else if (n == 0 || ctx->timing) {
       st = admm_local_step(ctx, n);
       if (st == CALIB_OK) st = admm_consensus_update(ctx, n);
     } else {

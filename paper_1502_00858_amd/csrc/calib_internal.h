@@ -113,6 +113,10 @@ hipError_t launch_chol_blocked(const Problem &pb, const Buffers &B, int k, const
 int chol_blocked_panels(const Problem &pb);
 hipError_t launch_lm_update_tr(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
                                double *lm_trace, int it, int lm_iters, hipStream_t s);
+hipError_t launch_lm_stopped(const Problem &pb, const Layout &L, const Buffers &B, int k, int *flag,
+                             hipStream_t s);
+hipError_t launch_lm_fill_trace(const Problem &pb, const Layout &L, const Buffers &B, int k,
+                                double *lm_trace, int it_from, int lm_iters, hipStream_t s);
 
 // consensus kernels
 hipError_t launch_basis_setup(const Problem &pb, const double *freq, double f0, const int32_t *ndir,

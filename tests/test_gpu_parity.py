@@ -253,6 +253,31 @@ def test_lm_stopping_rule_fp64(cal, oracle_mod, synth_mod):
     np.testing.assert_allclose(tr[:, 1], ref[:, 1], rtol=1e-10)
 
 
+@pytest.mark.parametrize("solver", [1, 2])
+def test_stopping_rule_skip_is_exact(cal, synth_mod, solver):
+    """Under the LM stopping rule, solve() runs each direction's LM iterations in chunks and skips
+    the rest once every run has stopped (writing their trace rows); stepping the same problem with
+    local_step / consensus_update launches every iteration.  Both give identical states, objective
+    traces and LM traces, in both precisions."""
+    cfg = tiny_cfg(synth_mod, N=9, P=5, Q=2, K=3, T=3, n_chan=2, lm_iters=7, flag_frac_max=0.2)
+    d = synth_mod.generate(cfg)
+    for prec in (0, 1):
+        print(f"solver {solver} precision {prec}", flush=True)
+        a = _ctx(cal, d, prec, lm_iters=7, lm_tol=1e-6, solver=solver)
+        b = _ctx(cal, d, prec, lm_iters=7, lm_tol=1e-6, solver=solver)
+        ta = a.solve(6)
+        for n in range(6):
+            b.local_step(n)
+            b.consensus_update(n)
+        np.testing.assert_array_equal(a.get(cal.FIELD_J).cpu().numpy(), b.get(cal.FIELD_J).cpu().numpy())
+        np.testing.assert_array_equal(a.get(cal.FIELD_Y).cpu().numpy(), b.get(cal.FIELD_Y).cpu().numpy())
+        lm = b.get(cal.FIELD_LM_TRACE).cpu().numpy()
+        np.testing.assert_array_equal(a.get(cal.FIELD_LM_TRACE).cpu().numpy(), lm)
+        np.testing.assert_array_equal(ta, b.get(cal.FIELD_TRACE)[:6])
+        # runs stopped before the last iteration (the skip was taken)
+        assert np.sum(lm[..., -1, 2] == 0) > 0
+
+
 def test_solvers_agree_on_a_local_step(cal, synth_mod):
     """The two Cholesky solvers sum in different orders: whole local steps agree to rounding."""
     cfg = tiny_cfg(synth_mod, N=20, P=5, Q=2, K=3, T=3, n_chan=2, lm_iters=6, flag_frac_max=0.2)
