@@ -3,27 +3,28 @@
 // on 256 compute units).  Same augmented matrix as chol_kernel.hip (row nf holds -G^T, so the
 // factorisation also performs the forward substitution) and the same back substitution.
 //
-// Right-looking over 64-column panels p (tile columns 4p .. 4p+wp-1), one launch per panel
-// (grid: subband x (64-row chunks below the panel's diagonal block + 64x64 blocks of the trailing
-// lower triangle)):
+// Over 64-column panels p (tile columns 4p .. 4p+wp-1), one launch per panel (grid: subband x
+// (64-row chunks below the panel's diagonal block, one workgroup for the previous panel's
+// diagonal block, the block rows of the next panel's column strip)):
 //   panel workgroups hold the panel's diagonal block and their chunk of rows (a 128x64 stack) in
 //          registers, apply the pending rank-64 update of the previous panel on MFMA, and
 //          eliminate the panel's columns two at a time across the whole workgroup: the stack's
 //          values of the next two columns are published in LDS, every lane forms the 2x2 pivot
 //          block's elimination itself, the owners of the following pair update it first and
-//          publish it, one barrier per pair, the rest of the update after the barrier.  Every
-//          panel workgroup factors the diagonal block redundantly, so none waits for another; the
-//          chunk rows come out as L[I, panel] = A[I, panel] L_pp^-T.  The workgroup of chunk 0
-//          also inverts the diagonal 16x16 tiles (for the back substitution) and keeps the
-//          block's strictly-lower tiles in a side buffer (the other workgroups are still reading
-//          the block from the matrix);
-//   trailing workgroups apply the previous panel's update to the lower triangle right of the
-//          panel (right-hand-side row included): A[I,K] -= sum_t L[I,t] L[K,t]^T on
-//          v_mfma_f64_16x16x4f64.
-// Both roles read only the previous panel's L and write disjoint regions; launch boundaries order
-// the panels and nothing spins.  A 1024-thread back substitution follows.  A non-positive pivot
-// sets a per-subband flag that makes the later launches skip the subband and the back
-// substitution report chol_ok = 0 (and clear the flag).
+//          publish it, one barrier per pair, the rest of the update on MFMA inside the next pair's
+//          pivot latency.  Every panel workgroup factors the diagonal block redundantly, so none
+//          waits for another; the chunk rows come out as L[I, panel] = A[I, panel] L_pp^-T.  The
+//          workgroup of chunk 0 keeps the block's lower tiles in a side buffer (the other
+//          workgroups are still reading the block from the matrix);
+//   the diagonal-block workgroup moves the previous panel's block from the side buffer into the
+//          matrix and inverts its diagonal 16x16 tiles for the back substitution;
+//   strip workgroups bring the next panel's column strip up to date with every panel before this
+//          one (left-looking: A[I,K] -= sum_s L[I,s] L[K,s]^T on v_mfma_f64_16x16x4f64), so that
+//          the next launch only has its pending rank-64 update left.
+// All roles read only finished panels' L and write disjoint regions; launch boundaries order the
+// panels and nothing spins.  A back substitution follows.  A non-positive pivot sets a per-subband
+// flag that makes the later launches skip the subband and the back substitution report
+// chol_ok = 0 (and clear the flag).
 #include "chol_common.h"
 
 namespace calib {
@@ -50,55 +51,50 @@ __device__ inline PanelGeom panel_geom(int p, int nct) {
   return g;
 }
 
-// Trailing update of one 4x4-tile block (rb, kb) of the lower triangle that starts at tile rs:
-// A[I,K] -= sum_{t in panel src} L[I,t] L[K,t]^T; each wavefront owns 2x2 tiles and has all
-// operands of the panel in flight at once.
-__device__ __attribute__((always_inline)) inline void trail_block(double *A, int nf, int nct, int nrt, const PanelGeom &src, int rs,
-                                   int rb, int kb, int w, int lane) {
+// Left-looking update of half of one 64x64 block of panel p+1's column strip (block row rb of
+// the strip, whose first tile row and column is rs = 4(p+1); half h holds its tile rows 2h and
+// 2h+1): A[I,K] -= sum over the source panels s < nsrc of L[I,s] L[K,s]^T (panel p's own update is
+// the pending update that panel p+1's workgroups apply).  Eight wavefronts, one tile each; the
+// operands of the next two source panels are in flight while the current one's are used.
+__device__ __attribute__((always_inline)) inline void strip_half(double *A, int nf, int nct,
+                                                                 int nrt, int nsrc, int rs, int rb,
+                                                                 int h, int w, int lane) {
   const int li = lane & 15, lq = lane >> 4;
-  const int i0 = rs + kPanelTiles * rb + 2 * (w >> 1);
-  const int k0 = rs + kPanelTiles * kb + 2 * (w & 1);
-  bool valid[2][2];
-  d4 acc[2][2];
+  const int I = rs + kPanelTiles * rb + 2 * h + (w >> 2);
+  const int K = rs + (w & 3);
+  if (I >= nrt || K >= nct || K > I) return;
+  d4 acc = load_tile(A, nf, I, K, lane);
+  double x[3][kPanelTiles][4], y[3][kPanelTiles][4];
+  auto load = [&](int s, int bf) {
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int I = i0 + a, K = k0 + b;
-      valid[a][b] = I < nrt && K < nct && K <= I;
-      acc[a][b] = valid[a][b] ? load_tile(A, nf, I, K, lane) : d4{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < kPanelTiles; ++t) {
+      const int tc = (s * kPanelTiles + t) * 16 + 4 * lq;
+      load4(A + (int64_t)(I * 16 + li) * nf + tc, x[bf][t][0], x[bf][t][1], x[bf][t][2], x[bf][t][3]);
+      load4(A + (int64_t)(K * 16 + li) * nf + tc, y[bf][t][0], y[bf][t][1], y[bf][t][2], y[bf][t][3]);
     }
-  const bool rowok[2] = {i0 < nrt, i0 + 1 < nrt};
-  const bool colok[2] = {k0 < nct, k0 + 1 < nct};
-  double x[kPanelTiles][2][4], y[kPanelTiles][2][4];
+  };
+  auto mma = [&](int bf) {
 #pragma unroll
-  for (int t = 0; t < kPanelTiles; ++t) {
-    const int tc = (src.c0 + t) * 16 + 4 * lq;
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      if (t < src.wp && rowok[a]) load4(A + (int64_t)((i0 + a) * 16 + li) * nf + tc, x[t][a][0], x[t][a][1], x[t][a][2], x[t][a][3]);
-      else x[t][a][0] = x[t][a][1] = x[t][a][2] = x[t][a][3] = 0.0;
-      if (t < src.wp && colok[a]) load4(A + (int64_t)((k0 + a) * 16 + li) * nf + tc, y[t][a][0], y[t][a][1], y[t][a][2], y[t][a][3]);
-      else y[t][a][0] = y[t][a][1] = y[t][a][2] = y[t][a][3] = 0.0;
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < kPanelTiles; ++t) {
-    if (t < src.wp) {
+    for (int t = 0; t < kPanelTiles; ++t)
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq)
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[t][a][qq], y[t][b][qq], acc[a][b], 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[bf][t][qq], y[bf][t][qq], acc, 0, 0, 0);
+  };
+  load(0, 0);
+  if (nsrc > 1) load(1, 1);
+  for (int s = 0; s < nsrc; s += 3) {
+    if (s + 2 < nsrc) load(s + 2, 2);
+    mma(0);
+    if (s + 1 < nsrc) {
+      if (s + 3 < nsrc) load(s + 3, 0);
+      mma(1);
+    }
+    if (s + 2 < nsrc) {
+      if (s + 4 < nsrc) load(s + 4, 1);
+      mma(2);
     }
   }
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-      if (valid[a][b]) store_tile(A, nf, i0 + a, k0 + b, lane, acc[a][b]);
+  store_tile(A, nf, I, K, lane, acc);
 }
 
 // A panel workgroup's stack: wavefront w owns stack tile row w (0-3: the panel's diagonal block,
@@ -228,22 +224,12 @@ __device__ __attribute__((always_inline)) inline void elim_tile(Stack &acc, doub
   elim_pair<J, J + 1, true>(acc, hist, cy, 16 * J + 14, wcol, w, lane);
 }
 
-// Lower-triangle 64x64 blocks of the trailing region right of a panel: block rows rb < nrb (the
-// last may hold the right-hand-side row), block columns kb <= rb and kb < nkb.
-__host__ __device__ inline int trail_blocks(int nrb, int nkb) {
-  int n = 0;
-  for (int rb = 0; rb < nrb; ++rb) n += min(rb + 1, nkb);
-  return n;
-}
-
-// One step p of the blocked factorisation (grid: subband x (nchunk panel workgroups, for p > 0 one
-// workgroup for panel p-1's diagonal block, trailing workgroups)).  Panel workgroups
-// (blockIdx.y < nchunk, dispatched first) apply the pending
-// rank-64 update of panel p-1 to their stack (panel p's diagonal block and their chunk of rows),
-// then factor panel p.  Trailing workgroups apply the same update of panel p-1 to the lower
-// triangle right of panel p, two 64x64 blocks each (four wavefronts per block).  Both roles only
-// read panel p-1's L and write disjoint regions, so one launch per panel suffices and nothing
-// waits across workgroups.
+// One step p of the blocked factorisation (grid: subband x (nchunk panel workgroups; for p > 0 one
+// workgroup for panel p-1's diagonal block and two per block row of panel p+1's column strip)).
+// Panel workgroups (blockIdx.y < nchunk, dispatched first) apply the pending rank-64 update of
+// panel p-1 to their stack (panel p's diagonal block and their chunk of rows), then factor panel p.
+// Every role reads only finished panels and writes a region no other workgroup of the launch
+// touches, so one launch per panel suffices and nothing waits across workgroups.
 __global__ __launch_bounds__(kBThreads) void k_chol_panel(Problem pb, Buffers B, int k,
                                                           const int32_t *ndir, int p, double *Ld,
                                                           int *cfail) {
@@ -289,17 +275,11 @@ __global__ __launch_bounds__(kBThreads) void k_chol_panel(Problem pb, Buffers B,
   }
   const int side = (p > 0) ? 1 : 0;
   if ((int)blockIdx.y >= nchunk + side) {
-    // trailing role: the region right of panel p, rows and columns from tile g.c1
-    const int nrb = (nrt - g.c1 + kPanelTiles - 1) / kPanelTiles;
-    const int nkb = (nct - g.c1 + kPanelTiles - 1) / kPanelTiles;
-    int rem = 2 * ((int)blockIdx.y - nchunk - side) + (w >> 2);
-    if (rem >= trail_blocks(nrb, nkb)) return;
-    int rb = 0;
-    while (rem >= min(rb + 1, nkb)) {
-      rem -= min(rb + 1, nkb);
-      ++rb;
-    }
-    trail_block(A, nf, nct, nrt, gs, g.c1, rb, rem, w & 3, lane);
+    // strip role: panel p+1's column strip, half a 64x64 block row each, panels 0 .. p-1
+    const int rs = kPanelTiles * (p + 1);
+    const int e = (int)blockIdx.y - nchunk - side, rb = e >> 1;
+    if (p + 1 >= np || rb >= (nrt - rs + kPanelTiles - 1) / kPanelTiles) return;
+    strip_half(A, nf, nct, nrt, p, rs, rb, e & 1, w, lane);
     return;
   }
   const int q = blockIdx.y;
@@ -673,9 +653,11 @@ hipError_t launch_chol_blocked(const Problem &pb, const Buffers &B, int k, const
   for (int p = 0; p < np; ++p) {
     const int c1 = min(kPanelTiles * (p + 1), nct);
     const int nchunk = (nrt - c1 + kPanelTiles - 1) / kPanelTiles;
-    const int nrb = (nrt - c1 + kPanelTiles - 1) / kPanelTiles;
-    const int nkb = (nct - c1 + kPanelTiles - 1) / kPanelTiles;
-    const int nextra = (p > 0) ? 1 + (trail_blocks(nrb, nkb) + 1) / 2 : 0;   // side + trailing
+    // for p > 0: one workgroup for panel p-1's diagonal block, then (unless p is the last panel)
+    // two per 64x64 block row of panel p+1's column strip
+    const int rs = kPanelTiles * (p + 1);
+    const int nstrip = (p > 0 && p + 1 < np) ? 2 * ((nrt - rs + kPanelTiles - 1) / kPanelTiles) : 0;
+    const int nextra = (p > 0) ? 1 + nstrip : 0;
     hipLaunchKernelGGL(k_chol_panel, dim3(pb.P, nchunk + nextra), dim3(kBThreads), 0, s, pb, B, k,
                        ndir, p, Ld, cfail);
     const hipError_t e = hipGetLastError();
