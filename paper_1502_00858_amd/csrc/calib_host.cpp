@@ -539,6 +539,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   const size_t nj = (size_t)P * K * N * 8, nz = (size_t)K * Q * N * 8;
   DALLOC(B.J, nj * 8); DALLOC(B.Y, nj * 8); DALLOC(B.BZ, nj * 8);
   DALLOC(B.Z, nz * 8); B.Zold = nullptr;
+  DALLOC(B.Sd, (size_t)P * K * N * N * 8);
   DALLOC(B.Jstart, (size_t)P * N * 8 * 8); DALLOC(B.Jtrial, (size_t)P * N * 8 * 8);
   DALLOC(B.Dcur, (size_t)nb_total * 8 * 8); DALLOC(B.Dtrial, (size_t)nb_total * 8 * 8);
   DALLOC(B.H, (size_t)P * pb.npad * pb.nf * 8);
@@ -584,6 +585,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
               : launch_pack<float>(pb, L, vis, coh, Vp, Cp, Sb, d_ivo, d_ico, d_comp, nb_total, flagbuf, s),
           "pack") &&
       dev(launch_basis_setup(pb, d_freq, c->f0, d_ndir, basis, fitw, flagbuf + 1, s), "basis setup") &&
+      dev(launch_dense_s(pb, L, B, s), "dense S") &&
       dev(launch_zero(B.H, (int64_t)P * pb.npad * pb.nf, s), "zero H") &&
       (!B.chol_fail || dev(hipMemsetAsync(B.chol_fail, 0, (size_t)P * sizeof(int), s), "zero flags")) &&
       dev(launch_zero(B.Y, (int64_t)nj, s), "zero Y") && dev(launch_zero(B.BZ, (int64_t)nj, s), "zero BZ") &&

@@ -67,6 +67,7 @@ struct Buffers {
   void *R;         // residual V - model (stream type)
   const void *C;   // packed coherencies (stream type)
   const double *Sb;
+  double *Sd;                           // [P][K][N][N] S_b of pair (p, q) in both orders, 0 if none
   double *J, *Y, *BZ, *Z, *Zold;        // FP64 master state
   double *Jstart, *Jtrial;              // [P][N][8] active direction
   double *Dcur, *Dtrial;                // [sum nb][8]
@@ -113,6 +114,7 @@ hipError_t launch_chol_blocked(const Problem &pb, const Buffers &B, int k, const
 int chol_blocked_panels(const Problem &pb);
 hipError_t launch_lm_update_tr(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
                                double *lm_trace, int it, int lm_iters, hipStream_t s);
+hipError_t launch_dense_s(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
 hipError_t launch_lm_stopped(const Problem &pb, const Layout &L, const Buffers &B, int k, int *flag,
                              hipStream_t s);
 hipError_t launch_lm_fill_trace(const Problem &pb, const Layout &L, const Buffers &B, int k,

@@ -95,24 +95,26 @@ __global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffe
   }
   const double *J = jdir(B, pb, f, k);
   const double F = objective(pb, L, B, f, k, unreg, J, red);
-  // largest diagonal entry of H_GN + rho I: 2 sum_c S_pc (|J_c[0][j]|^2 + |J_c[1][j]|^2) + rho
-  const int nb = L.nb[f];
-  // one wavefront per station at a time, its lanes over the station's baselines
+  // largest diagonal entry of H_GN + rho I: 2 sum_c S_pc (|J_c[0][j]|^2 + |J_c[1][j]|^2) + rho,
+  // from the column norms of the stations' Jones matrices and the dense S (coalesced: thread p
+  // reads column p of each row q, S being symmetric)
+  __shared__ double nrm[2][kMaxStations];
+  for (int p = threadIdx.x; p < pb.N; p += kBlock) {
+    const double *Jp = J + 8 * p;
+    nrm[0][p] = Jp[0] * Jp[0] + Jp[1] * Jp[1] + Jp[4] * Jp[4] + Jp[5] * Jp[5];
+    nrm[1][p] = Jp[2] * Jp[2] + Jp[3] * Jp[3] + Jp[6] * Jp[6] + Jp[7] * Jp[7];
+  }
+  __syncthreads();
+  const double *Sd = B.Sd + ((int64_t)f * pb.K + k) * pb.N * pb.N;
   double dmax = 0.0;
-  const int lane = threadIdx.x & 63;
-  for (int p = threadIdx.x >> 6; p < pb.N; p += kBlock / 64) {
-    double d0 = 0.0, d1 = 0.0;
-    for (int a = L.adj_off[f * pb.N + p] + lane; a < L.adj_off[f * pb.N + p + 1]; a += 64) {
-      const int gb = L.adj_b[a];
-      const int o = L.adj_o[a] >= 0 ? L.adj_o[a] : -1 - L.adj_o[a];
-      const double S = B.Sb[L.sb_off[f] + (int64_t)k * nb + (gb - L.bl_off[f])];
-      const double *Jo = J + 8 * o;
-      d0 += S * (Jo[0] * Jo[0] + Jo[1] * Jo[1] + Jo[4] * Jo[4] + Jo[5] * Jo[5]);
-      d1 += S * (Jo[2] * Jo[2] + Jo[3] * Jo[3] + Jo[6] * Jo[6] + Jo[7] * Jo[7]);
+  for (int p = threadIdx.x; p < pb.N; p += kBlock) {
+    double d0[2] = {0.0, 0.0}, d1[2] = {0.0, 0.0};
+    for (int q = 0; q < pb.N; ++q) {
+      const double S = Sd[(int64_t)q * pb.N + p];
+      d0[q & 1] = fma(S, nrm[0][q], d0[q & 1]);
+      d1[q & 1] = fma(S, nrm[1][q], d1[q & 1]);
     }
-    d0 = wave_sum(d0);
-    d1 = wave_sum(d1);
-    dmax = fmax(dmax, 2.0 * fmax(d0, d1));
+    dmax = fmax(dmax, 2.0 * fmax(d0[0] + d0[1], d1[0] + d1[1]));
   }
   __shared__ double mx[kBlock / 64];
   dmax = wave_max(dmax);
@@ -306,6 +308,23 @@ __global__ __launch_bounds__(kBlock) void k_lm_update(Problem pb, Layout L, Buff
   }
 }
 
+// Dense S_b per (subband, direction): entry (p, q) and (q, p) of the baseline of stations p, q,
+// zero on the diagonal and for pairs without an unflagged baseline (grid: subband x direction)
+__global__ __launch_bounds__(kBlock) void k_dense_s(Problem pb, Layout L, Buffers B) {
+  const int f = blockIdx.x, k = blockIdx.y, N = pb.N;
+  double *Sd = B.Sd + ((int64_t)f * pb.K + k) * N * N;
+  const int nb = L.nb[f];
+  for (int e = threadIdx.x; e < N * N; e += kBlock) {
+    const int p = e / N, q = e % N;
+    double v = 0.0;
+    if (k < L.ndir[f] && p != q) {
+      const int gb = L.bidx[((int64_t)f * N + min(p, q)) * N + max(p, q)];
+      if (gb >= 0) v = B.Sb[L.sb_off[f] + (int64_t)k * nb + (gb - L.bl_off[f])];
+    }
+    Sd[e] = v;
+  }
+}
+
 // 1 in *flag when every subband that has direction k has stopped its LM run, else 0 (one
 // workgroup; flag is pinned host memory that the host reads after the stream synchronises)
 __global__ __launch_bounds__(kBlock) void k_lm_stopped(Problem pb, Layout L, Buffers B, int k,
@@ -332,6 +351,11 @@ __global__ __launch_bounds__(64) void k_lm_fill_trace(Problem pb, Layout L, Buff
 }
 
 }  // namespace
+
+hipError_t launch_dense_s(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_s, dim3(pb.P, pb.K), dim3(kBlock), 0, s, pb, L, B);
+  return hipGetLastError();
+}
 
 hipError_t launch_lm_stopped(const Problem &pb, const Layout &L, const Buffers &B, int k, int *flag,
                              hipStream_t s) {
