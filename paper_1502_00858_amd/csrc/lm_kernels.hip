@@ -155,9 +155,17 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Problem pb, Layout L, Buffe
       for (int c = threadIdx.x; c < nf; c += kBlock) A[(int64_t)r * nf + c] = 0.0;
     return;
   }
-  const double *J = jdir(B, pb, f, k);
+  // the direction's Jones matrices in LDS (every row below reads them)
+  __shared__ double Js[8 * kMaxStations];
+  {
+    const double *Jg = jdir(B, pb, f, k);
+    for (int e = threadIdx.x; e < 8 * N; e += kBlock) Js[e] = Jg[e];
+  }
+  __syncthreads();
+  const double *J = Js;
   const int nb = L.nb[f];
   const double *Sb = B.Sb + L.sb_off[f] + (int64_t)k * nb - L.bl_off[f];   // indexed by global gb
+  const double *Sd = B.Sd + ((int64_t)f * pb.K + k) * N * N;                 // dense, by station pair
   // Q_p (q00, q11, Re q01, Im q01) and the data part of the gradient of station p
   double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int a = L.adj_off[f * N + p] + threadIdx.x; a < L.adj_off[f * N + p + 1]; a += kBlock) {
@@ -213,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Problem pb, Layout L, Buffe
   const double q00 = qg[0], q11 = qg[1], q01r = qg[2], q01i = qg[3];
   const int ncol = 8 * p + 8;
   const double *Jp = J + 8 * p;
-  const int32_t *bidx = L.bidx + (int64_t)f * N * N;
+#pragma unroll 4
   for (int idx = threadIdx.x; idx < 8 * ncol; idx += kBlock) {
     const int v8 = idx / ncol, c = idx - v8 * ncol;
     const int iv = v8 >> 2, jv = (v8 >> 1) & 1, rv = v8 & 1;
@@ -221,17 +229,13 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Problem pb, Layout L, Buffe
     if (c < 8 * p) {
       const int a = c >> 3, u = c & 7;
       const int iu = u >> 2, ju = (u >> 1) & 1, ru = u & 1;
-      const int gb = bidx[a * N + p];
-      if (gb < 0) {
-        val = 0.0;
-      } else {
-        const double *Ja = J + 8 * a;
-        const double ar = Ja[(iu * 2 + jv) * 2], ai = Ja[(iu * 2 + jv) * 2 + 1];
-        const double br = Jp[(iv * 2 + ju) * 2], bi = Jp[(iv * 2 + ju) * 2 + 1];
-        const double wr = ar * br - ai * bi, wi = ar * bi + ai * br;
-        const double g = (ru == 0) ? (rv == 0 ? wr : wi) : (rv == 0 ? wi : -wr);
-        val = 2.0 * Sb[gb] * g;
-      }
+      // S of the pair (zero without an unflagged baseline)
+      const double *Ja = J + 8 * a;
+      const double ar = Ja[(iu * 2 + jv) * 2], ai = Ja[(iu * 2 + jv) * 2 + 1];
+      const double br = Jp[(iv * 2 + ju) * 2], bi = Jp[(iv * 2 + ju) * 2 + 1];
+      const double wr = ar * br - ai * bi, wi = ar * bi + ai * br;
+      const double g = (ru == 0) ? (rv == 0 ? wr : wi) : (rv == 0 ? wi : -wr);
+      val = 2.0 * Sd[(int64_t)a * N + p] * g;
     } else {
       const int u = c - 8 * p;
       const int iu = u >> 2, ju = (u >> 1) & 1, ru = u & 1;
@@ -303,8 +307,13 @@ __global__ __launch_bounds__(kBlock) void k_lm_update(Problem pb, Layout L, Buff
   if (acc) {
     double *J = B.J + ((int64_t)f * pb.K + k) * pb.N * 8;
     for (int e = threadIdx.x; e < 8 * pb.N; e += kBlock) J[e] = B.Jtrial[(int64_t)f * pb.N * 8 + e];
-    const int64_t b0 = 8 * (int64_t)L.bl_off[f], b1 = b0 + 8 * (int64_t)L.nb[f];
-    for (int64_t e = b0 + threadIdx.x; e < b1; e += kBlock) B.Dcur[e] = B.Dtrial[e];
+    // D_b of the accepted point: 8 doubles per baseline, two per thread per step, the loads of
+    // several steps in flight
+    const double2 *src = reinterpret_cast<const double2 *>(B.Dtrial + 8 * (int64_t)L.bl_off[f]);
+    double2 *dst = reinterpret_cast<double2 *>(B.Dcur + 8 * (int64_t)L.bl_off[f]);
+    const int n2 = 4 * L.nb[f];
+#pragma unroll 8
+    for (int e = threadIdx.x; e < n2; e += kBlock) dst[e] = src[e];
   }
 }
 
