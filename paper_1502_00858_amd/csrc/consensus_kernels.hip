@@ -205,15 +205,19 @@ __global__ __launch_bounds__(kBlock) void k_gpa(Problem pb, Layout L, Buffers B,
 }
 
 // one workgroup per direction: Z_k = W_k (J + Y/rho); dual partial ||Z_new - Z_old||^2
-__global__ __launch_bounds__(kBlock) void k_z_fit(Problem pb, Layout L, Buffers B) {
-  __shared__ double red[1][kBlock / 64];
+// One workgroup per direction, one entry of the 8N real Jones parameters per thread (N <= 128);
+// the subband loop is unrolled so that its loads overlap.
+constexpr int kZThreads = 1024;
+__global__ __launch_bounds__(kZThreads) void k_z_fit(Problem pb, Layout L, Buffers B) {
+  __shared__ double red[kZThreads / 64];
   const int k = blockIdx.x, N = pb.N, P = pb.P, Q = pb.Q;
   const double rho = B.rho[k];
   const double *W = B.fitw + (int64_t)k * Q * P;
   double dz = 0.0;
-  for (int e = threadIdx.x; e < 8 * N; e += kBlock) {
+  for (int e = threadIdx.x; e < 8 * N; e += kZThreads) {
     double z[8];
     for (int l = 0; l < Q; ++l) z[l] = 0.0;
+#pragma unroll 8
     for (int f = 0; f < P; ++f) {
       if (L.ndir[f] <= k) continue;
       const int64_t o = ((int64_t)f * pb.K + k) * N * 8 + e;
@@ -227,9 +231,14 @@ __global__ __launch_bounds__(kBlock) void k_z_fit(Problem pb, Layout L, Buffers 
       B.Z[o] = z[l];
     }
   }
-  double v[1] = {dz};
-  block_sum_vec<1>(v, red);
-  if (threadIdx.x == 0) B.scratch[(int64_t)pb.P * pb.K + k] = v[0];
+  dz = wave_sum(dz);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dz;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = 0.0;
+    for (int i = 0; i < kZThreads / 64; ++i) v += red[i];
+    B.scratch[(int64_t)pb.P * pb.K + k] = v;
+  }
 }
 
 // grid (P, K): B_f Z_k, dual ascent, primal partial ||J - BZ||^2
@@ -259,13 +268,35 @@ __global__ __launch_bounds__(kBlock) void k_y_update(Problem pb, Layout L, Buffe
 
 // averages the residual partials into the trace row of the current iteration and advances the
 // iteration counter (so that a replayed graph writes the next row)
-__global__ void k_residuals(Problem pb, Buffers B) {
-  if (threadIdx.x != 0) return;
+// Primal and dual residual norms of the trace row from the per-(subband, direction) and
+// per-direction partials: 64 threads take strided shares, summed in a fixed order.
+__global__ __launch_bounds__(64) void k_residuals(Problem pb, Buffers B) {
+  __shared__ double sps[64];
+  __shared__ int spc[64];
+  const int t = threadIdx.x;
+  double ps = 0.0;
+  int pc = 0;
+  const double pn = sqrt(4.0 * pb.N);
+  for (int64_t i = t; i < (int64_t)pb.P * pb.K; i += 64) {
+    const double x = B.scratch[i];
+    if (x >= 0.0) {
+      ps += sqrt(x) / pn;
+      ++pc;
+    }
+  }
+  sps[t] = ps;
+  spc[t] = pc;
+  __syncthreads();
+  if (t != 0) return;
+  ps = 0.0;
+  pc = 0;
+  for (int i = 0; i < 64; ++i) {
+    ps += sps[i];
+    pc += spc[i];
+  }
   const int iter = B.iter[0];
-  double ps = 0.0, ds = 0.0;
-  int pc = 0, dc = 0;
-  for (int64_t i = 0; i < (int64_t)pb.P * pb.K; ++i)
-    if (B.scratch[i] >= 0.0) { ps += sqrt(B.scratch[i]) / sqrt(4.0 * pb.N); ++pc; }
+  double ds = 0.0;
+  int dc = 0;
   for (int k = 0; k < pb.K; ++k) {
     ds += sqrt(B.scratch[(int64_t)pb.P * pb.K + k]) / sqrt(4.0 * pb.Q * pb.N);
     ++dc;
@@ -327,7 +358,7 @@ hipError_t launch_gpa(const Problem &pb, const Layout &L, const Buffers &B, int 
 }
 
 hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
-  hipLaunchKernelGGL(k_z_fit, dim3(pb.K), dim3(kBlock), 0, s, pb, L, B);
+  hipLaunchKernelGGL(k_z_fit, dim3(pb.K), dim3(kZThreads), 0, s, pb, L, B);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_y_update, dim3(pb.P, pb.K), dim3(kBlock), 0, s, pb, L, B);
