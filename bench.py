@@ -47,8 +47,8 @@ FP64_PEAK_TFS = 78.6
 MEASURED_TRAFFIC = {
     ("chol_solve", "c2", "blocked"): (
         ("paper_1502_00858_amd/csrc/chol_blocked.hip", "paper_1502_00858_amd/csrc/chol_common.h"),
-        "fd342625a7b1e884633703c13a70e2a586d7e2d5528fb929c61115ecc7633255",
-        (153.56 + 87.81) * 1e6),
+        "d39eef5f9a663ecbc0a6f532fb25b078950bf9d406d4aa7c6044c0e59a77683b",
+        (160.84 + 58.98) * 1e6),
 }
 
 
