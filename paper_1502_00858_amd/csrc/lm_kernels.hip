@@ -155,31 +155,42 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Problem pb, Layout L, Buffe
       for (int c = threadIdx.x; c < nf; c += kBlock) A[(int64_t)r * nf + c] = 0.0;
     return;
   }
-  // the direction's Jones matrices in LDS (every row below reads them)
+  // the direction's Jones matrices and S of station p's pairs (row p of the dense table) in LDS:
+  // everything below reads them
   __shared__ double Js[8 * kMaxStations];
+  __shared__ double Sp[kMaxStations];
   {
     const double *Jg = jdir(B, pb, f, k);
+    const double *Sd = B.Sd + (((int64_t)f * pb.K + k) * N + p) * N;
     for (int e = threadIdx.x; e < 8 * N; e += kBlock) Js[e] = Jg[e];
+    for (int e = threadIdx.x; e < N; e += kBlock) Sp[e] = Sd[e];
   }
   __syncthreads();
   const double *J = Js;
-  const int nb = L.nb[f];
-  const double *Sb = B.Sb + L.sb_off[f] + (int64_t)k * nb - L.bl_off[f];   // indexed by global gb
-  const double *Sd = B.Sd + ((int64_t)f * pb.K + k) * N * N;                 // dense, by station pair
   // Q_p (q00, q11, Re q01, Im q01) and the data part of the gradient of station p
   double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int a = L.adj_off[f * N + p] + threadIdx.x; a < L.adj_off[f * N + p + 1]; a += kBlock) {
     const int gb = L.adj_b[a];
     const bool first = L.adj_o[a] >= 0;
     const int o = first ? L.adj_o[a] : -1 - L.adj_o[a];
-    const double S = Sb[gb];
+    const double S = Sp[o];
     const double *Jo = J + 8 * o;
     v[0] += S * (Jo[0] * Jo[0] + Jo[1] * Jo[1] + Jo[4] * Jo[4] + Jo[5] * Jo[5]);
     v[1] += S * (Jo[2] * Jo[2] + Jo[3] * Jo[3] + Jo[6] * Jo[6] + Jo[7] * Jo[7]);
     // (J^H J)[0][1] = conj(J00) J01 + conj(J10) J11
     v[2] += S * (Jo[0] * Jo[2] + Jo[1] * Jo[3] + Jo[4] * Jo[6] + Jo[5] * Jo[7]);
     v[3] += S * (Jo[0] * Jo[3] - Jo[1] * Jo[2] + Jo[4] * Jo[7] - Jo[5] * Jo[6]);
-    const double *D = B.Dcur + 8 * (int64_t)gb;
+    // D_b (8 doubles) loaded whole before either orientation is used: no load behind a branch
+    double d[8];
+    {
+      const double2 *D2 = reinterpret_cast<const double2 *>(B.Dcur + 8 * (int64_t)gb);
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const double2 x = D2[h];
+        d[2 * h] = x.x;
+        d[2 * h + 1] = x.y;
+      }
+    }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -187,17 +198,13 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Problem pb, Layout L, Buffe
         double re = 0.0, im = 0.0;
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-          if (first) {   // (D J_o)[i][j] = sum_t D[i][t] J_o[t][j]
-            const double dr = D[(i * 2 + t) * 2], di = D[(i * 2 + t) * 2 + 1];
-            const double jr = Jo[(t * 2 + j) * 2], ji = Jo[(t * 2 + j) * 2 + 1];
-            re += dr * jr - di * ji;
-            im += dr * ji + di * jr;
-          } else {       // (D^H J_o)[i][j] = sum_t conj(D[t][i]) J_o[t][j]
-            const double dr = D[(t * 2 + i) * 2], di = -D[(t * 2 + i) * 2 + 1];
-            const double jr = Jo[(t * 2 + j) * 2], ji = Jo[(t * 2 + j) * 2 + 1];
-            re += dr * jr - di * ji;
-            im += dr * ji + di * jr;
-          }
+          // first: (D J_o)[i][j] = sum_t D[i][t] J_o[t][j];
+          // second: (D^H J_o)[i][j] = sum_t conj(D[t][i]) J_o[t][j]
+          const double dr = first ? d[(i * 2 + t) * 2] : d[(t * 2 + i) * 2];
+          const double di = first ? d[(i * 2 + t) * 2 + 1] : -d[(t * 2 + i) * 2 + 1];
+          const double jr = Jo[(t * 2 + j) * 2], ji = Jo[(t * 2 + j) * 2 + 1];
+          re += dr * jr - di * ji;
+          im += dr * ji + di * jr;
         }
         v[4 + (i * 2 + j) * 2] += -2.0 * re;
         v[4 + (i * 2 + j) * 2 + 1] += -2.0 * im;
@@ -221,37 +228,38 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Problem pb, Layout L, Buffe
   const double q00 = qg[0], q11 = qg[1], q01r = qg[2], q01i = qg[3];
   const int ncol = 8 * p + 8;
   const double *Jp = J + 8 * p;
+  // 32 threads per row v of station p's 8 rows, stepping through its columns (coalesced stores,
+  // no division)
+  static_assert(kBlock == 8 * 32, "one row per 32 threads");
+  const int v8 = threadIdx.x >> 5, l32 = threadIdx.x & 31;
+  const int iv = v8 >> 2, jv = (v8 >> 1) & 1, rv = v8 & 1;
+  double *row = A + (int64_t)(8 * p + v8) * nf;
 #pragma unroll 4
-  for (int idx = threadIdx.x; idx < 8 * ncol; idx += kBlock) {
-    const int v8 = idx / ncol, c = idx - v8 * ncol;
-    const int iv = v8 >> 2, jv = (v8 >> 1) & 1, rv = v8 & 1;
+  for (int c = l32; c < ncol; c += 32) {
     double val;
+    const int u = c & 7;
+    const int iu = u >> 2, ju = (u >> 1) & 1, ru = u & 1;
     if (c < 8 * p) {
-      const int a = c >> 3, u = c & 7;
-      const int iu = u >> 2, ju = (u >> 1) & 1, ru = u & 1;
-      // S of the pair (zero without an unflagged baseline)
+      // baseline (a, p): S of the pair (zero without an unflagged baseline)
+      const int a = c >> 3;
       const double *Ja = J + 8 * a;
       const double ar = Ja[(iu * 2 + jv) * 2], ai = Ja[(iu * 2 + jv) * 2 + 1];
       const double br = Jp[(iv * 2 + ju) * 2], bi = Jp[(iv * 2 + ju) * 2 + 1];
       const double wr = ar * br - ai * bi, wi = ar * bi + ai * br;
       const double g = (ru == 0) ? (rv == 0 ? wr : wi) : (rv == 0 ? wi : -wr);
-      val = 2.0 * Sd[(int64_t)a * N + p] * g;
+      val = 2.0 * Sp[a] * g;
+    } else if (iu != iv) {
+      val = 0.0;
     } else {
-      const int u = c - 8 * p;
-      const int iu = u >> 2, ju = (u >> 1) & 1, ru = u & 1;
-      if (iu != iv) {
-        val = 0.0;
-      } else {
-        // g' = Q[jv][ju] (row index v, column index u)
-        double gr, gi;
-        if (jv == ju) { gr = (jv == 0) ? q00 : q11; gi = 0.0; }
-        else if (jv == 0) { gr = q01r; gi = q01i; }      // Q[0][1]
-        else { gr = q01r; gi = -q01i; }                  // Q[1][0] = conj(Q[0][1])
-        val = 2.0 * ((rv == 0) ? (ru == 0 ? gr : gi) : (ru == 0 ? -gi : gr));
-        if (u == v8) val += rho + lam;
-      }
+      // g' = Q[jv][ju] (row index v, column index u)
+      double gr, gi;
+      if (jv == ju) { gr = (jv == 0) ? q00 : q11; gi = 0.0; }
+      else if (jv == 0) { gr = q01r; gi = q01i; }      // Q[0][1]
+      else { gr = q01r; gi = -q01i; }                  // Q[1][0] = conj(Q[0][1])
+      val = 2.0 * ((rv == 0) ? (ru == 0 ? gr : gi) : (ru == 0 ? -gi : gr));
+      if (u == v8) val += rho + lam;
     }
-    A[(int64_t)(8 * p + v8) * nf + c] = val;
+    row[c] = val;
   }
 }
 
