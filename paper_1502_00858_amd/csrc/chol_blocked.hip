@@ -54,47 +54,65 @@ __device__ inline PanelGeom panel_geom(int p, int nct) {
 // Left-looking update of half of one 64x64 block of panel p+1's column strip (block row rb of
 // the strip, whose first tile row and column is rs = 4(p+1); half h holds its tile rows 2h and
 // 2h+1): A[I,K] -= sum over the source panels s < nsrc of L[I,s] L[K,s]^T (panel p's own update is
-// the pending update that panel p+1's workgroups apply).  Eight wavefronts, one tile each; the
-// operands of the next two source panels are in flight while the current one's are used.
-__device__ __attribute__((always_inline)) inline void strip_half(double *A, int nf, int nct,
-                                                                 int nrt, int nsrc, int rs, int rb,
-                                                                 int h, int w, int lane) {
-  const int li = lane & 15, lq = lane >> 4;
-  const int I = rs + kPanelTiles * rb + 2 * h + (w >> 2);
-  const int K = rs + (w & 3);
-  if (I >= nrt || K >= nct || K > I) return;
-  d4 acc = load_tile(A, nf, I, K, lane);
-  double x[3][kPanelTiles][4], y[3][kPanelTiles][4];
-  auto load = [&](int s, int bf) {
+// the pending update that panel p+1's workgroups apply).  Eight wavefronts, one tile each.  Per
+// source panel the workgroup stages the operands it needs once in LDS (L at its 2 tile rows and at
+// the strip's 4 tile columns: 48 KB, where eight wavefronts loading their own would move 128 KB
+// through the compute unit), the next panel's operands in flight in registers while the current
+// one's are multiplied.  Four accumulators per tile keep consecutive products independent.
+__device__ inline double2 lds2(const double *p) { return *reinterpret_cast<const double2 *>(p); }
+constexpr int kSRows = 6 * 16;   // staged rows: 2 tile rows of the block half + 4 of the strip
+__device__ __attribute__((always_inline)) inline void strip_half(double *A, double *lds, int nf,
+                                                                 int nct, int nrt, int nsrc, int rs,
+                                                                 int rb, int h, int w, int lane) {
+  const int li = lane & 15, lq = lane >> 4, tid = threadIdx.x;
+  const int I0 = rs + kPanelTiles * rb + 2 * h;
+  const int I = I0 + (w >> 2), K = rs + (w & 3);
+  const bool valid = I < nrt && K < nct && K <= I;
+  d4 acc[4] = {valid ? load_tile(A, nf, I, K, lane) : d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0},
+               d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
+  // thread tid stages elements e = 2 tid + 2 kBThreads it (pairs of columns) of the 96 x 64 operand
+  // block: rows 0-31 the block half's tile rows, rows 32-95 the strip's tile rows
+  constexpr int kPer = kSRows * kPB / (2 * kBThreads);
+  double2 reg[kPer];
+  auto load = [&](int s) {
 #pragma unroll
-    for (int t = 0; t < kPanelTiles; ++t) {
-      const int tc = (s * kPanelTiles + t) * 16 + 4 * lq;
-      load4(A + (int64_t)(I * 16 + li) * nf + tc, x[bf][t][0], x[bf][t][1], x[bf][t][2], x[bf][t][3]);
-      load4(A + (int64_t)(K * 16 + li) * nf + tc, y[bf][t][0], y[bf][t][1], y[bf][t][2], y[bf][t][3]);
+    for (int it = 0; it < kPer; ++it) {
+      const int e = 2 * tid + 2 * kBThreads * it, r = e >> 6, col = e & 63;
+      const int tr = (r < 32) ? I0 + (r >> 4) : rs + ((r - 32) >> 4);   // tile row
+      const int grow = (r < 32) ? 16 * I0 + r : 16 * rs + (r - 32);
+      const bool ok = (r < 32) ? tr < nrt : tr < nct;
+      reg[it] = ok ? *reinterpret_cast<const double2 *>(A + (int64_t)grow * nf + s * kPB + col)
+                   : double2{0.0, 0.0};
     }
   };
-  auto mma = [&](int bf) {
+  auto stage = [&]() {
 #pragma unroll
-    for (int t = 0; t < kPanelTiles; ++t)
-#pragma unroll
-      for (int qq = 0; qq < 4; ++qq)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-x[bf][t][qq], y[bf][t][qq], acc, 0, 0, 0);
+    for (int it = 0; it < kPer; ++it) {
+      const int e = 2 * tid + 2 * kBThreads * it, r = e >> 6, col = e & 63;
+      *reinterpret_cast<double2 *>(lds + r * kPs + col) = reg[it];
+    }
   };
-  load(0, 0);
-  if (nsrc > 1) load(1, 1);
-  for (int s = 0; s < nsrc; s += 3) {
-    if (s + 2 < nsrc) load(s + 2, 2);
-    mma(0);
-    if (s + 1 < nsrc) {
-      if (s + 3 < nsrc) load(s + 3, 0);
-      mma(1);
+  const double *xr = lds + (16 * (w >> 2) + li) * kPs + 4 * lq;
+  const double *yr = lds + (32 + 16 * (w & 3) + li) * kPs + 4 * lq;
+  load(0);
+  for (int s = 0; s < nsrc; ++s) {
+    stage();
+    __syncthreads();
+    if (s + 1 < nsrc) load(s + 1);
+    if (valid) {
+#pragma unroll
+      for (int t = 0; t < kPanelTiles; ++t) {
+        const double2 a0 = lds2(xr + 16 * t), a1 = lds2(xr + 16 * t + 2);
+        const double2 b0 = lds2(yr + 16 * t), b1 = lds2(yr + 16 * t + 2);
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0.x, b0.x, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a0.y, b0.y, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1.x, b1.x, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a1.y, b1.y, acc[3], 0, 0, 0);
+      }
     }
-    if (s + 2 < nsrc) {
-      if (s + 4 < nsrc) load(s + 4, 1);
-      mma(2);
-    }
+    __syncthreads();
   }
-  store_tile(A, nf, I, K, lane, acc);
+  if (valid) store_tile(A, nf, I, K, lane, (acc[0] + acc[1]) + (acc[2] + acc[3]));
 }
 
 // A panel workgroup's stack: wavefront w owns stack tile row w (0-3: the panel's diagonal block,
@@ -104,8 +122,6 @@ __device__ __attribute__((always_inline)) inline void strip_half(double *A, int 
 typedef d4 Stack[kPanelTiles];
 
 __device__ inline int stack_row(int w, int r, int lq) { return 16 * w + 4 * r + lq; }
-
-__device__ inline double2 lds2(const double *p) { return *reinterpret_cast<const double2 *>(p); }
 
 // 1/d: the v_rcp_f64 estimate (relative error below 2^-24) refined by one third-order step
 // y (1 + e + e^2), e = 1 - d y, which cubes the relative error.
@@ -279,7 +295,7 @@ __global__ __launch_bounds__(kBThreads) void k_chol_panel(Problem pb, Buffers B,
     const int rs = kPanelTiles * (p + 1);
     const int e = (int)blockIdx.y - nchunk - side, rb = e >> 1;
     if (p + 1 >= np || rb >= (nrt - rs + kPanelTiles - 1) / kPanelTiles) return;
-    strip_half(A, nf, nct, nrt, p, rs, rb, e & 1, w, lane);
+    strip_half(A, lds, nf, nct, nrt, p, rs, rb, e & 1, w, lane);
     return;
   }
   const int q = blockIdx.y;
