@@ -131,17 +131,18 @@ __device__ inline double rcp3(double d) {
   return fma(y, fma(e, e, e), y);
 }
 
-// What a pair's elimination leaves for the next step: this lane's v_mfma operands of the pair's
-// rank-2 update of the tile columns right of its priority tile (A: the pair's column k = l/16 at
-// stack row 16w + l%16, zero for k > 1; B, formed in the next step: row k of
-// M^-1 [a[j][c] a[j][c+1]]^T at column j = 16J + l%16, from the carried coefficients al, be and
-// the pair's values v0, v1 at row j).
+// What the eliminations of two consecutive pairs leave for the next odd step: this lane's
+// v_mfma operands of their rank-2 updates of the tile columns right of their priority tiles, the
+// pair of an even step in lanes l < 32 (k = 0, 1), the pair of an odd step in lanes l >= 32
+// (k = 2, 3), so one product applies both.  A: the pair's column k & 1 at stack row 16w + l%16;
+// B, formed when the product is issued: row k & 1 of M^-1 [a[j][c] a[j][c+1]]^T at column
+// j = 16J + l%16, from the carried coefficients al, be and the pair's values v0, v1 at row j.
 struct PairCarry {
   double aval, al, be, v0[kPanelTiles], v1[kPanelTiles];
 };
 
-// The pair's update of tile columns JD.. on v_mfma_f64_16x16x4f64 (k = 0, 1 carry the pair; the
-// tile columns past the panel's width hold padding that is never read).  The empty asm emits
+// The two carried pairs' update of tile columns JD.. on v_mfma_f64_16x16x4f64 (the tile columns
+// past the panel's width hold padding that is never read).  The empty asm emits
 // nothing; it keeps the products ahead of the publication that follows in the same step.
 template <int JD>
 __device__ __attribute__((always_inline)) inline void pair_rest(Stack &acc, const PairCarry &cy) {
@@ -162,14 +163,17 @@ __device__ __attribute__((always_inline)) inline void pair_rest(Stack &acc, cons
 //     a[i][j] -= [a[i][c] a[i][c+1]] M^-1 [a[j][c] a[j][c+1]]^T
 //              = (a[i][c] (a11 a[j][c] - a10 a[j][c+1]) + a[i][c+1] (a00 a[j][c+1] - a10 a[j][c])) / d,
 // and every lane forms it from hist itself.  The step: this pair's reads, d and the hardware
-// estimate of 1/d, the previous pair's update of the tile columns right of J on MFMA (independent
-// of this pair's pivots, it runs inside the estimate's latency), the refinement of 1/d, this
-// pair's update of tile JP on the vector unit and the publication of the pair c+2, c+3, the
-// carry, the barrier (sched_barrier keeps the compiler from interleaving the groups otherwise).
+// estimate of 1/d, on odd steps (kOdd: the second pair of a tile column's four column groups) the
+// two previous pairs' update of the tile columns right of J on MFMA (independent of this pair's
+// pivots, it runs inside the estimate's latency), the refinement of 1/d, this pair's update of
+// tile JP on the vector unit and the publication of the pair c+2, c+3, the carry, the barrier
+// (sched_barrier keeps the compiler from interleaving the groups otherwise).  Deferred updates
+// commute with the vector unit's; every pair reaches tile J+1 before its first column is published
+// (the last, odd, step of tile column J applies the pending two).
 // Columns stay unscaled: L is formed from hist after the last pair.  Entries above the diagonal
 // block's diagonal are carried along and never read; finished columns are left alone (their
 // lanes add zero).
-template <int J, int JP, bool kPrev>
+template <int J, int JP, bool kOdd>
 __device__ __attribute__((always_inline)) inline void elim_pair(Stack &acc, double *hist,
                                                                 PairCarry &cy, int c, int wcol,
                                                                 int w, int lane) {
@@ -202,7 +206,7 @@ __device__ __attribute__((always_inline)) inline void elim_pair(Stack &acc, doub
   double y0 = __builtin_amdgcn_rcp(det);
   __asm__ __volatile__("" : "+v"(y0));
   __builtin_amdgcn_sched_barrier(0);
-  if constexpr (kPrev) pair_rest<J + 1>(acc, cy);
+  if constexpr (kOdd) pair_rest<J + 1>(acc, cy);
   __builtin_amdgcn_sched_barrier(0);
   const double e0 = fma(-det, y0, 1.0);
   const double rdet = fma(y0, fma(e0, e0, e0), y0);   // third-order refinement, as in rcp3
@@ -218,25 +222,30 @@ __device__ __attribute__((always_inline)) inline void elim_pair(Stack &acc, doub
       for (int r = 0; r < 4; ++r) cn[2 * stack_row(w, r, lq) + (li - cc)] = acc[JP][r];
     }
   }
-  cy.aval = lq < 2 ? arow : 0.0;
-  cy.al = (lq == 0 ? a11 : (lq == 1 ? -a10 : 0.0)) * rdet;
-  cy.be = (lq == 0 ? -a10 : (lq == 1 ? a00 : 0.0)) * rdet;
+  const bool mine = kOdd ? lq >= 2 : lq < 2;
+  const double al = ((lq & 1) == 0 ? a11 : -a10) * rdet, be = ((lq & 1) == 0 ? -a10 : a00) * rdet;
+  cy.aval = mine ? arow : cy.aval;
+  cy.al = mine ? al : cy.al;
+  cy.be = mine ? be : cy.be;
 #pragma unroll
   for (int j2 = 0; j2 < kPanelTiles; ++j2) {
-    cy.v0[j2] = v0[j2];
-    cy.v1[j2] = v1[j2];
+    cy.v0[j2] = mine ? v0[j2] : cy.v0[j2];
+    cy.v1[j2] = mine ? v1[j2] : cy.v1[j2];
   }
   __syncthreads();
 }
 
-// The eight column pairs of tile column J
+// The eight column pairs of tile column J, even and odd steps alternating
 template <int J>
 __device__ __attribute__((always_inline)) inline void elim_tile(Stack &acc, double *hist,
                                                                 PairCarry &cy, int wcol, int w,
                                                                 int lane) {
-  elim_pair<J, J, (J > 0)>(acc, hist, cy, 16 * J, wcol, w, lane);
 #pragma unroll 1
-  for (int s = 1; s < 7; ++s) elim_pair<J, J, true>(acc, hist, cy, 16 * J + 2 * s, wcol, w, lane);
+  for (int s = 0; s < 6; s += 2) {
+    elim_pair<J, J, false>(acc, hist, cy, 16 * J + 2 * s, wcol, w, lane);
+    elim_pair<J, J, true>(acc, hist, cy, 16 * J + 2 * s + 2, wcol, w, lane);
+  }
+  elim_pair<J, J, false>(acc, hist, cy, 16 * J + 12, wcol, w, lane);
   elim_pair<J, J + 1, true>(acc, hist, cy, 16 * J + 14, wcol, w, lane);
 }
 
@@ -368,7 +377,7 @@ __global__ __launch_bounds__(kBThreads) void k_chol_panel(Problem pb, Buffers B,
     for (int r = 0; r < 4; ++r) hist[2 * stack_row(w, r, lq) + li] = acc[0][r];
   }
   __syncthreads();
-  PairCarry cy;
+  PairCarry cy{};   // the odd slot holds no pair before the first odd step: it adds zero
   elim_tile<0>(acc, hist, cy, wcol, w, lane);
   if (wp > 1) elim_tile<1>(acc, hist, cy, wcol, w, lane);
   if (wp > 2) elim_tile<2>(acc, hist, cy, wcol, w, lane);
