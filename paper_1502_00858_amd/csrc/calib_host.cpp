@@ -5,6 +5,7 @@
 #include "calib_internal.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -216,17 +217,24 @@ calib_status local_step_on(calib_ctx *c, int admm_iter, hipStream_t s) {
 
 constexpr int kLmChunk = 1;   // LM iterations between the host's looks at the stop flag
 
-// chunk ch of direction k's LM run (its first chunk opens the run), then the stop flag
+// Chunk ch of direction k's LM run.  Its first chunk opens the run, after the commit of the
+// previous direction when k > 0 (the stream order of run_local_step: commit k-1, begin k).  Every
+// chunk but the last ends with the stop flag (and, once every run has stopped, the trace rows of
+// the iterations that will not be launched).
 template <typename T>
 calib_status lm_chunk(calib_ctx *c, int k, int ch, int unreg, hipStream_t s) {
   const int it0 = ch * kLmChunk, it1 = std::min(it0 + kLmChunk, c->lm_iters);
-  if (ch == 0)
+  if (ch == 0) {
+    if (k > 0)
+      HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(c->pb, c->L, c->B, k - 1, s); }));
     HIPCHK(c, timed(c, CALIB_KERNEL_LM_BEGIN, [&] { return launch_lm_begin(c->pb, c->L, c->B, k, unreg, s); }));
+  }
   for (int it = it0; it < it1; ++it) {
     const calib_status st = lm_iteration<T>(c, k, it, unreg, s);
     if (st != CALIB_OK) return st;
   }
-  HIPCHK(c, launch_lm_stopped(c->pb, c->L, c->B, k, c->stop_flag, s));
+  if (it1 < c->lm_iters)
+    HIPCHK(c, launch_lm_stopped(c->pb, c->L, c->B, k, c->stop_flag, c->lm_trace, it1, c->lm_iters, s));
   return CALIB_OK;
 }
 
@@ -256,10 +264,30 @@ calib_status chunk_graph(calib_ctx *c, int k, int ch, hipGraphExec_t *out) {
   return CALIB_OK;
 }
 
+// The stop flag of the chunk just enqueued: the stopped kernel overwrites the -1 the host left in
+// the pinned word with 0 (running) or 1 (stopped).  The host spins on it, so the next launch
+// follows the flag within microseconds; after 50 ms it synchronises the stream instead, which also
+// reports a device error.
+calib_status wait_stop_flag(calib_ctx *c, hipStream_t s, bool *stopped) {
+  volatile int *fl = c->stop_flag;
+  const auto t0 = std::chrono::steady_clock::now();
+  int v;
+  while ((v = *fl) < 0) {
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50)) {
+      HIPCHK(c, hipStreamSynchronize(s));
+      v = *fl;
+      if (v < 0) return fail(c, CALIB_E_DEVICE, "the LM stop flag was not written");
+      break;
+    }
+  }
+  *stopped = v == 1;
+  return CALIB_OK;
+}
+
 // The local step under the LM stopping rule (same results as run_local_step): after each chunk
-// but the last the stream synchronises and, once every run of the direction has stopped, the
-// remaining iterations are skipped and their trace rows written.  Chunks run from captured graphs
-// (admm_iter >= 1, no kernel timing) or as direct launches.
+// but the last the host reads the stop flag and, once every run of the direction has stopped,
+// launches none of the remaining iterations.  Chunks run from captured graphs (admm_iter >= 1, no
+// kernel timing) or as direct launches.
 template <typename T>
 calib_status run_local_step_chunked(calib_ctx *c, int admm_iter, bool graphs, hipStream_t s) {
   const int unreg = (admm_iter == 0 && (c->options & CALIB_OPT_UNREG_FIRST)) ? 1 : 0;
@@ -270,7 +298,11 @@ calib_status run_local_step_chunked(calib_ctx *c, int admm_iter, bool graphs, hi
   HIPCHK(c, timed(c, CALIB_KERNEL_REFRESH, [&] { return launch_refresh<T>(pb, L, B, s); }));
   for (int sw = 0; sw < c->sage_sweeps; ++sw)
     for (int k = 0; k < c->K; ++k) {
+      if (k == 0 && sw > 0)
+        HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, c->K - 1, s); }));
       for (int ch = 0; ch < nch; ++ch) {
+        const bool checked = std::min((ch + 1) * kLmChunk, c->lm_iters) < c->lm_iters;
+        if (checked) *reinterpret_cast<volatile int *>(c->stop_flag) = -1;
         if (graphs) {
           hipGraphExec_t ge = nullptr;
           const calib_status st = chunk_graph(c, k, ch, &ge);
@@ -280,17 +312,15 @@ calib_status run_local_step_chunked(calib_ctx *c, int admm_iter, bool graphs, hi
           const calib_status st = lm_chunk<T>(c, k, ch, unreg, s);
           if (st != CALIB_OK) return st;
         }
-        const int it1 = std::min((ch + 1) * kLmChunk, c->lm_iters);
-        if (it1 < c->lm_iters) {
-          HIPCHK(c, hipStreamSynchronize(s));
-          if (*reinterpret_cast<volatile int *>(c->stop_flag)) {
-            HIPCHK(c, launch_lm_fill_trace(pb, L, B, k, c->lm_trace, it1, c->lm_iters, s));
-            break;
-          }
+        if (checked) {
+          bool stopped = false;
+          const calib_status st = wait_stop_flag(c, s, &stopped);
+          if (st != CALIB_OK) return st;
+          if (stopped) break;
         }
       }
-      HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, k, s); }));
     }
+  HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, c->K - 1, s); }));
   return CALIB_OK;
 }
 

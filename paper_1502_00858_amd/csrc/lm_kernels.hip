@@ -344,27 +344,29 @@ __global__ __launch_bounds__(kBlock) void k_dense_s(Problem pb, Layout L, Buffer
 
 // 1 in *flag when every subband that has direction k has stopped its LM run, else 0 (one
 // workgroup; flag is pinned host memory that the host reads after the stream synchronises)
+// Whether direction k's LM run has stopped on every subband that carries it (*flag = 1, else 0).
+// Once it has, the iterations it_from .. lm_iters-1 will not be launched: their trace rows get what
+// the update launches of those iterations would write (the final objective and damping, not
+// accepted).
 __global__ __launch_bounds__(kBlock) void k_lm_stopped(Problem pb, Layout L, Buffers B, int k,
-                                                       int *flag) {
+                                                       int *flag, double *lm_trace, int it_from,
+                                                       int lm_iters) {
   int running = 0;
   for (int f = threadIdx.x; f < pb.P; f += kBlock) running |= (k < L.ndir[f] && !B.lm[f].done) ? 1 : 0;
   running = __syncthreads_or(running);
-  if (threadIdx.x == 0) *flag = running ? 0 : 1;
-}
-
-// Trace rows it_from .. lm_iters-1 of direction k once every run has stopped: what the update
-// launches of those iterations write (the final objective and damping, not accepted)
-__global__ __launch_bounds__(64) void k_lm_fill_trace(Problem pb, Layout L, Buffers B, int k,
-                                                      double *lm_trace, int it_from, int lm_iters) {
-  const int f = blockIdx.x;
-  if (k >= L.ndir[f]) return;
-  const LmState *st = B.lm + f;
-  for (int it = it_from + threadIdx.x; it < lm_iters; it += 64) {
-    double *tr = lm_trace + 3 * ((int64_t)(f * pb.K + k) * lm_iters + it);
-    tr[0] = st->F;
-    tr[1] = st->lambda;
-    tr[2] = 0;
+  const int nrem = lm_iters - it_from;
+  if (!running && lm_trace && nrem > 0) {
+    for (int e = threadIdx.x; e < pb.P * nrem; e += kBlock) {
+      const int f = e / nrem, it = it_from + e % nrem;
+      if (k >= L.ndir[f]) continue;
+      const LmState *st = B.lm + f;
+      double *tr = lm_trace + 3 * ((int64_t)(f * pb.K + k) * lm_iters + it);
+      tr[0] = st->F;
+      tr[1] = st->lambda;
+      tr[2] = 0;
+    }
   }
+  if (threadIdx.x == 0) *flag = running ? 0 : 1;
 }
 
 }  // namespace
@@ -375,15 +377,8 @@ hipError_t launch_dense_s(const Problem &pb, const Layout &L, const Buffers &B, 
 }
 
 hipError_t launch_lm_stopped(const Problem &pb, const Layout &L, const Buffers &B, int k, int *flag,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_lm_stopped, dim3(1), dim3(kBlock), 0, s, pb, L, B, k, flag);
-  return hipGetLastError();
-}
-
-hipError_t launch_lm_fill_trace(const Problem &pb, const Layout &L, const Buffers &B, int k,
-                                double *lm_trace, int it_from, int lm_iters, hipStream_t s) {
-  if (!lm_trace || it_from >= lm_iters) return hipSuccess;
-  hipLaunchKernelGGL(k_lm_fill_trace, dim3(pb.P), dim3(64), 0, s, pb, L, B, k, lm_trace, it_from,
+                             double *lm_trace, int it_from, int lm_iters, hipStream_t s) {
+  hipLaunchKernelGGL(k_lm_stopped, dim3(1), dim3(kBlock), 0, s, pb, L, B, k, flag, lm_trace, it_from,
                      lm_iters);
   return hipGetLastError();
 }
