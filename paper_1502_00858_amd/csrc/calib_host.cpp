@@ -571,7 +571,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   DALLOC(B.Z, nz * 8); B.Zold = nullptr;
   DALLOC(B.Sd, (size_t)P * K * N * N * 8);
   DALLOC(B.Jstart, (size_t)P * N * 8 * 8); DALLOC(B.Jtrial, (size_t)P * N * 8 * 8);
-  DALLOC(B.Dcur, (size_t)nb_total * 8 * 8); DALLOC(B.Dtrial, (size_t)nb_total * 8 * 8);
+  DALLOC(B.D0, (size_t)nb_total * 8 * 8); DALLOC(B.D1, (size_t)nb_total * 8 * 8);
   DALLOC(B.H, (size_t)P * pb.npad * pb.nf * 8);
   DALLOC(B.Linv, (size_t)P * (pb.nf / 16) * 256 * 8);
   DALLOC(B.G, (size_t)P * pb.nf * 8); DALLOC(B.delta, (size_t)P * pb.nf * 8);
@@ -617,6 +617,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
       dev(launch_basis_setup(pb, d_freq, c->f0, d_ndir, basis, fitw, flagbuf + 1, s), "basis setup") &&
       dev(launch_dense_s(pb, L, B, s), "dense S") &&
       dev(launch_zero(B.H, (int64_t)P * pb.npad * pb.nf, s), "zero H") &&
+      dev(hipMemsetAsync(B.lm, 0, (size_t)P * sizeof(LmState), s), "zero LM state") &&
       (!B.chol_fail || dev(hipMemsetAsync(B.chol_fail, 0, (size_t)P * sizeof(int), s), "zero flags")) &&
       dev(launch_zero(B.Y, (int64_t)nj, s), "zero Y") && dev(launch_zero(B.BZ, (int64_t)nj, s), "zero BZ") &&
       dev(launch_zero(B.Z, (int64_t)nz, s), "zero Z") &&

@@ -44,6 +44,7 @@ struct LmState {
   int32_t accepted;// accepted steps in this LM run
   int32_t active;  // subband carries the active direction
   int32_t done;    // the LM run of the active direction has met its stopping rule
+  int32_t dsel;    // D_b of the accepted point is in D1 (1) or D0 (0); the trial pass writes the other
 };
 
 struct Problem {
@@ -70,7 +71,7 @@ struct Buffers {
   double *Sd;                           // [P][K][N][N] S_b of pair (p, q) in both orders, 0 if none
   double *J, *Y, *BZ, *Z, *Zold;        // FP64 master state
   double *Jstart, *Jtrial;              // [P][N][8] active direction
-  double *Dcur, *Dtrial;                // [sum nb][8]
+  double *D0, *D1;                      // [sum nb][8] D_b, accepted and trial point (LmState::dsel)
   double *H;                            // [P][npad][nf]
   double *Linv;                         // [P][nf/16][16*16] inverses of the diagonal tiles
   double *G, *delta;                    // [P][nf]
@@ -85,6 +86,11 @@ struct Buffers {
   int *chol_fail;                       // [P] blocked solver: a pivot failed in this solve
   double *chol_ld;                      // [P][panels][64*64] blocked solver: diagonal blocks' L
 };
+
+// D_b of subband f at its accepted point and at its trial point: an accepted LM step swaps the two
+// buffers instead of copying the trial values
+__device__ inline double *d_accepted(const Buffers &B, int f) { return B.lm[f].dsel ? B.D1 : B.D0; }
+__device__ inline double *d_trial(const Buffers &B, int f) { return B.lm[f].dsel ? B.D0 : B.D1; }
 
 // streaming kernels (templated on the stream element type float or double)
 template <typename T>

@@ -168,6 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Problem pb, Layout L, Buffe
   __syncthreads();
   const double *J = Js;
   // Q_p (q00, q11, Re q01, Im q01) and the data part of the gradient of station p
+  const double *Dacc = d_accepted(B, f);
   double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int a = L.adj_off[f * N + p] + threadIdx.x; a < L.adj_off[f * N + p + 1]; a += kBlock) {
     const int gb = L.adj_b[a];
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Problem pb, Layout L, Buffe
     // D_b (8 doubles) loaded whole before either orientation is used: no load behind a branch
     double d[8];
     {
-      const double2 *D2 = reinterpret_cast<const double2 *>(B.Dcur + 8 * (int64_t)gb);
+      const double2 *D2 = reinterpret_cast<const double2 *>(Dacc + 8 * (int64_t)gb);
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
         const double2 x = D2[h];
@@ -295,6 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_lm_update(Problem pb, Layout L, Buff
         st->nu = 2.0;
         st->F = Fn;
         st->accepted += 1;
+        st->dsel ^= 1;   // the trial point's D_b becomes the accepted one
         a = 1;
       }
     }
@@ -315,13 +317,6 @@ __global__ __launch_bounds__(kBlock) void k_lm_update(Problem pb, Layout L, Buff
   if (acc) {
     double *J = B.J + ((int64_t)f * pb.K + k) * pb.N * 8;
     for (int e = threadIdx.x; e < 8 * pb.N; e += kBlock) J[e] = B.Jtrial[(int64_t)f * pb.N * 8 + e];
-    // D_b of the accepted point: 8 doubles per baseline, two per thread per step, the loads of
-    // several steps in flight
-    const double2 *src = reinterpret_cast<const double2 *>(B.Dtrial + 8 * (int64_t)L.bl_off[f]);
-    double2 *dst = reinterpret_cast<double2 *>(B.Dcur + 8 * (int64_t)L.bl_off[f]);
-    const int n2 = 4 * L.nb[f];
-#pragma unroll 8
-    for (int e = threadIdx.x; e < n2; e += kBlock) dst[e] = src[e];
   }
 }
 
@@ -342,8 +337,6 @@ __global__ __launch_bounds__(kBlock) void k_dense_s(Problem pb, Layout L, Buffer
   }
 }
 
-// 1 in *flag when every subband that has direction k has stopped its LM run, else 0 (one
-// workgroup; flag is pinned host memory that the host reads after the stream synchronises)
 // Whether direction k's LM run has stopped on every subband that carries it (*flag = 1, else 0).
 // Once it has, the iterations it_from .. lm_iters-1 will not be launched: their trace rows get what
 // the update launches of those iterations would write (the final objective and damping, not

@@ -196,7 +196,7 @@ __device__ inline void stream_tile(const Problem &pb, const Layout &L, const Buf
     for (int o = G / 2; o > 0; o >>= 1) D[e] += __shfl_xor(D[e], o, G);
   }
   if (live && lane == 0) {
-    double *Dout = (MODE == SM_TRIAL ? B.Dtrial : B.Dcur) + 8 * gb;
+    double *Dout = (MODE == SM_TRIAL ? d_trial(B, f) : d_accepted(B, f)) + 8 * gb;
 #pragma unroll
     for (int e = 0; e < 8; ++e) Dout[e] = D[e];
   }

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kBlock) void k_ws_features(Problem pb, Layout L, Bu
     v[1] += S * (Jo[2] * Jo[2] + Jo[3] * Jo[3] + Jo[6] * Jo[6] + Jo[7] * Jo[7]);
     v[2] += S * (Jo[0] * Jo[2] + Jo[1] * Jo[3] + Jo[4] * Jo[6] + Jo[5] * Jo[7]);
     v[3] += S * (Jo[0] * Jo[3] - Jo[1] * Jo[2] + Jo[4] * Jo[7] - Jo[5] * Jo[6]);
-    const double *D = B.Dcur + 8 * (int64_t)gb;
+    const double *D = d_accepted(B, f) + 8 * (int64_t)gb;
     for (int i = 0; i < 2; ++i)
       for (int j = 0; j < 2; ++j) {
         double re = 0.0, im = 0.0;
