@@ -12,25 +12,21 @@
 //   y_update    : B_f Z_k, Y_fk += rho_k (J_fk - B_f Z_k) (minimisation M3) and primal partials.
 //   residuals   : primal and dual residuals of Section 4.1 averaged over (f, k) and k.
 #include "calib_internal.h"
+#include "wave_reduce.h"
 #include "device_math.h"
 
 namespace calib {
 
 namespace {
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 template <int NV>
 __device__ inline void block_sum_vec(double *v, double (*red)[kBlock / 64]) {
   const int w = threadIdx.x >> 6;
+  wave_sum_vec<NV>(v);
+  if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const double s = wave_sum(v[i]);
-    if ((threadIdx.x & 63) == 0) red[i][w] = s;
+    for (int i = 0; i < NV; ++i) red[i][w] = v[i];
   }
   __syncthreads();
 #pragma unroll

@@ -18,6 +18,7 @@
 // of the matrix augmented with -G^T as an extra row (so the forward substitution falls out of
 // the factorisation), followed by a blocked back substitution.
 #include "calib_internal.h"
+#include "wave_reduce.h"
 
 namespace calib {
 
@@ -25,11 +26,6 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 __device__ inline double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -41,10 +37,10 @@ __device__ inline double wave_max(double v) {
 template <int NV>
 __device__ inline void block_sum_vec(double *v, double (*red)[kBlock / 64]) {
   const int w = threadIdx.x >> 6;
+  wave_sum_vec<NV>(v);
+  if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const double s = wave_sum(v[i]);
-    if ((threadIdx.x & 63) == 0) red[i][w] = s;
+    for (int i = 0; i < NV; ++i) red[i][w] = v[i];
   }
   __syncthreads();
 #pragma unroll

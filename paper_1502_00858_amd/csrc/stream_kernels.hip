@@ -19,6 +19,7 @@
 // across the G lanes with cross-lane shuffles in FP64; the per-tile cost is reduced through LDS
 // into one FP64 partial per tile, summed later in a fixed order (run-to-run deterministic).
 #include "calib_internal.h"
+#include "wave_reduce.h"
 
 namespace calib {
 
@@ -81,11 +82,6 @@ __device__ inline void load2(const T *__restrict__ p, T &re, T &im) {
   im = p[1];
 }
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 // Sum over the workgroup in a fixed order; the result is valid in thread 0.
 __device__ inline double block_sum(double v, double *red) {
@@ -190,11 +186,11 @@ __device__ inline void stream_tile(const Problem &pb, const Layout &L, const Buf
       }
     }
   }
+  // the eight butterflies advance together (independent exchanges within a step)
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
+  for (int o = G / 2; o > 0; o >>= 1)
 #pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) D[e] += __shfl_xor(D[e], o, G);
-  }
+    for (int e = 0; e < 8; ++e) D[e] += __shfl_xor(D[e], o, G);
   if (live && lane == 0) {
     double *Dout = (MODE == SM_TRIAL ? d_trial(B, f) : d_accepted(B, f)) + 8 * gb;
 #pragma unroll

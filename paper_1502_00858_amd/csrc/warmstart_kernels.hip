@@ -16,17 +16,13 @@
 // sum_p J_new,p^H J_prev,p, i.e. the converged solution moved to the unitary gauge closest to the
 // previous one (the solutions are unique only up to a common right unitary factor, Section 3).
 #include "calib_internal.h"
+#include "wave_reduce.h"
 #include "device_math.h"
 
 namespace calib {
 
 namespace {
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 __global__ __launch_bounds__(kBlock) void k_ws_features(Problem pb, Layout L, Buffers B, int k,
                                                         const double *J2, const double *BZp,
@@ -70,9 +66,10 @@ __global__ __launch_bounds__(kBlock) void k_ws_features(Problem pb, Layout L, Bu
       }
   }
   const int w = threadIdx.x >> 6;
-  for (int i = 0; i < 12; ++i) {
-    const double s = wave_sum(v[i]);
-    if ((threadIdx.x & 63) == 0) red[i][w] = s;
+  wave_sum_vec<12>(v);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) red[i][w] = v[i];
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
@@ -154,9 +151,10 @@ __global__ __launch_bounds__(kBlock) void k_ws_target(Problem pb, Layout L, Buff
         }
   }
   const int w = threadIdx.x >> 6;
-  for (int e = 0; e < 8; ++e) {
-    const double t = wave_sum(v[e]);
-    if ((threadIdx.x & 63) == 0) red[e][w] = t;
+  wave_sum_vec<8>(v);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[e][w] = v[e];
   }
   __syncthreads();
   if (threadIdx.x == 0) {
