@@ -34,8 +34,8 @@ __device__ inline double wave_max(double v) {
 
 // Reduce NV values per thread over the workgroup in a fixed order; result in out[] of every
 // thread (broadcast through LDS).
-template <int NV>
-__device__ inline void block_sum_vec(double *v, double (*red)[kBlock / 64]) {
+template <int NV, int NT = kBlock>
+__device__ inline void block_sum_vec(double *v, double (*red)[NT / 64]) {
   const int w = threadIdx.x >> 6;
   wave_sum_vec<NV>(v);
   if ((threadIdx.x & 63) == 0) {
@@ -46,7 +46,7 @@ __device__ inline void block_sum_vec(double *v, double (*red)[kBlock / 64]) {
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     double s = 0.0;
-    for (int j = 0; j < kBlock / 64; ++j) s += red[i][j];
+    for (int j = 0; j < NT / 64; ++j) s += red[i][j];
     v[i] = s;
   }
   __syncthreads();
@@ -132,9 +132,11 @@ __global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffe
   }
 }
 
-// One workgroup per (subband, station row-block); blockIdx.y == N writes the padding rows.
-__global__ __launch_bounds__(kBlock) void k_assemble(Problem pb, Layout L, Buffers B, int k, int unreg) {
-  __shared__ double red[12][kBlock / 64];
+// One workgroup of two wavefronts per (subband, station row-block), so that all of them are resident
+// at once; blockIdx.y == N writes the padding rows.
+constexpr int kAsmBlock = 128;
+__global__ __launch_bounds__(kAsmBlock) void k_assemble(Problem pb, Layout L, Buffers B, int k, int unreg) {
+  __shared__ double red[12][kAsmBlock / 64];
   __shared__ double qg[12];
   const int f = blockIdx.x, p = blockIdx.y;
   if (k >= L.ndir[f] || B.lm[f].done) return;
@@ -145,10 +147,10 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Problem pb, Layout L, Buffe
   if (p == N) {
     // identity on padded factor columns, zero padding rows below the right-hand side row
     for (int r = 8 * N; r < nf; ++r)
-      for (int c = threadIdx.x; c < nf; c += kBlock) A[(int64_t)r * nf + c] = (c == r) ? 1.0 : 0.0;
-    for (int c = 8 * N + threadIdx.x; c < nf; c += kBlock) A[(int64_t)nf * nf + c] = 0.0;
+      for (int c = threadIdx.x; c < nf; c += kAsmBlock) A[(int64_t)r * nf + c] = (c == r) ? 1.0 : 0.0;
+    for (int c = 8 * N + threadIdx.x; c < nf; c += kAsmBlock) A[(int64_t)nf * nf + c] = 0.0;
     for (int r = nf + 1; r < npad; ++r)
-      for (int c = threadIdx.x; c < nf; c += kBlock) A[(int64_t)r * nf + c] = 0.0;
+      for (int c = threadIdx.x; c < nf; c += kAsmBlock) A[(int64_t)r * nf + c] = 0.0;
     return;
   }
   // the direction's Jones matrices and S of station p's pairs (row p of the dense table) in LDS:
@@ -158,15 +160,15 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Problem pb, Layout L, Buffe
   {
     const double *Jg = jdir(B, pb, f, k);
     const double *Sd = B.Sd + (((int64_t)f * pb.K + k) * N + p) * N;
-    for (int e = threadIdx.x; e < 8 * N; e += kBlock) Js[e] = Jg[e];
-    for (int e = threadIdx.x; e < N; e += kBlock) Sp[e] = Sd[e];
+    for (int e = threadIdx.x; e < 8 * N; e += kAsmBlock) Js[e] = Jg[e];
+    for (int e = threadIdx.x; e < N; e += kAsmBlock) Sp[e] = Sd[e];
   }
   __syncthreads();
   const double *J = Js;
   // Q_p (q00, q11, Re q01, Im q01) and the data part of the gradient of station p
   const double *Dacc = d_accepted(B, f);
   double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int a = L.adj_off[f * N + p] + threadIdx.x; a < L.adj_off[f * N + p + 1]; a += kBlock) {
+  for (int a = L.adj_off[f * N + p] + threadIdx.x; a < L.adj_off[f * N + p + 1]; a += kAsmBlock) {
     const int gb = L.adj_b[a];
     const bool first = L.adj_o[a] >= 0;
     const int o = first ? L.adj_o[a] : -1 - L.adj_o[a];
@@ -207,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Problem pb, Layout L, Buffe
         v[4 + (i * 2 + j) * 2 + 1] += -2.0 * im;
       }
   }
-  block_sum_vec<12>(v, red);
+  block_sum_vec<12, kAsmBlock>(v, red);
   if (threadIdx.x < 12) {
     double x = v[threadIdx.x];
     if (threadIdx.x >= 4 && !unreg) {
@@ -225,14 +227,14 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Problem pb, Layout L, Buffe
   const double q00 = qg[0], q11 = qg[1], q01r = qg[2], q01i = qg[3];
   const int ncol = 8 * p + 8;
   const double *Jp = J + 8 * p;
-  // 32 threads per row v of station p's 8 rows, stepping through its columns (coalesced stores,
+  // 16 threads per row v of station p's 8 rows, stepping through its columns (coalesced stores,
   // no division)
-  static_assert(kBlock == 8 * 32, "one row per 32 threads");
-  const int v8 = threadIdx.x >> 5, l32 = threadIdx.x & 31;
+  static_assert(kAsmBlock == 8 * 16, "one row per 16 threads");
+  const int v8 = threadIdx.x >> 4, l16 = threadIdx.x & 15;
   const int iv = v8 >> 2, jv = (v8 >> 1) & 1, rv = v8 & 1;
   double *row = A + (int64_t)(8 * p + v8) * nf;
 #pragma unroll 4
-  for (int c = l32; c < ncol; c += 32) {
+  for (int c = l16; c < ncol; c += 16) {
     double val;
     const int u = c & 7;
     const int iu = u >> 2, ju = (u >> 1) & 1, ru = u & 1;
@@ -380,7 +382,7 @@ hipError_t launch_lm_begin(const Problem &pb, const Layout &L, const Buffers &B,
 
 hipError_t launch_assemble(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_assemble, dim3(pb.P, pb.N + 1), dim3(kBlock), 0, s, pb, L, B, k, unreg);
+  hipLaunchKernelGGL(k_assemble, dim3(pb.P, pb.N + 1), dim3(kAsmBlock), 0, s, pb, L, B, k, unreg);
   return hipGetLastError();
 }
 
