@@ -92,9 +92,12 @@ __global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffe
   const double *J = jdir(B, pb, f, k);
   const double F = objective(pb, L, B, f, k, unreg, J, red);
   // largest diagonal entry of H_GN + rho I: 2 sum_c S_pc (|J_c[0][j]|^2 + |J_c[1][j]|^2) + rho,
-  // from the column norms of the stations' Jones matrices and the dense S (coalesced: thread p
-  // reads column p of each row q, S being symmetric)
+  // from the column norms of the stations' Jones matrices and the dense S.  Wavefront w sums the
+  // rows q of its quarter for every column p (coalesced: lane p reads column p of row q, S being
+  // symmetric), the quarters are added in LDS.
+  constexpr int kW = kBlock / 64;
   __shared__ double nrm[2][kMaxStations];
+  __shared__ double part[kW][2][kMaxStations];
   for (int p = threadIdx.x; p < pb.N; p += kBlock) {
     const double *Jp = J + 8 * p;
     nrm[0][p] = Jp[0] * Jp[0] + Jp[1] * Jp[1] + Jp[4] * Jp[4] + Jp[5] * Jp[5];
@@ -102,15 +105,31 @@ __global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffe
   }
   __syncthreads();
   const double *Sd = B.Sd + ((int64_t)f * pb.K + k) * pb.N * pb.N;
+  {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int qn = (pb.N + kW - 1) / kW, q0 = w * qn, q1 = min(pb.N, q0 + qn);
+    for (int p = lane; p < pb.N; p += 64) {
+      double d0 = 0.0, d1 = 0.0;
+#pragma unroll 8
+      for (int q = q0; q < q1; ++q) {
+        const double S = Sd[(int64_t)q * pb.N + p];
+        d0 = fma(S, nrm[0][q], d0);
+        d1 = fma(S, nrm[1][q], d1);
+      }
+      part[w][0][p] = d0;
+      part[w][1][p] = d1;
+    }
+  }
+  __syncthreads();
   double dmax = 0.0;
   for (int p = threadIdx.x; p < pb.N; p += kBlock) {
-    double d0[2] = {0.0, 0.0}, d1[2] = {0.0, 0.0};
-    for (int q = 0; q < pb.N; ++q) {
-      const double S = Sd[(int64_t)q * pb.N + p];
-      d0[q & 1] = fma(S, nrm[0][q], d0[q & 1]);
-      d1[q & 1] = fma(S, nrm[1][q], d1[q & 1]);
+    double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+    for (int w = 0; w < kW; ++w) {
+      d0 += part[w][0][p];
+      d1 += part[w][1][p];
     }
-    dmax = fmax(dmax, 2.0 * fmax(d0[0] + d0[1], d1[0] + d1[1]));
+    dmax = fmax(dmax, 2.0 * fmax(d0, d1));
   }
   __shared__ double mx[kBlock / 64];
   dmax = wave_max(dmax);
@@ -153,6 +172,31 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble(Problem pb, Layout L, Bu
       for (int c = threadIdx.x; c < nf; c += kAsmBlock) A[(int64_t)r * nf + c] = 0.0;
     return;
   }
+  // Station p's baselines, one per thread: the adjacency entry and D_b of the accepted point, and
+  // the consensus terms of the gradient, requested before the staging below so that the loads
+  // overlap
+  static_assert(kMaxStations <= kAsmBlock, "at most one baseline of station p per thread");
+  const int a = L.adj_off[f * N + p] + threadIdx.x;
+  const bool has = a < L.adj_off[f * N + p + 1];
+  int gb = 0, oraw = 0;
+  double d[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (has) {
+    gb = L.adj_b[a];
+    oraw = L.adj_o[a];
+    const double2 *D2 = reinterpret_cast<const double2 *>(d_accepted(B, f) + 8 * (int64_t)gb);
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const double2 x = D2[h];
+      d[2 * h] = x.x;
+      d[2 * h + 1] = x.y;
+    }
+  }
+  double yv = 0.0, bzv = 0.0;
+  if (threadIdx.x >= 4 && threadIdx.x < 12 && !unreg) {
+    const int64_t o = ((int64_t)f * pb.K + k) * N * 8 + 8 * p + (threadIdx.x - 4);
+    yv = B.Y[o];
+    bzv = B.BZ[o];
+  }
   // the direction's Jones matrices and S of station p's pairs (row p of the dense table) in LDS:
   // everything below reads them
   __shared__ double Js[8 * kMaxStations];
@@ -166,12 +210,10 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble(Problem pb, Layout L, Bu
   __syncthreads();
   const double *J = Js;
   // Q_p (q00, q11, Re q01, Im q01) and the data part of the gradient of station p
-  const double *Dacc = d_accepted(B, f);
   double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int a = L.adj_off[f * N + p] + threadIdx.x; a < L.adj_off[f * N + p + 1]; a += kAsmBlock) {
-    const int gb = L.adj_b[a];
-    const bool first = L.adj_o[a] >= 0;
-    const int o = first ? L.adj_o[a] : -1 - L.adj_o[a];
+  if (has) {
+    const bool first = oraw >= 0;
+    const int o = first ? oraw : -1 - oraw;
     const double S = Sp[o];
     const double *Jo = J + 8 * o;
     v[0] += S * (Jo[0] * Jo[0] + Jo[1] * Jo[1] + Jo[4] * Jo[4] + Jo[5] * Jo[5]);
@@ -179,17 +221,6 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble(Problem pb, Layout L, Bu
     // (J^H J)[0][1] = conj(J00) J01 + conj(J10) J11
     v[2] += S * (Jo[0] * Jo[2] + Jo[1] * Jo[3] + Jo[4] * Jo[6] + Jo[5] * Jo[7]);
     v[3] += S * (Jo[0] * Jo[3] - Jo[1] * Jo[2] + Jo[4] * Jo[7] - Jo[5] * Jo[6]);
-    // D_b (8 doubles) loaded whole before either orientation is used: no load behind a branch
-    double d[8];
-    {
-      const double2 *D2 = reinterpret_cast<const double2 *>(Dacc + 8 * (int64_t)gb);
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const double2 x = D2[h];
-        d[2 * h] = x.x;
-        d[2 * h + 1] = x.y;
-      }
-    }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -212,11 +243,7 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble(Problem pb, Layout L, Bu
   block_sum_vec<12, kAsmBlock>(v, red);
   if (threadIdx.x < 12) {
     double x = v[threadIdx.x];
-    if (threadIdx.x >= 4 && !unreg) {
-      const int e = threadIdx.x - 4;
-      const int64_t o = ((int64_t)f * pb.K + k) * N * 8 + 8 * p;
-      x += B.Y[o + e] + rho * (J[8 * p + e] - B.BZ[o + e]);
-    }
+    if (threadIdx.x >= 4 && !unreg) x += yv + rho * (J[8 * p + threadIdx.x - 4] - bzv);
     qg[threadIdx.x] = x;
   }
   __syncthreads();
