@@ -123,6 +123,14 @@ typedef d4 Stack[kPanelTiles];
 
 __device__ inline int stack_row(int w, int r, int lq) { return 16 * w + 4 * r + lq; }
 
+// The value of the even lane of this lane's pair of lanes (DPP quad_perm [0,0,2,2])
+__device__ inline double quad_even(double x) {
+  const long long v = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)v, 0xA0, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), 0xA0, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 // 1/d: the v_rcp_f64 estimate (relative error below 2^-24) refined by one third-order step
 // y (1 + e + e^2), e = 1 - d y, which cubes the relative error.
 __device__ inline double rcp3(double d) {
@@ -383,9 +391,12 @@ __global__ __launch_bounds__(kBThreads) void k_chol_panel(Problem pb, Buffers B,
   if (wp > 2) elim_tile<2>(acc, hist, cy, wcol, w, lane);
   if (wp > 3) elim_tile<3>(acc, hist, cy, wcol, w, lane);
 
-  // L from the history: column c of pair (c, c+1) is L[.][c] sqrt(a00), column c+1 is
-  // (a[.][c+1] - a[.][c] a10 / a00) / sqrt(det / a00); 1/L_jj in the diagonal slots.  Each lane
-  // checks the pivots of its columns' pairs (all pairs are covered).
+  // L: column c of pair (c, c+1) is L[.][c] sqrt(a00), column c+1 is
+  // (a[.][c+1] - a[.][c] a10 / a00) / sqrt(det / a00); 1/L_jj in the diagonal slots.  A column is
+  // never updated after its publication, so each lane's stack already holds its column as the
+  // history does; an odd column takes its even neighbour's value from the adjacent lane (DPP
+  // quad_perm [0,0,2,2]) and only the pivots come from the history.  Each lane checks the pivots
+  // of its columns' pairs (all pairs are covered).
   int okv = 1;
 #pragma unroll
   for (int J = 0; J < kPanelTiles; ++J) {
@@ -402,8 +413,9 @@ __global__ __launch_bounds__(kBThreads) void k_chol_panel(Problem pb, Buffers B,
     const double rs = rsqrt_nr(odd ? det * inv0 : a00);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const double2 x = lds2(h + 2 * stack_row(w, r, lq));
-      const double v = odd ? fma(-x.x, l10, x.y) : x.x;
+      const double own = acc[J][r];
+      const double ev = quad_even(own);
+      const double v = odd ? fma(-ev, l10, own) : own;
       acc[J][r] = (in_block && stack_row(w, r, lq) == 16 * J + li) ? rs : v * rs;
     }
   }
