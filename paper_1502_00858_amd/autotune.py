@@ -2,7 +2,7 @@
 
 Two launch parameters of calib_config shape those passes:
 
-* tile_group  - lanes that share one baseline (8, 16, 32 or 64); a workgroup of 256 lanes covers
+* tile_group  - lanes that share one baseline (4, 8, 16, 32 or 64); a workgroup of 256 lanes covers
                 256/tile_group baselines, each lane striding over that baseline's T*n_chan samples.
                 Few samples per baseline favour narrow groups (less idle lanes), many favour wide.
 * stream_grid - 0 launches one workgroup per tile; > 0 launches a persistent grid of that many
@@ -25,7 +25,7 @@ import numpy as np
 
 from . import calib
 
-GROUPS = (8, 16, 32, 64)
+GROUPS = (4, 8, 16, 32, 64)
 STREAM_KERNELS = ("refresh", "trial", "commit")
 
 

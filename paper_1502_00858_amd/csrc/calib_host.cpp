@@ -158,7 +158,8 @@ calib_status upload(calib_ctx *ctx, V **dst, const std::vector<V> &src) {
 // lanes per baseline for the streaming kernels: the configured value, else the fewest idle
 // lane-iterations over the subbands, ties to the larger group
 int choose_group(const std::vector<int32_t> &spb, const std::vector<int32_t> &nb, int requested) {
-  if (requested == 8 || requested == 16 || requested == 32 || requested == 64) return requested;
+  if (requested == 4 || requested == 8 || requested == 16 || requested == 32 || requested == 64)
+    return requested;
   int best = 16;
   double best_w = 1e300;
   for (int g : {64, 32, 16, 8}) {

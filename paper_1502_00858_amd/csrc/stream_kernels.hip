@@ -218,6 +218,7 @@ hipError_t launch_mode(const Problem &pb, const Layout &L, const Buffers &B, int
   if (pb.ntiles == 0) return hipSuccess;
   dim3 grid(pb.stream_grid > 0 && pb.stream_grid < pb.ntiles ? pb.stream_grid : pb.ntiles), block(kBlock);
   switch (pb.group) {
+    case 4: hipLaunchKernelGGL((k_stream<T, 4, MODE>), grid, block, 0, s, pb, L, B, k); break;
     case 8: hipLaunchKernelGGL((k_stream<T, 8, MODE>), grid, block, 0, s, pb, L, B, k); break;
     case 16: hipLaunchKernelGGL((k_stream<T, 16, MODE>), grid, block, 0, s, pb, L, B, k); break;
     case 32: hipLaunchKernelGGL((k_stream<T, 32, MODE>), grid, block, 0, s, pb, L, B, k); break;

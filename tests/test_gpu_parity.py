@@ -226,7 +226,7 @@ def test_tile_shapes_and_persistent_grid(cal, synth_mod):
     d = synth_mod.generate(cfg)
     ref = _ctx(cal, d, 1).solve(3)
     np.testing.assert_array_equal(_ctx(cal, d, 1, stream_grid=3).solve(3), ref)
-    for g in (8, 16, 32, 64):
+    for g in (4, 8, 16, 32, 64):
         tr = _ctx(cal, d, 1, tile_group=g).solve(3)
         np.testing.assert_allclose(tr, ref, rtol=1e-6)
 
