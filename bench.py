@@ -78,7 +78,8 @@ def kernel_work(name, data, elt):
     if name == "chol_solve":
         return ("mfma", float(np.sum(w)) * (n ** 3 / 3.0 + 2.0 * n ** 2), "TFLOP/s")
     if name == "trial":
-        return ("hbm", float(np.sum(w * (S_f * (8 + 2) * elt + nb * 64.0))), "GB/s")
+        # statistics of the trial point: D_b of the start point and S_b read, D_b written
+        return ("hbm", float(np.sum(w * nb * (64.0 + 8.0 + 64.0))), "GB/s")
     if name == "commit":
         return ("hbm", float(np.sum(w * (S_f * (8 * 2 + 2 * 2) * elt + nb * 64.0))), "GB/s")
     if name == "refresh":
@@ -327,10 +328,10 @@ def main():
                                "unit": unit, "frac": achieved / peak,
                                "traffic": measured_traffic(dom, args.config, solver_name),
                                "avg_launch_us": avg_s * 1e6, "share_of_step": ms / total}
-        # the streaming pass at the LM trial point: achieved HBM bandwidth
-        tl, tms = kt["trial"]
-        _, tb, _ = kernel_work("trial", data, elt)
-        out["trial_pass_GBs"] = tb / (tms / tl / 1e3) / 1e9
+        # the streaming pass that commits a direction: achieved HBM bandwidth
+        cl, cms = kt["commit"]
+        _, cb, _ = kernel_work("commit", data, elt)
+        out["commit_pass_GBs"] = cb / (cms / cl / 1e3) / 1e9
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(data, args.cpu_sample_iters,

@@ -1,4 +1,4 @@
-"""Tile-shape tuner for the streaming passes (refresh, LM trial, SAGE commit).
+"""Tile-shape tuner for the streaming passes (refresh, SAGE commit).
 
 Two launch parameters of calib_config shape those passes:
 
@@ -26,7 +26,7 @@ import numpy as np
 from . import calib
 
 GROUPS = (4, 8, 16, 32, 64)
-STREAM_KERNELS = ("refresh", "trial", "commit")
+STREAM_KERNELS = ("refresh", "commit")
 
 
 def shape_key(data: dict, precision: int) -> str:

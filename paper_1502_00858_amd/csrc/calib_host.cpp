@@ -185,7 +185,7 @@ calib_status lm_iteration(calib_ctx *c, int k, int it, int unreg, hipStream_t s)
                ? launch_chol_blocked(pb, B, k, c->d_ndir, B.chol_ld, B.chol_fail, s)
                : launch_chol_solve_nd(pb, B, k, c->d_ndir, s);
   }));
-  HIPCHK(c, timed(c, CALIB_KERNEL_TRIAL, [&] { return launch_trial<T>(pb, L, B, k, s); }));
+  HIPCHK(c, timed(c, CALIB_KERNEL_TRIAL, [&] { return launch_trial_stats(pb, L, B, k, s); }));
   HIPCHK(c, timed(c, CALIB_KERNEL_LM_UPDATE, [&] {
     return launch_lm_update_tr(pb, L, B, k, unreg, c->lm_trace, it, c->lm_iters, s);
   }));
@@ -573,6 +573,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   DALLOC(B.Sd, (size_t)P * K * N * N * 8);
   DALLOC(B.Jstart, (size_t)P * N * 8 * 8); DALLOC(B.Jtrial, (size_t)P * N * 8 * 8);
   DALLOC(B.D0, (size_t)nb_total * 8 * 8); DALLOC(B.D1, (size_t)nb_total * 8 * 8);
+  DALLOC(B.Dstart, (size_t)nb_total * 8 * 8);
   DALLOC(B.H, (size_t)P * pb.npad * pb.nf * 8);
   DALLOC(B.Linv, (size_t)P * (pb.nf / 16) * 256 * 8);
   DALLOC(B.G, (size_t)P * pb.nf * 8); DALLOC(B.delta, (size_t)P * pb.nf * 8);

@@ -36,6 +36,7 @@ struct Layout {
 // State of the Levenberg-Marquardt iteration of the active direction of each subband.
 struct LmState {
   double F;        // objective at the accepted point
+  double E0;       // data cost at the LM run's start point (the residual's energy)
   double lambda;   // damping
   double nu;       // damping growth factor
   double ell;      // predicted decrease of the last step
@@ -72,6 +73,7 @@ struct Buffers {
   double *J, *Y, *BZ, *Z, *Zold;        // FP64 master state
   double *Jstart, *Jtrial;              // [P][N][8] active direction
   double *D0, *D1;                      // [sum nb][8] D_b, accepted and trial point (LmState::dsel)
+  double *Dstart;                       // [sum nb][8] D_b at the LM run's start point
   double *H;                            // [P][npad][nf]
   double *Linv;                         // [P][nf/16][16*16] inverses of the diagonal tiles
   double *G, *delta;                    // [P][nf]
@@ -96,8 +98,6 @@ __device__ inline double *d_trial(const Buffers &B, int f) { return B.lm[f].dsel
 template <typename T>
 hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
 template <typename T>
-hipError_t launch_trial(const Problem &pb, const Layout &L, const Buffers &B, int k, hipStream_t s);
-template <typename T>
 hipError_t launch_commit(const Problem &pb, const Layout &L, const Buffers &B, int k, hipStream_t s);
 template <typename T>
 hipError_t launch_model(const Problem &pb, const Layout &L, const Buffers &B, void *model_out,
@@ -118,6 +118,8 @@ hipError_t launch_chol_solve_nd(const Problem &pb, const Buffers &B, int k, cons
 hipError_t launch_chol_blocked(const Problem &pb, const Buffers &B, int k, const int32_t *ndir,
                                double *Ld, int *cfail, hipStream_t s);
 int chol_blocked_panels(const Problem &pb);
+hipError_t launch_trial_stats(const Problem &pb, const Layout &L, const Buffers &B, int k,
+                              hipStream_t s);
 hipError_t launch_lm_update_tr(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
                                double *lm_trace, int it, int lm_iters, hipStream_t s);
 hipError_t launch_dense_s(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);

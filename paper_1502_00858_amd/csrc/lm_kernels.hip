@@ -62,9 +62,11 @@ __device__ inline const double *jdir(const Buffers &B, const Problem &pb, int f,
   return B.J + ((int64_t)f * pb.K + k) * pb.N * 8;
 }
 
-// data cost of subband f from its tiles' partials (fixed order) + consensus terms at Jx
+// data cost of subband f from its tiles' partials (fixed order) + consensus terms at Jx; the data
+// cost alone in *data when given
 __device__ inline double objective(const Problem &pb, const Layout &L, const Buffers &B, int f,
-                                   int k, int unreg, const double *Jx, double (*red)[kBlock / 64]) {
+                                   int k, int unreg, const double *Jx, double (*red)[kBlock / 64],
+                                   double *data = nullptr) {
   double acc[1] = {0.0};
   for (int t = L.tile_off[f] + threadIdx.x; t < L.tile_off[f + 1]; t += kBlock) acc[0] += B.cost_part[t];
   double pen = 0.0;
@@ -78,6 +80,7 @@ __device__ inline double objective(const Problem &pb, const Layout &L, const Buf
   }
   double v[2] = {acc[0], pen};
   block_sum_vec<2>(v, red);
+  if (data) *data = v[0];
   return v[0] + v[1];
 }
 
@@ -90,7 +93,8 @@ __global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffe
     return;
   }
   const double *J = jdir(B, pb, f, k);
-  const double F = objective(pb, L, B, f, k, unreg, J, red);
+  double E0 = 0.0;
+  const double F = objective(pb, L, B, f, k, unreg, J, red, &E0);
   // largest diagonal entry of H_GN + rho I: 2 sum_c S_pc (|J_c[0][j]|^2 + |J_c[1][j]|^2) + rho,
   // from the column norms of the stations' Jones matrices and the dense S.  Wavefront w sums the
   // rows q of its quarter for every column p (coalesced: lane p reads column p of row q, S being
@@ -141,6 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffe
     for (int i = 0; i < kBlock / 64; ++i) m = fmax(m, mx[i]);
     m += unreg ? 0.0 : B.rho[k];
     st->F = F;
+    st->E0 = E0;
     st->lambda = kLmTau * m;
     st->nu = 2.0;
     st->accepted = 0;

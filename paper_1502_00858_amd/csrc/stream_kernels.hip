@@ -3,11 +3,12 @@
 //
 //   refresh : R = V - sum_k c_k J_kp J_kq^H            (Section 2 visibility model; the full
 //             residual at the start of a local step), plus the statistics of direction 0
-//   trial   : r = R - c_k (M_trial - M_start)          (one Levenberg-Marquardt trial point of
-//             direction k: the SAGE expectation V_k = R + c_k M_start of Section 3 minus the
-//             trial model), accumulating sum ||r||^2 and D_b = sum conj(c_k) r
 //   commit  : R <- R - c_k (M_final - M_start)         (end of direction k), plus the statistics
 //             of the next direction
+// Both accumulate sum ||R||^2 and D_b = sum conj(c) R for the direction whose Levenberg-Marquardt
+// run follows.  A trial point of that run, r = R - c_k (M_trial - M_start) (the SAGE expectation
+// V_k = R + c_k M_start of Section 3 minus the trial model), needs no pass over the samples: its
+// cost and D_b follow from these statistics and S_b (k_trial_stats).
 //
 // The coherency of an unpolarised source is a scalar times I2 (Section 2), so one complex value
 // per sample and direction is streamed.  The Jones matrices are time invariant over the interval
@@ -25,7 +26,7 @@ namespace calib {
 
 namespace {
 
-enum { SM_REFRESH = 0, SM_TRIAL = 1, SM_COMMIT = 2 };
+enum { SM_REFRESH = 0, SM_COMMIT = 2 };
 
 __device__ inline void jjh(const double *__restrict__ a, const double *__restrict__ b, double *m) {
   // m = a b^H for 2x2 complex matrices stored as 8 doubles (row-major, re/im interleaved)
@@ -101,7 +102,6 @@ __device__ inline void stream_tile(const Problem &pb, const Layout &L, const Buf
                                    double *red) {
   const int f = L.tile_f[tile];
   const int Kf = L.ndir[f];
-  if (MODE == SM_TRIAL && (k >= Kf || !B.lm[f].chol_ok || B.lm[f].done)) return;   // uniform
   if (MODE == SM_COMMIT && k >= Kf) return;
 
   const int nb = L.nb[f], spb = L.spb[f];
@@ -109,7 +109,7 @@ __device__ inline void stream_tile(const Problem &pb, const Layout &L, const Buf
   const int bi = L.tile_b0[tile] + grp;
   const bool live = bi < nb;
   const int N = pb.N, K = pb.K;
-  const int kst = (MODE == SM_REFRESH) ? 0 : (MODE == SM_TRIAL ? k : (k + 1 < Kf ? k + 1 : 0));
+  const int kst = (MODE == SM_REFRESH) ? 0 : (k + 1 < Kf ? k + 1 : 0);
   const int64_t gb = (int64_t)L.bl_off[f] + bi;
   const int64_t s0 = L.samp_off[f] + (int64_t)bi * spb;
   const T *C = static_cast<const T *>(B.C);
@@ -130,8 +130,7 @@ __device__ inline void stream_tile(const Problem &pb, const Layout &L, const Buf
     __syncthreads();
   } else if (live) {
     const int p = L.bl_p[gb], q = L.bl_q[gb];
-    const double *J1 = (MODE == SM_TRIAL) ? B.Jtrial + (int64_t)f * N * 8
-                                          : B.J + ((int64_t)f * K + k) * N * 8;
+    const double *J1 = B.J + ((int64_t)f * K + k) * N * 8;
     const double *J0 = B.Jstart + (int64_t)f * N * 8;
     double m1[8], m0[8];
     jjh(J1 + 8 * p, J1 + 8 * q, m1);
@@ -170,7 +169,7 @@ __device__ inline void stream_tile(const Problem &pb, const Layout &L, const Buf
           r[2 * e] -= cr * dM[2 * e] - ci * dM[2 * e + 1];
           r[2 * e + 1] -= cr * dM[2 * e + 1] + ci * dM[2 * e];
         }
-        if (MODE == SM_COMMIT) store8<T>(R + 8 * (s0 + s), r);
+        store8<T>(R + 8 * (s0 + s), r);
       }
       T ss = 0;
 #pragma unroll
@@ -192,12 +191,55 @@ __device__ inline void stream_tile(const Problem &pb, const Layout &L, const Buf
 #pragma unroll
     for (int e = 0; e < 8; ++e) D[e] += __shfl_xor(D[e], o, G);
   if (live && lane == 0) {
-    double *Dout = (MODE == SM_TRIAL ? d_trial(B, f) : d_accepted(B, f)) + 8 * gb;
+    // the accepted point of the next LM run and its start point, from which its trial points'
+    // statistics derive
+    double *Dout = d_accepted(B, f) + 8 * gb;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) Dout[e] = D[e];
+    for (int e = 0; e < 8; ++e) {
+      Dout[e] = D[e];
+      B.Dstart[8 * gb + e] = D[e];
+    }
   }
   const double tot = block_sum(cost, red);
   if (threadIdx.x == 0) B.cost_part[tile] = tot;
+}
+
+// Data cost and D_b at the LM trial point from the start point's statistics (one wavefront per
+// tile, one lane per baseline).  The coherency is a scalar per sample and J_p J_q^H is the same
+// for every sample of a baseline, so with the residual R at the start point J0 and
+// dM = Jt_p Jt_q^H - J0_p J0_q^H (4 complex entries e),
+//     sum_s ||R_s - c_s dM||^2 = sum_s ||R_s||^2 - 2 Re sum_e conj(dM_e) D0_e + S_b sum_e |dM_e|^2,
+//     D_b(trial) = sum_s conj(c_s) (R_s - c_s dM) = D0 - S_b dM,
+// with D0 = sum_s conj(c_s) R_s and S_b = sum_s |c_s|^2.  The first term, summed over the
+// subband, is the data cost at the start point (LmState::E0), added by the subband's first tile;
+// the tile partials sum to the data cost at the trial point as the streaming pass's do.
+__global__ __launch_bounds__(64) void k_trial_stats(Problem pb, Layout L, Buffers B, int k) {
+  const int tile = blockIdx.x, f = L.tile_f[tile];
+  if (k >= L.ndir[f] || !B.lm[f].chol_ok || B.lm[f].done) return;   // uniform
+  const int nb = L.nb[f], bi = L.tile_b0[tile] + threadIdx.x;
+  double part = 0.0;
+  if (threadIdx.x < pb.bpt && bi < nb) {
+    const int64_t gb = (int64_t)L.bl_off[f] + bi;
+    const int p = L.bl_p[gb], q = L.bl_q[gb];
+    const double *Jt = B.Jtrial + (int64_t)f * pb.N * 8, *J0 = B.Jstart + (int64_t)f * pb.N * 8;
+    double m1[8], m0[8];
+    jjh(Jt + 8 * p, Jt + 8 * q, m1);
+    jjh(J0 + 8 * p, J0 + 8 * q, m0);
+    const double S = B.Sb[L.sb_off[f] + (int64_t)k * nb + bi];
+    const double *D0 = B.Dstart + 8 * gb;
+    double *Dt = d_trial(B, f) + 8 * gb;
+    double cross = 0.0, norm = 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const double dm = m1[e] - m0[e], d0 = D0[e];
+      cross = fma(dm, d0, cross);   // Re conj(dM_e) D0_e over the real and imaginary parts
+      norm = fma(dm, dm, norm);
+      Dt[e] = fma(-S, dm, d0);
+    }
+    part = fma(S, norm, -2.0 * cross);
+  }
+  part = wave_sum(part);
+  if (threadIdx.x == 0) B.cost_part[tile] = part + (tile == L.tile_off[f] ? B.lm[f].E0 : 0.0);
 }
 
 // One workgroup per tile (grid = ntiles), or a persistent grid that strides over the tiles.
@@ -317,10 +359,6 @@ hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, 
   return launch_mode<T, SM_REFRESH>(pb, L, B, 0, s);
 }
 template <typename T>
-hipError_t launch_trial(const Problem &pb, const Layout &L, const Buffers &B, int k, hipStream_t s) {
-  return launch_mode<T, SM_TRIAL>(pb, L, B, k, s);
-}
-template <typename T>
 hipError_t launch_commit(const Problem &pb, const Layout &L, const Buffers &B, int k, hipStream_t s) {
   return launch_mode<T, SM_COMMIT>(pb, L, B, k, s);
 }
@@ -348,8 +386,14 @@ hipError_t launch_pack(const Problem &pb, const Layout &L, const void *vis, cons
 
 template hipError_t launch_refresh<float>(const Problem &, const Layout &, const Buffers &, hipStream_t);
 template hipError_t launch_refresh<double>(const Problem &, const Layout &, const Buffers &, hipStream_t);
-template hipError_t launch_trial<float>(const Problem &, const Layout &, const Buffers &, int, hipStream_t);
-template hipError_t launch_trial<double>(const Problem &, const Layout &, const Buffers &, int, hipStream_t);
+hipError_t launch_trial_stats(const Problem &pb, const Layout &L, const Buffers &B, int k,
+                              hipStream_t s) {
+  if (pb.ntiles == 0) return hipSuccess;
+  if (pb.bpt > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_trial_stats, dim3(pb.ntiles), dim3(64), 0, s, pb, L, B, k);
+  return hipGetLastError();
+}
+
 template hipError_t launch_commit<float>(const Problem &, const Layout &, const Buffers &, int, hipStream_t);
 template hipError_t launch_commit<double>(const Problem &, const Layout &, const Buffers &, int, hipStream_t);
 template hipError_t launch_model<float>(const Problem &, const Layout &, const Buffers &, void *,
