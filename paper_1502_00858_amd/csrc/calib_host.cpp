@@ -578,6 +578,10 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   DALLOC(B.Linv, (size_t)P * (pb.nf / 16) * 256 * 8);
   DALLOC(B.G, (size_t)P * pb.nf * 8); DALLOC(B.delta, (size_t)P * pb.nf * 8);
   DALLOC(B.cost_part, (size_t)std::max(pb.ntiles, 1) * 8);
+  DALLOC(B.Epart, (size_t)std::max(pb.ntiles, 1) * 8);
+  DALLOC(B.Ucoh, (size_t)nb_total * K * 8 * 8);
+  DALLOC(B.Xcoh, (size_t)nb_total * K * K * 2 * 8);
+  DALLOC(B.Dall, (size_t)nb_total * K * 8 * 8);
   DALLOC(B.lm, (size_t)P * sizeof(LmState));
   double *basis, *fitw;
   DALLOC(basis, (size_t)P * Q * 8);
@@ -618,6 +622,9 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
           "pack") &&
       dev(launch_basis_setup(pb, d_freq, c->f0, d_ndir, basis, fitw, flagbuf + 1, s), "basis setup") &&
       dev(launch_dense_s(pb, L, B, s), "dense S") &&
+      dev(c->precision == CALIB_FP64 ? launch_coh_stats<double>(pb, L, B, s)
+                                     : launch_coh_stats<float>(pb, L, B, s),
+          "coherency statistics") &&
       dev(launch_zero(B.H, (int64_t)P * pb.npad * pb.nf, s), "zero H") &&
       dev(hipMemsetAsync(B.lm, 0, (size_t)P * sizeof(LmState), s), "zero LM state") &&
       (!B.chol_fail || dev(hipMemsetAsync(B.chol_fail, 0, (size_t)P * sizeof(int), s), "zero flags")) &&

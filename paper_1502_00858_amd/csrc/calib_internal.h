@@ -74,6 +74,10 @@ struct Buffers {
   double *Jstart, *Jtrial;              // [P][N][8] active direction
   double *D0, *D1;                      // [sum nb][8] D_b, accepted and trial point (LmState::dsel)
   double *Dstart;                       // [sum nb][8] D_b at the LM run's start point
+  double *Ucoh;                         // [sum nb][K][8] sum_s conj(c_l) V per direction l
+  double *Xcoh;                         // [sum nb][K][K][2] sum_s conj(c_l) c_m
+  double *Dall;                         // [sum nb][K][8] D_l of the current residual, every l
+  double *Epart;                        // [ntiles] energy of the current residual per tile
   double *H;                            // [P][npad][nf]
   double *Linv;                         // [P][nf/16][16*16] inverses of the diagonal tiles
   double *G, *delta;                    // [P][nf]
@@ -95,6 +99,8 @@ __device__ inline double *d_accepted(const Buffers &B, int f) { return B.lm[f].d
 __device__ inline double *d_trial(const Buffers &B, int f) { return B.lm[f].dsel ? B.D0 : B.D1; }
 
 // streaming kernels (templated on the stream element type float or double)
+template <typename T>
+hipError_t launch_coh_stats(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
 template <typename T>
 hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
 template <typename T>

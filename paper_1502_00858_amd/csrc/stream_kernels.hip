@@ -201,7 +201,10 @@ __device__ inline void stream_tile(const Problem &pb, const Layout &L, const Buf
     }
   }
   const double tot = block_sum(cost, red);
-  if (threadIdx.x == 0) B.cost_part[tile] = tot;
+  if (threadIdx.x == 0) {
+    B.cost_part[tile] = tot;
+    if (MODE == SM_REFRESH) B.Epart[tile] = tot;
+  }
 }
 
 // Data cost and D_b at the LM trial point from the start point's statistics (one wavefront per
@@ -240,6 +243,155 @@ __global__ __launch_bounds__(64) void k_trial_stats(Problem pb, Layout L, Buffer
   }
   part = wave_sum(part);
   if (threadIdx.x == 0) B.cost_part[tile] = part + (tile == L.tile_off[f] ? B.lm[f].E0 : 0.0);
+}
+
+// Per-baseline coherency statistics, once per context (grid: tile x direction l, one lane per
+// baseline): U_l = sum_s conj(c_ls) V_s (8 reals) and X_lm = sum_s conj(c_ls) c_ms for every
+// direction m of the subband, in FP64.  With the scalar coherency and J constant over a baseline's
+// samples, the residual's sums that the LM runs need follow from these: at a point with models
+// M_m, D_l = sum_s conj(c_ls) R_s = U_l - sum_m X_lm M_m.
+template <typename T>
+__global__ __launch_bounds__(64) void k_coh_stats(Problem pb, Layout L, Buffers B) {
+  const int tile = blockIdx.x, l = blockIdx.y, f = L.tile_f[tile];
+  const int Kf = L.ndir[f], nb = L.nb[f], spb = L.spb[f];
+  const int bi = L.tile_b0[tile] + threadIdx.x;
+  if (l >= Kf || threadIdx.x >= pb.bpt || bi >= nb) return;
+  const int K = pb.K;
+  const int64_t gb = (int64_t)L.bl_off[f] + bi, s0 = L.samp_off[f] + (int64_t)bi * spb;
+  const T *V = static_cast<const T *>(B.V), *C = static_cast<const T *>(B.C);
+  const T *cl = C + 2 * (L.coh_off[f] + ((int64_t)l * nb + bi) * spb);
+  double u[8] = {0, 0, 0, 0, 0, 0, 0, 0}, x[2 * kMaxDirs];
+#pragma unroll
+  for (int m = 0; m < 2 * kMaxDirs; ++m) x[m] = 0.0;
+  for (int s = 0; s < spb; ++s) {
+    const double cr = (double)cl[2 * s], ci = (double)cl[2 * s + 1];
+    T v[8];
+    load8<T>(V + 8 * (s0 + s), v);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      u[2 * e] += cr * (double)v[2 * e] + ci * (double)v[2 * e + 1];
+      u[2 * e + 1] += cr * (double)v[2 * e + 1] - ci * (double)v[2 * e];
+    }
+#pragma unroll
+    for (int m = 0; m < kMaxDirs; ++m) {
+      if (m < Kf) {
+        const T *cm = C + 2 * (L.coh_off[f] + ((int64_t)m * nb + bi) * spb + s);
+        const double mr = (double)cm[0], mi = (double)cm[1];
+        x[2 * m] += cr * mr + ci * mi;
+        x[2 * m + 1] += cr * mi - ci * mr;
+      }
+    }
+  }
+  double *U = B.Ucoh + (gb * K + l) * 8, *X = B.Xcoh + (gb * K + l) * K * 2;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) U[e] = u[e];
+#pragma unroll
+  for (int m = 0; m < kMaxDirs; ++m)
+    if (m < K) {
+      X[2 * m] = x[2 * m];
+      X[2 * m + 1] = x[2 * m + 1];
+    }
+}
+
+// d -= x m for the complex scalar x (re, im) and the 2x2 complex matrix m (8 reals)
+__device__ inline void sub_scaled(double *d, double xr, double xi, const double *m) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    d[2 * e] -= xr * m[2 * e] - xi * m[2 * e + 1];
+    d[2 * e + 1] -= xr * m[2 * e + 1] + xi * m[2 * e];
+  }
+}
+
+// Every direction's D_l at the current point from the coherency statistics (grid: tile x l, one
+// lane per baseline); direction 0's also becomes the accepted and start point of the next LM run.
+__global__ __launch_bounds__(64) void k_dall(Problem pb, Layout L, Buffers B) {
+  const int tile = blockIdx.x, l = blockIdx.y, f = L.tile_f[tile];
+  const int Kf = L.ndir[f], nb = L.nb[f];
+  const int bi = L.tile_b0[tile] + threadIdx.x;
+  if (l >= Kf || threadIdx.x >= pb.bpt || bi >= nb) return;
+  const int K = pb.K, N = pb.N;
+  const int64_t gb = (int64_t)L.bl_off[f] + bi;
+  const int p = L.bl_p[gb], q = L.bl_q[gb];
+  const double *X = B.Xcoh + (gb * K + l) * K * 2;
+  double d[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) d[e] = B.Ucoh[(gb * K + l) * 8 + e];
+  for (int m = 0; m < Kf; ++m) {
+    const double *Jm = B.J + ((int64_t)f * K + m) * N * 8;
+    double mm[8];
+    jjh(Jm + 8 * p, Jm + 8 * q, mm);
+    sub_scaled(d, X[2 * m], X[2 * m + 1], mm);
+  }
+  double *D = B.Dall + (gb * K + l) * 8;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) D[e] = d[e];
+  if (l == 0) {
+    double *Da = d_accepted(B, f) + 8 * gb;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      Da[e] = d[e];
+      B.Dstart[8 * gb + e] = d[e];
+    }
+  }
+}
+
+// End of direction k's LM run (the SAGE commit) without a pass over the samples (grid: tile x l,
+// one lane per baseline): with dM = J_kp J_kq^H - J0_p J0_q^H (J0 the run's start point), the
+// residual R - c_k dM has D_l - X_lk dM for every direction l, and energy
+// E - 2 Re sum_e conj(dM_e) D_k,e + X_kk ||dM||^2 (the direction-k workgroup updates the tile's
+// energy and cost partial).  The next direction's D becomes the accepted and start point of its
+// LM run.
+__global__ __launch_bounds__(64) void k_commit_stats(Problem pb, Layout L, Buffers B, int k) {
+  const int tile = blockIdx.x, l = blockIdx.y, f = L.tile_f[tile];
+  const int Kf = L.ndir[f], nb = L.nb[f];
+  if (k >= Kf || l >= Kf) return;   // uniform
+  const int K = pb.K, N = pb.N, next = k + 1 < Kf ? k + 1 : 0;
+  const int bi = L.tile_b0[tile] + threadIdx.x;
+  const bool live = threadIdx.x < pb.bpt && bi < nb;
+  double part = 0.0;
+  if (live) {
+    const int64_t gb = (int64_t)L.bl_off[f] + bi;
+    const int p = L.bl_p[gb], q = L.bl_q[gb];
+    const double *J1 = B.J + ((int64_t)f * K + k) * N * 8, *J0 = B.Jstart + (int64_t)f * N * 8;
+    double m1[8], m0[8], dm[8];
+    jjh(J1 + 8 * p, J1 + 8 * q, m1);
+    jjh(J0 + 8 * p, J0 + 8 * q, m0);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) dm[e] = m1[e] - m0[e];
+    const double *X = B.Xcoh + ((gb * K + l) * K + k) * 2;
+    double *D = B.Dall + (gb * K + l) * 8;
+    double d[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) d[e] = D[e];
+    if (l == k) {
+      double cross = 0.0, norm = 0.0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        cross = fma(dm[e], d[e], cross);
+        norm = fma(dm[e], dm[e], norm);
+      }
+      part = fma(X[0], norm, -2.0 * cross);
+    }
+    sub_scaled(d, X[0], X[1], dm);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) D[e] = d[e];
+    if (l == next) {
+      double *Da = d_accepted(B, f) + 8 * gb;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        Da[e] = d[e];
+        B.Dstart[8 * gb + e] = d[e];
+      }
+    }
+  }
+  if (l == k) {
+    part = wave_sum(part);
+    if (threadIdx.x == 0) {
+      const double e = B.Epart[tile] + part;
+      B.Epart[tile] = e;
+      B.cost_part[tile] = e;
+    }
+  }
 }
 
 // One workgroup per tile (grid = ntiles), or a persistent grid that strides over the tiles.
@@ -356,11 +508,25 @@ __global__ __launch_bounds__(kBlock) void k_model(Problem pb, Layout L, Buffers 
 
 template <typename T>
 hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
-  return launch_mode<T, SM_REFRESH>(pb, L, B, 0, s);
+  const hipError_t e = launch_mode<T, SM_REFRESH>(pb, L, B, 0, s);
+  if (e != hipSuccess || pb.ntiles == 0) return e;
+  if (pb.bpt > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dall, dim3(pb.ntiles, pb.K), dim3(64), 0, s, pb, L, B);
+  return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_commit(const Problem &pb, const Layout &L, const Buffers &B, int k, hipStream_t s) {
-  return launch_mode<T, SM_COMMIT>(pb, L, B, k, s);
+  if (pb.ntiles == 0) return hipSuccess;
+  if (pb.bpt > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_commit_stats, dim3(pb.ntiles, pb.K), dim3(64), 0, s, pb, L, B, k);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_coh_stats(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
+  if (pb.ntiles == 0) return hipSuccess;
+  if (pb.bpt > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_coh_stats<T>, dim3(pb.ntiles, pb.K), dim3(64), 0, s, pb, L, B);
+  return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_model(const Problem &pb, const Layout &L, const Buffers &B, void *model_out,
@@ -384,6 +550,8 @@ hipError_t launch_pack(const Problem &pb, const Layout &L, const void *vis, cons
   return hipGetLastError();
 }
 
+template hipError_t launch_coh_stats<float>(const Problem &, const Layout &, const Buffers &, hipStream_t);
+template hipError_t launch_coh_stats<double>(const Problem &, const Layout &, const Buffers &, hipStream_t);
 template hipError_t launch_refresh<float>(const Problem &, const Layout &, const Buffers &, hipStream_t);
 template hipError_t launch_refresh<double>(const Problem &, const Layout &, const Buffers &, hipStream_t);
 hipError_t launch_trial_stats(const Problem &pb, const Layout &L, const Buffers &B, int k,
