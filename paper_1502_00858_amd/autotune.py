@@ -1,4 +1,4 @@
-"""Tile-shape tuner for the streaming passes (refresh, SAGE commit).
+"""Tile-shape tuner for the streaming pass (the residual's energy at the start of a local step).
 
 Two launch parameters of calib_config shape those passes:
 
@@ -26,7 +26,7 @@ import numpy as np
 from . import calib
 
 GROUPS = (4, 8, 16, 32, 64)
-STREAM_KERNELS = ("refresh", "commit")
+STREAM_KERNELS = ("refresh",)
 
 
 def shape_key(data: dict, precision: int) -> str:

@@ -561,10 +561,9 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
     if (c->mem.alloc(&p_, (bytes)) != hipSuccess) return fail_alloc(#ptr);                     \
     ptr = reinterpret_cast<decltype(ptr)>(p_);                                                 \
   } while (0)
-  void *Vp, *Cp, *R;
+  void *Vp, *Cp;
   double *Sb;
   DALLOC(Vp, (size_t)so * 8 * elt);
-  DALLOC(R, (size_t)so * 8 * elt);
   DALLOC(Cp, (size_t)co * 2 * elt);
   DALLOC(Sb, (size_t)sbo * sizeof(double));
   const size_t nj = (size_t)P * K * N * 8, nz = (size_t)K * Q * N * 8;
@@ -606,7 +605,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   }
   int *flagbuf;
   DALLOC(flagbuf, 2 * sizeof(int));
-  B.V = Vp; B.R = R; B.C = Cp; B.Sb = Sb; B.rho = d_rho; B.basis = basis; B.fitw = fitw;
+  B.V = Vp; B.C = Cp; B.Sb = Sb; B.rho = d_rho; B.basis = basis; B.fitw = fitw;
 
   hipStream_t s = c->stream;
   auto dev = [&](hipError_t e, const char *what) -> bool {

@@ -66,7 +66,6 @@ constexpr int kBlockedSolverMaxSubbands = 128;   // automatic choice: blocked be
 
 struct Buffers {
   const void *V;   // packed visibilities (stream type)
-  void *R;         // residual V - model (stream type)
   const void *C;   // packed coherencies (stream type)
   const double *Sb;
   double *Sd;                           // [P][K][N][N] S_b of pair (p, q) in both orders, 0 if none

@@ -1,24 +1,26 @@
-// Streaming kernels of the local step: they read the packed visibilities / residuals and
-// coherencies once per pass, in the baseline-major layout, and reduce per-baseline statistics.
+// Kernels of the local step over the packed visibilities and coherencies (baseline-major).
 //
-//   refresh : R = V - sum_k c_k J_kp J_kq^H            (Section 2 visibility model; the full
-//             residual at the start of a local step), plus the statistics of direction 0
-//   commit  : R <- R - c_k (M_final - M_start)         (end of direction k), plus the statistics
-//             of the next direction
-// Both accumulate sum ||R||^2 and D_b = sum conj(c) R for the direction whose Levenberg-Marquardt
-// run follows.  A trial point of that run, r = R - c_k (M_trial - M_start) (the SAGE expectation
-// V_k = R + c_k M_start of Section 3 minus the trial model), needs no pass over the samples: its
-// cost and D_b follow from these statistics and S_b (k_trial_stats).
+// The coherency of an unpolarised source is a scalar times I2 (Section 2) and the Jones matrices
+// are constant over a baseline's samples, so everything the Levenberg-Marquardt runs need from
+// the residual R = V - sum_l c_l J_lp J_lq^H (Section 2 visibility model) is per-baseline sums:
+// D_l = sum_s conj(c_ls) R_s for every direction l, and the energy sum_s ||R_s||^2.
+//   k_coh_stats    (once)              U_l = sum conj(c_l) V, X_lm = sum conj(c_l) c_m per baseline
+//   refresh        (start of a local step) the energy, streaming V and the coherencies once
+//                  (k_stream), and every D_l = U_l - sum_m X_lm M_m (k_dall)
+//   k_trial_stats  (each LM trial point) cost and D_b of r = R - c_k (M_trial - M_start) (the
+//                  SAGE expectation V_k = R + c_k M_start of Section 3 minus the trial model)
+//   k_commit_stats (end of direction k)  R <- R - c_k (M_final - M_start) as an update of every
+//                  D_l and of the energy
 //
 // The coherency of an unpolarised source is a scalar times I2 (Section 2), so one complex value
 // per sample and direction is streamed.  The Jones matrices are time invariant over the interval
 // (Section 2), so the 2x2 products M = J_p J_q^H are formed once per baseline in FP64.
 //
-// Work decomposition: a tile is a run of kBlock/G consecutive baselines of one subband; G lanes
-// of a wavefront share a baseline and stride over its T*n_chan samples, so consecutive lanes
-// read consecutive 32-byte (float) or 64-byte (double) samples.  Per-baseline sums are reduced
-// across the G lanes with cross-lane shuffles in FP64; the per-tile cost is reduced through LDS
-// into one FP64 partial per tile, summed later in a fixed order (run-to-run deterministic).
+// Work decomposition: a tile is a run of kBlock/G consecutive baselines of one subband.  In the
+// streaming pass G lanes of a wavefront share a baseline and stride over its T*n_chan samples, so
+// consecutive lanes read consecutive 32-byte (float) or 64-byte (double) samples; the per-tile
+// energy is reduced into one FP64 partial per tile, summed later in a fixed order (run-to-run
+// deterministic).  The per-baseline kernels run one wavefront per tile, one lane per baseline.
 #include "calib_internal.h"
 #include "wave_reduce.h"
 
@@ -26,7 +28,6 @@ namespace calib {
 
 namespace {
 
-enum { SM_REFRESH = 0, SM_COMMIT = 2 };
 
 __device__ inline void jjh(const double *__restrict__ a, const double *__restrict__ b, double *m) {
   // m = a b^H for 2x2 complex matrices stored as 8 doubles (row-major, re/im interleaved)
@@ -96,114 +97,58 @@ __device__ inline double block_sum(double v, double *red) {
   return s;
 }
 
-template <typename T, int G, int MODE>
-__device__ inline void stream_tile(const Problem &pb, const Layout &L, const Buffers &B, int k,
-                                   int tile, T (*Msh)[(MODE == SM_REFRESH) ? kMaxDirs : 1][8],
-                                   double *red) {
+// Energy of the residual R = V - sum_l c_l J_lp J_lq^H over one tile (one FP64 partial per
+// tile); R itself is not stored.  G lanes share a baseline and stride over its samples.
+template <typename T, int G>
+__device__ inline void stream_tile(const Problem &pb, const Layout &L, const Buffers &B, int tile,
+                                   T (*Msh)[kMaxDirs][8], double *red) {
   const int f = L.tile_f[tile];
   const int Kf = L.ndir[f];
-  if (MODE == SM_COMMIT && k >= Kf) return;
-
   const int nb = L.nb[f], spb = L.spb[f];
   const int grp = threadIdx.x / G, lane = threadIdx.x % G;
   const int bi = L.tile_b0[tile] + grp;
   const bool live = bi < nb;
   const int N = pb.N, K = pb.K;
-  const int kst = (MODE == SM_REFRESH) ? 0 : (k + 1 < Kf ? k + 1 : 0);
   const int64_t gb = (int64_t)L.bl_off[f] + bi;
   const int64_t s0 = L.samp_off[f] + (int64_t)bi * spb;
   const T *C = static_cast<const T *>(B.C);
-  const T *cst = C + 2 * (L.coh_off[f] + ((int64_t)kst * nb + bi) * spb);
-
-  T dM[8];
-  if (MODE == SM_REFRESH) {
-    if (live) {
-      const int p = L.bl_p[gb], q = L.bl_q[gb];
-      for (int l = lane; l < Kf; l += G) {
-        double m[8];
-        const double *Jl = B.J + ((int64_t)f * K + l) * N * 8;
-        jjh(Jl + 8 * p, Jl + 8 * q, m);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) Msh[grp][l][e] = (T)m[e];
-      }
-    }
-    __syncthreads();
-  } else if (live) {
+  if (live) {
     const int p = L.bl_p[gb], q = L.bl_q[gb];
-    const double *J1 = B.J + ((int64_t)f * K + k) * N * 8;
-    const double *J0 = B.Jstart + (int64_t)f * N * 8;
-    double m1[8], m0[8];
-    jjh(J1 + 8 * p, J1 + 8 * q, m1);
-    jjh(J0 + 8 * p, J0 + 8 * q, m0);
+    for (int l = lane; l < Kf; l += G) {
+      double m[8];
+      const double *Jl = B.J + ((int64_t)f * K + l) * N * 8;
+      jjh(Jl + 8 * p, Jl + 8 * q, m);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) dM[e] = (T)(m1[e] - m0[e]);
+      for (int e = 0; e < 8; ++e) Msh[grp][l][e] = (T)m[e];
+    }
   }
-
+  __syncthreads();
   double cost = 0.0;
-  double D[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (live) {
     const T *V = static_cast<const T *>(B.V);
-    T *R = static_cast<T *>(B.R);
-    const T *ck = C + 2 * (L.coh_off[f] + ((int64_t)k * nb + bi) * spb);
     for (int s = lane; s < spb; s += G) {
       T r[8];
-      if (MODE == SM_REFRESH) {
-        load8<T>(V + 8 * (s0 + s), r);
-        for (int l = 0; l < Kf; ++l) {
-          T cr, ci;
-          load2<T>(C + 2 * (L.coh_off[f] + ((int64_t)l * nb + bi) * spb + s), cr, ci);
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const T mr = Msh[grp][l][2 * e], mi = Msh[grp][l][2 * e + 1];
-            r[2 * e] -= cr * mr - ci * mi;
-            r[2 * e + 1] -= cr * mi + ci * mr;
-          }
-        }
-        store8<T>(R + 8 * (s0 + s), r);
-      } else {
-        load8<T>(R + 8 * (s0 + s), r);
+      load8<T>(V + 8 * (s0 + s), r);
+      for (int l = 0; l < Kf; ++l) {
         T cr, ci;
-        load2<T>(ck + 2 * s, cr, ci);
+        load2<T>(C + 2 * (L.coh_off[f] + ((int64_t)l * nb + bi) * spb + s), cr, ci);
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          r[2 * e] -= cr * dM[2 * e] - ci * dM[2 * e + 1];
-          r[2 * e + 1] -= cr * dM[2 * e + 1] + ci * dM[2 * e];
+          const T mr = Msh[grp][l][2 * e], mi = Msh[grp][l][2 * e + 1];
+          r[2 * e] -= cr * mr - ci * mi;
+          r[2 * e + 1] -= cr * mi + ci * mr;
         }
-        store8<T>(R + 8 * (s0 + s), r);
       }
       T ss = 0;
 #pragma unroll
       for (int e = 0; e < 8; ++e) ss += r[e] * r[e];
       cost += (double)ss;
-      T cr, ci;
-      load2<T>(cst + 2 * s, cr, ci);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        // conj(c) * r
-        D[2 * e] += (double)(cr * r[2 * e] + ci * r[2 * e + 1]);
-        D[2 * e + 1] += (double)(cr * r[2 * e + 1] - ci * r[2 * e]);
-      }
-    }
-  }
-  // the eight butterflies advance together (independent exchanges within a step)
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1)
-#pragma unroll
-    for (int e = 0; e < 8; ++e) D[e] += __shfl_xor(D[e], o, G);
-  if (live && lane == 0) {
-    // the accepted point of the next LM run and its start point, from which its trial points'
-    // statistics derive
-    double *Dout = d_accepted(B, f) + 8 * gb;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      Dout[e] = D[e];
-      B.Dstart[8 * gb + e] = D[e];
     }
   }
   const double tot = block_sum(cost, red);
   if (threadIdx.x == 0) {
     B.cost_part[tile] = tot;
-    if (MODE == SM_REFRESH) B.Epart[tile] = tot;
+    B.Epart[tile] = tot;
   }
 }
 
@@ -395,28 +340,27 @@ __global__ __launch_bounds__(64) void k_commit_stats(Problem pb, Layout L, Buffe
 }
 
 // One workgroup per tile (grid = ntiles), or a persistent grid that strides over the tiles.
-template <typename T, int G, int MODE>
-__global__ __launch_bounds__(kBlock) void k_stream(Problem pb, Layout L, Buffers B, int k) {
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_stream(Problem pb, Layout L, Buffers B) {
   constexpr int BPT = kBlock / G;
-  constexpr int MD = (MODE == SM_REFRESH) ? kMaxDirs : 1;
-  __shared__ T Msh[BPT][MD][8];
+  __shared__ T Msh[BPT][kMaxDirs][8];
   __shared__ double red[kBlock / 64];
   for (int tile = blockIdx.x; tile < pb.ntiles; tile += gridDim.x) {
-    stream_tile<T, G, MODE>(pb, L, B, k, tile, Msh, red);
+    stream_tile<T, G>(pb, L, B, tile, Msh, red);
     __syncthreads();
   }
 }
 
-template <typename T, int MODE>
-hipError_t launch_mode(const Problem &pb, const Layout &L, const Buffers &B, int k, hipStream_t s) {
+template <typename T>
+hipError_t launch_energy(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
   if (pb.ntiles == 0) return hipSuccess;
   dim3 grid(pb.stream_grid > 0 && pb.stream_grid < pb.ntiles ? pb.stream_grid : pb.ntiles), block(kBlock);
   switch (pb.group) {
-    case 4: hipLaunchKernelGGL((k_stream<T, 4, MODE>), grid, block, 0, s, pb, L, B, k); break;
-    case 8: hipLaunchKernelGGL((k_stream<T, 8, MODE>), grid, block, 0, s, pb, L, B, k); break;
-    case 16: hipLaunchKernelGGL((k_stream<T, 16, MODE>), grid, block, 0, s, pb, L, B, k); break;
-    case 32: hipLaunchKernelGGL((k_stream<T, 32, MODE>), grid, block, 0, s, pb, L, B, k); break;
-    case 64: hipLaunchKernelGGL((k_stream<T, 64, MODE>), grid, block, 0, s, pb, L, B, k); break;
+    case 4: hipLaunchKernelGGL((k_stream<T, 4>), grid, block, 0, s, pb, L, B); break;
+    case 8: hipLaunchKernelGGL((k_stream<T, 8>), grid, block, 0, s, pb, L, B); break;
+    case 16: hipLaunchKernelGGL((k_stream<T, 16>), grid, block, 0, s, pb, L, B); break;
+    case 32: hipLaunchKernelGGL((k_stream<T, 32>), grid, block, 0, s, pb, L, B); break;
+    case 64: hipLaunchKernelGGL((k_stream<T, 64>), grid, block, 0, s, pb, L, B); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -508,7 +452,7 @@ __global__ __launch_bounds__(kBlock) void k_model(Problem pb, Layout L, Buffers 
 
 template <typename T>
 hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
-  const hipError_t e = launch_mode<T, SM_REFRESH>(pb, L, B, 0, s);
+  const hipError_t e = launch_energy<T>(pb, L, B, s);
   if (e != hipSuccess || pb.ntiles == 0) return e;
   if (pb.bpt > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_dall, dim3(pb.ntiles, pb.K), dim3(64), 0, s, pb, L, B);
