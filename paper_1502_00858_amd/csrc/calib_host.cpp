@@ -519,6 +519,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   pb.ntiles = (int)tile_f.size();
   pb.group = group;
   pb.bpt = bpt;
+  pb.nbt = nb_total;
   pb.stream_grid = cfg->stream_grid > 0 ? cfg->stream_grid : 0;
   pb.lm_tol = cfg->lm_tol;
   pb.solver = cfg->solver == 1 ? kSolverSingle

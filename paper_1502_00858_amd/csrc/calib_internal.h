@@ -55,6 +55,7 @@ struct Problem {
   int ntiles;
   int group;       // lanes per baseline in the streaming kernels
   int bpt;         // baselines per tile = kBlock / group
+  int nbt;         // unflagged baselines over all subbands
   int stream_grid; // 0 = one workgroup per tile, else persistent grid size
   double lm_tol;   // LM stops once a step's predicted decrease <= lm_tol * F (0 = never)
   int solver;      // normal-equation solver: kSolverSingle or kSolverBlocked
@@ -73,9 +74,11 @@ struct Buffers {
   double *Jstart, *Jtrial;              // [P][N][8] active direction
   double *D0, *D1;                      // [sum nb][8] D_b, accepted and trial point (LmState::dsel)
   double *Dstart;                       // [sum nb][8] D_b at the LM run's start point
-  double *Ucoh;                         // [sum nb][K][8] sum_s conj(c_l) V per direction l
-  double *Xcoh;                         // [sum nb][K][K][2] sum_s conj(c_l) c_m
-  double *Dall;                         // [sum nb][K][8] D_l of the current residual, every l
+  // per-baseline tables, direction-major with the baseline index fastest (a wavefront's lanes,
+  // consecutive baselines, read consecutive entries)
+  double *Ucoh;                         // [K][sum nb][8] sum_s conj(c_l) V per direction l
+  double *Xcoh;                         // [K][K][sum nb][2] sum_s conj(c_l) c_m
+  double *Dall;                         // [K][sum nb][8] D_l of the current residual, every l
   double *Epart;                        // [ntiles] energy of the current residual per tile
   double *H;                            // [P][npad][nf]
   double *Linv;                         // [P][nf/16][16*16] inverses of the diagonal tiles

@@ -161,12 +161,15 @@ __device__ inline void stream_tile(const Problem &pb, const Layout &L, const Buf
 // with D0 = sum_s conj(c_s) R_s and S_b = sum_s |c_s|^2.  The first term, summed over the
 // subband, is the data cost at the start point (LmState::E0), added by the subband's first tile;
 // the tile partials sum to the data cost at the trial point as the streaming pass's do.
-__global__ __launch_bounds__(64) void k_trial_stats(Problem pb, Layout L, Buffers B, int k) {
-  const int tile = blockIdx.x, f = L.tile_f[tile];
+constexpr int kStatTiles = 4;   // tiles per workgroup of the per-baseline kernels, one per wavefront
+__global__ __launch_bounds__(64 * kStatTiles) void k_trial_stats(Problem pb, Layout L, Buffers B, int k) {
+  const int tile = kStatTiles * blockIdx.x + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (tile >= pb.ntiles) return;   // uniform per wavefront
+  const int f = L.tile_f[tile];
   if (k >= L.ndir[f] || !B.lm[f].chol_ok || B.lm[f].done) return;   // uniform
-  const int nb = L.nb[f], bi = L.tile_b0[tile] + threadIdx.x;
+  const int nb = L.nb[f], bi = L.tile_b0[tile] + lane;
   double part = 0.0;
-  if (threadIdx.x < pb.bpt && bi < nb) {
+  if (lane < pb.bpt && bi < nb) {
     const int64_t gb = (int64_t)L.bl_off[f] + bi;
     const int p = L.bl_p[gb], q = L.bl_q[gb];
     const double *Jt = B.Jtrial + (int64_t)f * pb.N * 8, *J0 = B.Jstart + (int64_t)f * pb.N * 8;
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(64) void k_trial_stats(Problem pb, Layout L, Buffer
     part = fma(S, norm, -2.0 * cross);
   }
   part = wave_sum(part);
-  if (threadIdx.x == 0) B.cost_part[tile] = part + (tile == L.tile_off[f] ? B.lm[f].E0 : 0.0);
+  if (lane == 0) B.cost_part[tile] = part + (tile == L.tile_off[f] ? B.lm[f].E0 : 0.0);
 }
 
 // Per-baseline coherency statistics, once per context (grid: tile x direction l, one lane per
@@ -196,11 +199,13 @@ __global__ __launch_bounds__(64) void k_trial_stats(Problem pb, Layout L, Buffer
 // samples, the residual's sums that the LM runs need follow from these: at a point with models
 // M_m, D_l = sum_s conj(c_ls) R_s = U_l - sum_m X_lm M_m.
 template <typename T>
-__global__ __launch_bounds__(64) void k_coh_stats(Problem pb, Layout L, Buffers B) {
-  const int tile = blockIdx.x, l = blockIdx.y, f = L.tile_f[tile];
+__global__ __launch_bounds__(64 * kStatTiles) void k_coh_stats(Problem pb, Layout L, Buffers B) {
+  const int tile = kStatTiles * blockIdx.x + (threadIdx.x >> 6), lane = threadIdx.x & 63, l = blockIdx.y;
+  if (tile >= pb.ntiles) return;
+  const int f = L.tile_f[tile];
   const int Kf = L.ndir[f], nb = L.nb[f], spb = L.spb[f];
-  const int bi = L.tile_b0[tile] + threadIdx.x;
-  if (l >= Kf || threadIdx.x >= pb.bpt || bi >= nb) return;
+  const int bi = L.tile_b0[tile] + lane;
+  if (l >= Kf || lane >= pb.bpt || bi >= nb) return;
   const int K = pb.K;
   const int64_t gb = (int64_t)L.bl_off[f] + bi, s0 = L.samp_off[f] + (int64_t)bi * spb;
   const T *V = static_cast<const T *>(B.V), *C = static_cast<const T *>(B.C);
@@ -227,14 +232,16 @@ __global__ __launch_bounds__(64) void k_coh_stats(Problem pb, Layout L, Buffers 
       }
     }
   }
-  double *U = B.Ucoh + (gb * K + l) * 8, *X = B.Xcoh + (gb * K + l) * K * 2;
+  const int64_t nbt = pb.nbt;
+  double *U = B.Ucoh + ((int64_t)l * nbt + gb) * 8;
 #pragma unroll
   for (int e = 0; e < 8; ++e) U[e] = u[e];
 #pragma unroll
   for (int m = 0; m < kMaxDirs; ++m)
     if (m < K) {
-      X[2 * m] = x[2 * m];
-      X[2 * m + 1] = x[2 * m + 1];
+      double *X = B.Xcoh + (((int64_t)l * K + m) * nbt + gb) * 2;
+      X[0] = x[2 * m];
+      X[1] = x[2 * m + 1];
     }
 }
 
@@ -249,25 +256,28 @@ __device__ inline void sub_scaled(double *d, double xr, double xi, const double 
 
 // Every direction's D_l at the current point from the coherency statistics (grid: tile x l, one
 // lane per baseline); direction 0's also becomes the accepted and start point of the next LM run.
-__global__ __launch_bounds__(64) void k_dall(Problem pb, Layout L, Buffers B) {
-  const int tile = blockIdx.x, l = blockIdx.y, f = L.tile_f[tile];
+__global__ __launch_bounds__(64 * kStatTiles) void k_dall(Problem pb, Layout L, Buffers B) {
+  const int tile = kStatTiles * blockIdx.x + (threadIdx.x >> 6), lane = threadIdx.x & 63, l = blockIdx.y;
+  if (tile >= pb.ntiles) return;
+  const int f = L.tile_f[tile];
   const int Kf = L.ndir[f], nb = L.nb[f];
-  const int bi = L.tile_b0[tile] + threadIdx.x;
-  if (l >= Kf || threadIdx.x >= pb.bpt || bi >= nb) return;
+  const int bi = L.tile_b0[tile] + lane;
+  if (l >= Kf || lane >= pb.bpt || bi >= nb) return;
   const int K = pb.K, N = pb.N;
   const int64_t gb = (int64_t)L.bl_off[f] + bi;
   const int p = L.bl_p[gb], q = L.bl_q[gb];
-  const double *X = B.Xcoh + (gb * K + l) * K * 2;
+  const int64_t nbt = pb.nbt;
   double d[8];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) d[e] = B.Ucoh[(gb * K + l) * 8 + e];
+  for (int e = 0; e < 8; ++e) d[e] = B.Ucoh[((int64_t)l * nbt + gb) * 8 + e];
   for (int m = 0; m < Kf; ++m) {
     const double *Jm = B.J + ((int64_t)f * K + m) * N * 8;
+    const double *X = B.Xcoh + (((int64_t)l * K + m) * nbt + gb) * 2;
     double mm[8];
     jjh(Jm + 8 * p, Jm + 8 * q, mm);
-    sub_scaled(d, X[2 * m], X[2 * m + 1], mm);
+    sub_scaled(d, X[0], X[1], mm);
   }
-  double *D = B.Dall + (gb * K + l) * 8;
+  double *D = B.Dall + ((int64_t)l * nbt + gb) * 8;
 #pragma unroll
   for (int e = 0; e < 8; ++e) D[e] = d[e];
   if (l == 0) {
@@ -286,13 +296,15 @@ __global__ __launch_bounds__(64) void k_dall(Problem pb, Layout L, Buffers B) {
 // E - 2 Re sum_e conj(dM_e) D_k,e + X_kk ||dM||^2 (the direction-k workgroup updates the tile's
 // energy and cost partial).  The next direction's D becomes the accepted and start point of its
 // LM run.
-__global__ __launch_bounds__(64) void k_commit_stats(Problem pb, Layout L, Buffers B, int k) {
-  const int tile = blockIdx.x, l = blockIdx.y, f = L.tile_f[tile];
+__global__ __launch_bounds__(64 * kStatTiles) void k_commit_stats(Problem pb, Layout L, Buffers B, int k) {
+  const int tile = kStatTiles * blockIdx.x + (threadIdx.x >> 6), lane = threadIdx.x & 63, l = blockIdx.y;
+  if (tile >= pb.ntiles) return;   // uniform per wavefront
+  const int f = L.tile_f[tile];
   const int Kf = L.ndir[f], nb = L.nb[f];
-  if (k >= Kf || l >= Kf) return;   // uniform
+  if (k >= Kf || l >= Kf) return;   // uniform per wavefront
   const int K = pb.K, N = pb.N, next = k + 1 < Kf ? k + 1 : 0;
-  const int bi = L.tile_b0[tile] + threadIdx.x;
-  const bool live = threadIdx.x < pb.bpt && bi < nb;
+  const int bi = L.tile_b0[tile] + lane;
+  const bool live = lane < pb.bpt && bi < nb;
   double part = 0.0;
   if (live) {
     const int64_t gb = (int64_t)L.bl_off[f] + bi;
@@ -303,8 +315,9 @@ __global__ __launch_bounds__(64) void k_commit_stats(Problem pb, Layout L, Buffe
     jjh(J0 + 8 * p, J0 + 8 * q, m0);
 #pragma unroll
     for (int e = 0; e < 8; ++e) dm[e] = m1[e] - m0[e];
-    const double *X = B.Xcoh + ((gb * K + l) * K + k) * 2;
-    double *D = B.Dall + (gb * K + l) * 8;
+    const int64_t nbt = pb.nbt;
+    const double *X = B.Xcoh + (((int64_t)l * K + k) * nbt + gb) * 2;
+    double *D = B.Dall + ((int64_t)l * nbt + gb) * 8;
     double d[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) d[e] = D[e];
@@ -331,7 +344,7 @@ __global__ __launch_bounds__(64) void k_commit_stats(Problem pb, Layout L, Buffe
   }
   if (l == k) {
     part = wave_sum(part);
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
       const double e = B.Epart[tile] + part;
       B.Epart[tile] = e;
       B.cost_part[tile] = e;
@@ -455,21 +468,24 @@ hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, 
   const hipError_t e = launch_energy<T>(pb, L, B, s);
   if (e != hipSuccess || pb.ntiles == 0) return e;
   if (pb.bpt > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dall, dim3(pb.ntiles, pb.K), dim3(64), 0, s, pb, L, B);
+  hipLaunchKernelGGL(k_dall, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles, pb.K), dim3(64 * kStatTiles),
+                     0, s, pb, L, B);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_commit(const Problem &pb, const Layout &L, const Buffers &B, int k, hipStream_t s) {
   if (pb.ntiles == 0) return hipSuccess;
   if (pb.bpt > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_commit_stats, dim3(pb.ntiles, pb.K), dim3(64), 0, s, pb, L, B, k);
+  hipLaunchKernelGGL(k_commit_stats, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles, pb.K),
+                     dim3(64 * kStatTiles), 0, s, pb, L, B, k);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_coh_stats(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
   if (pb.ntiles == 0) return hipSuccess;
   if (pb.bpt > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_coh_stats<T>, dim3(pb.ntiles, pb.K), dim3(64), 0, s, pb, L, B);
+  hipLaunchKernelGGL(k_coh_stats<T>, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles, pb.K),
+                     dim3(64 * kStatTiles), 0, s, pb, L, B);
   return hipGetLastError();
 }
 template <typename T>
@@ -502,7 +518,8 @@ hipError_t launch_trial_stats(const Problem &pb, const Layout &L, const Buffers 
                               hipStream_t s) {
   if (pb.ntiles == 0) return hipSuccess;
   if (pb.bpt > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_trial_stats, dim3(pb.ntiles), dim3(64), 0, s, pb, L, B, k);
+  hipLaunchKernelGGL(k_trial_stats, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles), dim3(64 * kStatTiles),
+                     0, s, pb, L, B, k);
   return hipGetLastError();
 }
 
