@@ -206,7 +206,7 @@ calib_status run_local_step(calib_ctx *c, int admm_iter, hipStream_t s) {
         const calib_status st = lm_iteration<T>(c, k, it, unreg, s);
         if (st != CALIB_OK) return st;
       }
-      HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, k, s); }));
+      HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, k, c->sage_sweeps > 1, s); }));
     }
   return CALIB_OK;
 }
@@ -227,7 +227,7 @@ calib_status lm_chunk(calib_ctx *c, int k, int ch, int unreg, hipStream_t s) {
   const int it0 = ch * kLmChunk, it1 = std::min(it0 + kLmChunk, c->lm_iters);
   if (ch == 0) {
     if (k > 0)
-      HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(c->pb, c->L, c->B, k - 1, s); }));
+      HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(c->pb, c->L, c->B, k - 1, c->sage_sweeps > 1, s); }));
     HIPCHK(c, timed(c, CALIB_KERNEL_LM_BEGIN, [&] { return launch_lm_begin(c->pb, c->L, c->B, k, unreg, s); }));
   }
   for (int it = it0; it < it1; ++it) {
@@ -300,7 +300,7 @@ calib_status run_local_step_chunked(calib_ctx *c, int admm_iter, bool graphs, hi
   for (int sw = 0; sw < c->sage_sweeps; ++sw)
     for (int k = 0; k < c->K; ++k) {
       if (k == 0 && sw > 0)
-        HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, c->K - 1, s); }));
+        HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, c->K - 1, c->sage_sweeps > 1, s); }));
       for (int ch = 0; ch < nch; ++ch) {
         const bool checked = std::min((ch + 1) * kLmChunk, c->lm_iters) < c->lm_iters;
         if (checked) *reinterpret_cast<volatile int *>(c->stop_flag) = -1;
@@ -321,7 +321,7 @@ calib_status run_local_step_chunked(calib_ctx *c, int admm_iter, bool graphs, hi
         }
       }
     }
-  HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, c->K - 1, s); }));
+  HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, c->K - 1, c->sage_sweeps > 1, s); }));
   return CALIB_OK;
 }
 
@@ -787,8 +787,8 @@ calib_status calib_warmstart_features(calib_ctx *ctx, const void *jones_prev2, c
   for (int k = 0; k < ctx->K; ++k) {
     HIPCHK(ctx, launch_lm_begin(pb, L, B, k, 1, s));
     HIPCHK(ctx, launch_ws_features(pb, L, B, k, J2, BZp, features, s));
-    HIPCHK(ctx, ctx->precision == CALIB_FP64 ? launch_commit<double>(pb, L, B, k, s)
-                                             : launch_commit<float>(pb, L, B, k, s));
+    HIPCHK(ctx, ctx->precision == CALIB_FP64 ? launch_commit<double>(pb, L, B, k, 0, s)
+                                             : launch_commit<float>(pb, L, B, k, 0, s));
   }
   return CALIB_OK;
 }

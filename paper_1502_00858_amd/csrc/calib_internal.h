@@ -106,7 +106,8 @@ hipError_t launch_coh_stats(const Problem &pb, const Layout &L, const Buffers &B
 template <typename T>
 hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
 template <typename T>
-hipError_t launch_commit(const Problem &pb, const Layout &L, const Buffers &B, int k, hipStream_t s);
+hipError_t launch_commit(const Problem &pb, const Layout &L, const Buffers &B, int k, int all,
+                         hipStream_t s);
 template <typename T>
 hipError_t launch_model(const Problem &pb, const Layout &L, const Buffers &B, void *model_out,
                         const int64_t *full_off, const int32_t *full_bmap, hipStream_t s);

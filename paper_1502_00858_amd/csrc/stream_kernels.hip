@@ -295,14 +295,17 @@ __global__ __launch_bounds__(64 * kStatTiles) void k_dall(Problem pb, Layout L, 
 // residual R - c_k dM has D_l - X_lk dM for every direction l, and energy
 // E - 2 Re sum_e conj(dM_e) D_k,e + X_kk ||dM||^2 (the direction-k workgroup updates the tile's
 // energy and cost partial).  The next direction's D becomes the accepted and start point of its
-// LM run.
-__global__ __launch_bounds__(64 * kStatTiles) void k_commit_stats(Problem pb, Layout L, Buffers B, int k) {
+// LM run.  Unless all is set only the directions after k are updated: within one SAGE sweep no
+// other is read again before the next local step's refresh rebuilds them all.
+__global__ __launch_bounds__(64 * kStatTiles) void k_commit_stats(Problem pb, Layout L, Buffers B, int k,
+                                                                   int all) {
   const int tile = kStatTiles * blockIdx.x + (threadIdx.x >> 6), lane = threadIdx.x & 63, l = blockIdx.y;
   if (tile >= pb.ntiles) return;   // uniform per wavefront
   const int f = L.tile_f[tile];
   const int Kf = L.ndir[f], nb = L.nb[f];
-  if (k >= Kf || l >= Kf) return;   // uniform per wavefront
+  if (k >= Kf || l >= Kf || (!all && l < k)) return;   // uniform per wavefront
   const int K = pb.K, N = pb.N, next = k + 1 < Kf ? k + 1 : 0;
+  const bool upd = all || l > k;
   const int bi = L.tile_b0[tile] + lane;
   const bool live = lane < pb.bpt && bi < nb;
   double part = 0.0;
@@ -330,10 +333,12 @@ __global__ __launch_bounds__(64 * kStatTiles) void k_commit_stats(Problem pb, La
       }
       part = fma(X[0], norm, -2.0 * cross);
     }
-    sub_scaled(d, X[0], X[1], dm);
+    if (upd) {
+      sub_scaled(d, X[0], X[1], dm);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) D[e] = d[e];
-    if (l == next) {
+      for (int e = 0; e < 8; ++e) D[e] = d[e];
+    }
+    if (upd && l == next) {
       double *Da = d_accepted(B, f) + 8 * gb;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
@@ -473,11 +478,12 @@ hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, 
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_commit(const Problem &pb, const Layout &L, const Buffers &B, int k, hipStream_t s) {
+hipError_t launch_commit(const Problem &pb, const Layout &L, const Buffers &B, int k, int all,
+                         hipStream_t s) {
   if (pb.ntiles == 0) return hipSuccess;
   if (pb.bpt > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_commit_stats, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles, pb.K),
-                     dim3(64 * kStatTiles), 0, s, pb, L, B, k);
+                     dim3(64 * kStatTiles), 0, s, pb, L, B, k, all);
   return hipGetLastError();
 }
 template <typename T>
@@ -523,8 +529,8 @@ hipError_t launch_trial_stats(const Problem &pb, const Layout &L, const Buffers 
   return hipGetLastError();
 }
 
-template hipError_t launch_commit<float>(const Problem &, const Layout &, const Buffers &, int, hipStream_t);
-template hipError_t launch_commit<double>(const Problem &, const Layout &, const Buffers &, int, hipStream_t);
+template hipError_t launch_commit<float>(const Problem &, const Layout &, const Buffers &, int, int, hipStream_t);
+template hipError_t launch_commit<double>(const Problem &, const Layout &, const Buffers &, int, int, hipStream_t);
 template hipError_t launch_model<float>(const Problem &, const Layout &, const Buffers &, void *,
                                         const int64_t *, const int32_t *, hipStream_t);
 template hipError_t launch_model<double>(const Problem &, const Layout &, const Buffers &, void *,
