@@ -68,6 +68,28 @@ def test_local_step_lm_trace_fp64(cal, oracle_mod, synth_mod):
     assert _rel(pb.predict(Jg), pb.predict(Jo)) < 1e-9
 
 
+def test_two_sage_sweeps_fp64(cal, oracle_mod, synth_mod):
+    """Two SAGE sweeps per local step: each commit then updates every direction's statistics (the
+    second sweep starts again from direction 0).  The last sweep's LM trace, the local step's J and
+    a short C-ADMM trajectory agree with the oracle."""
+    cfg = tiny_cfg(synth_mod, N=6, P=3, K=3, T=3, n_chan=2, lm_iters=4)
+    d = synth_mod.generate(cfg)
+    J0 = synth_mod.identity_jones(cfg.P, cfg.K, cfg.N)
+    c = _ctx(cal, d, 0, lm_iters=4, sage_sweeps=2)
+    c.local_step(0)
+    Jg = c.get(cal.FIELD_J).cpu().numpy()
+    trg = c.get(cal.FIELD_LM_TRACE).cpu().numpy()
+    pb = oracle_mod.Problem(d, lm_iters=4, sage_sweeps=2)
+    z = np.zeros_like(J0)
+    Jo, tro = pb.local_step(J0, z, z, trace=True)
+    np.testing.assert_array_equal(trg[..., 2], tro[:, 1, :, :, 2])
+    np.testing.assert_allclose(trg[..., 0], tro[:, 1, :, :, 0], rtol=1e-10)
+    assert _rel(pb.predict(Jg), pb.predict(Jo)) < 1e-9
+    trg = _ctx(cal, d, 0, lm_iters=4, sage_sweeps=2).solve(3)
+    tro = pb.admm_solve(J0, 3)["trace"]
+    np.testing.assert_allclose(trg[:, 0], tro[:, 0], rtol=1e-10)
+
+
 def test_consensus_step_fp64(cal, oracle_mod, synth_mod):
     cfg = tiny_cfg(synth_mod, N=5, P=6, Q=3, K=2, rho=2.0)
     d = synth_mod.generate(cfg)
