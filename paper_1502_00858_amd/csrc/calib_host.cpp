@@ -74,8 +74,6 @@ struct calib_ctx {
   // host skips the rest of a direction once it has (those iterations would change nothing but
   // trace rows, which one small launch writes instead)
   int *stop_flag = nullptr;                 // pinned host memory
-  std::vector<hipGraph_t> chunk_graphs;     // [K][chunks]
-  std::vector<hipGraphExec_t> chunk_execs;
   // warm start
   double *ws_jsave = nullptr;   // [P][K][N][8]
   double *ws_cost = nullptr;    // [2][P]
@@ -173,9 +171,10 @@ int choose_group(const std::vector<int32_t> &spb, const std::vector<int32_t> &nb
   return best;
 }
 
-// one LM iteration of direction k: normal equations, solve, trial point, accept / damping
+// one LM iteration of direction k: normal equations, solve, trial point, accept / damping; with
+// flag, the stop flag right after the solve
 template <typename T>
-calib_status lm_iteration(calib_ctx *c, int k, int it, int unreg, hipStream_t s) {
+calib_status lm_iteration(calib_ctx *c, int k, int it, int unreg, hipStream_t s, int *flag = nullptr) {
   const Problem &pb = c->pb;
   const Layout &L = c->L;
   const Buffers &B = c->B;
@@ -185,6 +184,7 @@ calib_status lm_iteration(calib_ctx *c, int k, int it, int unreg, hipStream_t s)
                ? launch_chol_blocked(pb, B, k, c->d_ndir, B.chol_ld, B.chol_fail, s)
                : launch_chol_solve_nd(pb, B, k, c->d_ndir, s);
   }));
+  if (flag) HIPCHK(c, launch_lm_stopped(pb, L, B, k, flag, s));
   HIPCHK(c, timed(c, CALIB_KERNEL_TRIAL, [&] { return launch_trial_stats(pb, L, B, k, s); }));
   HIPCHK(c, timed(c, CALIB_KERNEL_LM_UPDATE, [&] {
     return launch_lm_update_tr(pb, L, B, k, unreg, c->lm_trace, it, c->lm_iters, s);
@@ -219,9 +219,8 @@ calib_status local_step_on(calib_ctx *c, int admm_iter, hipStream_t s) {
 constexpr int kLmChunk = 1;   // LM iterations between the host's looks at the stop flag
 
 // Chunk ch of direction k's LM run.  Its first chunk opens the run, after the commit of the
-// previous direction when k > 0 (the stream order of run_local_step: commit k-1, begin k).  Every
-// chunk but the last ends with the stop flag (and, once every run has stopped, the trace rows of
-// the iterations that will not be launched).
+// previous direction when k > 0 (the stream order of run_local_step: commit k-1, begin k).  In
+// every chunk but the last, the final iteration writes the stop flag after its solve.
 template <typename T>
 calib_status lm_chunk(calib_ctx *c, int k, int ch, int unreg, hipStream_t s) {
   const int it0 = ch * kLmChunk, it1 = std::min(it0 + kLmChunk, c->lm_iters);
@@ -231,37 +230,10 @@ calib_status lm_chunk(calib_ctx *c, int k, int ch, int unreg, hipStream_t s) {
     HIPCHK(c, timed(c, CALIB_KERNEL_LM_BEGIN, [&] { return launch_lm_begin(c->pb, c->L, c->B, k, unreg, s); }));
   }
   for (int it = it0; it < it1; ++it) {
-    const calib_status st = lm_iteration<T>(c, k, it, unreg, s);
+    int *flag = (it == it1 - 1 && it1 < c->lm_iters) ? c->stop_flag : nullptr;
+    const calib_status st = lm_iteration<T>(c, k, it, unreg, s, flag);
     if (st != CALIB_OK) return st;
   }
-  if (it1 < c->lm_iters)
-    HIPCHK(c, launch_lm_stopped(c->pb, c->L, c->B, k, c->stop_flag, c->lm_trace, it1, c->lm_iters, s));
-  return CALIB_OK;
-}
-
-calib_status chunk_graph(calib_ctx *c, int k, int ch, hipGraphExec_t *out) {
-  const int nch = (c->lm_iters + kLmChunk - 1) / kLmChunk;
-  const size_t idx = (size_t)k * nch + ch;
-  if (c->chunk_execs.empty()) {
-    c->chunk_graphs.assign((size_t)c->K * nch, nullptr);
-    c->chunk_execs.assign((size_t)c->K * nch, nullptr);
-  }
-  if (!c->chunk_execs[idx]) {
-    if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-    HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-    calib_status st = c->precision == CALIB_FP64 ? lm_chunk<double>(c, k, ch, 0, c->cap_stream)
-                                                 : lm_chunk<float>(c, k, ch, 0, c->cap_stream);
-    hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
-    if (st != CALIB_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      return st;
-    }
-    if (e != hipSuccess) return fail(c, CALIB_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-    c->chunk_graphs[idx] = g;
-    HIPCHK(c, hipGraphInstantiate(&c->chunk_execs[idx], g, nullptr, nullptr, 0));
-  }
-  *out = c->chunk_execs[idx];
   return CALIB_OK;
 }
 
@@ -287,10 +259,11 @@ calib_status wait_stop_flag(calib_ctx *c, hipStream_t s, bool *stopped) {
 
 // The local step under the LM stopping rule (same results as run_local_step): after each chunk
 // but the last the host reads the stop flag and, once every run of the direction has stopped,
-// launches none of the remaining iterations.  Chunks run from captured graphs (admm_iter >= 1, no
-// kernel timing) or as direct launches.
+// launches none of the remaining iterations.  The kernels are launched directly, not from
+// captured graphs: the flag comes right after the solve, and while the trial point and the update
+// run the host already enqueues what follows (a graph per chunk was measured 2.8% slower).
 template <typename T>
-calib_status run_local_step_chunked(calib_ctx *c, int admm_iter, bool graphs, hipStream_t s) {
+calib_status run_local_step_chunked(calib_ctx *c, int admm_iter, hipStream_t s) {
   const int unreg = (admm_iter == 0 && (c->options & CALIB_OPT_UNREG_FIRST)) ? 1 : 0;
   const Problem &pb = c->pb;
   const Layout &L = c->L;
@@ -304,12 +277,7 @@ calib_status run_local_step_chunked(calib_ctx *c, int admm_iter, bool graphs, hi
       for (int ch = 0; ch < nch; ++ch) {
         const bool checked = std::min((ch + 1) * kLmChunk, c->lm_iters) < c->lm_iters;
         if (checked) *reinterpret_cast<volatile int *>(c->stop_flag) = -1;
-        if (graphs) {
-          hipGraphExec_t ge = nullptr;
-          const calib_status st = chunk_graph(c, k, ch, &ge);
-          if (st != CALIB_OK) return st;
-          HIPCHK(c, hipGraphLaunch(ge, s));
-        } else {
+        {
           const calib_status st = lm_chunk<T>(c, k, ch, unreg, s);
           if (st != CALIB_OK) return st;
         }
@@ -325,9 +293,9 @@ calib_status run_local_step_chunked(calib_ctx *c, int admm_iter, bool graphs, hi
   return CALIB_OK;
 }
 
-calib_status local_step_chunked_on(calib_ctx *c, int admm_iter, bool graphs, hipStream_t s) {
-  return c->precision == CALIB_FP64 ? run_local_step_chunked<double>(c, admm_iter, graphs, s)
-                                    : run_local_step_chunked<float>(c, admm_iter, graphs, s);
+calib_status local_step_chunked_on(calib_ctx *c, int admm_iter, hipStream_t s) {
+  return c->precision == CALIB_FP64 ? run_local_step_chunked<double>(c, admm_iter, s)
+                                    : run_local_step_chunked<float>(c, admm_iter, s);
 }
 
 // Lagrangian trace row, first-iteration alignment, Z, B_f Z, Y and residuals; the trace row is
@@ -371,10 +339,6 @@ const char *calib_last_error(const calib_ctx *ctx) {
 void calib_destroy(calib_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
-  for (hipGraphExec_t ge : ctx->chunk_execs)
-    if (ge) (void)hipGraphExecDestroy(ge);
-  for (hipGraph_t g : ctx->chunk_graphs)
-    if (g) (void)hipGraphDestroy(g);
   if (ctx->stop_flag) (void)hipHostFree(ctx->stop_flag);
   if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
   if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
@@ -675,7 +639,7 @@ calib_status admm_solve(calib_ctx *ctx, int32_t max_iters, double rel_cost_tol, 
     calib_status st = CALIB_OK;
     if (chunked) {
       const bool eager = n == 0 || ctx->timing;
-      st = local_step_chunked_on(ctx, n, !eager, ctx->stream);
+      st = local_step_chunked_on(ctx, n, ctx->stream);
       if (st == CALIB_OK) {
         if (eager) {
           st = admm_consensus_update(ctx, n);

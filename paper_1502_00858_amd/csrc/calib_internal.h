@@ -133,7 +133,7 @@ hipError_t launch_lm_update_tr(const Problem &pb, const Layout &L, const Buffers
                                double *lm_trace, int it, int lm_iters, hipStream_t s);
 hipError_t launch_dense_s(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
 hipError_t launch_lm_stopped(const Problem &pb, const Layout &L, const Buffers &B, int k, int *flag,
-                             double *lm_trace, int it_from, int lm_iters, hipStream_t s);
+                             hipStream_t s);
 
 // consensus kernels
 hipError_t launch_basis_setup(const Problem &pb, const double *freq, double f0, const int32_t *ndir,

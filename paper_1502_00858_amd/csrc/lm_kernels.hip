@@ -341,6 +341,14 @@ __global__ __launch_bounds__(kBlock) void k_lm_update(Problem pb, Layout L, Buff
       tr[0] = st->F;
       tr[1] = st->lambda;
       tr[2] = a;
+      // a run that stops here: the rows of its remaining iterations, which the host may not
+      // launch, get what their updates would write (the final objective and damping)
+      for (int i2 = it + 1; st->done && i2 < lm_iters; ++i2) {
+        double *tn = lm_trace + 3 * ((int64_t)(f * pb.K + k) * lm_iters + i2);
+        tn[0] = st->F;
+        tn[1] = st->lambda;
+        tn[2] = 0;
+      }
     }
   }
   __syncthreads();
@@ -367,28 +375,19 @@ __global__ __launch_bounds__(kBlock) void k_dense_s(Problem pb, Layout L, Buffer
   }
 }
 
-// Whether direction k's LM run has stopped on every subband that carries it (*flag = 1, else 0).
-// Once it has, the iterations it_from .. lm_iters-1 will not be launched: their trace rows get what
-// the update launches of those iterations would write (the final objective and damping, not
-// accepted).
+// Whether direction k's LM run stops, after the current iteration, on every subband that carries
+// it (*flag = 1, else 0), launched right after the solve: the stopping rule needs only the step's
+// predicted decrease and the objective before it (k_lm_update applies the same test), so the host
+// can enqueue what follows while the trial point and the update still run.
 __global__ __launch_bounds__(kBlock) void k_lm_stopped(Problem pb, Layout L, Buffers B, int k,
-                                                       int *flag, double *lm_trace, int it_from,
-                                                       int lm_iters) {
+                                                       int *flag) {
   int running = 0;
-  for (int f = threadIdx.x; f < pb.P; f += kBlock) running |= (k < L.ndir[f] && !B.lm[f].done) ? 1 : 0;
-  running = __syncthreads_or(running);
-  const int nrem = lm_iters - it_from;
-  if (!running && lm_trace && nrem > 0) {
-    for (int e = threadIdx.x; e < pb.P * nrem; e += kBlock) {
-      const int f = e / nrem, it = it_from + e % nrem;
-      if (k >= L.ndir[f]) continue;
-      const LmState *st = B.lm + f;
-      double *tr = lm_trace + 3 * ((int64_t)(f * pb.K + k) * lm_iters + it);
-      tr[0] = st->F;
-      tr[1] = st->lambda;
-      tr[2] = 0;
-    }
+  for (int f = threadIdx.x; f < pb.P; f += kBlock) {
+    const LmState &st = B.lm[f];
+    const bool stops = st.done || (st.chol_ok && pb.lm_tol > 0.0 && st.ell <= pb.lm_tol * st.F);
+    running |= (k < L.ndir[f] && !stops) ? 1 : 0;
   }
+  running = __syncthreads_or(running);
   if (threadIdx.x == 0) *flag = running ? 0 : 1;
 }
 
@@ -400,9 +399,8 @@ hipError_t launch_dense_s(const Problem &pb, const Layout &L, const Buffers &B, 
 }
 
 hipError_t launch_lm_stopped(const Problem &pb, const Layout &L, const Buffers &B, int k, int *flag,
-                             double *lm_trace, int it_from, int lm_iters, hipStream_t s) {
-  hipLaunchKernelGGL(k_lm_stopped, dim3(1), dim3(kBlock), 0, s, pb, L, B, k, flag, lm_trace, it_from,
-                     lm_iters);
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_lm_stopped, dim3(1), dim3(kBlock), 0, s, pb, L, B, k, flag);
   return hipGetLastError();
 }
 
