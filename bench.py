@@ -47,8 +47,8 @@ FP64_PEAK_TFS = 78.6
 MEASURED_TRAFFIC = {
     ("chol_solve", "c2", "blocked"): (
         ("paper_1502_00858_amd/csrc/chol_blocked.hip", "paper_1502_00858_amd/csrc/chol_common.h"),
-        "fe88c90fdd3b050b153f6e4096e68260c53db562ae2e5e4e994042026e86bee1",
-        (161.14 + 58.98) * 1e6),
+        "5963cf33b49e827b0509122a00c1efeb7c6b493776e027b98a77db2e520e3165",
+        (161.00 + 58.98) * 1e6),
 }
 
 
@@ -67,7 +67,7 @@ def measured_traffic(kernel, config, solver):
 
 def kernel_work(name, data, elt):
     """Algorithmic bytes or FLOPs of one launch of a kernel class, averaged over the directions
-    (a direction's LM launches cover only the subbands that carry it; see DESIGN.md)."""
+    (a direction's LM launches cover only the subbands that carry it)."""
     N = int(data["N"])
     K = int(data["K"])
     n = 8 * N
@@ -162,7 +162,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the method's cross-subband exchange is a device-wide "
-              "reduction here; multi-GPU sharding is not built (see DESIGN.md).", file=sys.stderr)
+              "reduction here; multi-GPU sharding is not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch

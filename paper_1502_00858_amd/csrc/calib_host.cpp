@@ -171,8 +171,9 @@ int choose_group(const std::vector<int32_t> &spb, const std::vector<int32_t> &nb
   return best;
 }
 
-// one LM iteration of direction k: normal equations, solve, trial point, accept / damping; with
-// flag, the stop flag right after the solve
+// one LM iteration of direction k (k < 0: of each subband's own direction): normal equations,
+// solve, trial point, accept / damping; with flag (own directions only), the stop flag right
+// after the solve
 template <typename T>
 calib_status lm_iteration(calib_ctx *c, int k, int it, int unreg, hipStream_t s, int *flag = nullptr) {
   const Problem &pb = c->pb;
@@ -184,7 +185,7 @@ calib_status lm_iteration(calib_ctx *c, int k, int it, int unreg, hipStream_t s,
                ? launch_chol_blocked(pb, B, k, c->d_ndir, B.chol_ld, B.chol_fail, s)
                : launch_chol_solve_nd(pb, B, k, c->d_ndir, s);
   }));
-  if (flag) HIPCHK(c, launch_lm_stopped(pb, L, B, k, flag, s));
+  if (flag) HIPCHK(c, launch_lm_stopped(pb, L, B, flag, c->lm_iters, c->sage_sweeps, s));
   HIPCHK(c, timed(c, CALIB_KERNEL_TRIAL, [&] { return launch_trial_stats(pb, L, B, k, s); }));
   HIPCHK(c, timed(c, CALIB_KERNEL_LM_UPDATE, [&] {
     return launch_lm_update_tr(pb, L, B, k, unreg, c->lm_trace, it, c->lm_iters, s);
@@ -216,28 +217,7 @@ calib_status local_step_on(calib_ctx *c, int admm_iter, hipStream_t s) {
                                     : run_local_step<float>(c, admm_iter, s);
 }
 
-constexpr int kLmChunk = 1;   // LM iterations between the host's looks at the stop flag
-
-// Chunk ch of direction k's LM run.  Its first chunk opens the run, after the commit of the
-// previous direction when k > 0 (the stream order of run_local_step: commit k-1, begin k).  In
-// every chunk but the last, the final iteration writes the stop flag after its solve.
-template <typename T>
-calib_status lm_chunk(calib_ctx *c, int k, int ch, int unreg, hipStream_t s) {
-  const int it0 = ch * kLmChunk, it1 = std::min(it0 + kLmChunk, c->lm_iters);
-  if (ch == 0) {
-    if (k > 0)
-      HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(c->pb, c->L, c->B, k - 1, c->sage_sweeps > 1, s); }));
-    HIPCHK(c, timed(c, CALIB_KERNEL_LM_BEGIN, [&] { return launch_lm_begin(c->pb, c->L, c->B, k, unreg, s); }));
-  }
-  for (int it = it0; it < it1; ++it) {
-    int *flag = (it == it1 - 1 && it1 < c->lm_iters) ? c->stop_flag : nullptr;
-    const calib_status st = lm_iteration<T>(c, k, it, unreg, s, flag);
-    if (st != CALIB_OK) return st;
-  }
-  return CALIB_OK;
-}
-
-// The stop flag of the chunk just enqueued: the stopped kernel overwrites the -1 the host left in
+// The stop flag of the step just enqueued: the stopped kernel overwrites the -1 the host left in
 // the pinned word with 0 (running) or 1 (stopped).  The host spins on it, so the next launch
 // follows the flag within microseconds; after 50 ms it synchronises the stream instead, which also
 // reports a device error.
@@ -257,39 +237,36 @@ calib_status wait_stop_flag(calib_ctx *c, hipStream_t s, bool *stopped) {
   return CALIB_OK;
 }
 
-// The local step under the LM stopping rule (same results as run_local_step): after each chunk
-// but the last the host reads the stop flag and, once every run of the direction has stopped,
-// launches none of the remaining iterations.  The kernels are launched directly, not from
-// captured graphs: the flag comes right after the solve, and while the trial point and the update
-// run the host already enqueues what follows (a graph per chunk was measured 2.8% slower).
+// The local step under the LM stopping rule (per subband the same results as run_local_step).
+// Every launch of a step takes each subband's own direction: a subband whose LM run has stopped
+// commits it and starts its next direction's run in the next step while the others still iterate,
+// so a step costs one solve per subband that still works and no launch waits for the slowest
+// subband of a direction.  After each step the host reads the stop flag (written right after the
+// solve: the host enqueues the next step while the trial point and the update run) and ends the
+// loop once every subband has finished its last run.  The kernels are launched directly, not from
+// captured graphs (a graph per step was measured slower: the flag would come only at its end).
 template <typename T>
 calib_status run_local_step_chunked(calib_ctx *c, int admm_iter, hipStream_t s) {
   const int unreg = (admm_iter == 0 && (c->options & CALIB_OPT_UNREG_FIRST)) ? 1 : 0;
   const Problem &pb = c->pb;
   const Layout &L = c->L;
   const Buffers &B = c->B;
-  const int nch = (c->lm_iters + kLmChunk - 1) / kLmChunk;
+  const int sweeps = c->sage_sweeps, all = sweeps > 1;
   HIPCHK(c, timed(c, CALIB_KERNEL_REFRESH, [&] { return launch_refresh<T>(pb, L, B, s); }));
-  for (int sw = 0; sw < c->sage_sweeps; ++sw)
-    for (int k = 0; k < c->K; ++k) {
-      if (k == 0 && sw > 0)
-        HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, c->K - 1, c->sage_sweeps > 1, s); }));
-      for (int ch = 0; ch < nch; ++ch) {
-        const bool checked = std::min((ch + 1) * kLmChunk, c->lm_iters) < c->lm_iters;
-        if (checked) *reinterpret_cast<volatile int *>(c->stop_flag) = -1;
-        {
-          const calib_status st = lm_chunk<T>(c, k, ch, unreg, s);
-          if (st != CALIB_OK) return st;
-        }
-        if (checked) {
-          bool stopped = false;
-          const calib_status st = wait_stop_flag(c, s, &stopped);
-          if (st != CALIB_OK) return st;
-          if (stopped) break;
-        }
-      }
-    }
-  HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, c->K - 1, c->sage_sweeps > 1, s); }));
+  HIPCHK(c, launch_dir_reset(pb, B, s));
+  // each step runs one LM iteration of every unfinished subband: at most sweeps x K x lm_iters
+  const int64_t max_steps = (int64_t)sweeps * c->K * c->lm_iters;
+  bool stopped = max_steps == 0;
+  for (int64_t step = 0; step < max_steps && !stopped; ++step) {
+    *reinterpret_cast<volatile int *>(c->stop_flag) = -1;
+    HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, -1, all, s); }));
+    HIPCHK(c, timed(c, CALIB_KERNEL_LM_BEGIN, [&] { return launch_lm_begin(pb, L, B, -1, unreg, s, sweeps); }));
+    calib_status st = lm_iteration<T>(c, -1, -1, unreg, s, c->stop_flag);
+    if (st == CALIB_OK) st = wait_stop_flag(c, s, &stopped);
+    if (st != CALIB_OK) return st;
+  }
+  if (!stopped) return fail(c, CALIB_E_DEVICE, "the local step did not finish within its LM iterations");
+  HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, -1, all, s); }));
   return CALIB_OK;
 }
 

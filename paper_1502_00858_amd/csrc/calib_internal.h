@@ -46,7 +46,15 @@ struct LmState {
   int32_t active;  // subband carries the active direction
   int32_t done;    // the LM run of the active direction has met its stopping rule
   int32_t dsel;    // D_b of the accepted point is in D1 (1) or D0 (0); the trial pass writes the other
+  // A local step whose launches take the direction from each subband (direction argument k < 0):
+  // every subband moves through its own SAGE sequence, the direction of its current run, that
+  // run's LM iteration, the sweep and the phase below
+  int32_t cur, itc, sweep, phase;
 };
+constexpr int kPhaseLm = 0;        // in an LM run of direction cur
+constexpr int kPhaseAdvance = 1;   // the run of cur has ended: commit it, go to the next direction
+constexpr int kPhaseFinished = 2;  // every direction of every sweep done
+constexpr int kPhaseBegin = 3;     // the run of cur starts (taken inside the LM start launch)
 
 struct Problem {
   int N, P, Q, K;
@@ -95,6 +103,13 @@ struct Buffers {
   double *chol_ld;                      // [P][panels][64*64] blocked solver: diagonal blocks' L
 };
 
+// The direction a launch works on for subband f: its argument k, or (k < 0) the subband's own
+__device__ inline int lm_dir(const Buffers &B, int f, int k) { return k >= 0 ? k : B.lm[f].cur; }
+// Whether subband f takes part in a launch of an LM iteration (assembly, solve, trial point)
+__device__ inline bool lm_live(const Buffers &B, const int32_t *ndir, int f, int k) {
+  return (k >= 0 ? k < ndir[f] : B.lm[f].phase == kPhaseLm) && !B.lm[f].done;
+}
+
 // D_b of subband f at its accepted point and at its trial point: an accepted LM step swaps the two
 // buffers instead of copying the trial values
 __device__ inline double *d_accepted(const Buffers &B, int f) { return B.lm[f].dsel ? B.D1 : B.D0; }
@@ -118,8 +133,9 @@ hipError_t launch_pack(const Problem &pb, const Layout &L, const void *vis, cons
                        int *bad_flag, hipStream_t s);
 
 // LM kernels
+// k < 0: each subband's own next direction (sweeps = SAGE sweeps of the local step)
 hipError_t launch_lm_begin(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
-                           hipStream_t s);
+                           hipStream_t s, int sweeps = 1);
 hipError_t launch_assemble(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
                            hipStream_t s);
 hipError_t launch_chol_solve_nd(const Problem &pb, const Buffers &B, int k, const int32_t *ndir,
@@ -132,8 +148,10 @@ hipError_t launch_trial_stats(const Problem &pb, const Layout &L, const Buffers 
 hipError_t launch_lm_update_tr(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
                                double *lm_trace, int it, int lm_iters, hipStream_t s);
 hipError_t launch_dense_s(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
-hipError_t launch_lm_stopped(const Problem &pb, const Layout &L, const Buffers &B, int k, int *flag,
-                             hipStream_t s);
+// each subband on its own direction (k < 0 launches): *flag = 1 once all have finished the local step
+hipError_t launch_lm_stopped(const Problem &pb, const Layout &L, const Buffers &B, int *flag,
+                             int lm_iters, int sweeps, hipStream_t s);
+hipError_t launch_dir_reset(const Problem &pb, const Buffers &B, hipStream_t s);
 
 // consensus kernels
 hipError_t launch_basis_setup(const Problem &pb, const double *freq, double f0, const int32_t *ndir,

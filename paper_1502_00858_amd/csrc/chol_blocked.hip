@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kBThreads) void k_chol_panel(Problem pb, Buffers B,
   static_assert(kPB / 2 * 2 * kStack <= 2 * kPB * kPs, "column history fits");
   double *Pd = lds, *Px = lds + kPB * kPs, *hist = lds;
   const int f = blockIdx.x;
-  if (k >= ndir[f] || B.lm[f].done || cfail[f]) return;
+  if (!lm_live(B, ndir, f, k) || cfail[f]) return;
   const int nf = pb.nf, nct = nf >> 4, nrt = pb.npad >> 4;
   const PanelGeom g = panel_geom(p, nct);
   double *A = B.H + (int64_t)f * pb.npad * nf;
@@ -480,7 +480,8 @@ __global__ __launch_bounds__(kBsThreads) void k_chol_backsub(Problem pb, Buffers
   __shared__ double red[kBsWaves];
   __shared__ int failed;
   const int f = blockIdx.x;
-  if (k >= ndir[f] || B.lm[f].done) return;
+  if (!lm_live(B, ndir, f, k)) return;
+  k = lm_dir(B, f, k);
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (tid == 0) failed = cfail[f];
@@ -605,7 +606,8 @@ __global__ __launch_bounds__(kBrThreads) void k_chol_backsub_ring(Problem pb, Bu
   __shared__ double red[kBrWaves];
   __shared__ int failed;
   const int f = blockIdx.x;
-  if (k >= ndir[f] || B.lm[f].done) return;
+  if (!lm_live(B, ndir, f, k)) return;
+  k = lm_dir(B, f, k);
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   if (tid == 0) failed = cfail[f];

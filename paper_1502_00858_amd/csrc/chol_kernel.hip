@@ -36,7 +36,8 @@ __global__ __launch_bounds__(kCholThreads) void k_chol_solve(Problem pb, Buffers
   __shared__ double red[kCholWaves];
   __shared__ int fail;
   const int f = blockIdx.x;
-  if (k >= ndir[f] || B.lm[f].done) return;
+  if (!lm_live(B, ndir, f, k)) return;
+  k = lm_dir(B, f, k);
   const int nf = pb.nf, npad = pb.npad, nct = nf >> 4, nrt = npad >> 4;
   double *A = B.H + (int64_t)f * npad * nf;
   double *Li = B.Linv + (int64_t)f * nct * 256;

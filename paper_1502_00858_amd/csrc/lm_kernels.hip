@@ -84,11 +84,33 @@ __device__ inline double objective(const Problem &pb, const Layout &L, const Buf
   return v[0] + v[1];
 }
 
-__global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffers B, int k, int unreg) {
+__global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffers B, int k, int unreg,
+                                                     int sweeps) {
   __shared__ double red[2][kBlock / 64];
   const int f = blockIdx.x;
   LmState *st = B.lm + f;
-  if (k >= L.ndir[f]) {
+  // k < 0: the subband's own direction.  A subband whose run has ended (and been committed) moves
+  // to its next direction, wrapping to the next SAGE sweep, and starts that direction's run.
+  const bool own = k < 0;
+  int cur = 0, sweep = 0;
+  if (own) {
+    int ph = st->phase;
+    cur = st->cur;
+    sweep = st->sweep;
+    if (ph == kPhaseAdvance) {
+      if (++cur >= L.ndir[f]) {
+        cur = 0;
+        ++sweep;
+      }
+      ph = (L.ndir[f] == 0 || sweep >= sweeps) ? kPhaseFinished : kPhaseBegin;
+    }
+    __syncthreads();   // every wavefront has read the state before thread 0 moves it on
+    if (ph != kPhaseBegin) {
+      if (ph == kPhaseFinished && threadIdx.x == 0) st->phase = kPhaseFinished;
+      return;
+    }
+    k = cur;
+  } else if (k >= L.ndir[f]) {
     if (threadIdx.x == 0) st->active = 0;
     return;
   }
@@ -153,6 +175,12 @@ __global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffe
     st->chol_ok = 0;
     st->ell = 0.0;
     st->done = 0;
+    if (own) {
+      st->cur = cur;
+      st->sweep = sweep;
+      st->phase = kPhaseLm;
+      st->itc = 0;
+    }
   }
 }
 
@@ -163,7 +191,8 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble(Problem pb, Layout L, Bu
   __shared__ double red[12][kAsmBlock / 64];
   __shared__ double qg[12];
   const int f = blockIdx.x, p = blockIdx.y;
-  if (k >= L.ndir[f] || B.lm[f].done) return;
+  if (!lm_live(B, L.ndir, f, k)) return;
+  k = lm_dir(B, f, k);
   const int N = pb.N, nf = pb.nf, npad = pb.npad;
   double *A = B.H + (int64_t)f * npad * nf;
   const double lam = B.lm[f].lambda;
@@ -299,10 +328,19 @@ __global__ __launch_bounds__(kBlock) void k_lm_update(Problem pb, Layout L, Buff
   __shared__ double red[2][kBlock / 64];
   __shared__ int acc;
   const int f = blockIdx.x;
-  if (k >= L.ndir[f]) return;
   LmState *st = B.lm + f;
+  const bool own = k < 0;   // the subband's own direction and iteration count
+  if (own) {
+    if (st->phase != kPhaseLm) return;
+    k = st->cur;
+    it = st->itc;
+    __syncthreads();   // every wavefront has read the phase before thread 0 moves it on
+  } else if (k >= L.ndir[f]) {
+    return;
+  }
   if (st->done) {
     // the run has stopped: the trace repeats the final objective and damping
+    if (own && threadIdx.x == 0) st->phase = kPhaseAdvance;
     if (threadIdx.x == 0 && lm_trace) {
       double *tr = lm_trace + 3 * ((int64_t)(f * pb.K + k) * lm_iters + it);
       tr[0] = st->F;
@@ -350,6 +388,10 @@ __global__ __launch_bounds__(kBlock) void k_lm_update(Problem pb, Layout L, Buff
         tn[2] = 0;
       }
     }
+    if (own) {
+      st->itc = it + 1;
+      if (st->done || it + 1 >= lm_iters) st->phase = kPhaseAdvance;
+    }
   }
   __syncthreads();
   if (acc) {
@@ -375,20 +417,36 @@ __global__ __launch_bounds__(kBlock) void k_dense_s(Problem pb, Layout L, Buffer
   }
 }
 
-// Whether direction k's LM run stops, after the current iteration, on every subband that carries
-// it (*flag = 1, else 0), launched right after the solve: the stopping rule needs only the step's
-// predicted decrease and the objective before it (k_lm_update applies the same test), so the host
-// can enqueue what follows while the trial point and the update still run.
-__global__ __launch_bounds__(kBlock) void k_lm_stopped(Problem pb, Layout L, Buffers B, int k,
-                                                       int *flag) {
+// Whether every subband has finished its local step after the current LM iteration (*flag = 1,
+// else 0), each subband on its own direction: it is done, or its run ends now (stopping rule or
+// last LM iteration) and that run is the last direction of the last sweep.  Launched right after
+// the solve: the stopping rule needs only the step's predicted decrease and the objective before
+// it (k_lm_update applies the same test), so the host can enqueue the next step while the trial
+// point and the update still run.
+__global__ __launch_bounds__(kBlock) void k_lm_stopped(Problem pb, Layout L, Buffers B, int *flag,
+                                                       int lm_iters, int sweeps) {
   int running = 0;
   for (int f = threadIdx.x; f < pb.P; f += kBlock) {
     const LmState &st = B.lm[f];
+    if (st.phase == kPhaseFinished) continue;
     const bool stops = st.done || (st.chol_ok && pb.lm_tol > 0.0 && st.ell <= pb.lm_tol * st.F);
-    running |= (k < L.ndir[f] && !stops) ? 1 : 0;
+    const bool ends = st.phase == kPhaseLm && (stops || st.itc + 1 >= lm_iters);
+    const bool last = st.cur + 1 >= L.ndir[f] && st.sweep + 1 >= sweeps;
+    running |= (ends && last) ? 0 : 1;
   }
   running = __syncthreads_or(running);
   if (threadIdx.x == 0) *flag = running ? 0 : 1;
+}
+
+// Start of a local step whose subbands move on their own: no direction yet, first sweep
+__global__ void k_dir_reset(Problem pb, Buffers B) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= pb.P) return;
+  LmState *st = B.lm + f;
+  st->cur = -1;
+  st->itc = 0;
+  st->sweep = 0;
+  st->phase = kPhaseAdvance;
 }
 
 }  // namespace
@@ -398,15 +456,20 @@ hipError_t launch_dense_s(const Problem &pb, const Layout &L, const Buffers &B, 
   return hipGetLastError();
 }
 
-hipError_t launch_lm_stopped(const Problem &pb, const Layout &L, const Buffers &B, int k, int *flag,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_lm_stopped, dim3(1), dim3(kBlock), 0, s, pb, L, B, k, flag);
+hipError_t launch_lm_stopped(const Problem &pb, const Layout &L, const Buffers &B, int *flag,
+                             int lm_iters, int sweeps, hipStream_t s) {
+  hipLaunchKernelGGL(k_lm_stopped, dim3(1), dim3(kBlock), 0, s, pb, L, B, flag, lm_iters, sweeps);
+  return hipGetLastError();
+}
+
+hipError_t launch_dir_reset(const Problem &pb, const Buffers &B, hipStream_t s) {
+  hipLaunchKernelGGL(k_dir_reset, dim3((pb.P + 63) / 64), dim3(64), 0, s, pb, B);
   return hipGetLastError();
 }
 
 hipError_t launch_lm_begin(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_lm_begin, dim3(pb.P), dim3(kBlock), 0, s, pb, L, B, k, unreg);
+                           hipStream_t s, int sweeps) {
+  hipLaunchKernelGGL(k_lm_begin, dim3(pb.P), dim3(kBlock), 0, s, pb, L, B, k, unreg, sweeps);
   return hipGetLastError();
 }
 

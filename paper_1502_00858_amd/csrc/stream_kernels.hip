@@ -166,7 +166,8 @@ __global__ __launch_bounds__(64 * kStatTiles) void k_trial_stats(Problem pb, Lay
   const int tile = kStatTiles * blockIdx.x + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (tile >= pb.ntiles) return;   // uniform per wavefront
   const int f = L.tile_f[tile];
-  if (k >= L.ndir[f] || !B.lm[f].chol_ok || B.lm[f].done) return;   // uniform
+  if (!lm_live(B, L.ndir, f, k) || !B.lm[f].chol_ok) return;   // uniform
+  k = lm_dir(B, f, k);
   const int nb = L.nb[f], bi = L.tile_b0[tile] + lane;
   double part = 0.0;
   if (lane < pb.bpt && bi < nb) {
@@ -303,6 +304,10 @@ __global__ __launch_bounds__(64 * kStatTiles) void k_commit_stats(Problem pb, La
   if (tile >= pb.ntiles) return;   // uniform per wavefront
   const int f = L.tile_f[tile];
   const int Kf = L.ndir[f], nb = L.nb[f];
+  if (k < 0) {   // the subband's own direction, if its run has just ended
+    if (B.lm[f].phase != kPhaseAdvance || B.lm[f].cur < 0) return;
+    k = B.lm[f].cur;
+  }
   if (k >= Kf || l >= Kf || (!all && l < k)) return;   // uniform per wavefront
   const int K = pb.K, N = pb.N, next = k + 1 < Kf ? k + 1 : 0;
   const bool upd = all || l > k;

@@ -300,6 +300,33 @@ def test_stopping_rule_skip_is_exact(cal, synth_mod, solver):
         assert np.sum(lm[..., -1, 2] == 0) > 0
 
 
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_own_direction_progression_ragged(cal, synth_mod, sweeps):
+    """Under the stopping rule each subband moves through its directions on its own (a subband
+    whose run stopped commits it and starts the next direction while others still iterate, and
+    wraps to the next SAGE sweep on its own).  With subbands of 1 to 4 directions (one finishing its
+    local step long before the rest) the states and LM traces equal those of the lockstep local
+    step, which launches every direction's every LM iteration for all subbands."""
+    cfg = tiny_cfg(synth_mod, N=8, P=6, Q=2, K=4, T=3, n_chan=2, n_dirs=[4, 1, 3, 4, 2, 4],
+                   flag_frac_max=0.2, lm_iters=6)
+    d = synth_mod.generate(cfg)
+    for prec in (0, 1):
+        print(f"sweeps {sweeps} precision {prec}", flush=True)
+        a = _ctx(cal, d, prec, lm_iters=6, lm_tol=1e-5, sage_sweeps=sweeps)
+        b = _ctx(cal, d, prec, lm_iters=6, lm_tol=1e-5, sage_sweeps=sweeps)
+        ta = a.solve(4)
+        for n in range(4):
+            b.local_step(n)
+            b.consensus_update(n)
+        np.testing.assert_array_equal(a.get(cal.FIELD_J).cpu().numpy(), b.get(cal.FIELD_J).cpu().numpy())
+        np.testing.assert_array_equal(a.get(cal.FIELD_BZ).cpu().numpy(), b.get(cal.FIELD_BZ).cpu().numpy())
+        lm = b.get(cal.FIELD_LM_TRACE).cpu().numpy()
+        np.testing.assert_array_equal(a.get(cal.FIELD_LM_TRACE).cpu().numpy(), lm)
+        np.testing.assert_array_equal(ta, b.get(cal.FIELD_TRACE)[:4])
+        # runs stopped before their last LM iteration (so the subbands moved on unevenly)
+        assert np.sum(lm[..., -1, 2] == 0) > 0
+
+
 def test_solvers_agree_on_a_local_step(cal, synth_mod):
     """The two Cholesky solvers sum in different orders: whole local steps agree to rounding."""
     cfg = tiny_cfg(synth_mod, N=20, P=5, Q=2, K=3, T=3, n_chan=2, lm_iters=6, flag_frac_max=0.2)
