@@ -68,6 +68,25 @@ def test_local_step_lm_trace_fp64(cal, oracle_mod, synth_mod):
     assert _rel(pb.predict(Jg), pb.predict(Jo)) < 1e-9
 
 
+def test_max_directions_fp64(cal, oracle_mod, synth_mod):
+    """The largest direction count (16 per subband, the size of the per-sample direction arrays of
+    the streaming and coherency-statistics kernels), subbands carrying 16 and 11 of them: the local
+    step's LM trace and J agree with the oracle."""
+    cfg = tiny_cfg(synth_mod, N=5, P=2, Q=1, K=16, T=3, n_chan=2, n_dirs=[16, 11], lm_iters=3)
+    d = synth_mod.generate(cfg)
+    J0 = synth_mod.identity_jones(cfg.P, cfg.K, cfg.N)
+    c = _ctx(cal, d, 0, lm_iters=3)
+    c.local_step(0)
+    Jg = c.get(cal.FIELD_J).cpu().numpy()
+    trg = c.get(cal.FIELD_LM_TRACE).cpu().numpy()
+    pb = oracle_mod.Problem(d, lm_iters=3)
+    z = np.zeros_like(J0)
+    Jo, tro = pb.local_step(J0, z, z, trace=True)
+    np.testing.assert_array_equal(trg[..., 2], tro[:, 0, :, :, 2])
+    np.testing.assert_allclose(trg[..., 0], tro[:, 0, :, :, 0], rtol=1e-10)
+    assert _rel(pb.predict(Jg), pb.predict(Jo)) < 1e-9
+
+
 def test_two_sage_sweeps_fp64(cal, oracle_mod, synth_mod):
     """Two SAGE sweeps per local step: each commit then updates every direction's statistics (the
     second sweep starts again from direction 0).  The last sweep's LM trace, the local step's J and
@@ -200,9 +219,11 @@ def test_normal_equation_solve_fp64(cal, oracle_mod, synth_mod, solver):
     """One LM iteration from a random state: the GPU step solves (H_GN + (rho+lambda) I) delta = -G
     with the oracle's Gauss-Newton matrix, for both Cholesky solvers (one workgroup per matrix;
     64-column panels over many workgroups) and station counts that give padded factors and
-    partial last panels (8N = 48, 72, 136, 264 columns), and 8N = 528 (past the 512 columns of
-    the panel solver's register-ring back substitution: its 1024-thread back substitution)."""
-    for N in (6, 9, 17, 33, 66):
+    partial last panels (8N = 48, 72, 136, 264 columns), 8N = 528 (past the 512 columns of the
+    panel solver's register-ring back substitution: its 1024-thread back substitution) and the
+    largest array, N = 128 (8N = 1024: two columns per thread in the one-workgroup solver, one in
+    the 1024-thread back substitution, 16 panels)."""
+    for N in (6, 9, 17, 33, 66, 128):
         print(f"solver {solver} N {N}", flush=True)
         cfg = tiny_cfg(synth_mod, N=N, P=2, Q=1, K=1, T=3, n_chan=2, rho=3.0, lm_iters=1)
         d = synth_mod.generate(cfg)
