@@ -43,7 +43,6 @@ struct LmState {
   double Fnew;     // objective at the last trial point
   int32_t chol_ok; // last factorisation succeeded
   int32_t accepted;// accepted steps in this LM run
-  int32_t active;  // subband carries the active direction
   int32_t done;    // the LM run of the active direction has met its stopping rule
   int32_t dsel;    // D_b of the accepted point is in D1 (1) or D0 (0); the trial pass writes the other
   // A local step whose launches take the direction from each subband (direction argument k < 0):

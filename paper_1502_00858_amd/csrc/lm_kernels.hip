@@ -111,7 +111,6 @@ __global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffe
     }
     k = cur;
   } else if (k >= L.ndir[f]) {
-    if (threadIdx.x == 0) st->active = 0;
     return;
   }
   const double *J = jdir(B, pb, f, k);
@@ -171,7 +170,6 @@ __global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffe
     st->lambda = kLmTau * m;
     st->nu = 2.0;
     st->accepted = 0;
-    st->active = 1;
     st->chol_ok = 0;
     st->ell = 0.0;
     st->done = 0;
@@ -288,17 +286,18 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble(Problem pb, Layout L, Bu
   const double q00 = qg[0], q11 = qg[1], q01r = qg[2], q01i = qg[3];
   const int ncol = 8 * p + 8;
   const double *Jp = J + 8 * p;
-  // 16 threads per row v of station p's 8 rows, stepping through its columns (coalesced stores,
-  // no division)
+  // 16 threads per row v of station p's 8 rows, stepping through its columns two at a time
+  // (columns c, c+1 differ only in real / imaginary part: one complex product, one 16-byte store;
+  // coalesced, no division)
   static_assert(kAsmBlock == 8 * 16, "one row per 16 threads");
   const int v8 = threadIdx.x >> 4, l16 = threadIdx.x & 15;
   const int iv = v8 >> 2, jv = (v8 >> 1) & 1, rv = v8 & 1;
-  double *row = A + (int64_t)(8 * p + v8) * nf;
-#pragma unroll 4
-  for (int c = l16; c < ncol; c += 16) {
-    double val;
-    const int u = c & 7;
-    const int iu = u >> 2, ju = (u >> 1) & 1, ru = u & 1;
+  double2 *row = reinterpret_cast<double2 *>(A + (int64_t)(8 * p + v8) * nf);   // nf is even
+#pragma unroll 2
+  for (int c = 2 * l16; c < ncol; c += 32) {
+    double2 val;
+    const int u = c & 7;   // even: ru = 0 at c, 1 at c+1
+    const int iu = u >> 2, ju = (u >> 1) & 1;
     if (c < 8 * p) {
       // baseline (a, p): S of the pair (zero without an unflagged baseline)
       const int a = c >> 3;
@@ -306,20 +305,23 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble(Problem pb, Layout L, Bu
       const double ar = Ja[(iu * 2 + jv) * 2], ai = Ja[(iu * 2 + jv) * 2 + 1];
       const double br = Jp[(iv * 2 + ju) * 2], bi = Jp[(iv * 2 + ju) * 2 + 1];
       const double wr = ar * br - ai * bi, wi = ar * bi + ai * br;
-      const double g = (ru == 0) ? (rv == 0 ? wr : wi) : (rv == 0 ? wi : -wr);
-      val = 2.0 * Sp[a] * g;
+      const double s2 = 2.0 * Sp[a];
+      val.x = s2 * (rv == 0 ? wr : wi);
+      val.y = s2 * (rv == 0 ? wi : -wr);
     } else if (iu != iv) {
-      val = 0.0;
+      val.x = val.y = 0.0;
     } else {
       // g' = Q[jv][ju] (row index v, column index u)
       double gr, gi;
       if (jv == ju) { gr = (jv == 0) ? q00 : q11; gi = 0.0; }
       else if (jv == 0) { gr = q01r; gi = q01i; }      // Q[0][1]
       else { gr = q01r; gi = -q01i; }                  // Q[1][0] = conj(Q[0][1])
-      val = 2.0 * ((rv == 0) ? (ru == 0 ? gr : gi) : (ru == 0 ? -gi : gr));
-      if (u == v8) val += rho + lam;
+      val.x = 2.0 * ((rv == 0) ? gr : -gi);
+      val.y = 2.0 * ((rv == 0) ? gi : gr);
+      if (u == v8) val.x += rho + lam;
+      if (u + 1 == v8) val.y += rho + lam;
     }
-    row[c] = val;
+    row[c >> 1] = val;
   }
 }
 
