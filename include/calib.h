@@ -147,7 +147,12 @@ calib_status admm_consensus_update(calib_ctx *ctx, int32_t admm_iter);
 
 /* The whole C-ADMM loop: iterations 0..max_iters-1 of local step + consensus update.  Iteration
  * 0 is enqueued kernel by kernel; the launch sequence of the later iterations is identical, so it
- * is captured once into a HIP graph and replayed (not while kernel timing is enabled).  When
+ * is captured once into a HIP graph and replayed (not while kernel timing is enabled).  With
+ * lm_tol > 0 the local step is launched directly instead, one LM iteration of every unfinished
+ * subband per step, each subband moving through its own directions and SAGE sweeps; after each
+ * step's solve the host reads a word of pinned memory that the device writes (whether every
+ * subband has finished its local step) and launches the next step only if not; results per
+ * subband are those of the iteration-by-iteration schedule of admm_local_step.  When
  * rel_cost_tol > 0 it stops after an iteration whose data cost changed by less than
  * rel_cost_tol relative to the previous one (this check synchronises the stream each
  * iteration).  trace_out (host, may be NULL) receives [iters][4] as CALIB_FIELD_TRACE;
