@@ -69,10 +69,9 @@ struct calib_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  // LM runs under the stopping rule: each direction's run in chunks of kLmChunk iterations, one
-  // captured graph per (direction, chunk) that ends by writing whether every run has stopped; the
-  // host skips the rest of a direction once it has (those iterations would change nothing but
-  // trace rows, which one small launch writes instead)
+  // the local step under the LM stopping rule: after each step's solve the device writes here
+  // whether every subband has finished its local step, and the host reads it before launching
+  // the next step
   int *stop_flag = nullptr;                 // pinned host memory
   // warm start
   double *ws_jsave = nullptr;   // [P][K][N][8]
@@ -246,7 +245,7 @@ calib_status wait_stop_flag(calib_ctx *c, hipStream_t s, bool *stopped) {
 // loop once every subband has finished its last run.  The kernels are launched directly, not from
 // captured graphs (a graph per step was measured slower: the flag would come only at its end).
 template <typename T>
-calib_status run_local_step_chunked(calib_ctx *c, int admm_iter, hipStream_t s) {
+calib_status run_local_step_stopping(calib_ctx *c, int admm_iter, hipStream_t s) {
   const int unreg = (admm_iter == 0 && (c->options & CALIB_OPT_UNREG_FIRST)) ? 1 : 0;
   const Problem &pb = c->pb;
   const Layout &L = c->L;
@@ -270,9 +269,9 @@ calib_status run_local_step_chunked(calib_ctx *c, int admm_iter, hipStream_t s) 
   return CALIB_OK;
 }
 
-calib_status local_step_chunked_on(calib_ctx *c, int admm_iter, hipStream_t s) {
-  return c->precision == CALIB_FP64 ? run_local_step_chunked<double>(c, admm_iter, s)
-                                    : run_local_step_chunked<float>(c, admm_iter, s);
+calib_status local_step_stopping_on(calib_ctx *c, int admm_iter, hipStream_t s) {
+  return c->precision == CALIB_FP64 ? run_local_step_stopping<double>(c, admm_iter, s)
+                                    : run_local_step_stopping<float>(c, admm_iter, s);
 }
 
 // Lagrangian trace row, first-iteration alignment, Z, B_f Z, Y and residuals; the trace row is
@@ -611,12 +610,12 @@ calib_status admm_solve(calib_ctx *ctx, int32_t max_iters, double rel_cost_tol, 
   if (max_iters < 0 || max_iters > kMaxTrace) return fail(ctx, CALIB_E_INVAL, "max_iters out of range");
   int n = 0;
   double prev = 0.0;
-  const bool chunked = ctx->pb.lm_tol > 0.0;
+  const bool stopping = ctx->pb.lm_tol > 0.0;
   for (; n < max_iters; ++n) {
     calib_status st = CALIB_OK;
-    if (chunked) {
+    if (stopping) {
       const bool eager = n == 0 || ctx->timing;
-      st = local_step_chunked_on(ctx, n, ctx->stream);
+      st = local_step_stopping_on(ctx, n, ctx->stream);
       if (st == CALIB_OK) {
         if (eager) {
           st = admm_consensus_update(ctx, n);

@@ -298,10 +298,11 @@ def test_lm_stopping_rule_fp64(cal, oracle_mod, synth_mod):
 
 @pytest.mark.parametrize("solver", [1, 2])
 def test_stopping_rule_skip_is_exact(cal, synth_mod, solver):
-    """Under the LM stopping rule, solve() runs each direction's LM iterations in chunks and skips
-    the rest once every run has stopped (writing their trace rows); stepping the same problem with
-    local_step / consensus_update launches every iteration.  Both give identical states, objective
-    traces and LM traces, in both precisions."""
+    """Under the LM stopping rule, solve() launches one LM iteration per step for every subband
+    still working, each on its own direction, and ends the local step once every subband has
+    finished (stopped runs write their remaining trace rows); stepping the same problem with
+    local_step / consensus_update launches every direction's every iteration.  Both give identical
+    states, objective traces and LM traces, in both precisions."""
     cfg = tiny_cfg(synth_mod, N=9, P=5, Q=2, K=3, T=3, n_chan=2, lm_iters=7, flag_frac_max=0.2)
     d = synth_mod.generate(cfg)
     for prec in (0, 1):
