@@ -82,6 +82,24 @@ def test_c2_whole_iteration(cal, oracle_mod, synth_mod):
     np.testing.assert_allclose(trg[0, 2:], tro[0, 2:], rtol=1e-3)
 
 
+def test_c2_stopping_rule_solve(cal, oracle_mod, synth_mod):
+    """The benchmark's launch configuration on the full c2 problem: FP32 streaming, the LM stopping
+    rule at lm_tol 1e-7 (each subband moving through its own directions, the host reading the
+    device's stop flag), three C-ADMM iterations from identity; the oracle runs the same rule on
+    the FP32-rounded inputs of all 32 subbands.  Data cost and Lagrangian within 1e-5 (a stop
+    decision that the FP32 energies flip changes the cost by about lm_tol)."""
+    cfg = synth_mod.named_config("c2")
+    d, d32 = _data(synth_mod, "c2")
+    vis, coh, flags = cal.device_inputs(d, cal.CALIB_FP32_MIXED)
+    c = cal.Calib(d, vis, coh, flags, precision=cal.CALIB_FP32_MIXED, lm_tol=1e-7)
+    trg = c.solve(3)
+    c.close()
+    print("c2: three C-ADMM iterations under the stopping rule, oracle on all 32 subbands", flush=True)
+    pb = oracle_mod.Problem(d32, lm_tol=1e-7)
+    tro = pb.admm_solve(synth_mod.identity_jones(cfg.P, cfg.K, cfg.N), 3)["trace"]
+    np.testing.assert_allclose(trg[:, :2], tro[:, :2], rtol=1e-5)
+
+
 def test_autotune_measures_and_caches(cal, synth_mod, tmp_path, monkeypatch):
     from paper_1502_00858_amd import autotune
     cfg = synth_mod.SynthConfig("tune", N=12, P=6, Q=2, K=3, T=4, n_chan=[1, 9, 3, 16, 2, 5],
