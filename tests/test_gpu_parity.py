@@ -222,8 +222,8 @@ def test_normal_equation_solve_fp64(cal, oracle_mod, synth_mod, solver):
     partial last panels (8N = 48, 72, 136, 264 columns), 8N = 528 (past the 512 columns of the
     panel solver's register-ring back substitution: its 1024-thread back substitution) and the
     largest array, N = 128 (8N = 1024: two columns per thread in the one-workgroup solver, one in
-    the 1024-thread back substitution, 16 panels)."""
-    for N in (6, 9, 17, 33, 66, 128):
+    the 1024-thread back substitution, 16 panels); the smallest, N = 2 (one baseline, one tile)."""
+    for N in (2, 6, 9, 17, 33, 66, 128):
         print(f"solver {solver} N {N}", flush=True)
         cfg = tiny_cfg(synth_mod, N=N, P=2, Q=1, K=1, T=3, n_chan=2, rho=3.0, lm_iters=1)
         d = synth_mod.generate(cfg)
