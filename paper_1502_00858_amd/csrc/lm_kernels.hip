@@ -183,12 +183,13 @@ __global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffe
 }
 
 // One workgroup of two wavefronts per (subband, station row-block), so that all of them are resident
-// at once; blockIdx.y == N writes the padding rows.
+// at once; blockIdx.y == 0 writes the padding rows, then the stations from the last (whose rows
+// are the longest) to the first, so that the longest workgroups are dispatched first.
 constexpr int kAsmBlock = 128;
 __global__ __launch_bounds__(kAsmBlock) void k_assemble(Problem pb, Layout L, Buffers B, int k, int unreg) {
   __shared__ double red[12][kAsmBlock / 64];
   __shared__ double qg[12];
-  const int f = blockIdx.x, p = blockIdx.y;
+  const int f = blockIdx.x, p = blockIdx.y == 0 ? pb.N : pb.N - (int)blockIdx.y;
   if (!lm_live(B, L.ndir, f, k)) return;
   k = lm_dir(B, f, k);
   const int N = pb.N, nf = pb.nf, npad = pb.npad;
