@@ -291,16 +291,17 @@ __global__ __launch_bounds__(64 * kStatTiles) void k_dall(Problem pb, Layout L, 
   }
 }
 
-// End of direction k's LM run (the SAGE commit) without a pass over the samples (grid: tile x l,
-// one lane per baseline): with dM = J_kp J_kq^H - J0_p J0_q^H (J0 the run's start point), the
+// End of direction k's LM run (the SAGE commit) without a pass over the samples (one wavefront per
+// tile, one lane per baseline): with dM = J_kp J_kq^H - J0_p J0_q^H (J0 the run's start point), the
 // residual R - c_k dM has D_l - X_lk dM for every direction l, and energy
-// E - 2 Re sum_e conj(dM_e) D_k,e + X_kk ||dM||^2 (the direction-k workgroup updates the tile's
-// energy and cost partial).  The next direction's D becomes the accepted and start point of its
+// E - 2 Re sum_e conj(dM_e) D_k,e + X_kk ||dM||^2 (the tile's energy and cost partial).  Each lane
+// forms dM once and walks the directions, the next direction's D_l and X_lk requested before the
+// current one's are stored.  The next direction's D becomes the accepted and start point of its
 // LM run.  Unless all is set only the directions after k are updated: within one SAGE sweep no
 // other is read again before the next local step's refresh rebuilds them all.
 __global__ __launch_bounds__(64 * kStatTiles) void k_commit_stats(Problem pb, Layout L, Buffers B, int k,
                                                                    int all) {
-  const int tile = kStatTiles * blockIdx.x + (threadIdx.x >> 6), lane = threadIdx.x & 63, l = blockIdx.y;
+  const int tile = kStatTiles * blockIdx.x + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (tile >= pb.ntiles) return;   // uniform per wavefront
   const int f = L.tile_f[tile];
   const int Kf = L.ndir[f], nb = L.nb[f];
@@ -308,57 +309,69 @@ __global__ __launch_bounds__(64 * kStatTiles) void k_commit_stats(Problem pb, La
     if (B.lm[f].phase != kPhaseAdvance || B.lm[f].cur < 0) return;
     k = B.lm[f].cur;
   }
-  if (k >= Kf || l >= Kf || (!all && l < k)) return;   // uniform per wavefront
+  if (k >= Kf) return;   // uniform per wavefront
   const int K = pb.K, N = pb.N, next = k + 1 < Kf ? k + 1 : 0;
-  const bool upd = all || l > k;
   const int bi = L.tile_b0[tile] + lane;
   const bool live = lane < pb.bpt && bi < nb;
   double part = 0.0;
   if (live) {
     const int64_t gb = (int64_t)L.bl_off[f] + bi;
     const int p = L.bl_p[gb], q = L.bl_q[gb];
+    const int64_t nbt = pb.nbt;
+    const int l0 = all ? 0 : k;
+    // D_l and X_lk of direction l, requested ahead of their use
+    double dn[8], xn[2];
+    auto request = [&](int l) {
+      const double *X = B.Xcoh + (((int64_t)l * K + k) * nbt + gb) * 2;
+      const double *D = B.Dall + ((int64_t)l * nbt + gb) * 8;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) dn[e] = D[e];
+      xn[0] = X[0];
+      xn[1] = X[1];
+    };
+    request(l0);
     const double *J1 = B.J + ((int64_t)f * K + k) * N * 8, *J0 = B.Jstart + (int64_t)f * N * 8;
     double m1[8], m0[8], dm[8];
     jjh(J1 + 8 * p, J1 + 8 * q, m1);
     jjh(J0 + 8 * p, J0 + 8 * q, m0);
 #pragma unroll
     for (int e = 0; e < 8; ++e) dm[e] = m1[e] - m0[e];
-    const int64_t nbt = pb.nbt;
-    const double *X = B.Xcoh + (((int64_t)l * K + k) * nbt + gb) * 2;
-    double *D = B.Dall + ((int64_t)l * nbt + gb) * 8;
-    double d[8];
+    for (int l = l0; l < Kf; ++l) {
+      double d[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) d[e] = D[e];
-    if (l == k) {
-      double cross = 0.0, norm = 0.0;
+      for (int e = 0; e < 8; ++e) d[e] = dn[e];
+      const double x0 = xn[0], x1 = xn[1];
+      if (l + 1 < Kf) request(l + 1);
+      if (l == k) {
+        double cross = 0.0, norm = 0.0;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        cross = fma(dm[e], d[e], cross);
-        norm = fma(dm[e], dm[e], norm);
+        for (int e = 0; e < 8; ++e) {
+          cross = fma(dm[e], d[e], cross);
+          norm = fma(dm[e], dm[e], norm);
+        }
+        part = fma(x0, norm, -2.0 * cross);
       }
-      part = fma(X[0], norm, -2.0 * cross);
-    }
-    if (upd) {
-      sub_scaled(d, X[0], X[1], dm);
+      if (all || l > k) {
+        sub_scaled(d, x0, x1, dm);
+        double *D = B.Dall + ((int64_t)l * nbt + gb) * 8;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) D[e] = d[e];
-    }
-    if (upd && l == next) {
-      double *Da = d_accepted(B, f) + 8 * gb;
+        for (int e = 0; e < 8; ++e) D[e] = d[e];
+        if (l == next) {
+          double *Da = d_accepted(B, f) + 8 * gb;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        Da[e] = d[e];
-        B.Dstart[8 * gb + e] = d[e];
+          for (int e = 0; e < 8; ++e) {
+            Da[e] = d[e];
+            B.Dstart[8 * gb + e] = d[e];
+          }
+        }
       }
     }
   }
-  if (l == k) {
-    part = wave_sum(part);
-    if (lane == 0) {
-      const double e = B.Epart[tile] + part;
-      B.Epart[tile] = e;
-      B.cost_part[tile] = e;
-    }
+  part = wave_sum(part);
+  if (lane == 0) {
+    const double e = B.Epart[tile] + part;
+    B.Epart[tile] = e;
+    B.cost_part[tile] = e;
   }
 }
 
@@ -487,7 +500,7 @@ hipError_t launch_commit(const Problem &pb, const Layout &L, const Buffers &B, i
                          hipStream_t s) {
   if (pb.ntiles == 0) return hipSuccess;
   if (pb.bpt > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_commit_stats, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles, pb.K),
+  hipLaunchKernelGGL(k_commit_stats, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles),
                      dim3(64 * kStatTiles), 0, s, pb, L, B, k, all);
   return hipGetLastError();
 }
