@@ -363,3 +363,76 @@ def test_lm_stopping_rule_truncates_the_run(oracle_mod, synth_mod):
             assert np.all(b[s:, 2] == 0)
             stopped += 1
     assert stopped >= 2
+
+
+def test_gradient_is_twice_the_papers_printed_gradient(oracle_mod, synth_mod):
+    """Section 3 prints the gradient of the augmented Lagrangian as grad g + Y/2 + rho/2 (J - B Z),
+    with grad g = -sum_pq [A_p^T R A_q J C^H + A_q^T R^H A_p J C], R = V - A_p J C J^H A_q^T, J the
+    2N x 2 stack of the stations' Jones matrices and A_p the 2 x 2N selector of station p (the
+    Riemannian gradient under the inner product tr(x^H y + y^H x) of Appendix A).  The oracle's
+    Euclidean gradient over the real parameters (d/dRe + i d/dIm per entry) is exactly twice it:
+    this fixes the scale of the Y and rho terms, which finite differences of the oracle's own
+    objective cannot tell apart from a consistent slip in objective and gradient together."""
+    rng = np.random.default_rng(21)
+    cfg = tiny_cfg(synth_mod, N=4, P=2, K=2, T=2, n_chan=2, rho=3.0)
+    d = synth_mod.generate(cfg)
+    pb = oracle_mod.Problem(d)
+    N, K, spb = cfg.N, cfg.K, cfg.T * 2
+    J = rand_jones(rng, cfg.P, K, N)
+    Y = 0.4 * (rng.normal(size=J.shape) + 1j * rng.normal(size=J.shape))
+    BZ = rand_jones(rng, cfg.P, K, N)
+    pairs = list(zip(*synth_mod.baseline_pairs(N)))
+    I2 = np.eye(2)
+    A = []
+    for p in range(N):
+        a = np.zeros((2, 2 * N))
+        a[:, 2 * p:2 * p + 2] = I2
+        A.append(a)
+    for f, k in ((0, 1), (1, 0)):
+        _, G = pb.dir_objective(J, Y, BZ, f, k)
+        V = d["vis"][d["vis_off"][f]:d["vis_off"][f + 1]]
+        c = d["coh"][d["coh_off"][f]:d["coh_off"][f + 1]].reshape(K, -1)
+        Js = [J[f, l].reshape(2 * N, 2) for l in range(K)]
+        grad_g = np.zeros((2 * N, 2), np.complex128)
+        for b, (p, q) in enumerate(pairs):
+            for s in range(b * spb, (b + 1) * spb):
+                # the SAGE expectation of direction k (Section 3): the other directions' models
+                # removed from the data
+                Vk = V[s] - sum(c[l, s] * A[p] @ Js[l] @ Js[l].conj().T @ A[q].T
+                                for l in range(K) if l != k)
+                C = c[k, s] * I2
+                R = Vk - A[p] @ Js[k] @ C @ Js[k].conj().T @ A[q].T
+                grad_g -= (A[p].T @ R @ A[q] @ Js[k] @ C.conj().T
+                           + A[q].T @ R.conj().T @ A[p] @ Js[k] @ C)
+        grad_L = (grad_g + 0.5 * Y[f, k].reshape(2 * N, 2)
+                  + 0.5 * 3.0 * (Js[k] - BZ[f, k].reshape(2 * N, 2)))
+        assert np.linalg.norm(G.reshape(2 * N, 2) - 2 * grad_L) <= 1e-12 * np.linalg.norm(grad_L)
+
+
+def test_trace_lagrangian_column(oracle_mod, synth_mod):
+    """Trace row n holds the data cost sum_f g_f after the local step of iteration n and the
+    augmented Lagrangian of Section 3 (linear term in the trace form of Appendix A) at that J with
+    the multipliers and B_f Z of the previous consensus update.  Tied to the per-direction
+    objectives of the local step (each direction's objective after the SAGE expectation holds the
+    whole residual, so sum_k L_fk = K_f g_f + sum_k penalty_fk) and to the trace form summed
+    directly; per-direction rho_k (Section 3 allows one per direction) of 2 and 7."""
+    cfg = tiny_cfg(synth_mod, N=5, P=4, Q=2, K=2, T=2, n_chan=2, lm_iters=4)
+    d = synth_mod.generate(cfg)
+    rho = np.array([2.0, 7.0])
+    pb = oracle_mod.Problem(d, lm_iters=4, rho=rho)
+    J0 = synth_mod.identity_jones(cfg.P, cfg.K, cfg.N)
+    one = pb.admm_solve(J0, 1)
+    two = pb.admm_solve(J0, 2)
+    J2 = pb.local_step(one["J"], one["Y"], one["BZ"])
+    np.testing.assert_array_equal(J2, two["J"])
+    Y1, BZ1 = one["Y"], one["BZ"]
+    g = pb.subband_cost(J2)
+    via_dirs = sum(pb.dir_objective(J2, Y1, BZ1, f, k, grad=False)
+                   for f in range(cfg.P) for k in range(cfg.K)) - (cfg.K - 1) * g.sum()
+    e = J2 - BZ1
+    direct = g.sum() + sum(np.sum(np.real(np.conj(Y1[:, k]) * e[:, k]))
+                           + 0.5 * rho[k] * np.sum(np.abs(e[:, k]) ** 2) for k in range(cfg.K))
+    L = two["trace"][1, 1]
+    assert abs(two["trace"][1, 0] - g.sum()) <= 1e-13 * g.sum()
+    assert abs(L - via_dirs) <= 1e-12 * abs(L)
+    assert abs(L - direct) <= 1e-12 * abs(L)
