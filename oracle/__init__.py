@@ -17,6 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 OPT_GPA_FIRST = 1
 OPT_UNREG_FIRST = 2
+SOLVE_CHOLESKY = 0
+SOLVE_PCG = 1
 
 
 def build() -> str:
@@ -31,7 +33,8 @@ class _Cfg(C.Structure):
                 ("n_chan", C.POINTER(C.c_int32)), ("n_dirs", C.POINTER(C.c_int32)),
                 ("freq", C.POINTER(C.c_double)), ("f0", C.c_double),
                 ("rho", C.POINTER(C.c_double)), ("lm_iters", C.c_int),
-                ("sage_sweeps", C.c_int), ("options", C.c_uint32), ("lm_tol", C.c_double)]
+                ("sage_sweeps", C.c_int), ("options", C.c_uint32), ("lm_tol", C.c_double),
+                ("solver", C.c_int), ("cg_tol", C.c_double)]
 
 
 class _Data(C.Structure):
@@ -59,6 +62,8 @@ def lib():
         _lib.or_consensus.restype = ip
         _lib.or_admm_solve.argtypes = [vp, vp, ip, vp, vp, vp, vp, vp]
         _lib.or_admm_solve.restype = ip
+        _lib.or_pcg.argtypes = [ip, vp, vp, C.c_double, vp, vp]
+        _lib.or_pcg.restype = ip
         _lib.or_cholesky.argtypes = [ip, vp, vp]
         _lib.or_cholesky.restype = ip
         _lib.or_polar2.argtypes = [vp, vp]
@@ -78,7 +83,8 @@ class Problem:
     """Holds one interval's arrays in the layout the C oracle expects (contiguous copies)."""
 
     def __init__(self, data: dict, lm_iters: int | None = None, sage_sweeps: int = 1,
-                 options: int = OPT_GPA_FIRST, rho=None, lm_tol: float = 0.0):
+                 options: int = OPT_GPA_FIRST, rho=None, lm_tol: float = 0.0,
+                 solver: int = SOLVE_CHOLESKY, cg_tol: float = 1e-10):
         self.N, self.P, self.Q, self.K, self.T = (int(data[k]) for k in ("N", "P", "Q", "K", "T"))
         self.n_chan = np.ascontiguousarray(data["n_chan"], np.int32)
         self.n_dirs = np.ascontiguousarray(data["n_dirs"], np.int32)
@@ -93,7 +99,8 @@ class Problem:
                         self.n_dirs.ctypes.data_as(C.POINTER(C.c_int32)),
                         self.freq.ctypes.data_as(C.POINTER(C.c_double)), float(data["f0"]),
                         self.rho.ctypes.data_as(C.POINTER(C.c_double)), self.lm_iters,
-                        int(sage_sweeps), int(options), float(lm_tol))
+                        int(sage_sweeps), int(options), float(lm_tol), int(solver),
+                        float(cg_tol))
         self.dat = _Data(self.vis.ctypes.data, self.coh.ctypes.data, self.flags.ctypes.data)
         self.sage_sweeps = int(sage_sweeps)
 
@@ -180,6 +187,16 @@ def cholesky(A):
     L = np.zeros_like(A)
     st = lib().or_cholesky(A.shape[0], _ptr(A), _ptr(L))
     return L if st == 0 else None
+
+
+def pcg(M, b, tol):
+    """(x, iterations) of the block-Jacobi preconditioned CG on M x = b, or None on breakdown."""
+    M = np.ascontiguousarray(M, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    x = np.zeros_like(b)
+    it = np.zeros(1, np.int32)
+    st = lib().or_pcg(M.shape[0], _ptr(M), _ptr(b), float(tol), _ptr(x), _ptr(it))
+    return (x, int(it[0])) if st == 0 else None
 
 
 def polar2(A):

@@ -152,6 +152,8 @@ typedef struct {
   const uint8_t *flag;          /* [B] or NULL */
   const double complex *Y, *BZ; /* [N][4] */
   double rho;
+  int solver;                   /* OR_SOLVE_CHOLESKY or OR_SOLVE_PCG */
+  double cg_tol;
 } dir_problem;
 
 /* SAGE expectation step: V_k = V - sum_{l != k} c_l J_lp J_lq^H */
@@ -301,10 +303,68 @@ static void chol_solve(int n, const double *L, const double *b, double *x) {
   free(y);
 }
 
+/* Preconditioned conjugate gradients (Hestenes & Stiefel 1952; preconditioned form as in Saad,
+ * "Iterative Methods for Sparse Linear Systems", 2nd ed., Algorithm 9.1) for M x = b with M
+ * symmetric positive definite, from x = 0.  The preconditioner is block Jacobi: the inverse of
+ * each 8x8 diagonal block of M (the real parameters of one station), applied through that block's
+ * Cholesky factor.  Iterates until ||r|| <= tol ||b|| (r = b - M x) or n iterations; a search
+ * direction with p.Mp <= 0 or a block that is not positive definite is a failure (-1). */
+int or_pcg(int n, const double *M, const double *b, double tol, double *x, int *iters) {
+  const int nb = n / 8;
+  double *Lb = malloc(sizeof(double) * 64 * nb);
+  double *r = malloc(sizeof(double) * n), *z = malloc(sizeof(double) * n);
+  double *p = malloc(sizeof(double) * n), *q = malloc(sizeof(double) * n);
+  int status = 0, it = 0;
+  for (int s = 0; s < nb && status == 0; ++s) {
+    double blk[64];
+    for (int i = 0; i < 8; ++i)
+      for (int j = 0; j < 8; ++j) blk[i * 8 + j] = M[(int64_t)(8 * s + i) * n + 8 * s + j];
+    if (or_cholesky(8, blk, Lb + 64 * s) != 0) status = -1;
+  }
+  double bb = 0;
+  for (int i = 0; i < n; ++i) { x[i] = 0; r[i] = b[i]; bb += b[i] * b[i]; }
+  if (status == 0 && bb > 0) {
+    for (int s = 0; s < nb; ++s) chol_solve(8, Lb + 64 * s, r + 8 * s, z + 8 * s);
+    double rz = 0;
+    for (int i = 0; i < n; ++i) { p[i] = z[i]; rz += r[i] * z[i]; }
+    while (it < n) {
+      ++it;
+      double pq = 0;
+      for (int i = 0; i < n; ++i) {
+        double t = 0;
+        for (int j = 0; j < n; ++j) t += M[(int64_t)i * n + j] * p[j];
+        q[i] = t;
+        pq += p[i] * t;
+      }
+      if (!(pq > 0.0) || !isfinite(pq)) { status = -1; break; }
+      const double alpha = rz / pq;
+      double rr = 0;
+      for (int i = 0; i < n; ++i) {
+        x[i] += alpha * p[i];
+        r[i] -= alpha * q[i];
+        rr += r[i] * r[i];
+      }
+      if (rr <= tol * tol * bb) break;
+      for (int s = 0; s < nb; ++s) chol_solve(8, Lb + 64 * s, r + 8 * s, z + 8 * s);
+      double rzn = 0;
+      for (int i = 0; i < n; ++i) rzn += r[i] * z[i];
+      const double beta = rzn / rz;
+      for (int i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+      rz = rzn;
+    }
+  }
+  if (iters) *iters = it;
+  free(Lb); free(r); free(z); free(p); free(q);
+  return status;
+}
+
 /* Levenberg-Marquardt on one direction's augmented Lagrangian (minimisation M1).
  * Damping follows Nielsen's rule (Madsen, Nielsen & Tingleff 2004, Sec. 3.2): lambda_0 =
  * tau * max diag(A), A = H_GN + rho I; step (A + lambda I) delta = -G; predicted decrease
- * ell = delta.(lambda delta - G)/2; accept iff ell > 0 and the objective decreases.
+ * ell = delta.(lambda delta - G)/2; accept iff ell > 0 and the objective decreases.  The step is
+ * the Cholesky solution, or (solver OR_SOLVE_PCG) the conjugate-gradient iterate at the stated
+ * residual tolerance: a CG iterate from zero satisfies delta.(A + lambda I) delta = -G.delta
+ * (its residual is orthogonal to the Krylov space holding delta), so ell keeps the same form.
  * Stopping: after an iteration whose step predicts ell <= lm_tol * F (F the objective before
  * the step) the run ends, the trace rows of the iterations not run repeating (F, lambda) with
  * accepted = 0; lm_tol = 0 runs all iterations. */
@@ -331,11 +391,17 @@ static void lm_dir(const dir_problem *P, double complex *Jd, int iters, double l
     const double F_before = F;
     memcpy(Mw, A, sizeof(double) * n * n);
     for (int i = 0; i < n; ++i) Mw[(int64_t)i * n + i] += lambda;
-    if (or_cholesky(n, Mw, L) != 0) {
+    for (int i = 0; i < 4 * N; ++i) { rhs[2 * i] = -creal(G[i]); rhs[2 * i + 1] = -cimag(G[i]); }
+    int solved;
+    if (P->solver == OR_SOLVE_PCG) {
+      solved = or_pcg(n, Mw, rhs, P->cg_tol, delta, NULL) == 0;
+    } else {
+      solved = or_cholesky(n, Mw, L) == 0;
+      if (solved) chol_solve(n, L, rhs, delta);
+    }
+    if (!solved) {
       lambda *= nu; nu *= 2.0;
     } else {
-      for (int i = 0; i < 4 * N; ++i) { rhs[2 * i] = -creal(G[i]); rhs[2 * i + 1] = -cimag(G[i]); }
-      chol_solve(n, L, rhs, delta);
       double ell = 0;
       for (int i = 0; i < 4 * N; ++i)
         ell += delta[2 * i] * (lambda * delta[2 * i] - creal(G[i]))
@@ -379,6 +445,8 @@ static void make_problem(const or_cfg *c, const or_data *d, int f, int k, const 
   P->ck = d->coh + coh_offset(c, f) + (int64_t)k * samples_of(c, f);
   P->flag = d->flags ? d->flags + (int64_t)f * P->B : NULL;
   P->Y = Y; P->BZ = BZ; P->rho = rho;
+  P->solver = c->solver;
+  P->cg_tol = c->cg_tol;
 }
 
 void or_dir_objective(const or_cfg *c, const or_data *d, const double complex *J,

@@ -33,7 +33,12 @@ typedef struct {
   int lm_iters, sage_sweeps;
   uint32_t options;
   double lm_tol;           /* stop a direction's LM once a step's predicted decrease <= lm_tol*F */
+  int solver;              /* damped normal equations: OR_SOLVE_CHOLESKY or OR_SOLVE_PCG         */
+  double cg_tol;           /* OR_SOLVE_PCG: stop once ||r|| <= cg_tol ||G||                      */
 } or_cfg;
+
+#define OR_SOLVE_CHOLESKY 0
+#define OR_SOLVE_PCG 1
 
 typedef struct {
   const double complex *vis;    /* [sum_f S_f][2][2] */
@@ -68,6 +73,9 @@ int or_admm_solve(const or_cfg *c, const or_data *d, int iters, double complex *
 
 /* textbook helpers exposed for pinning */
 int or_cholesky(int n, const double *A, double *L);
+/* preconditioned conjugate gradients on the SPD system M x = b (block-Jacobi, 8x8 blocks), x0 = 0;
+ * returns -1 on a non-positive curvature or block, else 0; *iters receives the iterations run */
+int or_pcg(int n, const double *M, const double *b, double tol, double *x, int *iters);
 int or_polar2(const double complex *A, double complex *U);
 int or_lstsq(int m, int n, const double *A, int nrhs, const double complex *X, double complex *Z);
 int or_num_threads(void);
