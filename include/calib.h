@@ -145,6 +145,36 @@ calib_status admm_local_step(calib_ctx *ctx, int32_t admm_iter);
  * residuals of Section 4.1 into the trace row of admm_iter. */
 calib_status admm_consensus_update(calib_ctx *ctx, int32_t admm_iter);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the fusion-centre part of admm_consensus_update at an
+ * iteration after the first, on caller-owned arrays and without a context - Z_k, B_f Z_k, the
+ * dual update of Y and the primal and dual residuals - computed by the same kernels.  Their
+ * working memory (basis values, the per-direction least-squares operator, residual partials,
+ * direction counts, a rank flag) is a fixed 4 MiB device array inside the library, one per GPU,
+ * held until the process ends; nothing is allocated or freed.
+ *   n_stations N in [2, 128], n_subbands P >= 1, n_basis Q in [1, 8], n_dirs_max K in [1, 16], with
+ *   P*(Q + K*Q + K) + K + 4 + (P + 3)/2 <= 524288 (else CALIB_E_INVAL, nothing enqueued)
+ *   n_dirs   device int32 [P] directions per subband (nested 0..K_f-1), or NULL = K for all
+ *   freq_hz  device double [P];  f0_hz > 0;  rho  device double [K], >= 0
+ *   jones    device double complex [P][K][N][2][2] (read only)
+ *   y        device, same layout: Y in, Y + rho (J - B_f Z) out
+ *   z        device double complex [K][Q][N][2][2]: the previous Z in (for the dual residual), the
+ *            new Z out
+ *   bz       device, J's layout: B_f Z out (slots of directions a subband does not carry are
+ *            left as they are, as are those of y)
+ *   residuals device double [2] (primal, dual of Section 4.1) or NULL
+ *   status   device int32 [1] or NULL: CALIB_OK, or CALIB_E_RANK when the basis matrix of the
+ *            subbands carrying some direction is rank deficient (then y, z, bz and residuals are
+ *            left unchanged)
+ * Enqueued on hip_stream (of the current device), returns without synchronising.  Calls that
+ * overlap on one GPU share the working memory and race; each call rewrites all of it.  Errors are
+ * reported by calib_last_error(NULL). */
+calib_status calib_consensus_noalloc(int32_t n_stations, int32_t n_subbands, int32_t n_basis,
+                                     int32_t n_dirs_max, const int32_t *n_dirs,
+                                     const double *freq_hz, double f0_hz, const double *rho,
+                                     const double *jones, double *y, double *z, double *bz,
+                                     double *residuals, int32_t *status, void *hip_stream);
+
 /* The whole C-ADMM loop: iterations 0..max_iters-1 of local step + consensus update.  Iteration
  * 0 is enqueued kernel by kernel; the launch sequence of the later iterations is identical, so it
  * is captured once into a HIP graph and replayed (not while kernel timing is enabled).  With

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(PKG, LIB_NAME)
 BUILD_DIR = os.path.join(PKG, "_build")
 
 SOURCES = ["stream_kernels.hip", "lm_kernels.hip", "chol_kernel.hip", "chol_blocked.hip",
-           "consensus_kernels.hip",
+           "consensus_kernels.hip", "consensus_noalloc.hip",
            "warmstart_kernels.hip", "mlp_kernels.hip", "calib_host.cpp", "mlp_host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -27,7 +27,7 @@ EXPORTS = ["calib_init", "admm_local_step", "admm_consensus_update", "admm_solve
            "calib_set_jones", "calib_set_state", "calib_warmstart_features", "calib_warmstart_target",
            "calib_warmstart_apply", "calib_mlp_create", "calib_mlp_forward", "calib_mlp_train_step", "calib_mlp_get",
            "calib_mlp_destroy", "calib_mlp_last_error", "calib_set_kernel_timing",
-           "calib_destroy", "calib_last_error"]
+           "calib_destroy", "calib_last_error", "calib_consensus_noalloc"]
 WS_FEATURES = 32
 WS_OUTPUTS = 8
 WS_SCALE = 10.0
@@ -87,7 +87,9 @@ def load(path: str = LIB_PATH):
         lib.calib_mlp_destroy.restype = None
         lib.calib_mlp_last_error.argtypes = [vp]
         lib.calib_mlp_last_error.restype = C.c_char_p
-        for name in ("calib_init", "admm_local_step", "admm_consensus_update", "admm_solve",
+        lib.calib_consensus_noalloc.argtypes = [i32, i32, i32, i32, vp, vp, dbl, vp, vp, vp, vp,
+                                                vp, vp, vp, vp]
+        for name in ("calib_consensus_noalloc", "calib_init", "admm_local_step", "admm_consensus_update", "admm_solve",
                      "calib_get", "calib_set_jones", "calib_set_state", "calib_set_kernel_timing",
                      "calib_warmstart_features", "calib_warmstart_target", "calib_warmstart_apply",
                      "calib_mlp_create",
@@ -293,6 +295,19 @@ class MLP:
             self.close()
         except Exception:
             pass
+
+
+def consensus_noalloc(N: int, P: int, Q: int, K: int, n_dirs, freq, f0: float, rho, jones, y, z,
+                      bz, residuals=None, status=None, stream=None):
+    """calib_consensus_noalloc on device tensors (y and z updated in place, bz written)."""
+    import torch
+    lib = load()
+    s = torch.cuda.current_stream() if stream is None else stream
+    st = lib.calib_consensus_noalloc(int(N), int(P), int(Q), int(K), _ptr(n_dirs), _ptr(freq),
+                                     float(f0), _ptr(rho), _ptr(jones), _ptr(y), _ptr(z), _ptr(bz),
+                                     _ptr(residuals), _ptr(status), C.c_void_p(s.cuda_stream))
+    if st != 0:
+        raise CalibError(st, lib.calib_last_error(None).decode())
 
 
 def n_params(dims) -> int:

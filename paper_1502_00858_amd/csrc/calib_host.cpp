@@ -38,6 +38,8 @@ struct DevAlloc {
 };
 }  // namespace
 
+void calib::set_context_free_error(const char *msg) { g_init_error = msg; }
+
 struct calib_ctx {
   int N = 0, P = 0, Q = 0, K = 0, T = 0;
   calib_precision precision = CALIB_FP64;

@@ -100,6 +100,9 @@ struct Buffers {
   int *iter;                            // ADMM iteration whose trace row is being written
   int *chol_fail;                       // [P] blocked solver: a pivot failed in this solve
   double *chol_ld;                      // [P][panels][64*64] blocked solver: diagonal blocks' L
+  const int *rank_fail;                 // set by the basis setup of a context-free consensus
+                                        // update: the Z fit, Y update and residuals do nothing
+                                        // (null in a context, whose rank is checked at init)
 };
 
 // The direction a launch works on for subband f: its argument k, or (k < 0) the subband's own
@@ -175,6 +178,8 @@ hipError_t launch_ws_choose(const Problem &pb, const Buffers &B, const double *c
                             const double *cost1, const double *Jsave, int32_t *kept, hipStream_t s);
 
 hipError_t launch_fill_identity(double *J, int64_t nblocks, hipStream_t s);
+// message returned by calib_last_error(NULL) for entry points that take no context
+void set_context_free_error(const char *msg);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 
 }  // namespace calib

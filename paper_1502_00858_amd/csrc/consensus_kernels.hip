@@ -206,6 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_gpa(Problem pb, Layout L, Buffers B,
 constexpr int kZThreads = 1024;
 __global__ __launch_bounds__(kZThreads) void k_z_fit(Problem pb, Layout L, Buffers B) {
   __shared__ double red[kZThreads / 64];
+  if (B.rank_fail && *B.rank_fail) return;
   const int k = blockIdx.x, N = pb.N, P = pb.P, Q = pb.Q;
   const double rho = B.rho[k];
   const double *W = B.fitw + (int64_t)k * Q * P;
@@ -240,6 +241,7 @@ __global__ __launch_bounds__(kZThreads) void k_z_fit(Problem pb, Layout L, Buffe
 // grid (P, K): B_f Z_k, dual ascent, primal partial ||J - BZ||^2
 __global__ __launch_bounds__(kBlock) void k_y_update(Problem pb, Layout L, Buffers B) {
   __shared__ double red[1][kBlock / 64];
+  if (B.rank_fail && *B.rank_fail) return;
   const int f = blockIdx.x, k = blockIdx.y, N = pb.N, Q = pb.Q;
   const int64_t slot = (int64_t)f * pb.K + k;
   if (k >= L.ndir[f]) {
@@ -269,6 +271,7 @@ __global__ __launch_bounds__(kBlock) void k_y_update(Problem pb, Layout L, Buffe
 __global__ __launch_bounds__(64) void k_residuals(Problem pb, Buffers B) {
   __shared__ double sps[64];
   __shared__ int spc[64];
+  if (B.rank_fail && *B.rank_fail) return;
   const int t = threadIdx.x;
   double ps = 0.0;
   int pc = 0;
