@@ -158,7 +158,10 @@ def main():
                     help="choose tile_group / stream_grid with paper_1502_00858_amd.autotune")
     ap.add_argument("--batch", type=int, default=512, help="training minibatch rows")
     ap.add_argument("--solver", type=int, default=0,
-                    help="normal-equation solver: 0 auto, 1 one workgroup per matrix, 2 blocked")
+                    help="normal-equation solver: 0 auto (Cholesky), 1 one workgroup per matrix, "
+                         "2 blocked panels, 3 matrix-free conjugate gradients")
+    ap.add_argument("--cg-tol", type=float, default=0.0,
+                    help="solver 3: relative residual at which CG stops (0 = library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the method's cross-subband exchange is a device-wide "
@@ -182,7 +185,8 @@ def main():
     train_iv = []
     for e in range(args.train_episodes):
         train_iv += warmstart.solve_episode(cfg, e, args.episode_intervals, prec, args.chain_iters,
-                                            lm_iters, lm_tol=args.lm_tol)
+                                            lm_iters, lm_tol=args.lm_tol, solver=args.solver,
+                                            cg_tol=args.cg_tol)
         log(f"training episode {e} solved ({time.perf_counter() - t0:.1f} s)")
     gen_s = time.perf_counter() - t0
     X, Y = warmstart.stack_rows(train_iv)
@@ -193,7 +197,8 @@ def main():
 
     # ---- the measured interval and its predecessors (untimed) -----------------------------------
     chain = warmstart.solve_episode(cfg, TEST_EPISODE, args.episode_intervals, prec,
-                                    args.chain_iters, lm_iters, count=J_EVAL, lm_tol=args.lm_tol)
+                                    args.chain_iters, lm_iters, count=J_EVAL, lm_tol=args.lm_tol,
+                                    solver=args.solver, cg_tol=args.cg_tol)
     prev, prev2 = chain[-1], chain[-2]
     data = synth.episode_interval(cfg, TEST_EPISODE, J_EVAL, args.episode_intervals)
     P, B = int(data["P"]), cfg.B
@@ -209,10 +214,10 @@ def main():
         log(f"autotune: {shape}")
     ctx = calib.Calib(data, vis, coh, flags, precision=prec, lm_iters=lm_iters, options=0,
                       tile_group=shape["tile_group"], stream_grid=shape["stream_grid"],
-                      lm_tol=args.lm_tol, solver=args.solver)
+                      lm_tol=args.lm_tol, solver=args.solver, cg_tol=args.cg_tol)
     ctx_id = calib.Calib(data, vis, coh, flags, precision=prec, lm_iters=lm_iters,
                          options=calib.OPT_GPA_FIRST_ITER, tile_group=shape["tile_group"],
-                         stream_grid=shape["stream_grid"], lm_tol=args.lm_tol, solver=args.solver)
+                         stream_grid=shape["stream_grid"], lm_tol=args.lm_tol, solver=args.solver, cg_tol=args.cg_tol)
     J_id = torch.from_numpy(synth.identity_jones(P, cfg.K, cfg.N)).cuda()
 
     def start_plain():
@@ -238,7 +243,7 @@ def main():
     # the same target with every LM run at its full iteration count: the stopping rule must not
     # move the cost that the solves reach
     ctx0 = calib.Calib(data, vis, coh, flags, precision=prec, lm_iters=lm_iters, options=0,
-                       tile_group=shape["tile_group"], stream_grid=shape["stream_grid"], solver=args.solver)
+                       tile_group=shape["tile_group"], stream_grid=shape["stream_grid"], solver=args.solver, cg_tol=args.cg_tol)
     ctx0.set_state(prev.J, prev.Y, prev.Z, prev.BZ)
     g_inf0 = float(np.median(ctx0.solve(args.ref_iters)[args.ref_iters // 2:, 0]))
 
@@ -282,7 +287,8 @@ def main():
     out["learned_kept_subbands"] = int(kept.sum())
     out["tile_shape"] = shape
     out["solver"] = {0: "auto (blocked below 128 subbands, else one workgroup per matrix)",
-                     1: "one workgroup per matrix", 2: "blocked panels"}[args.solver]
+                     1: "one workgroup per matrix", 2: "blocked panels",
+                     3: f"matrix-free conjugate gradients (cg_tol {args.cg_tol or 1e-10:g})"}[args.solver]
     out["training"] = {"rows": int(X.shape[0]), "epochs": args.epochs, "batch": args.batch,
                        "pair_generation_s": round(gen_s, 2), "train_s": round(train_s, 2),
                        "final_loss": net.history[-1],

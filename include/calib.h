@@ -96,10 +96,16 @@ typedef struct {
                               the step); 0 = always lm_iters iterations.  Skipped iterations
                               launch nothing for that subband; their CALIB_FIELD_LM_TRACE rows
                               repeat (F, lambda) with accepted = 0                             */
-  int32_t solver;          /* Cholesky solver of the damped normal equations: 1 = one workgroup
-                              per subband matrix, 2 = 64-column panels spread over many
-                              workgroups per matrix (for batches that leave compute units idle),
-                              0 = chosen from the number of subbands                           */
+  int32_t solver;          /* solver of the damped normal equations of each LM step: 1 = Cholesky,
+                              one workgroup per subband matrix; 2 = Cholesky in 64-column panels
+                              spread over many workgroups per matrix (for batches that leave
+                              compute units idle); 3 = matrix-free preconditioned conjugate
+                              gradients on the Gauss-Newton operator (no dense matrix is formed:
+                              the operator is applied from S_b and J, Section 3 and Appendix A
+                              operator form), stopped at cg_tol; 0 = Cholesky, chosen from the
+                              number of subbands                                               */
+  double cg_tol;           /* solver 3: stop once ||G + (H + (rho + lambda) I) delta|| <= cg_tol ||G||
+                              (or after 8N iterations); 0 = 1e-10                              */
 } calib_config;
 
 /* Field selectors for calib_get. */
@@ -178,6 +184,8 @@ calib_status calib_consensus_noalloc(int32_t n_stations, int32_t n_subbands, int
 /* The whole C-ADMM loop: iterations 0..max_iters-1 of local step + consensus update.  Iteration
  * 0 is enqueued kernel by kernel; the launch sequence of the later iterations is identical, so it
  * is captured once into a HIP graph and replayed (not while kernel timing is enabled).  With
+ * solver 3 the whole local step is one launch whose workgroups apply the LM stopping rule
+ * themselves, so the graph is replayed whatever lm_tol is.  With a Cholesky solver and
  * lm_tol > 0 the local step is launched directly instead, one LM iteration of every unfinished
  * subband per step, each subband moving through its own directions and SAGE sweeps; after each
  * step's solve the host reads a word of pinned memory that the device writes (whether every
@@ -210,13 +218,19 @@ calib_status calib_set_state(calib_ctx *ctx, const void *jones, const void *y, c
 /* Kernel classes reported by CALIB_FIELD_KERNEL_TIMES. */
 #define CALIB_KERNEL_REFRESH 0      /* full residual + statistics of the first direction        */
 #define CALIB_KERNEL_LM_BEGIN 1     /* initial objective and damping of a direction            */
-#define CALIB_KERNEL_ASSEMBLE 2     /* gradient and Gauss-Newton normal equations              */
-#define CALIB_KERNEL_CHOL_SOLVE 3   /* batched FP64 Cholesky factorisation and solve           */
+#define CALIB_KERNEL_ASSEMBLE 2     /* gradient and dense Gauss-Newton normal equations (the
+                                       Cholesky solvers only)                                   */
+#define CALIB_KERNEL_CHOL_SOLVE 3   /* batched FP64 solve of the damped normal equations
+                                       (Cholesky factorisation, or the gradient and conjugate
+                                       gradients of solver 3)                                   */
 #define CALIB_KERNEL_TRIAL 4        /* streaming pass at the LM trial point                     */
 #define CALIB_KERNEL_LM_UPDATE 5    /* gain ratio, accept/reject, damping update                */
 #define CALIB_KERNEL_COMMIT 6       /* SAGE residual commit + statistics of the next direction  */
 #define CALIB_KERNEL_CONSENSUS 7    /* Lagrangian trace, alignment, Z, B_f Z, Y, residuals      */
-#define CALIB_NUM_KERNELS 8
+#define CALIB_KERNEL_LOCAL_STEP 8   /* solver 3: every subband's whole local step (LM runs with
+                                       the matrix-free solve, stopping rule, SAGE commits) in one
+                                       launch after the refresh                               */
+#define CALIB_NUM_KERNELS 9
 #define CALIB_FIELD_KERNEL_TIMES 9  /* host double [CALIB_NUM_KERNELS][2]: launches and total
                                        milliseconds since timing was enabled (synchronises)     */
 

@@ -13,7 +13,7 @@ LIB_NAME = "libcalib_mi355x.so"
 LIB_PATH = os.path.join(PKG, LIB_NAME)
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["stream_kernels.hip", "lm_kernels.hip", "chol_kernel.hip", "chol_blocked.hip",
+SOURCES = ["stream_kernels.hip", "lm_kernels.hip", "chol_kernel.hip", "chol_blocked.hip", "pcg_kernel.hip",
            "consensus_kernels.hip", "consensus_noalloc.hip",
            "warmstart_kernels.hip", "mlp_kernels.hip", "calib_host.cpp", "mlp_host.cpp"]
 

@@ -20,7 +20,7 @@ OPT_UNREG_FIRST = 2
 (FIELD_J, FIELD_Z, FIELD_BZ, FIELD_Y, FIELD_MODEL_VIS, FIELD_COST, FIELD_TRACE, FIELD_LM_TRACE,
  FIELD_LM_STEP, FIELD_KERNEL_TIMES) = range(10)
 KERNELS = ["refresh", "lm_begin", "assemble", "chol_solve", "trial", "lm_update", "commit",
-           "consensus"]
+           "consensus", "local_step"]
 STATUS = {0: "CALIB_OK", 1: "CALIB_E_INVAL", 2: "CALIB_E_NOMEM", 3: "CALIB_E_DEVICE",
           4: "CALIB_E_RANK", 5: "CALIB_E_NUMERIC", 6: "CALIB_E_STATE"}
 EXPORTS = ["calib_init", "admm_local_step", "admm_consensus_update", "admm_solve", "calib_get",
@@ -47,7 +47,7 @@ class _Config(C.Structure):
                 ("rho", C.POINTER(C.c_double)), ("precision", C.c_int),
                 ("lm_iters", C.c_int32), ("sage_sweeps", C.c_int32), ("options", C.c_uint32),
                 ("tile_group", C.c_int32), ("stream_grid", C.c_int32), ("lm_tol", C.c_double),
-                ("solver", C.c_int32)]
+                ("solver", C.c_int32), ("cg_tol", C.c_double)]
 
 
 _lib = None
@@ -119,7 +119,7 @@ class Calib:
     def __init__(self, data: dict, vis, coh, flags=None, jones0=None, precision: int = CALIB_FP64,
                  lm_iters: Optional[int] = None, sage_sweeps: int = 1,
                  options: int = OPT_GPA_FIRST_ITER, rho=None, stream=None, tile_group: int = 0,
-                 stream_grid: int = 0, lm_tol: float = 0.0, solver: int = 0):
+                 stream_grid: int = 0, lm_tol: float = 0.0, solver: int = 0, cg_tol: float = 0.0):
         import torch
         self.lib = load()
         self.N, self.P, self.Q, self.K, self.T = (int(data[k]) for k in ("N", "P", "Q", "K", "T"))
@@ -137,7 +137,7 @@ class Calib:
                       self._freq.ctypes.data_as(C.POINTER(C.c_double)), float(data["f0"]),
                       self._rho.ctypes.data_as(C.POINTER(C.c_double)), int(precision),
                       self.lm_iters, int(sage_sweeps), int(options), int(tile_group),
-                      int(stream_grid), float(lm_tol), int(solver))
+                      int(stream_grid), float(lm_tol), int(solver), float(cg_tol))
         self.stream = torch.cuda.current_stream() if stream is None else stream
         ctx = C.c_void_p()
         st = self.lib.calib_init(C.byref(cfg), _ptr(vis), _ptr(coh), _ptr(flags), _ptr(jones0),

@@ -201,6 +201,14 @@ calib_status run_local_step(calib_ctx *c, int admm_iter, hipStream_t s) {
   const Layout &L = c->L;
   const Buffers &B = c->B;
   HIPCHK(c, timed(c, CALIB_KERNEL_REFRESH, [&] { return launch_refresh<T>(pb, L, B, s); }));
+  if (pb.solver == kSolverPcg) {
+    // every subband's whole local step in one launch: the LM runs, the stopping rule and the
+    // SAGE commits stay on the device
+    HIPCHK(c, timed(c, CALIB_KERNEL_LOCAL_STEP, [&] {
+      return launch_local_step(pb, L, B, unreg, c->lm_trace, c->lm_iters, c->sage_sweeps, s);
+    }));
+    return CALIB_OK;
+  }
   for (int sw = 0; sw < c->sage_sweeps; ++sw)
     for (int k = 0; k < c->K; ++k) {
       HIPCHK(c, timed(c, CALIB_KERNEL_LM_BEGIN, [&] { return launch_lm_begin(pb, L, B, k, unreg, s); }));
@@ -350,7 +358,9 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
     return fail(nullptr, CALIB_E_INVAL, "lm_iters and sage_sweeps must be >= 1");
   if (!(cfg->lm_tol >= 0.0) || !std::isfinite(cfg->lm_tol))
     return fail(nullptr, CALIB_E_INVAL, "lm_tol must be finite and >= 0");
-  if (cfg->solver < 0 || cfg->solver > 2) return fail(nullptr, CALIB_E_INVAL, "solver must be 0, 1 or 2");
+  if (cfg->solver < 0 || cfg->solver > 3) return fail(nullptr, CALIB_E_INVAL, "solver must be 0, 1, 2 or 3");
+  if (!(cfg->cg_tol >= 0.0) || !(cfg->cg_tol < 1.0))
+    return fail(nullptr, CALIB_E_INVAL, "cg_tol must be in [0, 1)");
 
   calib_ctx *c = new calib_ctx();
   c->N = N; c->P = P; c->Q = Q; c->K = K; c->T = T;
@@ -466,7 +476,9 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   pb.lm_tol = cfg->lm_tol;
   pb.solver = cfg->solver == 1 ? kSolverSingle
               : cfg->solver == 2 ? kSolverBlocked
+              : cfg->solver == 3 ? kSolverPcg
               : (P < kBlockedSolverMaxSubbands ? kSolverBlocked : kSolverSingle);
+  pb.cg_tol = cfg->cg_tol > 0.0 ? cfg->cg_tol : kDefaultCgTol;
 
   calib_status st = CALIB_OK;
 #define UPL(dst, src)                                                                          \
@@ -516,8 +528,12 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   DALLOC(B.Jstart, (size_t)P * N * 8 * 8); DALLOC(B.Jtrial, (size_t)P * N * 8 * 8);
   DALLOC(B.D0, (size_t)nb_total * 8 * 8); DALLOC(B.D1, (size_t)nb_total * 8 * 8);
   DALLOC(B.Dstart, (size_t)nb_total * 8 * 8);
-  DALLOC(B.H, (size_t)P * pb.npad * pb.nf * 8);
-  DALLOC(B.Linv, (size_t)P * (pb.nf / 16) * 256 * 8);
+  B.H = nullptr;
+  B.Linv = nullptr;
+  if (pb.solver != kSolverPcg) {   // the dense normal equations of the Cholesky solvers
+    DALLOC(B.H, (size_t)P * pb.npad * pb.nf * 8);
+    DALLOC(B.Linv, (size_t)P * (pb.nf / 16) * 256 * 8);
+  }
   DALLOC(B.G, (size_t)P * pb.nf * 8); DALLOC(B.delta, (size_t)P * pb.nf * 8);
   DALLOC(B.cost_part, (size_t)std::max(pb.ntiles, 1) * 8);
   DALLOC(B.Epart, (size_t)std::max(pb.ntiles, 1) * 8);
@@ -567,7 +583,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
       dev(c->precision == CALIB_FP64 ? launch_coh_stats<double>(pb, L, B, s)
                                      : launch_coh_stats<float>(pb, L, B, s),
           "coherency statistics") &&
-      dev(launch_zero(B.H, (int64_t)P * pb.npad * pb.nf, s), "zero H") &&
+      (!B.H || dev(launch_zero(B.H, (int64_t)P * pb.npad * pb.nf, s), "zero H")) &&
       dev(hipMemsetAsync(B.lm, 0, (size_t)P * sizeof(LmState), s), "zero LM state") &&
       (!B.chol_fail || dev(hipMemsetAsync(B.chol_fail, 0, (size_t)P * sizeof(int), s), "zero flags")) &&
       dev(launch_zero(B.Y, (int64_t)nj, s), "zero Y") && dev(launch_zero(B.BZ, (int64_t)nj, s), "zero BZ") &&
@@ -612,7 +628,9 @@ calib_status admm_solve(calib_ctx *ctx, int32_t max_iters, double rel_cost_tol, 
   if (max_iters < 0 || max_iters > kMaxTrace) return fail(ctx, CALIB_E_INVAL, "max_iters out of range");
   int n = 0;
   double prev = 0.0;
-  const bool stopping = ctx->pb.lm_tol > 0.0;
+  // the host-driven local step of the stopping rule (Cholesky solvers); the matrix-free solver
+  // applies the rule inside its one-launch local step, so its iterations replay a graph as well
+  const bool stopping = ctx->pb.lm_tol > 0.0 && ctx->pb.solver != kSolverPcg;
   for (; n < max_iters; ++n) {
     calib_status st = CALIB_OK;
     if (stopping) {

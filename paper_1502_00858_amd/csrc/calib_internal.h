@@ -65,11 +65,14 @@ struct Problem {
   int nbt;         // unflagged baselines over all subbands
   int stream_grid; // 0 = one workgroup per tile, else persistent grid size
   double lm_tol;   // LM stops once a step's predicted decrease <= lm_tol * F (0 = never)
-  int solver;      // normal-equation solver: kSolverSingle or kSolverBlocked
+  int solver;      // normal-equation solver: kSolverSingle, kSolverBlocked or kSolverPcg
+  double cg_tol;   // kSolverPcg: relative residual at which conjugate gradients stop
 };
 
 constexpr int kSolverSingle = 1;    // one workgroup per matrix (chol_kernel.hip)
 constexpr int kSolverBlocked = 2;   // 64-column panels over many workgroups (chol_blocked.hip)
+constexpr int kSolverPcg = 3;       // matrix-free conjugate gradients, no dense H (pcg_kernel.hip)
+constexpr double kDefaultCgTol = 1e-10;
 constexpr int kBlockedSolverMaxSubbands = 128;   // automatic choice: blocked below this batch
 
 struct Buffers {
@@ -145,6 +148,9 @@ hipError_t launch_chol_solve_nd(const Problem &pb, const Buffers &B, int k, cons
 hipError_t launch_chol_blocked(const Problem &pb, const Buffers &B, int k, const int32_t *ndir,
                                double *Ld, int *cfail, hipStream_t s);
 int chol_blocked_panels(const Problem &pb);
+// the whole local step of every subband in one launch (after the refresh), solver kSolverPcg
+hipError_t launch_local_step(const Problem &pb, const Layout &L, const Buffers &B, int unreg,
+                             double *lm_trace, int lm_iters, int sweeps, hipStream_t s);
 hipError_t launch_trial_stats(const Problem &pb, const Layout &L, const Buffers &B, int k,
                               hipStream_t s);
 hipError_t launch_lm_update_tr(const Problem &pb, const Layout &L, const Buffers &B, int k, int unreg,

@@ -18,75 +18,18 @@
 // of the matrix augmented with -G^T as an extra row (so the forward substitution falls out of
 // the factorisation), followed by a blocked back substitution.
 #include "calib_internal.h"
+#include "lm_device.h"
 #include "wave_reduce.h"
 
 namespace calib {
 
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-__device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-// Reduce NV values per thread over the workgroup in a fixed order; result in out[] of every
-// thread (broadcast through LDS).
-template <int NV, int NT = kBlock>
-__device__ inline void block_sum_vec(double *v, double (*red)[NT / 64]) {
-  const int w = threadIdx.x >> 6;
-  wave_sum_vec<NV>(v);
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) red[i][w] = v[i];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    double s = 0.0;
-    for (int j = 0; j < NT / 64; ++j) s += red[i][j];
-    v[i] = s;
-  }
-  __syncthreads();
-}
-
-__device__ inline double readlane_d(double x, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
-  return __hiloint2double(hi, lo);
-}
-
-__device__ inline const double *jdir(const Buffers &B, const Problem &pb, int f, int k) {
-  return B.J + ((int64_t)f * pb.K + k) * pb.N * 8;
-}
-
-// data cost of subband f from its tiles' partials (fixed order) + consensus terms at Jx; the data
-// cost alone in *data when given
-__device__ inline double objective(const Problem &pb, const Layout &L, const Buffers &B, int f,
-                                   int k, int unreg, const double *Jx, double (*red)[kBlock / 64],
-                                   double *data = nullptr) {
-  double acc[1] = {0.0};
-  for (int t = L.tile_off[f] + threadIdx.x; t < L.tile_off[f + 1]; t += kBlock) acc[0] += B.cost_part[t];
-  double pen = 0.0;
-  if (!unreg) {
-    const double rho = B.rho[k];
-    const int64_t o = ((int64_t)f * pb.K + k) * pb.N * 8;
-    for (int e = threadIdx.x; e < 8 * pb.N; e += kBlock) {
-      const double d = Jx[e] - B.BZ[o + e];
-      pen += B.Y[o + e] * d + 0.5 * rho * d * d;
-    }
-  }
-  double v[2] = {acc[0], pen};
-  block_sum_vec<2>(v, red);
-  if (data) *data = v[0];
-  return v[0] + v[1];
-}
+using lmd::block_sum_vec;
+using lmd::jdir;
 
 __global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffers B, int k, int unreg,
                                                      int sweeps) {
-  __shared__ double red[2][kBlock / 64];
   const int f = blockIdx.x;
   LmState *st = B.lm + f;
   // k < 0: the subband's own direction.  A subband whose run has ended (and been committed) moves
@@ -113,73 +56,7 @@ __global__ __launch_bounds__(kBlock) void k_lm_begin(Problem pb, Layout L, Buffe
   } else if (k >= L.ndir[f]) {
     return;
   }
-  const double *J = jdir(B, pb, f, k);
-  double E0 = 0.0;
-  const double F = objective(pb, L, B, f, k, unreg, J, red, &E0);
-  // largest diagonal entry of H_GN + rho I: 2 sum_c S_pc (|J_c[0][j]|^2 + |J_c[1][j]|^2) + rho,
-  // from the column norms of the stations' Jones matrices and the dense S.  Wavefront w sums the
-  // rows q of its quarter for every column p (coalesced: lane p reads column p of row q, S being
-  // symmetric), the quarters are added in LDS.
-  constexpr int kW = kBlock / 64;
-  __shared__ double nrm[2][kMaxStations];
-  __shared__ double part[kW][2][kMaxStations];
-  for (int p = threadIdx.x; p < pb.N; p += kBlock) {
-    const double *Jp = J + 8 * p;
-    nrm[0][p] = Jp[0] * Jp[0] + Jp[1] * Jp[1] + Jp[4] * Jp[4] + Jp[5] * Jp[5];
-    nrm[1][p] = Jp[2] * Jp[2] + Jp[3] * Jp[3] + Jp[6] * Jp[6] + Jp[7] * Jp[7];
-  }
-  __syncthreads();
-  const double *Sd = B.Sd + ((int64_t)f * pb.K + k) * pb.N * pb.N;
-  {
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int qn = (pb.N + kW - 1) / kW, q0 = w * qn, q1 = min(pb.N, q0 + qn);
-    for (int p = lane; p < pb.N; p += 64) {
-      double d0 = 0.0, d1 = 0.0;
-#pragma unroll 8
-      for (int q = q0; q < q1; ++q) {
-        const double S = Sd[(int64_t)q * pb.N + p];
-        d0 = fma(S, nrm[0][q], d0);
-        d1 = fma(S, nrm[1][q], d1);
-      }
-      part[w][0][p] = d0;
-      part[w][1][p] = d1;
-    }
-  }
-  __syncthreads();
-  double dmax = 0.0;
-  for (int p = threadIdx.x; p < pb.N; p += kBlock) {
-    double d0 = 0.0, d1 = 0.0;
-#pragma unroll
-    for (int w = 0; w < kW; ++w) {
-      d0 += part[w][0][p];
-      d1 += part[w][1][p];
-    }
-    dmax = fmax(dmax, 2.0 * fmax(d0, d1));
-  }
-  __shared__ double mx[kBlock / 64];
-  dmax = wave_max(dmax);
-  if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = dmax;
-  for (int e = threadIdx.x; e < 8 * pb.N; e += kBlock) B.Jstart[(int64_t)f * pb.N * 8 + e] = J[e];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = 0.0;
-    for (int i = 0; i < kBlock / 64; ++i) m = fmax(m, mx[i]);
-    m += unreg ? 0.0 : B.rho[k];
-    st->F = F;
-    st->E0 = E0;
-    st->lambda = kLmTau * m;
-    st->nu = 2.0;
-    st->accepted = 0;
-    st->chol_ok = 0;
-    st->ell = 0.0;
-    st->done = 0;
-    if (own) {
-      st->cur = cur;
-      st->sweep = sweep;
-      st->phase = kPhaseLm;
-      st->itc = 0;
-    }
-  }
+  lmd::begin_dir(pb, L, B, f, k, unreg, own, cur, sweep);
 }
 
 // One workgroup of two wavefronts per (subband, station row-block), so that all of them are resident
@@ -328,8 +205,6 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble(Problem pb, Layout L, Bu
 
 __global__ __launch_bounds__(kBlock) void k_lm_update(Problem pb, Layout L, Buffers B, int k, int unreg,
                                                       double *lm_trace, int it, int lm_iters) {
-  __shared__ double red[2][kBlock / 64];
-  __shared__ int acc;
   const int f = blockIdx.x;
   LmState *st = B.lm + f;
   const bool own = k < 0;   // the subband's own direction and iteration count
@@ -341,66 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_lm_update(Problem pb, Layout L, Buff
   } else if (k >= L.ndir[f]) {
     return;
   }
-  if (st->done) {
-    // the run has stopped: the trace repeats the final objective and damping
-    if (own && threadIdx.x == 0) st->phase = kPhaseAdvance;
-    if (threadIdx.x == 0 && lm_trace) {
-      double *tr = lm_trace + 3 * ((int64_t)(f * pb.K + k) * lm_iters + it);
-      tr[0] = st->F;
-      tr[1] = st->lambda;
-      tr[2] = 0;
-    }
-    return;
-  }
-  int ok = st->chol_ok;
-  double Fn = 0.0;
-  if (ok) Fn = objective(pb, L, B, f, k, unreg, B.Jtrial + (int64_t)f * pb.N * 8, red);
-  if (threadIdx.x == 0) {
-    int a = 0;
-    if (ok) {
-      const double ell = st->ell, F = st->F;
-      if (pb.lm_tol > 0.0 && ell <= pb.lm_tol * F) st->done = 1;
-      if (ell > 0.0 && F - Fn > 0.0) {
-        const double gain = (F - Fn) / ell;
-        const double t = 2.0 * gain - 1.0;
-        st->lambda *= fmax(1.0 / 3.0, 1.0 - t * t * t);
-        st->nu = 2.0;
-        st->F = Fn;
-        st->accepted += 1;
-        st->dsel ^= 1;   // the trial point's D_b becomes the accepted one
-        a = 1;
-      }
-    }
-    if (!a) {
-      st->lambda *= st->nu;
-      st->nu *= 2.0;
-    }
-    st->Fnew = Fn;
-    acc = a;
-    if (lm_trace) {
-      double *tr = lm_trace + 3 * ((int64_t)(f * pb.K + k) * lm_iters + it);
-      tr[0] = st->F;
-      tr[1] = st->lambda;
-      tr[2] = a;
-      // a run that stops here: the rows of its remaining iterations, which the host may not
-      // launch, get what their updates would write (the final objective and damping)
-      for (int i2 = it + 1; st->done && i2 < lm_iters; ++i2) {
-        double *tn = lm_trace + 3 * ((int64_t)(f * pb.K + k) * lm_iters + i2);
-        tn[0] = st->F;
-        tn[1] = st->lambda;
-        tn[2] = 0;
-      }
-    }
-    if (own) {
-      st->itc = it + 1;
-      if (st->done || it + 1 >= lm_iters) st->phase = kPhaseAdvance;
-    }
-  }
-  __syncthreads();
-  if (acc) {
-    double *J = B.J + ((int64_t)f * pb.K + k) * pb.N * 8;
-    for (int e = threadIdx.x; e < 8 * pb.N; e += kBlock) J[e] = B.Jtrial[(int64_t)f * pb.N * 8 + e];
-  }
+  lmd::update_dir(pb, L, B, f, k, unreg, lm_trace, it, lm_iters, own);
 }
 
 // Dense S_b per (subband, direction): entry (p, q) and (q, p) of the baseline of stations p, q,

@@ -1,0 +1,635 @@
+// Matrix-free solve of the damped Gauss-Newton normal equations of the Levenberg-Marquardt step:
+// (H_GN + (rho + lambda) I) delta = -G by preconditioned conjugate gradients, one workgroup of
+// four wavefronts per subband, without forming H.
+//
+// The coherency is a scalar times I2 (Section 2) and J is time invariant, so the Gauss-Newton
+// matrix depends on the data only through S_pq = sum_s |c_s|^2 of each baseline, and its product
+// with a direction v (N 2x2 complex blocks) is, per station p,
+//     (H_GN v)_p = 2 (v_p Q_p + J_p W_p),   Q_p = sum_q S_pq J_q^H J_q,   W_p = sum_q S_pq v_q^H J_q
+// (the operator form of the Hessian in Section 3 and Appendix A, without the residual term: the
+// Gauss-Newton part).  Both sums are products of the symmetric N x N table S with a stack of
+// per-station 2x2 matrices.  The preconditioner is block Jacobi: the diagonal block of station p
+// is v_p -> v_p (2 Q_p + mu I) (the J_p W_p term only couples other stations), inverted in closed
+// form as a 2x2 Hermitian matrix acting from the right.  Same iteration as the oracle's reading
+// (x0 = 0, stop once ||r|| <= tol ||G|| or after 8N iterations; non-positive curvature fails the
+// step like a failed factorisation).
+//
+// Work layout.  Wavefront 0 owns the vectors: lane l holds x, r, the search direction d, J_p, Q_p
+// and the preconditioner of stations p = l + 64 s (s < SPL), so every dot product is a wavefront
+// sum and the CG recurrences need no barrier.  The table products are split by columns: wavefront
+// w takes stations q in [w C, w C + C), C = ceil(N / 4), keeps S_pq of those columns for its rows
+// p = l + 64 s in registers for the whole solve (read coalesced through the symmetry of S),
+// broadcasts each column's u_q = d_q^H J_q (loaded by lane q - w C) to the wavefront with
+// readlane, and leaves its partial sums in LDS, which wavefront 0 adds in a fixed order.  One CG
+// iteration: wavefront 0 writes u | all wavefronts their partial W | wavefront 0 finishes H d and
+// the recurrences.
+#include "calib_internal.h"
+#include "lm_device.h"
+#include "wave_reduce.h"
+
+namespace calib {
+namespace {
+
+constexpr int kPcgThreads = 256;
+constexpr int kPcgWaves = kPcgThreads / 64;
+
+__device__ inline double bcast(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// c = a b for 2x2 complex matrices (8 doubles, row-major re/im)
+__device__ inline void cmul(const double *a, const double *b, double *c) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const double ar = a[(i * 2 + t) * 2], ai = a[(i * 2 + t) * 2 + 1];
+        const double br = b[(t * 2 + j) * 2], bi = b[(t * 2 + j) * 2 + 1];
+        re += ar * br - ai * bi;
+        im += ar * bi + ai * br;
+      }
+      c[(i * 2 + j) * 2] = re;
+      c[(i * 2 + j) * 2 + 1] = im;
+    }
+}
+
+// c = a^H b
+__device__ inline void chmul(const double *a, const double *b, double *c) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const double ar = a[(t * 2 + i) * 2], ai = -a[(t * 2 + i) * 2 + 1];
+        const double br = b[(t * 2 + j) * 2], bi = b[(t * 2 + j) * 2 + 1];
+        re += ar * br - ai * bi;
+        im += ar * bi + ai * br;
+      }
+      c[(i * 2 + j) * 2] = re;
+      c[(i * 2 + j) * 2 + 1] = im;
+    }
+}
+
+// c = a h for the Hermitian h = [[h0, h2 + i h3], [h2 - i h3, h1]] (4 reals)
+__device__ inline void hmul(const double *a, const double *h, double *c) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const double a0r = a[(i * 2) * 2], a0i = a[(i * 2) * 2 + 1];
+    const double a1r = a[(i * 2 + 1) * 2], a1i = a[(i * 2 + 1) * 2 + 1];
+    c[(i * 2) * 2] = a0r * h[0] + a1r * h[2] + a1i * h[3];
+    c[(i * 2) * 2 + 1] = a0i * h[0] + a1i * h[2] - a1r * h[3];
+    c[(i * 2 + 1) * 2] = a0r * h[2] - a0i * h[3] + a1r * h[1];
+    c[(i * 2 + 1) * 2 + 1] = a0r * h[3] + a0i * h[2] + a1i * h[1];
+  }
+}
+
+// J_q^H J_q as a Hermitian (q00, q11, Re q01, Im q01)
+__device__ inline void gram(const double *Jq, double *v) {
+  v[0] = Jq[0] * Jq[0] + Jq[1] * Jq[1] + Jq[4] * Jq[4] + Jq[5] * Jq[5];
+  v[1] = Jq[2] * Jq[2] + Jq[3] * Jq[3] + Jq[6] * Jq[6] + Jq[7] * Jq[7];
+  v[2] = Jq[0] * Jq[2] + Jq[1] * Jq[3] + Jq[4] * Jq[6] + Jq[5] * Jq[7];
+  v[3] = Jq[0] * Jq[3] - Jq[1] * Jq[2] + Jq[4] * Jq[7] - Jq[5] * Jq[6];
+}
+
+// LDS of one solve; SPL: stations per lane of wavefront 0 (1 for N <= 64, 2 for N <= 128)
+template <int SPL>
+struct PcgLds {
+  double Js[64 * SPL * 8];                  // J of the direction
+  double Us[64 * SPL * 8];                  // u_q = d_q^H J_q
+  double Wp[kPcgWaves][64 * SPL][8];        // per-wavefront partials over its columns
+  int ctl[2];                               // continue, failed
+};
+
+// The gradient and the solve of direction k of subband f (whole workgroup of kPcgThreads): G, the
+// step delta, the trial point J + delta and the predicted decrease in the LM state (chol_ok = 0
+// on a failed solve).  Wavefronts 1-3 return before wavefront 0 writes the results.
+template <int SPL>
+__device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
+                                 int unreg, double tol, PcgLds<SPL> &sh, double *jt_lds = nullptr) {
+  constexpr int kRows = 64 * SPL;               // stations covered
+  constexpr int kC = kRows / kPcgWaves;          // columns per wavefront (at most)
+  constexpr int kBatch = 8 / SPL;                // baselines of the gradient in flight per lane
+  double *Js = sh.Js, *Us = sh.Us;
+  auto &Wp = sh.Wp;
+  int *ctl = sh.ctl;
+  const int N = pb.N, nf = pb.nf;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int C = (N + kPcgWaves - 1) / kPcgWaves, c0 = w * C;
+  LmState *st = B.lm + f;
+  const double lam = st->lambda;
+  const double rho = unreg ? 0.0 : B.rho[k];
+  const double mu = rho + lam;
+  const int64_t jo = ((int64_t)f * pb.K + k) * N * 8;
+  const double *Jg = B.J + jo;
+  const double *Sd = B.Sd + ((int64_t)f * pb.K + k) * N * N;
+
+  // gradient of the data term, gathered over station p's baselines (wavefront w takes every
+  // fourth one): G_p = -2 sum_{q>p} D_pq J_q - 2 sum_{c<p} D_cp^H J_c (+ Y_p + rho (J_p - BZ_p)
+  // below).  The first batch's adjacency entries and D_b are requested before S and J, so that
+  // their two dependent latencies overlap the loads of S and J.
+  const double *Dacc = d_accepted(B, f);
+  int gb[kBatch], oraw[kBatch];
+  double d[kBatch][8];
+  auto request = [&](int s, int ab) {
+    const int p = lane + 64 * s;
+    const int a1 = p < N ? L.adj_off[f * N + p + 1] : 0;
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      const int a = ab + kPcgWaves * i;
+      gb[i] = a < a1 ? L.adj_b[a] : -1;
+      oraw[i] = a < a1 ? L.adj_o[a] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      if (gb[i] >= 0) {
+        const double2 *D2 = reinterpret_cast<const double2 *>(Dacc + 8 * (int64_t)gb[i]);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const double2 x = D2[h];
+          d[i][2 * h] = x.x;
+          d[i][2 * h + 1] = x.y;
+        }
+      }
+    }
+  };
+  double gp[SPL][8];
+  auto consume = [&](int s) {
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      if (gb[i] < 0) continue;
+      const bool first = oraw[i] >= 0;
+      const int o = first ? oraw[i] : -1 - oraw[i];
+      double t[8];
+      if (first) cmul(d[i], Js + 8 * o, t);
+      else chmul(d[i], Js + 8 * o, t);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) gp[s][e] = fma(-2.0, t[e], gp[s][e]);
+    }
+  };
+  int a_first[SPL];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    const int p = lane + 64 * s;
+    a_first[s] = p < N ? L.adj_off[f * N + p] + w : 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) gp[s][e] = 0.0;
+  }
+  request(0, a_first[0]);
+
+  // S_pq for rows p = lane + 64 s and this wavefront's columns q = c0 + j; S is symmetric, so
+  // the read goes down column p of row q (consecutive lanes, consecutive addresses)
+  double S[SPL][kC];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s)
+#pragma unroll
+    for (int j = 0; j < kC; ++j) {
+      const int p = lane + 64 * s, q = c0 + j;
+      S[s][j] = (p < N && j < C && q < N) ? Sd[(int64_t)q * N + p] : 0.0;
+    }
+  for (int e = threadIdx.x; e < 8 * N; e += kPcgThreads) Js[e] = Jg[e];
+  __syncthreads();
+
+  // the rest of the gradient, the next batch in flight while the current one is used (and,
+  // after the first, while the Q partials are formed)
+  int cs = 0, ab = a_first[0];
+  bool more = true;
+  auto advance = [&]() {
+    consume(cs);
+    const int p = lane + 64 * cs;
+    const int a1 = p < N ? L.adj_off[f * N + p + 1] : 0;
+    ab += kPcgWaves * kBatch;
+    if (ab < a1) {
+      request(cs, ab);
+    } else if (cs + 1 < SPL) {
+      ++cs;
+      ab = a_first[cs];
+      request(cs, ab);
+    } else {
+      more = false;
+    }
+  };
+  advance();
+  // Q_p partials: column lane j holds J_q^H J_q of q = c0 + j, broadcast to the wavefront
+  {
+    double vq[4] = {0.0, 0.0, 0.0, 0.0};
+    if (lane < C && c0 + lane < N) gram(Js + 8 * (c0 + lane), vq);
+    double qp[SPL][4];
+#pragma unroll
+    for (int s = 0; s < SPL; ++s)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) qp[s][c] = 0.0;
+#pragma unroll
+    for (int j = 0; j < kC; ++j) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double v = bcast(vq[c], j);
+#pragma unroll
+        for (int s = 0; s < SPL; ++s) qp[s][c] = fma(S[s][j], v, qp[s][c]);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < SPL; ++s)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Wp[w][lane + 64 * s][c] = qp[s][c];
+  }
+  while (more) advance();
+  __syncthreads();   // Q partials in Wp
+  double Qp[SPL][4], Jp[SPL][8];
+  if (w == 0) {
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < kPcgWaves; ++i) v += Wp[i][lane + 64 * s][c];
+        Qp[s][c] = v;
+      }
+    }
+  }
+  __syncthreads();   // Q read; the gradient partials go to Wp
+#pragma unroll
+  for (int s = 0; s < SPL; ++s)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) Wp[w][lane + 64 * s][e] = gp[s][e];
+  __syncthreads();
+
+  // wavefront 0: right-hand side b = -G, preconditioner (2 Q_p + mu I)^-1, x = 0, r = b, d = z
+  double x[SPL][8], r[SPL][8], dv[SPL][8], g[SPL][8], Mi[SPL][4];
+  double bb = 0.0, rz = 0.0, stop = 0.0;
+  int failed = 0;
+  const int maxit = 8 * N;
+  if (w == 0) {
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+      const int p = lane + 64 * s;
+      const bool live = p < N;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < kPcgWaves; ++i) v += Wp[i][p][e];
+        if (live && !unreg) v += B.Y[jo + 8 * p + e] + rho * (Js[8 * p + e] - B.BZ[jo + 8 * p + e]);
+        g[s][e] = live ? v : 0.0;
+        Jp[s][e] = live ? Js[8 * p + e] : 0.0;
+        x[s][e] = 0.0;
+        r[s][e] = -g[s][e];
+        bb = fma(r[s][e], r[s][e], bb);
+      }
+      const double a = 2.0 * Qp[s][0] + mu, dd = 2.0 * Qp[s][1] + mu;
+      const double br = 2.0 * Qp[s][2], bi = 2.0 * Qp[s][3];
+      const double det = a * dd - (br * br + bi * bi);
+      if (live && (!(a > 0.0) || !(det > 0.0) || !isfinite(det))) failed = 1;
+      const double id = live ? 1.0 / det : 0.0;
+      Mi[s][0] = dd * id;
+      Mi[s][1] = a * id;
+      Mi[s][2] = -br * id;
+      Mi[s][3] = -bi * id;
+      hmul(r[s], Mi[s], dv[s]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) rz = fma(r[s][e], dv[s][e], rz);
+    }
+    double v2[2] = {bb, rz};
+    wave_sum_vec<2>(v2);
+    bb = v2[0];
+    rz = v2[1];
+    stop = tol * tol * bb;
+    failed = __any(failed) ? 1 : 0;
+  }
+  for (int it = 0;; ++it) {
+    // wavefront 0: u_p = d_p^H J_p for the partial products, and whether to iterate
+    if (w == 0) {
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) {
+        double u[8];
+        chmul(dv[s], Jp[s], u);
+        double2 *u2 = reinterpret_cast<double2 *>(Us + 8 * (lane + 64 * s));
+#pragma unroll
+        for (int h = 0; h < 4; ++h) u2[h] = make_double2(u[2 * h], u[2 * h + 1]);
+      }
+      if (lane == 0) {
+        ctl[0] = (!failed && bb > 0.0 && it < maxit) ? 1 : 0;
+        ctl[1] = failed;
+      }
+    }
+    __syncthreads();
+    if (!ctl[0]) break;
+    // partial W_p over this wavefront's columns: lane j loads u of column c0 + j
+    {
+      double uq[8];
+      const int q = min(c0 + lane, kRows - 1);
+      const double2 *u2 = reinterpret_cast<const double2 *>(Us + 8 * q);
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const double2 t = u2[h];
+        uq[2 * h] = t.x;
+        uq[2 * h + 1] = t.y;
+      }
+      double W[SPL][8];
+#pragma unroll
+      for (int s = 0; s < SPL; ++s)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) W[s][e] = 0.0;
+#pragma unroll
+      for (int j = 0; j < kC; ++j) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const double v = bcast(uq[e], j);
+#pragma unroll
+          for (int s = 0; s < SPL; ++s) W[s][e] = fma(S[s][j], v, W[s][e]);
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) {
+        double2 *w2 = reinterpret_cast<double2 *>(&Wp[w][lane + 64 * s][0]);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) w2[h] = make_double2(W[s][2 * h], W[s][2 * h + 1]);
+      }
+    }
+    __syncthreads();
+    if (w != 0) continue;
+    // wavefront 0: (H d)_p = 2 (d_p Q_p + J_p W_p) + mu d_p, then the CG recurrences
+    double Hd[SPL][8], pq = 0.0;
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+      const int p = lane + 64 * s;
+      double W[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < kPcgWaves; ++i) {
+        const double2 *w2 = reinterpret_cast<const double2 *>(&Wp[i][p][0]);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const double2 t = w2[h];
+          W[2 * h] += t.x;
+          W[2 * h + 1] += t.y;
+        }
+      }
+      double t1[8], t2[8];
+      hmul(dv[s], Qp[s], t1);
+      cmul(Jp[s], W, t2);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        Hd[s][e] = 2.0 * (t1[e] + t2[e]) + mu * dv[s][e];
+        pq = fma(dv[s][e], Hd[s][e], pq);
+      }
+    }
+    pq = wave_sum(pq);
+    if (!(pq > 0.0) || !isfinite(pq)) {
+      failed = 1;
+      continue;   // the next pass through the loop head stops every wavefront
+    }
+    const double alpha = rz / pq;
+    double z[SPL][8], v2[2] = {0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        x[s][e] = fma(alpha, dv[s][e], x[s][e]);
+        r[s][e] = fma(-alpha, Hd[s][e], r[s][e]);
+        v2[1] = fma(r[s][e], r[s][e], v2[1]);
+      }
+      hmul(r[s], Mi[s], z[s]);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v2[0] = fma(r[s][e], z[s][e], v2[0]);
+    }
+    wave_sum_vec<2>(v2);
+    if (v2[1] <= stop) {
+      bb = 0.0;   // converged: the loop head stops
+      continue;
+    }
+    const double beta = v2[0] / rz;
+    rz = v2[0];
+#pragma unroll
+    for (int s = 0; s < SPL; ++s)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) dv[s][e] = fma(beta, dv[s][e], z[s][e]);
+  }
+  if (w != 0) return;
+  if (ctl[1]) {
+    if (lane == 0) st->chol_ok = 0;
+    return;
+  }
+  // delta, trial point, gradient for the record, predicted decrease ell = delta.(lambda delta - G)/2
+  double ell = 0.0;
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    const int p = lane + 64 * s;
+    if (p >= N) continue;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int c = 8 * p + e;
+      B.delta[(int64_t)f * nf + c] = x[s][e];
+      B.G[(int64_t)f * nf + c] = g[s][e];
+      B.Jtrial[(int64_t)f * N * 8 + c] = Jp[s][e] + x[s][e];
+      if (jt_lds) jt_lds[c] = Jp[s][e] + x[s][e];
+      ell = fma(x[s][e], fma(lam, x[s][e], -g[s][e]), ell);
+    }
+  }
+  ell = wave_sum(ell);
+  if (lane == 0) {
+    st->ell = 0.5 * ell;
+    st->chol_ok = 1;
+  }
+}
+
+// Per-baseline passes of the one-workgroup local step.  A subband's baselines are spread over all
+// threads, kU at a time per thread with every load of a round issued together (a single workgroup
+// has only its own loads in flight, so each round pays one memory latency), the Jones matrices
+// read from LDS.  Their energy partials are summed over the workgroup and kept in the subband's
+// first tile (the objective adds the tiles of a subband).
+constexpr int kU = 8;   // baselines per thread per round
+
+// Data cost and D_b at the trial point Jt from the start point J0's statistics (lmd::trial_tile)
+__device__ inline void fused_trial(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
+                                   const double *Jt, const double *J0, double (*red)[kBlock / 64]) {
+  const int nb = L.nb[f];
+  const int64_t b0 = L.bl_off[f];
+  const double *Sb = B.Sb + L.sb_off[f] + (int64_t)k * nb;
+  double *Dt = d_trial(B, f);
+  double part = 0.0;
+  for (int base = 0; base < nb; base += kBlock * kU) {
+    int p[kU], q[kU];
+    double S[kU], d0[kU][8];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int bi = base + threadIdx.x + kBlock * u;
+      if (bi < nb) {
+        const int64_t gb = b0 + bi;
+        p[u] = L.bl_p[gb];
+        q[u] = L.bl_q[gb];
+        S[u] = Sb[bi];
+        const double2 *D2 = reinterpret_cast<const double2 *>(B.Dstart + 8 * gb);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const double2 x = D2[h];
+          d0[u][2 * h] = x.x;
+          d0[u][2 * h + 1] = x.y;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int bi = base + threadIdx.x + kBlock * u;
+      if (bi >= nb) continue;
+      double m1[8], m0[8], dt[8];
+      lmd::jjh(Jt + 8 * p[u], Jt + 8 * q[u], m1);
+      lmd::jjh(J0 + 8 * p[u], J0 + 8 * q[u], m0);
+      double cross = 0.0, norm = 0.0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const double dm = m1[e] - m0[e];
+        cross = fma(dm, d0[u][e], cross);
+        norm = fma(dm, dm, norm);
+        dt[e] = fma(-S[u], dm, d0[u][e]);
+      }
+      double2 *T2 = reinterpret_cast<double2 *>(Dt + 8 * (b0 + bi));
+#pragma unroll
+      for (int h = 0; h < 4; ++h) T2[h] = make_double2(dt[2 * h], dt[2 * h + 1]);
+      part += fma(S[u], norm, -2.0 * cross);
+    }
+  }
+  double v[1] = {part};
+  lmd::block_sum_vec<1>(v, reinterpret_cast<double (*)[kBlock / 64]>(red));
+  const int t0 = L.tile_off[f], t1 = L.tile_off[f + 1];
+  for (int t = t0 + threadIdx.x; t < t1; t += kBlock)
+    B.cost_part[t] = t == t0 ? v[0] + B.lm[f].E0 : 0.0;
+}
+
+// SAGE commit of direction k (lmd::commit_tile): every direction l from l0 updates
+// D_l -= X_lk dM for all baselines, one direction per round; the energy changes by
+// sum_b X_kk ||dM||^2 - 2 Re <dM, D_k>.  J1 (the run's final J) and J0 (its start) in LDS.
+__device__ inline void fused_commit(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
+                                    int all, const double *J1, const double *J0,
+                                    double (*red)[kBlock / 64]) {
+  const int Kf = L.ndir[f], nb = L.nb[f], K = pb.K, next = k + 1 < Kf ? k + 1 : 0;
+  const int64_t b0 = L.bl_off[f], nbt = pb.nbt;
+  const int l0 = all ? 0 : k;
+  double part = 0.0;
+  for (int l = l0; l < Kf; ++l) {
+    const bool upd = all || l > k;
+    if (!upd && l != k) continue;
+    for (int base = 0; base < nb; base += kBlock * kU) {
+      int p[kU], q[kU];
+      double d[kU][8], x[kU][2];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int bi = base + threadIdx.x + kBlock * u;
+        if (bi < nb) {
+          const int64_t gb = b0 + bi;
+          p[u] = L.bl_p[gb];
+          q[u] = L.bl_q[gb];
+          const double2 *D2 = reinterpret_cast<const double2 *>(B.Dall + ((int64_t)l * nbt + gb) * 8);
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            const double2 t = D2[h];
+            d[u][2 * h] = t.x;
+            d[u][2 * h + 1] = t.y;
+          }
+          const double2 X = *reinterpret_cast<const double2 *>(B.Xcoh + (((int64_t)l * K + k) * nbt + gb) * 2);
+          x[u][0] = X.x;
+          x[u][1] = X.y;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int bi = base + threadIdx.x + kBlock * u;
+        if (bi >= nb) continue;
+        const int64_t gb = b0 + bi;
+        double m1[8], m0[8], dm[8];
+        lmd::jjh(J1 + 8 * p[u], J1 + 8 * q[u], m1);
+        lmd::jjh(J0 + 8 * p[u], J0 + 8 * q[u], m0);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dm[e] = m1[e] - m0[e];
+        if (l == k) {
+          double cross = 0.0, norm = 0.0;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            cross = fma(dm[e], d[u][e], cross);
+            norm = fma(dm[e], dm[e], norm);
+          }
+          part += fma(x[u][0], norm, -2.0 * cross);
+        }
+        if (upd) {
+          lmd::sub_scaled(d[u], x[u][0], x[u][1], dm);
+          double2 *D2 = reinterpret_cast<double2 *>(B.Dall + ((int64_t)l * nbt + gb) * 8);
+#pragma unroll
+          for (int h = 0; h < 4; ++h) D2[h] = make_double2(d[u][2 * h], d[u][2 * h + 1]);
+          if (l == next) {
+            double2 *A2 = reinterpret_cast<double2 *>(d_accepted(B, f) + 8 * gb);
+            double2 *S2 = reinterpret_cast<double2 *>(B.Dstart + 8 * gb);
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+              A2[h] = make_double2(d[u][2 * h], d[u][2 * h + 1]);
+              S2[h] = make_double2(d[u][2 * h], d[u][2 * h + 1]);
+            }
+          }
+        }
+      }
+    }
+  }
+  double v[1] = {part};
+  lmd::block_sum_vec<1>(v, reinterpret_cast<double (*)[kBlock / 64]>(red));
+  const int t0 = L.tile_off[f], t1 = L.tile_off[f + 1];
+  if (threadIdx.x == 0) B.Epart[t0] += v[0];
+  __syncthreads();
+  for (int t = t0 + threadIdx.x; t < t1; t += kBlock) B.cost_part[t] = B.Epart[t];
+}
+
+// A subband's whole local step in one workgroup: for every SAGE sweep and direction, the LM run
+// (start, then per iteration the gradient and solve, the trial point's statistics, the update
+// with the stopping rule) and the SAGE commit, in the order of the launches of the lockstep local
+// step.  Nothing is launched or read back between LM iterations.
+template <int SPL>
+__global__ __launch_bounds__(kPcgThreads) void k_local_step(Problem pb, Layout L, Buffers B, int unreg,
+                                                            double *lm_trace, int lm_iters, int sweeps) {
+  __shared__ __align__(16) PcgLds<SPL> sh;
+  __shared__ __align__(16) double J0s[64 * SPL * 8];   // the run's start point
+  __shared__ double red[1][kBlock / 64];
+  const int f = blockIdx.x;
+  const int Kf = L.ndir[f];
+  const int all = sweeps > 1;
+  const int n8 = 8 * pb.N;
+  const LmState *st = B.lm + f;
+  for (int sw = 0; sw < sweeps; ++sw)
+    for (int k = 0; k < Kf; ++k) {
+      lmd::begin_dir(pb, L, B, f, k, unreg, false, 0, 0);
+      for (int e = threadIdx.x; e < n8; e += kBlock) J0s[e] = B.Jstart[(int64_t)f * n8 + e];
+      __syncthreads();
+      for (int it = 0; it < lm_iters; ++it) {
+        pcg_solve<SPL>(pb, L, B, f, k, unreg, pb.cg_tol, sh, sh.Us);
+        __syncthreads();
+        if (st->chol_ok) fused_trial(pb, L, B, f, k, sh.Us, J0s, red);
+        __syncthreads();
+        lmd::update_dir(pb, L, B, f, k, unreg, lm_trace, it, lm_iters, false);
+        __syncthreads();
+        if (st->done) break;
+      }
+      for (int e = threadIdx.x; e < n8; e += kBlock) sh.Js[e] = B.J[((int64_t)f * pb.K + k) * n8 + e];
+      __syncthreads();
+      fused_commit(pb, L, B, f, k, all, sh.Js, J0s, red);
+      __syncthreads();
+    }
+}
+
+}  // namespace
+
+hipError_t launch_local_step(const Problem &pb, const Layout &L, const Buffers &B, int unreg,
+                             double *lm_trace, int lm_iters, int sweeps, hipStream_t s) {
+  if (pb.N > kMaxStations || pb.bpt > 64) return hipErrorInvalidValue;
+  if (pb.N <= 64)
+    hipLaunchKernelGGL(k_local_step<1>, dim3(pb.P), dim3(kPcgThreads), 0, s, pb, L, B, unreg, lm_trace,
+                       lm_iters, sweeps);
+  else
+    hipLaunchKernelGGL(k_local_step<2>, dim3(pb.P), dim3(kPcgThreads), 0, s, pb, L, B, unreg, lm_trace,
+                       lm_iters, sweeps);
+  return hipGetLastError();
+}
+
+}  // namespace calib

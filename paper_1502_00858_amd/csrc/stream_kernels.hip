@@ -22,6 +22,7 @@
 // energy is reduced into one FP64 partial per tile, summed later in a fixed order (run-to-run
 // deterministic).  The per-baseline kernels run one wavefront per tile, one lane per baseline.
 #include "calib_internal.h"
+#include "lm_device.h"
 #include "wave_reduce.h"
 
 namespace calib {
@@ -29,24 +30,8 @@ namespace calib {
 namespace {
 
 
-__device__ inline void jjh(const double *__restrict__ a, const double *__restrict__ b, double *m) {
-  // m = a b^H for 2x2 complex matrices stored as 8 doubles (row-major, re/im interleaved)
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      double re = 0.0, im = 0.0;
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const double ar = a[(i * 2 + t) * 2], ai = a[(i * 2 + t) * 2 + 1];
-        const double br = b[(j * 2 + t) * 2], bi = b[(j * 2 + t) * 2 + 1];
-        re += ar * br + ai * bi;
-        im += ai * br - ar * bi;
-      }
-      m[(i * 2 + j) * 2] = re;
-      m[(i * 2 + j) * 2 + 1] = im;
-    }
-}
+using lmd::jjh;
+using lmd::sub_scaled;
 
 template <typename T>
 __device__ inline void load8(const T *__restrict__ p, T *v);
@@ -152,15 +137,7 @@ __device__ inline void stream_tile(const Problem &pb, const Layout &L, const Buf
   }
 }
 
-// Data cost and D_b at the LM trial point from the start point's statistics (one wavefront per
-// tile, one lane per baseline).  The coherency is a scalar per sample and J_p J_q^H is the same
-// for every sample of a baseline, so with the residual R at the start point J0 and
-// dM = Jt_p Jt_q^H - J0_p J0_q^H (4 complex entries e),
-//     sum_s ||R_s - c_s dM||^2 = sum_s ||R_s||^2 - 2 Re sum_e conj(dM_e) D0_e + S_b sum_e |dM_e|^2,
-//     D_b(trial) = sum_s conj(c_s) (R_s - c_s dM) = D0 - S_b dM,
-// with D0 = sum_s conj(c_s) R_s and S_b = sum_s |c_s|^2.  The first term, summed over the
-// subband, is the data cost at the start point (LmState::E0), added by the subband's first tile;
-// the tile partials sum to the data cost at the trial point as the streaming pass's do.
+// Data cost and D_b at the LM trial point (lmd::trial_tile), one wavefront per tile.
 constexpr int kStatTiles = 4;   // tiles per workgroup of the per-baseline kernels, one per wavefront
 __global__ __launch_bounds__(64 * kStatTiles) void k_trial_stats(Problem pb, Layout L, Buffers B, int k) {
   const int tile = kStatTiles * blockIdx.x + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -168,30 +145,7 @@ __global__ __launch_bounds__(64 * kStatTiles) void k_trial_stats(Problem pb, Lay
   const int f = L.tile_f[tile];
   if (!lm_live(B, L.ndir, f, k) || !B.lm[f].chol_ok) return;   // uniform
   k = lm_dir(B, f, k);
-  const int nb = L.nb[f], bi = L.tile_b0[tile] + lane;
-  double part = 0.0;
-  if (lane < pb.bpt && bi < nb) {
-    const int64_t gb = (int64_t)L.bl_off[f] + bi;
-    const int p = L.bl_p[gb], q = L.bl_q[gb];
-    const double *Jt = B.Jtrial + (int64_t)f * pb.N * 8, *J0 = B.Jstart + (int64_t)f * pb.N * 8;
-    double m1[8], m0[8];
-    jjh(Jt + 8 * p, Jt + 8 * q, m1);
-    jjh(J0 + 8 * p, J0 + 8 * q, m0);
-    const double S = B.Sb[L.sb_off[f] + (int64_t)k * nb + bi];
-    const double *D0 = B.Dstart + 8 * gb;
-    double *Dt = d_trial(B, f) + 8 * gb;
-    double cross = 0.0, norm = 0.0;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const double dm = m1[e] - m0[e], d0 = D0[e];
-      cross = fma(dm, d0, cross);   // Re conj(dM_e) D0_e over the real and imaginary parts
-      norm = fma(dm, dm, norm);
-      Dt[e] = fma(-S, dm, d0);
-    }
-    part = fma(S, norm, -2.0 * cross);
-  }
-  part = wave_sum(part);
-  if (lane == 0) B.cost_part[tile] = part + (tile == L.tile_off[f] ? B.lm[f].E0 : 0.0);
+  lmd::trial_tile(pb, L, B, f, k, tile, lane);
 }
 
 // Per-baseline coherency statistics, once per context (grid: tile x direction l, one lane per
@@ -246,15 +200,6 @@ __global__ __launch_bounds__(64 * kStatTiles) void k_coh_stats(Problem pb, Layou
     }
 }
 
-// d -= x m for the complex scalar x (re, im) and the 2x2 complex matrix m (8 reals)
-__device__ inline void sub_scaled(double *d, double xr, double xi, const double *m) {
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    d[2 * e] -= xr * m[2 * e] - xi * m[2 * e + 1];
-    d[2 * e + 1] -= xr * m[2 * e + 1] + xi * m[2 * e];
-  }
-}
-
 // Every direction's D_l at the current point from the coherency statistics (grid: tile x l, one
 // lane per baseline); direction 0's also becomes the accepted and start point of the next LM run.
 __global__ __launch_bounds__(64 * kStatTiles) void k_dall(Problem pb, Layout L, Buffers B) {
@@ -291,88 +236,18 @@ __global__ __launch_bounds__(64 * kStatTiles) void k_dall(Problem pb, Layout L, 
   }
 }
 
-// End of direction k's LM run (the SAGE commit) without a pass over the samples (one wavefront per
-// tile, one lane per baseline): with dM = J_kp J_kq^H - J0_p J0_q^H (J0 the run's start point), the
-// residual R - c_k dM has D_l - X_lk dM for every direction l, and energy
-// E - 2 Re sum_e conj(dM_e) D_k,e + X_kk ||dM||^2 (the tile's energy and cost partial).  Each lane
-// forms dM once and walks the directions, the next direction's D_l and X_lk requested before the
-// current one's are stored.  The next direction's D becomes the accepted and start point of its
-// LM run.  Unless all is set only the directions after k are updated: within one SAGE sweep no
-// other is read again before the next local step's refresh rebuilds them all.
+// End of direction k's LM run (the SAGE commit, lmd::commit_tile), one wavefront per tile.
 __global__ __launch_bounds__(64 * kStatTiles) void k_commit_stats(Problem pb, Layout L, Buffers B, int k,
                                                                    int all) {
   const int tile = kStatTiles * blockIdx.x + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (tile >= pb.ntiles) return;   // uniform per wavefront
   const int f = L.tile_f[tile];
-  const int Kf = L.ndir[f], nb = L.nb[f];
   if (k < 0) {   // the subband's own direction, if its run has just ended
     if (B.lm[f].phase != kPhaseAdvance || B.lm[f].cur < 0) return;
     k = B.lm[f].cur;
   }
-  if (k >= Kf) return;   // uniform per wavefront
-  const int K = pb.K, N = pb.N, next = k + 1 < Kf ? k + 1 : 0;
-  const int bi = L.tile_b0[tile] + lane;
-  const bool live = lane < pb.bpt && bi < nb;
-  double part = 0.0;
-  if (live) {
-    const int64_t gb = (int64_t)L.bl_off[f] + bi;
-    const int p = L.bl_p[gb], q = L.bl_q[gb];
-    const int64_t nbt = pb.nbt;
-    const int l0 = all ? 0 : k;
-    // D_l and X_lk of direction l, requested ahead of their use
-    double dn[8], xn[2];
-    auto request = [&](int l) {
-      const double *X = B.Xcoh + (((int64_t)l * K + k) * nbt + gb) * 2;
-      const double *D = B.Dall + ((int64_t)l * nbt + gb) * 8;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) dn[e] = D[e];
-      xn[0] = X[0];
-      xn[1] = X[1];
-    };
-    request(l0);
-    const double *J1 = B.J + ((int64_t)f * K + k) * N * 8, *J0 = B.Jstart + (int64_t)f * N * 8;
-    double m1[8], m0[8], dm[8];
-    jjh(J1 + 8 * p, J1 + 8 * q, m1);
-    jjh(J0 + 8 * p, J0 + 8 * q, m0);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) dm[e] = m1[e] - m0[e];
-    for (int l = l0; l < Kf; ++l) {
-      double d[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) d[e] = dn[e];
-      const double x0 = xn[0], x1 = xn[1];
-      if (l + 1 < Kf) request(l + 1);
-      if (l == k) {
-        double cross = 0.0, norm = 0.0;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          cross = fma(dm[e], d[e], cross);
-          norm = fma(dm[e], dm[e], norm);
-        }
-        part = fma(x0, norm, -2.0 * cross);
-      }
-      if (all || l > k) {
-        sub_scaled(d, x0, x1, dm);
-        double *D = B.Dall + ((int64_t)l * nbt + gb) * 8;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) D[e] = d[e];
-        if (l == next) {
-          double *Da = d_accepted(B, f) + 8 * gb;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            Da[e] = d[e];
-            B.Dstart[8 * gb + e] = d[e];
-          }
-        }
-      }
-    }
-  }
-  part = wave_sum(part);
-  if (lane == 0) {
-    const double e = B.Epart[tile] + part;
-    B.Epart[tile] = e;
-    B.cost_part[tile] = e;
-  }
+  if (k >= L.ndir[f]) return;   // uniform per wavefront
+  lmd::commit_tile(pb, L, B, f, k, all, tile, lane);
 }
 
 // One workgroup per tile (grid = ntiles), or a persistent grid that strides over the tiles.

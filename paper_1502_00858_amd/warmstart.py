@@ -45,10 +45,10 @@ class Interval:
 
 def solve_episode(cfg: synth.SynthConfig, episode: int, n_intervals: int, precision: int,
                   admm_iters: int, lm_iters: Optional[int] = None, rel_cost_tol: float = 0.0,
-                  count: Optional[int] = None, lm_tol: float = 0.0) -> List[Interval]:
+                  count: Optional[int] = None, lm_tol: float = 0.0, **ctx_kw) -> List[Interval]:
     """Solve the first ``count`` (default all) of the n_intervals intervals of one episode in
     order, each from the previous one's state, and collect features and targets of every interval
-    after the first."""
+    after the first.  ctx_kw: further calib.Calib settings (solver, cg_tol, tile shapes)."""
     import torch
     out: List[Interval] = []
     for j in range(n_intervals if count is None else count):
@@ -56,7 +56,8 @@ def solve_episode(cfg: synth.SynthConfig, episode: int, n_intervals: int, precis
         vis, coh, flags = calib.device_inputs(data, precision)
         prev = out[-1] if out else None
         ctx = calib.Calib(data, vis, coh, flags, precision=precision, lm_iters=lm_iters,
-                          options=calib.OPT_GPA_FIRST_ITER if prev is None else 0, lm_tol=lm_tol)
+                          options=calib.OPT_GPA_FIRST_ITER if prev is None else 0, lm_tol=lm_tol,
+                          **ctx_kw)
         feats = tgt = None
         if prev is not None:
             ctx.set_state(prev.J, prev.Y, prev.Z, prev.BZ)

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from conftest import rand_jones, tiny_cfg
+from parity_tol import FP64_VIS_TOL
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -214,11 +215,12 @@ def test_run_to_run_bitwise(cal, synth_mod):
     np.testing.assert_array_equal(a.get(cal.FIELD_J).cpu().numpy(), b.get(cal.FIELD_J).cpu().numpy())
 
 
-@pytest.mark.parametrize("solver", [1, 2])
+@pytest.mark.parametrize("solver", [1, 2, 3])
 def test_normal_equation_solve_fp64(cal, oracle_mod, synth_mod, solver):
     """One LM iteration from a random state: the GPU step solves (H_GN + (rho+lambda) I) delta = -G
     with the oracle's Gauss-Newton matrix, for both Cholesky solvers (one workgroup per matrix;
-    64-column panels over many workgroups) and station counts that give padded factors and
+    64-column panels over many workgroups) and the matrix-free conjugate gradients (16 stations
+    per wavefront up to N = 64, 32 above), and station counts that give padded factors and
     partial last panels (8N = 48, 72, 136, 264 columns), 8N = 528 (past the 512 columns of the
     panel solver's register-ring back substitution: its 1024-thread back substitution) and the
     largest array, N = 128 (8N = 1024: two columns per thread in the one-workgroup solver, one in
@@ -228,7 +230,9 @@ def test_normal_equation_solve_fp64(cal, oracle_mod, synth_mod, solver):
         cfg = tiny_cfg(synth_mod, N=N, P=2, Q=1, K=1, T=3, n_chan=2, rho=3.0, lm_iters=1)
         d = synth_mod.generate(cfg)
         J = rand_jones(np.random.default_rng(14), cfg.P, 1, N)
-        c = _ctx(cal, d, 0, jones0=J, lm_iters=1, options=0, solver=solver)
+        # solver 3 (conjugate gradients) at a tolerance below rounding: it runs to 8N iterations
+        # or an exact zero residual, the dense solve's accuracy
+        c = _ctx(cal, d, 0, jones0=J, lm_iters=1, options=0, solver=solver, cg_tol=1e-15)
         c.local_step(1)
         step = c.get(cal.FIELD_LM_STEP).cpu().numpy()
         pb = oracle_mod.Problem(d, lm_iters=1)
@@ -296,7 +300,7 @@ def test_lm_stopping_rule_fp64(cal, oracle_mod, synth_mod):
     np.testing.assert_allclose(tr[:, 1], ref[:, 1], rtol=1e-10)
 
 
-@pytest.mark.parametrize("solver", [1, 2])
+@pytest.mark.parametrize("solver", [1, 2, 3])
 def test_stopping_rule_skip_is_exact(cal, synth_mod, solver):
     """Under the LM stopping rule, solve() launches one LM iteration per step for every subband
     still working, each on its own direction, and ends the local step once every subband has
@@ -360,3 +364,39 @@ def test_solvers_agree_on_a_local_step(cal, synth_mod):
         tr.append(c.get(cal.FIELD_LM_TRACE).cpu().numpy())
     np.testing.assert_array_equal(tr[0][..., 2], tr[1][..., 2])
     np.testing.assert_allclose(tr[0][..., 0], tr[1][..., 0], rtol=1e-11)
+
+
+def test_pcg_local_step_matches_oracle_pcg(cal, oracle_mod, synth_mod):
+    """The matrix-free solver (conjugate gradients at cg_tol 1e-10) against the oracle's reading of
+    the same iteration: per-LM-iteration objective within 1e-10, accept decisions equal wherever
+    the step moves the objective by more than rounding, visibilities after the local step within
+    1e-10; then a short C-ADMM trajectory with the stopping rule, station counts on both sides of
+    the 64-station switch of the work layout."""
+    for N, K in ((7, 3), (70, 2)):
+        print(f"pcg local step N={N} K={K}", flush=True)
+        cfg = tiny_cfg(synth_mod, N=N, P=3, K=K, T=3, n_chan=2, lm_iters=6, flag_frac_max=0.2)
+        d = synth_mod.generate(cfg)
+        J0 = synth_mod.identity_jones(cfg.P, cfg.K, cfg.N)
+        z = np.zeros_like(J0)
+        c = _ctx(cal, d, 0, lm_iters=6, solver=3, cg_tol=1e-10)
+        c.local_step(0)
+        Jg = c.get(cal.FIELD_J).cpu().numpy()
+        trg = c.get(cal.FIELD_LM_TRACE).cpu().numpy()
+        pb = oracle_mod.Problem(d, lm_iters=6, solver=oracle_mod.SOLVE_PCG, cg_tol=1e-10)
+        Jo, tro = pb.local_step(J0, z, z, trace=True)
+        tro = tro[:, 0]
+        prev = np.concatenate([np.full(tro.shape[:-2] + (1,), np.inf), tro[..., :-1, 0]], axis=-1)
+        decisive = np.abs(tro[..., 0] - prev) > 1e-12 * np.abs(tro[..., 0])
+        np.testing.assert_array_equal(trg[..., 2][decisive], tro[..., 2][decisive])
+        np.testing.assert_allclose(trg[..., 0], tro[..., 0], rtol=1e-10)
+        err = _rel(pb.predict(Jg), pb.predict(Jo))
+        same = np.array_equal(trg[..., 2], tro[..., 2])
+        print(f"  visibilities after the local step: {err:.2e} (accept sequences equal: {same})",
+              flush=True)
+        # a step taken or refused at a rounding tie near the optimum (where the objective is
+        # quadratic) has size ~sqrt(eps) relative; without such a tie the bound is FP64_VIS_TOL
+        assert err < (FP64_VIS_TOL if same else 1e-7)
+        tr = _ctx(cal, d, 0, lm_iters=6, solver=3, cg_tol=1e-10, lm_tol=1e-7).solve(4)
+        ref = oracle_mod.Problem(d, lm_iters=6, solver=oracle_mod.SOLVE_PCG, cg_tol=1e-10,
+                                 lm_tol=1e-7).admm_solve(J0, 4)["trace"]
+        np.testing.assert_allclose(tr[:, :2], ref[:, :2], rtol=1e-10)
