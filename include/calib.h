@@ -60,8 +60,13 @@ typedef enum {
   CALIB_E_DEVICE = 3,   /* a HIP call failed                                                  */
   CALIB_E_RANK = 4,     /* fewer than Q distinct subband frequencies carry a direction (the
                            rank condition P >= F of the Z update, Section 3)                  */
-  CALIB_E_NUMERIC = 5,  /* non-finite values in the inputs                                     */
-  CALIB_E_STATE = 6     /* entry point called out of order                                    */
+  CALIB_E_NUMERIC = 5,  /* non-finite values in the inputs (calib_init); or, from admm_solve, a
+                           subband whose LM objective is not finite at the start of a run or
+                           whose damped normal equations cannot be solved even at a damping
+                           1e16 times the run's initial one (that subband's runs then stop;
+                           CALIB_FIELD_STATUS names it)                                       */
+  CALIB_E_STATE = 6     /* entry point called out of order, or the device's local-step
+                           schedule did not finish within its LM iterations                   */
 } calib_status;
 
 typedef enum { CALIB_FP64 = 0, CALIB_FP32_MIXED = 1 } calib_precision;
@@ -124,11 +129,16 @@ typedef struct {
 #define CALIB_FIELD_LM_STEP 8    /* double [P][2][8N]: gradient G and solution delta of
                                     (H_GN + (rho + lambda) I) delta = -G of the last LM
                                     iteration (real parameters p*8 + (i*2+j)*2 + re/im)       */
+#define CALIB_FIELD_STATUS 10    /* int32 [P]: CALIB_OK, or CALIB_E_NUMERIC for a subband whose
+                                    objective became non-finite or whose normal equations could
+                                    not be solved (reset by calib_set_jones / calib_set_state)  */
 
 /* Validate the configuration, pack the inputs into the library's baseline-major layout (dropping
  * flagged baselines, converting nothing: the element type must match cfg->precision), compute
- * the per-baseline coherency energies S_b = sum |c|^2, set J to jones0 (or identity blocks,
- * Section 3 initialisation) and Z = Y = 0.
+ * the per-baseline coherency statistics S_b = sum |c|^2, U_l = sum conj(c_l) V and
+ * X_lm = sum conj(c_l) c_m (everything the local steps need from the samples besides the
+ * residual's energy), set J to jones0 (or identity blocks, Section 3 initialisation) and
+ * Z = Y = 0.
  *   vis    device, see layout above;       coh    device, see layout above
  *   flags  device [P*B] or NULL;           jones0 device double complex [P][K][N][2][2] or NULL
  *   hip_stream  hipStream_t or NULL;       out    receives the new context
@@ -138,9 +148,10 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
                         const uint8_t *flags, const void *jones0, void *hip_stream,
                         calib_ctx **out);
 
-/* Step D1/S1 for all subbands at ADMM iteration admm_iter (minimisation M1): refresh the full
- * residual, then for each SAGE sweep and direction run lm_iters Levenberg-Marquardt iterations
- * on L_fk with Y and B_f Z from the previous consensus update.  At admm_iter 0 with
+/* Step D1/S1 for all subbands at ADMM iteration admm_iter (minimisation M1): the residual's
+ * energy (one pass over the samples) and every direction's per-baseline statistics of the
+ * residual, then for each SAGE sweep and direction lm_iters Levenberg-Marquardt iterations on
+ * L_fk with Y and B_f Z from the previous consensus update (fewer under the stopping rule).  At admm_iter 0 with
  * CALIB_OPT_UNREG_FIRST the consensus terms are left out. */
 calib_status admm_local_step(calib_ctx *ctx, int32_t admm_iter);
 
@@ -194,7 +205,9 @@ calib_status calib_consensus_noalloc(int32_t n_stations, int32_t n_subbands, int
  * rel_cost_tol > 0 it stops after an iteration whose data cost changed by less than
  * rel_cost_tol relative to the previous one (this check synchronises the stream each
  * iteration).  trace_out (host, may be NULL) receives [iters][4] as CALIB_FIELD_TRACE;
- * iters_done (host, may be NULL) the number of iterations run.  Synchronises the stream. */
+ * iters_done (host, may be NULL) the number of iterations run.  Synchronises the stream.
+ * Returns CALIB_E_NUMERIC (after the iterations) when some subband's state became non-finite or
+ * its normal equations could not be solved; CALIB_FIELD_STATUS names the subbands. */
 calib_status admm_solve(calib_ctx *ctx, int32_t max_iters, double rel_cost_tol, double *trace_out,
                         int32_t *iters_done);
 
@@ -216,16 +229,18 @@ calib_status calib_set_state(calib_ctx *ctx, const void *jones, const void *y, c
                              const void *bz);
 
 /* Kernel classes reported by CALIB_FIELD_KERNEL_TIMES. */
-#define CALIB_KERNEL_REFRESH 0      /* full residual + statistics of the first direction        */
+#define CALIB_KERNEL_REFRESH 0      /* residual energy over the samples + every direction's
+                                       per-baseline residual statistics                        */
 #define CALIB_KERNEL_LM_BEGIN 1     /* initial objective and damping of a direction            */
 #define CALIB_KERNEL_ASSEMBLE 2     /* gradient and dense Gauss-Newton normal equations (the
                                        Cholesky solvers only)                                   */
 #define CALIB_KERNEL_CHOL_SOLVE 3   /* batched FP64 solve of the damped normal equations
                                        (Cholesky factorisation, or the gradient and conjugate
                                        gradients of solver 3)                                   */
-#define CALIB_KERNEL_TRIAL 4        /* streaming pass at the LM trial point                     */
+#define CALIB_KERNEL_TRIAL 4        /* cost and per-baseline statistics at the LM trial point    */
 #define CALIB_KERNEL_LM_UPDATE 5    /* gain ratio, accept/reject, damping update                */
-#define CALIB_KERNEL_COMMIT 6       /* SAGE residual commit + statistics of the next direction  */
+#define CALIB_KERNEL_COMMIT 6       /* SAGE commit: every later direction's statistics and the
+                                       residual energy updated for the direction just solved    */
 #define CALIB_KERNEL_CONSENSUS 7    /* Lagrangian trace, alignment, Z, B_f Z, Y, residuals      */
 #define CALIB_KERNEL_LOCAL_STEP 8   /* solver 3: every subband's whole local step (LM runs with
                                        the matrix-free solve, stopping rule, SAGE commits) in one

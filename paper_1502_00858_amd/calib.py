@@ -18,7 +18,7 @@ CALIB_FP32_MIXED = 1
 OPT_GPA_FIRST_ITER = 1
 OPT_UNREG_FIRST = 2
 (FIELD_J, FIELD_Z, FIELD_BZ, FIELD_Y, FIELD_MODEL_VIS, FIELD_COST, FIELD_TRACE, FIELD_LM_TRACE,
- FIELD_LM_STEP, FIELD_KERNEL_TIMES) = range(10)
+ FIELD_LM_STEP, FIELD_KERNEL_TIMES, FIELD_STATUS) = range(11)
 KERNELS = ["refresh", "lm_begin", "assemble", "chol_solve", "trial", "lm_update", "commit",
            "consensus", "local_step"]
 STATUS = {0: "CALIB_OK", 1: "CALIB_E_INVAL", 2: "CALIB_E_NOMEM", 3: "CALIB_E_DEVICE",
@@ -184,6 +184,8 @@ class Calib:
             out = torch.empty(self.P, dtype=torch.float64, device="cuda")
         elif field == FIELD_LM_STEP:
             out = torch.empty((self.P, 2, 8 * self.N), dtype=torch.float64, device="cuda")
+        elif field == FIELD_STATUS:
+            out = torch.empty(self.P, dtype=torch.int32, device="cuda")
         elif field == FIELD_LM_TRACE:
             out = torch.empty((self.P, self.K, self.lm_iters, 3), dtype=torch.float64, device="cuda")
         else:

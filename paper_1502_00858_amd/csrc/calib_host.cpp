@@ -274,7 +274,7 @@ calib_status run_local_step_stopping(calib_ctx *c, int admm_iter, hipStream_t s)
     if (st == CALIB_OK) st = wait_stop_flag(c, s, &stopped);
     if (st != CALIB_OK) return st;
   }
-  if (!stopped) return fail(c, CALIB_E_DEVICE, "the local step did not finish within its LM iterations");
+  if (!stopped) return fail(c, CALIB_E_STATE, "the local step did not finish within its LM iterations");
   HIPCHK(c, timed(c, CALIB_KERNEL_COMMIT, [&] { return launch_commit<T>(pb, L, B, -1, all, s); }));
   return CALIB_OK;
 }
@@ -541,6 +541,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   DALLOC(B.Xcoh, (size_t)nb_total * K * K * 2 * 8);
   DALLOC(B.Dall, (size_t)nb_total * K * 8 * 8);
   DALLOC(B.lm, (size_t)P * sizeof(LmState));
+  DALLOC(B.status, (size_t)P * sizeof(int));
   double *basis, *fitw;
   DALLOC(basis, (size_t)P * Q * 8);
   DALLOC(fitw, (size_t)K * Q * P * 8);
@@ -585,6 +586,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
           "coherency statistics") &&
       (!B.H || dev(launch_zero(B.H, (int64_t)P * pb.npad * pb.nf, s), "zero H")) &&
       dev(hipMemsetAsync(B.lm, 0, (size_t)P * sizeof(LmState), s), "zero LM state") &&
+      dev(hipMemsetAsync(B.status, 0, (size_t)P * sizeof(int), s), "zero status") &&
       (!B.chol_fail || dev(hipMemsetAsync(B.chol_fail, 0, (size_t)P * sizeof(int), s), "zero flags")) &&
       dev(launch_zero(B.Y, (int64_t)nj, s), "zero Y") && dev(launch_zero(B.BZ, (int64_t)nj, s), "zero BZ") &&
       dev(launch_zero(B.Z, (int64_t)nz, s), "zero Z") &&
@@ -669,6 +671,16 @@ calib_status admm_solve(calib_ctx *ctx, int32_t max_iters, double rel_cost_tol, 
   if (trace_out && n > 0)
     HIPCHK(ctx, hipMemcpy(trace_out, ctx->B.trace, sizeof(double) * 4 * n, hipMemcpyDeviceToHost));
   if (iters_done) *iters_done = n;
+  std::vector<int> status(ctx->P);
+  HIPCHK(ctx, hipMemcpy(status.data(), ctx->B.status, sizeof(int) * ctx->P, hipMemcpyDeviceToHost));
+  std::string bad;
+  int nbad = 0;
+  for (int f = 0; f < ctx->P; ++f)
+    if (status[f] != CALIB_OK && ++nbad <= 8) bad += (bad.empty() ? "" : ", ") + std::to_string(f);
+  if (nbad)
+    return fail(ctx, CALIB_E_NUMERIC, std::to_string(nbad) + " subband(s) with a non-finite objective or "
+                                      "normal equations that could not be solved (" + bad +
+                                      (nbad > 8 ? ", ...)" : ")") + "; see CALIB_FIELD_STATUS");
   return CALIB_OK;
 }
 
@@ -718,6 +730,9 @@ calib_status calib_get(calib_ctx *ctx, int32_t field, void *dst) {
       for (int i = 0; i < CALIB_NUM_KERNELS; ++i) { o[2 * i] = ctx->kcount[i]; o[2 * i + 1] = ctx->kms[i]; }
       return CALIB_OK;
     }
+    case CALIB_FIELD_STATUS:
+      HIPCHK(ctx, hipMemcpyAsync(dst, ctx->B.status, sizeof(int) * ctx->P, hipMemcpyDeviceToDevice, s));
+      return CALIB_OK;
     case CALIB_FIELD_LM_STEP: {
       const size_t w = (size_t)8 * ctx->N * sizeof(double), sp = (size_t)ctx->pb.nf * sizeof(double);
       char *d = static_cast<char *>(dst);
@@ -798,6 +813,7 @@ calib_status calib_set_state(calib_ctx *ctx, const void *jones, const void *y, c
   const int64_t nj = (int64_t)ctx->P * ctx->K * ctx->N * 8;
   const int64_t nz = (int64_t)ctx->K * ctx->Q * ctx->N * 8;
   HIPCHK(ctx, hipMemcpyAsync(ctx->B.J, jones, nj * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(ctx, launch_zero_int(ctx->B.status, ctx->P, s));
   if (y) HIPCHK(ctx, hipMemcpyAsync(ctx->B.Y, y, nj * 8, hipMemcpyDeviceToDevice, s));
   else HIPCHK(ctx, launch_zero(ctx->B.Y, nj, s));
   if (z) HIPCHK(ctx, hipMemcpyAsync(ctx->B.Z, z, nz * 8, hipMemcpyDeviceToDevice, s));
@@ -814,6 +830,7 @@ calib_status calib_set_jones(calib_ctx *ctx, const void *jones) {
   hipStream_t s = ctx->stream;
   const int64_t nj = (int64_t)ctx->P * ctx->K * ctx->N * 8;
   HIPCHK(ctx, hipMemcpyAsync(ctx->B.J, jones, nj * 8, hipMemcpyDeviceToDevice, s));
+  HIPCHK(ctx, launch_zero_int(ctx->B.status, ctx->P, s));
   HIPCHK(ctx, launch_zero(ctx->B.Y, nj, s));
   HIPCHK(ctx, launch_zero(ctx->B.BZ, nj, s));
   HIPCHK(ctx, launch_zero(ctx->B.Z, (int64_t)ctx->K * ctx->Q * ctx->N * 8, s));

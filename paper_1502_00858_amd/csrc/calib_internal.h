@@ -9,6 +9,8 @@ namespace calib {
 constexpr int kBlock = 256;        // threads per workgroup of every kernel (4 wave64)
 constexpr int kMaxDirs = 16;       // directions per subband
 constexpr double kLmTau = 1e-3;    // Nielsen's initial damping factor
+constexpr double kLmFailFactor = 1e16;   // a solve still failing at lambda > this x lambda_0 is a
+                                         // numeric failure of the subband
 constexpr int kCholMaxTilesPerWave = 9;   // 16-row tiles per wavefront in one Cholesky panel
 constexpr int kMaxStations = 128;         // the solve keeps one column of 8N per thread
 
@@ -41,6 +43,7 @@ struct LmState {
   double nu;       // damping growth factor
   double ell;      // predicted decrease of the last step
   double Fnew;     // objective at the last trial point
+  double lambda0;  // damping at the start of the run
   int32_t chol_ok; // last factorisation succeeded
   int32_t accepted;// accepted steps in this LM run
   int32_t done;    // the LM run of the active direction has met its stopping rule
@@ -103,6 +106,9 @@ struct Buffers {
   int *iter;                            // ADMM iteration whose trace row is being written
   int *chol_fail;                       // [P] blocked solver: a pivot failed in this solve
   double *chol_ld;                      // [P][panels][64*64] blocked solver: diagonal blocks' L
+  int *status;                          // [P] CALIB_OK or CALIB_E_NUMERIC per subband (a run
+                                        // whose objective is not finite, or whose normal
+                                        // equations fail past kLmFailFactor lambda_0)
   const int *rank_fail;                 // set by the basis setup of a context-free consensus
                                         // update: the Z fit, Y update and residuals do nothing
                                         // (null in a context, whose rank is checked at init)
@@ -187,5 +193,6 @@ hipError_t launch_fill_identity(double *J, int64_t nblocks, hipStream_t s);
 // message returned by calib_last_error(NULL) for entry points that take no context
 void set_context_free_error(const char *msg);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
+hipError_t launch_zero_int(int *p, int64_t n, hipStream_t s);
 
 }  // namespace calib

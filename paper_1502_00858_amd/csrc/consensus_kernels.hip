@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_penalty_part(Problem pb, Layout L, B
   for (int t = L.tile_off[f] + threadIdx.x; t < L.tile_off[f + 1]; t += kBlock) v[0] += B.cost_part[t];
   const int n8 = 8 * pb.N;
   const int64_t o = (int64_t)f * pb.K * n8;
-  for (int e = threadIdx.x; e < pb.K * n8; e += kBlock) {
+  for (int e = threadIdx.x; e < L.ndir[f] * n8; e += kBlock) {   // the directions f carries
     const int k = e / n8;
     const double d = B.J[o + e] - B.BZ[o + e];
     v[1] += B.Y[o + e] * d + 0.5 * B.rho[k] * d * d;
@@ -322,6 +322,11 @@ __global__ void k_zero(double *p, int64_t n) {
   if (i < n) p[i] = 0.0;
 }
 
+__global__ void k_zero_int(int *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 }  // namespace
 
 hipError_t launch_basis_setup(const Problem &pb, const double *freq, double f0, const int32_t *ndir,
@@ -370,6 +375,12 @@ hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B
 hipError_t launch_fill_identity(double *J, int64_t nblocks, hipStream_t s) {
   if (nblocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_identity, dim3((unsigned)((nblocks + 255) / 256)), dim3(256), 0, s, J, nblocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_int(int *p, int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_int, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
   return hipGetLastError();
 }
 

@@ -158,11 +158,16 @@ __device__ inline void begin_dir(const Problem &pb, const Layout &L, const Buffe
     st->F = F;
     st->E0 = E0;
     st->lambda = kLmTau * m;
+    st->lambda0 = st->lambda;
     st->nu = 2.0;
     st->accepted = 0;
     st->chol_ok = 0;
     st->ell = 0.0;
     st->done = 0;
+    if (!isfinite(F)) {   // a state that is not finite: the run does nothing, the subband is reported
+      st->done = 1;
+      if (B.status) B.status[f] = 5;   // CALIB_E_NUMERIC
+    }
     if (own) {
       st->cur = cur;
       st->sweep = sweep;
@@ -327,6 +332,11 @@ __device__ inline void update_dir(const Problem &pb, const Layout &L, const Buff
     if (!a) {
       st->lambda *= st->nu;
       st->nu *= 2.0;
+      // normal equations that cannot be solved even with overwhelming damping: not finite
+      if (!ok && !(st->lambda <= kLmFailFactor * st->lambda0)) {
+        st->done = 1;
+        if (B.status) B.status[f] = 5;   // CALIB_E_NUMERIC
+      }
     }
     st->Fnew = Fn;
     acc = a;

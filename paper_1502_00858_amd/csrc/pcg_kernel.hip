@@ -602,7 +602,9 @@ __global__ __launch_bounds__(kPcgThreads) void k_local_step(Problem pb, Layout L
       lmd::begin_dir(pb, L, B, f, k, unreg, false, 0, 0);
       for (int e = threadIdx.x; e < n8; e += kBlock) J0s[e] = B.Jstart[(int64_t)f * n8 + e];
       __syncthreads();
-      for (int it = 0; it < lm_iters; ++it) {
+      if (st->done)   // a run that cannot start (non-finite state): its trace rows only
+        for (int it = 0; it < lm_iters; ++it) lmd::update_dir(pb, L, B, f, k, unreg, lm_trace, it, lm_iters, false);
+      for (int it = 0; it < lm_iters && !st->done; ++it) {
         pcg_solve<SPL>(pb, L, B, f, k, unreg, pb.cg_tol, sh, sh.Us);
         __syncthreads();
         if (st->chol_ok) fused_trial(pb, L, B, f, k, sh.Us, J0s, red);

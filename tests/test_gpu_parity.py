@@ -1,22 +1,18 @@
 """GPU library against the FP64 CPU oracle on identical seeded inputs.
 
-Tolerances: FP64 path 1e-10 relative on predicted visibilities and per-iteration cost; the
+Tolerances (tests/parity_tol.py): FP64 path 1e-10 relative on predicted visibilities and
+per-iteration cost; over multi-iteration trajectories the visibility bound is derived per case
+from the oracle's own sensitivity (a flipped LM decision moves the trajectory by one step); the
 FP32-streaming path 1e-5 relative, compared with the oracle run on the FP32-rounded inputs.
 """
 import numpy as np
 import pytest
 
 from conftest import rand_jones, tiny_cfg
-from parity_tol import FP64_VIS_TOL
+from parity_tol import FP64_VIS_TOL, AdmmRun, traj_vis_tol
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-
-# Whole-trajectory tolerance on predicted visibilities: an LM accept decision taken at a gain ratio
-# of rounding size can flip between two FP64 codes; a 1e-15 relative perturbation of the inputs
-# moves the oracle's own visibilities by up to ~1e-8 over a few ADMM iterations.  Single LM steps
-# from identical state are held to 1e-10.
-TRAJ_VIS_TOL = 1e-7
 
 
 @pytest.fixture(scope="module")
@@ -66,7 +62,9 @@ def test_local_step_lm_trace_fp64(cal, oracle_mod, synth_mod):
     # lambda is scaled by a function of the gain ratio (F - F_new)/ell, a quotient of the difference
     # of two nearly equal objectives: its rounding is amplified by F/(F - F_new) (up to ~1e6 here)
     np.testing.assert_allclose(trg[..., 1], tro[:, 0, :, :, 1], rtol=1e-5)
-    assert _rel(pb.predict(Jg), pb.predict(Jo)) < 1e-9
+    err = _rel(pb.predict(Jg), pb.predict(Jo))
+    print(f"visibilities after one local step: {err:.2e}")
+    assert err < FP64_VIS_TOL
 
 
 def test_max_directions_fp64(cal, oracle_mod, synth_mod):
@@ -85,7 +83,9 @@ def test_max_directions_fp64(cal, oracle_mod, synth_mod):
     Jo, tro = pb.local_step(J0, z, z, trace=True)
     np.testing.assert_array_equal(trg[..., 2], tro[:, 0, :, :, 2])
     np.testing.assert_allclose(trg[..., 0], tro[:, 0, :, :, 0], rtol=1e-10)
-    assert _rel(pb.predict(Jg), pb.predict(Jo)) < 1e-9
+    err = _rel(pb.predict(Jg), pb.predict(Jo))
+    print(f"visibilities after one local step: {err:.2e}")
+    assert err < FP64_VIS_TOL
 
 
 def test_two_sage_sweeps_fp64(cal, oracle_mod, synth_mod):
@@ -104,7 +104,9 @@ def test_two_sage_sweeps_fp64(cal, oracle_mod, synth_mod):
     Jo, tro = pb.local_step(J0, z, z, trace=True)
     np.testing.assert_array_equal(trg[..., 2], tro[:, 1, :, :, 2])
     np.testing.assert_allclose(trg[..., 0], tro[:, 1, :, :, 0], rtol=1e-10)
-    assert _rel(pb.predict(Jg), pb.predict(Jo)) < 1e-9
+    err = _rel(pb.predict(Jg), pb.predict(Jo))
+    print(f"visibilities after one local step: {err:.2e}")
+    assert err < FP64_VIS_TOL
     trg = _ctx(cal, d, 0, lm_iters=4, sage_sweeps=2).solve(3)
     tro = pb.admm_solve(J0, 3)["trace"]
     np.testing.assert_allclose(trg[:, 0], tro[:, 0], rtol=1e-10)
@@ -147,7 +149,10 @@ def test_admm_c1_fp64(cal, oracle_mod, synth_mod):
     np.testing.assert_allclose(trg[:, 0], tro[:, 0], rtol=1e-10)
     np.testing.assert_allclose(trg[:, 1], tro[:, 1], rtol=1e-10)
     model_g = c.get(cal.FIELD_MODEL_VIS).cpu().numpy()
-    assert _rel(model_g, pb.predict(out["J"])) < TRAJ_VIS_TOL
+    err = _rel(model_g, pb.predict(out["J"]))
+    tol = traj_vis_tol(oracle_mod, d, AdmmRun(cfg.P, cfg.K, cfg.N, cfg.admm_iters, lm_iters=cfg.lm_iters))
+    print(f"visibilities after {cfg.admm_iters} iterations: {err:.2e} (bound {tol:.2e})")
+    assert err < tol
 
 
 def test_admm_fp32_mixed(cal, oracle_mod, synth_mod):
@@ -171,9 +176,14 @@ def test_ragged_flags_fp64(cal, oracle_mod, synth_mod):
     trg = c.solve(4)
     pb = oracle_mod.Problem(d, lm_iters=5)
     out = pb.admm_solve(synth_mod.identity_jones(cfg.P, cfg.K, cfg.N), 4)
-    np.testing.assert_allclose(trg[:, 0], out["trace"][:, 0], rtol=1e-10)
+    # data cost and augmented Lagrangian (whose penalty covers only the directions a subband
+    # carries)
+    np.testing.assert_allclose(trg[:, :2], out["trace"][:, :2], rtol=1e-10)
     model_g = c.get(cal.FIELD_MODEL_VIS).cpu().numpy()
-    assert _rel(model_g, pb.predict(out["J"])) < TRAJ_VIS_TOL
+    err = _rel(model_g, pb.predict(out["J"]))
+    tol = traj_vis_tol(oracle_mod, d, AdmmRun(cfg.P, cfg.K, cfg.N, 4, lm_iters=5))
+    print(f"visibilities after 4 iterations: {err:.2e} (bound {tol:.2e})")
+    assert err < tol
 
 
 def test_rank_and_numeric_errors(cal, synth_mod):
