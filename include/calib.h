@@ -129,6 +129,10 @@ typedef struct {
 #define CALIB_FIELD_LM_STEP 8    /* double [P][2][8N]: gradient G and solution delta of
                                     (H_GN + (rho + lambda) I) delta = -G of the last LM
                                     iteration (real parameters p*8 + (i*2+j)*2 + re/im)       */
+#define CALIB_FIELD_WORK 11      /* double [P][2]: conjugate-gradient iterations and LM solves
+                                    of solver 3 per subband since calib_set_kernel_timing last
+                                    enabled timing (measurement aid: the algorithmic work of the
+                                    local step's launches)                                     */
 #define CALIB_FIELD_STATUS 10    /* int32 [P]: CALIB_OK, or CALIB_E_NUMERIC for a subband whose
                                     objective became non-finite or whose normal equations could
                                     not be solved (reset by calib_set_jones / calib_set_state)  */
@@ -227,6 +231,16 @@ calib_status calib_set_jones(calib_ctx *ctx, const void *jones);
  * this state; a context initialised without CALIB_OPT_GPA_FIRST_ITER keeps its gauge. */
 calib_status calib_set_state(calib_ctx *ctx, const void *jones, const void *y, const void *z,
                              const void *bz);
+
+/* A new solution interval of the same observation (Section 3 calibrates interval after interval):
+ * visibilities and coherencies of the same array, subband frequencies, channel and direction
+ * counts and flags as at calib_init (device, same layouts and element type).  Repacks them into
+ * the context's buffers and recomputes the per-baseline coherency statistics (S_b, U_l, X_lm) in
+ * one pass over the inputs; J, Y, Z and B_f Z are kept - the previous interval's solution, the
+ * paper's warm start (Section 3, initialisation) - until calib_set_state or calib_set_jones
+ * replaces them.  Allocates nothing and does not synchronise.  Non-finite inputs mark their
+ * subbands CALIB_E_NUMERIC in CALIB_FIELD_STATUS, and the next admm_solve returns it. */
+calib_status calib_set_data(calib_ctx *ctx, const void *vis, const void *coh);
 
 /* Kernel classes reported by CALIB_FIELD_KERNEL_TIMES. */
 #define CALIB_KERNEL_REFRESH 0      /* residual energy over the samples + every direction's

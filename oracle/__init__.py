@@ -60,7 +60,7 @@ def lib():
         _lib.or_gpa.argtypes = [vp, vp, ip]
         _lib.or_consensus.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         _lib.or_consensus.restype = ip
-        _lib.or_admm_solve.argtypes = [vp, vp, ip, vp, vp, vp, vp, vp]
+        _lib.or_admm_solve.argtypes = [vp, vp, ip, vp, vp, vp, vp, vp, ip]
         _lib.or_admm_solve.restype = ip
         _lib.or_pcg.argtypes = [ip, vp, vp, C.c_double, vp, vp]
         _lib.or_pcg.restype = ip
@@ -71,6 +71,8 @@ def lib():
         _lib.or_lstsq.argtypes = [ip, ip, vp, ip, vp, vp]
         _lib.or_lstsq.restype = ip
         _lib.or_num_threads.restype = ip
+        _lib.or_set_num_threads.argtypes = [ip]
+        _lib.or_set_num_threads.restype = None
         del dp
     return _lib
 
@@ -170,13 +172,17 @@ class Problem:
             raise ValueError("rank condition violated: fewer subbands than basis terms")
         return Y, Z, BZ, float(pr[0]), float(du[0])
 
-    def admm_solve(self, J0, iters):
+    def admm_solve(self, J0, iters, Y0=None, Z0=None, BZ0=None):
+        """C-ADMM from J0 with Y = Z = B_f Z = 0, or (Y0, Z0, BZ0 given) continuing from that
+        state, e.g. the previous solution interval's."""
         J = np.array(J0, np.complex128, copy=True, order="C")
-        Y = np.zeros(self.jshape(), np.complex128)
-        BZ = np.zeros(self.jshape(), np.complex128)
-        Z = np.zeros(self.zshape(), np.complex128)
+        carry = Y0 is not None
+        Y = np.array(Y0, np.complex128, copy=True, order="C") if carry else np.zeros(self.jshape(), np.complex128)
+        BZ = np.array(BZ0, np.complex128, copy=True, order="C") if carry else np.zeros(self.jshape(), np.complex128)
+        Z = np.array(Z0, np.complex128, copy=True, order="C") if carry else np.zeros(self.zshape(), np.complex128)
         tr = np.zeros((iters, 4))
-        st = lib().or_admm_solve(*self._c(), iters, _ptr(J), _ptr(Y), _ptr(Z), _ptr(BZ), _ptr(tr))
+        st = lib().or_admm_solve(*self._c(), iters, _ptr(J), _ptr(Y), _ptr(Z), _ptr(BZ), _ptr(tr),
+                                 int(carry))
         if st != 0:
             raise ValueError("rank condition violated: fewer subbands than basis terms")
         return dict(J=J, Y=Y, Z=Z, BZ=BZ, trace=tr)
@@ -217,3 +223,7 @@ def lstsq(A, X):
 
 def num_threads() -> int:
     return int(lib().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    lib().or_set_num_threads(int(n))

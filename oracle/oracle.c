@@ -36,6 +36,14 @@ int or_num_threads(void) {
 #endif
 }
 
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 static int n_baselines(int N) { return N * (N - 1) / 2; }
 
 static void baseline_tables(int N, int *bp, int *bq) {
@@ -685,11 +693,14 @@ static double total_penalty(const or_cfg *c, const double complex *J, const doub
 }
 
 int or_admm_solve(const or_cfg *c, const or_data *d, int iters, double complex *J,
-                  double complex *Y, double complex *Z, double complex *BZ, double *trace) {
+                  double complex *Y, double complex *Z, double complex *BZ, double *trace,
+                  int carry) {
   const int64_t nj = (int64_t)c->P * c->K * c->N * 4, nz = (int64_t)c->K * c->Q * c->N * 4;
-  memset(Y, 0, sizeof(double complex) * nj);
-  memset(BZ, 0, sizeof(double complex) * nj);
-  memset(Z, 0, sizeof(double complex) * nz);
+  if (!carry) {   /* Y^0 = Z^0 = 0 (Section 3); carry: continue from the given state */
+    memset(Y, 0, sizeof(double complex) * nj);
+    memset(BZ, 0, sizeof(double complex) * nj);
+    memset(Z, 0, sizeof(double complex) * nz);
+  }
   double *g = malloc(sizeof(double) * c->P);
   int status = 0;
   for (int n = 0; n < iters && status == 0; ++n) {

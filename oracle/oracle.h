@@ -67,9 +67,12 @@ void or_gpa(const or_cfg *c, double complex *J, int rounds);
 /* fusion-centre Z update, B_f Z, dual update and residuals (Section 3, steps D2-D3) */
 int or_consensus(const or_cfg *c, const double complex *J, double complex *Y, double complex *Z,
                  double complex *BZ, double *primal, double *dual);
-/* the whole C-ADMM loop; trace [iters][4] = data cost, Lagrangian, primal, dual */
+/* the whole C-ADMM loop; trace [iters][4] = data cost, Lagrangian, primal, dual.  carry = 0
+ * starts from Y = Z = B_f Z = 0 (Section 3); carry = 1 continues from the given Y, Z and B_f Z
+ * (the previous solution interval's state) */
 int or_admm_solve(const or_cfg *c, const or_data *d, int iters, double complex *J,
-                  double complex *Y, double complex *Z, double complex *BZ, double *trace);
+                  double complex *Y, double complex *Z, double complex *BZ, double *trace,
+                  int carry);
 
 /* textbook helpers exposed for pinning */
 int or_cholesky(int n, const double *A, double *L);
@@ -79,5 +82,6 @@ int or_pcg(int n, const double *M, const double *b, double tol, double *x, int *
 int or_polar2(const double complex *A, double complex *U);
 int or_lstsq(int m, int n, const double *A, int nrhs, const double complex *X, double complex *Z);
 int or_num_threads(void);
+void or_set_num_threads(int n);
 
 #endif

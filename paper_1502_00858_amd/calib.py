@@ -18,7 +18,7 @@ CALIB_FP32_MIXED = 1
 OPT_GPA_FIRST_ITER = 1
 OPT_UNREG_FIRST = 2
 (FIELD_J, FIELD_Z, FIELD_BZ, FIELD_Y, FIELD_MODEL_VIS, FIELD_COST, FIELD_TRACE, FIELD_LM_TRACE,
- FIELD_LM_STEP, FIELD_KERNEL_TIMES, FIELD_STATUS) = range(11)
+ FIELD_LM_STEP, FIELD_KERNEL_TIMES, FIELD_STATUS, FIELD_WORK) = range(12)
 KERNELS = ["refresh", "lm_begin", "assemble", "chol_solve", "trial", "lm_update", "commit",
            "consensus", "local_step"]
 STATUS = {0: "CALIB_OK", 1: "CALIB_E_INVAL", 2: "CALIB_E_NOMEM", 3: "CALIB_E_DEVICE",
@@ -27,7 +27,7 @@ EXPORTS = ["calib_init", "admm_local_step", "admm_consensus_update", "admm_solve
            "calib_set_jones", "calib_set_state", "calib_warmstart_features", "calib_warmstart_target",
            "calib_warmstart_apply", "calib_mlp_create", "calib_mlp_forward", "calib_mlp_train_step", "calib_mlp_get",
            "calib_mlp_destroy", "calib_mlp_last_error", "calib_set_kernel_timing",
-           "calib_destroy", "calib_last_error", "calib_consensus_noalloc"]
+           "calib_destroy", "calib_last_error", "calib_consensus_noalloc", "calib_set_data"]
 WS_FEATURES = 32
 WS_OUTPUTS = 8
 WS_SCALE = 10.0
@@ -71,6 +71,7 @@ def load(path: str = LIB_PATH):
         lib.calib_get.argtypes = [vp, i32, vp]
         lib.calib_set_jones.argtypes = [vp, vp]
         lib.calib_set_state.argtypes = [vp, vp, vp, vp, vp]
+        lib.calib_set_data.argtypes = [vp, vp, vp]
         lib.calib_set_kernel_timing.argtypes = [vp, i32]
         lib.calib_destroy.argtypes = [vp]
         lib.calib_destroy.restype = None
@@ -89,7 +90,7 @@ def load(path: str = LIB_PATH):
         lib.calib_mlp_last_error.restype = C.c_char_p
         lib.calib_consensus_noalloc.argtypes = [i32, i32, i32, i32, vp, vp, dbl, vp, vp, vp, vp,
                                                 vp, vp, vp, vp]
-        for name in ("calib_consensus_noalloc", "calib_init", "admm_local_step", "admm_consensus_update", "admm_solve",
+        for name in ("calib_consensus_noalloc", "calib_set_data", "calib_init", "admm_local_step", "admm_consensus_update", "admm_solve",
                      "calib_get", "calib_set_jones", "calib_set_state", "calib_set_kernel_timing",
                      "calib_warmstart_features", "calib_warmstart_target", "calib_warmstart_apply",
                      "calib_mlp_create",
@@ -184,6 +185,8 @@ class Calib:
             out = torch.empty(self.P, dtype=torch.float64, device="cuda")
         elif field == FIELD_LM_STEP:
             out = torch.empty((self.P, 2, 8 * self.N), dtype=torch.float64, device="cuda")
+        elif field == FIELD_WORK:
+            out = torch.empty((self.P, 2), dtype=torch.float64, device="cuda")
         elif field == FIELD_STATUS:
             out = torch.empty(self.P, dtype=torch.int32, device="cuda")
         elif field == FIELD_LM_TRACE:
@@ -198,6 +201,12 @@ class Calib:
 
     def set_jones(self, J):
         self._check(self.lib.calib_set_jones(self.ctx, _ptr(J)))
+
+    def set_data(self, vis, coh):
+        """A new solution interval of the same observation (same shapes, flags and dtype)."""
+        if tuple(vis.shape) != self._vis_shape or vis.dtype != self._vis_dtype:
+            raise ValueError("calib_set_data needs visibilities of the context's shape and dtype")
+        self._check(self.lib.calib_set_data(self.ctx, _ptr(vis), _ptr(coh)))
 
     def set_state(self, J, Y=None, Z=None, BZ=None):
         self._check(self.lib.calib_set_state(self.ctx, _ptr(J), _ptr(Y), _ptr(Z), _ptr(BZ)))

@@ -56,6 +56,12 @@ struct calib_ctx {
   int64_t total_full_samples = 0;
   int64_t *d_full_off = nullptr;
   int32_t *d_full_bmap = nullptr;
+  // packing of a solution interval's inputs (calib_init, calib_set_data)
+  int64_t *d_in_vis_off = nullptr, *d_in_coh_off = nullptr;
+  int32_t *d_comp = nullptr;   // full-layout baseline of each compact baseline, then its subband
+  int nb_total = 0;
+  void *Vp = nullptr, *Cp = nullptr;
+  double *Sb = nullptr;
   int32_t *d_ndir = nullptr;
   double *lm_trace = nullptr;
   int iters_done = 0;
@@ -542,6 +548,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   DALLOC(B.Dall, (size_t)nb_total * K * 8 * 8);
   DALLOC(B.lm, (size_t)P * sizeof(LmState));
   DALLOC(B.status, (size_t)P * sizeof(int));
+  DALLOC(B.work, (size_t)P * 2 * sizeof(double));
   double *basis, *fitw;
   DALLOC(basis, (size_t)P * Q * 8);
   DALLOC(fitw, (size_t)K * Q * P * 8);
@@ -566,6 +573,8 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   int *flagbuf;
   DALLOC(flagbuf, 2 * sizeof(int));
   B.V = Vp; B.C = Cp; B.Sb = Sb; B.rho = d_rho; B.basis = basis; B.fitw = fitw;
+  c->d_in_vis_off = d_ivo; c->d_in_coh_off = d_ico; c->d_comp = d_comp; c->nb_total = nb_total;
+  c->Vp = Vp; c->Cp = Cp; c->Sb = Sb;
 
   hipStream_t s = c->stream;
   auto dev = [&](hipError_t e, const char *what) -> bool {
@@ -576,17 +585,17 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   const bool ok =
       dev(hipMemsetAsync(flagbuf, 0, 2 * sizeof(int), s), "clear flags") &&
       dev(c->precision == CALIB_FP64
-              ? launch_pack<double>(pb, L, vis, coh, Vp, Cp, Sb, d_ivo, d_ico, d_comp, nb_total, flagbuf, s)
-              : launch_pack<float>(pb, L, vis, coh, Vp, Cp, Sb, d_ivo, d_ico, d_comp, nb_total, flagbuf, s),
-          "pack") &&
+              ? launch_pack_stats<double>(pb, L, B, vis, coh, Vp, Cp, Sb, d_ivo, d_ico, d_comp, nb_total,
+                                          flagbuf, nullptr, s)
+              : launch_pack_stats<float>(pb, L, B, vis, coh, Vp, Cp, Sb, d_ivo, d_ico, d_comp, nb_total,
+                                         flagbuf, nullptr, s),
+          "pack and coherency statistics") &&
       dev(launch_basis_setup(pb, d_freq, c->f0, d_ndir, basis, fitw, flagbuf + 1, s), "basis setup") &&
       dev(launch_dense_s(pb, L, B, s), "dense S") &&
-      dev(c->precision == CALIB_FP64 ? launch_coh_stats<double>(pb, L, B, s)
-                                     : launch_coh_stats<float>(pb, L, B, s),
-          "coherency statistics") &&
       (!B.H || dev(launch_zero(B.H, (int64_t)P * pb.npad * pb.nf, s), "zero H")) &&
       dev(hipMemsetAsync(B.lm, 0, (size_t)P * sizeof(LmState), s), "zero LM state") &&
       dev(hipMemsetAsync(B.status, 0, (size_t)P * sizeof(int), s), "zero status") &&
+      dev(launch_zero(B.work, (int64_t)P * 2, s), "zero work counters") &&
       (!B.chol_fail || dev(hipMemsetAsync(B.chol_fail, 0, (size_t)P * sizeof(int), s), "zero flags")) &&
       dev(launch_zero(B.Y, (int64_t)nj, s), "zero Y") && dev(launch_zero(B.BZ, (int64_t)nj, s), "zero BZ") &&
       dev(launch_zero(B.Z, (int64_t)nz, s), "zero Z") &&
@@ -730,6 +739,9 @@ calib_status calib_get(calib_ctx *ctx, int32_t field, void *dst) {
       for (int i = 0; i < CALIB_NUM_KERNELS; ++i) { o[2 * i] = ctx->kcount[i]; o[2 * i + 1] = ctx->kms[i]; }
       return CALIB_OK;
     }
+    case CALIB_FIELD_WORK:
+      HIPCHK(ctx, hipMemcpyAsync(dst, ctx->B.work, sizeof(double) * 2 * ctx->P, hipMemcpyDeviceToDevice, s));
+      return CALIB_OK;
     case CALIB_FIELD_STATUS:
       HIPCHK(ctx, hipMemcpyAsync(dst, ctx->B.status, sizeof(int) * ctx->P, hipMemcpyDeviceToDevice, s));
       return CALIB_OK;
@@ -797,11 +809,29 @@ calib_status calib_warmstart_apply(calib_ctx *ctx, const float *delta, int32_t *
   return CALIB_OK;
 }
 
+calib_status calib_set_data(calib_ctx *ctx, const void *vis, const void *coh) {
+  if (!ctx) return CALIB_E_INVAL;
+  if (!vis || !coh) return fail(ctx, CALIB_E_INVAL, "vis and coh are required");
+  hipStream_t s = ctx->stream;
+  HIPCHK(ctx, launch_zero_int(ctx->B.status, ctx->P, s));
+  HIPCHK(ctx, ctx->precision == CALIB_FP64
+                  ? launch_pack_stats<double>(ctx->pb, ctx->L, ctx->B, vis, coh, ctx->Vp, ctx->Cp, ctx->Sb,
+                                              ctx->d_in_vis_off, ctx->d_in_coh_off, ctx->d_comp,
+                                              ctx->nb_total, nullptr, ctx->B.status, s)
+                  : launch_pack_stats<float>(ctx->pb, ctx->L, ctx->B, vis, coh, ctx->Vp, ctx->Cp, ctx->Sb,
+                                             ctx->d_in_vis_off, ctx->d_in_coh_off, ctx->d_comp,
+                                             ctx->nb_total, nullptr, ctx->B.status, s));
+  HIPCHK(ctx, launch_dense_s(ctx->pb, ctx->L, ctx->B, s));
+  ctx->iters_done = 0;
+  return CALIB_OK;
+}
+
 calib_status calib_set_kernel_timing(calib_ctx *ctx, int32_t enable) {
   if (!ctx) return CALIB_E_INVAL;
   HIPCHK(ctx, flush_timing(ctx));
   ctx->timing = enable != 0;
   for (int i = 0; i < CALIB_NUM_KERNELS; ++i) ctx->kms[i] = ctx->kcount[i] = 0.0;
+  if (ctx->timing) HIPCHK(ctx, launch_zero(ctx->B.work, (int64_t)ctx->P * 2, ctx->stream));
   return CALIB_OK;
 }
 

@@ -106,6 +106,8 @@ struct Buffers {
   int *iter;                            // ADMM iteration whose trace row is being written
   int *chol_fail;                       // [P] blocked solver: a pivot failed in this solve
   double *chol_ld;                      // [P][panels][64*64] blocked solver: diagonal blocks' L
+  double *work;                         // [P][2] CG iterations and LM solves of the matrix-free
+                                        // solver since kernel timing was enabled (measurement)
   int *status;                          // [P] CALIB_OK or CALIB_E_NUMERIC per subband (a run
                                         // whose objective is not finite, or whose normal
                                         // equations fail past kLmFailFactor lambda_0)
@@ -128,8 +130,6 @@ __device__ inline double *d_trial(const Buffers &B, int f) { return B.lm[f].dsel
 
 // streaming kernels (templated on the stream element type float or double)
 template <typename T>
-hipError_t launch_coh_stats(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
-template <typename T>
 hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
 template <typename T>
 hipError_t launch_commit(const Problem &pb, const Layout &L, const Buffers &B, int k, int all,
@@ -137,11 +137,13 @@ hipError_t launch_commit(const Problem &pb, const Layout &L, const Buffers &B, i
 template <typename T>
 hipError_t launch_model(const Problem &pb, const Layout &L, const Buffers &B, void *model_out,
                         const int64_t *full_off, const int32_t *full_bmap, hipStream_t s);
+// per solution interval: packed V and C, S_b, U_l and X_lm in one pass over the caller's arrays
 template <typename T>
-hipError_t launch_pack(const Problem &pb, const Layout &L, const void *vis, const void *coh,
-                       void *Vp, void *Cp, double *Sb, const int64_t *in_vis_off,
-                       const int64_t *in_coh_off, const int32_t *comp2full, int nb_total,
-                       int *bad_flag, hipStream_t s);
+hipError_t launch_pack_stats(const Problem &pb, const Layout &L, const Buffers &B, const void *vis,
+                             const void *coh, void *Vp, void *Cp, double *Sb,
+                             const int64_t *in_vis_off, const int64_t *in_coh_off,
+                             const int32_t *comp_tab, int nb_total, int *bad, int *status,
+                             hipStream_t s);
 
 // LM kernels
 // k < 0: each subband's own next direction (sweeps = SAGE sweeps of the local step)

@@ -303,6 +303,7 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
     stop = tol * tol * bb;
     failed = __any(failed) ? 1 : 0;
   }
+  int iters_run = 0;
   for (int it = 0;; ++it) {
     // wavefront 0: u_p = d_p^H J_p for the partial products, and whether to iterate
     if (w == 0) {
@@ -321,6 +322,7 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
     }
     __syncthreads();
     if (!ctl[0]) break;
+    ++iters_run;
     // partial W_p over this wavefront's columns: lane j loads u of column c0 + j
     {
       double uq[8];
@@ -412,6 +414,10 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
       for (int e = 0; e < 8; ++e) dv[s][e] = fma(beta, dv[s][e], z[s][e]);
   }
   if (w != 0) return;
+  if (lane == 0 && B.work) {
+    B.work[2 * f] += iters_run;
+    B.work[2 * f + 1] += 1.0;
+  }
   if (ctl[1]) {
     if (lane == 0) st->chol_ok = 0;
     return;

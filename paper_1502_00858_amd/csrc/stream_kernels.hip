@@ -4,7 +4,8 @@
 // are constant over a baseline's samples, so everything the Levenberg-Marquardt runs need from
 // the residual R = V - sum_l c_l J_lp J_lq^H (Section 2 visibility model) is per-baseline sums:
 // D_l = sum_s conj(c_ls) R_s for every direction l, and the energy sum_s ||R_s||^2.
-//   k_coh_stats    (once)              U_l = sum conj(c_l) V, X_lm = sum conj(c_l) c_m per baseline
+//   k_pack_stats   (per interval)      packed V, C and U_l = sum conj(c_l) V, X_lm = sum conj(c_l) c_m
+//                                      per baseline
 //   refresh        (start of a local step) the energy, streaming V and the coherencies once
 //                  (k_stream), and every D_l = U_l - sum_m X_lm M_m (k_dall)
 //   k_trial_stats  (each LM trial point) cost and D_b of r = R - c_k (M_trial - M_start) (the
@@ -148,58 +149,6 @@ __global__ __launch_bounds__(64 * kStatTiles) void k_trial_stats(Problem pb, Lay
   lmd::trial_tile(pb, L, B, f, k, tile, lane);
 }
 
-// Per-baseline coherency statistics, once per context (grid: tile x direction l, one lane per
-// baseline): U_l = sum_s conj(c_ls) V_s (8 reals) and X_lm = sum_s conj(c_ls) c_ms for every
-// direction m of the subband, in FP64.  With the scalar coherency and J constant over a baseline's
-// samples, the residual's sums that the LM runs need follow from these: at a point with models
-// M_m, D_l = sum_s conj(c_ls) R_s = U_l - sum_m X_lm M_m.
-template <typename T>
-__global__ __launch_bounds__(64 * kStatTiles) void k_coh_stats(Problem pb, Layout L, Buffers B) {
-  const int tile = kStatTiles * blockIdx.x + (threadIdx.x >> 6), lane = threadIdx.x & 63, l = blockIdx.y;
-  if (tile >= pb.ntiles) return;
-  const int f = L.tile_f[tile];
-  const int Kf = L.ndir[f], nb = L.nb[f], spb = L.spb[f];
-  const int bi = L.tile_b0[tile] + lane;
-  if (l >= Kf || lane >= pb.bpt || bi >= nb) return;
-  const int K = pb.K;
-  const int64_t gb = (int64_t)L.bl_off[f] + bi, s0 = L.samp_off[f] + (int64_t)bi * spb;
-  const T *V = static_cast<const T *>(B.V), *C = static_cast<const T *>(B.C);
-  const T *cl = C + 2 * (L.coh_off[f] + ((int64_t)l * nb + bi) * spb);
-  double u[8] = {0, 0, 0, 0, 0, 0, 0, 0}, x[2 * kMaxDirs];
-#pragma unroll
-  for (int m = 0; m < 2 * kMaxDirs; ++m) x[m] = 0.0;
-  for (int s = 0; s < spb; ++s) {
-    const double cr = (double)cl[2 * s], ci = (double)cl[2 * s + 1];
-    T v[8];
-    load8<T>(V + 8 * (s0 + s), v);
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      u[2 * e] += cr * (double)v[2 * e] + ci * (double)v[2 * e + 1];
-      u[2 * e + 1] += cr * (double)v[2 * e + 1] - ci * (double)v[2 * e];
-    }
-#pragma unroll
-    for (int m = 0; m < kMaxDirs; ++m) {
-      if (m < Kf) {
-        const T *cm = C + 2 * (L.coh_off[f] + ((int64_t)m * nb + bi) * spb + s);
-        const double mr = (double)cm[0], mi = (double)cm[1];
-        x[2 * m] += cr * mr + ci * mi;
-        x[2 * m + 1] += cr * mi - ci * mr;
-      }
-    }
-  }
-  const int64_t nbt = pb.nbt;
-  double *U = B.Ucoh + ((int64_t)l * nbt + gb) * 8;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) U[e] = u[e];
-#pragma unroll
-  for (int m = 0; m < kMaxDirs; ++m)
-    if (m < K) {
-      double *X = B.Xcoh + (((int64_t)l * K + m) * nbt + gb) * 2;
-      X[0] = x[2 * m];
-      X[1] = x[2 * m + 1];
-    }
-}
-
 // Every direction's D_l at the current point from the coherency statistics (grid: tile x l, one
 // lane per baseline); direction 0's also becomes the accepted and start point of the next LM run.
 __global__ __launch_bounds__(64 * kStatTiles) void k_dall(Problem pb, Layout L, Buffers B) {
@@ -277,44 +226,101 @@ hipError_t launch_energy(const Problem &pb, const Layout &L, const Buffers &B, h
   return hipGetLastError();
 }
 
-// Pack one compact baseline per workgroup: copy its samples of V and of each direction's
-// coherencies from the caller's layout, and reduce S_b = sum_s |c_s|^2 per direction.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pack(Problem pb, Layout L, const T *vis, const T *coh,
-                                                 T *Vp, T *Cp, double *Sb, const int64_t *in_vis_off,
-                                                 const int64_t *in_coh_off, const int32_t *comp2full,
-                                                 const int32_t *comp_f, int *bad) {
-  __shared__ double red[kBlock / 64];
-  const int64_t gb = blockIdx.x;
+// Per solution interval: pack the caller's visibilities and coherencies into the library's
+// baseline-major layout (flagged baselines dropped) and form every baseline's coherency statistics
+// in the same pass, in FP64 from the element type:
+//   S_b,l = sum_s |c_ls|^2,   U_l = sum_s conj(c_ls) V_s,   X_lm = sum_s conj(c_ls) c_ms.
+// With the scalar coherency and J constant over a baseline's samples, everything the local steps
+// need from the samples besides the residual's energy follows from these: at a point with models
+// M_m, D_l = sum_s conj(c_ls) R_s = U_l - sum_m X_lm M_m.  One group of G lanes per compact
+// baseline; lane l of the group owns direction l's sums and walks the baseline's samples, all
+// lanes of a group reading the same V and coherencies (identical addresses within a request), so
+// the caller's arrays are read once; lane 0 stores the packed V and lane l the packed coherency of
+// direction l.  A non-finite input sets *bad (when given) and the subband's status word.
+template <typename T, int G>
+__global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buffers B, const T *vis,
+                                                       const T *coh, T *Vp, T *Cp, double *Sb,
+                                                       const int64_t *in_vis_off,
+                                                       const int64_t *in_coh_off,
+                                                       const int32_t *comp2full,
+                                                       const int32_t *comp_f, int nb_total, int *bad,
+                                                       int *status) {
+  const int64_t gb = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
+  const int l = threadIdx.x % G;
+  if (gb >= nb_total) return;   // whole groups
   const int f = comp_f[gb];
   const int bi = (int)(gb - L.bl_off[f]);
   const int bfull = comp2full[gb];
   const int spb = L.spb[f], nb = L.nb[f], Kf = L.ndir[f];
-  const int B = pb.N * (pb.N - 1) / 2;
-  bool finite = true;
-  for (int s = threadIdx.x; s < spb; s += kBlock) {
-    T v[8];
-    load8<T>(vis + 8 * (in_vis_off[f] + (int64_t)bfull * spb + s), v);
+  const int Bfull = pb.N * (pb.N - 1) / 2;
+  const T *vsrc = vis + 8 * (in_vis_off[f] + (int64_t)bfull * spb);
+  const T *csrc = coh + 2 * (in_coh_off[f] + (int64_t)bfull * spb);
+  const int64_t cs = 2 * (int64_t)Bfull * spb;   // between directions, caller's layout
+  T *vdst = Vp + 8 * (L.samp_off[f] + (int64_t)bi * spb);
+  T *cdst = Cp + 2 * (L.coh_off[f] + (int64_t)bi * spb);
+  const int64_t cd = 2 * (int64_t)nb * spb;      // between directions, packed layout
+  double u[8] = {0, 0, 0, 0, 0, 0, 0, 0}, x[2 * G];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) finite &= isfinite((double)v[e]);
-    store8<T>(Vp + 8 * (L.samp_off[f] + (int64_t)bi * spb + s), v);
-  }
-  for (int k = 0; k < Kf; ++k) {
-    double acc = 0.0;
-    for (int s = threadIdx.x; s < spb; s += kBlock) {
-      const T *src = coh + 2 * (in_coh_off[f] + ((int64_t)k * B + bfull) * spb + s);
-      const T cr = src[0], ci = src[1];
-      finite &= isfinite((double)cr) && isfinite((double)ci);
-      T *dst = Cp + 2 * (L.coh_off[f] + ((int64_t)k * nb + bi) * spb + s);
-      dst[0] = cr;
-      dst[1] = ci;
-      acc += (double)cr * (double)cr + (double)ci * (double)ci;
+  for (int m = 0; m < 2 * G; ++m) x[m] = 0.0;
+  bool finite = true;
+  for (int s = 0; s < spb; ++s) {
+    T v[8];
+    load8<T>(vsrc + 8 * s, v);
+    double c[2 * G];
+#pragma unroll
+    for (int m = 0; m < G; ++m) {
+      c[2 * m] = 0.0;
+      c[2 * m + 1] = 0.0;
+      if (m < Kf) {
+        c[2 * m] = (double)csrc[m * cs + 2 * s];
+        c[2 * m + 1] = (double)csrc[m * cs + 2 * s + 1];
+      }
     }
-    const double tot = block_sum(acc, red);
-    if (threadIdx.x == 0) Sb[L.sb_off[f] + (int64_t)k * nb + bi] = tot;
-    __syncthreads();
+    if (l == 0) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) finite &= isfinite((double)v[e]);
+      store8<T>(vdst + 8 * s, v);
+    }
+    if (l < Kf) {
+      double cr = 0.0, ci = 0.0;
+#pragma unroll
+      for (int m = 0; m < G; ++m)
+        if (m == l) {
+          cr = c[2 * m];
+          ci = c[2 * m + 1];
+        }
+      finite &= isfinite(cr) && isfinite(ci);
+      cdst[l * cd + 2 * s] = (T)cr;
+      cdst[l * cd + 2 * s + 1] = (T)ci;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double vr = (double)v[2 * e], vi = (double)v[2 * e + 1];
+        u[2 * e] = fma(cr, vr, fma(ci, vi, u[2 * e]));
+        u[2 * e + 1] = fma(cr, vi, fma(-ci, vr, u[2 * e + 1]));
+      }
+#pragma unroll
+      for (int m = 0; m < G; ++m) {
+        x[2 * m] = fma(cr, c[2 * m], fma(ci, c[2 * m + 1], x[2 * m]));
+        x[2 * m + 1] = fma(cr, c[2 * m + 1], fma(-ci, c[2 * m], x[2 * m + 1]));
+      }
+    }
   }
-  if (!finite) atomicOr(bad, 1);
+  if (!finite) {
+    if (bad) atomicOr(bad, 1);
+    if (status) atomicOr(status + f, 5);   // CALIB_E_NUMERIC
+  }
+  if (l >= Kf) return;
+  const int64_t nbt = pb.nbt;
+  double2 *U2 = reinterpret_cast<double2 *>(B.Ucoh + ((int64_t)l * nbt + gb) * 8);
+#pragma unroll
+  for (int h = 0; h < 4; ++h) U2[h] = make_double2(u[2 * h], u[2 * h + 1]);
+#pragma unroll
+  for (int m = 0; m < G; ++m)
+    if (m < pb.K) {
+      double2 *X2 = reinterpret_cast<double2 *>(B.Xcoh + (((int64_t)l * pb.K + m) * nbt + gb) * 2);
+      *X2 = m < Kf ? make_double2(x[2 * m], x[2 * m + 1]) : make_double2(0.0, 0.0);
+    }
+  Sb[L.sb_off[f] + (int64_t)l * nb + bi] = x[2 * l];
 }
 
 // Model visibilities in the caller's full layout (zero on flagged baselines).
@@ -380,14 +386,6 @@ hipError_t launch_commit(const Problem &pb, const Layout &L, const Buffers &B, i
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_coh_stats(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
-  if (pb.ntiles == 0) return hipSuccess;
-  if (pb.bpt > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_coh_stats<T>, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles, pb.K),
-                     dim3(64 * kStatTiles), 0, s, pb, L, B);
-  return hipGetLastError();
-}
-template <typename T>
 hipError_t launch_model(const Problem &pb, const Layout &L, const Buffers &B, void *model_out,
                         const int64_t *full_off, const int32_t *full_bmap, hipStream_t s) {
   const int Bfull = pb.N * (pb.N - 1) / 2;
@@ -396,21 +394,27 @@ hipError_t launch_model(const Problem &pb, const Layout &L, const Buffers &B, vo
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_pack(const Problem &pb, const Layout &L, const void *vis, const void *coh,
-                       void *Vp, void *Cp, double *Sb, const int64_t *in_vis_off,
-                       const int64_t *in_coh_off, const int32_t *comp2full, int nb_total,
-                       int *bad_flag, hipStream_t s) {
+hipError_t launch_pack_stats(const Problem &pb, const Layout &L, const Buffers &B, const void *vis,
+                             const void *coh, void *Vp, void *Cp, double *Sb,
+                             const int64_t *in_vis_off, const int64_t *in_coh_off,
+                             const int32_t *comp_tab, int nb_total, int *bad, int *status,
+                             hipStream_t s) {
   if (nb_total == 0) return hipSuccess;
-  // comp_f is stored right after comp2full (see host packing)
-  hipLaunchKernelGGL(k_pack<T>, dim3(nb_total), dim3(kBlock), 0, s, pb, L,
-                     static_cast<const T *>(vis), static_cast<const T *>(coh), static_cast<T *>(Vp),
-                     static_cast<T *>(Cp), Sb, in_vis_off, in_coh_off, comp2full,
-                     comp2full + nb_total, bad_flag);
+  // comp_tab: the full-layout baseline of each compact baseline, then its subband
+  const T *v = static_cast<const T *>(vis), *c = static_cast<const T *>(coh);
+  T *vp = static_cast<T *>(Vp), *cp = static_cast<T *>(Cp);
+  if (pb.K <= 8) {
+    const unsigned grid = (unsigned)(((int64_t)nb_total * 8 + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_pack_stats<T, 8>), dim3(grid), dim3(kBlock), 0, s, pb, L, B, v, c, vp, cp, Sb,
+                       in_vis_off, in_coh_off, comp_tab, comp_tab + nb_total, nb_total, bad, status);
+  } else {
+    const unsigned grid = (unsigned)(((int64_t)nb_total * 16 + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_pack_stats<T, 16>), dim3(grid), dim3(kBlock), 0, s, pb, L, B, v, c, vp, cp, Sb,
+                       in_vis_off, in_coh_off, comp_tab, comp_tab + nb_total, nb_total, bad, status);
+  }
   return hipGetLastError();
 }
 
-template hipError_t launch_coh_stats<float>(const Problem &, const Layout &, const Buffers &, hipStream_t);
-template hipError_t launch_coh_stats<double>(const Problem &, const Layout &, const Buffers &, hipStream_t);
 template hipError_t launch_refresh<float>(const Problem &, const Layout &, const Buffers &, hipStream_t);
 template hipError_t launch_refresh<double>(const Problem &, const Layout &, const Buffers &, hipStream_t);
 hipError_t launch_trial_stats(const Problem &pb, const Layout &L, const Buffers &B, int k,
@@ -428,11 +432,13 @@ template hipError_t launch_model<float>(const Problem &, const Layout &, const B
                                         const int64_t *, const int32_t *, hipStream_t);
 template hipError_t launch_model<double>(const Problem &, const Layout &, const Buffers &, void *,
                                          const int64_t *, const int32_t *, hipStream_t);
-template hipError_t launch_pack<float>(const Problem &, const Layout &, const void *, const void *,
-                                       void *, void *, double *, const int64_t *, const int64_t *,
-                                       const int32_t *, int, int *, hipStream_t);
-template hipError_t launch_pack<double>(const Problem &, const Layout &, const void *, const void *,
-                                        void *, void *, double *, const int64_t *, const int64_t *,
-                                        const int32_t *, int, int *, hipStream_t);
+template hipError_t launch_pack_stats<float>(const Problem &, const Layout &, const Buffers &, const void *,
+                                             const void *, void *, void *, double *, const int64_t *,
+                                             const int64_t *, const int32_t *, int, int *, int *,
+                                             hipStream_t);
+template hipError_t launch_pack_stats<double>(const Problem &, const Layout &, const Buffers &, const void *,
+                                              const void *, void *, void *, double *, const int64_t *,
+                                              const int64_t *, const int32_t *, int, int *, int *,
+                                              hipStream_t);
 
 }  // namespace calib

@@ -436,3 +436,22 @@ def test_trace_lagrangian_column(oracle_mod, synth_mod):
     assert abs(two["trace"][1, 0] - g.sum()) <= 1e-13 * g.sum()
     assert abs(L - via_dirs) <= 1e-12 * abs(L)
     assert abs(L - direct) <= 1e-12 * abs(L)
+
+
+def test_admm_continues_from_a_carried_state(oracle_mod, synth_mod):
+    """Section 3 starts a new interval from the previous one's solution: continuing a run from its
+    own state after n iterations reproduces the uninterrupted run (the iteration depends on the
+    state only), and a zero carried state is the cold start."""
+    cfg = tiny_cfg(synth_mod, N=6, P=4, Q=2, K=2, T=3, n_chan=2, lm_iters=4)
+    d = synth_mod.generate(cfg)
+    pb = oracle_mod.Problem(d, lm_iters=4, options=0)
+    J0 = synth_mod.identity_jones(cfg.P, cfg.K, cfg.N)
+    whole = pb.admm_solve(J0, 5)
+    first = pb.admm_solve(J0, 2)
+    rest = pb.admm_solve(first["J"], 3, first["Y"], first["Z"], first["BZ"])
+    np.testing.assert_array_equal(rest["J"], whole["J"])
+    # the dual residual of the first continued iteration uses the carried Z, the rest is identical
+    np.testing.assert_array_equal(rest["trace"][:, :3], whole["trace"][2:, :3])
+    zero = np.zeros(pb.jshape(), np.complex128)
+    cold = pb.admm_solve(J0, 2, zero, np.zeros(pb.zshape(), np.complex128), zero)
+    np.testing.assert_array_equal(cold["trace"], first["trace"])
