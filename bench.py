@@ -3,18 +3,24 @@
 learned warm start against the plain starts.
 
 Workload (default c2): N=62 stations (1891 baselines), K=5 directions, T=10 slots, 32 subbands x 4
-channels over 115-185 MHz, 4-term polynomial basis, rho=5, 10 LM iterations per direction, FP32
-streaming with FP64 normal-equation solve / cost / Z.  The data are consecutive solution
-intervals of a drifting observation (synth.episode_interval); the measured interval is interval 3
-of a held-out episode, whose predecessors were solved (30 ADMM iterations each) to give the
-previous C-ADMM state (J, Y, Z, B_f Z).
+channels over 115-185 MHz, 4-term polynomial basis, rho=5, at most 10 LM iterations per direction
+under the LM stopping rule (lm_tol 1e-7), FP32 streaming with FP64 statistics, solve, cost and Z;
+local solver: matrix-free conjugate gradients (solver 3, cg_tol 1e-4) inside the one-launch local
+step.  The data are consecutive solution intervals of a drifting observation
+(synth.episode_interval); the measured interval is interval 3 of a held-out episode, whose
+predecessors were solved (30 ADMM iterations each) to give the previous C-ADMM state (J, Y, Z, B_f Z).
 
-Target: g_inf, the median data cost over iterations 50-99 of a 100-iteration run from the
-previous state; a start "reaches" the target at the first ADMM iteration whose data cost is within
-1e-6 relative of g_inf (iterations counted in untimed reference runs of each start).
+Target: g* and primal* are the medians of the data cost and of the primal residual over the last
+two thirds of a 600-iteration FP64 run from the previous state (the cost does not settle: it keeps
+wandering by ~1e-5 relative around its long-run level, so the median of that stretch is the
+reference); a start reaches the target at the first ADMM iteration whose data cost is within 1e-6
+relative of g* and whose primal residual is at most 1.001 primal* (iterations counted in untimed
+runs of each start in the timed configuration).
 
-One timed step = one solve of all 32 subbands from a start, run for exactly the iterations that
-start needs to reach the target, with the inputs resident in HBM:
+One timed step = one new solution interval for all 32 subbands, with the inputs resident in HBM:
+the interval's visibilities and coherencies loaded into the context (calib_set_data: repacking and
+the per-baseline coherency statistics), the start, then exactly the ADMM iterations that start
+needs to reach the target:
   learned : previous state, features, network forward, per-subband cost fallback, then ADMM
   plain   : previous state (the paper's warm start, J and the dual variables), then ADMM
   identity: identity Jones matrices, Y = Z = 0, first-iteration gauge alignment, then ADMM
@@ -22,8 +28,9 @@ value = subbands x steps / wall time of the learned steps (subband-solves per se
 
 Also reported: training cost of the network (pairs, epochs, seconds), per-kernel time breakdown and
 the roofline of the dominant kernel (HIP events on the library's stream around every launch, in a
-separate untimed pass), the FP32-vs-FP64 accuracy of the data cost, and the FP64 CPU oracle timed
-on a bounded sample of the same workload.
+separate untimed pass; algorithmic FLOPs from the solver's work counters), the bandwidth of the
+HBM-streaming passes, the FP32-vs-FP64 accuracy of the data cost, and the FP64 CPU oracle timed on
+a bounded sample of the same workload from the same previous state.
 """
 from __future__ import annotations
 
@@ -44,12 +51,7 @@ FP64_PEAK_TFS = 78.6
 # HBM bytes per launch of a kernel class (FETCH_SIZE + WRITE_SIZE, scaled by a 256 MiB copy) as
 # measured for a workload (profiles/hbm_counters_c2.md); reported only while the kernel sources
 # are unchanged (sha256 over the listed files) and for that workload and solver.
-MEASURED_TRAFFIC = {
-    ("chol_solve", "c2", "blocked"): (
-        ("paper_1502_00858_amd/csrc/chol_blocked.hip", "paper_1502_00858_amd/csrc/chol_common.h"),
-        "5963cf33b49e827b0509122a00c1efeb7c6b493776e027b98a77db2e520e3165",
-        (161.00 + 58.98) * 1e6),
-}
+MEASURED_TRAFFIC = {}
 
 
 def measured_traffic(kernel, config, solver):
@@ -65,57 +67,92 @@ def measured_traffic(kernel, config, solver):
     return nbytes if h.hexdigest() == sha else None
 
 
-def kernel_work(name, data, elt):
-    """Algorithmic bytes or FLOPs of one launch of a kernel class, averaged over the directions
-    (a direction's LM launches cover only the subbands that carry it)."""
+def local_step_flops(data, work, launches):
+    """Algorithmic FP64 FLOPs of one launch of the one-launch local step (solver 3), from the
+    solver's counters (CG iterations and LM solves per subband over the profiled launches):
+      per CG iteration  16 N^2 (the S table against the stacked u_q = d_q^H J_q, 8 reals per
+                        station) + 260 N (u_q, the preconditioner, the recurrences);
+      per LM solve      8 N^2 (Q_p = sum_q S_pq J_q^H J_q) + 144 nb (gradient: two 2x2 complex
+                        products per baseline) + 160 nb (trial point: two J_p J_q^H per baseline
+                        and its D_b) + 132 N;
+      per direction     2 N^2 (largest diagonal entry) + nb (120 + 48 (K_f - k)) (the SAGE commit
+                        into every later direction's statistics);
+    nb = unflagged baselines of the subband, K_f its directions, k the direction's index."""
     N = int(data["N"])
-    K = int(data["K"])
-    n = 8 * N
+    nb = data["nb_live"].astype(np.float64)
+    Kf = np.asarray(data["n_dirs"], np.float64)
+    cg, lm = work[:, 0] / launches, work[:, 1] / launches
+    per_dir = 2.0 * N * N * Kf + nb * (120.0 * Kf + 48.0 * Kf * (Kf + 1) / 2.0)
+    return float(np.sum(cg * (16.0 * N * N + 260.0 * N)
+                        + lm * (8.0 * N * N + 304.0 * nb + 132.0 * N) + per_dir))
+
+
+def stream_bytes(name, data, elt):
+    """Algorithmic HBM bytes of one launch of an HBM-streaming pass."""
+    N, K = int(data["N"]), int(data["K"])
     nb = data["nb_live"].astype(np.float64)
     Kf = np.asarray(data["n_dirs"], np.float64)
     S_f = nb * data["T"] * np.asarray(data["n_chan"], np.float64)   # samples per subband
-    w = Kf / K                                   # share of a class's launches that cover f
-    if name == "chol_solve":
-        return ("mfma", float(np.sum(w)) * (n ** 3 / 3.0 + 2.0 * n ** 2), "TFLOP/s")
-    if name == "trial":
-        # statistics of the trial point: D_b of the start point and S_b read, D_b written
-        return ("hbm", float(np.sum(w * nb * (64.0 + 8.0 + 64.0))), "GB/s")
-    if name == "commit":
-        # every direction's D_b read and written, X_lk read, per baseline
-        return ("hbm", float(np.sum(w * nb * Kf * (64.0 * 2 + 16.0))), "GB/s")
     if name == "refresh":
         # the residual's energy: V and every direction's coherency streamed once; then every
         # direction's D_b from U_l and X_lm
-        return ("hbm", float(np.sum(S_f * (8 + 2 * Kf) * elt
-                                    + nb * Kf * (64.0 + 16.0 * Kf + 64.0))), "GB/s")
-    if name == "assemble":
-        return ("hbm", float(np.sum(w)) * (n * (n + 1) / 2.0) * 8.0, "GB/s")
-    return (None, None, None)
+        return float(np.sum(S_f * (8 + 2 * Kf) * elt + nb * Kf * (64.0 + 16.0 * Kf + 64.0)))
+    if name == "pack":
+        # the interval's V and coherencies read and written once in the packed layout; U_l, a row
+        # of X_lm and S_b written per baseline and direction; the dense S table rebuilt
+        return float(np.sum(2 * S_f * (8 + 2 * Kf) * elt + nb * Kf * (64.0 + 16.0 * K + 8.0))
+                     + len(nb) * K * N * N * 8.0)
+    raise KeyError(name)
 
 
-def cpu_baseline(data, iters_sample, iters_to_target, lm_iters, lm_tol):
-    """The FP64 oracle's plain C-ADMM on the same interval (FP32-rounded inputs).  Per-iteration
-    time = (time of 2 + iters_sample iterations - time of 2 iterations) / iters_sample, i.e. the
-    cost of iterations after the first two (where the LM stopping rule acts as it does in the
-    timed GPU runs), scaled to the iterations the plain start needs to reach the target."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(data, prev, iters_sample, iters_to_target, lm_iters, lm_tol, cg_tol):
+    """The FP64 oracle's C-ADMM on the same interval (FP32-rounded inputs), continued from the same
+    previous state as the GPU's plain start, with the same LM stopping rule and solver reading
+    (conjugate gradients at cg_tol).  Per-iteration time = (time of 2 + n iterations - time of 2
+    iterations) / n, the cost of iterations after the first two, scaled to the iterations the plain
+    start needs to reach the target; n = iters_sample on all the oracle's threads, 1 on one."""
     import oracle
     from paper_1502_00858_amd import synth
-    pb = oracle.Problem(synth.as_fp32_inputs(data), lm_iters=lm_iters, options=0, lm_tol=lm_tol)
-    P, K, N = int(data["P"]), int(data["K"]), int(data["N"])
-    J0 = synth.identity_jones(P, K, N)
-    t0 = time.perf_counter()
-    pb.admm_solve(J0, 2)
-    t1 = time.perf_counter()
-    pb.admm_solve(J0, 2 + iters_sample)
-    t2 = time.perf_counter()
-    per_iter = ((t2 - t1) - (t1 - t0)) / iters_sample
-    per_solve = per_iter * iters_to_target
-    return {"value": P / per_solve, "unit": "subband-solves/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+    pb = oracle.Problem(synth.as_fp32_inputs(data), lm_iters=lm_iters, options=0, lm_tol=lm_tol,
+                        solver=oracle.SOLVE_PCG, cg_tol=cg_tol)
+    P = int(data["P"])
+    st = [x.cpu().numpy() for x in (prev.J, prev.Y, prev.Z, prev.BZ)]
+
+    def per_iteration(n):
+        t0 = time.perf_counter()
+        pb.admm_solve(st[0], 2, st[1], st[2], st[3])
+        t1 = time.perf_counter()
+        pb.admm_solve(st[0], 2 + n, st[1], st[2], st[3])
+        t2 = time.perf_counter()
+        return ((t2 - t1) - (t1 - t0)) / n, t2 - t0
+
+    threads = oracle.num_threads()
+    per_iter, wall = per_iteration(iters_sample)
+    oracle.set_num_threads(1)
+    try:
+        per_iter_1, wall_1 = per_iteration(1)
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": P / (per_iter * iters_to_target), "unit": "subband-solves/s",
+            "cores": threads, "kind": "oracle", "cpu": cpu_model(), "host_cpus": os.cpu_count(),
+            "value_1_thread": P / (per_iter_1 * iters_to_target),
             "sample": f"ADMM iterations 3-{2 + iters_sample} over all {P} subbands of the measured "
-                      f"interval (FP64 oracle on the FP32-rounded inputs, same LM stopping rule), "
-                      f"{per_iter:.2f} s per iteration ({t2 - t0:.1f} s of runs), scaled to the "
-                      f"{iters_to_target} iterations the plain start needs to reach the target"}
+                      f"interval from the previous interval's state (FP64 oracle on the "
+                      f"FP32-rounded inputs, same LM stopping rule and CG tolerance): "
+                      f"{per_iter:.3f} s per iteration on {threads} threads, {per_iter_1:.3f} s on "
+                      f"one ({wall + wall_1:.1f} s of runs), scaled to the {iters_to_target} "
+                      f"iterations the plain start needs to reach the target"}
 
 
 def timed(fn, steps, warmup):
@@ -133,23 +170,29 @@ def timed(fn, steps, warmup):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--lm-iters", type=int, default=None)
     ap.add_argument("--lm-tol", type=float, default=1e-7,
                     help="LM stopping rule: predicted decrease <= lm_tol * objective (0 = off)")
+    ap.add_argument("--solver", type=int, default=3,
+                    help="local solver: 3 matrix-free conjugate gradients in the one-launch local "
+                         "step; 0 Cholesky (auto), 1 one workgroup per matrix, 2 blocked panels")
+    ap.add_argument("--cg-tol", type=float, default=1e-4,
+                    help="solver 3: relative residual at which conjugate gradients stop")
     ap.add_argument("--chain-iters", type=int, default=30,
                     help="ADMM iterations per interval when solving the episodes")
-    ap.add_argument("--ref-iters", type=int, default=100,
-                    help="iterations of the reference runs that fix the target")
+    ap.add_argument("--target-iters", type=int, default=600,
+                    help="iterations of the FP64 run that fixes the target")
+    ap.add_argument("--ref-iters", type=int, default=160,
+                    help="iterations of the untimed runs that count each start's iterations")
     ap.add_argument("--train-episodes", type=int, default=2)
     ap.add_argument("--episode-intervals", type=int, default=6)
     ap.add_argument("--epochs", type=int, default=60)
-    ap.add_argument("--cpu-sample-iters", type=int, default=2)
+    ap.add_argument("--cpu-sample-iters", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
-    ap.add_argument("--no-reference", action="store_true", help="skip the FP64 accuracy run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--tile-group", type=int, default=0)
@@ -157,11 +200,6 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="choose tile_group / stream_grid with paper_1502_00858_amd.autotune")
     ap.add_argument("--batch", type=int, default=512, help="training minibatch rows")
-    ap.add_argument("--solver", type=int, default=0,
-                    help="normal-equation solver: 0 auto (Cholesky), 1 one workgroup per matrix, "
-                         "2 blocked panels, 3 matrix-free conjugate gradients")
-    ap.add_argument("--cg-tol", type=float, default=0.0,
-                    help="solver 3: relative residual at which CG stops (0 = library default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the method's cross-subband exchange is a device-wide "
@@ -179,14 +217,14 @@ def main():
     prec = calib.CALIB_FP64 if args.config == "c1" else calib.CALIB_FP32_MIXED
     elt = 8 if prec == calib.CALIB_FP64 else 4
     TEST_EPISODE, J_EVAL = 9, 3
+    solve_kw = dict(solver=args.solver, cg_tol=args.cg_tol)
 
     # ---- training pairs and the network (untimed; reported as training cost) ----------------------
     t0 = time.perf_counter()
     train_iv = []
     for e in range(args.train_episodes):
         train_iv += warmstart.solve_episode(cfg, e, args.episode_intervals, prec, args.chain_iters,
-                                            lm_iters, lm_tol=args.lm_tol, solver=args.solver,
-                                            cg_tol=args.cg_tol)
+                                            lm_iters, lm_tol=args.lm_tol, **solve_kw)
         log(f"training episode {e} solved ({time.perf_counter() - t0:.1f} s)")
     gen_s = time.perf_counter() - t0
     X, Y = warmstart.stack_rows(train_iv)
@@ -195,10 +233,10 @@ def main():
     train_s = net.train(X, Y, epochs=args.epochs, batch=args.batch, lr=2e-3, lr_final=2e-4)
     log(f"trained on {X.shape[0]} rows in {train_s:.1f} s, loss {net.history[-1]:.3e}")
 
-    # ---- the measured interval and its predecessors (untimed) -----------------------------------
+    # ---- the measured interval, its predecessors and the contexts (untimed) ------------------------
     chain = warmstart.solve_episode(cfg, TEST_EPISODE, args.episode_intervals, prec,
                                     args.chain_iters, lm_iters, count=J_EVAL, lm_tol=args.lm_tol,
-                                    solver=args.solver, cg_tol=args.cg_tol)
+                                    **solve_kw)
     prev, prev2 = chain[-1], chain[-2]
     data = synth.episode_interval(cfg, TEST_EPISODE, J_EVAL, args.episode_intervals)
     P, B = int(data["P"]), cfg.B
@@ -207,45 +245,60 @@ def main():
     shape = {"tile_group": args.tile_group, "stream_grid": args.stream_grid, "source": "flags"}
     if args.autotune:
         from paper_1502_00858_amd import autotune
-        tuned = autotune.tune(data, vis, coh, flags, prec, refresh=True)
+        tuned = autotune.tune(data, vis, coh, flags, prec, refresh=True, **solve_kw)
         shape = {"tile_group": tuned["tile_group"], "stream_grid": tuned["stream_grid"],
                  "source": "autotune", "stream_ms_per_local_step": round(tuned["ms"], 3),
                  "worst_candidate_ms": round(max(c["ms"] for c in tuned["candidates"]), 3)}
         log(f"autotune: {shape}")
-    ctx = calib.Calib(data, vis, coh, flags, precision=prec, lm_iters=lm_iters, options=0,
-                      tile_group=shape["tile_group"], stream_grid=shape["stream_grid"],
-                      lm_tol=args.lm_tol, solver=args.solver, cg_tol=args.cg_tol)
-    ctx_id = calib.Calib(data, vis, coh, flags, precision=prec, lm_iters=lm_iters,
-                         options=calib.OPT_GPA_FIRST_ITER, tile_group=shape["tile_group"],
-                         stream_grid=shape["stream_grid"], lm_tol=args.lm_tol, solver=args.solver, cg_tol=args.cg_tol)
+    # the contexts are made once per observation, on its first interval; every timed step loads
+    # the measured interval into them (calib_set_data)
+    first = synth.episode_interval(cfg, TEST_EPISODE, 0, args.episode_intervals)
+    v0, c0, f0 = calib.device_inputs(first, prec)
+    ctx_kw = dict(precision=prec, lm_iters=lm_iters, tile_group=shape["tile_group"],
+                  stream_grid=shape["stream_grid"], lm_tol=args.lm_tol, **solve_kw)
+    ctx = calib.Calib(first, v0, c0, f0, options=0, **ctx_kw)
+    ctx_id = calib.Calib(first, v0, c0, f0, options=calib.OPT_GPA_FIRST_ITER, **ctx_kw)
+    del v0, c0, f0
     J_id = torch.from_numpy(synth.identity_jones(P, cfg.K, cfg.N)).cuda()
 
     def start_plain():
+        ctx.set_data(vis, coh)
         ctx.set_state(prev.J, prev.Y, prev.Z, prev.BZ)
 
     def start_learned():
+        ctx.set_data(vis, coh)
         ctx.set_state(prev.J, prev.Y, prev.Z, prev.BZ)
         feats = ctx.warmstart_features(prev2.J, prev.BZ)
         return ctx.warmstart_apply(net.predict(feats))
 
     def start_identity():
+        ctx_id.set_data(vis, coh)
         ctx_id.set_jones(J_id)
 
     starts = {"learned": (ctx, start_learned), "plain": (ctx, start_plain),
               "identity": (ctx_id, start_identity)}
+
+    # ---- the target: a long FP64 run from the previous state ---------------------------------------
+    v64, c64, f64 = calib.device_inputs(data, calib.CALIB_FP64)
+    r64 = calib.Calib(data, v64, c64, f64, options=0,
+                      **dict(ctx_kw, precision=calib.CALIB_FP64))
+    r64.set_state(prev.J, prev.Y, prev.Z, prev.BZ)
+    tr64 = r64.solve(args.target_iters)
+    r64.close()
+    del v64, c64, f64
+    lo = args.target_iters // 3
+    g_star = float(np.median(tr64[lo:, 0]))
+    primal_star = float(np.median(tr64[lo:, 2]))
+    wander = float(np.max(np.abs(tr64[lo:, 0] - g_star)) / g_star)
+    log(f"target g* {g_star:.9e} primal* {primal_star:.6e} (FP64 iterations {lo + 1}-"
+        f"{args.target_iters}; cost within {wander:.1e} of g* there)")
     ref = {}
     for name, (c, st) in starts.items():
         st()
         ref[name] = c.solve(args.ref_iters)
-    g_inf = float(np.median(ref["plain"][args.ref_iters // 2:, 0]))
-    iters = {k: warmstart.iters_to_target(tr, g_inf) for k, tr in ref.items()}
-    log(f"target {g_inf:.9e}; iterations to it: {iters}")
-    # the same target with every LM run at its full iteration count: the stopping rule must not
-    # move the cost that the solves reach
-    ctx0 = calib.Calib(data, vis, coh, flags, precision=prec, lm_iters=lm_iters, options=0,
-                       tile_group=shape["tile_group"], stream_grid=shape["stream_grid"], solver=args.solver, cg_tol=args.cg_tol)
-    ctx0.set_state(prev.J, prev.Y, prev.Z, prev.BZ)
-    g_inf0 = float(np.median(ctx0.solve(args.ref_iters)[args.ref_iters // 2:, 0]))
+    iters = {k: warmstart.iters_to_target(tr, g_star, primal_target=primal_star)
+             for k, tr in ref.items()}
+    log(f"iterations to the target: {iters}")
 
     # ---- timed steps ----------------------------------------------------------------------------
     sec, final = {}, {}
@@ -256,13 +309,16 @@ def main():
             st()
             final[name] = c.solve(n_it)
         sec[name] = timed(step, args.steps, args.warmup)
+        log(f"{name}: {1e3 * sec[name]:.2f} ms per step ({n_it} iterations)")
     kept = start_learned().cpu().numpy()
     ws_s = timed(start_learned, max(args.steps, 3), 1) - timed(start_plain, max(args.steps, 3), 1)
     value = P / sec["learned"]
     kdesc = cfg.K if cfg.n_dirs is None and cfg.name != "c3" else f"{cfg.K} (K_f ~ U{{3..10}})"
     cdesc = cfg.n_chan if cfg.n_chan > 0 else "U{1..16}"
     fdesc = f" flagged ~U(0,{cfg.flag_frac_max})" if cfg.flag_frac_max > 0 else ""
-
+    solver_desc = {0: "Cholesky (auto: blocked below 128 subbands, else one workgroup per matrix)",
+                   1: "Cholesky, one workgroup per matrix", 2: "Cholesky, blocked panels",
+                   3: f"matrix-free CG (cg_tol {args.cg_tol:g}) in the one-launch local step"}
     out = {"metric": "subband ADMM solves/s (N=62,K=5) at 1e-6 rel cost, learned vs plain; HBM GB/s",
            "value": value, "unit": "subband-solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * sec["learned"], "higher_is_better": True,
@@ -270,85 +326,80 @@ def main():
            "dtype": "f64+bf16" if prec == calib.CALIB_FP64 else "f32+f64+bf16",
            "data": "synthetic",
            "config": {"workload": f"{args.config}: N={cfg.N} K={kdesc} T={cfg.T} P={P} "
-                                  f"n_chan={cdesc} Q={cfg.Q} rho={cfg.rho} lm<={lm_iters} lm_tol={args.lm_tol:g}{fdesc}, "
-                                  f"interval {J_EVAL} of a drifting episode, learned warm start",
+                                  f"n_chan={cdesc} Q={cfg.Q} rho={cfg.rho} lm<={lm_iters} "
+                                  f"lm_tol={args.lm_tol:g}{fdesc}, interval {J_EVAL} of a drifting "
+                                  f"episode loaded per step, learned warm start, "
+                                  f"{solver_desc[args.solver]}",
                       "global_batch": P, "parallelism": "none (1 GPU)"}}
-    out["target_cost"] = g_inf
+    out["target"] = {"g_star": g_star, "primal_star": primal_star,
+                     "source": f"medians over iterations {lo + 1}-{args.target_iters} of an FP64 "
+                               f"run from the previous state",
+                     "cost_wander_there": wander,
+                     "rule": "first iteration with |g - g*| <= 1e-6 g* and primal <= 1.001 primal*"}
     out["iters_to_target"] = iters
     out["solves_per_s"] = {k: P / v for k, v in sec.items()}
     out["speedup_learned_vs_plain"] = sec["plain"] / sec["learned"]
     out["speedup_learned_vs_identity"] = sec["identity"] / sec["learned"]
-    out["final_rel_cost"] = {k: float((v[-1, 0] - g_inf) / g_inf) for k, v in final.items()}
-    out["target_cost_full_lm"] = g_inf0
-    out["final_rel_cost_vs_full_lm_target"] = {k: float((v[-1, 0] - g_inf0) / g_inf0)
-                                               for k, v in final.items()}
+    out["final_rel_cost"] = {k: float((v[-1, 0] - g_star) / g_star) for k, v in final.items()}
     out["final_primal_residual"] = {k: float(v[-1, 2]) for k, v in final.items()}
+    n64 = iters["plain"] or args.ref_iters
+    if prec == calib.CALIB_FP32_MIXED:
+        # the FP64 path from the same previous state after the same iterations as the timed plain step
+        out["fp32_vs_fp64_rel_cost"] = float(abs(final["plain"][-1, 0] - tr64[n64 - 1, 0])
+                                             / tr64[n64 - 1, 0])
     out["warm_start_ms"] = 1e3 * ws_s
     out["learned_kept_subbands"] = int(kept.sum())
     out["tile_shape"] = shape
-    out["solver"] = {0: "auto (blocked below 128 subbands, else one workgroup per matrix)",
-                     1: "one workgroup per matrix", 2: "blocked panels",
-                     3: f"matrix-free conjugate gradients (cg_tol {args.cg_tol or 1e-10:g})"}[args.solver]
+    out["solver"] = solver_desc[args.solver]
     out["training"] = {"rows": int(X.shape[0]), "epochs": args.epochs, "batch": args.batch,
                        "pair_generation_s": round(gen_s, 2), "train_s": round(train_s, 2),
                        "final_loss": net.history[-1],
                        "zero_predictor_loss": float(np.mean(Y.astype(np.float64) ** 2))}
 
-    if prec == calib.CALIB_FP32_MIXED and not args.no_reference:
-        # FP64 solve from the same previous state, same iterations as the timed plain step
-        v64, c64, f64 = calib.device_inputs(data, calib.CALIB_FP64)
-        r64 = calib.Calib(data, v64, c64, f64, precision=calib.CALIB_FP64, lm_iters=lm_iters,
-                          options=0, lm_tol=args.lm_tol)
-        r64.set_state(prev.J, prev.Y, prev.Z, prev.BZ)
-        tr64 = r64.solve(iters["plain"] or args.ref_iters)
-        g32 = final["plain"][-1, 0]
-        out["fp32_vs_fp64_rel_cost"] = float(abs(g32 - tr64[-1, 0]) / tr64[-1, 0])
-        r64.close()
-        del v64, c64, f64
-
     if not args.no_profile:
-        def profiled(c):
-            c.set_kernel_timing(True)
-            c.set_state(prev.J, prev.Y, prev.Z, prev.BZ)
-            c.warmstart_apply(net.predict(c.warmstart_features(prev2.J, prev.BZ)))
-            c.solve(iters["learned"] or args.ref_iters)
-            kt = c.get(calib.FIELD_KERNEL_TIMES)
-            c.set_kernel_timing(False)
-            return kt
-        # where the timed learned step spends its time (stopping rule as timed)
-        kt_run = profiled(ctx)
-        out["kernel_ms_per_step"] = {k: round(v[1], 3) for k, v in kt_run.items()}
-        out["kernel_launches_per_step"] = {k: v[0] for k, v in kt_run.items()}
-        # per-launch work is only well defined when every launch covers every subband that
-        # carries the direction: the roofline pass runs with the stopping rule off
-        kt = profiled(ctx0)
-        out["roofline_pass"] = "learned start, stopping rule off (every LM launch full)"
+        # where the timed learned step spends its time, kernel by kernel (eager launches, each
+        # bracketed by HIP events on the library's stream)
+        ctx.set_kernel_timing(True)
+        start_learned()
+        ctx.solve(iters["learned"] or args.ref_iters)
+        kt = ctx.get(calib.FIELD_KERNEL_TIMES)
+        work = ctx.get(calib.FIELD_WORK).cpu().numpy()
+        ctx.set_kernel_timing(False)
         total = sum(v[1] for v in kt.values())
-        out["kernel_ms_per_step_full_lm"] = {k: round(v[1], 3) for k, v in kt.items()}
+        out["kernel_ms_per_step"] = {k: round(v[1], 3) for k, v in kt.items() if v[0]}
+        out["kernel_launches_per_step"] = {k: v[0] for k, v in kt.items() if v[0]}
         dom = max(kt, key=lambda k: kt[k][1])
         launches, ms = kt[dom]
         avg_s = ms / launches / 1e3
-        bound, work, unit = kernel_work(dom, data, elt)
-        solver_name = ("blocked" if (args.solver == 2 or (args.solver == 0 and P < 128))
-                       else "single")
-        if bound is not None:
-            achieved = work / avg_s / (1e12 if unit == "TFLOP/s" else 1e9)
-            peak = FP64_PEAK_TFS if unit == "TFLOP/s" else HBM_PEAK_GBS
-            out["roofline"] = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": peak,
-                               "unit": unit, "frac": achieved / peak,
-                               "traffic": measured_traffic(dom, args.config, solver_name),
-                               "avg_launch_us": avg_s * 1e6, "share_of_step": ms / total}
-        # the streaming pass at the start of a local step: achieved HBM bandwidth
-        rl, rms = kt["refresh"]
-        _, rb, _ = kernel_work("refresh", data, elt)
-        out["refresh_pass_GBs"] = rb / (rms / rl / 1e3) / 1e9
+        rl = {"kernel": dom, "avg_launch_us": avg_s * 1e6, "share_of_step": ms / total}
+        if dom == "local_step":
+            flops = local_step_flops(data, work, launches)
+            achieved = flops / avg_s / 1e12
+            rl.update({"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFS,
+                       "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFS,
+                       "traffic": measured_traffic(dom, args.config, "pcg"),
+                       "flops_per_launch": flops,
+                       "cg_iterations_per_launch": float(work[:, 0].sum() / launches),
+                       "lm_solves_per_launch": float(work[:, 1].sum() / launches),
+                       "workgroups": P})
+        elif dom in ("refresh", "pack"):
+            nbytes = stream_bytes(dom, data, elt)
+            achieved = nbytes / avg_s / 1e9
+            rl.update({"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": measured_traffic(dom, args.config, "pcg")})
+        out["roofline"] = rl
+        # the HBM-streaming passes: the residual's energy at each local step, the interval's pack
+        for name in ("refresh", "pack"):
+            if kt[name][0]:
+                n, t_ms = kt[name]
+                out[f"{name}_pass_GBs"] = stream_bytes(name, data, elt) / (t_ms / n / 1e3) / 1e9
+        log(f"kernels: {out['kernel_ms_per_step']}")
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(data, args.cpu_sample_iters,
-                                           iters["plain"] or args.ref_iters, lm_iters,
-                                           args.lm_tol)
+        out["cpu_baseline"] = cpu_baseline(data, prev, args.cpu_sample_iters, n64, lm_iters,
+                                           args.lm_tol, args.cg_tol)
     ctx.close()
-    ctx0.close()
     ctx_id.close()
     net.close()
     if args.copy_calibration:

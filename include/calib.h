@@ -259,7 +259,9 @@ calib_status calib_set_data(calib_ctx *ctx, const void *vis, const void *coh);
 #define CALIB_KERNEL_LOCAL_STEP 8   /* solver 3: every subband's whole local step (LM runs with
                                        the matrix-free solve, stopping rule, SAGE commits) in one
                                        launch after the refresh                               */
-#define CALIB_NUM_KERNELS 9
+#define CALIB_KERNEL_PACK 9         /* calib_set_data: the interval's visibilities and coherency
+                                       statistics packed, and the dense S table rebuilt         */
+#define CALIB_NUM_KERNELS 10
 #define CALIB_FIELD_KERNEL_TIMES 9  /* host double [CALIB_NUM_KERNELS][2]: launches and total
                                        milliseconds since timing was enabled (synchronises)     */
 

@@ -20,7 +20,7 @@ OPT_UNREG_FIRST = 2
 (FIELD_J, FIELD_Z, FIELD_BZ, FIELD_Y, FIELD_MODEL_VIS, FIELD_COST, FIELD_TRACE, FIELD_LM_TRACE,
  FIELD_LM_STEP, FIELD_KERNEL_TIMES, FIELD_STATUS, FIELD_WORK) = range(12)
 KERNELS = ["refresh", "lm_begin", "assemble", "chol_solve", "trial", "lm_update", "commit",
-           "consensus", "local_step"]
+           "consensus", "local_step", "pack"]
 STATUS = {0: "CALIB_OK", 1: "CALIB_E_INVAL", 2: "CALIB_E_NOMEM", 3: "CALIB_E_DEVICE",
           4: "CALIB_E_RANK", 5: "CALIB_E_NUMERIC", 6: "CALIB_E_STATE"}
 EXPORTS = ["calib_init", "admm_local_step", "admm_consensus_update", "admm_solve", "calib_get",

@@ -814,14 +814,16 @@ calib_status calib_set_data(calib_ctx *ctx, const void *vis, const void *coh) {
   if (!vis || !coh) return fail(ctx, CALIB_E_INVAL, "vis and coh are required");
   hipStream_t s = ctx->stream;
   HIPCHK(ctx, launch_zero_int(ctx->B.status, ctx->P, s));
-  HIPCHK(ctx, ctx->precision == CALIB_FP64
-                  ? launch_pack_stats<double>(ctx->pb, ctx->L, ctx->B, vis, coh, ctx->Vp, ctx->Cp, ctx->Sb,
-                                              ctx->d_in_vis_off, ctx->d_in_coh_off, ctx->d_comp,
-                                              ctx->nb_total, nullptr, ctx->B.status, s)
-                  : launch_pack_stats<float>(ctx->pb, ctx->L, ctx->B, vis, coh, ctx->Vp, ctx->Cp, ctx->Sb,
-                                             ctx->d_in_vis_off, ctx->d_in_coh_off, ctx->d_comp,
-                                             ctx->nb_total, nullptr, ctx->B.status, s));
-  HIPCHK(ctx, launch_dense_s(ctx->pb, ctx->L, ctx->B, s));
+  HIPCHK(ctx, timed(ctx, CALIB_KERNEL_PACK, [&] {
+    hipError_t e = ctx->precision == CALIB_FP64
+        ? launch_pack_stats<double>(ctx->pb, ctx->L, ctx->B, vis, coh, ctx->Vp, ctx->Cp, ctx->Sb,
+                                    ctx->d_in_vis_off, ctx->d_in_coh_off, ctx->d_comp,
+                                    ctx->nb_total, nullptr, ctx->B.status, s)
+        : launch_pack_stats<float>(ctx->pb, ctx->L, ctx->B, vis, coh, ctx->Vp, ctx->Cp, ctx->Sb,
+                                   ctx->d_in_vis_off, ctx->d_in_coh_off, ctx->d_comp,
+                                   ctx->nb_total, nullptr, ctx->B.status, s);
+    return e == hipSuccess ? launch_dense_s(ctx->pb, ctx->L, ctx->B, s) : e;
+  }));
   ctx->iters_done = 0;
   return CALIB_OK;
 }

@@ -133,8 +133,15 @@ def stack_rows(intervals: List[Interval]):
     return np.ascontiguousarray(X[live]), np.ascontiguousarray(Y[live])
 
 
-def iters_to_target(trace: np.ndarray, target_cost: float, rel: float = 1e-6) -> Optional[int]:
-    """First ADMM iteration (1-based) whose data cost is within rel of target_cost."""
+def iters_to_target(trace: np.ndarray, target_cost: float, rel: float = 1e-6,
+                    primal_target: Optional[float] = None,
+                    primal_rel: float = 1e-3) -> Optional[int]:
+    """First ADMM iteration (1-based) whose data cost is within rel of target_cost and, when
+    primal_target is given, whose primal residual is at most (1 + primal_rel) primal_target (the
+    cost alone can pass through the target band while the subbands still disagree)."""
     g = trace[:, 0]
-    hit = np.nonzero(np.abs(g - target_cost) <= rel * abs(target_cost))[0]
+    ok = np.abs(g - target_cost) <= rel * abs(target_cost)
+    if primal_target is not None:
+        ok &= trace[:, 2] <= (1.0 + primal_rel) * primal_target
+    hit = np.nonzero(ok)[0]
     return int(hit[0]) + 1 if len(hit) else None
