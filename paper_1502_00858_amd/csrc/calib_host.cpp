@@ -478,6 +478,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   pb.group = group;
   pb.bpt = bpt;
   pb.nbt = nb_total;
+  pb.max_nb = P > 0 ? *std::max_element(nb.begin(), nb.end()) : 0;
   pb.stream_grid = cfg->stream_grid > 0 ? cfg->stream_grid : 0;
   pb.lm_tol = cfg->lm_tol;
   pb.solver = cfg->solver == 1 ? kSolverSingle

@@ -66,6 +66,7 @@ struct Problem {
   int group;       // lanes per baseline in the streaming kernels
   int bpt;         // baselines per tile = kBlock / group
   int nbt;         // unflagged baselines over all subbands
+  int max_nb;      // unflagged baselines of the fullest subband
   int stream_grid; // 0 = one workgroup per tile, else persistent grid size
   double lm_tol;   // LM stops once a step's predicted decrease <= lm_tol * F (0 = never)
   int solver;      // normal-equation solver: kSolverSingle, kSolverBlocked or kSolverPcg

@@ -232,85 +232,118 @@ hipError_t launch_energy(const Problem &pb, const Layout &L, const Buffers &B, h
 //   S_b,l = sum_s |c_ls|^2,   U_l = sum_s conj(c_ls) V_s,   X_lm = sum_s conj(c_ls) c_ms.
 // With the scalar coherency and J constant over a baseline's samples, everything the local steps
 // need from the samples besides the residual's energy follows from these: at a point with models
-// M_m, D_l = sum_s conj(c_ls) R_s = U_l - sum_m X_lm M_m.  One group of G lanes per compact
-// baseline; lane l of the group owns direction l's sums and walks the baseline's samples, all
-// lanes of a group reading the same V and coherencies (identical addresses within a request), so
-// the caller's arrays are read once; lane 0 stores the packed V and lane l the packed coherency of
-// direction l.  A non-finite input sets *bad (when given) and the subband's status word.
+// M_m, D_l = sum_s conj(c_ls) R_s = U_l - sum_m X_lm M_m.
+//
+// One workgroup per (run of TB = kBlock / G compact baselines, subband) walks the baselines'
+// samples in chunks of SC.  Per chunk the whole workgroup copies every baseline's V and coherency
+// rows of the chunk, one complex value per thread and step, consecutive threads on consecutive
+// addresses of the caller's arrays (each byte read once, in full cache lines), into LDS and into
+// the packed arrays; then group j of G lanes takes baseline j, lane l accumulating direction l's
+// sums from LDS (the group's lanes read the same words: broadcasts).  Rows are padded by 16 bytes
+// so that the groups of a wavefront hit different LDS banks.  A non-finite input sets *bad (when
+// given) and the subband's status word.
+template <typename T>
+struct Cplx;
+template <>
+struct Cplx<float> { using type = float2; };
+template <>
+struct Cplx<double> { using type = double2; };
+
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buffers B, const T *vis,
                                                        const T *coh, T *Vp, T *Cp, double *Sb,
                                                        const int64_t *in_vis_off,
                                                        const int64_t *in_coh_off,
-                                                       const int32_t *comp2full,
-                                                       const int32_t *comp_f, int nb_total, int *bad,
+                                                       const int32_t *comp2full, int *bad,
                                                        int *status) {
-  const int64_t gb = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / G;
-  const int l = threadIdx.x % G;
-  if (gb >= nb_total) return;   // whole groups
-  const int f = comp_f[gb];
-  const int bi = (int)(gb - L.bl_off[f]);
-  const int bfull = comp2full[gb];
-  const int spb = L.spb[f], nb = L.nb[f], Kf = L.ndir[f];
-  const int Bfull = pb.N * (pb.N - 1) / 2;
-  const T *vsrc = vis + 8 * (in_vis_off[f] + (int64_t)bfull * spb);
-  const T *csrc = coh + 2 * (in_coh_off[f] + (int64_t)bfull * spb);
-  const int64_t cs = 2 * (int64_t)Bfull * spb;   // between directions, caller's layout
-  T *vdst = Vp + 8 * (L.samp_off[f] + (int64_t)bi * spb);
-  T *cdst = Cp + 2 * (L.coh_off[f] + (int64_t)bi * spb);
-  const int64_t cd = 2 * (int64_t)nb * spb;      // between directions, packed layout
+  using C2 = typename Cplx<T>::type;
+  constexpr int TB = kBlock / G;                   // baselines per workgroup
+  constexpr int SC = 32 / (int)sizeof(T);          // samples per chunk
+  constexpr int PAD = 16 / (int)sizeof(T);
+  constexpr int VR = SC * 8 + PAD, CR = SC * 2 + PAD;   // padded LDS rows (elements)
+  __shared__ __align__(16) T Vs[TB * VR];
+  __shared__ __align__(16) T Cs[G * TB * CR];
+  __shared__ int bfull_s[TB];
+  const int f = blockIdx.y;
+  const int nb = L.nb[f];
+  const int bi0 = blockIdx.x * TB;
+  if (bi0 >= nb) return;                           // whole workgroup
+  const int nt = min(TB, nb - bi0);                // baselines of this workgroup
+  const int spb = L.spb[f], Kf = L.ndir[f];
+  const int64_t Bfull = (int64_t)pb.N * (pb.N - 1) / 2;
+  const int64_t gb0 = (int64_t)L.bl_off[f] + bi0;
+  if (threadIdx.x < nt) bfull_s[threadIdx.x] = comp2full[gb0 + threadIdx.x];
+  const int64_t ivo = in_vis_off[f], ico = in_coh_off[f];
+  const int64_t vso = L.samp_off[f], cso = L.coh_off[f];
+  const int j = threadIdx.x / G, l = threadIdx.x % G;
   double u[8] = {0, 0, 0, 0, 0, 0, 0, 0}, x[2 * G];
 #pragma unroll
   for (int m = 0; m < 2 * G; ++m) x[m] = 0.0;
   bool finite = true;
-  for (int s = 0; s < spb; ++s) {
-    T v[8];
-    load8<T>(vsrc + 8 * s, v);
-    double c[2 * G];
-#pragma unroll
-    for (int m = 0; m < G; ++m) {
-      c[2 * m] = 0.0;
-      c[2 * m + 1] = 0.0;
-      if (m < Kf) {
-        c[2 * m] = (double)csrc[m * cs + 2 * s];
-        c[2 * m + 1] = (double)csrc[m * cs + 2 * s + 1];
+  __syncthreads();
+  for (int s0 = 0; s0 < spb; s0 += SC) {
+    const int n = min(SC, spb - s0);
+    const int per = (4 + Kf) * n;                  // complex values per baseline in the chunk
+    for (int e = threadIdx.x; e < nt * per; e += kBlock) {
+      const int jj = e / per, r = e - jj * per;
+      const int64_t bf = bfull_s[jj], bi = bi0 + jj;
+      const C2 *src;
+      C2 *dst;
+      T *lds;
+      if (r < 4 * n) {                             // V: 4 complex values per sample
+        src = reinterpret_cast<const C2 *>(vis + 8 * (ivo + bf * spb + s0)) + r;
+        dst = reinterpret_cast<C2 *>(Vp + 8 * (vso + bi * spb + s0)) + r;
+        lds = Vs + jj * VR + 2 * r;
+      } else {                                     // direction m's coherency
+        const int r2 = r - 4 * n, m = r2 / n, t = r2 - m * n;
+        src = reinterpret_cast<const C2 *>(coh + 2 * (ico + (m * Bfull + bf) * spb + s0)) + t;
+        dst = reinterpret_cast<C2 *>(Cp + 2 * (cso + ((int64_t)m * nb + bi) * spb + s0)) + t;
+        lds = Cs + (m * TB + jj) * CR + 2 * t;
       }
+      const C2 val = *src;
+      finite &= isfinite(val.x) && isfinite(val.y);
+      *dst = val;
+      lds[0] = val.x;
+      lds[1] = val.y;
     }
-    if (l == 0) {
+    __syncthreads();
+    if (j < nt && l < Kf) {
+      for (int t = 0; t < n; ++t) {
+        double v[8], c[2 * G];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) finite &= isfinite((double)v[e]);
-      store8<T>(vdst + 8 * s, v);
-    }
-    if (l < Kf) {
-      double cr = 0.0, ci = 0.0;
+        for (int e = 0; e < 8; ++e) v[e] = (double)Vs[j * VR + 8 * t + e];
 #pragma unroll
-      for (int m = 0; m < G; ++m)
-        if (m == l) {
-          cr = c[2 * m];
-          ci = c[2 * m + 1];
+        for (int m = 0; m < G; ++m) {
+          c[2 * m] = m < Kf ? (double)Cs[(m * TB + j) * CR + 2 * t] : 0.0;
+          c[2 * m + 1] = m < Kf ? (double)Cs[(m * TB + j) * CR + 2 * t + 1] : 0.0;
         }
-      finite &= isfinite(cr) && isfinite(ci);
-      cdst[l * cd + 2 * s] = (T)cr;
-      cdst[l * cd + 2 * s + 1] = (T)ci;
+        double cr = 0.0, ci = 0.0;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const double vr = (double)v[2 * e], vi = (double)v[2 * e + 1];
-        u[2 * e] = fma(cr, vr, fma(ci, vi, u[2 * e]));
-        u[2 * e + 1] = fma(cr, vi, fma(-ci, vr, u[2 * e + 1]));
-      }
+        for (int m = 0; m < G; ++m)
+          if (m == l) {
+            cr = c[2 * m];
+            ci = c[2 * m + 1];
+          }
 #pragma unroll
-      for (int m = 0; m < G; ++m) {
-        x[2 * m] = fma(cr, c[2 * m], fma(ci, c[2 * m + 1], x[2 * m]));
-        x[2 * m + 1] = fma(cr, c[2 * m + 1], fma(-ci, c[2 * m], x[2 * m + 1]));
+        for (int e = 0; e < 4; ++e) {
+          u[2 * e] = fma(cr, v[2 * e], fma(ci, v[2 * e + 1], u[2 * e]));
+          u[2 * e + 1] = fma(cr, v[2 * e + 1], fma(-ci, v[2 * e], u[2 * e + 1]));
+        }
+#pragma unroll
+        for (int m = 0; m < G; ++m) {
+          x[2 * m] = fma(cr, c[2 * m], fma(ci, c[2 * m + 1], x[2 * m]));
+          x[2 * m + 1] = fma(cr, c[2 * m + 1], fma(-ci, c[2 * m], x[2 * m + 1]));
+        }
       }
     }
+    __syncthreads();
   }
   if (!finite) {
     if (bad) atomicOr(bad, 1);
     if (status) atomicOr(status + f, 5);   // CALIB_E_NUMERIC
   }
-  if (l >= Kf) return;
-  const int64_t nbt = pb.nbt;
+  if (j >= nt || l >= Kf) return;
+  const int64_t nbt = pb.nbt, gb = gb0 + j;
   double2 *U2 = reinterpret_cast<double2 *>(B.Ucoh + ((int64_t)l * nbt + gb) * 8);
 #pragma unroll
   for (int h = 0; h < 4; ++h) U2[h] = make_double2(u[2 * h], u[2 * h + 1]);
@@ -320,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
       double2 *X2 = reinterpret_cast<double2 *>(B.Xcoh + (((int64_t)l * pb.K + m) * nbt + gb) * 2);
       *X2 = m < Kf ? make_double2(x[2 * m], x[2 * m + 1]) : make_double2(0.0, 0.0);
     }
-  Sb[L.sb_off[f] + (int64_t)l * nb + bi] = x[2 * l];
+  Sb[L.sb_off[f] + (int64_t)l * nb + bi0 + j] = x[2 * l];
 }
 
 // Model visibilities in the caller's full layout (zero on flagged baselines).
@@ -400,17 +433,18 @@ hipError_t launch_pack_stats(const Problem &pb, const Layout &L, const Buffers &
                              const int32_t *comp_tab, int nb_total, int *bad, int *status,
                              hipStream_t s) {
   if (nb_total == 0) return hipSuccess;
-  // comp_tab: the full-layout baseline of each compact baseline, then its subband
+  if (pb.K > kMaxDirs || pb.max_nb <= 0) return hipErrorInvalidValue;
+  // comp_tab: the full-layout baseline of each compact baseline (then its subband, unused here)
   const T *v = static_cast<const T *>(vis), *c = static_cast<const T *>(coh);
   T *vp = static_cast<T *>(Vp), *cp = static_cast<T *>(Cp);
   if (pb.K <= 8) {
-    const unsigned grid = (unsigned)(((int64_t)nb_total * 8 + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_pack_stats<T, 8>), dim3(grid), dim3(kBlock), 0, s, pb, L, B, v, c, vp, cp, Sb,
-                       in_vis_off, in_coh_off, comp_tab, comp_tab + nb_total, nb_total, bad, status);
+    const dim3 grid((pb.max_nb + kBlock / 8 - 1) / (kBlock / 8), pb.P);
+    hipLaunchKernelGGL((k_pack_stats<T, 8>), grid, dim3(kBlock), 0, s, pb, L, B, v, c, vp, cp, Sb,
+                       in_vis_off, in_coh_off, comp_tab, bad, status);
   } else {
-    const unsigned grid = (unsigned)(((int64_t)nb_total * 16 + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_pack_stats<T, 16>), dim3(grid), dim3(kBlock), 0, s, pb, L, B, v, c, vp, cp, Sb,
-                       in_vis_off, in_coh_off, comp_tab, comp_tab + nb_total, nb_total, bad, status);
+    const dim3 grid((pb.max_nb + kBlock / 16 - 1) / (kBlock / 16), pb.P);
+    hipLaunchKernelGGL((k_pack_stats<T, 16>), grid, dim3(kBlock), 0, s, pb, L, B, v, c, vp, cp, Sb,
+                       in_vis_off, in_coh_off, comp_tab, bad, status);
   }
   return hipGetLastError();
 }

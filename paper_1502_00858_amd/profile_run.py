@@ -1,10 +1,12 @@
 """A short, fixed run of the C-ADMM iteration for hardware-counter profiling.
 
-    python -m paper_1502_00858_amd.profile_run --config c2 --iters 2 [--solver 2] [--lm-tol 0]
+    python -m paper_1502_00858_amd.profile_run --config c2 --iters 2 [--solver 3 --cg-tol 1e-4]
+        [--lm-tol 1e-7] [--set-data]
 
 Solves the named synthetic workload from identity Jones matrices for a few ADMM iterations (every
-LM launch full unless --lm-tol is given), then copies 256 MiB between two device buffers once: the
-copy's FETCH_SIZE / WRITE_SIZE readings calibrate the counters to bytes.  Prints what ran.
+LM launch full unless --lm-tol is given), optionally after loading the same data again as a new
+solution interval (calib_set_data), then copies 256 MiB between two device buffers once: the copy's
+FETCH_SIZE / WRITE_SIZE readings calibrate the counters to bytes.  Prints what ran.
 """
 from __future__ import annotations
 
@@ -18,6 +20,8 @@ def main():
     ap.add_argument("--iters", type=int, default=2)
     ap.add_argument("--solver", type=int, default=0)
     ap.add_argument("--lm-tol", type=float, default=0.0)
+    ap.add_argument("--cg-tol", type=float, default=0.0)
+    ap.add_argument("--set-data", action="store_true")
     ap.add_argument("--fp64", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     args = ap.parse_args()
@@ -29,9 +33,11 @@ def main():
     prec = calib.CALIB_FP64 if args.fp64 else calib.CALIB_FP32_MIXED
     vis, coh, flags = calib.device_inputs(data, prec)
     ctx = calib.Calib(data, vis, coh, flags, precision=prec, solver=args.solver,
-                      lm_tol=args.lm_tol)
+                      lm_tol=args.lm_tol, cg_tol=args.cg_tol)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    if args.set_data:
+        ctx.set_data(vis, coh)
     tr = ctx.solve(args.iters)
     torch.cuda.synchronize()
     print(f"{args.config}: {args.iters} ADMM iterations in {time.perf_counter() - t0:.3f} s, "
