@@ -18,11 +18,11 @@
 // and the preconditioner of stations p = l + 64 s (s < SPL), so every dot product is a wavefront
 // sum and the CG recurrences need no barrier.  The table products are split by columns: wavefront
 // w takes stations q in [w C, w C + C), C = ceil(N / 4), keeps S_pq of those columns for its rows
-// p = l + 64 s in registers for the whole solve (read coalesced through the symmetry of S),
-// broadcasts each column's u_q = d_q^H J_q (loaded by lane q - w C) to the wavefront with
-// readlane, and leaves its partial sums in LDS, which wavefront 0 adds in a fixed order.  One CG
-// iteration: wavefront 0 writes u | all wavefronts their partial W | wavefront 0 finishes H d and
-// the recurrences.
+// p = l + 64 s in registers for the whole solve (read coalesced through the symmetry of S), reads
+// each column's u_q = d_q^H J_q from LDS (every lane the same words: a broadcast) and leaves its
+// partial sums in LDS, component-major so that lanes touch consecutive words, which wavefront 0
+// adds in a fixed order.  One CG iteration: wavefront 0 writes u | all wavefronts their partial W
+// | wavefront 0 finishes H d and the recurrences.
 #include "calib_internal.h"
 #include "lm_device.h"
 #include "wave_reduce.h"
@@ -32,12 +32,6 @@ namespace {
 
 constexpr int kPcgThreads = 256;
 constexpr int kPcgWaves = kPcgThreads / 64;
-
-__device__ inline double bcast(double x, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
-  return __hiloint2double(hi, lo);
-}
 
 // c = a b for 2x2 complex matrices (8 doubles, row-major re/im)
 __device__ inline void cmul(const double *a, const double *b, double *c) {
@@ -103,7 +97,8 @@ template <int SPL>
 struct PcgLds {
   double Js[64 * SPL * 8];                  // J of the direction
   double Us[64 * SPL * 8];                  // u_q = d_q^H J_q
-  double Wp[kPcgWaves][64 * SPL][8];        // per-wavefront partials over its columns
+  double Wp[kPcgWaves][8][64 * SPL];        // per-wavefront partials over its columns,
+                                            // component-major (lane-consecutive, no bank conflicts)
   int ctl[2];                               // continue, failed
 };
 
@@ -120,7 +115,7 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
   auto &Wp = sh.Wp;
   int *ctl = sh.ctl;
   const int N = pb.N, nf = pb.nf;
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int C = (N + kPcgWaves - 1) / kPcgWaves, c0 = w * C;
   LmState *st = B.lm + f;
   const double lam = st->lambda;
@@ -193,7 +188,7 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
       const int p = lane + 64 * s, q = c0 + j;
       S[s][j] = (p < N && j < C && q < N) ? Sd[(int64_t)q * N + p] : 0.0;
     }
-  for (int e = threadIdx.x; e < 8 * N; e += kPcgThreads) Js[e] = Jg[e];
+  for (int e = threadIdx.x; e < 8 * kRows; e += kPcgThreads) Js[e] = e < 8 * N ? Jg[e] : 0.0;
   __syncthreads();
 
   // the rest of the gradient, the next batch in flight while the current one is used (and,
@@ -216,10 +211,9 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
     }
   };
   advance();
-  // Q_p partials: column lane j holds J_q^H J_q of q = c0 + j, broadcast to the wavefront
+  // Q_p partials over this wavefront's columns: J_q^H J_q of column q = c0 + j from LDS (the
+  // same words for every lane: broadcast reads); columns past N have S = 0
   {
-    double vq[4] = {0.0, 0.0, 0.0, 0.0};
-    if (lane < C && c0 + lane < N) gram(Js + 8 * (c0 + lane), vq);
     double qp[SPL][4];
 #pragma unroll
     for (int s = 0; s < SPL; ++s)
@@ -227,17 +221,17 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
       for (int c = 0; c < 4; ++c) qp[s][c] = 0.0;
 #pragma unroll
     for (int j = 0; j < kC; ++j) {
+      double vq[4];
+      gram(Js + 8 * (c0 + j), vq);   // past N: zeros; past this wavefront's columns: S = 0
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const double v = bcast(vq[c], j);
+      for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int s = 0; s < SPL; ++s) qp[s][c] = fma(S[s][j], v, qp[s][c]);
-      }
+        for (int s = 0; s < SPL; ++s) qp[s][c] = fma(S[s][j], vq[c], qp[s][c]);
     }
 #pragma unroll
     for (int s = 0; s < SPL; ++s)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) Wp[w][lane + 64 * s][c] = qp[s][c];
+      for (int c = 0; c < 4; ++c) Wp[w][c][lane + 64 * s] = qp[s][c];
   }
   while (more) advance();
   __syncthreads();   // Q partials in Wp
@@ -249,7 +243,7 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
       for (int c = 0; c < 4; ++c) {
         double v = 0.0;
 #pragma unroll
-        for (int i = 0; i < kPcgWaves; ++i) v += Wp[i][lane + 64 * s][c];
+        for (int i = 0; i < kPcgWaves; ++i) v += Wp[i][c][lane + 64 * s];
         Qp[s][c] = v;
       }
     }
@@ -258,7 +252,7 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
 #pragma unroll
   for (int s = 0; s < SPL; ++s)
 #pragma unroll
-    for (int e = 0; e < 8; ++e) Wp[w][lane + 64 * s][e] = gp[s][e];
+    for (int e = 0; e < 8; ++e) Wp[w][e][lane + 64 * s] = gp[s][e];
   __syncthreads();
 
   // wavefront 0: right-hand side b = -G, preconditioner (2 Q_p + mu I)^-1, x = 0, r = b, d = z
@@ -275,7 +269,7 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
       for (int e = 0; e < 8; ++e) {
         double v = 0.0;
 #pragma unroll
-        for (int i = 0; i < kPcgWaves; ++i) v += Wp[i][p][e];
+        for (int i = 0; i < kPcgWaves; ++i) v += Wp[i][e][p];
         if (live && !unreg) v += B.Y[jo + 8 * p + e] + rho * (Js[8 * p + e] - B.BZ[jo + 8 * p + e]);
         g[s][e] = live ? v : 0.0;
         Jp[s][e] = live ? Js[8 * p + e] : 0.0;
@@ -323,17 +317,9 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
     __syncthreads();
     if (!ctl[0]) break;
     ++iters_run;
-    // partial W_p over this wavefront's columns: lane j loads u of column c0 + j
+    // partial W_p over this wavefront's columns: u of column c0 + j read from LDS by every lane
+    // (broadcast)
     {
-      double uq[8];
-      const int q = min(c0 + lane, kRows - 1);
-      const double2 *u2 = reinterpret_cast<const double2 *>(Us + 8 * q);
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const double2 t = u2[h];
-        uq[2 * h] = t.x;
-        uq[2 * h + 1] = t.y;
-      }
       double W[SPL][8];
 #pragma unroll
       for (int s = 0; s < SPL; ++s)
@@ -341,19 +327,24 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
         for (int e = 0; e < 8; ++e) W[s][e] = 0.0;
 #pragma unroll
       for (int j = 0; j < kC; ++j) {
+        // past N: zeros; past this wavefront's columns: S = 0
+        const double2 *u2 = reinterpret_cast<const double2 *>(Us + 8 * (c0 + j));
+        double uq[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const double v = bcast(uq[e], j);
-#pragma unroll
-          for (int s = 0; s < SPL; ++s) W[s][e] = fma(S[s][j], v, W[s][e]);
+        for (int h = 0; h < 4; ++h) {
+          const double2 t = u2[h];
+          uq[2 * h] = t.x;
+          uq[2 * h + 1] = t.y;
         }
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+#pragma unroll
+          for (int s = 0; s < SPL; ++s) W[s][e] = fma(S[s][j], uq[e], W[s][e]);
       }
 #pragma unroll
-      for (int s = 0; s < SPL; ++s) {
-        double2 *w2 = reinterpret_cast<double2 *>(&Wp[w][lane + 64 * s][0]);
+      for (int s = 0; s < SPL; ++s)
 #pragma unroll
-        for (int h = 0; h < 4; ++h) w2[h] = make_double2(W[s][2 * h], W[s][2 * h + 1]);
-      }
+        for (int e = 0; e < 8; ++e) Wp[w][e][lane + 64 * s] = W[s][e];
     }
     __syncthreads();
     if (w != 0) continue;
@@ -364,15 +355,9 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
       const int p = lane + 64 * s;
       double W[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-      for (int i = 0; i < kPcgWaves; ++i) {
-        const double2 *w2 = reinterpret_cast<const double2 *>(&Wp[i][p][0]);
+      for (int i = 0; i < kPcgWaves; ++i)
 #pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          const double2 t = w2[h];
-          W[2 * h] += t.x;
-          W[2 * h + 1] += t.y;
-        }
-      }
+        for (int e = 0; e < 8; ++e) W[e] += Wp[i][e][p];
       double t1[8], t2[8];
       hmul(dv[s], Qp[s], t1);
       cmul(Jp[s], W, t2);
@@ -445,12 +430,29 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
   }
 }
 
-// Per-baseline passes of the one-workgroup local step.  A subband's baselines are spread over all
-// threads, kU at a time per thread with every load of a round issued together (a single workgroup
-// has only its own loads in flight, so each round pays one memory latency), the Jones matrices
-// read from LDS.  Their energy partials are summed over the workgroup and kept in the subband's
-// first tile (the objective adds the tiles of a subband).
-constexpr int kU = 8;   // baselines per thread per round
+// Per-baseline passes of the one-workgroup local step.  Four lanes share a baseline, lane h
+// holding complex entry h = (i, j) of its 2x2 matrices (D_b, M = J_p J_q^H), so that the
+// wavefront's loads and stores of D_b cover 16 consecutive baselines (1 KiB, whole cache lines)
+// per instruction; 64 baselines per round of the workgroup, kU rounds with every load issued
+// together (a single workgroup has only its own loads in flight, so each batch pays one memory
+// latency).  The Jones matrices are read from LDS.  Energy partials are summed over the workgroup
+// and kept in the subband's first tile (the objective adds the tiles of a subband).
+constexpr int kQuad = 4;                    // lanes per baseline
+constexpr int kBpr = kBlock / kQuad;        // baselines per round
+constexpr int kU = 8;                       // rounds per batch
+
+// entry (i, j) of a_p a_q^H for the stations' 2x2 complex matrices in LDS (8 doubles each)
+__device__ inline double2 jjh_entry(const double *A, int p, int q, int i, int j) {
+  const double *a = A + 8 * p + 4 * i, *b = A + 8 * q + 4 * j;
+  double re = 0.0, im = 0.0;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const double ar = a[2 * t], ai = a[2 * t + 1], br = b[2 * t], bi = b[2 * t + 1];
+    re += ar * br + ai * bi;
+    im += ai * br - ar * bi;
+  }
+  return make_double2(re, im);
+}
 
 // Data cost and D_b at the trial point Jt from the start point J0's statistics (lmd::trial_tile)
 __device__ inline void fused_trial(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
@@ -458,46 +460,33 @@ __device__ inline void fused_trial(const Problem &pb, const Layout &L, const Buf
   const int nb = L.nb[f];
   const int64_t b0 = L.bl_off[f];
   const double *Sb = B.Sb + L.sb_off[f] + (int64_t)k * nb;
-  double *Dt = d_trial(B, f);
+  double2 *Dt = reinterpret_cast<double2 *>(d_trial(B, f));
+  const double2 *D0 = reinterpret_cast<const double2 *>(B.Dstart);
+  const int h = threadIdx.x & 3, ei = h >> 1, ej = h & 1, sub = threadIdx.x >> 2;
   double part = 0.0;
-  for (int base = 0; base < nb; base += kBlock * kU) {
+  for (int base = 0; base < nb; base += kBpr * kU) {
     int p[kU], q[kU];
-    double S[kU], d0[kU][8];
+    double S[kU];
+    double2 d0[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const int bi = base + threadIdx.x + kBlock * u;
+      const int bi = base + sub + kBpr * u;
       if (bi < nb) {
         const int64_t gb = b0 + bi;
         p[u] = L.bl_p[gb];
         q[u] = L.bl_q[gb];
         S[u] = Sb[bi];
-        const double2 *D2 = reinterpret_cast<const double2 *>(B.Dstart + 8 * gb);
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          const double2 x = D2[h];
-          d0[u][2 * h] = x.x;
-          d0[u][2 * h + 1] = x.y;
-        }
+        d0[u] = D0[4 * gb + h];
       }
     }
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const int bi = base + threadIdx.x + kBlock * u;
+      const int bi = base + sub + kBpr * u;
       if (bi >= nb) continue;
-      double m1[8], m0[8], dt[8];
-      lmd::jjh(Jt + 8 * p[u], Jt + 8 * q[u], m1);
-      lmd::jjh(J0 + 8 * p[u], J0 + 8 * q[u], m0);
-      double cross = 0.0, norm = 0.0;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const double dm = m1[e] - m0[e];
-        cross = fma(dm, d0[u][e], cross);
-        norm = fma(dm, dm, norm);
-        dt[e] = fma(-S[u], dm, d0[u][e]);
-      }
-      double2 *T2 = reinterpret_cast<double2 *>(Dt + 8 * (b0 + bi));
-#pragma unroll
-      for (int h = 0; h < 4; ++h) T2[h] = make_double2(dt[2 * h], dt[2 * h + 1]);
+      const double2 m1 = jjh_entry(Jt, p[u], q[u], ei, ej), m0 = jjh_entry(J0, p[u], q[u], ei, ej);
+      const double dr = m1.x - m0.x, di = m1.y - m0.y;
+      const double cross = fma(dr, d0[u].x, di * d0[u].y), norm = fma(dr, dr, di * di);
+      Dt[4 * (b0 + bi) + h] = make_double2(fma(-S[u], dr, d0[u].x), fma(-S[u], di, d0[u].y));
       part += fma(S[u], norm, -2.0 * cross);
     }
   }
@@ -508,73 +497,73 @@ __device__ inline void fused_trial(const Problem &pb, const Layout &L, const Buf
     B.cost_part[t] = t == t0 ? v[0] + B.lm[f].E0 : 0.0;
 }
 
-// SAGE commit of direction k (lmd::commit_tile): every direction l from l0 updates
-// D_l -= X_lk dM for all baselines, one direction per round; the energy changes by
-// sum_b X_kk ||dM||^2 - 2 Re <dM, D_k>.  J1 (the run's final J) and J0 (its start) in LDS.
+// SAGE commit of direction k (lmd::commit_tile): with dM = J1_p J1_q^H - J0_p J0_q^H (J1 the run's
+// final J, J0 its start, both in LDS), every direction l from l0 updates D_l -= X_lk dM and the
+// energy changes by sum_b X_kk ||dM||^2 - 2 Re <dM, D_k>.  dM is formed once per baseline; the
+// directions are walked with the next one's D_l and X_lk requested before the current one's are
+// stored.
 __device__ inline void fused_commit(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
                                     int all, const double *J1, const double *J0,
                                     double (*red)[kBlock / 64]) {
   const int Kf = L.ndir[f], nb = L.nb[f], K = pb.K, next = k + 1 < Kf ? k + 1 : 0;
   const int64_t b0 = L.bl_off[f], nbt = pb.nbt;
   const int l0 = all ? 0 : k;
+  const int h = threadIdx.x & 3, ei = h >> 1, ej = h & 1, sub = threadIdx.x >> 2;
+  double2 *Dall = reinterpret_cast<double2 *>(B.Dall);
+  const double2 *X = reinterpret_cast<const double2 *>(B.Xcoh);
+  double2 *Da = reinterpret_cast<double2 *>(d_accepted(B, f));
+  double2 *Ds = reinterpret_cast<double2 *>(B.Dstart);
   double part = 0.0;
-  for (int l = l0; l < Kf; ++l) {
-    const bool upd = all || l > k;
-    if (!upd && l != k) continue;
-    for (int base = 0; base < nb; base += kBlock * kU) {
-      int p[kU], q[kU];
-      double d[kU][8], x[kU][2];
+  for (int base = 0; base < nb; base += kBpr * kU) {
+    double2 dm[kU], dn[kU], xn[kU];
+    auto request = [&](int l) {
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        const int bi = base + threadIdx.x + kBlock * u;
+        const int bi = base + sub + kBpr * u;
         if (bi < nb) {
           const int64_t gb = b0 + bi;
-          p[u] = L.bl_p[gb];
-          q[u] = L.bl_q[gb];
-          const double2 *D2 = reinterpret_cast<const double2 *>(B.Dall + ((int64_t)l * nbt + gb) * 8);
-#pragma unroll
-          for (int h = 0; h < 4; ++h) {
-            const double2 t = D2[h];
-            d[u][2 * h] = t.x;
-            d[u][2 * h + 1] = t.y;
-          }
-          const double2 X = *reinterpret_cast<const double2 *>(B.Xcoh + (((int64_t)l * K + k) * nbt + gb) * 2);
-          x[u][0] = X.x;
-          x[u][1] = X.y;
+          dn[u] = Dall[4 * ((int64_t)l * nbt + gb) + h];
+          xn[u] = X[((int64_t)l * K + k) * nbt + gb];
         }
       }
+    };
+    request(l0);
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int bi = base + sub + kBpr * u;
+      if (bi < nb) {
+        const int64_t gb = b0 + bi;
+        const int p = L.bl_p[gb], q = L.bl_q[gb];
+        const double2 m1 = jjh_entry(J1, p, q, ei, ej), m0 = jjh_entry(J0, p, q, ei, ej);
+        dm[u] = make_double2(m1.x - m0.x, m1.y - m0.y);
+      }
+    }
+    for (int l = l0; l < Kf; ++l) {
+      double2 d[kU], x[kU];
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        const int bi = base + threadIdx.x + kBlock * u;
+        d[u] = dn[u];
+        x[u] = xn[u];
+      }
+      if (l + 1 < Kf) request(l + 1);
+      const bool upd = all || l > k;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int bi = base + sub + kBpr * u;
         if (bi >= nb) continue;
         const int64_t gb = b0 + bi;
-        double m1[8], m0[8], dm[8];
-        lmd::jjh(J1 + 8 * p[u], J1 + 8 * q[u], m1);
-        lmd::jjh(J0 + 8 * p[u], J0 + 8 * q[u], m0);
-#pragma unroll
-        for (int e = 0; e < 8; ++e) dm[e] = m1[e] - m0[e];
         if (l == k) {
-          double cross = 0.0, norm = 0.0;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            cross = fma(dm[e], d[u][e], cross);
-            norm = fma(dm[e], dm[e], norm);
-          }
-          part += fma(x[u][0], norm, -2.0 * cross);
+          const double cross = fma(dm[u].x, d[u].x, dm[u].y * d[u].y);
+          const double norm = fma(dm[u].x, dm[u].x, dm[u].y * dm[u].y);
+          part += fma(x[u].x, norm, -2.0 * cross);
         }
         if (upd) {
-          lmd::sub_scaled(d[u], x[u][0], x[u][1], dm);
-          double2 *D2 = reinterpret_cast<double2 *>(B.Dall + ((int64_t)l * nbt + gb) * 8);
-#pragma unroll
-          for (int h = 0; h < 4; ++h) D2[h] = make_double2(d[u][2 * h], d[u][2 * h + 1]);
+          const double2 t = make_double2(d[u].x - (x[u].x * dm[u].x - x[u].y * dm[u].y),
+                                         d[u].y - (x[u].x * dm[u].y + x[u].y * dm[u].x));
+          Dall[4 * ((int64_t)l * nbt + gb) + h] = t;
           if (l == next) {
-            double2 *A2 = reinterpret_cast<double2 *>(d_accepted(B, f) + 8 * gb);
-            double2 *S2 = reinterpret_cast<double2 *>(B.Dstart + 8 * gb);
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-              A2[h] = make_double2(d[u][2 * h], d[u][2 * h + 1]);
-              S2[h] = make_double2(d[u][2 * h], d[u][2 * h + 1]);
-            }
+            Da[4 * gb + h] = t;
+            Ds[4 * gb + h] = t;
           }
         }
       }
