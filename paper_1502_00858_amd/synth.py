@@ -60,6 +60,9 @@ class SynthConfig:
     lm_box: float = 0.05                     # |l|,|m| bound of the sources (rad)
     flux_range: tuple = (1.0, 20.0)
     config_index: int = 0
+    # each subband's noise from its own stream seeded by (seed[, interval], subband), so that the
+    # subbands can be simulated in parallel threads (the large array); False: one stream for all
+    noise_per_subband: bool = False
 
     @property
     def B(self) -> int:
@@ -80,7 +83,7 @@ def named_config(name: str) -> SynthConfig:
                            config_index=3)
     if name == "c5":   # large array
         return SynthConfig("c5", N=128, P=64, Q=6, K=10, T=20, n_chan=8, rho=5.0,
-                           admm_iters=30, lm_iters=10, config_index=5)
+                           admm_iters=30, lm_iters=10, config_index=5, noise_per_subband=True)
     raise KeyError(name)
 
 
@@ -190,7 +193,7 @@ def generate(cfg: SynthConfig, seed: Optional[int] = None, episode: int = 0,
     noise_power = np.zeros(P)
     nrng = rng if interval is None else np.random.default_rng([seed, interval])
 
-    for f in range(P):
+    def subband(f, frng):
         nch = int(n_chan[f])
         Kf = int(n_dirs[f])
         fch = freq[f] + (np.arange(nch) - (nch - 1) / 2.0) * CHAN_WIDTH_HZ   # [nch]
@@ -209,13 +212,23 @@ def generate(cfg: SynthConfig, seed: Optional[int] = None, episode: int = 0,
             live = flags[f] == 0
             spow = np.mean(np.abs(sig[live]) ** 2) if live.any() else 0.0
             npow = spow / cfg.snr                    # per complex entry
-            noise = (nrng.normal(0, np.sqrt(npow / 2), sig.shape)
-                     + 1j * nrng.normal(0, np.sqrt(npow / 2), sig.shape))
+            noise = (frng.normal(0, np.sqrt(npow / 2), sig.shape)
+                     + 1j * frng.normal(0, np.sqrt(npow / 2), sig.shape))
             noise[flags[f] == 1] = 0.0
             sig = sig + noise
             noise_power[f] = npow
         vis[vis_off[f]:vis_off[f + 1]] = sig.reshape(-1, 2, 2)
         coh[coh_off[f]:coh_off[f + 1]] = c.reshape(-1)
+
+    if cfg.noise_per_subband:
+        import concurrent.futures
+        import os
+        key = [seed] if interval is None else [seed, interval]
+        with concurrent.futures.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+            list(ex.map(lambda f: subband(f, np.random.default_rng(key + [1000003, f])), range(P)))
+    else:
+        for f in range(P):
+            subband(f, nrng)
 
     return dict(
         name=cfg.name, N=N, P=P, Q=cfg.Q, K=K, T=T, B=B,
