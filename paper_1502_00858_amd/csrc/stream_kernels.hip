@@ -112,17 +112,25 @@ __device__ inline void stream_tile(const Problem &pb, const Layout &L, const Buf
   double cost = 0.0;
   if (live) {
     const T *V = static_cast<const T *>(B.V);
+    const T *Cb = C + 2 * (L.coh_off[f] + (int64_t)bi * spb);
+    const int64_t cstride = 2 * (int64_t)nb * spb;   // between directions
     for (int s = lane; s < spb; s += G) {
-      T r[8];
+      T r[8], c[kMaxDirs][2];
       load8<T>(V + 8 * (s0 + s), r);
-      for (int l = 0; l < Kf; ++l) {
-        T cr, ci;
-        load2<T>(C + 2 * (L.coh_off[f] + ((int64_t)l * nb + bi) * spb + s), cr, ci);
+      // every direction's coherency requested before the first is used
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const T mr = Msh[grp][l][2 * e], mi = Msh[grp][l][2 * e + 1];
-          r[2 * e] -= cr * mr - ci * mi;
-          r[2 * e + 1] -= cr * mi + ci * mr;
+      for (int l = 0; l < kMaxDirs; ++l)
+        if (l < Kf) load2<T>(Cb + l * cstride + 2 * s, c[l][0], c[l][1]);
+#pragma unroll
+      for (int l = 0; l < kMaxDirs; ++l) {
+        if (l < Kf) {
+          const T cr = c[l][0], ci = c[l][1];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const T mr = Msh[grp][l][2 * e], mi = Msh[grp][l][2 * e + 1];
+            r[2 * e] -= cr * mr - ci * mi;
+            r[2 * e + 1] -= cr * mi + ci * mr;
+          }
         }
       }
       T ss = 0;
@@ -234,20 +242,30 @@ hipError_t launch_energy(const Problem &pb, const Layout &L, const Buffers &B, h
 // need from the samples besides the residual's energy follows from these: at a point with models
 // M_m, D_l = sum_s conj(c_ls) R_s = U_l - sum_m X_lm M_m.
 //
-// One workgroup per (run of TB = kBlock / G compact baselines, subband) walks the baselines'
-// samples in chunks of SC.  Per chunk the whole workgroup copies every baseline's V and coherency
-// rows of the chunk, one complex value per thread and step, consecutive threads on consecutive
-// addresses of the caller's arrays (each byte read once, in full cache lines), into LDS and into
-// the packed arrays; then group j of G lanes takes baseline j, lane l accumulating direction l's
-// sums from LDS (the group's lanes read the same words: broadcasts).  Rows are padded by 16 bytes
-// so that the groups of a wavefront hit different LDS banks.  A non-finite input sets *bad (when
-// given) and the subband's status word.
+// One workgroup per (run of TB = kBlock / G compact baselines, subband); group j of G lanes (one
+// wavefront holds 64 / G groups) takes baseline j and walks its samples in chunks of SC.  Per chunk
+// the group copies the baseline's V and coherency rows of the chunk, lane l taking elements
+// l, l + G, ... of each row, so that consecutive lanes read consecutive complex values of the
+// caller's arrays (each byte read once, in full cache lines per wavefront request), every load of
+// the chunk issued before the first is used, into LDS and into the packed arrays; then lane l
+// accumulates direction l's sums from LDS (the group's lanes read the same words: broadcasts).
+// Only the group's own lanes exchange data through LDS, so the wavefronts never wait for each
+// other.  Rows are padded by 16 bytes so that the groups of a wavefront hit different LDS banks.
+// A non-finite input sets *bad (when given) and the subband's status word.
 template <typename T>
 struct Cplx;
 template <>
 struct Cplx<float> { using type = float2; };
 template <>
 struct Cplx<double> { using type = double2; };
+
+// ordering of LDS writes and reads among the lanes of one wavefront (in-order within a wavefront;
+// the fences keep the compiler from moving accesses across)
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buffers B, const T *vis,
@@ -261,89 +279,98 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
   constexpr int SC = 32 / (int)sizeof(T);          // samples per chunk
   constexpr int PAD = 16 / (int)sizeof(T);
   constexpr int VR = SC * 8 + PAD, CR = SC * 2 + PAD;   // padded LDS rows (elements)
+  constexpr int NV = 4 * SC / G;                   // V values per lane per chunk
+  constexpr int NC = SC;                           // coherency values per lane per chunk (G*SC >= K_f*SC)
+  static_assert(NV >= 1 && 4 * SC == NV * G, "chunk of V split evenly over the group");
   __shared__ __align__(16) T Vs[TB * VR];
   __shared__ __align__(16) T Cs[G * TB * CR];
-  __shared__ int bfull_s[TB];
   const int f = blockIdx.y;
   const int nb = L.nb[f];
   const int bi0 = blockIdx.x * TB;
   if (bi0 >= nb) return;                           // whole workgroup
-  const int nt = min(TB, nb - bi0);                // baselines of this workgroup
+  const int j = threadIdx.x / G, l = threadIdx.x % G;
+  const int bi = bi0 + j;
+  if (bi >= nb) return;                            // whole group (no workgroup barrier below)
   const int spb = L.spb[f], Kf = L.ndir[f];
   const int64_t Bfull = (int64_t)pb.N * (pb.N - 1) / 2;
-  const int64_t gb0 = (int64_t)L.bl_off[f] + bi0;
-  if (threadIdx.x < nt) bfull_s[threadIdx.x] = comp2full[gb0 + threadIdx.x];
-  const int64_t ivo = in_vis_off[f], ico = in_coh_off[f];
-  const int64_t vso = L.samp_off[f], cso = L.coh_off[f];
-  const int j = threadIdx.x / G, l = threadIdx.x % G;
-  double u[8] = {0, 0, 0, 0, 0, 0, 0, 0}, x[2 * G];
+  const int64_t gb = (int64_t)L.bl_off[f] + bi;
+  const int64_t bf = comp2full[gb];
+  const C2 *vsrc = reinterpret_cast<const C2 *>(vis + 8 * (in_vis_off[f] + bf * spb));
+  const C2 *csrc = reinterpret_cast<const C2 *>(coh + 2 * (in_coh_off[f] + bf * spb));
+  C2 *vdst = reinterpret_cast<C2 *>(Vp + 8 * (L.samp_off[f] + (int64_t)bi * spb));
+  C2 *cdst = reinterpret_cast<C2 *>(Cp + 2 * (L.coh_off[f] + (int64_t)bi * spb));
+  const int64_t cs = Bfull * spb, cd = (int64_t)nb * spb;   // between directions (complex values)
+  T *vl = Vs + j * VR;
+  double u[8] = {0, 0, 0, 0, 0, 0, 0, 0}, x[2 * G], sbl = 0.0;
 #pragma unroll
   for (int m = 0; m < 2 * G; ++m) x[m] = 0.0;
   bool finite = true;
-  __syncthreads();
   for (int s0 = 0; s0 < spb; s0 += SC) {
     const int n = min(SC, spb - s0);
-    const int per = (4 + Kf) * n;                  // complex values per baseline in the chunk
-    for (int e = threadIdx.x; e < nt * per; e += kBlock) {
-      const int jj = e / per, r = e - jj * per;
-      const int64_t bf = bfull_s[jj], bi = bi0 + jj;
-      const C2 *src;
-      C2 *dst;
-      T *lds;
-      if (r < 4 * n) {                             // V: 4 complex values per sample
-        src = reinterpret_cast<const C2 *>(vis + 8 * (ivo + bf * spb + s0)) + r;
-        dst = reinterpret_cast<C2 *>(Vp + 8 * (vso + bi * spb + s0)) + r;
-        lds = Vs + jj * VR + 2 * r;
-      } else {                                     // direction m's coherency
-        const int r2 = r - 4 * n, m = r2 / n, t = r2 - m * n;
-        src = reinterpret_cast<const C2 *>(coh + 2 * (ico + (m * Bfull + bf) * spb + s0)) + t;
-        dst = reinterpret_cast<C2 *>(Cp + 2 * (cso + ((int64_t)m * nb + bi) * spb + s0)) + t;
-        lds = Cs + (m * TB + jj) * CR + 2 * t;
-      }
-      const C2 val = *src;
-      finite &= isfinite(val.x) && isfinite(val.y);
-      *dst = val;
-      lds[0] = val.x;
-      lds[1] = val.y;
+    C2 v[NV], c[NC];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int e = l + G * i;                     // complex value e of the chunk's V row
+      if (e < 4 * n) v[i] = vsrc[4 * s0 + e];
     }
-    __syncthreads();
-    if (j < nt && l < Kf) {
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      const int e = l + G * i, m = e / SC, t = e % SC;
+      if (m < Kf && t < n) c[i] = csrc[m * cs + s0 + t];
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const int e = l + G * i;
+      if (e < 4 * n) {
+        finite &= isfinite(v[i].x) && isfinite(v[i].y);
+        vdst[4 * s0 + e] = v[i];
+        vl[2 * e] = v[i].x;
+        vl[2 * e + 1] = v[i].y;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      const int e = l + G * i, m = e / SC, t = e % SC;
+      if (m < Kf && t < n) {
+        finite &= isfinite(c[i].x) && isfinite(c[i].y);
+        cdst[m * cd + s0 + t] = c[i];
+        T *cl = Cs + (m * TB + j) * CR + 2 * t;
+        cl[0] = c[i].x;
+        cl[1] = c[i].y;
+      }
+    }
+    wave_lds_sync();
+    if (l < Kf) {
       for (int t = 0; t < n; ++t) {
-        double v[8], c[2 * G];
+        double vv[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = (double)Vs[j * VR + 8 * t + e];
-#pragma unroll
-        for (int m = 0; m < G; ++m) {
-          c[2 * m] = m < Kf ? (double)Cs[(m * TB + j) * CR + 2 * t] : 0.0;
-          c[2 * m + 1] = m < Kf ? (double)Cs[(m * TB + j) * CR + 2 * t + 1] : 0.0;
-        }
-        double cr = 0.0, ci = 0.0;
-#pragma unroll
-        for (int m = 0; m < G; ++m)
-          if (m == l) {
-            cr = c[2 * m];
-            ci = c[2 * m + 1];
-          }
+        for (int e = 0; e < 8; ++e) vv[e] = (double)vl[8 * t + e];
+        const T *ct = Cs + j * CR + 2 * t;         // direction m's value at ct[m * TB * CR]
+        const double cr = (double)ct[l * TB * CR], ci = (double)ct[l * TB * CR + 1];
+        sbl = fma(cr, cr, fma(ci, ci, sbl));       // X_ll, kept apart: x is indexed statically
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          u[2 * e] = fma(cr, v[2 * e], fma(ci, v[2 * e + 1], u[2 * e]));
-          u[2 * e + 1] = fma(cr, v[2 * e + 1], fma(-ci, v[2 * e], u[2 * e + 1]));
+          u[2 * e] = fma(cr, vv[2 * e], fma(ci, vv[2 * e + 1], u[2 * e]));
+          u[2 * e + 1] = fma(cr, vv[2 * e + 1], fma(-ci, vv[2 * e], u[2 * e + 1]));
         }
 #pragma unroll
         for (int m = 0; m < G; ++m) {
-          x[2 * m] = fma(cr, c[2 * m], fma(ci, c[2 * m + 1], x[2 * m]));
-          x[2 * m + 1] = fma(cr, c[2 * m + 1], fma(-ci, c[2 * m], x[2 * m + 1]));
+          if (m < Kf) {                            // uniform over the workgroup
+            const double mr = (double)ct[m * TB * CR], mi = (double)ct[m * TB * CR + 1];
+            x[2 * m] = fma(cr, mr, fma(ci, mi, x[2 * m]));
+            x[2 * m + 1] = fma(cr, mi, fma(-ci, mr, x[2 * m + 1]));
+          }
         }
       }
     }
-    __syncthreads();
+    wave_lds_sync();   // the chunk's LDS rows are read before the next chunk overwrites them
   }
   if (!finite) {
     if (bad) atomicOr(bad, 1);
     if (status) atomicOr(status + f, 5);   // CALIB_E_NUMERIC
   }
-  if (j >= nt || l >= Kf) return;
-  const int64_t nbt = pb.nbt, gb = gb0 + j;
+  if (l >= Kf) return;
+  const int64_t nbt = pb.nbt;
   double2 *U2 = reinterpret_cast<double2 *>(B.Ucoh + ((int64_t)l * nbt + gb) * 8);
 #pragma unroll
   for (int h = 0; h < 4; ++h) U2[h] = make_double2(u[2 * h], u[2 * h + 1]);
@@ -353,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
       double2 *X2 = reinterpret_cast<double2 *>(B.Xcoh + (((int64_t)l * pb.K + m) * nbt + gb) * 2);
       *X2 = m < Kf ? make_double2(x[2 * m], x[2 * m + 1]) : make_double2(0.0, 0.0);
     }
-  Sb[L.sb_off[f] + (int64_t)l * nb + bi0 + j] = x[2 * l];
+  Sb[L.sb_off[f] + (int64_t)l * nb + bi] = sbl;
 }
 
 // Model visibilities in the caller's full layout (zero on flagged baselines).
