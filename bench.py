@@ -200,7 +200,8 @@ def main():
     ap.add_argument("--tile-group", type=int, default=0)
     ap.add_argument("--stream-grid", type=int, default=0)
     ap.add_argument("--autotune", action="store_true",
-                    help="choose tile_group / stream_grid with paper_1502_00858_amd.autotune")
+                    help="choose tile_group / stream_grid and the solver with "
+                         "paper_1502_00858_amd.autotune (measured on the measured interval)")
     ap.add_argument("--batch", type=int, default=512, help="training minibatch rows")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -247,11 +248,14 @@ def main():
     shape = {"tile_group": args.tile_group, "stream_grid": args.stream_grid, "source": "flags"}
     if args.autotune:
         from paper_1502_00858_amd import autotune
-        tuned = autotune.tune(data, vis, coh, flags, prec, refresh=True, **solve_kw)
+        tuned = autotune.tune(data, vis, coh, flags, prec, refresh=True, lm_iters=lm_iters,
+                              lm_tol=args.lm_tol, cg_tol=args.cg_tol, verbose=True)
         shape = {"tile_group": tuned["tile_group"], "stream_grid": tuned["stream_grid"],
                  "source": "autotune", "stream_ms_per_local_step": round(tuned["ms"], 3),
-                 "worst_candidate_ms": round(max(c["ms"] for c in tuned["candidates"]), 3)}
-        log(f"autotune: {shape}")
+                 "worst_candidate_ms": round(max(c["ms"] for c in tuned["candidates"]), 3),
+                 "solver_ms_per_local_step": tuned["solver_ms"]}
+        solve_kw["solver"] = args.solver = int(tuned["solver"])
+        log(f"autotune: {shape}, solver {args.solver}")
     # the contexts are made once per observation, on its first interval; every timed step loads
     # the measured interval into them (calib_set_data)
     first = synth.episode_interval(cfg, TEST_EPISODE, 0, args.episode_intervals)

@@ -1,6 +1,7 @@
-"""Tile-shape tuner for the streaming pass (the residual's energy at the start of a local step).
+"""Tuner for the launch shape of the streaming pass and for the local solver.
 
-Two launch parameters of calib_config shape those passes:
+Two launch parameters of calib_config shape the streaming pass (the residual's energy at the start
+of a local step):
 
 * tile_group  - lanes that share one baseline (4, 8, 16, 32 or 64); a workgroup of 256 lanes covers
                 256/tile_group baselines, each lane striding over that baseline's T*n_chan samples.
@@ -9,10 +10,19 @@ Two launch parameters of calib_config shape those passes:
                 workgroups striding over the tiles (fewer, longer-lived workgroups for ragged
                 batches with many small tiles).
 
-``tune`` measures the candidates on the caller's data with the library's own per-kernel HIP-event
-timing over one local step and returns the fastest; results are cached in a JSON file keyed by the
-problem shape.  Every candidate computes the same numbers up to the order of the per-baseline
-reductions, so the choice affects time only.
+and the solver of the damped normal equations (calib_config.solver): the one-workgroup Cholesky
+(1), the blocked Cholesky over many workgroups (2) or the matrix-free conjugate gradients inside
+the one-launch local step (3).  Which Cholesky wins depends on how many subbands share the GPU
+(the blocked one spreads a factorisation over many workgroups, the other runs one per
+workgroup); the matrix-free one avoids the factorisation altogether but is bound by the latency of
+its iteration.  The tuner measures instead of using a fixed crossover.
+
+``tune`` measures the stream-shape candidates on the caller's data with the library's own
+per-kernel HIP-event timing over one local step, then, at the fastest shape, the wall time of a
+whole local step with each solver candidate (LM iterations and stopping rule as given), and
+returns the fastest of each; results are cached in a JSON file keyed by the problem shape.  The
+stream-shape candidates compute the same numbers up to the order of the per-baseline reductions;
+the solvers differ within the solve's tolerance.
 """
 from __future__ import annotations
 
@@ -51,7 +61,7 @@ def measure(data: dict, vis, coh, flags, precision: int, tile_group: int, stream
             lm_iters: int = 2, repeats: int = 2) -> Dict[str, float]:
     """Milliseconds per local step spent in each streaming kernel class for one candidate."""
     ctx = calib.Calib(data, vis, coh, flags, precision=precision, lm_iters=lm_iters,
-                      tile_group=tile_group, stream_grid=stream_grid)
+                      tile_group=tile_group, stream_grid=stream_grid, solver=3)
     try:
         ctx.local_step(1)                      # warm-up
         ctx.set_kernel_timing(True)
@@ -64,12 +74,37 @@ def measure(data: dict, vis, coh, flags, precision: int, tile_group: int, stream
     return {k: kt[k][1] / repeats for k in STREAM_KERNELS}
 
 
+def measure_solver(data: dict, vis, coh, flags, precision: int, tile_group: int, stream_grid: int,
+                   solver: int, lm_iters: int, lm_tol: float, cg_tol: float,
+                   repeats: int = 2) -> float:
+    """Milliseconds of wall time per local step (from the second one on) with one solver."""
+    import time
+    import torch
+    ctx = calib.Calib(data, vis, coh, flags, precision=precision, lm_iters=lm_iters,
+                      tile_group=tile_group, stream_grid=stream_grid, solver=solver,
+                      lm_tol=lm_tol, cg_tol=cg_tol)
+    try:
+        ctx.local_step(0)
+        ctx.consensus_update(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(repeats):
+            ctx.local_step(1 + i)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / repeats * 1e3
+    finally:
+        ctx.close()
+
+
 def tune(data: dict, vis, coh, flags, precision: int, n_cu: int = 256,
          grids: Optional[Sequence[int]] = None, cache: Optional[str] = None,
-         refresh: bool = False, verbose: bool = False) -> dict:
-    """Fastest (tile_group, stream_grid) for this problem shape; cached by shape_key."""
+         refresh: bool = False, verbose: bool = False, solvers: Sequence[int] = (3, 1, 2),
+         lm_iters: int = 10, lm_tol: float = 1e-7, cg_tol: float = 1e-4) -> dict:
+    """Fastest (tile_group, stream_grid) and solver for this problem shape; cached by shape_key
+    and the solver settings."""
     cache = cache or _default_cache()
-    key = shape_key(data, precision)
+    key = (shape_key(data, precision) + f"-s{''.join(str(int(x)) for x in solvers)}"
+           f"-lm{lm_iters}-{lm_tol:g}-cg{cg_tol:g}")
     table = {}
     if os.path.exists(cache):
         with open(cache) as fh:
@@ -87,8 +122,16 @@ def tune(data: dict, vis, coh, flags, precision: int, n_cu: int = 256,
                 print(f"[autotune] group {g:2d} grid {sg:5d}: {total:.3f} ms "
                       + " ".join(f"{k} {v:.3f}" for k, v in t.items()), flush=True)
     best = min(results, key=lambda r: r["ms"])
+    solver_ms = {}
+    for sv in solvers:
+        solver_ms[int(sv)] = measure_solver(data, vis, coh, flags, precision, best["tile_group"],
+                                            best["stream_grid"], int(sv), lm_iters, lm_tol, cg_tol)
+        if verbose:
+            print(f"[autotune] solver {sv}: {solver_ms[int(sv)]:.3f} ms per local step", flush=True)
+    best_solver = min(solver_ms, key=solver_ms.get)
     entry = {"tile_group": best["tile_group"], "stream_grid": best["stream_grid"],
-             "ms": best["ms"], "candidates": results}
+             "ms": best["ms"], "candidates": results, "solver": best_solver,
+             "solver_ms": {str(k): v for k, v in solver_ms.items()}}
     table[key] = entry
     os.makedirs(os.path.dirname(cache), exist_ok=True)
     tmp = cache + ".tmp"

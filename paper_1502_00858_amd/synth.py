@@ -80,7 +80,7 @@ def named_config(name: str) -> SynthConfig:
     if name == "c3":   # batched uneven subbands
         return SynthConfig("c3", N=62, P=256, Q=4, K=10, T=10, n_chan=-1, n_dirs=None,
                            flag_frac_max=0.3, rho=5.0, admm_iters=30, lm_iters=10,
-                           config_index=3)
+                           config_index=3, noise_per_subband=True)
     if name == "c5":   # large array
         return SynthConfig("c5", N=128, P=64, Q=6, K=10, T=20, n_chan=8, rho=5.0,
                            admm_iters=30, lm_iters=10, config_index=5, noise_per_subband=True)

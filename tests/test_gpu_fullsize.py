@@ -111,9 +111,13 @@ def test_autotune_measures_and_caches(cal, synth_mod, tmp_path, monkeypatch):
     assert best["tile_group"] in autotune.GROUPS and best["stream_grid"] in (0, 4)
     assert len(best["candidates"]) == 2 * len(autotune.GROUPS)
     assert best["ms"] == min(r["ms"] for r in best["candidates"])
+    # the solver: every candidate timed, the fastest chosen
+    assert sorted(best["solver_ms"]) == ["1", "2", "3"]
+    assert best["solver_ms"][str(best["solver"])] == min(best["solver_ms"].values())
 
     def no_measure(*a, **k):
         raise AssertionError("cached shape measured again")
     monkeypatch.setattr(autotune, "measure", no_measure)
+    monkeypatch.setattr(autotune, "measure_solver", no_measure)
     again = autotune.tune(d, vis, coh, flags, cal.CALIB_FP32_MIXED, grids=[0, 4], cache=cache)
     assert again == best
