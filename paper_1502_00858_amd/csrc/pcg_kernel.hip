@@ -92,11 +92,17 @@ __device__ inline void gram(const double *Jq, double *v) {
   v[3] = Jq[0] * Jq[3] - Jq[1] * Jq[2] + Jq[4] * Jq[7] - Jq[5] * Jq[6];
 }
 
+// Per-station 2x2 complex matrices in LDS take kJS doubles (8 + 2 of padding): at a stride of
+// 20 dwords, 16 stations fall in 16 different 4-bank groups of the 64 LDS banks, so a wavefront's
+// 16-byte reads at scattered stations (baselines' p and q, adjacency lists) rarely conflict; at a
+// stride of 16 dwords every fourth station shares its banks.
+constexpr int kJS = 10;
+
 // LDS of one solve; SPL: stations per lane of wavefront 0 (1 for N <= 64, 2 for N <= 128)
 template <int SPL>
 struct PcgLds {
-  double Js[64 * SPL * 8];                  // J of the direction
-  double Us[64 * SPL * 8];                  // u_q = d_q^H J_q
+  double Js[64 * SPL * kJS];                // J of the direction
+  double Us[64 * SPL * kJS];                // u_q = d_q^H J_q
   double Wp[kPcgWaves][8][64 * SPL];        // per-wavefront partials over its columns,
                                             // component-major (lane-consecutive, no bank conflicts)
   int ctl[2];                               // continue, failed
@@ -162,8 +168,8 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
       const bool first = oraw[i] >= 0;
       const int o = first ? oraw[i] : -1 - oraw[i];
       double t[8];
-      if (first) cmul(d[i], Js + 8 * o, t);
-      else chmul(d[i], Js + 8 * o, t);
+      if (first) cmul(d[i], Js + kJS * o, t);
+      else chmul(d[i], Js + kJS * o, t);
 #pragma unroll
       for (int e = 0; e < 8; ++e) gp[s][e] = fma(-2.0, t[e], gp[s][e]);
     }
@@ -188,7 +194,7 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
       const int p = lane + 64 * s, q = c0 + j;
       S[s][j] = (p < N && j < C && q < N) ? Sd[(int64_t)q * N + p] : 0.0;
     }
-  for (int e = threadIdx.x; e < 8 * kRows; e += kPcgThreads) Js[e] = e < 8 * N ? Jg[e] : 0.0;
+  for (int e = threadIdx.x; e < 8 * kRows; e += kPcgThreads) Js[kJS * (e >> 3) + (e & 7)] = e < 8 * N ? Jg[e] : 0.0;
   __syncthreads();
 
   // the rest of the gradient, the next batch in flight while the current one is used (and,
@@ -222,7 +228,7 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
 #pragma unroll
     for (int j = 0; j < kC; ++j) {
       double vq[4];
-      gram(Js + 8 * (c0 + j), vq);   // past N: zeros; past this wavefront's columns: S = 0
+      gram(Js + kJS * (c0 + j), vq);   // past N: zeros; past this wavefront's columns: S = 0
 #pragma unroll
       for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -270,9 +276,9 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
         double v = 0.0;
 #pragma unroll
         for (int i = 0; i < kPcgWaves; ++i) v += Wp[i][e][p];
-        if (live && !unreg) v += B.Y[jo + 8 * p + e] + rho * (Js[8 * p + e] - B.BZ[jo + 8 * p + e]);
+        if (live && !unreg) v += B.Y[jo + 8 * p + e] + rho * (Js[kJS * p + e] - B.BZ[jo + 8 * p + e]);
         g[s][e] = live ? v : 0.0;
-        Jp[s][e] = live ? Js[8 * p + e] : 0.0;
+        Jp[s][e] = live ? Js[kJS * p + e] : 0.0;
         x[s][e] = 0.0;
         r[s][e] = -g[s][e];
         bb = fma(r[s][e], r[s][e], bb);
@@ -305,7 +311,7 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
       for (int s = 0; s < SPL; ++s) {
         double u[8];
         chmul(dv[s], Jp[s], u);
-        double2 *u2 = reinterpret_cast<double2 *>(Us + 8 * (lane + 64 * s));
+        double2 *u2 = reinterpret_cast<double2 *>(Us + kJS * (lane + 64 * s));
 #pragma unroll
         for (int h = 0; h < 4; ++h) u2[h] = make_double2(u[2 * h], u[2 * h + 1]);
       }
@@ -328,7 +334,7 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
 #pragma unroll
       for (int j = 0; j < kC; ++j) {
         // past N: zeros; past this wavefront's columns: S = 0
-        const double2 *u2 = reinterpret_cast<const double2 *>(Us + 8 * (c0 + j));
+        const double2 *u2 = reinterpret_cast<const double2 *>(Us + kJS * (c0 + j));
         double uq[8];
 #pragma unroll
         for (int h = 0; h < 4; ++h) {
@@ -419,7 +425,7 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
       B.delta[(int64_t)f * nf + c] = x[s][e];
       B.G[(int64_t)f * nf + c] = g[s][e];
       B.Jtrial[(int64_t)f * N * 8 + c] = Jp[s][e] + x[s][e];
-      if (jt_lds) jt_lds[c] = Jp[s][e] + x[s][e];
+      if (jt_lds) jt_lds[kJS * p + e] = Jp[s][e] + x[s][e];
       ell = fma(x[s][e], fma(lam, x[s][e], -g[s][e]), ell);
     }
   }
@@ -441,9 +447,9 @@ constexpr int kQuad = 4;                    // lanes per baseline
 constexpr int kBpr = kBlock / kQuad;        // baselines per round
 constexpr int kU = 8;                       // rounds per batch
 
-// entry (i, j) of a_p a_q^H for the stations' 2x2 complex matrices in LDS (8 doubles each)
+// entry (i, j) of a_p a_q^H for the stations' 2x2 complex matrices in LDS (kJS doubles each)
 __device__ inline double2 jjh_entry(const double *A, int p, int q, int i, int j) {
-  const double *a = A + 8 * p + 4 * i, *b = A + 8 * q + 4 * j;
+  const double *a = A + kJS * p + 4 * i, *b = A + kJS * q + 4 * j;
   double re = 0.0, im = 0.0;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
@@ -585,7 +591,7 @@ template <int SPL>
 __global__ __launch_bounds__(kPcgThreads) void k_local_step(Problem pb, Layout L, Buffers B, int unreg,
                                                             double *lm_trace, int lm_iters, int sweeps) {
   __shared__ __align__(16) PcgLds<SPL> sh;
-  __shared__ __align__(16) double J0s[64 * SPL * 8];   // the run's start point
+  __shared__ __align__(16) double J0s[64 * SPL * kJS];   // the run's start point
   __shared__ double red[1][kBlock / 64];
   const int f = blockIdx.x;
   const int Kf = L.ndir[f];
@@ -595,7 +601,7 @@ __global__ __launch_bounds__(kPcgThreads) void k_local_step(Problem pb, Layout L
   for (int sw = 0; sw < sweeps; ++sw)
     for (int k = 0; k < Kf; ++k) {
       lmd::begin_dir(pb, L, B, f, k, unreg, false, 0, 0);
-      for (int e = threadIdx.x; e < n8; e += kBlock) J0s[e] = B.Jstart[(int64_t)f * n8 + e];
+      for (int e = threadIdx.x; e < n8; e += kBlock) J0s[kJS * (e >> 3) + (e & 7)] = B.Jstart[(int64_t)f * n8 + e];
       __syncthreads();
       if (st->done)   // a run that cannot start (non-finite state): its trace rows only
         for (int it = 0; it < lm_iters; ++it) lmd::update_dir(pb, L, B, f, k, unreg, lm_trace, it, lm_iters, false);
@@ -608,7 +614,8 @@ __global__ __launch_bounds__(kPcgThreads) void k_local_step(Problem pb, Layout L
         __syncthreads();
         if (st->done) break;
       }
-      for (int e = threadIdx.x; e < n8; e += kBlock) sh.Js[e] = B.J[((int64_t)f * pb.K + k) * n8 + e];
+      for (int e = threadIdx.x; e < n8; e += kBlock)
+        sh.Js[kJS * (e >> 3) + (e & 7)] = B.J[((int64_t)f * pb.K + k) * n8 + e];
       __syncthreads();
       fused_commit(pb, L, B, f, k, all, sh.Js, J0s, red);
       __syncthreads();
