@@ -128,6 +128,9 @@ __device__ inline bool lm_live(const Buffers &B, const int32_t *ndir, int f, int
 // buffers instead of copying the trial values
 __device__ inline double *d_accepted(const Buffers &B, int f) { return B.lm[f].dsel ? B.D1 : B.D0; }
 __device__ inline double *d_trial(const Buffers &B, int f) { return B.lm[f].dsel ? B.D0 : B.D1; }
+// the same from a copy of the subband's LM state (the one-launch local step keeps it in LDS)
+__device__ inline double *d_accepted(const Buffers &B, const LmState &st) { return st.dsel ? B.D1 : B.D0; }
+__device__ inline double *d_trial(const Buffers &B, const LmState &st) { return st.dsel ? B.D0 : B.D1; }
 
 // streaming kernels (templated on the stream element type float or double)
 template <typename T>

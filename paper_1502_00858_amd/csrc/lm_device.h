@@ -96,25 +96,18 @@ __device__ inline double objective(const Problem &pb, const Layout &L, const Buf
   return v[0] + v[1];
 }
 
-// Start of direction k's LM run of subband f (whole workgroup of kBlock threads): objective F at
-// J, the residual's energy E0, lambda_0 = tau * max diag(H_GN + rho I), nu = 2, start point Jstart.
-// With own, the run's direction, sweep and phase are recorded in the LM state.
-__device__ inline void begin_dir(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
-                                 int unreg, bool own, int cur, int sweep) {
-  __shared__ double red[2][kBlock / 64];
-  LmState *st = B.lm + f;
-  const double *J = jdir(B, pb, f, k);
-  double E0 = 0.0;
-  const double F = objective(pb, L, B, f, k, unreg, J, red, &E0);
-  // largest diagonal entry of H_GN + rho I: 2 sum_c S_pc (|J_c[0][j]|^2 + |J_c[1][j]|^2) + rho,
-  // from the column norms of the stations' Jones matrices and the dense S.  Wavefront w sums the
-  // rows q of its quarter for every column p (coalesced: lane p reads column p of row q, S being
-  // symmetric), the quarters are added in LDS.
+// Largest diagonal entry of H_GN + rho I of direction k of subband f at J (whole workgroup of
+// kBlock threads; result in every thread; J at a stride of js doubles per station):
+// 2 sum_c S_pc (|J_c[0][j]|^2 + |J_c[1][j]|^2), from the column norms of the stations' Jones
+// matrices and the dense S.  Wavefront w sums the rows q of its quarter for every column p
+// (coalesced: lane p reads column p of row q, S being symmetric), the quarters are added in LDS.
+__device__ inline double max_diag(const Problem &pb, const Buffers &B, int f, int k, const double *J, int js) {
   constexpr int kW = kBlock / 64;
   __shared__ double nrm[2][kMaxStations];
   __shared__ double part[kW][2][kMaxStations];
+  __shared__ double mx[kBlock / 64];
   for (int p = threadIdx.x; p < pb.N; p += kBlock) {
-    const double *Jp = J + 8 * p;
+    const double *Jp = J + js * p;
     nrm[0][p] = Jp[0] * Jp[0] + Jp[1] * Jp[1] + Jp[4] * Jp[4] + Jp[5] * Jp[5];
     nrm[1][p] = Jp[2] * Jp[2] + Jp[3] * Jp[3] + Jp[6] * Jp[6] + Jp[7] * Jp[7];
   }
@@ -146,35 +139,54 @@ __device__ inline void begin_dir(const Problem &pb, const Layout &L, const Buffe
     }
     dmax = fmax(dmax, 2.0 * fmax(d0, d1));
   }
-  __shared__ double mx[kBlock / 64];
   dmax = wave_max(dmax);
   if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = dmax;
-  for (int e = threadIdx.x; e < 8 * pb.N; e += kBlock) B.Jstart[(int64_t)f * pb.N * 8 + e] = J[e];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = 0.0;
-    for (int i = 0; i < kBlock / 64; ++i) m = fmax(m, mx[i]);
-    m += unreg ? 0.0 : B.rho[k];
-    st->F = F;
-    st->E0 = E0;
-    st->lambda = kLmTau * m;
-    st->lambda0 = st->lambda;
-    st->nu = 2.0;
-    st->accepted = 0;
-    st->chol_ok = 0;
-    st->ell = 0.0;
-    st->done = 0;
-    if (!isfinite(F)) {   // a state that is not finite: the run does nothing, the subband is reported
-      st->done = 1;
-      if (B.status) B.status[f] = 5;   // CALIB_E_NUMERIC
-    }
-    if (own) {
-      st->cur = cur;
-      st->sweep = sweep;
-      st->phase = kPhaseLm;
-      st->itc = 0;
-    }
+  double m = 0.0;
+  for (int i = 0; i < kBlock / 64; ++i) m = fmax(m, mx[i]);
+  return m;
+}
+
+// State at the start of direction k's LM run (one thread): objective F and data cost E0 at the
+// start point, lambda_0 = tau * max diag(H_GN + rho I), nu = 2.  A state that is not finite ends
+// the run at once and reports the subband.  With own, the run's direction, sweep and phase are
+// recorded.
+__device__ inline void begin_state(const Buffers &B, int f, LmState *st, double F, double E0,
+                                   double maxdiag, bool own, int cur, int sweep) {
+  st->F = F;
+  st->E0 = E0;
+  st->lambda = kLmTau * maxdiag;
+  st->lambda0 = st->lambda;
+  st->nu = 2.0;
+  st->accepted = 0;
+  st->chol_ok = 0;
+  st->ell = 0.0;
+  st->done = 0;
+  if (!isfinite(F)) {   // a state that is not finite: the run does nothing, the subband is reported
+    st->done = 1;
+    if (B.status) B.status[f] = 5;   // CALIB_E_NUMERIC
   }
+  if (own) {
+    st->cur = cur;
+    st->sweep = sweep;
+    st->phase = kPhaseLm;
+    st->itc = 0;
+  }
+}
+
+// Start of direction k's LM run of subband f (whole workgroup of kBlock threads): objective F at
+// J, the residual's energy E0, lambda_0, nu = 2, start point Jstart.
+// With own, the run's direction, sweep and phase are recorded in the LM state.
+__device__ inline void begin_dir(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
+                                 int unreg, bool own, int cur, int sweep) {
+  __shared__ double red[2][kBlock / 64];
+  LmState *st = B.lm + f;
+  const double *J = jdir(B, pb, f, k);
+  double E0 = 0.0;
+  const double F = objective(pb, L, B, f, k, unreg, J, red, &E0);
+  const double m = max_diag(pb, B, f, k, J, 8) + (unreg ? 0.0 : B.rho[k]);
+  for (int e = threadIdx.x; e < 8 * pb.N; e += kBlock) B.Jstart[(int64_t)f * pb.N * 8 + e] = J[e];
+  if (threadIdx.x == 0) begin_state(B, f, st, F, E0, m, own, cur, sweep);
 }
 
 // Data cost and D_b at the LM trial point from the start point's statistics (one wavefront per
@@ -290,10 +302,67 @@ __device__ inline void commit_tile(const Problem &pb, const Layout &L, const Buf
   }
 }
 
+// Trace rows [from, to) of a run that has stopped (one thread): the final objective and damping.
+__device__ inline void stopped_rows(const Problem &pb, int f, int k, const LmState *st, double *lm_trace,
+                                    int from, int to, int lm_iters) {
+  for (int i2 = from; lm_trace && i2 < to; ++i2) {
+    double *tn = lm_trace + 3 * ((int64_t)(f * pb.K + k) * lm_iters + i2);
+    tn[0] = st->F;
+    tn[1] = st->lambda;
+    tn[2] = 0;
+  }
+}
+
+// Gain ratio, accept / reject and damping after the trial point of LM iteration `it` (one thread),
+// Nielsen's rule; the stopping rule on the step's predicted decrease; numeric failure; the LM
+// trace row(s).  ok: the step was solved; Fn: the objective at the trial point.  Returns whether
+// the step was accepted (the trial point's D_b then becomes the accepted one).
+__device__ inline int update_state(const Problem &pb, const Buffers &B, int f, int k, LmState *st, int ok,
+                                   double Fn, double *lm_trace, int it, int lm_iters, bool own) {
+  int a = 0;
+  if (ok) {
+    const double ell = st->ell, F = st->F;
+    if (pb.lm_tol > 0.0 && ell <= pb.lm_tol * F) st->done = 1;
+    if (ell > 0.0 && F - Fn > 0.0) {
+      const double gain = (F - Fn) / ell;
+      const double t = 2.0 * gain - 1.0;
+      st->lambda *= fmax(1.0 / 3.0, 1.0 - t * t * t);
+      st->nu = 2.0;
+      st->F = Fn;
+      st->accepted += 1;
+      st->dsel ^= 1;   // the trial point's D_b becomes the accepted one
+      a = 1;
+    }
+  }
+  if (!a) {
+    st->lambda *= st->nu;
+    st->nu *= 2.0;
+    // normal equations that cannot be solved even with overwhelming damping: not finite
+    if (!ok && !(st->lambda <= kLmFailFactor * st->lambda0)) {
+      st->done = 1;
+      if (B.status) B.status[f] = 5;   // CALIB_E_NUMERIC
+    }
+  }
+  st->Fnew = Fn;
+  if (lm_trace) {
+    double *tr = lm_trace + 3 * ((int64_t)(f * pb.K + k) * lm_iters + it);
+    tr[0] = st->F;
+    tr[1] = st->lambda;
+    tr[2] = a;
+    // a run that stops here: the rows of its remaining iterations, which the host may not
+    // launch, get what their updates would write (the final objective and damping)
+    if (st->done) stopped_rows(pb, f, k, st, lm_trace, it + 1, lm_iters, lm_iters);
+  }
+  if (own) {
+    st->itc = it + 1;
+    if (st->done || it + 1 >= lm_iters) st->phase = kPhaseAdvance;
+  }
+  return a;
+}
+
 // Gain ratio, accept / reject and damping after the trial point of LM iteration `it` of direction
-// k of subband f (whole workgroup of kBlock threads), Nielsen's rule; the stopping rule on the
-// step's predicted decrease; the LM trace row(s).  With own, the run's iteration count and phase
-// are advanced in the LM state.
+// k of subband f (whole workgroup of kBlock threads).  With own, the run's iteration count and
+// phase are advanced in the LM state.
 __device__ inline void update_dir(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
                                   int unreg, double *lm_trace, int it, int lm_iters, bool own) {
   __shared__ double red[2][kBlock / 64];
@@ -302,63 +371,13 @@ __device__ inline void update_dir(const Problem &pb, const Layout &L, const Buff
   if (st->done) {
     // the run has stopped: the trace repeats the final objective and damping
     if (own && threadIdx.x == 0) st->phase = kPhaseAdvance;
-    if (threadIdx.x == 0 && lm_trace) {
-      double *tr = lm_trace + 3 * ((int64_t)(f * pb.K + k) * lm_iters + it);
-      tr[0] = st->F;
-      tr[1] = st->lambda;
-      tr[2] = 0;
-    }
+    if (threadIdx.x == 0) stopped_rows(pb, f, k, st, lm_trace, it, it + 1, lm_iters);
     return;
   }
-  int ok = st->chol_ok;
+  const int ok = st->chol_ok;
   double Fn = 0.0;
   if (ok) Fn = objective(pb, L, B, f, k, unreg, B.Jtrial + (int64_t)f * pb.N * 8, red);
-  if (threadIdx.x == 0) {
-    int a = 0;
-    if (ok) {
-      const double ell = st->ell, F = st->F;
-      if (pb.lm_tol > 0.0 && ell <= pb.lm_tol * F) st->done = 1;
-      if (ell > 0.0 && F - Fn > 0.0) {
-        const double gain = (F - Fn) / ell;
-        const double t = 2.0 * gain - 1.0;
-        st->lambda *= fmax(1.0 / 3.0, 1.0 - t * t * t);
-        st->nu = 2.0;
-        st->F = Fn;
-        st->accepted += 1;
-        st->dsel ^= 1;   // the trial point's D_b becomes the accepted one
-        a = 1;
-      }
-    }
-    if (!a) {
-      st->lambda *= st->nu;
-      st->nu *= 2.0;
-      // normal equations that cannot be solved even with overwhelming damping: not finite
-      if (!ok && !(st->lambda <= kLmFailFactor * st->lambda0)) {
-        st->done = 1;
-        if (B.status) B.status[f] = 5;   // CALIB_E_NUMERIC
-      }
-    }
-    st->Fnew = Fn;
-    acc = a;
-    if (lm_trace) {
-      double *tr = lm_trace + 3 * ((int64_t)(f * pb.K + k) * lm_iters + it);
-      tr[0] = st->F;
-      tr[1] = st->lambda;
-      tr[2] = a;
-      // a run that stops here: the rows of its remaining iterations, which the host may not
-      // launch, get what their updates would write (the final objective and damping)
-      for (int i2 = it + 1; st->done && i2 < lm_iters; ++i2) {
-        double *tn = lm_trace + 3 * ((int64_t)(f * pb.K + k) * lm_iters + i2);
-        tn[0] = st->F;
-        tn[1] = st->lambda;
-        tn[2] = 0;
-      }
-    }
-    if (own) {
-      st->itc = it + 1;
-      if (st->done || it + 1 >= lm_iters) st->phase = kPhaseAdvance;
-    }
-  }
+  if (threadIdx.x == 0) acc = update_state(pb, B, f, k, st, ok, Fn, lm_trace, it, lm_iters, own);
   __syncthreads();
   if (acc) {
     double *J = B.J + ((int64_t)f * pb.K + k) * pb.N * 8;

@@ -108,12 +108,15 @@ struct PcgLds {
   int ctl[2];                               // continue, failed
 };
 
-// The gradient and the solve of direction k of subband f (whole workgroup of kPcgThreads): G, the
-// step delta, the trial point J + delta and the predicted decrease in the LM state (chol_ok = 0
-// on a failed solve).  Wavefronts 1-3 return before wavefront 0 writes the results.
+// The gradient and the solve of direction k of subband f (whole workgroup of kPcgThreads) at the
+// current J (sh.Js), with the direction's Y and B_f Z in LDS (Ys, BZs, 8 doubles per station): G
+// and the step delta to the record (CALIB_FIELD_LM_STEP), the trial point J + delta into jt_lds,
+// the predicted decrease into the LM state st (chol_ok = 0 on a failed solve).  Wavefronts 1-3
+// return before wavefront 0 writes the results.
 template <int SPL>
 __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
-                                 int unreg, double tol, PcgLds<SPL> &sh, double *jt_lds = nullptr) {
+                                 int unreg, double tol, PcgLds<SPL> &sh, double *jt_lds, LmState *st,
+                                 const double *Ys, const double *BZs) {
   constexpr int kRows = 64 * SPL;               // stations covered
   constexpr int kC = kRows / kPcgWaves;          // columns per wavefront (at most)
   constexpr int kBatch = 8 / SPL;                // baselines of the gradient in flight per lane
@@ -123,19 +126,16 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
   const int N = pb.N, nf = pb.nf;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int C = (N + kPcgWaves - 1) / kPcgWaves, c0 = w * C;
-  LmState *st = B.lm + f;
   const double lam = st->lambda;
   const double rho = unreg ? 0.0 : B.rho[k];
   const double mu = rho + lam;
-  const int64_t jo = ((int64_t)f * pb.K + k) * N * 8;
-  const double *Jg = B.J + jo;
   const double *Sd = B.Sd + ((int64_t)f * pb.K + k) * N * N;
 
   // gradient of the data term, gathered over station p's baselines (wavefront w takes every
   // fourth one): G_p = -2 sum_{q>p} D_pq J_q - 2 sum_{c<p} D_cp^H J_c (+ Y_p + rho (J_p - BZ_p)
-  // below).  The first batch's adjacency entries and D_b are requested before S and J, so that
-  // their two dependent latencies overlap the loads of S and J.
-  const double *Dacc = d_accepted(B, f);
+  // below).  The first batch's adjacency entries and D_b are requested before S, so that their two
+  // dependent latencies overlap the loads of S.
+  const double *Dacc = d_accepted(B, *st);
   int gb[kBatch], oraw[kBatch];
   double d[kBatch][8];
   auto request = [&](int s, int ab) {
@@ -194,8 +194,6 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
       const int p = lane + 64 * s, q = c0 + j;
       S[s][j] = (p < N && j < C && q < N) ? Sd[(int64_t)q * N + p] : 0.0;
     }
-  for (int e = threadIdx.x; e < 8 * kRows; e += kPcgThreads) Js[kJS * (e >> 3) + (e & 7)] = e < 8 * N ? Jg[e] : 0.0;
-  __syncthreads();
 
   // the rest of the gradient, the next batch in flight while the current one is used (and,
   // after the first, while the Q partials are formed)
@@ -276,7 +274,7 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
         double v = 0.0;
 #pragma unroll
         for (int i = 0; i < kPcgWaves; ++i) v += Wp[i][e][p];
-        if (live && !unreg) v += B.Y[jo + 8 * p + e] + rho * (Js[kJS * p + e] - B.BZ[jo + 8 * p + e]);
+        if (live && !unreg) v += Ys[8 * p + e] + rho * (Js[kJS * p + e] - BZs[8 * p + e]);
         g[s][e] = live ? v : 0.0;
         Jp[s][e] = live ? Js[kJS * p + e] : 0.0;
         x[s][e] = 0.0;
@@ -424,8 +422,7 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
       const int c = 8 * p + e;
       B.delta[(int64_t)f * nf + c] = x[s][e];
       B.G[(int64_t)f * nf + c] = g[s][e];
-      B.Jtrial[(int64_t)f * N * 8 + c] = Jp[s][e] + x[s][e];
-      if (jt_lds) jt_lds[kJS * p + e] = Jp[s][e] + x[s][e];
+      jt_lds[kJS * p + e] = Jp[s][e] + x[s][e];
       ell = fma(x[s][e], fma(lam, x[s][e], -g[s][e]), ell);
     }
   }
@@ -460,13 +457,15 @@ __device__ inline double2 jjh_entry(const double *A, int p, int q, int i, int j)
   return make_double2(re, im);
 }
 
-// Data cost and D_b at the trial point Jt from the start point J0's statistics (lmd::trial_tile)
-__device__ inline void fused_trial(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
-                                   const double *Jt, const double *J0, double (*red)[kBlock / 64]) {
+// Data cost (returned to every thread) and D_b at the trial point Jt from the start point J0's
+// statistics (lmd::trial_tile); st: the subband's LM state
+__device__ inline double fused_trial(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
+                                     const double *Jt, const double *J0, const LmState *st,
+                                     double (*red)[kBlock / 64]) {
   const int nb = L.nb[f];
   const int64_t b0 = L.bl_off[f];
   const double *Sb = B.Sb + L.sb_off[f] + (int64_t)k * nb;
-  double2 *Dt = reinterpret_cast<double2 *>(d_trial(B, f));
+  double2 *Dt = reinterpret_cast<double2 *>(d_trial(B, *st));
   const double2 *D0 = reinterpret_cast<const double2 *>(B.Dstart);
   const int h = threadIdx.x & 3, ei = h >> 1, ej = h & 1, sub = threadIdx.x >> 2;
   double part = 0.0;
@@ -498,26 +497,24 @@ __device__ inline void fused_trial(const Problem &pb, const Layout &L, const Buf
   }
   double v[1] = {part};
   lmd::block_sum_vec<1>(v, reinterpret_cast<double (*)[kBlock / 64]>(red));
-  const int t0 = L.tile_off[f], t1 = L.tile_off[f + 1];
-  for (int t = t0 + threadIdx.x; t < t1; t += kBlock)
-    B.cost_part[t] = t == t0 ? v[0] + B.lm[f].E0 : 0.0;
+  return v[0] + st->E0;
 }
 
 // SAGE commit of direction k (lmd::commit_tile): with dM = J1_p J1_q^H - J0_p J0_q^H (J1 the run's
 // final J, J0 its start, both in LDS), every direction l from l0 updates D_l -= X_lk dM and the
-// energy changes by sum_b X_kk ||dM||^2 - 2 Re <dM, D_k>.  dM is formed once per baseline; the
-// directions are walked with the next one's D_l and X_lk requested before the current one's are
-// stored.
-__device__ inline void fused_commit(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
-                                    int all, const double *J1, const double *J0,
-                                    double (*red)[kBlock / 64]) {
+// energy changes by sum_b X_kk ||dM||^2 - 2 Re <dM, D_k> (returned to every thread).  dM is formed
+// once per baseline; the directions are walked with the next one's D_l and X_lk requested before
+// the current one's are stored.
+__device__ inline double fused_commit(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
+                                      int all, const double *J1, const double *J0, const LmState *st,
+                                      double (*red)[kBlock / 64]) {
   const int Kf = L.ndir[f], nb = L.nb[f], K = pb.K, next = k + 1 < Kf ? k + 1 : 0;
   const int64_t b0 = L.bl_off[f], nbt = pb.nbt;
   const int l0 = all ? 0 : k;
   const int h = threadIdx.x & 3, ei = h >> 1, ej = h & 1, sub = threadIdx.x >> 2;
   double2 *Dall = reinterpret_cast<double2 *>(B.Dall);
   const double2 *X = reinterpret_cast<const double2 *>(B.Xcoh);
-  double2 *Da = reinterpret_cast<double2 *>(d_accepted(B, f));
+  double2 *Da = reinterpret_cast<double2 *>(d_accepted(B, *st));
   double2 *Ds = reinterpret_cast<double2 *>(B.Dstart);
   double part = 0.0;
   for (int base = 0; base < nb; base += kBpr * kU) {
@@ -577,49 +574,100 @@ __device__ inline void fused_commit(const Problem &pb, const Layout &L, const Bu
   }
   double v[1] = {part};
   lmd::block_sum_vec<1>(v, reinterpret_cast<double (*)[kBlock / 64]>(red));
-  const int t0 = L.tile_off[f], t1 = L.tile_off[f + 1];
-  if (threadIdx.x == 0) B.Epart[t0] += v[0];
-  __syncthreads();
-  for (int t = t0 + threadIdx.x; t < t1; t += kBlock) B.cost_part[t] = B.Epart[t];
+  return v[0];   // the change of the residual's energy
+}
+
+// Re tr(Y^H (J - BZ)) + rho/2 ||J - BZ||^2 of the direction (whole workgroup; result in every
+// thread): J in LDS at kJS doubles per station, Y and B_f Z in LDS at 8
+__device__ inline double penalty_lds(int N, double rho, const double *Jx, const double *Ys,
+                                     const double *BZs, double (*red)[kBlock / 64]) {
+  double pen = 0.0;
+  for (int e = threadIdx.x; e < 8 * N; e += kBlock) {
+    const double d = Jx[kJS * (e >> 3) + (e & 7)] - BZs[e];
+    pen += Ys[e] * d + 0.5 * rho * d * d;
+  }
+  double v[1] = {pen};
+  lmd::block_sum_vec<1>(v, red);
+  return v[0];
 }
 
 // A subband's whole local step in one workgroup: for every SAGE sweep and direction, the LM run
 // (start, then per iteration the gradient and solve, the trial point's statistics, the update
 // with the stopping rule) and the SAGE commit, in the order of the launches of the lockstep local
-// step.  Nothing is launched or read back between LM iterations.
+// step.  Nothing is launched or read back between LM iterations, and what an LM iteration reads
+// besides the per-baseline statistics stays in LDS for the whole run: the LM state, the current
+// and the start point J, the direction's Y and B_f Z, the residual's energy (from the streaming
+// pass's tile partials at the start, then moved by each commit).  The LM state and the energy are
+// written back at the end (the energy into the subband's first tile, the others zero).
 template <int SPL>
 __global__ __launch_bounds__(kPcgThreads) void k_local_step(Problem pb, Layout L, Buffers B, int unreg,
                                                             double *lm_trace, int lm_iters, int sweeps) {
+  constexpr int kRows = 64 * SPL;
   __shared__ __align__(16) PcgLds<SPL> sh;
-  __shared__ __align__(16) double J0s[64 * SPL * kJS];   // the run's start point
+  __shared__ __align__(16) double J0s[kRows * kJS];   // the run's start point
+  __shared__ __align__(16) double Ys[kRows * 8], BZs[kRows * 8];
   __shared__ double red[1][kBlock / 64];
+  __shared__ LmState lst;
+  __shared__ int acc;
   const int f = blockIdx.x;
-  const int Kf = L.ndir[f];
+  const int Kf = L.ndir[f], N = pb.N, n8 = 8 * N;
   const int all = sweeps > 1;
-  const int n8 = 8 * pb.N;
-  const LmState *st = B.lm + f;
+  const int t0 = L.tile_off[f], t1 = L.tile_off[f + 1];
+  if (threadIdx.x == 0) lst = B.lm[f];
+  double E;   // energy of the current residual
+  {
+    double v[1] = {0.0};
+    for (int t = t0 + threadIdx.x; t < t1; t += kBlock) v[0] += B.Epart[t];
+    lmd::block_sum_vec<1>(v, red);
+    E = v[0];
+  }
   for (int sw = 0; sw < sweeps; ++sw)
     for (int k = 0; k < Kf; ++k) {
-      lmd::begin_dir(pb, L, B, f, k, unreg, false, 0, 0);
-      for (int e = threadIdx.x; e < n8; e += kBlock) J0s[kJS * (e >> 3) + (e & 7)] = B.Jstart[(int64_t)f * n8 + e];
-      __syncthreads();
-      if (st->done)   // a run that cannot start (non-finite state): its trace rows only
-        for (int it = 0; it < lm_iters; ++it) lmd::update_dir(pb, L, B, f, k, unreg, lm_trace, it, lm_iters, false);
-      for (int it = 0; it < lm_iters && !st->done; ++it) {
-        pcg_solve<SPL>(pb, L, B, f, k, unreg, pb.cg_tol, sh, sh.Us);
-        __syncthreads();
-        if (st->chol_ok) fused_trial(pb, L, B, f, k, sh.Us, J0s, red);
-        __syncthreads();
-        lmd::update_dir(pb, L, B, f, k, unreg, lm_trace, it, lm_iters, false);
-        __syncthreads();
-        if (st->done) break;
+      const double rho = unreg ? 0.0 : B.rho[k];
+      const int64_t jo = ((int64_t)f * pb.K + k) * n8;
+      for (int e = threadIdx.x; e < 8 * kRows; e += kBlock) {
+        const double j = e < n8 ? B.J[jo + e] : 0.0;   // zero past the last station
+        sh.Js[kJS * (e >> 3) + (e & 7)] = j;
+        J0s[kJS * (e >> 3) + (e & 7)] = j;
+        if (e < n8) {
+          Ys[e] = B.Y[jo + e];
+          BZs[e] = B.BZ[jo + e];
+        }
       }
-      for (int e = threadIdx.x; e < n8; e += kBlock)
-        sh.Js[kJS * (e >> 3) + (e & 7)] = B.J[((int64_t)f * pb.K + k) * n8 + e];
       __syncthreads();
-      fused_commit(pb, L, B, f, k, all, sh.Js, J0s, red);
+      const double F = E + (unreg ? 0.0 : penalty_lds(N, rho, sh.Js, Ys, BZs, red));
+      const double md = lmd::max_diag(pb, B, f, k, sh.Js, kJS) + rho;
+      if (threadIdx.x == 0) lmd::begin_state(B, f, &lst, F, E, md, false, 0, 0);
+      __syncthreads();
+      if (lst.done && threadIdx.x == 0)   // a run that cannot start (non-finite state): trace rows only
+        lmd::stopped_rows(pb, f, k, &lst, lm_trace, 0, lm_iters, lm_iters);
+      for (int it = 0; it < lm_iters && !lst.done; ++it) {
+        pcg_solve<SPL>(pb, L, B, f, k, unreg, pb.cg_tol, sh, sh.Us, &lst, Ys, BZs);
+        __syncthreads();
+        const int ok = lst.chol_ok;
+        double Fn = 0.0;
+        if (ok)
+          Fn = fused_trial(pb, L, B, f, k, sh.Us, J0s, &lst, red) +
+               (unreg ? 0.0 : penalty_lds(N, rho, sh.Us, Ys, BZs, red));
+        if (threadIdx.x == 0) acc = lmd::update_state(pb, B, f, k, &lst, ok, Fn, lm_trace, it, lm_iters, false);
+        __syncthreads();
+        if (acc)   // the trial point is the new J
+          for (int e = threadIdx.x; e < n8; e += kBlock) {
+            const double j = sh.Us[kJS * (e >> 3) + (e & 7)];
+            sh.Js[kJS * (e >> 3) + (e & 7)] = j;
+            B.J[jo + e] = j;
+          }
+        __syncthreads();
+      }
+      E += fused_commit(pb, L, B, f, k, all, sh.Js, J0s, &lst, red);
       __syncthreads();
     }
+  if (threadIdx.x == 0) B.lm[f] = lst;
+  for (int t = t0 + threadIdx.x; t < t1; t += kBlock) {
+    const double v = t == t0 ? E : 0.0;
+    B.Epart[t] = v;
+    B.cost_part[t] = v;
+  }
 }
 
 }  // namespace
