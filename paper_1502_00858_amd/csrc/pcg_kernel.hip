@@ -23,6 +23,8 @@
 // partial sums in LDS, component-major so that lanes touch consecutive words, which wavefront 0
 // adds in a fixed order.  One CG iteration: wavefront 0 writes u | all wavefronts their partial W
 // | wavefront 0 finishes H d and the recurrences.
+#include <type_traits>
+
 #include "calib_internal.h"
 #include "lm_device.h"
 #include "wave_reduce.h"
@@ -469,14 +471,17 @@ __device__ inline double fused_trial(const Problem &pb, const Layout &L, const B
   const double2 *D0 = reinterpret_cast<const double2 *>(B.Dstart);
   const int h = threadIdx.x & 3, ei = h >> 1, ej = h & 1, sub = threadIdx.x >> 2;
   double part = 0.0;
-  for (int base = 0; base < nb; base += kBpr * kU) {
+  // a full batch runs without per-baseline guards (and the branches they cost); the last one
+  // may be partial
+  auto batch = [&](int base, auto full) {
+    constexpr bool kFull = decltype(full)::value;
     int p[kU], q[kU];
     double S[kU];
     double2 d0[kU];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int bi = base + sub + kBpr * u;
-      if (bi < nb) {
+      if (kFull || bi < nb) {
         const int64_t gb = b0 + bi;
         p[u] = L.bl_p[gb];
         q[u] = L.bl_q[gb];
@@ -487,13 +492,17 @@ __device__ inline double fused_trial(const Problem &pb, const Layout &L, const B
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int bi = base + sub + kBpr * u;
-      if (bi >= nb) continue;
+      if (!kFull && bi >= nb) continue;
       const double2 m1 = jjh_entry(Jt, p[u], q[u], ei, ej), m0 = jjh_entry(J0, p[u], q[u], ei, ej);
       const double dr = m1.x - m0.x, di = m1.y - m0.y;
       const double cross = fma(dr, d0[u].x, di * d0[u].y), norm = fma(dr, dr, di * di);
       Dt[4 * (b0 + bi) + h] = make_double2(fma(-S[u], dr, d0[u].x), fma(-S[u], di, d0[u].y));
       part += fma(S[u], norm, -2.0 * cross);
     }
+  };
+  for (int base = 0; base < nb; base += kBpr * kU) {
+    if (base + kBpr * kU <= nb) batch(base, std::true_type{});
+    else batch(base, std::false_type{});
   }
   double v[1] = {part};
   lmd::block_sum_vec<1>(v, reinterpret_cast<double (*)[kBlock / 64]>(red));
@@ -517,13 +526,15 @@ __device__ inline double fused_commit(const Problem &pb, const Layout &L, const 
   double2 *Da = reinterpret_cast<double2 *>(d_accepted(B, *st));
   double2 *Ds = reinterpret_cast<double2 *>(B.Dstart);
   double part = 0.0;
-  for (int base = 0; base < nb; base += kBpr * kU) {
+  // a full batch runs without per-baseline guards; the last one may be partial
+  auto batch = [&](int base, auto full) {
+    constexpr bool kFull = decltype(full)::value;
     double2 dm[kU], dn[kU], xn[kU];
     auto request = [&](int l) {
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int bi = base + sub + kBpr * u;
-        if (bi < nb) {
+        if (kFull || bi < nb) {
           const int64_t gb = b0 + bi;
           dn[u] = Dall[4 * ((int64_t)l * nbt + gb) + h];
           xn[u] = X[((int64_t)l * K + k) * nbt + gb];
@@ -534,7 +545,7 @@ __device__ inline double fused_commit(const Problem &pb, const Layout &L, const 
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       const int bi = base + sub + kBpr * u;
-      if (bi < nb) {
+      if (kFull || bi < nb) {
         const int64_t gb = b0 + bi;
         const int p = L.bl_p[gb], q = L.bl_q[gb];
         const double2 m1 = jjh_entry(J1, p, q, ei, ej), m0 = jjh_entry(J0, p, q, ei, ej);
@@ -553,7 +564,7 @@ __device__ inline double fused_commit(const Problem &pb, const Layout &L, const 
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int bi = base + sub + kBpr * u;
-        if (bi >= nb) continue;
+        if (!kFull && bi >= nb) continue;
         const int64_t gb = b0 + bi;
         if (l == k) {
           const double cross = fma(dm[u].x, d[u].x, dm[u].y * d[u].y);
@@ -571,6 +582,10 @@ __device__ inline double fused_commit(const Problem &pb, const Layout &L, const 
         }
       }
     }
+  };
+  for (int base = 0; base < nb; base += kBpr * kU) {
+    if (base + kBpr * kU <= nb) batch(base, std::true_type{});
+    else batch(base, std::false_type{});
   }
   double v[1] = {part};
   lmd::block_sum_vec<1>(v, reinterpret_cast<double (*)[kBlock / 64]>(red));
