@@ -206,15 +206,17 @@ calib_status run_local_step(calib_ctx *c, int admm_iter, hipStream_t s) {
   const Problem &pb = c->pb;
   const Layout &L = c->L;
   const Buffers &B = c->B;
-  HIPCHK(c, timed(c, CALIB_KERNEL_REFRESH, [&] { return launch_refresh<T>(pb, L, B, s); }));
   if (pb.solver == kSolverPcg) {
-    // every subband's whole local step in one launch: the LM runs, the stopping rule and the
-    // SAGE commits stay on the device
+    // every D_l and the residual's energy from the coherency statistics (no pass over the
+    // samples), then every subband's whole local step in one launch: the LM runs, the stopping
+    // rule and the SAGE commits stay on the device
+    HIPCHK(c, timed(c, CALIB_KERNEL_REFRESH, [&] { return launch_refresh_stats(pb, L, B, s); }));
     HIPCHK(c, timed(c, CALIB_KERNEL_LOCAL_STEP, [&] {
       return launch_local_step(pb, L, B, unreg, c->lm_trace, c->lm_iters, c->sage_sweeps, s);
     }));
     return CALIB_OK;
   }
+  HIPCHK(c, timed(c, CALIB_KERNEL_REFRESH, [&] { return launch_refresh<T>(pb, L, B, s); }));
   for (int sw = 0; sw < c->sage_sweeps; ++sw)
     for (int k = 0; k < c->K; ++k) {
       HIPCHK(c, timed(c, CALIB_KERNEL_LM_BEGIN, [&] { return launch_lm_begin(pb, L, B, k, unreg, s); }));
@@ -544,6 +546,8 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   DALLOC(B.G, (size_t)P * pb.nf * 8); DALLOC(B.delta, (size_t)P * pb.nf * 8);
   DALLOC(B.cost_part, (size_t)std::max(pb.ntiles, 1) * 8);
   DALLOC(B.Epart, (size_t)std::max(pb.ntiles, 1) * 8);
+  DALLOC(B.Ev, (size_t)std::max(nb_total, 1) * 8);
+  DALLOC(B.Epl, (size_t)K * std::max(pb.ntiles, 1) * 8);
   DALLOC(B.Ucoh, (size_t)nb_total * K * 8 * 8);
   DALLOC(B.Xcoh, (size_t)nb_total * K * K * 2 * 8);
   DALLOC(B.Dall, (size_t)nb_total * K * 8 * 8);

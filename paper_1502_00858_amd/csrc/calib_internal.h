@@ -94,6 +94,9 @@ struct Buffers {
   double *Xcoh;                         // [K][K][sum nb][2] sum_s conj(c_l) c_m
   double *Dall;                         // [K][sum nb][8] D_l of the current residual, every l
   double *Epart;                        // [ntiles] energy of the current residual per tile
+  double *Ev;                           // [sum nb] sum_s ||V_s||^2 per baseline (per interval)
+  double *Epl;                          // [K][ntiles] energy of the residual from the statistics:
+                                        // per direction l and tile, direction 0 with the V part
   double *H;                            // [P][npad][nf]
   double *Linv;                         // [P][nf/16][16*16] inverses of the diagonal tiles
   double *G, *delta;                    // [P][nf]
@@ -135,6 +138,9 @@ __device__ inline double *d_trial(const Buffers &B, const LmState &st) { return 
 // streaming kernels (templated on the stream element type float or double)
 template <typename T>
 hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
+// the refresh without a pass over the samples: every D_l and the residual's energy from the
+// coherency statistics (into Epl), for the one-launch local step
+hipError_t launch_refresh_stats(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
 template <typename T>
 hipError_t launch_commit(const Problem &pb, const Layout &L, const Buffers &B, int k, int all,
                          hipStream_t s);

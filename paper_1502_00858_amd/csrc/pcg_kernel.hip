@@ -611,8 +611,8 @@ __device__ inline double penalty_lds(int N, double rho, const double *Jx, const 
 // with the stopping rule) and the SAGE commit, in the order of the launches of the lockstep local
 // step.  Nothing is launched or read back between LM iterations, and what an LM iteration reads
 // besides the per-baseline statistics stays in LDS for the whole run: the LM state, the current
-// and the start point J, the direction's Y and B_f Z, the residual's energy (from the streaming
-// pass's tile partials at the start, then moved by each commit).  The LM state and the energy are
+// and the start point J, the direction's Y and B_f Z, the residual's energy (from the refresh's
+// per-(direction, tile) terms at the start, then moved by each commit).  The LM state and the energy are
 // written back at the end (the energy into the subband's first tile, the others zero).
 template <int SPL>
 __global__ __launch_bounds__(kPcgThreads) void k_local_step(Problem pb, Layout L, Buffers B, int unreg,
@@ -629,10 +629,11 @@ __global__ __launch_bounds__(kPcgThreads) void k_local_step(Problem pb, Layout L
   const int all = sweeps > 1;
   const int t0 = L.tile_off[f], t1 = L.tile_off[f + 1];
   if (threadIdx.x == 0) lst = B.lm[f];
-  double E;   // energy of the current residual
+  double E;   // energy of the current residual, from the statistics' per-(direction, tile) terms
   {
     double v[1] = {0.0};
-    for (int t = t0 + threadIdx.x; t < t1; t += kBlock) v[0] += B.Epart[t];
+    for (int t = t0 + threadIdx.x; t < t1; t += kBlock)
+      for (int l = 0; l < Kf; ++l) v[0] += B.Epl[(int64_t)l * pb.ntiles + t];
     lmd::block_sum_vec<1>(v, red);
     E = v[0];
   }

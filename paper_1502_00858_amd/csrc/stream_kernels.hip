@@ -4,10 +4,11 @@
 // are constant over a baseline's samples, so everything the Levenberg-Marquardt runs need from
 // the residual R = V - sum_l c_l J_lp J_lq^H (Section 2 visibility model) is per-baseline sums:
 // D_l = sum_s conj(c_ls) R_s for every direction l, and the energy sum_s ||R_s||^2.
-//   k_pack_stats   (per interval)      packed V, C and U_l = sum conj(c_l) V, X_lm = sum conj(c_l) c_m
-//                                      per baseline
+//   k_pack_stats   (per interval)      packed V, C and U_l = sum conj(c_l) V, X_lm = sum conj(c_l) c_m,
+//                                      sum ||V||^2 per baseline
 //   refresh        (start of a local step) the energy, streaming V and the coherencies once
-//                  (k_stream), and every D_l = U_l - sum_m X_lm M_m (k_dall)
+//                  (k_stream), and every D_l = U_l - sum_m X_lm M_m (k_dall); for the one-launch
+//                  local step D_l and the energy both from the statistics (k_dall<true>)
 //   k_trial_stats  (each LM trial point) cost and D_b of r = R - c_k (M_trial - M_start) (the
 //                  SAGE expectation V_k = R + c_k M_start of Section 3 minus the trial model)
 //   k_commit_stats (end of direction k)  R <- R - c_k (M_final - M_start) as an update of every
@@ -159,37 +160,62 @@ __global__ __launch_bounds__(64 * kStatTiles) void k_trial_stats(Problem pb, Lay
 
 // Every direction's D_l at the current point from the coherency statistics (grid: tile x l, one
 // lane per baseline); direction 0's also becomes the accepted and start point of the next LM run.
+// With kEnergy, also the residual's energy from the statistics, with R = V - sum_m c_m M_m:
+//   sum_s ||R_s||^2 = sum_s ||V_s||^2 - 2 Re sum_m <M_m, U_m> + sum_lm X_lm <M_l, M_m>
+//                   = Ev - Re sum_l <M_l, U_l + D_l>     (<A, B> = tr(A^H B), D_l = U_l - sum_m X_lm M_m)
+// each (tile, l) workgroup wavefront summing its baselines' terms (direction 0 with Ev) into
+// Epl[l][tile].  In FP64 the expansion cancels by about the ratio of the data's energy to the
+// residual's (~SNR), far inside the double's precision; at a perfect fit it leaves an absolute
+// error of order eps * sum ||V||^2.
+template <bool kEnergy>
 __global__ __launch_bounds__(64 * kStatTiles) void k_dall(Problem pb, Layout L, Buffers B) {
   const int tile = kStatTiles * blockIdx.x + (threadIdx.x >> 6), lane = threadIdx.x & 63, l = blockIdx.y;
-  if (tile >= pb.ntiles) return;
+  if (tile >= pb.ntiles) return;   // uniform per wavefront
   const int f = L.tile_f[tile];
   const int Kf = L.ndir[f], nb = L.nb[f];
   const int bi = L.tile_b0[tile] + lane;
-  if (l >= Kf || lane >= pb.bpt || bi >= nb) return;
-  const int K = pb.K, N = pb.N;
-  const int64_t gb = (int64_t)L.bl_off[f] + bi;
-  const int p = L.bl_p[gb], q = L.bl_q[gb];
-  const int64_t nbt = pb.nbt;
-  double d[8];
+  const bool live = l < Kf && lane < pb.bpt && bi < nb;
+  double part = 0.0;
+  if (live) {
+    const int K = pb.K, N = pb.N;
+    const int64_t gb = (int64_t)L.bl_off[f] + bi;
+    const int p = L.bl_p[gb], q = L.bl_q[gb];
+    const int64_t nbt = pb.nbt;
+    double d[8], u[8], ml[8];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) d[e] = B.Ucoh[((int64_t)l * nbt + gb) * 8 + e];
-  for (int m = 0; m < Kf; ++m) {
-    const double *Jm = B.J + ((int64_t)f * K + m) * N * 8;
-    const double *X = B.Xcoh + (((int64_t)l * K + m) * nbt + gb) * 2;
-    double mm[8];
-    jjh(Jm + 8 * p, Jm + 8 * q, mm);
-    sub_scaled(d, X[0], X[1], mm);
-  }
-  double *D = B.Dall + ((int64_t)l * nbt + gb) * 8;
+    for (int e = 0; e < 8; ++e) d[e] = u[e] = B.Ucoh[((int64_t)l * nbt + gb) * 8 + e];
+    for (int m = 0; m < Kf; ++m) {
+      const double *Jm = B.J + ((int64_t)f * K + m) * N * 8;
+      const double *X = B.Xcoh + (((int64_t)l * K + m) * nbt + gb) * 2;
+      double mm[8];
+      jjh(Jm + 8 * p, Jm + 8 * q, mm);
+      sub_scaled(d, X[0], X[1], mm);
+      if (kEnergy && m == l) {
 #pragma unroll
-  for (int e = 0; e < 8; ++e) D[e] = d[e];
-  if (l == 0) {
-    double *Da = d_accepted(B, f) + 8 * gb;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      Da[e] = d[e];
-      B.Dstart[8 * gb + e] = d[e];
+        for (int e = 0; e < 8; ++e) ml[e] = mm[e];
+      }
     }
+    double *D = B.Dall + ((int64_t)l * nbt + gb) * 8;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) D[e] = d[e];
+    if (l == 0) {
+      double *Da = d_accepted(B, f) + 8 * gb;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        Da[e] = d[e];
+        B.Dstart[8 * gb + e] = d[e];
+      }
+    }
+    if (kEnergy) {
+      double t = 0.0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) t = fma(ml[e], u[e] + d[e], t);   // Re <M_l, U_l + D_l>
+      part = (l == 0 ? B.Ev[gb] : 0.0) - t;
+    }
+  }
+  if (kEnergy) {
+    part = wave_sum(part);
+    if (lane == 0) B.Epl[(int64_t)l * pb.ntiles + tile] = part;
   }
 }
 
@@ -236,8 +262,9 @@ hipError_t launch_energy(const Problem &pb, const Layout &L, const Buffers &B, h
 
 // Per solution interval: pack the caller's visibilities and coherencies into the library's
 // baseline-major layout (flagged baselines dropped) and form every baseline's coherency statistics
-// in the same pass, in FP64 from the element type:
-//   S_b,l = sum_s |c_ls|^2,   U_l = sum_s conj(c_ls) V_s,   X_lm = sum_s conj(c_ls) c_ms.
+// and the energy of its visibilities in the same pass, in FP64 from the element type:
+//   S_b,l = sum_s |c_ls|^2,   U_l = sum_s conj(c_ls) V_s,   X_lm = sum_s conj(c_ls) c_ms,
+//   Ev_b = sum_s ||V_s||^2.
 // With the scalar coherency and J constant over a baseline's samples, everything the local steps
 // need from the samples besides the residual's energy follows from these: at a point with models
 // M_m, D_l = sum_s conj(c_ls) R_s = U_l - sum_m X_lm M_m.
@@ -301,7 +328,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
   C2 *cdst = reinterpret_cast<C2 *>(Cp + 2 * (L.coh_off[f] + (int64_t)bi * spb));
   const int64_t cs = Bfull * spb, cd = (int64_t)nb * spb;   // between directions (complex values)
   T *vl = Vs + j * VR;
-  double u[8] = {0, 0, 0, 0, 0, 0, 0, 0}, x[2 * G], sbl = 0.0;
+  double u[8] = {0, 0, 0, 0, 0, 0, 0, 0}, x[2 * G], sbl = 0.0, ev = 0.0;
 #pragma unroll
   for (int m = 0; m < 2 * G; ++m) x[m] = 0.0;
   bool finite = true;
@@ -345,6 +372,10 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
         double vv[8];
 #pragma unroll
         for (int e = 0; e < 8; ++e) vv[e] = (double)vl[8 * t + e];
+        if (l == 0) {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) ev = fma(vv[e], vv[e], ev);   // sum_s ||V_s||^2
+        }
         const T *ct = Cs + j * CR + 2 * t;         // direction m's value at ct[m * TB * CR]
         const double cr = (double)ct[l * TB * CR], ci = (double)ct[l * TB * CR + 1];
         sbl = fma(cr, cr, fma(ci, ci, sbl));       // X_ll, kept apart: x is indexed statically
@@ -369,6 +400,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
     if (bad) atomicOr(bad, 1);
     if (status) atomicOr(status + f, 5);   // CALIB_E_NUMERIC
   }
+  if (l == 0) B.Ev[gb] = ev;
   if (l >= Kf) return;
   const int64_t nbt = pb.nbt;
   double2 *U2 = reinterpret_cast<double2 *>(B.Ucoh + ((int64_t)l * nbt + gb) * 8);
@@ -432,8 +464,15 @@ hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, 
   const hipError_t e = launch_energy<T>(pb, L, B, s);
   if (e != hipSuccess || pb.ntiles == 0) return e;
   if (pb.bpt > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dall, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles, pb.K), dim3(64 * kStatTiles),
-                     0, s, pb, L, B);
+  hipLaunchKernelGGL(k_dall<false>, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles, pb.K),
+                     dim3(64 * kStatTiles), 0, s, pb, L, B);
+  return hipGetLastError();
+}
+hipError_t launch_refresh_stats(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
+  if (pb.ntiles == 0) return hipSuccess;
+  if (pb.bpt > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dall<true>, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles, pb.K),
+                     dim3(64 * kStatTiles), 0, s, pb, L, B);
   return hipGetLastError();
 }
 template <typename T>
