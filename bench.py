@@ -31,8 +31,9 @@ value = subbands x steps / wall time of the learned steps (subband-solves per se
 Also reported: training cost of the network (pairs, epochs, seconds), per-kernel time breakdown and
 the roofline of the dominant kernel (HIP events on the library's stream around every launch, in a
 separate untimed pass; algorithmic FLOPs from the solver's work counters), the bandwidth of the
-HBM-streaming passes, the FP32-vs-FP64 accuracy of the data cost, and the FP64 CPU oracle timed on
-a bounded sample of the same workload from the same previous state.
+per-interval pack (the pass over the samples; the metric's "HBM GB/s") and of the per-iteration
+refresh (statistics only with solver 3), the FP32-vs-FP64 accuracy of the data cost, and the FP64
+CPU oracle timed on a bounded sample of the same workload from the same previous state.
 """
 from __future__ import annotations
 
@@ -89,12 +90,16 @@ def local_step_flops(data, work, launches):
                         + lm * (8.0 * N * N + 304.0 * nb + 132.0 * N) + per_dir))
 
 
-def stream_bytes(name, data, elt):
-    """Algorithmic HBM bytes of one launch of an HBM-streaming pass."""
+def stream_bytes(name, data, elt, solver=3):
+    """Algorithmic bytes of one launch of the refresh or of the per-interval pack."""
     N, K = int(data["N"]), int(data["K"])
     nb = data["nb_live"].astype(np.float64)
     Kf = np.asarray(data["n_dirs"], np.float64)
     S_f = nb * data["T"] * np.asarray(data["n_chan"], np.float64)   # samples per subband
+    if name == "refresh" and solver == 3:
+        # every direction's D_l and the energy from the statistics: U_l and the row X_l. read, D_l
+        # written per (baseline, direction); Ev read and the run's start D_b written per baseline
+        return float(np.sum(nb * Kf * (64.0 + 16.0 * Kf + 64.0) + nb * (8.0 + 128.0)))
     if name == "refresh":
         # the residual's energy: V and every direction's coherency streamed once; then every
         # direction's D_b from U_l and X_lm
@@ -389,7 +394,7 @@ def main():
                        "lm_solves_per_launch": float(work[:, 1].sum() / launches),
                        "workgroups": P})
         elif dom in ("refresh", "pack"):
-            nbytes = stream_bytes(dom, data, elt)
+            nbytes = stream_bytes(dom, data, elt, args.solver)
             achieved = nbytes / avg_s / 1e9
             rl.update({"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS,
@@ -399,7 +404,7 @@ def main():
         for name in ("refresh", "pack"):
             if kt[name][0]:
                 n, t_ms = kt[name]
-                out[f"{name}_pass_GBs"] = stream_bytes(name, data, elt) / (t_ms / n / 1e3) / 1e9
+                out[f"{name}_pass_GBs"] = stream_bytes(name, data, elt, args.solver) / (t_ms / n / 1e3) / 1e9
         log(f"kernels: {out['kernel_ms_per_step']}")
 
     if not args.no_cpu_baseline:

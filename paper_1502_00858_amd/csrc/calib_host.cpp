@@ -210,7 +210,7 @@ calib_status run_local_step(calib_ctx *c, int admm_iter, hipStream_t s) {
     // every D_l and the residual's energy from the coherency statistics (no pass over the
     // samples), then every subband's whole local step in one launch: the LM runs, the stopping
     // rule and the SAGE commits stay on the device
-    HIPCHK(c, timed(c, CALIB_KERNEL_REFRESH, [&] { return launch_refresh_stats(pb, L, B, s); }));
+    HIPCHK(c, timed(c, CALIB_KERNEL_REFRESH, [&] { return launch_refresh_stats(pb, L, B, false, s); }));
     HIPCHK(c, timed(c, CALIB_KERNEL_LOCAL_STEP, [&] {
       return launch_local_step(pb, L, B, unreg, c->lm_trace, c->lm_iters, c->sage_sweeps, s);
     }));
@@ -772,10 +772,10 @@ calib_status calib_warmstart_features(calib_ctx *ctx, const void *jones_prev2, c
   const Buffers &B = ctx->B;
   const double *J2 = static_cast<const double *>(jones_prev2);
   const double *BZp = static_cast<const double *>(bz_prev);
-  // residual at the current J and the per-baseline sums of direction 0; each direction's
-  // statistics follow from a commit with an unchanged J (start point = current point)
-  HIPCHK(ctx, ctx->precision == CALIB_FP64 ? launch_refresh<double>(pb, L, B, s)
-                                           : launch_refresh<float>(pb, L, B, s));
+  // residual's energy and per-baseline sums at the current J (from the coherency statistics);
+  // each direction's statistics follow from a commit with an unchanged J (start point = current
+  // point)
+  HIPCHK(ctx, launch_refresh_stats(pb, L, B, true, s));
   for (int k = 0; k < ctx->K; ++k) {
     HIPCHK(ctx, launch_lm_begin(pb, L, B, k, 1, s));
     HIPCHK(ctx, launch_ws_features(pb, L, B, k, J2, BZp, features, s));
@@ -801,9 +801,9 @@ calib_status calib_warmstart_apply(calib_ctx *ctx, const float *delta, int32_t *
   const Layout &L = ctx->L;
   const Buffers &B = ctx->B;
   double *cost0 = ctx->ws_cost, *cost1 = ctx->ws_cost + ctx->P;
+  // data cost per subband from the coherency statistics (no pass over the samples)
   auto cost = [&](double *out) -> hipError_t {
-    hipError_t e = ctx->precision == CALIB_FP64 ? launch_refresh<double>(pb, L, B, s)
-                                                : launch_refresh<float>(pb, L, B, s);
+    const hipError_t e = launch_refresh_stats(pb, L, B, true, s);
     return e == hipSuccess ? launch_subband_cost(pb, L, B, out, s) : e;
   };
   HIPCHK(ctx, cost(cost0));

@@ -139,8 +139,9 @@ __device__ inline double *d_trial(const Buffers &B, const LmState &st) { return 
 template <typename T>
 hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
 // the refresh without a pass over the samples: every D_l and the residual's energy from the
-// coherency statistics (into Epl), for the one-launch local step
-hipError_t launch_refresh_stats(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
+// coherency statistics (into Epl; with fold, also into the tiles' Epart and cost_part)
+hipError_t launch_refresh_stats(const Problem &pb, const Layout &L, const Buffers &B, bool fold,
+                                hipStream_t s);
 template <typename T>
 hipError_t launch_commit(const Problem &pb, const Layout &L, const Buffers &B, int k, int all,
                          hipStream_t s);

@@ -219,6 +219,17 @@ __global__ __launch_bounds__(64 * kStatTiles) void k_dall(Problem pb, Layout L, 
   }
 }
 
+// The tiles' energies (Epart, cost_part) from the statistics' per-(direction, tile) terms, for the
+// kernels that read the energy per tile
+__global__ __launch_bounds__(kBlock) void k_fold_energy(Problem pb, Buffers B) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= pb.ntiles) return;
+  double e = 0.0;
+  for (int l = 0; l < pb.K; ++l) e += B.Epl[(int64_t)l * pb.ntiles + t];
+  B.Epart[t] = e;
+  B.cost_part[t] = e;
+}
+
 // End of direction k's LM run (the SAGE commit, lmd::commit_tile), one wavefront per tile.
 __global__ __launch_bounds__(64 * kStatTiles) void k_commit_stats(Problem pb, Layout L, Buffers B, int k,
                                                                    int all) {
@@ -468,11 +479,14 @@ hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, 
                      dim3(64 * kStatTiles), 0, s, pb, L, B);
   return hipGetLastError();
 }
-hipError_t launch_refresh_stats(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
+hipError_t launch_refresh_stats(const Problem &pb, const Layout &L, const Buffers &B, bool fold,
+                                hipStream_t s) {
   if (pb.ntiles == 0) return hipSuccess;
   if (pb.bpt > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_dall<true>, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles, pb.K),
                      dim3(64 * kStatTiles), 0, s, pb, L, B);
+  if (!fold) return hipGetLastError();
+  hipLaunchKernelGGL(k_fold_energy, dim3((pb.ntiles + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pb, B);
   return hipGetLastError();
 }
 template <typename T>
