@@ -28,6 +28,7 @@ struct calib_mlp {
   unsigned short *dZ0 = nullptr, *dZ1 = nullptr;
   double *part = nullptr;
   double *cpart = nullptr;   // column-sum partials
+  float *ws = nullptr;       // split-k partial sums of the GEMMs
   std::string err;
 
   template <typename T>
@@ -60,7 +61,7 @@ calib_status forward(calib_mlp *m, const float *x, int64_t rows, float *y) {
   MCHK(m, mlp_to_bf16(x, m->Xb[0], rows * m->dims[0], s));
   for (int l = 0; l < m->L; ++l) {
     const int in = m->dims[l], out = m->dims[l + 1];
-    MCHK(m, mlp_gemm(m->Xb[l], false, m->Wb[l], false, m->C, (int)rows, out, in, s));
+    MCHK(m, mlp_gemm(m->Xb[l], false, m->Wb[l], false, m->C, (int)rows, out, in, m->ws, s));
     const bool last = (l == m->L - 1);
     MCHK(m, mlp_bias_act(m->C, m->b[l], last ? nullptr : m->Z[l], last ? nullptr : m->Xb[l + 1],
                          last ? (y ? y : m->Y) : nullptr, rows, out, !last, s));
@@ -131,7 +132,8 @@ calib_status calib_mlp_create(int32_t n_layers, const int32_t *dims, const float
   const size_t big = (size_t)max_rows * m->maxd;
   if (m->alloc(&m->C, big) || m->alloc(&m->Y, (size_t)max_rows * m->dims[m->L]) ||
       m->alloc(&m->dA, big) || m->alloc(&m->dZ0, big) || m->alloc(&m->dZ1, big) ||
-      m->alloc(&m->part, kLossParts) || m->alloc(&m->cpart, (size_t)mlp_colsum_scratch(m->maxd)))
+      m->alloc(&m->part, kLossParts) || m->alloc(&m->cpart, (size_t)mlp_colsum_scratch(m->maxd)) ||
+      m->alloc(&m->ws, (size_t)mlp_gemm_scratch()))
     return oom();
   if (hipStreamSynchronize(m->stream) != hipSuccess) {
     calib_mlp_destroy(m);
@@ -161,11 +163,11 @@ calib_status calib_mlp_train_step(calib_mlp *m, const float *x, const float *tar
   for (int l = L - 1; l >= 0; --l) {
     const int in = m->dims[l], out = m->dims[l + 1];
     // dW_l = X_l^T dZ_l, db_l = column sums of dZ_l
-    MCHK(m, mlp_gemm(m->Xb[l], true, dz, false, m->gW[l], in, out, (int)rows, s));
+    MCHK(m, mlp_gemm(m->Xb[l], true, dz, false, m->gW[l], in, out, (int)rows, m->ws, s));
     MCHK(m, mlp_colsum(dz, m->gb[l], m->cpart, rows, out, s));
     if (l > 0) {
       // dX_l = dZ_l W_l^T, then through the GELU of layer l-1
-      MCHK(m, mlp_gemm(dz, false, m->Wb[l], true, m->dA, (int)rows, in, out, s));
+      MCHK(m, mlp_gemm(dz, false, m->Wb[l], true, m->dA, (int)rows, in, out, m->ws, s));
       MCHK(m, mlp_gelu_back(m->dA, m->Z[l - 1], dz_next, rows * in, s));
       std::swap(dz, dz_next);
     }

@@ -6,8 +6,10 @@
 
 namespace calib {
 
+int mlp_gemm_scratch();   // floats of split-k partial sums mlp_gemm may use
+// C = A' B' (see k_gemm_bf16); ws (mlp_gemm_scratch() floats, or null: no k split)
 hipError_t mlp_gemm(const unsigned short *A, bool ta, const unsigned short *B, bool tb, float *C,
-                    int M, int N, int K, hipStream_t s);
+                    int M, int N, int K, float *ws, hipStream_t s);
 hipError_t mlp_bias_act(const float *C, const float *b, float *Z, unsigned short *Hb, float *Y,
                         int64_t rows, int n, bool act, hipStream_t s);
 hipError_t mlp_to_bf16(const float *x, unsigned short *y, int64_t n, hipStream_t s);

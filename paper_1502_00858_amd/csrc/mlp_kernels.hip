@@ -4,7 +4,9 @@
 #include "calib_internal.h"
 #include "mlp_internal.h"
 
+#include <algorithm>
 #include <cmath>
+#include <cstdint>
 
 namespace calib {
 
@@ -13,7 +15,8 @@ namespace {
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTM = 64, kTN = 64, kTK = 16;   // output tile and k step of one workgroup
+constexpr int kTM = 64, kTN = 64, kTK = 32;   // output tile and k step of one workgroup
+constexpr int kLdk = kTK + 8;                   // LDS row stride (80 bytes: conflict-free 8-byte reads)
 
 __device__ inline unsigned short bf16_rne(float x) {
   unsigned int u = __float_as_uint(x);
@@ -22,55 +25,97 @@ __device__ inline unsigned short bf16_rne(float x) {
 }
 __device__ inline float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
 
+// One k step's share of an operand tile (64 rows x 32 k) for one thread: 8 elements, as one
+// 16-byte load where the run is whole and aligned.  KC: the operand is stored [rows][K] (k
+// contiguous: the thread takes row t/4, k 8(t%4)..+7); else stored [K][rows] (rows contiguous: k
+// t/8, rows 8(t%8)..+7).  Elements outside rows < R, k < kend read as zero.
+template <bool KC>
+__device__ inline uint4 fetch8(const unsigned short *X, int R, int K, int r0, int k0, int kend,
+                               bool vec) {
+  const int t = threadIdx.x;
+  const int r = r0 + (KC ? t >> 2 : (t & 7) * 8), k = k0 + (KC ? (t & 3) * 8 : t >> 3);
+  const bool whole = KC ? (r < R && k + 8 <= kend) : (k < kend && r + 8 <= R);
+  if (vec && whole)
+    return *reinterpret_cast<const uint4 *>(KC ? X + (int64_t)r * K + k : X + (int64_t)k * R + r);
+  unsigned short v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int re = KC ? r : r + e, ke = KC ? k + e : k;
+    v[e] = (re < R && ke < kend) ? (KC ? X[(int64_t)re * K + ke] : X[(int64_t)ke * R + re]) : 0;
+  }
+  uint4 u;
+  u.x = v[0] | ((unsigned)v[1] << 16);
+  u.y = v[2] | ((unsigned)v[3] << 16);
+  u.z = v[4] | ((unsigned)v[5] << 16);
+  u.w = v[6] | ((unsigned)v[7] << 16);
+  return u;
+}
+
+// Stores a thread's 8 elements into the [row][k] LDS tile (one 16-byte write when k is contiguous)
+template <bool KC>
+__device__ inline void put8(unsigned short (*S)[kLdk], uint4 u) {
+  const int t = threadIdx.x;
+  if (KC) {
+    *reinterpret_cast<uint4 *>(&S[t >> 2][(t & 3) * 8]) = u;
+  } else {
+    const int k = t >> 3, r = (t & 7) * 8;
+    const unsigned w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      S[r + 2 * e][k] = (unsigned short)(w[e] & 0xFFFFu);
+      S[r + 2 * e + 1][k] = (unsigned short)(w[e] >> 16);
+    }
+  }
+}
+
 // C[M][N] = A'[M][K] B'[K][N] (FP32 out).  A' = A (stored [M][K]) or A^T (A stored [K][M]);
 // B' = B (stored [K][N]) or B^T (B stored [N][K]).  Out-of-range elements load as zero.
+// Workgroup z of a split launch sums k in [z kchunk, (z+1) kchunk) into its own slice of ws
+// ([splits][M][N]), added in a fixed order afterwards; with one split it writes C.  The next k
+// step's operands are fetched into registers while the MFMAs consume the current one from LDS.
 // MFMA layouts (16x16x16 bf16): A lane l holds A[l%16][4(l/16)+e], B lane l holds
 // B[4(l/16)+e][l%16], accumulator element r of lane l is D[4(l/16)+r][l%16].
 template <bool TA, bool TB>
 __global__ __launch_bounds__(kBlock) void k_gemm_bf16(const unsigned short *A, const unsigned short *B,
-                                                      float *C, int M, int N, int K) {
-  __shared__ unsigned short As[kTM][kTK + 4];   // [m][k]
-  __shared__ unsigned short Bs[kTN][kTK + 4];   // [n][k]
+                                                      float *C, float *ws, int M, int N, int K,
+                                                      int kchunk, int avec, int bvec) {
+  __shared__ __align__(16) unsigned short As[kTM][kLdk];   // [m][k]
+  __shared__ __align__(16) unsigned short Bs[kTN][kLdk];   // [n][k]
   const int m0 = blockIdx.x * kTM, n0 = blockIdx.y * kTN;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;   // 2x2 waves, 32x32 each
   f4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += kTK) {
-    // consecutive threads walk the operand's contiguous dimension (coalesced loads)
-    for (int idx = tid; idx < kTM * kTK; idx += kBlock) {
-      const int mm = TA ? idx % kTM : idx / kTK, kk = TA ? idx / kTM : idx % kTK;
-      const int gm = m0 + mm, gk = k0 + kk;
-      unsigned short v = 0;
-      if (gm < M && gk < K) v = TA ? A[(int64_t)gk * M + gm] : A[(int64_t)gm * K + gk];
-      As[mm][kk] = v;
-    }
-    for (int idx = tid; idx < kTN * kTK; idx += kBlock) {
-      const int nn = TB ? idx / kTK : idx % kTN, kk = TB ? idx % kTK : idx / kTN;
-      const int gn = n0 + nn, gk = k0 + kk;
-      unsigned short v = 0;
-      if (gn < N && gk < K) v = TB ? B[(int64_t)gn * K + gk] : B[(int64_t)gk * N + gn];
-      Bs[nn][kk] = v;
-    }
+  uint4 ra = fetch8<!TA>(A, M, K, m0, kb, ke, avec), rb = fetch8<TB>(B, N, K, n0, kb, ke, bvec);
+  for (int k0 = kb; k0 < ke; k0 += kTK) {
+    put8<!TA>(As, ra);
+    put8<TB>(Bs, rb);
     __syncthreads();
-    s4 a[2], b[2];
+    if (k0 + kTK < ke) {
+      ra = fetch8<!TA>(A, M, K, m0, k0 + kTK, ke, avec);
+      rb = fetch8<TB>(B, N, K, n0, k0 + kTK, ke, bvec);
+    }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int ks = 0; ks < kTK; ks += 16) {
+      s4 a[2], b[2];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        a[i][e] = (short)As[wm + i * 16 + (lane & 15)][4 * (lane >> 4) + e];
-        b[i][e] = (short)Bs[wn + i * 16 + (lane & 15)][4 * (lane >> 4) + e];
+      for (int i = 0; i < 2; ++i) {
+        a[i] = *reinterpret_cast<const s4 *>(&As[wm + i * 16 + (lane & 15)][ks + 4 * (lane >> 4)]);
+        b[i] = *reinterpret_cast<const s4 *>(&Bs[wn + i * 16 + (lane & 15)][ks + 4 * (lane >> 4)]);
       }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
     __syncthreads();
   }
+  float *out = gridDim.z == 1 ? C : ws + (int64_t)blockIdx.z * M * N;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -78,8 +123,17 @@ __global__ __launch_bounds__(kBlock) void k_gemm_bf16(const unsigned short *A, c
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gm = m0 + wm + i * 16 + 4 * (lane >> 4) + r, gn = n0 + wn + j * 16 + (lane & 15);
-        if (gm < M && gn < N) C[(int64_t)gm * N + gn] = acc[i][j][r];
+        if (gm < M && gn < N) out[(int64_t)gm * N + gn] = acc[i][j][r];
       }
+}
+
+// C = sum over the splits of ws, in split order
+__global__ void k_splitk_sum(const float *ws, float *C, int64_t n, int splits) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = ws[i];
+  for (int z = 1; z < splits; ++z) s += ws[(int64_t)z * n + i];
+  C[i] = s;
 }
 
 __device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
@@ -182,13 +236,33 @@ inline unsigned blocks(int64_t n, int t = 256) { return (unsigned)((n + t - 1) /
 
 }  // namespace
 
+int mlp_gemm_scratch() { return 256 * kTM * kTN; }
+
 hipError_t mlp_gemm(const unsigned short *A, bool ta, const unsigned short *B, bool tb, float *C,
-                    int M, int N, int K, hipStream_t s) {
-  dim3 grid((M + kTM - 1) / kTM, (N + kTN - 1) / kTN), block(kBlock);
-  if (!ta && !tb) hipLaunchKernelGGL((k_gemm_bf16<false, false>), grid, block, 0, s, A, B, C, M, N, K);
-  else if (ta && !tb) hipLaunchKernelGGL((k_gemm_bf16<true, false>), grid, block, 0, s, A, B, C, M, N, K);
-  else if (!ta && tb) hipLaunchKernelGGL((k_gemm_bf16<false, true>), grid, block, 0, s, A, B, C, M, N, K);
-  else hipLaunchKernelGGL((k_gemm_bf16<true, true>), grid, block, 0, s, A, B, C, M, N, K);
+                    int M, int N, int K, float *ws, hipStream_t s) {
+  if (M < 1 || N < 1 || K < 1) return hipErrorInvalidValue;
+  const int tiles_m = (M + kTM - 1) / kTM, tiles_n = (N + kTN - 1) / kTN;
+  const int tiles = tiles_m * tiles_n, ksteps = (K + kTK - 1) / kTK;
+  // split k over more workgroups when the output tiles alone fill under half the chip, each
+  // split keeping at least two k steps; split partial sums fit the scratch by construction
+  // (splits <= 256 / tiles and M N <= tiles kTM kTN)
+  int splits = 1;
+  if (ws && tiles < 128) splits = std::max(1, std::min(ksteps / 2, 256 / tiles));
+  const int kchunk = ((ksteps + splits - 1) / splits) * kTK;
+  splits = (K + kchunk - 1) / kchunk;
+  if (splits > 1 && (int64_t)splits * M * N > mlp_gemm_scratch()) return hipErrorInvalidValue;
+  auto aligned = [](const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  const int avec = aligned(A) && ((ta ? M : K) % 8 == 0);
+  const int bvec = aligned(B) && ((tb ? K : N) % 8 == 0);
+  dim3 grid(tiles_m, tiles_n, splits), block(kBlock);
+  if (!ta && !tb) hipLaunchKernelGGL((k_gemm_bf16<false, false>), grid, block, 0, s, A, B, C, ws, M, N, K, kchunk, avec, bvec);
+  else if (ta && !tb) hipLaunchKernelGGL((k_gemm_bf16<true, false>), grid, block, 0, s, A, B, C, ws, M, N, K, kchunk, avec, bvec);
+  else if (!ta && tb) hipLaunchKernelGGL((k_gemm_bf16<false, true>), grid, block, 0, s, A, B, C, ws, M, N, K, kchunk, avec, bvec);
+  else hipLaunchKernelGGL((k_gemm_bf16<true, true>), grid, block, 0, s, A, B, C, ws, M, N, K, kchunk, avec, bvec);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || splits == 1) return e;
+  const int64_t n = (int64_t)M * N;
+  hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ws, C, n, splits);
   return hipGetLastError();
 }
 
