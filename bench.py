@@ -162,16 +162,29 @@ def cpu_baseline(data, prev, iters_sample, iters_to_target, lm_iters, lm_tol, cg
                       f"iterations the plain start needs to reach the target"}
 
 
-def timed(fn, steps, warmup):
+def mark():
+    """A short spin kernel on torch's stream, run to completion: brackets a window of the kernel
+    trace (outside any timed region) for `prof_summary trace DIR --between spin_kernel`."""
+    import torch
+    torch.cuda._sleep(1000)
+    torch.cuda.synchronize()
+
+
+def timed(fn, steps, warmup, marked=False):
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    if marked:
+        mark()
     t0 = time.perf_counter()
     for _ in range(steps):
         fn()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    sec = (time.perf_counter() - t0) / steps
+    if marked:
+        mark()
+    return sec
 
 
 def main():
@@ -319,7 +332,7 @@ def main():
         def step():
             st()
             final[name] = c.solve(n_it)
-        sec[name] = timed(step, args.steps, args.warmup)
+        sec[name] = timed(step, args.steps, args.warmup, marked=name == "learned")
         log(f"{name}: {1e3 * sec[name]:.2f} ms per step ({n_it} iterations)")
     kept = start_learned().cpu().numpy()
     ws_s = timed(start_learned, max(args.steps, 3), 1) - timed(start_plain, max(args.steps, 3), 1)

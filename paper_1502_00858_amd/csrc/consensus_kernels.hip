@@ -210,16 +210,26 @@ __global__ __launch_bounds__(kZThreads) void k_z_fit(Problem pb, Layout L, Buffe
   const int k = blockIdx.x, N = pb.N, P = pb.P, Q = pb.Q;
   const double rho = B.rho[k];
   const double *W = B.fitw + (int64_t)k * Q * P;
+  constexpr int kF = 8;   // subbands whose J and Y entries are requested before the first is used
   double dz = 0.0;
   for (int e = threadIdx.x; e < 8 * N; e += kZThreads) {
     double z[8];
     for (int l = 0; l < Q; ++l) z[l] = 0.0;
-#pragma unroll 8
-    for (int f = 0; f < P; ++f) {
-      if (L.ndir[f] <= k) continue;
-      const int64_t o = ((int64_t)f * pb.K + k) * N * 8 + e;
-      const double x = (rho > 0.0) ? B.J[o] + B.Y[o] / rho : B.J[o];
-      for (int l = 0; l < Q; ++l) z[l] += W[l * P + f] * x;
+    for (int f0 = 0; f0 < P; f0 += kF) {
+      double jv[kF], yv[kF];
+#pragma unroll
+      for (int u = 0; u < kF; ++u) {
+        const int64_t o = ((int64_t)min(f0 + u, P - 1) * pb.K + k) * N * 8 + e;
+        jv[u] = B.J[o];
+        yv[u] = B.Y[o];
+      }
+#pragma unroll
+      for (int u = 0; u < kF; ++u) {
+        const int f = f0 + u;
+        if (f >= P || L.ndir[f] <= k) continue;
+        const double x = (rho > 0.0) ? jv[u] + yv[u] / rho : jv[u];
+        for (int l = 0; l < Q; ++l) z[l] += W[l * P + f] * x;
+      }
     }
     for (int l = 0; l < Q; ++l) {
       const int64_t o = ((int64_t)k * Q + l) * N * 8 + e;

@@ -177,11 +177,14 @@ __global__ __launch_bounds__(kBlock) void k_mse(const float *Y, const float *T, 
   if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// one wavefront: lane l sums the partials l, l + 64, ... in order, then a butterfly over lanes
 __global__ void k_loss_final(const double *part, int nparts, int64_t total, float *loss) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int lane = threadIdx.x;
   double s = 0.0;
-  for (int i = 0; i < nparts; ++i) s += part[i];
-  loss[0] = (float)(s / (double)total);
+  for (int i = lane; i < nparts; i += 64) s += part[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) loss[0] = (float)(s / (double)total);
 }
 
 // gb[j] = sum over rows of dZ[r][j] (dZ stored BF16) in two fixed-order stages: workgroup

@@ -184,16 +184,35 @@ __global__ __launch_bounds__(64 * kStatTiles) void k_dall(Problem pb, Layout L, 
     double d[8], u[8], ml[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) d[e] = u[e] = B.Ucoh[((int64_t)l * nbt + gb) * 8 + e];
-    for (int m = 0; m < Kf; ++m) {
-      const double *Jm = B.J + ((int64_t)f * K + m) * N * 8;
-      const double *X = B.Xcoh + (((int64_t)l * K + m) * nbt + gb) * 2;
+    // direction m's J_p, J_q and X_lm, requested one direction ahead of their use
+    auto fetch = [&](int m, double *jp, double *jq, double *x) {
+      const double2 *P2 = reinterpret_cast<const double2 *>(B.J + (((int64_t)f * K + m) * N + p) * 8);
+      const double2 *Q2 = reinterpret_cast<const double2 *>(B.J + (((int64_t)f * K + m) * N + q) * 8);
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const double2 a = P2[h], b = Q2[h];
+        jp[2 * h] = a.x; jp[2 * h + 1] = a.y;
+        jq[2 * h] = b.x; jq[2 * h + 1] = b.y;
+      }
+      const double2 xv = *reinterpret_cast<const double2 *>(B.Xcoh + (((int64_t)l * K + m) * nbt + gb) * 2);
+      x[0] = xv.x; x[1] = xv.y;
+    };
+    auto use = [&](int m, const double *jp, const double *jq, const double *x) {
       double mm[8];
-      jjh(Jm + 8 * p, Jm + 8 * q, mm);
-      sub_scaled(d, X[0], X[1], mm);
+      jjh(jp, jq, mm);
+      sub_scaled(d, x[0], x[1], mm);
       if (kEnergy && m == l) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) ml[e] = mm[e];
       }
+    };
+    double jpa[8], jqa[8], xa[2], jpb[8], jqb[8], xb[2];
+    fetch(0, jpa, jqa, xa);
+    for (int m = 0; m < Kf; m += 2) {
+      if (m + 1 < Kf) fetch(m + 1, jpb, jqb, xb);
+      use(m, jpa, jqa, xa);
+      if (m + 2 < Kf) fetch(m + 2, jpa, jqa, xa);
+      if (m + 1 < Kf) use(m + 1, jpb, jqb, xb);
     }
     double *D = B.Dall + ((int64_t)l * nbt + gb) * 8;
 #pragma unroll

@@ -1,13 +1,16 @@
 """Summaries of rocprofv3 CSV output (kernel trace / stats, FETCH_SIZE and WRITE_SIZE passes).
 
-    python -m paper_1502_00858_amd.prof_summary trace DIR           # DIR: --kernel-trace --stats -o run
+    python -m paper_1502_00858_amd.prof_summary trace DIR [--between NAME]
+                                                # DIR: --kernel-trace --stats -o run
     python -m paper_1502_00858_amd.prof_summary pmc FETCH_DIR WRITE_DIR
 
 `trace` prints, per kernel, calls, total and average time and the average over dispatches longer
 than 5 us (launches whose subbands all stopped their LM runs exit at once), and, for the Cholesky
 solve, the wall time of each full solve: from the first kernel of a solve to the end of its last
 one (blocked solver: the panel launches + back substitution; one-workgroup solver: one launch).
-`pmc` prints per-dispatch FETCH_SIZE / WRITE_SIZE per kernel in MB, scaled by what the counters
+With --between NAME, only the dispatches that run after the first dispatch of a kernel whose name
+contains NAME ends and before the second one starts (bench.py brackets its timed steps of the
+learned start with such a kernel).  `pmc` prints per-dispatch FETCH_SIZE / WRITE_SIZE per kernel in MB, scaled by what the counters
 read for the 256 MiB device copy that profile_run ends with, and per-solve sums for the Cholesky.
 Output is markdown on stdout.
 """
@@ -35,8 +38,17 @@ def _one(dirname: str, suffix: str) -> str:
     return hits[0]
 
 
-def trace(dirname: str):
+def trace(dirname: str, between: str | None = None):
     rows = list(csv.DictReader(open(_one(dirname, "kernel_trace.csv"))))
+    if between:
+        marks = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows
+                       if between in r["Kernel_Name"])
+        if len(marks) < 2:
+            raise SystemExit(f"fewer than two dispatches of {between}")
+        lo, hi = marks[0][1], marks[1][0]
+        rows = [r for r in rows if int(r["Start_Timestamp"]) >= lo and int(r["End_Timestamp"]) <= hi]
+        print(f"Window: {len(rows)} dispatches over {(hi - lo) / 1e6:.2f} ms between the first two "
+              f"dispatches of {between}.\n")
     per = collections.defaultdict(list)
     seq = []
     for r in rows:
@@ -110,7 +122,7 @@ def pmc(fetch_dir: str, write_dir: str):
 
 if __name__ == "__main__":
     if len(sys.argv) >= 3 and sys.argv[1] == "trace":
-        trace(sys.argv[2])
+        trace(sys.argv[2], sys.argv[4] if len(sys.argv) >= 5 and sys.argv[3] == "--between" else None)
     elif len(sys.argv) >= 4 and sys.argv[1] == "pmc":
         pmc(sys.argv[2], sys.argv[3])
     else:

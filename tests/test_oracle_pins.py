@@ -455,3 +455,63 @@ def test_admm_continues_from_a_carried_state(oracle_mod, synth_mod):
     zero = np.zeros(pb.jshape(), np.complex128)
     cold = pb.admm_solve(J0, 2, zero, np.zeros(pb.zshape(), np.complex128), zero)
     np.testing.assert_array_equal(cold["trace"], first["trace"])
+
+
+def test_lm_damping_schedule_on_an_exact_quadratic(oracle_mod, synth_mod):
+    """Nielsen's damping (Madsen, Nielsen & Tingleff 2004, Sec. 3.2) in closed form.  With every
+    coherency zero the data term of M1 is the constant sum ||V||^2 and H_GN = 0, so the objective
+    is the quadratic penalty with Euclidean gradient G = Y + rho (J - B Z) and Hessian rho I.  The
+    LM step delta = -G / (rho + lambda) then decreases the objective by exactly the predicted
+    amount, |G|^2 (rho + 2 lambda) / (2 (rho + lambda)^2), so the gain ratio is 1: each step is
+    accepted, lambda starts at tau max diag = 1e-3 rho and falls by the rule's floor factor 1/3,
+    G shrinks by lambda / (rho + lambda), and each step lowers the objective by the fall of
+    |G|^2 / (2 rho), leaving J at |G| / rho from the minimiser B Z - Y / rho.  Within a few steps
+    the next step's true decrease falls below the objective's rounding; such steps are rejected
+    and lambda grows by nu = 2, 4, 8, ... (the reject branch)."""
+    rng = np.random.default_rng(23)
+    rho, iters = 3.0, 8
+    cfg = tiny_cfg(synth_mod, N=4, P=2, K=1, T=2, n_chan=2, rho=rho, lm_iters=iters)
+    d = synth_mod.generate(cfg)
+    d = dict(d, coh=np.zeros_like(d["coh"]))
+    pb = oracle_mod.Problem(d)
+    J0 = rand_jones(rng, cfg.P, 1, cfg.N)
+    Y = rand_jones(rng, cfg.P, 1, cfg.N, scale=0.5) - J0
+    BZ = rand_jones(rng, cfg.P, 1, cfg.N)
+    J, tr = pb.local_step(J0, Y, BZ, trace=True)
+    eps = np.finfo(float).eps
+    for f in range(cfg.P):
+        t = tr[f, 0, 0]
+        F_scale = abs(t[0, 0])
+        # closed-form accepted phase
+        lam = 1e-3 * rho
+        G = Y[f, 0] + rho * (J0[f, 0] - BZ[f, 0])
+        g2, lams = [np.sum(np.abs(G) ** 2)], []
+        for _ in range(iters):
+            G = G * lam / (rho + lam)
+            g2.append(np.sum(np.abs(G) ** 2))
+            lam /= 3.0
+            lams.append(lam)
+        rejected = np.nonzero(t[:, 2] == 0)[0]
+        n_acc = int(rejected[0]) if len(rejected) else iters
+        assert n_acc >= 2
+        assert np.all(t[:n_acc, 2] == 1)
+        np.testing.assert_allclose(t[:n_acc, 1], lams[:n_acc], rtol=1e-14)
+        for i in range(1, n_acc):
+            want = (g2[i] - g2[i + 1]) / (2 * rho)
+            assert abs((t[i - 1, 0] - t[i, 0]) - want) <= 64 * eps * F_scale
+        # the distance from the minimiser B Z - Y / rho after the accepted steps: |G| / rho
+        Jstar = BZ[f, 0] - Y[f, 0] / rho
+        dist = np.sqrt(np.sum(np.abs(J[f, 0] - Jstar) ** 2))
+        assert abs(dist - np.sqrt(g2[n_acc]) / rho) <= 1e-13 * np.max(np.abs(Jstar))
+        # the first rejected step's true decrease is below the objective's rounding, and each
+        # rejection in a row multiplies lambda by the next power of two
+        if n_acc < iters:
+            assert (g2[n_acc] - g2[n_acc + 1]) / (2 * rho) <= 8 * eps * F_scale
+            lam, nu = t[n_acc - 1, 1], 2.0
+            for i in range(n_acc, iters):
+                if t[i, 2] == 1:
+                    break
+                lam *= nu
+                nu *= 2.0
+                assert t[i, 1] == lam
+                assert t[i, 0] == t[n_acc - 1, 0]
