@@ -97,16 +97,17 @@ __device__ inline double objective(const Problem &pb, const Layout &L, const Buf
 }
 
 // Largest diagonal entry of H_GN + rho I of direction k of subband f at J (whole workgroup of
-// kBlock threads; result in every thread; J at a stride of js doubles per station):
+// NT threads; result in every thread; J at a stride of js doubles per station):
 // 2 sum_c S_pc (|J_c[0][j]|^2 + |J_c[1][j]|^2), from the column norms of the stations' Jones
-// matrices and the dense S.  Wavefront w sums the rows q of its quarter for every column p
-// (coalesced: lane p reads column p of row q, S being symmetric), the quarters are added in LDS.
+// matrices and the dense S.  Wavefront w sums the rows q of its share for every column p
+// (coalesced: lane p reads column p of row q, S being symmetric), the shares are added in LDS.
+template <int NT = kBlock>
 __device__ inline double max_diag(const Problem &pb, const Buffers &B, int f, int k, const double *J, int js) {
-  constexpr int kW = kBlock / 64;
+  constexpr int kW = NT / 64;
   __shared__ double nrm[2][kMaxStations];
   __shared__ double part[kW][2][kMaxStations];
-  __shared__ double mx[kBlock / 64];
-  for (int p = threadIdx.x; p < pb.N; p += kBlock) {
+  __shared__ double mx[NT / 64];
+  for (int p = threadIdx.x; p < pb.N; p += NT) {
     const double *Jp = J + js * p;
     nrm[0][p] = Jp[0] * Jp[0] + Jp[1] * Jp[1] + Jp[4] * Jp[4] + Jp[5] * Jp[5];
     nrm[1][p] = Jp[2] * Jp[2] + Jp[3] * Jp[3] + Jp[6] * Jp[6] + Jp[7] * Jp[7];
@@ -130,7 +131,7 @@ __device__ inline double max_diag(const Problem &pb, const Buffers &B, int f, in
   }
   __syncthreads();
   double dmax = 0.0;
-  for (int p = threadIdx.x; p < pb.N; p += kBlock) {
+  for (int p = threadIdx.x; p < pb.N; p += NT) {
     double d0 = 0.0, d1 = 0.0;
 #pragma unroll
     for (int w = 0; w < kW; ++w) {
@@ -143,7 +144,7 @@ __device__ inline double max_diag(const Problem &pb, const Buffers &B, int f, in
   if ((threadIdx.x & 63) == 0) mx[threadIdx.x >> 6] = dmax;
   __syncthreads();
   double m = 0.0;
-  for (int i = 0; i < kBlock / 64; ++i) m = fmax(m, mx[i]);
+  for (int i = 0; i < NT / 64; ++i) m = fmax(m, mx[i]);
   return m;
 }
 

@@ -32,8 +32,10 @@
 namespace calib {
 namespace {
 
-constexpr int kPcgThreads = 256;
-constexpr int kPcgWaves = kPcgThreads / 64;
+// threads of the one-launch local step: eight wavefronts (two per SIMD) for N <= 64, four for
+// N <= 128 (whose per-lane state, two stations per lane, leaves room for one wavefront per SIMD)
+template <int SPL>
+constexpr int pcg_threads() { return SPL == 1 ? 512 : 256; }
 
 // c = a b for 2x2 complex matrices (8 doubles, row-major re/im)
 __device__ inline void cmul(const double *a, const double *b, double *c) {
@@ -101,16 +103,17 @@ __device__ inline void gram(const double *Jq, double *v) {
 constexpr int kJS = 10;
 
 // LDS of one solve; SPL: stations per lane of wavefront 0 (1 for N <= 64, 2 for N <= 128)
-template <int SPL>
+template <int SPL, int NW = pcg_threads<SPL>() / 64>
 struct PcgLds {
   double Js[64 * SPL * kJS];                // J of the direction
   double Us[64 * SPL * kJS];                // u_q = d_q^H J_q
-  double Wp[kPcgWaves][8][64 * SPL];        // per-wavefront partials over its columns,
+  double Wp[NW][8][64 * SPL];               // per-wavefront partials over its columns,
                                             // component-major (lane-consecutive, no bank conflicts)
+  double Gs[8][64 * SPL];                   // the gradient, component-major, for the record
   int ctl[2];                               // continue, failed
 };
 
-// The gradient and the solve of direction k of subband f (whole workgroup of kPcgThreads) at the
+// The gradient and the solve of direction k of subband f (whole workgroup) at the
 // current J (sh.Js), with the direction's Y and B_f Z in LDS (Ys, BZs, 8 doubles per station): G
 // and the step delta to the record (CALIB_FIELD_LM_STEP), the trial point J + delta into jt_lds,
 // the predicted decrease into the LM state st (chol_ok = 0 on a failed solve).  Wavefronts 1-3
@@ -119,9 +122,10 @@ template <int SPL>
 __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
                                  int unreg, double tol, PcgLds<SPL> &sh, double *jt_lds, LmState *st,
                                  const double *Ys, const double *BZs) {
+  constexpr int kPcgWaves = pcg_threads<SPL>() / 64;
   constexpr int kRows = 64 * SPL;               // stations covered
   constexpr int kC = kRows / kPcgWaves;          // columns per wavefront (at most)
-  constexpr int kBatch = 8 / SPL;                // baselines of the gradient in flight per lane
+  constexpr int kBatch = 32 / (SPL * kPcgWaves); // baselines of the gradient in flight per lane
   double *Js = sh.Js, *Us = sh.Us;
   auto &Wp = sh.Wp;
   int *ctl = sh.ctl;
@@ -262,7 +266,7 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
   __syncthreads();
 
   // wavefront 0: right-hand side b = -G, preconditioner (2 Q_p + mu I)^-1, x = 0, r = b, d = z
-  double x[SPL][8], r[SPL][8], dv[SPL][8], g[SPL][8], Mi[SPL][4];
+  double x[SPL][8], r[SPL][8], dv[SPL][8], Mi[SPL][4];
   double bb = 0.0, rz = 0.0, stop = 0.0;
   int failed = 0;
   const int maxit = 8 * N;
@@ -277,10 +281,11 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
 #pragma unroll
         for (int i = 0; i < kPcgWaves; ++i) v += Wp[i][e][p];
         if (live && !unreg) v += Ys[8 * p + e] + rho * (Js[kJS * p + e] - BZs[8 * p + e]);
-        g[s][e] = live ? v : 0.0;
+        const double gv = live ? v : 0.0;
+        sh.Gs[e][p] = gv;
         Jp[s][e] = live ? Js[kJS * p + e] : 0.0;
         x[s][e] = 0.0;
-        r[s][e] = -g[s][e];
+        r[s][e] = -gv;
         bb = fma(r[s][e], r[s][e], bb);
       }
       const double a = 2.0 * Qp[s][0] + mu, dd = 2.0 * Qp[s][1] + mu;
@@ -422,10 +427,11 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int c = 8 * p + e;
+      const double gv = sh.Gs[e][p];
       B.delta[(int64_t)f * nf + c] = x[s][e];
-      B.G[(int64_t)f * nf + c] = g[s][e];
+      B.G[(int64_t)f * nf + c] = gv;
       jt_lds[kJS * p + e] = Jp[s][e] + x[s][e];
-      ell = fma(x[s][e], fma(lam, x[s][e], -g[s][e]), ell);
+      ell = fma(x[s][e], fma(lam, x[s][e], -gv), ell);
     }
   }
   ell = wave_sum(ell);
@@ -443,8 +449,8 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
 // latency).  The Jones matrices are read from LDS.  Energy partials are summed over the workgroup
 // and kept in the subband's first tile (the objective adds the tiles of a subband).
 constexpr int kQuad = 4;                    // lanes per baseline
-constexpr int kBpr = kBlock / kQuad;        // baselines per round
-constexpr int kU = 8;                       // rounds per batch
+template <int NT>
+constexpr int rounds() { return 2048 / NT; }   // rounds per batch: 512 baselines per batch
 
 // entry (i, j) of a_p a_q^H for the stations' 2x2 complex matrices in LDS (kJS doubles each)
 __device__ inline double2 jjh_entry(const double *A, int p, int q, int i, int j) {
@@ -460,10 +466,13 @@ __device__ inline double2 jjh_entry(const double *A, int p, int q, int i, int j)
 }
 
 // Data cost (returned to every thread) and D_b at the trial point Jt from the start point J0's
-// statistics (lmd::trial_tile); st: the subband's LM state
+// statistics (lmd::trial_tile); st: the subband's LM state; NT threads
+template <int NT>
 __device__ inline double fused_trial(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
                                      const double *Jt, const double *J0, const LmState *st,
-                                     double (*red)[kBlock / 64]) {
+                                     double (*red)[NT / 64]) {
+  constexpr int kBpr = NT / kQuad;   // baselines per round
+  constexpr int kU = rounds<NT>();
   const int nb = L.nb[f];
   const int64_t b0 = L.bl_off[f];
   const double *Sb = B.Sb + L.sb_off[f] + (int64_t)k * nb;
@@ -505,7 +514,7 @@ __device__ inline double fused_trial(const Problem &pb, const Layout &L, const B
     else batch(base, std::false_type{});
   }
   double v[1] = {part};
-  lmd::block_sum_vec<1>(v, reinterpret_cast<double (*)[kBlock / 64]>(red));
+  lmd::block_sum_vec<1, NT>(v, red);
   return v[0] + st->E0;
 }
 
@@ -514,9 +523,12 @@ __device__ inline double fused_trial(const Problem &pb, const Layout &L, const B
 // energy changes by sum_b X_kk ||dM||^2 - 2 Re <dM, D_k> (returned to every thread).  dM is formed
 // once per baseline; the directions are walked with the next one's D_l and X_lk requested before
 // the current one's are stored.
+template <int NT>
 __device__ inline double fused_commit(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
                                       int all, const double *J1, const double *J0, const LmState *st,
-                                      double (*red)[kBlock / 64]) {
+                                      double (*red)[NT / 64]) {
+  constexpr int kBpr = NT / kQuad;   // baselines per round
+  constexpr int kU = rounds<NT>();
   const int Kf = L.ndir[f], nb = L.nb[f], K = pb.K, next = k + 1 < Kf ? k + 1 : 0;
   const int64_t b0 = L.bl_off[f], nbt = pb.nbt;
   const int l0 = all ? 0 : k;
@@ -588,21 +600,22 @@ __device__ inline double fused_commit(const Problem &pb, const Layout &L, const 
     else batch(base, std::false_type{});
   }
   double v[1] = {part};
-  lmd::block_sum_vec<1>(v, reinterpret_cast<double (*)[kBlock / 64]>(red));
+  lmd::block_sum_vec<1, NT>(v, red);
   return v[0];   // the change of the residual's energy
 }
 
-// Re tr(Y^H (J - BZ)) + rho/2 ||J - BZ||^2 of the direction (whole workgroup; result in every
-// thread): J in LDS at kJS doubles per station, Y and B_f Z in LDS at 8
+// Re tr(Y^H (J - BZ)) + rho/2 ||J - BZ||^2 of the direction (whole workgroup of NT threads;
+// result in every thread): J in LDS at kJS doubles per station, Y and B_f Z in LDS at 8
+template <int NT>
 __device__ inline double penalty_lds(int N, double rho, const double *Jx, const double *Ys,
-                                     const double *BZs, double (*red)[kBlock / 64]) {
+                                     const double *BZs, double (*red)[NT / 64]) {
   double pen = 0.0;
-  for (int e = threadIdx.x; e < 8 * N; e += kBlock) {
+  for (int e = threadIdx.x; e < 8 * N; e += NT) {
     const double d = Jx[kJS * (e >> 3) + (e & 7)] - BZs[e];
     pen += Ys[e] * d + 0.5 * rho * d * d;
   }
   double v[1] = {pen};
-  lmd::block_sum_vec<1>(v, red);
+  lmd::block_sum_vec<1, NT>(v, red);
   return v[0];
 }
 
@@ -615,13 +628,14 @@ __device__ inline double penalty_lds(int N, double rho, const double *Jx, const 
 // per-(direction, tile) terms at the start, then moved by each commit).  The LM state and the energy are
 // written back at the end (the energy into the subband's first tile, the others zero).
 template <int SPL>
-__global__ __launch_bounds__(kPcgThreads) void k_local_step(Problem pb, Layout L, Buffers B, int unreg,
-                                                            double *lm_trace, int lm_iters, int sweeps) {
+__global__ __launch_bounds__(pcg_threads<SPL>()) void k_local_step(Problem pb, Layout L, Buffers B, int unreg,
+                                                                   double *lm_trace, int lm_iters, int sweeps) {
+  constexpr int NT = pcg_threads<SPL>();
   constexpr int kRows = 64 * SPL;
   __shared__ __align__(16) PcgLds<SPL> sh;
   __shared__ __align__(16) double J0s[kRows * kJS];   // the run's start point
   __shared__ __align__(16) double Ys[kRows * 8], BZs[kRows * 8];
-  __shared__ double red[1][kBlock / 64];
+  __shared__ double red[1][NT / 64];
   __shared__ LmState lst;
   __shared__ int acc;
   const int f = blockIdx.x;
@@ -632,16 +646,16 @@ __global__ __launch_bounds__(kPcgThreads) void k_local_step(Problem pb, Layout L
   double E;   // energy of the current residual, from the statistics' per-(direction, tile) terms
   {
     double v[1] = {0.0};
-    for (int t = t0 + threadIdx.x; t < t1; t += kBlock)
+    for (int t = t0 + threadIdx.x; t < t1; t += NT)
       for (int l = 0; l < Kf; ++l) v[0] += B.Epl[(int64_t)l * pb.ntiles + t];
-    lmd::block_sum_vec<1>(v, red);
+    lmd::block_sum_vec<1, NT>(v, red);
     E = v[0];
   }
   for (int sw = 0; sw < sweeps; ++sw)
     for (int k = 0; k < Kf; ++k) {
       const double rho = unreg ? 0.0 : B.rho[k];
       const int64_t jo = ((int64_t)f * pb.K + k) * n8;
-      for (int e = threadIdx.x; e < 8 * kRows; e += kBlock) {
+      for (int e = threadIdx.x; e < 8 * kRows; e += NT) {
         const double j = e < n8 ? B.J[jo + e] : 0.0;   // zero past the last station
         sh.Js[kJS * (e >> 3) + (e & 7)] = j;
         J0s[kJS * (e >> 3) + (e & 7)] = j;
@@ -651,8 +665,8 @@ __global__ __launch_bounds__(kPcgThreads) void k_local_step(Problem pb, Layout L
         }
       }
       __syncthreads();
-      const double F = E + (unreg ? 0.0 : penalty_lds(N, rho, sh.Js, Ys, BZs, red));
-      const double md = lmd::max_diag(pb, B, f, k, sh.Js, kJS) + rho;
+      const double F = E + (unreg ? 0.0 : penalty_lds<NT>(N, rho, sh.Js, Ys, BZs, red));
+      const double md = lmd::max_diag<NT>(pb, B, f, k, sh.Js, kJS) + rho;
       if (threadIdx.x == 0) lmd::begin_state(B, f, &lst, F, E, md, false, 0, 0);
       __syncthreads();
       if (lst.done && threadIdx.x == 0)   // a run that cannot start (non-finite state): trace rows only
@@ -663,23 +677,23 @@ __global__ __launch_bounds__(kPcgThreads) void k_local_step(Problem pb, Layout L
         const int ok = lst.chol_ok;
         double Fn = 0.0;
         if (ok)
-          Fn = fused_trial(pb, L, B, f, k, sh.Us, J0s, &lst, red) +
-               (unreg ? 0.0 : penalty_lds(N, rho, sh.Us, Ys, BZs, red));
+          Fn = fused_trial<NT>(pb, L, B, f, k, sh.Us, J0s, &lst, red) +
+               (unreg ? 0.0 : penalty_lds<NT>(N, rho, sh.Us, Ys, BZs, red));
         if (threadIdx.x == 0) acc = lmd::update_state(pb, B, f, k, &lst, ok, Fn, lm_trace, it, lm_iters, false);
         __syncthreads();
         if (acc)   // the trial point is the new J
-          for (int e = threadIdx.x; e < n8; e += kBlock) {
+          for (int e = threadIdx.x; e < n8; e += NT) {
             const double j = sh.Us[kJS * (e >> 3) + (e & 7)];
             sh.Js[kJS * (e >> 3) + (e & 7)] = j;
             B.J[jo + e] = j;
           }
         __syncthreads();
       }
-      E += fused_commit(pb, L, B, f, k, all, sh.Js, J0s, &lst, red);
+      E += fused_commit<NT>(pb, L, B, f, k, all, sh.Js, J0s, &lst, red);
       __syncthreads();
     }
   if (threadIdx.x == 0) B.lm[f] = lst;
-  for (int t = t0 + threadIdx.x; t < t1; t += kBlock) {
+  for (int t = t0 + threadIdx.x; t < t1; t += NT) {
     const double v = t == t0 ? E : 0.0;
     B.Epart[t] = v;
     B.cost_part[t] = v;
@@ -692,10 +706,10 @@ hipError_t launch_local_step(const Problem &pb, const Layout &L, const Buffers &
                              double *lm_trace, int lm_iters, int sweeps, hipStream_t s) {
   if (pb.N > kMaxStations || pb.bpt > 64) return hipErrorInvalidValue;
   if (pb.N <= 64)
-    hipLaunchKernelGGL(k_local_step<1>, dim3(pb.P), dim3(kPcgThreads), 0, s, pb, L, B, unreg, lm_trace,
+    hipLaunchKernelGGL(k_local_step<1>, dim3(pb.P), dim3(pcg_threads<1>()), 0, s, pb, L, B, unreg, lm_trace,
                        lm_iters, sweeps);
   else
-    hipLaunchKernelGGL(k_local_step<2>, dim3(pb.P), dim3(kPcgThreads), 0, s, pb, L, B, unreg, lm_trace,
+    hipLaunchKernelGGL(k_local_step<2>, dim3(pb.P), dim3(pcg_threads<2>()), 0, s, pb, L, B, unreg, lm_trace,
                        lm_iters, sweeps);
   return hipGetLastError();
 }
