@@ -3,7 +3,8 @@
 At full size the oracle checks what it can compute one subband at a time: the first local step
 (Y = Z = 0, so subbands are independent) of sampled subbands of c2 (62 stations, 5 directions,
 32 subbands x 4 channels) and of the batched c3 (256 subbands, 1-16 channels, 3-10 directions,
-0-30% flagged baselines), and one whole C-ADMM iteration of c2.  FP32 streaming against the FP64
+0-30% flagged baselines), and whole C-ADMM iterations of c2, with the Cholesky solvers and with
+the benchmark's solver settings.  FP32 streaming against the FP64
 oracle on the FP32-rounded inputs: 1e-5 relative on data costs.
 """
 import numpy as np
@@ -34,7 +35,7 @@ def _data(synth_mod, name):
     return _DATA[name]
 
 
-def _first_local_step_sampled(cal, oracle_mod, synth_mod, name, sample, **shape):
+def _first_local_step_sampled(cal, oracle_mod, synth_mod, name, sample, oracle_kw=None, **shape):
     cfg = synth_mod.named_config(name)
     d, d32 = _data(synth_mod, name)
     print(f"{name}: P={cfg.P} sampled subbands {sample} "
@@ -46,7 +47,7 @@ def _first_local_step_sampled(cal, oracle_mod, synth_mod, name, sample, **shape)
     g = c.get(cal.FIELD_COST).cpu().numpy()
     c.close()
     sub = subset(d32, sample)
-    pb = oracle_mod.Problem(sub)
+    pb = oracle_mod.Problem(sub, **(oracle_kw or {}))
     J0 = synth_mod.identity_jones(len(sample), cfg.K, cfg.N)
     z = np.zeros_like(J0)
     want = pb.subband_cost(pb.local_step(J0, z, z))
@@ -97,6 +98,44 @@ def test_c2_stopping_rule_solve(cal, oracle_mod, synth_mod):
     print("c2: three C-ADMM iterations under the stopping rule, oracle on all 32 subbands", flush=True)
     pb = oracle_mod.Problem(d32, lm_tol=1e-7)
     tro = pb.admm_solve(synth_mod.identity_jones(cfg.P, cfg.K, cfg.N), 3)["trace"]
+    np.testing.assert_allclose(trg[:, :2], tro[:, :2], rtol=1e-5)
+
+
+# the benchmark's solver settings: matrix-free CG at cg_tol 1e-4 in the one-launch local step, LM
+# stopping rule at lm_tol 1e-7; the oracle takes the same reading (block-Jacobi CG to the same
+# relative residual, same rule)
+BENCH_GPU = dict(solver=3, cg_tol=1e-4, lm_tol=1e-7)
+
+
+def _bench_oracle(oracle_mod):
+    return dict(solver=oracle_mod.SOLVE_PCG, cg_tol=1e-4, lm_tol=1e-7)
+
+
+def test_c3_first_local_step_benchmark_solver(cal, oracle_mod, synth_mod):
+    _first_local_step_sampled(cal, oracle_mod, synth_mod, "c3", [0, 77, 200, 255],
+                              oracle_kw=_bench_oracle(oracle_mod), **BENCH_GPU)
+
+
+def test_c2_benchmark_configuration(cal, oracle_mod, synth_mod):
+    """The timed configuration on the full c2 problem: FP32 streaming, the one-launch local step
+    with CG at cg_tol 1e-4 and the stopping rule at lm_tol 1e-7, three C-ADMM iterations from
+    identity replayed from the captured graph; the oracle runs the same reading on the
+    FP32-rounded inputs of all 32 subbands.  Data cost and Lagrangian within 1e-5: a CG run that
+    stops one iteration apart on the two sides (a residual within rounding of the tolerance)
+    moves that LM step by about cg_tol relative, and a flipped stop decision the cost by about
+    lm_tol."""
+    cfg = synth_mod.named_config("c2")
+    d, d32 = _data(synth_mod, "c2")
+    vis, coh, flags = cal.device_inputs(d, cal.CALIB_FP32_MIXED)
+    c = cal.Calib(d, vis, coh, flags, precision=cal.CALIB_FP32_MIXED, **BENCH_GPU)
+    trg = c.solve(3)
+    c.close()
+    print("c2: three C-ADMM iterations in the benchmark's configuration, oracle on all 32 subbands",
+          flush=True)
+    pb = oracle_mod.Problem(d32, **_bench_oracle(oracle_mod))
+    tro = pb.admm_solve(synth_mod.identity_jones(cfg.P, cfg.K, cfg.N), 3)["trace"]
+    print(f"  data cost {np.max(np.abs(trg[:, 0] / tro[:, 0] - 1)):.2e}, Lagrangian "
+          f"{np.max(np.abs(trg[:, 1] / tro[:, 1] - 1)):.2e} relative", flush=True)
     np.testing.assert_allclose(trg[:, :2], tro[:, :2], rtol=1e-5)
 
 
