@@ -671,16 +671,19 @@ __global__ __launch_bounds__(pcg_threads<SPL>()) void k_local_step(Problem pb, L
       __syncthreads();
       if (lst.done && threadIdx.x == 0)   // a run that cannot start (non-finite state): trace rows only
         lmd::stopped_rows(pb, f, k, &lst, lm_trace, 0, lm_iters, lm_iters);
+      double Ecur = E;   // data cost at the run's current point
       for (int it = 0; it < lm_iters && !lst.done; ++it) {
         pcg_solve<SPL>(pb, L, B, f, k, unreg, pb.cg_tol, sh, sh.Us, &lst, Ys, BZs);
         __syncthreads();
         const int ok = lst.chol_ok;
-        double Fn = 0.0;
-        if (ok)
-          Fn = fused_trial<NT>(pb, L, B, f, k, sh.Us, J0s, &lst, red) +
-               (unreg ? 0.0 : penalty_lds<NT>(N, rho, sh.Us, Ys, BZs, red));
+        double En = 0.0, Fn = 0.0;
+        if (ok) {
+          En = fused_trial<NT>(pb, L, B, f, k, sh.Us, J0s, &lst, red);
+          Fn = En + (unreg ? 0.0 : penalty_lds<NT>(N, rho, sh.Us, Ys, BZs, red));
+        }
         if (threadIdx.x == 0) acc = lmd::update_state(pb, B, f, k, &lst, ok, Fn, lm_trace, it, lm_iters, false);
         __syncthreads();
+        if (acc) Ecur = En;
         if (acc)   // the trial point is the new J
           for (int e = threadIdx.x; e < n8; e += NT) {
             const double j = sh.Us[kJS * (e >> 3) + (e & 7)];
@@ -689,7 +692,13 @@ __global__ __launch_bounds__(pcg_threads<SPL>()) void k_local_step(Problem pb, L
           }
         __syncthreads();
       }
-      E += fused_commit<NT>(pb, L, B, f, k, all, sh.Js, J0s, &lst, red);
+      // the commit updates the later directions' D_l; the last direction of a single sweep has none
+      // to update, and the residual's energy after the run is the data cost of its last accepted
+      // trial point (the commit's energy change is the same sum, at the same points)
+      if (all || k + 1 < Kf)
+        E += fused_commit<NT>(pb, L, B, f, k, all, sh.Js, J0s, &lst, red);
+      else
+        E = Ecur;
       __syncthreads();
     }
   if (threadIdx.x == 0) B.lm[f] = lst;
