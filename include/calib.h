@@ -174,7 +174,7 @@ calib_status admm_consensus_update(calib_ctx *ctx, int32_t admm_iter);
  * direction counts, a rank flag) is a fixed 4 MiB device array inside the library, one per GPU,
  * held until the process ends; nothing is allocated or freed.
  *   n_stations N in [2, 128], n_subbands P >= 1, n_basis Q in [1, 8], n_dirs_max K in [1, 16], with
- *   P*(Q + K*Q + K) + K + 4 + (P + 3)/2 <= 524288 (else CALIB_E_INVAL, nothing enqueued)
+ *   P*(Q + K*Q + K) + 16K + 4 + (P + 3)/2 <= 524288 (else CALIB_E_INVAL, nothing enqueued)
  *   n_dirs   device int32 [P] directions per subband (nested 0..K_f-1), or NULL = K for all
  *   freq_hz  device double [P];  f0_hz > 0;  rho  device double [K], >= 0
  *   jones    device double complex [P][K][N][2][2] (read only)

@@ -558,7 +558,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   DALLOC(basis, (size_t)P * Q * 8);
   DALLOC(fitw, (size_t)K * Q * P * 8);
   DALLOC(B.trace, (size_t)kMaxTrace * 4 * 8);
-  DALLOC(B.scratch, ((size_t)P * K + K + 2 * P) * 8);   // residual partials, then cost/penalty per subband
+  DALLOC(B.scratch, ((size_t)P * K + (size_t)K * kZChunks + 2 * P) * 8);   // residual partials, then cost/penalty per subband
   DALLOC(B.iter, sizeof(int));
   B.chol_fail = nullptr;
   B.chol_ld = nullptr;

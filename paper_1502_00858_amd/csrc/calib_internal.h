@@ -13,6 +13,8 @@ constexpr double kLmFailFactor = 1e16;   // a solve still failing at lambda > th
                                          // numeric failure of the subband
 constexpr int kCholMaxTilesPerWave = 9;   // 16-row tiles per wavefront in one Cholesky panel
 constexpr int kMaxStations = 128;         // the solve keeps one column of 8N per thread
+constexpr int kZChunks = 8 * kMaxStations / 64;   // per-direction partials of the dual residual,
+                                                  // one per 64 entries of a direction's 8N
 
 // Per-subband tables of the packed, baseline-major layout.  Flagged baselines are dropped at
 // init, so "baseline index" below always means the compact index of an unflagged baseline.
@@ -106,7 +108,7 @@ struct Buffers {
   const double *basis;                  // [P][Q] b_l(f)
   const double *fitw;                   // [K][Q][P] least-squares operator per direction
   double *trace;                        // [iters][4]
-  double *scratch;                      // [P*K + K] residual partials, [2P] cost/penalty partials
+  double *scratch;                      // [P*K + K*kZChunks] residual partials, [2P] cost/penalty partials
   int *iter;                            // ADMM iteration whose trace row is being written
   int *chol_fail;                       // [P] blocked solver: a pivot failed in this solve
   double *chol_ld;                      // [P][panels][64*64] blocked solver: diagonal blocks' L

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_penalty_part(Problem pb, Layout L, B
   }
   block_sum_vec<2>(v, red);
   if (threadIdx.x == 0) {
-    double *part = B.scratch + (int64_t)pb.P * pb.K + pb.K;
+    double *part = B.scratch + (int64_t)pb.P * pb.K + (int64_t)pb.K * kZChunks;
     part[2 * f] = v[0];
     part[2 * f + 1] = v[1];
   }
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_penalty_part(Problem pb, Layout L, B
 
 __global__ __launch_bounds__(kBlock) void k_penalty_trace(Problem pb, Buffers B) {
   __shared__ double red[2][kBlock / 64];
-  const double *part = B.scratch + (int64_t)pb.P * pb.K + pb.K;
+  const double *part = B.scratch + (int64_t)pb.P * pb.K + (int64_t)pb.K * kZChunks;
   double v[2] = {0.0, 0.0};
   for (int f = threadIdx.x; f < pb.P; f += kBlock) {
     v[0] += part[2 * f];
@@ -200,19 +200,19 @@ __global__ __launch_bounds__(kBlock) void k_gpa(Problem pb, Layout L, Buffers B,
   }
 }
 
-// one workgroup per direction: Z_k = W_k (J + Y/rho); dual partial ||Z_new - Z_old||^2
-// One workgroup per direction, one entry of the 8N real Jones parameters per thread (N <= 128);
-// the subband loop is unrolled so that its loads overlap.
-constexpr int kZThreads = 1024;
-__global__ __launch_bounds__(kZThreads) void k_z_fit(Problem pb, Layout L, Buffers B) {
-  __shared__ double red[kZThreads / 64];
+// grid (K, kZChunks) of one wavefront each: Z_k = W_k (J + Y/rho) for 64 of the direction's 8N
+// real Jones parameters (N <= 128), one per lane, the subbands taken in order with eight
+// subbands' J and Y requested before the first is used; the chunk's part of ||Z_new - Z_old||^2
+// to the dual-residual partials (chunks past 8N write zero)
+__global__ __launch_bounds__(64) void k_z_fit(Problem pb, Layout L, Buffers B) {
   if (B.rank_fail && *B.rank_fail) return;
-  const int k = blockIdx.x, N = pb.N, P = pb.P, Q = pb.Q;
+  const int k = blockIdx.x, c = blockIdx.y, N = pb.N, P = pb.P, Q = pb.Q;
+  const int e = c * 64 + threadIdx.x;
   const double rho = B.rho[k];
   const double *W = B.fitw + (int64_t)k * Q * P;
-  constexpr int kF = 8;   // subbands whose J and Y entries are requested before the first is used
+  constexpr int kF = 8;
   double dz = 0.0;
-  for (int e = threadIdx.x; e < 8 * N; e += kZThreads) {
+  if (e < 8 * N) {
     double z[8];
     for (int l = 0; l < Q; ++l) z[l] = 0.0;
     for (int f0 = 0; f0 < P; f0 += kF) {
@@ -239,13 +239,7 @@ __global__ __launch_bounds__(kZThreads) void k_z_fit(Problem pb, Layout L, Buffe
     }
   }
   dz = wave_sum(dz);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dz;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double v = 0.0;
-    for (int i = 0; i < kZThreads / 64; ++i) v += red[i];
-    B.scratch[(int64_t)pb.P * pb.K + k] = v;
-  }
+  if (threadIdx.x == 0) B.scratch[(int64_t)pb.P * pb.K + (int64_t)k * kZChunks + c] = dz;
 }
 
 // grid (P, K): B_f Z_k, dual ascent, primal partial ||J - BZ||^2
@@ -307,7 +301,9 @@ __global__ __launch_bounds__(64) void k_residuals(Problem pb, Buffers B) {
   double ds = 0.0;
   int dc = 0;
   for (int k = 0; k < pb.K; ++k) {
-    ds += sqrt(B.scratch[(int64_t)pb.P * pb.K + k]) / sqrt(4.0 * pb.Q * pb.N);
+    double dz = 0.0;
+    for (int c = 0; c < kZChunks; ++c) dz += B.scratch[(int64_t)pb.P * pb.K + (int64_t)k * kZChunks + c];
+    ds += sqrt(dz) / sqrt(4.0 * pb.Q * pb.N);
     ++dc;
   }
   B.trace[4 * iter + 2] = pc ? ps / pc : 0.0;
@@ -372,7 +368,8 @@ hipError_t launch_gpa(const Problem &pb, const Layout &L, const Buffers &B, int 
 }
 
 hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
-  hipLaunchKernelGGL(k_z_fit, dim3(pb.K), dim3(kZThreads), 0, s, pb, L, B);
+  if (pb.N > kMaxStations) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_z_fit, dim3(pb.K, kZChunks), dim3(64), 0, s, pb, L, B);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_y_update, dim3(pb.P, pb.K), dim3(kBlock), 0, s, pb, L, B);

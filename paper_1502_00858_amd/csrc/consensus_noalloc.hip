@@ -20,7 +20,7 @@
 namespace calib {
 namespace {
 
-// scratch size in doubles (4 MiB): basis P*Q, operator K*Q*P, residual partials P*K + K, four
+// scratch size in doubles (4 MiB): basis P*Q, operator K*Q*P, residual partials P*K + 16K, four
 // trace values, then the int region (iteration counter, rank flag, P direction counts)
 constexpr int64_t kScratchDoubles = int64_t(1) << 19;
 constexpr int kMaxDevices = 64;
@@ -49,7 +49,7 @@ hipError_t scratch_address(double **out) {
 
 int64_t scratch_need(int P, int Q, int K) {
   const int64_t ints = 2 + (int64_t)P;
-  return (int64_t)P * Q + (int64_t)K * Q * P + (int64_t)P * K + K + 4 + (ints + 1) / 2;
+  return (int64_t)P * Q + (int64_t)K * Q * P + (int64_t)P * K + (int64_t)K * kZChunks + 4 + (ints + 1) / 2;
 }
 
 // per-call set-up of the scratch's int region: iteration counter 0, rank flag 0, direction counts
@@ -102,7 +102,7 @@ extern "C" calib_status calib_consensus_noalloc(int32_t n_stations, int32_t n_su
     return fail_msg(CALIB_E_INVAL, "problem too large for the scratch array: needs " +
                                        std::to_string(need) + " doubles, holds " +
                                        std::to_string(kScratchDoubles) +
-                                       " (P*(Q + K*Q + K) + K + 4 + (P + 3)/2)");
+                                       " (P*(Q + K*Q + K) + 16K + 4 + (P + 3)/2)");
   double *base = nullptr;
   hipError_t e = scratch_address(&base);
   if (e != hipSuccess) return fail_msg(CALIB_E_DEVICE, std::string("scratch address: ") + hipGetErrorString(e));
@@ -110,7 +110,7 @@ extern "C" calib_status calib_consensus_noalloc(int32_t n_stations, int32_t n_su
   double *basis = base;
   double *fitw = basis + (int64_t)P * Q;
   double *part = fitw + (int64_t)K * Q * P;
-  double *trace = part + (int64_t)P * K + K;
+  double *trace = part + (int64_t)P * K + (int64_t)K * kZChunks;
   int *ints = reinterpret_cast<int *>(trace + 4);
   int *iter = ints, *rank_fail = ints + 1;
   int32_t *ndir = ints + 2;
