@@ -105,10 +105,12 @@ def stream_bytes(name, data, elt, solver=3):
         # direction's D_b from U_l and X_lm
         return float(np.sum(S_f * (8 + 2 * Kf) * elt + nb * Kf * (64.0 + 16.0 * Kf + 64.0)))
     if name == "pack":
-        # the interval's V and coherencies read and written once in the packed layout; U_l, a row
-        # of X_lm and S_b written per baseline and direction; the dense S table rebuilt
-        return float(np.sum(2 * S_f * (8 + 2 * Kf) * elt + nb * Kf * (64.0 + 16.0 * K + 8.0))
-                     + len(nb) * K * N * N * 8.0)
+        # the interval's V and coherencies read once (and, except for the statistics-only contexts
+        # of the matrix-free solver, written once in the packed layout); U_l, a row of X_lm and S_b
+        # written per baseline and direction, sum ||V||^2 per baseline; the dense S table rebuilt
+        copies = 1 if solver == 3 else 2
+        return float(np.sum(copies * S_f * (8 + 2 * Kf) * elt + nb * Kf * (64.0 + 16.0 * K + 8.0)
+                            + nb * 8.0) + len(nb) * K * N * N * 8.0)
     raise KeyError(name)
 
 
@@ -280,8 +282,10 @@ def main():
     v0, c0, f0 = calib.device_inputs(first, prec)
     ctx_kw = dict(precision=prec, lm_iters=lm_iters, tile_group=shape["tile_group"],
                   stream_grid=shape["stream_grid"], lm_tol=args.lm_tol, **solve_kw)
-    ctx = calib.Calib(first, v0, c0, f0, options=0, **ctx_kw)
-    ctx_id = calib.Calib(first, v0, c0, f0, options=calib.OPT_GPA_FIRST_ITER, **ctx_kw)
+    # the matrix-free solver works from the coherency statistics alone: no packed sample copy
+    stats = calib.OPT_STATS_ONLY if args.solver == 3 else 0
+    ctx = calib.Calib(first, v0, c0, f0, options=stats, **ctx_kw)
+    ctx_id = calib.Calib(first, v0, c0, f0, options=calib.OPT_GPA_FIRST_ITER | stats, **ctx_kw)
     del v0, c0, f0
     J_id = torch.from_numpy(synth.identity_jones(P, cfg.K, cfg.N)).cuda()
 
@@ -304,7 +308,7 @@ def main():
 
     # ---- the target: a long FP64 run from the previous state ---------------------------------------
     v64, c64, f64 = calib.device_inputs(data, calib.CALIB_FP64)
-    r64 = calib.Calib(data, v64, c64, f64, options=0,
+    r64 = calib.Calib(data, v64, c64, f64, options=stats,
                       **dict(ctx_kw, precision=calib.CALIB_FP64))
     r64.set_state(prev.J, prev.Y, prev.Z, prev.BZ)
     tr64 = r64.solve(args.target_iters)
@@ -342,7 +346,8 @@ def main():
     fdesc = f" flagged ~U(0,{cfg.flag_frac_max})" if cfg.flag_frac_max > 0 else ""
     solver_desc = {0: "Cholesky (auto: blocked below 128 subbands, else one workgroup per matrix)",
                    1: "Cholesky, one workgroup per matrix", 2: "Cholesky, blocked panels",
-                   3: f"matrix-free CG (cg_tol {args.cg_tol:g}) in the one-launch local step"}
+                   3: f"matrix-free CG (cg_tol {args.cg_tol:g}) in the one-launch local step, "
+                      f"coherency statistics only"}
     out = {"metric": "subband ADMM solves/s (N=62,K=5) at 1e-6 rel cost, learned vs plain; HBM GB/s",
            "value": value, "unit": "subband-solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * sec["learned"], "higher_is_better": True,

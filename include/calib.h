@@ -75,6 +75,12 @@ typedef enum { CALIB_FP64 = 0, CALIB_FP32_MIXED = 1 } calib_precision;
 #define CALIB_OPT_GPA_FIRST_ITER 1u  /* align the unitary ambiguity across subbands after the first
                                         local step (Section 3, initialisation)                  */
 #define CALIB_OPT_UNREG_FIRST 2u     /* first local step without the consensus terms            */
+#define CALIB_OPT_STATS_ONLY 4u      /* keep only the per-baseline coherency statistics, no packed
+                                        copy of the samples (the matrix-free solver works from the
+                                        statistics alone; a new interval is then one read of the
+                                        inputs): needs solver 3 (else CALIB_E_INVAL);
+                                        CALIB_FIELD_MODEL_VIS returns CALIB_E_STATE and
+                                        CALIB_FIELD_COST comes from the statistics              */
 
 typedef struct {
   int32_t n_stations;      /* N >= 2                                                           */
@@ -120,7 +126,9 @@ typedef struct {
 #define CALIB_FIELD_Y 3          /* double complex [P][K][N][2][2], Lagrange multipliers        */
 #define CALIB_FIELD_MODEL_VIS 4  /* vis layout and element type: sum_k c J_p J_q^H, zero on
                                     flagged baselines (Section 2, visibility model)           */
-#define CALIB_FIELD_COST 5       /* double [P]: data cost g_f at the current J (Section 2)     */
+#define CALIB_FIELD_COST 5       /* double [P]: data cost g_f at the current J (Section 2): a
+                                    pass over the samples, or with CALIB_OPT_STATS_ONLY the
+                                    expansion over the coherency statistics                    */
 #define CALIB_FIELD_TRACE 6      /* double [admm iterations run][4]: data cost after the local
                                     step, augmented Lagrangian, primal, dual residual         */
 #define CALIB_FIELD_LM_TRACE 7   /* double [P][K][lm_iters][3] of the last SAGE sweep of the last

@@ -17,6 +17,7 @@ CALIB_FP64 = 0
 CALIB_FP32_MIXED = 1
 OPT_GPA_FIRST_ITER = 1
 OPT_UNREG_FIRST = 2
+OPT_STATS_ONLY = 4
 (FIELD_J, FIELD_Z, FIELD_BZ, FIELD_Y, FIELD_MODEL_VIS, FIELD_COST, FIELD_TRACE, FIELD_LM_TRACE,
  FIELD_LM_STEP, FIELD_KERNEL_TIMES, FIELD_STATUS, FIELD_WORK) = range(12)
 KERNELS = ["refresh", "lm_begin", "assemble", "chol_solve", "trial", "lm_update", "commit",

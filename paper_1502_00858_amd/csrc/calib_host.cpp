@@ -367,6 +367,8 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   if (!(cfg->lm_tol >= 0.0) || !std::isfinite(cfg->lm_tol))
     return fail(nullptr, CALIB_E_INVAL, "lm_tol must be finite and >= 0");
   if (cfg->solver < 0 || cfg->solver > 3) return fail(nullptr, CALIB_E_INVAL, "solver must be 0, 1, 2 or 3");
+  if ((cfg->options & CALIB_OPT_STATS_ONLY) && cfg->solver != 3)
+    return fail(nullptr, CALIB_E_INVAL, "CALIB_OPT_STATS_ONLY needs solver 3");
   if (!(cfg->cg_tol >= 0.0) || !(cfg->cg_tol < 1.0))
     return fail(nullptr, CALIB_E_INVAL, "cg_tol must be in [0, 1)");
 
@@ -479,7 +481,9 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   pb.ntiles = (int)tile_f.size();
   pb.group = group;
   pb.bpt = bpt;
-  pb.nbt = nb_total;
+  // stride of the per-direction planes of the baseline statistics: padded so that the planes do
+  // not start at the same offsets modulo large powers of two
+  pb.nbt = nb_total + kPlanePad;
   pb.max_nb = P > 0 ? *std::max_element(nb.begin(), nb.end()) : 0;
   pb.stream_grid = cfg->stream_grid > 0 ? cfg->stream_grid : 0;
   pb.lm_tol = cfg->lm_tol;
@@ -525,10 +529,12 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
     if (c->mem.alloc(&p_, (bytes)) != hipSuccess) return fail_alloc(#ptr);                     \
     ptr = reinterpret_cast<decltype(ptr)>(p_);                                                 \
   } while (0)
-  void *Vp, *Cp;
+  void *Vp = nullptr, *Cp = nullptr;   // the packed samples (none with CALIB_OPT_STATS_ONLY)
   double *Sb;
-  DALLOC(Vp, (size_t)so * 8 * elt);
-  DALLOC(Cp, (size_t)co * 2 * elt);
+  if (!(cfg->options & CALIB_OPT_STATS_ONLY)) {
+    DALLOC(Vp, (size_t)so * 8 * elt);
+    DALLOC(Cp, (size_t)co * 2 * elt);
+  }
   DALLOC(Sb, (size_t)sbo * sizeof(double));
   const size_t nj = (size_t)P * K * N * 8, nz = (size_t)K * Q * N * 8;
   DALLOC(B.J, nj * 8); DALLOC(B.Y, nj * 8); DALLOC(B.BZ, nj * 8);
@@ -548,9 +554,9 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   DALLOC(B.Epart, (size_t)std::max(pb.ntiles, 1) * 8);
   DALLOC(B.Ev, (size_t)std::max(nb_total, 1) * 8);
   DALLOC(B.Epl, (size_t)K * std::max(pb.ntiles, 1) * 8);
-  DALLOC(B.Ucoh, (size_t)nb_total * K * 8 * 8);
-  DALLOC(B.Xcoh, (size_t)nb_total * K * K * 2 * 8);
-  DALLOC(B.Dall, (size_t)nb_total * K * 8 * 8);
+  DALLOC(B.Ucoh, (size_t)pb.nbt * K * 8 * 8);
+  DALLOC(B.Xcoh, (size_t)pb.nbt * K * K * 2 * 8);
+  DALLOC(B.Dall, (size_t)pb.nbt * K * 8 * 8);
   DALLOC(B.lm, (size_t)P * sizeof(LmState));
   DALLOC(B.status, (size_t)P * sizeof(int));
   DALLOC(B.work, (size_t)P * 2 * sizeof(double));
@@ -719,13 +725,17 @@ calib_status calib_get(calib_ctx *ctx, int32_t field, void *dst) {
                                  hipMemcpyDeviceToDevice, s));
       return CALIB_OK;
     case CALIB_FIELD_MODEL_VIS:
+      if (!ctx->Vp) return fail(ctx, CALIB_E_STATE, "the context keeps no samples (CALIB_OPT_STATS_ONLY)");
       HIPCHK(ctx, ctx->precision == CALIB_FP64
                       ? launch_model<double>(ctx->pb, ctx->L, ctx->B, dst, ctx->d_full_off, ctx->d_full_bmap, s)
                       : launch_model<float>(ctx->pb, ctx->L, ctx->B, dst, ctx->d_full_off, ctx->d_full_bmap, s));
       return CALIB_OK;
     case CALIB_FIELD_COST:
-      HIPCHK(ctx, ctx->precision == CALIB_FP64 ? launch_refresh<double>(ctx->pb, ctx->L, ctx->B, s)
-                                               : launch_refresh<float>(ctx->pb, ctx->L, ctx->B, s));
+      if (!ctx->Vp)
+        HIPCHK(ctx, launch_refresh_stats(ctx->pb, ctx->L, ctx->B, true, s));
+      else
+        HIPCHK(ctx, ctx->precision == CALIB_FP64 ? launch_refresh<double>(ctx->pb, ctx->L, ctx->B, s)
+                                                 : launch_refresh<float>(ctx->pb, ctx->L, ctx->B, s));
       HIPCHK(ctx, launch_subband_cost(ctx->pb, ctx->L, ctx->B, static_cast<double *>(dst), s));
       return CALIB_OK;
     case CALIB_FIELD_TRACE:

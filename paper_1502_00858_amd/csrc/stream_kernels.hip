@@ -158,34 +158,51 @@ __global__ __launch_bounds__(64 * kStatTiles) void k_trial_stats(Problem pb, Lay
   lmd::trial_tile(pb, L, B, f, k, tile, lane);
 }
 
-// Every direction's D_l at the current point from the coherency statistics (grid: tile x l, one
-// lane per baseline); direction 0's also becomes the accepted and start point of the next LM run.
+// Every direction's D_l at the current point from the coherency statistics (grid: tile x block of
+// kDallL directions, one lane per baseline: M_m = J_p J_q^H of every direction m is formed once per
+// lane and block and applied to the block's D_l = U_l - sum_m X_lm M_m); direction 0's D also
+// becomes the accepted and start point of the next LM run.
 // With kEnergy, also the residual's energy from the statistics, with R = V - sum_m c_m M_m:
 //   sum_s ||R_s||^2 = sum_s ||V_s||^2 - 2 Re sum_m <M_m, U_m> + sum_lm X_lm <M_l, M_m>
 //                   = Ev - Re sum_l <M_l, U_l + D_l>     (<A, B> = tr(A^H B), D_l = U_l - sum_m X_lm M_m)
-// each (tile, l) workgroup wavefront summing its baselines' terms (direction 0 with Ev) into
-// Epl[l][tile].  In FP64 the expansion cancels by about the ratio of the data's energy to the
-// residual's (~SNR), far inside the double's precision; at a perfect fit it leaves an absolute
-// error of order eps * sum ||V||^2.
+// each wavefront (one tile) summing its baselines' terms of direction l (direction 0 with Ev) into
+// Epl[l][tile] (zero for the directions l >= K_f of its subband).  In FP64 the expansion cancels by
+// about the ratio of the data's energy to the residual's (~SNR), far inside the double's
+// precision; at a perfect fit it leaves an absolute error of order eps * sum ||V||^2.
+constexpr int kDallL = 4;   // directions per lane
 template <bool kEnergy>
 __global__ __launch_bounds__(64 * kStatTiles) void k_dall(Problem pb, Layout L, Buffers B) {
-  const int tile = kStatTiles * blockIdx.x + (threadIdx.x >> 6), lane = threadIdx.x & 63, l = blockIdx.y;
+  const int tile = kStatTiles * blockIdx.x + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int l0 = kDallL * blockIdx.y;
   if (tile >= pb.ntiles) return;   // uniform per wavefront
   const int f = L.tile_f[tile];
-  const int Kf = L.ndir[f], nb = L.nb[f];
+  const int Kf = L.ndir[f], nb = L.nb[f], K = pb.K;
   const int bi = L.tile_b0[tile] + lane;
-  const bool live = l < Kf && lane < pb.bpt && bi < nb;
-  double part = 0.0;
+  const bool live = l0 < Kf && lane < pb.bpt && bi < nb;
+  double part[kDallL];
+#pragma unroll
+  for (int j = 0; j < kDallL; ++j) part[j] = 0.0;
   if (live) {
-    const int K = pb.K, N = pb.N;
+    const int N = pb.N;
     const int64_t gb = (int64_t)L.bl_off[f] + bi;
     const int p = L.bl_p[gb], q = L.bl_q[gb];
     const int64_t nbt = pb.nbt;
-    double d[8], u[8], ml[8];
+    double d[kDallL][8], ml[kDallL][8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) d[e] = u[e] = B.Ucoh[((int64_t)l * nbt + gb) * 8 + e];
-    // direction m's J_p, J_q and X_lm, requested one direction ahead of their use
-    auto fetch = [&](int m, double *jp, double *jq, double *x) {
+    for (int j = 0; j < kDallL; ++j) {
+      const int l = l0 + j;
+      if (l < Kf) {
+        const double2 *U2 = reinterpret_cast<const double2 *>(B.Ucoh + ((int64_t)l * nbt + gb) * 8);
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const double2 u = U2[h];
+          d[j][2 * h] = u.x;
+          d[j][2 * h + 1] = u.y;
+        }
+      }
+    }
+    // direction m's J_p and J_q, requested one direction ahead of their use
+    auto fetch = [&](int m, double *jp, double *jq) {
       const double2 *P2 = reinterpret_cast<const double2 *>(B.J + (((int64_t)f * K + m) * N + p) * 8);
       const double2 *Q2 = reinterpret_cast<const double2 *>(B.J + (((int64_t)f * K + m) * N + q) * 8);
 #pragma unroll
@@ -194,47 +211,67 @@ __global__ __launch_bounds__(64 * kStatTiles) void k_dall(Problem pb, Layout L, 
         jp[2 * h] = a.x; jp[2 * h + 1] = a.y;
         jq[2 * h] = b.x; jq[2 * h + 1] = b.y;
       }
-      const double2 xv = *reinterpret_cast<const double2 *>(B.Xcoh + (((int64_t)l * K + m) * nbt + gb) * 2);
-      x[0] = xv.x; x[1] = xv.y;
     };
-    auto use = [&](int m, const double *jp, const double *jq, const double *x) {
+    auto use = [&](int m, const double *jp, const double *jq) {
+      double x[kDallL][2];
+#pragma unroll
+      for (int j = 0; j < kDallL; ++j)
+        if (l0 + j < Kf) {
+          const double2 xv =
+              *reinterpret_cast<const double2 *>(B.Xcoh + (((int64_t)(l0 + j) * K + m) * nbt + gb) * 2);
+          x[j][0] = xv.x;
+          x[j][1] = xv.y;
+        }
       double mm[8];
       jjh(jp, jq, mm);
-      sub_scaled(d, x[0], x[1], mm);
-      if (kEnergy && m == l) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) ml[e] = mm[e];
-      }
+      for (int j = 0; j < kDallL; ++j)
+        if (l0 + j < Kf) {
+          sub_scaled(d[j], x[j][0], x[j][1], mm);
+          if (kEnergy && m == l0 + j) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) ml[j][e] = mm[e];
+          }
+        }
     };
-    double jpa[8], jqa[8], xa[2], jpb[8], jqb[8], xb[2];
-    fetch(0, jpa, jqa, xa);
+    double jpa[8], jqa[8], jpb[8], jqb[8];
+    fetch(0, jpa, jqa);
     for (int m = 0; m < Kf; m += 2) {
-      if (m + 1 < Kf) fetch(m + 1, jpb, jqb, xb);
-      use(m, jpa, jqa, xa);
-      if (m + 2 < Kf) fetch(m + 2, jpa, jqa, xa);
-      if (m + 1 < Kf) use(m + 1, jpb, jqb, xb);
+      if (m + 1 < Kf) fetch(m + 1, jpb, jqb);
+      use(m, jpa, jqa);
+      if (m + 2 < Kf) fetch(m + 2, jpa, jqa);
+      if (m + 1 < Kf) use(m + 1, jpb, jqb);
     }
-    double *D = B.Dall + ((int64_t)l * nbt + gb) * 8;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) D[e] = d[e];
-    if (l == 0) {
-      double *Da = d_accepted(B, f) + 8 * gb;
+    for (int j = 0; j < kDallL; ++j) {
+      const int l = l0 + j;
+      if (l >= Kf) continue;
+      double *D = B.Dall + ((int64_t)l * nbt + gb) * 8;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        Da[e] = d[e];
-        B.Dstart[8 * gb + e] = d[e];
+      for (int e = 0; e < 8; ++e) D[e] = d[j][e];
+      if (l == 0) {
+        double *Da = d_accepted(B, f) + 8 * gb;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          Da[e] = d[j][e];
+          B.Dstart[8 * gb + e] = d[j][e];
+        }
       }
-    }
-    if (kEnergy) {
-      double t = 0.0;
+      if (kEnergy) {
+        const double *U = B.Ucoh + ((int64_t)l * nbt + gb) * 8;
+        double t = 0.0;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) t = fma(ml[e], u[e] + d[e], t);   // Re <M_l, U_l + D_l>
-      part = (l == 0 ? B.Ev[gb] : 0.0) - t;
+        for (int e = 0; e < 8; ++e) t = fma(ml[j][e], U[e] + d[j][e], t);   // Re <M_l, U_l + D_l>
+        part[j] = (l == 0 ? B.Ev[gb] : 0.0) - t;
+      }
     }
   }
   if (kEnergy) {
-    part = wave_sum(part);
-    if (lane == 0) B.Epl[(int64_t)l * pb.ntiles + tile] = part;
+    wave_sum_vec<kDallL>(part);
+    if (lane == 0)
+#pragma unroll
+      for (int j = 0; j < kDallL; ++j)
+        if (l0 + j < K) B.Epl[(int64_t)(l0 + j) * pb.ntiles + tile] = part[j];
   }
 }
 
@@ -354,8 +391,10 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
   const int64_t bf = comp2full[gb];
   const C2 *vsrc = reinterpret_cast<const C2 *>(vis + 8 * (in_vis_off[f] + bf * spb));
   const C2 *csrc = reinterpret_cast<const C2 *>(coh + 2 * (in_coh_off[f] + bf * spb));
-  C2 *vdst = reinterpret_cast<C2 *>(Vp + 8 * (L.samp_off[f] + (int64_t)bi * spb));
-  C2 *cdst = reinterpret_cast<C2 *>(Cp + 2 * (L.coh_off[f] + (int64_t)bi * spb));
+  // the packed copies (not kept when Vp and Cp are null: the statistics alone)
+  const bool keep = Vp != nullptr;
+  C2 *vdst = keep ? reinterpret_cast<C2 *>(Vp + 8 * (L.samp_off[f] + (int64_t)bi * spb)) : nullptr;
+  C2 *cdst = keep ? reinterpret_cast<C2 *>(Cp + 2 * (L.coh_off[f] + (int64_t)bi * spb)) : nullptr;
   const int64_t cs = Bfull * spb, cd = (int64_t)nb * spb;   // between directions (complex values)
   T *vl = Vs + j * VR;
   double u[8] = {0, 0, 0, 0, 0, 0, 0, 0}, x[2 * G], sbl = 0.0, ev = 0.0;
@@ -380,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
       const int e = l + G * i;
       if (e < 4 * n) {
         finite &= isfinite(v[i].x) && isfinite(v[i].y);
-        vdst[4 * s0 + e] = v[i];
+        if (keep) vdst[4 * s0 + e] = v[i];
         vl[2 * e] = v[i].x;
         vl[2 * e + 1] = v[i].y;
       }
@@ -390,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
       const int e = l + G * i, m = e / SC, t = e % SC;
       if (m < Kf && t < n) {
         finite &= isfinite(c[i].x) && isfinite(c[i].y);
-        cdst[m * cd + s0 + t] = c[i];
+        if (keep) cdst[m * cd + s0 + t] = c[i];
         T *cl = Cs + (m * TB + j) * CR + 2 * t;
         cl[0] = c[i].x;
         cl[1] = c[i].y;
@@ -494,7 +533,7 @@ hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, 
   const hipError_t e = launch_energy<T>(pb, L, B, s);
   if (e != hipSuccess || pb.ntiles == 0) return e;
   if (pb.bpt > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dall<false>, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles, pb.K),
+  hipLaunchKernelGGL(k_dall<false>, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles, (pb.K + kDallL - 1) / kDallL),
                      dim3(64 * kStatTiles), 0, s, pb, L, B);
   return hipGetLastError();
 }
@@ -502,7 +541,7 @@ hipError_t launch_refresh_stats(const Problem &pb, const Layout &L, const Buffer
                                 hipStream_t s) {
   if (pb.ntiles == 0) return hipSuccess;
   if (pb.bpt > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dall<true>, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles, pb.K),
+  hipLaunchKernelGGL(k_dall<true>, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles, (pb.K + kDallL - 1) / kDallL),
                      dim3(64 * kStatTiles), 0, s, pb, L, B);
   if (!fold) return hipGetLastError();
   hipLaunchKernelGGL(k_fold_energy, dim3((pb.ntiles + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pb, B);

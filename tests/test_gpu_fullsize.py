@@ -102,9 +102,10 @@ def test_c2_stopping_rule_solve(cal, oracle_mod, synth_mod):
 
 
 # the benchmark's solver settings: matrix-free CG at cg_tol 1e-4 in the one-launch local step, LM
-# stopping rule at lm_tol 1e-7; the oracle takes the same reading (block-Jacobi CG to the same
+# stopping rule at lm_tol 1e-7, no packed sample copy (CALIB_OPT_STATS_ONLY, data costs from the
+# coherency statistics); the oracle takes the same reading (block-Jacobi CG to the same
 # relative residual, same rule)
-BENCH_GPU = dict(solver=3, cg_tol=1e-4, lm_tol=1e-7)
+BENCH_GPU = dict(solver=3, cg_tol=1e-4, lm_tol=1e-7, options=1 | 4)   # GPA first, statistics only
 
 
 def _bench_oracle(oracle_mod):

@@ -56,3 +56,44 @@ def test_set_data_reports_non_finite_inputs(cal, synth_mod):
     with pytest.raises(cal.CalibError) as e:
         c.solve(1)
     assert e.value.status == 5
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_statistics_only_context(cal, synth_mod, oracle_mod, precision):
+    """CALIB_OPT_STATS_ONLY keeps no packed copy of the samples: the matrix-free solve, which
+    reads only the coherency statistics, gives bitwise what a context with the copy gives, over a
+    new interval too; the data cost comes from the statistics, formed in FP64 also from FP32
+    inputs (within 1e-12 of the oracle's per-sample sum on the same, FP32-rounded, inputs); the
+    model visibilities are refused, and so is any other solver."""
+    cfg = synth_mod.SynthConfig("so", N=9, P=5, Q=2, K=3, T=3, n_chan=[1, 3, 2, 4, 2],
+                                n_dirs=[3, 2, 3, 3, 2], flag_frac_max=0.25, lm_iters=4,
+                                config_index=23)
+    a = synth_mod.episode_interval(cfg, 0, 1, 4)
+    b = synth_mod.episode_interval(cfg, 0, 2, 4)
+    kw = dict(precision=precision, lm_iters=4, lm_tol=1e-7, solver=3, cg_tol=1e-10)
+    va, ca, fa = cal.device_inputs(a, precision)
+    vb, cb, _ = cal.device_inputs(b, precision)
+    full = cal.Calib(a, va, ca, fa, options=0, **kw)
+    only = cal.Calib(a, va, ca, fa, options=cal.OPT_STATS_ONLY, **kw)
+    for c in (full, only):
+        c.solve(2)
+        c.set_data(vb, cb)
+    ta, tb = full.solve(3), only.solve(3)
+    np.testing.assert_array_equal(ta, tb)
+    J = only.get(cal.FIELD_J).cpu().numpy()
+    np.testing.assert_array_equal(full.get(cal.FIELD_J).cpu().numpy(), J)
+    g_full = full.get(cal.FIELD_COST).cpu().numpy()
+    g_only = only.get(cal.FIELD_COST).cpu().numpy()
+    # the full context's cost is a pass over the samples, in FP32 per sample on the FP32 path
+    np.testing.assert_allclose(g_only, g_full, rtol=1e-12 if precision == 0 else 1e-6)
+    inputs = b if precision == 0 else synth_mod.as_fp32_inputs(b)
+    want = oracle_mod.Problem(inputs).subband_cost(J)
+    np.testing.assert_allclose(g_only, want, rtol=1e-12)
+    with pytest.raises(cal.CalibError) as e:
+        only.get(cal.FIELD_MODEL_VIS)
+    assert e.value.status == 6
+    full.close()
+    only.close()
+    with pytest.raises(cal.CalibError) as e:
+        cal.Calib(a, va, ca, fa, options=cal.OPT_STATS_ONLY, precision=precision, solver=1)
+    assert e.value.status == 1
