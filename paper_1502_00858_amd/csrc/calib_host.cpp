@@ -481,9 +481,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   pb.ntiles = (int)tile_f.size();
   pb.group = group;
   pb.bpt = bpt;
-  // stride of the per-direction planes of the baseline statistics: padded so that the planes do
-  // not start at the same offsets modulo large powers of two
-  pb.nbt = nb_total + kPlanePad;
+  pb.nbt = nb_total;
   pb.max_nb = P > 0 ? *std::max_element(nb.begin(), nb.end()) : 0;
   pb.stream_grid = cfg->stream_grid > 0 ? cfg->stream_grid : 0;
   pb.lm_tol = cfg->lm_tol;

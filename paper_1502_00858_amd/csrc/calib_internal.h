@@ -12,7 +12,6 @@ constexpr double kLmTau = 1e-3;    // Nielsen's initial damping factor
 constexpr double kLmFailFactor = 1e16;   // a solve still failing at lambda > this x lambda_0 is a
                                          // numeric failure of the subband
 constexpr int kCholMaxTilesPerWave = 9;   // 16-row tiles per wavefront in one Cholesky panel
-constexpr int kPlanePad = 0;              // baselines of padding between statistics planes
 constexpr int kMaxStations = 128;         // the solve keeps one column of 8N per thread
 constexpr int kZChunks = 8 * kMaxStations / 64;   // per-direction partials of the dual residual,
                                                   // one per 64 entries of a direction's 8N
@@ -68,7 +67,7 @@ struct Problem {
   int ntiles;
   int group;       // lanes per baseline in the streaming kernels
   int bpt;         // baselines per tile = kBlock / group
-  int nbt;         // plane stride of the baseline statistics: unflagged baselines over all subbands + kPlanePad
+  int nbt;         // unflagged baselines over all subbands (the plane stride of the baseline statistics)
   int max_nb;      // unflagged baselines of the fullest subband
   int stream_grid; // 0 = one workgroup per tile, else persistent grid size
   double lm_tol;   // LM stops once a step's predicted decrease <= lm_tol * F (0 = never)
