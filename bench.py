@@ -275,6 +275,10 @@ def main():
                  "worst_candidate_ms": round(max(c["ms"] for c in tuned["candidates"]), 3),
                  "solver_ms_per_local_step": tuned["solver_ms"]}
         solve_kw["solver"] = args.solver = int(tuned["solver"])
+        if args.solver == 3:
+            # the matrix-free path streams no samples after the pack: the library's own tile
+            # shape for it (64 baselines per tile, one lane per baseline in the statistics kernels)
+            shape.update(tile_group=0, stream_grid=0)
         log(f"autotune: {shape}, solver {args.solver}")
     # the contexts are made once per observation, on its first interval; every timed step loads
     # the measured interval into them (calib_set_data)

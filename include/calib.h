@@ -97,9 +97,11 @@ typedef struct {
   int32_t lm_iters;        /* LM iterations per direction per local step, >= 1                  */
   int32_t sage_sweeps;     /* SAGE sweeps over the directions per local step, >= 1              */
   uint32_t options;        /* CALIB_OPT_* bits                                                  */
-  int32_t tile_group;      /* lanes per baseline in the streaming passes: 4, 8, 16, 32 or 64;
-                              0 = chosen from the samples per baseline among 8..64 (tile-shape
-                              tuner output)                                                    */
+  int32_t tile_group;      /* lanes per baseline in the streaming passes: 4, 8, 16, 32 or 64
+                              (a tile holds 256 / tile_group baselines); 0 = chosen from the
+                              samples per baseline among 8..64 (tile-shape tuner output), or 4
+                              with solver 3 (its per-baseline kernels take one lane per
+                              baseline of a tile)                                              */
   int32_t stream_grid;     /* workgroups of the streaming passes: 0 = one per tile, > 0 = a
                               persistent grid striding over the tiles                          */
   double lm_tol;           /* LM stopping rule: a direction's LM run ends after an iteration whose

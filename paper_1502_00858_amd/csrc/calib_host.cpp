@@ -162,9 +162,14 @@ calib_status upload(calib_ctx *ctx, V **dst, const std::vector<V> &src) {
 
 // lanes per baseline for the streaming kernels: the configured value, else the fewest idle
 // lane-iterations over the subbands, ties to the larger group
-int choose_group(const std::vector<int32_t> &spb, const std::vector<int32_t> &nb, int requested) {
+int choose_group(const std::vector<int32_t> &spb, const std::vector<int32_t> &nb, int requested,
+                 bool matrix_free) {
   if (requested == 4 || requested == 8 || requested == 16 || requested == 32 || requested == 64)
     return requested;
+  // the matrix-free solver's per-baseline kernels take one lane per baseline of a tile: 64
+  // baselines per tile fill every lane (its samples are read only by the per-interval pack, whose
+  // shape does not depend on the tile)
+  if (matrix_free) return 4;
   int best = 16;
   double best_w = 1e300;
   for (int g : {64, 32, 16, 8}) {
@@ -452,7 +457,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   std::vector<int32_t> comp_tab(comp2full);
   comp_tab.insert(comp_tab.end(), comp_f.begin(), comp_f.end());
 
-  const int group = choose_group(spb, nb, cfg->tile_group);
+  const int group = choose_group(spb, nb, cfg->tile_group, cfg->solver == 3);
   const int bpt = kBlock / group;
   std::vector<int32_t> tile_f, tile_b0, tile_off(P + 1);
   for (int f = 0; f < P; ++f) {
