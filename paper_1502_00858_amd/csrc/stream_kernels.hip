@@ -401,12 +401,13 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
 #pragma unroll
   for (int m = 0; m < 2 * G; ++m) x[m] = 0.0;
   bool finite = true;
-  for (int s0 = 0; s0 < spb; s0 += SC) {
+  // chunk s0's V and coherency values of this lane (complex value e of the chunk's V row; value
+  // t of direction m's coherency row)
+  auto fetch = [&](int s0, C2 *v, C2 *c) {
     const int n = min(SC, spb - s0);
-    C2 v[NV], c[NC];
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-      const int e = l + G * i;                     // complex value e of the chunk's V row
+      const int e = l + G * i;
       if (e < 4 * n) v[i] = vsrc[4 * s0 + e];
     }
 #pragma unroll
@@ -414,6 +415,11 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
       const int e = l + G * i, m = e / SC, t = e % SC;
       if (m < Kf && t < n) c[i] = csrc[m * cs + s0 + t];
     }
+  };
+  C2 v[NV], c[NC];
+  fetch(0, v, c);
+  for (int s0 = 0; s0 < spb; s0 += SC) {
+    const int n = min(SC, spb - s0);
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
       const int e = l + G * i;
@@ -436,6 +442,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
       }
     }
     wave_lds_sync();
+    if (s0 + SC < spb) fetch(s0 + SC, v, c);   // the next chunk in flight during this one's sums
     if (l < Kf) {
       for (int t = 0; t < n; ++t) {
         double vv[8];
