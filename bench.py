@@ -54,7 +54,17 @@ FP64_PEAK_TFS = 78.6
 # HBM bytes per launch of a kernel class (FETCH_SIZE + WRITE_SIZE, scaled by a 256 MiB copy) as
 # measured for a workload (profiles/hbm_counters_c2.md); reported only while the kernel sources
 # are unchanged (sha256 over the listed files) and for that workload and solver.
-MEASURED_TRAFFIC = {}
+# HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE passes over the timed learned steps
+# of this benchmark (profiles/hbm_counters_c2_timed.md), valid while the kernel's sources hash to
+# the recorded value: (kernel, config, solver) -> (sources, sha256 of their contents, bytes)
+MEASURED_TRAFFIC = {
+    ("local_step", "c2", 3): (
+        ("paper_1502_00858_amd/csrc/pcg_kernel.hip", "paper_1502_00858_amd/csrc/lm_device.h",
+         "paper_1502_00858_amd/csrc/calib_internal.h", "paper_1502_00858_amd/csrc/wave_reduce.h",
+         "paper_1502_00858_amd/csrc/calib_host.cpp"),
+        "fff1ebf9009d7b6a51317fb83918b66e287fc7cb2d0af93a619d7ca04f7048fc",
+        (79.82 + 91.40) * 1e6),
+}
 
 
 def measured_traffic(kernel, config, solver):
@@ -253,7 +263,7 @@ def main():
     X, Y = warmstart.stack_rows(train_iv)
     del train_iv
     net = warmstart.WarmStartNet(max_rows=max(args.batch, int(cfg.P * cfg.K * cfg.N)))
-    train_s = net.train(X, Y, epochs=args.epochs, batch=args.batch, lr=2e-3, lr_final=2e-4)
+    train_s = net.train(X, Y, epochs=args.epochs, batch=args.batch, lr=2e-3, lr_final=2e-4, log=log)
     log(f"trained on {X.shape[0]} rows in {train_s:.1f} s, loss {net.history[-1]:.3e}")
 
     # ---- the measured interval, its predecessors and the contexts (untimed) ------------------------
@@ -410,7 +420,7 @@ def main():
             achieved = flops / avg_s / 1e12
             rl.update({"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFS,
                        "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFS,
-                       "traffic": measured_traffic(dom, args.config, "pcg"),
+                       "traffic": measured_traffic(dom, args.config, args.solver),
                        "flops_per_launch": flops,
                        "cg_iterations_per_launch": float(work[:, 0].sum() / launches),
                        "lm_solves_per_launch": float(work[:, 1].sum() / launches),
@@ -420,7 +430,7 @@ def main():
             achieved = nbytes / avg_s / 1e9
             rl.update({"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": achieved / HBM_PEAK_GBS,
-                       "traffic": measured_traffic(dom, args.config, "pcg")})
+                       "traffic": measured_traffic(dom, args.config, args.solver)})
         out["roofline"] = rl
         # the HBM-streaming passes: the residual's energy at each local step, the interval's pack
         for name in ("refresh", "pack"):

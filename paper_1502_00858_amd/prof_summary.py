@@ -2,7 +2,7 @@
 
     python -m paper_1502_00858_amd.prof_summary trace DIR [--between NAME]
                                                 # DIR: --kernel-trace --stats -o run
-    python -m paper_1502_00858_amd.prof_summary pmc FETCH_DIR WRITE_DIR
+    python -m paper_1502_00858_amd.prof_summary pmc FETCH_DIR WRITE_DIR [--between NAME]
 
 `trace` prints, per kernel, calls, total and average time and the average over dispatches longer
 than 5 us (launches whose subbands all stopped their LM runs exit at once), and, for the Cholesky
@@ -85,17 +85,34 @@ def trace(dirname: str, between: str | None = None):
               f"{sum(solves) / len(solves):.1f} us, median {solves[len(solves) // 2]:.1f} us")
 
 
-def _pmc(dirname: str):
+def _window(rows, between):
+    """The rows of dispatches that start after the first dispatch of a kernel named like `between`
+    ends and end before its second one starts (all rows when between is None)."""
+    if not between:
+        return rows
+    marks = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows
+                   if between in r["Kernel_Name"])
+    if len(marks) < 2:
+        raise SystemExit(f"fewer than two dispatches of {between}")
+    lo, hi = marks[0][1], marks[1][0]
+    return [r for r in rows if int(r["Start_Timestamp"]) >= lo and int(r["End_Timestamp"]) <= hi]
+
+
+def _pmc(dirname: str, between=None):
     path = _one(dirname, "counter_collection.csv")
     rows = list(csv.DictReader(open(path)))
     vals = collections.defaultdict(list)
-    for r in rows:
+    copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+    for r in _window(rows, between) + (copies if between else []):
         vals[_short(r["Kernel_Name"])].append(float(r["Counter_Value"]))
     return vals
 
 
-def pmc(fetch_dir: str, write_dir: str):
-    fv, wv = _pmc(fetch_dir), _pmc(write_dir)
+def pmc(fetch_dir: str, write_dir: str, between=None):
+    fv, wv = _pmc(fetch_dir, between), _pmc(write_dir, between)
+    if between:
+        print(f"Window: the dispatches between the first two dispatches of {between} (the "
+              f"calibration copy taken from the whole run).\n")
     copy = [k for k in fv if "copyBuffer" in k]
     if not copy:
         raise SystemExit("no copy kernel in the FETCH_SIZE pass")
@@ -124,6 +141,7 @@ if __name__ == "__main__":
     if len(sys.argv) >= 3 and sys.argv[1] == "trace":
         trace(sys.argv[2], sys.argv[4] if len(sys.argv) >= 5 and sys.argv[3] == "--between" else None)
     elif len(sys.argv) >= 4 and sys.argv[1] == "pmc":
-        pmc(sys.argv[2], sys.argv[3])
+        pmc(sys.argv[2], sys.argv[3],
+            sys.argv[5] if len(sys.argv) >= 6 and sys.argv[4] == "--between" else None)
     else:
         raise SystemExit(__doc__)

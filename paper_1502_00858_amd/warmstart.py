@@ -83,10 +83,11 @@ class WarmStartNet:
         self.history: List[float] = []
 
     def train(self, X_host: np.ndarray, Y_host: np.ndarray, epochs: int, batch: int, lr: float,
-              seed: int = 0, lr_final: Optional[float] = None):
+              seed: int = 0, lr_final: Optional[float] = None, log=None):
         """Minibatch Adam on mean square error over host rows X_host [n, 32] -> Y_host [n, 8];
         rows are reshuffled on the host every epoch.  The learning rate decays geometrically
-        from lr to lr_final over the run.  Returns the wall time in seconds."""
+        from lr to lr_final over the run.  log (optional) receives a line every ten epochs.
+        Returns the wall time in seconds."""
         import torch
         n = X_host.shape[0]
         batch = min(batch, n, self.max_rows)
@@ -108,6 +109,8 @@ class WarmStartNet:
                 ep += float(loss.item()) if b == nb - 1 else 0.0
                 cur *= decay
             self.history.append(ep)
+            if log and len(self.history) % 10 == 0:
+                log(f"epoch {len(self.history)}: loss {ep:.3e}")
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
