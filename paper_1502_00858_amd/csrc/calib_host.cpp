@@ -785,16 +785,10 @@ calib_status calib_warmstart_features(calib_ctx *ctx, const void *jones_prev2, c
   const Buffers &B = ctx->B;
   const double *J2 = static_cast<const double *>(jones_prev2);
   const double *BZp = static_cast<const double *>(bz_prev);
-  // residual's energy and per-baseline sums at the current J (from the coherency statistics);
-  // each direction's statistics follow from a commit with an unchanged J (start point = current
-  // point)
-  HIPCHK(ctx, launch_refresh_stats(pb, L, B, true, s));
-  for (int k = 0; k < ctx->K; ++k) {
-    HIPCHK(ctx, launch_lm_begin(pb, L, B, k, 1, s));
-    HIPCHK(ctx, launch_ws_features(pb, L, B, k, J2, BZp, features, s));
-    HIPCHK(ctx, ctx->precision == CALIB_FP64 ? launch_commit<double>(pb, L, B, k, 0, s)
-                                             : launch_commit<float>(pb, L, B, k, 0, s));
-  }
+  // every direction's per-baseline sums D_k at the current J (from the coherency statistics),
+  // then the features of every (subband, direction, station) in one launch
+  HIPCHK(ctx, launch_refresh_stats(pb, L, B, false, s));
+  HIPCHK(ctx, launch_ws_features(pb, L, B, J2, BZp, features, s));
   return CALIB_OK;
 }
 

@@ -195,7 +195,7 @@ hipError_t launch_subband_cost(const Problem &pb, const Layout &L, const Buffers
 constexpr int kWsFeatures = 32;     // network inputs per (subband, direction, station)
 constexpr int kWsOutputs = 8;       // network outputs: scaled change of the station's Jones
 constexpr double kWsScale = 10.0;   // scale of the difference features and of the outputs
-hipError_t launch_ws_features(const Problem &pb, const Layout &L, const Buffers &B, int k,
+hipError_t launch_ws_features(const Problem &pb, const Layout &L, const Buffers &B,
                               const double *J2, const double *BZp, float *feat, hipStream_t s);
 hipError_t launch_ws_add(const Problem &pb, const Layout &L, const Buffers &B, const float *delta,
                          double *Jsave, hipStream_t s);

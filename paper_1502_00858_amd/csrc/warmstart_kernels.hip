@@ -24,11 +24,11 @@ namespace calib {
 namespace {
 
 
-__global__ __launch_bounds__(kBlock) void k_ws_features(Problem pb, Layout L, Buffers B, int k,
+__global__ __launch_bounds__(kBlock) void k_ws_features(Problem pb, Layout L, Buffers B,
                                                         const double *J2, const double *BZp,
                                                         float *feat) {
   __shared__ double red[12][kBlock / 64];
-  const int f = blockIdx.x, p = blockIdx.y, N = pb.N;
+  const int f = blockIdx.x, p = blockIdx.y, k = blockIdx.z, N = pb.N;
   const int64_t row = ((int64_t)f * pb.K + k) * N + p;
   float *o = feat + row * kWsFeatures;
   if (k >= L.ndir[f]) {
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kBlock) void k_ws_features(Problem pb, Layout L, Bu
     v[1] += S * (Jo[2] * Jo[2] + Jo[3] * Jo[3] + Jo[6] * Jo[6] + Jo[7] * Jo[7]);
     v[2] += S * (Jo[0] * Jo[2] + Jo[1] * Jo[3] + Jo[4] * Jo[6] + Jo[5] * Jo[7]);
     v[3] += S * (Jo[0] * Jo[3] - Jo[1] * Jo[2] + Jo[4] * Jo[7] - Jo[5] * Jo[6]);
-    const double *D = d_accepted(B, f) + 8 * (int64_t)gb;
+    const double *D = B.Dall + ((int64_t)k * pb.nbt + gb) * 8;   // D_k at the current J
     for (int i = 0; i < 2; ++i)
       for (int j = 0; j < 2; ++j) {
         double re = 0.0, im = 0.0;
@@ -188,9 +188,9 @@ hipError_t launch_ws_target(const Problem &pb, const Layout &L, const Buffers &B
   return hipGetLastError();
 }
 
-hipError_t launch_ws_features(const Problem &pb, const Layout &L, const Buffers &B, int k,
+hipError_t launch_ws_features(const Problem &pb, const Layout &L, const Buffers &B,
                               const double *J2, const double *BZp, float *feat, hipStream_t s) {
-  hipLaunchKernelGGL(k_ws_features, dim3(pb.P, pb.N), dim3(kBlock), 0, s, pb, L, B, k, J2, BZp, feat);
+  hipLaunchKernelGGL(k_ws_features, dim3(pb.P, pb.N, pb.K), dim3(kBlock), 0, s, pb, L, B, J2, BZp, feat);
   return hipGetLastError();
 }
 
