@@ -62,8 +62,8 @@ MEASURED_TRAFFIC = {
         ("paper_1502_00858_amd/csrc/pcg_kernel.hip", "paper_1502_00858_amd/csrc/lm_device.h",
          "paper_1502_00858_amd/csrc/calib_internal.h", "paper_1502_00858_amd/csrc/wave_reduce.h",
          "paper_1502_00858_amd/csrc/calib_host.cpp"),
-        "fff1ebf9009d7b6a51317fb83918b66e287fc7cb2d0af93a619d7ca04f7048fc",
-        (79.82 + 91.40) * 1e6),
+        "f07f5010e39b772b5acb37af323f0c8e03ee798812ace55d21f3544706d937e4",
+        (85.67 + 92.97) * 1e6),
 }
 
 
