@@ -62,7 +62,7 @@ MEASURED_TRAFFIC = {
         ("paper_1502_00858_amd/csrc/pcg_kernel.hip", "paper_1502_00858_amd/csrc/lm_device.h",
          "paper_1502_00858_amd/csrc/calib_internal.h", "paper_1502_00858_amd/csrc/wave_reduce.h",
          "paper_1502_00858_amd/csrc/calib_host.cpp"),
-        "f07f5010e39b772b5acb37af323f0c8e03ee798812ace55d21f3544706d937e4",
+        "c24e7f5d2624424d03fa3a43d4e000fb9218783991674c25ba03d6fec8782b32",
         (85.67 + 92.97) * 1e6),
 }
 

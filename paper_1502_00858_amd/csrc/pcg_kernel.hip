@@ -1,6 +1,6 @@
 // Matrix-free solve of the damped Gauss-Newton normal equations of the Levenberg-Marquardt step:
-// (H_GN + (rho + lambda) I) delta = -G by preconditioned conjugate gradients, one workgroup of
-// four wavefronts per subband, without forming H.
+// (H_GN + (rho + lambda) I) delta = -G by preconditioned conjugate gradients, one workgroup per
+// subband (eight wavefronts for N <= 64, four for N <= 128), without forming H.
 //
 // The coherency is a scalar times I2 (Section 2) and J is time invariant, so the Gauss-Newton
 // matrix depends on the data only through S_pq = sum_s |c_s|^2 of each baseline, and its product
@@ -17,7 +17,7 @@
 // Work layout.  Wavefront 0 owns the vectors: lane l holds x, r, the search direction d, J_p, Q_p
 // and the preconditioner of stations p = l + 64 s (s < SPL), so every dot product is a wavefront
 // sum and the CG recurrences need no barrier.  The table products are split by columns: wavefront
-// w takes stations q in [w C, w C + C), C = ceil(N / 4), keeps S_pq of those columns for its rows
+// w of W takes stations q in [w C, w C + C), C = ceil(N / W), keeps S_pq of those columns for its rows
 // p = l + 64 s in registers for the whole solve (read coalesced through the symmetry of S), reads
 // each column's u_q = d_q^H J_q from LDS (every lane the same words: a broadcast) and leaves its
 // partial sums in LDS, component-major so that lanes touch consecutive words, which wavefront 0
@@ -116,8 +116,8 @@ struct PcgLds {
 // The gradient and the solve of direction k of subband f (whole workgroup) at the
 // current J (sh.Js), with the direction's Y and B_f Z in LDS (Ys, BZs, 8 doubles per station): G
 // and the step delta to the record (CALIB_FIELD_LM_STEP), the trial point J + delta into jt_lds,
-// the predicted decrease into the LM state st (chol_ok = 0 on a failed solve).  Wavefronts 1-3
-// return before wavefront 0 writes the results.
+// the predicted decrease into the LM state st (chol_ok = 0 on a failed solve).  The other
+// wavefronts return before wavefront 0 writes the results.
 template <int SPL>
 __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
                                  int unreg, double tol, PcgLds<SPL> &sh, double *jt_lds, LmState *st,
@@ -138,7 +138,7 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
   const double *Sd = B.Sd + ((int64_t)f * pb.K + k) * N * N;
 
   // gradient of the data term, gathered over station p's baselines (wavefront w takes every
-  // fourth one): G_p = -2 sum_{q>p} D_pq J_q - 2 sum_{c<p} D_cp^H J_c (+ Y_p + rho (J_p - BZ_p)
+  // W-th one, from the w-th): G_p = -2 sum_{q>p} D_pq J_q - 2 sum_{c<p} D_cp^H J_c (+ Y_p + rho (J_p - BZ_p)
   // below).  The first batch's adjacency entries and D_b are requested before S, so that their two
   // dependent latencies overlap the loads of S.
   const double *Dacc = d_accepted(B, *st);
