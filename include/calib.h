@@ -31,9 +31,10 @@
  *     baselines are excluded from every sum and never read after calib_init.
  *
  * Ownership and execution
- *   - Pointers marked "device" are GPU memory owned by the caller; calib_init copies and repacks
- *     them, so the caller may release them once the stream has synchronised.  Pointers marked
- *     "host" are read during the call only.
+ *   - Pointers marked "device" are GPU memory owned by the caller; calib_init and calib_set_data
+ *     read them into the context (a packed copy and the statistics, or the statistics alone with
+ *     CALIB_OPT_STATS_ONLY), so the caller may release them once the stream has synchronised.
+ *     Pointers marked "host" are read during the call only.
  *   - All work is enqueued on the stream given to calib_init (a hipStream_t, NULL = default
  *     stream).  Entry points return once the work is enqueued, except where stated.
  *   - A context is not thread-safe; distinct contexts are independent.
@@ -148,10 +149,10 @@ typedef struct {
                                     not be solved (reset by calib_set_jones / calib_set_state)  */
 
 /* Validate the configuration, pack the inputs into the library's baseline-major layout (dropping
- * flagged baselines, converting nothing: the element type must match cfg->precision), compute
- * the per-baseline coherency statistics S_b = sum |c|^2, U_l = sum conj(c_l) V and
- * X_lm = sum conj(c_l) c_m (everything the local steps need from the samples besides the
- * residual's energy), set J to jones0 (or identity blocks, Section 3 initialisation) and
+ * flagged baselines, converting nothing: the element type must match cfg->precision; no packed
+ * copy with CALIB_OPT_STATS_ONLY), compute the per-baseline coherency statistics
+ * S_b = sum |c|^2, U_l = sum conj(c_l) V, X_lm = sum conj(c_l) c_m and sum ||V||^2 (everything
+ * the matrix-free local steps need from the samples), set J to jones0 (or identity blocks, Section 3 initialisation) and
  * Z = Y = 0.
  *   vis    device, see layout above;       coh    device, see layout above
  *   flags  device [P*B] or NULL;           jones0 device double complex [P][K][N][2][2] or NULL
@@ -245,16 +246,17 @@ calib_status calib_set_state(calib_ctx *ctx, const void *jones, const void *y, c
 /* A new solution interval of the same observation (Section 3 calibrates interval after interval):
  * visibilities and coherencies of the same array, subband frequencies, channel and direction
  * counts and flags as at calib_init (device, same layouts and element type).  Repacks them into
- * the context's buffers and recomputes the per-baseline coherency statistics (S_b, U_l, X_lm) in
- * one pass over the inputs; J, Y, Z and B_f Z are kept - the previous interval's solution, the
+ * the context's buffers (unless CALIB_OPT_STATS_ONLY) and recomputes the per-baseline coherency
+ * statistics (S_b, U_l, X_lm, sum ||V||^2) in one pass over the inputs; J, Y, Z and B_f Z are kept - the previous interval's solution, the
  * paper's warm start (Section 3, initialisation) - until calib_set_state or calib_set_jones
  * replaces them.  Allocates nothing and does not synchronise.  Non-finite inputs mark their
  * subbands CALIB_E_NUMERIC in CALIB_FIELD_STATUS, and the next admm_solve returns it. */
 calib_status calib_set_data(calib_ctx *ctx, const void *vis, const void *coh);
 
 /* Kernel classes reported by CALIB_FIELD_KERNEL_TIMES. */
-#define CALIB_KERNEL_REFRESH 0      /* residual energy over the samples + every direction's
-                                       per-baseline residual statistics                        */
+#define CALIB_KERNEL_REFRESH 0      /* every direction's per-baseline residual statistics and
+                                       the residual's energy (from the coherency statistics
+                                       with solver 3, over the samples otherwise)              */
 #define CALIB_KERNEL_LM_BEGIN 1     /* initial objective and damping of a direction            */
 #define CALIB_KERNEL_ASSEMBLE 2     /* gradient and dense Gauss-Newton normal equations (the
                                        Cholesky solvers only)                                   */
@@ -269,8 +271,9 @@ calib_status calib_set_data(calib_ctx *ctx, const void *vis, const void *coh);
 #define CALIB_KERNEL_LOCAL_STEP 8   /* solver 3: every subband's whole local step (LM runs with
                                        the matrix-free solve, stopping rule, SAGE commits) in one
                                        launch after the refresh                               */
-#define CALIB_KERNEL_PACK 9         /* calib_set_data: the interval's visibilities and coherency
-                                       statistics packed, and the dense S table rebuilt         */
+#define CALIB_KERNEL_PACK 9         /* calib_set_data: the interval's coherency statistics (and,
+                                       unless statistics-only, the packed samples), and the
+                                       dense S table rebuilt                                    */
 #define CALIB_NUM_KERNELS 10
 #define CALIB_FIELD_KERNEL_TIMES 9  /* host double [CALIB_NUM_KERNELS][2]: launches and total
                                        milliseconds since timing was enabled (synchronises)     */
