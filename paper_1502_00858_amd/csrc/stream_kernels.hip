@@ -382,6 +382,8 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
   const int nb = L.nb[f];
   const int bi0 = blockIdx.x * TB;
   if (bi0 >= nb) return;                           // whole workgroup
+  // subbands of up to 8 directions go to the 8-lane launch, the others to the 16-lane one
+  if (G == 8 ? L.ndir[f] > 8 : L.ndir[f] <= 8) return;   // whole workgroup
   const int j = threadIdx.x / G, l = threadIdx.x % G;
   const int bi = bi0 + j;
   if (bi >= nb) return;                            // whole group (no workgroup barrier below)
@@ -582,15 +584,17 @@ hipError_t launch_pack_stats(const Problem &pb, const Layout &L, const Buffers &
   // comp_tab: the full-layout baseline of each compact baseline (then its subband, unused here)
   const T *v = static_cast<const T *>(vis), *c = static_cast<const T *>(coh);
   T *vp = static_cast<T *>(Vp), *cp = static_cast<T *>(Cp);
-  if (pb.K <= 8) {
-    const dim3 grid((pb.max_nb + kBlock / 8 - 1) / (kBlock / 8), pb.P);
-    hipLaunchKernelGGL((k_pack_stats<T, 8>), grid, dim3(kBlock), 0, s, pb, L, B, v, c, vp, cp, Sb,
-                       in_vis_off, in_coh_off, comp_tab, bad, status);
-  } else {
-    const dim3 grid((pb.max_nb + kBlock / 16 - 1) / (kBlock / 16), pb.P);
-    hipLaunchKernelGGL((k_pack_stats<T, 16>), grid, dim3(kBlock), 0, s, pb, L, B, v, c, vp, cp, Sb,
-                       in_vis_off, in_coh_off, comp_tab, bad, status);
-  }
+  // 8 lanes per baseline for the subbands of up to 8 directions, 16 for the others (each lane
+  // sums the statistics of one direction), one launch per lane count
+  const dim3 grid8((pb.max_nb + kBlock / 8 - 1) / (kBlock / 8), pb.P);
+  hipLaunchKernelGGL((k_pack_stats<T, 8>), grid8, dim3(kBlock), 0, s, pb, L, B, v, c, vp, cp, Sb,
+                     in_vis_off, in_coh_off, comp_tab, bad, status);
+  if (pb.K <= 8) return hipGetLastError();
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 grid16((pb.max_nb + kBlock / 16 - 1) / (kBlock / 16), pb.P);
+  hipLaunchKernelGGL((k_pack_stats<T, 16>), grid16, dim3(kBlock), 0, s, pb, L, B, v, c, vp, cp, Sb,
+                     in_vis_off, in_coh_off, comp_tab, bad, status);
   return hipGetLastError();
 }
 
