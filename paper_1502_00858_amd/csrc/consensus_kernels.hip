@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_gpa(Problem pb, Layout L, Buffers B,
 }
 
 // grid (K, kZChunks) of one wavefront each: Z_k = W_k (J + Y/rho) for 64 of the direction's 8N
-// real Jones parameters (N <= 128), one per lane, the subbands taken in order with eight
+// real Jones parameters (N <= 128), one per lane, the subbands taken in order with sixteen
 // subbands' J and Y requested before the first is used; the chunk's part of ||Z_new - Z_old||^2
 // to the dual-residual partials (chunks past 8N write zero)
 __global__ __launch_bounds__(64) void k_z_fit(Problem pb, Layout L, Buffers B) {
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(64) void k_z_fit(Problem pb, Layout L, Buffers B) {
   const int e = c * 64 + threadIdx.x;
   const double rho = B.rho[k];
   const double *W = B.fitw + (int64_t)k * Q * P;
-  constexpr int kF = 8;
+  constexpr int kF = 16;
   double dz = 0.0;
   if (e < 8 * N) {
     double z[8];
