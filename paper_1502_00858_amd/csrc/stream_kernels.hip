@@ -399,9 +399,14 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
   C2 *cdst = keep ? reinterpret_cast<C2 *>(Cp + 2 * (L.coh_off[f] + (int64_t)bi * spb)) : nullptr;
   const int64_t cs = Bfull * spb, cd = (int64_t)nb * spb;   // between directions (complex values)
   T *vl = Vs + j * VR;
-  double u[8] = {0, 0, 0, 0, 0, 0, 0, 0}, x[2 * G], sbl = 0.0, ev = 0.0;
+  // X is Hermitian (X_ml = conj X_lm): lane l sums X_lm for m = (l + d) mod K_f at distances
+  // d = 0 .. K_f/2 (at d = K_f/2 for even K_f only lanes l < K_f/2), so every pair is summed once
+  constexpr int kD = G / 2 + 1;
+  double u[8] = {0, 0, 0, 0, 0, 0, 0, 0}, x[2 * kD], ev = 0.0;
 #pragma unroll
-  for (int m = 0; m < 2 * G; ++m) x[m] = 0.0;
+  for (int d = 0; d < 2 * kD; ++d) x[d] = 0.0;
+  const int dmax = Kf / 2;                         // largest distance
+  const bool half = (Kf & 1) == 0 && l >= dmax;    // lanes that skip distance K_f/2
   bool finite = true;
   // chunk s0's V and coherency values of this lane (complex value e of the chunk's V row; value
   // t of direction m's coherency row)
@@ -456,18 +461,18 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
         }
         const T *ct = Cs + j * CR + 2 * t;         // direction m's value at ct[m * TB * CR]
         const double cr = (double)ct[l * TB * CR], ci = (double)ct[l * TB * CR + 1];
-        sbl = fma(cr, cr, fma(ci, ci, sbl));       // X_ll, kept apart: x is indexed statically
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           u[2 * e] = fma(cr, vv[2 * e], fma(ci, vv[2 * e + 1], u[2 * e]));
           u[2 * e + 1] = fma(cr, vv[2 * e + 1], fma(-ci, vv[2 * e], u[2 * e + 1]));
         }
 #pragma unroll
-        for (int m = 0; m < G; ++m) {
-          if (m < Kf) {                            // uniform over the workgroup
+        for (int d = 0; d < kD; ++d) {
+          if (d <= dmax) {                         // uniform over the workgroup
+            const int m = l + d < Kf ? l + d : l + d - Kf;
             const double mr = (double)ct[m * TB * CR], mi = (double)ct[m * TB * CR + 1];
-            x[2 * m] = fma(cr, mr, fma(ci, mi, x[2 * m]));
-            x[2 * m + 1] = fma(cr, mi, fma(-ci, mr, x[2 * m + 1]));
+            x[2 * d] = fma(cr, mr, fma(ci, mi, x[2 * d]));
+            x[2 * d + 1] = fma(cr, mi, fma(-ci, mr, x[2 * d + 1]));
           }
         }
       }
@@ -484,13 +489,18 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
   double2 *U2 = reinterpret_cast<double2 *>(B.Ucoh + ((int64_t)l * nbt + gb) * 8);
 #pragma unroll
   for (int h = 0; h < 4; ++h) U2[h] = make_double2(u[2 * h], u[2 * h + 1]);
+  auto xat = [&](int a, int b) {
+    return reinterpret_cast<double2 *>(B.Xcoh + (((int64_t)a * pb.K + b) * nbt + gb) * 2);
+  };
 #pragma unroll
-  for (int m = 0; m < G; ++m)
-    if (m < pb.K) {
-      double2 *X2 = reinterpret_cast<double2 *>(B.Xcoh + (((int64_t)l * pb.K + m) * nbt + gb) * 2);
-      *X2 = m < Kf ? make_double2(x[2 * m], x[2 * m + 1]) : make_double2(0.0, 0.0);
-    }
-  Sb[L.sb_off[f] + (int64_t)l * nb + bi] = sbl;
+  for (int d = 0; d < kD; ++d) {
+    if (d > dmax || (d == dmax && d > 0 && half)) continue;
+    const int m = l + d < Kf ? l + d : l + d - Kf;
+    *xat(l, m) = make_double2(x[2 * d], x[2 * d + 1]);
+    if (d > 0) *xat(m, l) = make_double2(x[2 * d], -x[2 * d + 1]);
+  }
+  for (int m = Kf; m < pb.K; ++m) *xat(l, m) = make_double2(0.0, 0.0);   // directions f lacks
+  Sb[L.sb_off[f] + (int64_t)l * nb + bi] = x[0];   // X_ll = sum |c_l|^2
 }
 
 // Model visibilities in the caller's full layout (zero on flagged baselines).
