@@ -121,7 +121,7 @@ struct PcgLds {
 template <int SPL>
 __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
                                  int unreg, double tol, PcgLds<SPL> &sh, double *jt_lds, LmState *st,
-                                 const double *Ys, const double *BZs) {
+                                 const double *Ys, const double *BZs, bool first) {
   constexpr int kPcgWaves = pcg_threads<SPL>() / 64;
   constexpr int kRows = 64 * SPL;               // stations covered
   constexpr int kC = kRows / kPcgWaves;          // columns per wavefront (at most)
@@ -132,9 +132,9 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
   const int N = pb.N, nf = pb.nf;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int C = (N + kPcgWaves - 1) / kPcgWaves, c0 = w * C;
-  const double lam = st->lambda;
+  double lam = st->lambda;   // at the run's first solve set below from Q
   const double rho = unreg ? 0.0 : B.rho[k];
-  const double mu = rho + lam;
+  double mu = rho + lam;
   const double *Sd = B.Sd + ((int64_t)f * pb.K + k) * N * N;
 
   // gradient of the data term, gathered over station p's baselines (wavefront w takes every
@@ -255,6 +255,22 @@ __device__ inline void pcg_solve(const Problem &pb, const Layout &L, const Buffe
 #pragma unroll
         for (int i = 0; i < kPcgWaves; ++i) v += Wp[i][c][lane + 64 * s];
         Qp[s][c] = v;
+      }
+    }
+    if (first) {
+      // the run's initial damping lambda_0 = tau max diag(H_GN + rho I): the diagonal of H_GN
+      // at station p holds 2 Q_p[0][0] and 2 Q_p[1][1] (the squared column norms of the J_q
+      // weighted by S_pq)
+      double m = 0.0;
+#pragma unroll
+      for (int s = 0; s < SPL; ++s)
+        if (lane + 64 * s < N) m = fmax(m, fmax(Qp[s][0], Qp[s][1]));
+      m = lmd::wave_max(m);
+      lam = kLmTau * (2.0 * m + rho);
+      mu = rho + lam;
+      if (lane == 0) {
+        st->lambda = lam;
+        st->lambda0 = lam;
       }
     }
   }
@@ -666,14 +682,14 @@ __global__ __launch_bounds__(pcg_threads<SPL>()) void k_local_step(Problem pb, L
       }
       __syncthreads();
       const double F = E + (unreg ? 0.0 : penalty_lds<NT>(N, rho, sh.Js, Ys, BZs, red));
-      const double md = lmd::max_diag<NT>(pb, B, f, k, sh.Js, kJS) + rho;
-      if (threadIdx.x == 0) lmd::begin_state(B, f, &lst, F, E, md, false, 0, 0);
+      // lambda_0 comes from the first solve's Q blocks (pcg_solve)
+      if (threadIdx.x == 0) lmd::begin_state(B, f, &lst, F, E, 0.0, false, 0, 0);
       __syncthreads();
       if (lst.done && threadIdx.x == 0)   // a run that cannot start (non-finite state): trace rows only
         lmd::stopped_rows(pb, f, k, &lst, lm_trace, 0, lm_iters, lm_iters);
       double Ecur = E;   // data cost at the run's current point
       for (int it = 0; it < lm_iters && !lst.done; ++it) {
-        pcg_solve<SPL>(pb, L, B, f, k, unreg, pb.cg_tol, sh, sh.Us, &lst, Ys, BZs);
+        pcg_solve<SPL>(pb, L, B, f, k, unreg, pb.cg_tol, sh, sh.Us, &lst, Ys, BZs, it == 0);
         __syncthreads();
         const int ok = lst.chol_ok;
         double En = 0.0, Fn = 0.0;
