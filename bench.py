@@ -62,8 +62,8 @@ MEASURED_TRAFFIC = {
         ("paper_1502_00858_amd/csrc/pcg_kernel.hip", "paper_1502_00858_amd/csrc/lm_device.h",
          "paper_1502_00858_amd/csrc/calib_internal.h", "paper_1502_00858_amd/csrc/wave_reduce.h",
          "paper_1502_00858_amd/csrc/calib_host.cpp"),
-        "c24e7f5d2624424d03fa3a43d4e000fb9218783991674c25ba03d6fec8782b32",
-        (85.67 + 92.97) * 1e6),
+        "066d049fb241703ec9f7804dd0e29082d33fe37c26686c1b205b43edaee25835",
+        (79.43 + 90.41) * 1e6),
 }
 
 
