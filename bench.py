@@ -5,7 +5,7 @@ learned warm start against the plain starts.
 Workload (default c2): N=62 stations (1891 baselines), K=5 directions, T=10 slots, 32 subbands x 4
 channels over 115-185 MHz, 4-term polynomial basis, rho=5, at most 10 LM iterations per direction
 under the LM stopping rule (lm_tol 1e-7), FP32 streaming with FP64 statistics, solve, cost and Z;
-local solver: matrix-free conjugate gradients (solver 3, cg_tol 1e-4) inside the one-launch local
+local solver: matrix-free conjugate gradients (solver 3, cg_tol 1e-2) inside the one-launch local
 step.  The data are consecutive solution intervals of a drifting observation
 (synth.episode_interval); the measured interval is interval 3 of a held-out episode, whose
 predecessors were solved (30 ADMM iterations each) to give the previous C-ADMM state (J, Y, Z, B_f Z).
@@ -211,8 +211,10 @@ def main():
     ap.add_argument("--solver", type=int, default=3,
                     help="local solver: 3 matrix-free conjugate gradients in the one-launch local "
                          "step; 0 Cholesky (auto), 1 one workgroup per matrix, 2 blocked panels")
-    ap.add_argument("--cg-tol", type=float, default=1e-4,
-                    help="solver 3: relative residual at which conjugate gradients stop")
+    ap.add_argument("--cg-tol", type=float, default=1e-2,
+                    help="solver 3: relative residual at which conjugate gradients stop (inexact "
+                         "LM steps: 1e-4, 1e-3 and 1e-2 reach the target in the same C-ADMM "
+                         "iterations from every start on c2)")
     ap.add_argument("--chain-iters", type=int, default=30,
                     help="ADMM iterations per interval when solving the episodes")
     ap.add_argument("--target-iters", type=int, default=600,

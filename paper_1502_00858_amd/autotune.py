@@ -104,7 +104,7 @@ def measure_solver(data: dict, vis, coh, flags, precision: int, tile_group: int,
 def tune(data: dict, vis, coh, flags, precision: int, n_cu: int = 256,
          grids: Optional[Sequence[int]] = None, cache: Optional[str] = None,
          refresh: bool = False, verbose: bool = False, solvers: Sequence[int] = (3, 1, 2),
-         lm_iters: int = 10, lm_tol: float = 1e-7, cg_tol: float = 1e-4) -> dict:
+         lm_iters: int = 10, lm_tol: float = 1e-7, cg_tol: float = 1e-2) -> dict:
     """Fastest (tile_group, stream_grid) and solver for this problem shape; cached by shape_key
     and the solver settings."""
     cache = cache or _default_cache()

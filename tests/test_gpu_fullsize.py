@@ -101,15 +101,15 @@ def test_c2_stopping_rule_solve(cal, oracle_mod, synth_mod):
     np.testing.assert_allclose(trg[:, :2], tro[:, :2], rtol=1e-5)
 
 
-# the benchmark's solver settings: matrix-free CG at cg_tol 1e-4 in the one-launch local step, LM
+# the benchmark's solver settings: matrix-free CG at cg_tol 1e-2 in the one-launch local step, LM
 # stopping rule at lm_tol 1e-7, no packed sample copy (CALIB_OPT_STATS_ONLY, data costs from the
 # coherency statistics); the oracle takes the same reading (block-Jacobi CG to the same
 # relative residual, same rule)
-BENCH_GPU = dict(solver=3, cg_tol=1e-4, lm_tol=1e-7, options=1 | 4)   # GPA first, statistics only
+BENCH_GPU = dict(solver=3, cg_tol=1e-2, lm_tol=1e-7, options=1 | 4)   # GPA first, statistics only
 
 
 def _bench_oracle(oracle_mod):
-    return dict(solver=oracle_mod.SOLVE_PCG, cg_tol=1e-4, lm_tol=1e-7)
+    return dict(solver=oracle_mod.SOLVE_PCG, cg_tol=1e-2, lm_tol=1e-7)
 
 
 def test_c3_first_local_step_benchmark_solver(cal, oracle_mod, synth_mod):
@@ -119,7 +119,7 @@ def test_c3_first_local_step_benchmark_solver(cal, oracle_mod, synth_mod):
 
 def test_c2_benchmark_configuration(cal, oracle_mod, synth_mod):
     """The timed configuration on the full c2 problem: FP32 streaming, the one-launch local step
-    with CG at cg_tol 1e-4 and the stopping rule at lm_tol 1e-7, three C-ADMM iterations from
+    with CG at cg_tol 1e-2 and the stopping rule at lm_tol 1e-7, three C-ADMM iterations from
     identity replayed from the captured graph; the oracle runs the same reading on the
     FP32-rounded inputs of all 32 subbands.  Data cost and Lagrangian within 1e-5: a CG run that
     stops one iteration apart on the two sides (a residual within rounding of the tolerance)
