@@ -535,25 +535,25 @@ __device__ inline double fused_trial(const Problem &pb, const Layout &L, const B
 }
 
 // SAGE commit of direction k (lmd::commit_tile): with dM = J1_p J1_q^H - J0_p J0_q^H (J1 the run's
-// final J, J0 its start, both in LDS), every direction l from l0 updates D_l -= X_lk dM and the
-// energy changes by sum_b X_kk ||dM||^2 - 2 Re <dM, D_k> (returned to every thread).  dM is formed
-// once per baseline; the directions are walked with the next one's D_l and X_lk requested before
-// the current one's are stored.
+// final J, J0 its start, both in LDS), every later direction l (every direction, k's own included,
+// with several sweeps) updates D_l -= X_lk dM.  The residual's energy after the run needs no pass:
+// it is the data cost of the run's last accepted trial point.  dM is formed once per baseline; the
+// directions are walked with the next one's D_l and X_lk requested before the current one's are
+// stored.
 template <int NT>
-__device__ inline double fused_commit(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
-                                      int all, const double *J1, const double *J0, const LmState *st,
-                                      double (*red)[NT / 64]) {
+__device__ inline void fused_commit(const Problem &pb, const Layout &L, const Buffers &B, int f, int k,
+                                    int all, const double *J1, const double *J0, const LmState *st) {
   constexpr int kBpr = NT / kQuad;   // baselines per round
   constexpr int kU = rounds<NT>();
   const int Kf = L.ndir[f], nb = L.nb[f], K = pb.K, next = k + 1 < Kf ? k + 1 : 0;
   const int64_t b0 = L.bl_off[f], nbt = pb.nbt;
-  const int l0 = all ? 0 : k;
+  const int l0 = all ? 0 : k + 1;
+  if (l0 >= Kf) return;
   const int h = threadIdx.x & 3, ei = h >> 1, ej = h & 1, sub = threadIdx.x >> 2;
   double2 *Dall = reinterpret_cast<double2 *>(B.Dall);
   const double2 *X = reinterpret_cast<const double2 *>(B.Xcoh);
   double2 *Da = reinterpret_cast<double2 *>(d_accepted(B, *st));
   double2 *Ds = reinterpret_cast<double2 *>(B.Dstart);
-  double part = 0.0;
   // a full batch runs without per-baseline guards; the last one may be partial
   auto batch = [&](int base, auto full) {
     constexpr bool kFull = decltype(full)::value;
@@ -588,25 +588,17 @@ __device__ inline double fused_commit(const Problem &pb, const Layout &L, const 
         x[u] = xn[u];
       }
       if (l + 1 < Kf) request(l + 1);
-      const bool upd = all || l > k;
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int bi = base + sub + kBpr * u;
         if (!kFull && bi >= nb) continue;
         const int64_t gb = b0 + bi;
-        if (l == k) {
-          const double cross = fma(dm[u].x, d[u].x, dm[u].y * d[u].y);
-          const double norm = fma(dm[u].x, dm[u].x, dm[u].y * dm[u].y);
-          part += fma(x[u].x, norm, -2.0 * cross);
-        }
-        if (upd) {
-          const double2 t = make_double2(d[u].x - (x[u].x * dm[u].x - x[u].y * dm[u].y),
-                                         d[u].y - (x[u].x * dm[u].y + x[u].y * dm[u].x));
-          Dall[4 * ((int64_t)l * nbt + gb) + h] = t;
-          if (l == next) {
-            Da[4 * gb + h] = t;
-            Ds[4 * gb + h] = t;
-          }
+        const double2 t = make_double2(d[u].x - (x[u].x * dm[u].x - x[u].y * dm[u].y),
+                                       d[u].y - (x[u].x * dm[u].y + x[u].y * dm[u].x));
+        Dall[4 * ((int64_t)l * nbt + gb) + h] = t;
+        if (l == next) {
+          Da[4 * gb + h] = t;
+          Ds[4 * gb + h] = t;
         }
       }
     }
@@ -615,9 +607,6 @@ __device__ inline double fused_commit(const Problem &pb, const Layout &L, const 
     if (base + kBpr * kU <= nb) batch(base, std::true_type{});
     else batch(base, std::false_type{});
   }
-  double v[1] = {part};
-  lmd::block_sum_vec<1, NT>(v, red);
-  return v[0];   // the change of the residual's energy
 }
 
 // Re tr(Y^H (J - BZ)) + rho/2 ||J - BZ||^2 of the direction (whole workgroup of NT threads;
@@ -708,13 +697,11 @@ __global__ __launch_bounds__(pcg_threads<SPL>()) void k_local_step(Problem pb, L
           }
         __syncthreads();
       }
-      // the commit updates the later directions' D_l; the last direction of a single sweep has none
-      // to update, and the residual's energy after the run is the data cost of its last accepted
-      // trial point (the commit's energy change is the same sum, at the same points)
-      if (all || k + 1 < Kf)
-        E += fused_commit<NT>(pb, L, B, f, k, all, sh.Js, J0s, &lst, red);
-      else
-        E = Ecur;
+      // the commit updates the later directions' D_l (the last direction of a single sweep has none
+      // to update); the residual's energy after the run is the data cost of its last accepted
+      // trial point (the same sum as the energy change the commit would form, at the same points)
+      fused_commit<NT>(pb, L, B, f, k, all, sh.Js, J0s, &lst);
+      E = Ecur;
       __syncthreads();
     }
   if (threadIdx.x == 0) B.lm[f] = lst;

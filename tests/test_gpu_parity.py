@@ -88,18 +88,22 @@ def test_max_directions_fp64(cal, oracle_mod, synth_mod):
     assert err < FP64_VIS_TOL
 
 
-def test_two_sage_sweeps_fp64(cal, oracle_mod, synth_mod):
+@pytest.mark.parametrize("solver", [0, 3])
+def test_two_sage_sweeps_fp64(cal, oracle_mod, synth_mod, solver):
     """Two SAGE sweeps per local step: each commit then updates every direction's statistics (the
     second sweep starts again from direction 0).  The last sweep's LM trace, the local step's J and
-    a short C-ADMM trajectory agree with the oracle."""
+    a short C-ADMM trajectory agree with the oracle, for the Cholesky and the matrix-free solver
+    (CG at cg_tol 1e-10 on both sides)."""
     cfg = tiny_cfg(synth_mod, N=6, P=3, K=3, T=3, n_chan=2, lm_iters=4)
     d = synth_mod.generate(cfg)
     J0 = synth_mod.identity_jones(cfg.P, cfg.K, cfg.N)
-    c = _ctx(cal, d, 0, lm_iters=4, sage_sweeps=2)
+    gkw = dict(solver=3, cg_tol=1e-10) if solver == 3 else {}
+    okw = dict(solver=oracle_mod.SOLVE_PCG, cg_tol=1e-10) if solver == 3 else {}
+    c = _ctx(cal, d, 0, lm_iters=4, sage_sweeps=2, **gkw)
     c.local_step(0)
     Jg = c.get(cal.FIELD_J).cpu().numpy()
     trg = c.get(cal.FIELD_LM_TRACE).cpu().numpy()
-    pb = oracle_mod.Problem(d, lm_iters=4, sage_sweeps=2)
+    pb = oracle_mod.Problem(d, lm_iters=4, sage_sweeps=2, **okw)
     z = np.zeros_like(J0)
     Jo, tro = pb.local_step(J0, z, z, trace=True)
     np.testing.assert_array_equal(trg[..., 2], tro[:, 1, :, :, 2])
@@ -107,7 +111,7 @@ def test_two_sage_sweeps_fp64(cal, oracle_mod, synth_mod):
     err = _rel(pb.predict(Jg), pb.predict(Jo))
     print(f"visibilities after one local step: {err:.2e}")
     assert err < FP64_VIS_TOL
-    trg = _ctx(cal, d, 0, lm_iters=4, sage_sweeps=2).solve(3)
+    trg = _ctx(cal, d, 0, lm_iters=4, sage_sweeps=2, **gkw).solve(3)
     tro = pb.admm_solve(J0, 3)["trace"]
     np.testing.assert_allclose(trg[:, 0], tro[:, 0], rtol=1e-10)
 
