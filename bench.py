@@ -62,8 +62,8 @@ MEASURED_TRAFFIC = {
         ("paper_1502_00858_amd/csrc/pcg_kernel.hip", "paper_1502_00858_amd/csrc/lm_device.h",
          "paper_1502_00858_amd/csrc/calib_internal.h", "paper_1502_00858_amd/csrc/wave_reduce.h",
          "paper_1502_00858_amd/csrc/calib_host.cpp"),
-        "066d049fb241703ec9f7804dd0e29082d33fe37c26686c1b205b43edaee25835",
-        (79.76 + 90.61) * 1e6),
+        "ac3f6ef1c0d31462db05b2ab3bb9b8e8b41eac642f4057cdce68d51580777776",
+        (57.56 + 84.43) * 1e6),
 }
 
 
@@ -88,14 +88,15 @@ def local_step_flops(data, work, launches):
       per LM solve      8 N^2 (Q_p = sum_q S_pq J_q^H J_q) + 144 nb (gradient: two 2x2 complex
                         products per baseline) + 160 nb (trial point: two J_p J_q^H per baseline
                         and its D_b) + 132 N;
-      per direction     2 N^2 (largest diagonal entry) + nb (120 + 48 (K_f - k)) (the SAGE commit
-                        into every later direction's statistics);
+      per direction     2 N^2 (largest diagonal entry), and for every direction but the last
+                        nb (120 + 32 (K_f - 1 - k)) (the SAGE commit: the change of J_p J_q^H, then
+                        one complex product per later direction's D_l);
     nb = unflagged baselines of the subband, K_f its directions, k the direction's index."""
     N = int(data["N"])
     nb = data["nb_live"].astype(np.float64)
     Kf = np.asarray(data["n_dirs"], np.float64)
     cg, lm = work[:, 0] / launches, work[:, 1] / launches
-    per_dir = 2.0 * N * N * Kf + nb * (120.0 * Kf + 48.0 * Kf * (Kf + 1) / 2.0)
+    per_dir = 2.0 * N * N * Kf + nb * (120.0 * (Kf - 1.0) + 32.0 * (Kf - 1.0) * Kf / 2.0)
     return float(np.sum(cg * (16.0 * N * N + 260.0 * N)
                         + lm * (8.0 * N * N + 304.0 * nb + 132.0 * N) + per_dir))
 
