@@ -301,9 +301,9 @@ calib_status local_step_stopping_on(calib_ctx *c, int admm_iter, hipStream_t s) 
 // the device iteration counter, which the last kernel advances
 calib_status consensus_on(calib_ctx *c, bool gpa, hipStream_t s) {
   HIPCHK(c, timed(c, CALIB_KERNEL_CONSENSUS, [&] {
-    hipError_t e = launch_penalty_trace(c->pb, c->L, c->B, s);
+    hipError_t e = launch_penalty_part(c->pb, c->L, c->B, s);
     if (e == hipSuccess && gpa) e = launch_gpa(c->pb, c->L, c->B, 3, s);
-    if (e == hipSuccess) e = launch_consensus(c->pb, c->L, c->B, s);
+    if (e == hipSuccess) e = launch_consensus(c->pb, c->L, c->B, true, s);
     return e;
   }));
   return CALIB_OK;

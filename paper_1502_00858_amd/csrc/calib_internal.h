@@ -186,9 +186,12 @@ hipError_t launch_dir_reset(const Problem &pb, const Buffers &B, hipStream_t s);
 hipError_t launch_basis_setup(const Problem &pb, const double *freq, double f0, const int32_t *ndir,
                               double *basis, double *fitw, int *rank_fail, hipStream_t s);
 hipError_t launch_set_iter(const Buffers &B, int iter, hipStream_t s);
-hipError_t launch_penalty_trace(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
+// per-subband data cost and penalty partials of the trace row, taken before the alignment and the
+// Y update; launch_consensus(with_penalty) folds them into the row
+hipError_t launch_penalty_part(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
 hipError_t launch_gpa(const Problem &pb, const Layout &L, const Buffers &B, int rounds, hipStream_t s);
-hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
+hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, bool with_penalty,
+                             hipStream_t s);
 hipError_t launch_subband_cost(const Problem &pb, const Layout &L, const Buffers &B, double *out,
                                hipStream_t s);
 // warm start (warmstart_kernels.hip)

@@ -10,7 +10,8 @@
 //                 initialisation): generalised Procrustes to the mean over subbands.
 //   z_fit       : Z_k per direction and the dual-residual partials.
 //   y_update    : B_f Z_k, Y_fk += rho_k (J_fk - B_f Z_k) (minimisation M3) and primal partials.
-//   residuals   : primal and dual residuals of Section 4.1 averaged over (f, k) and k.
+//   residuals   : primal and dual residuals of Section 4.1 averaged over (f, k) and k, and the
+//                 trace row's data cost and augmented Lagrangian.
 #include "calib_internal.h"
 #include "wave_reduce.h"
 #include "device_math.h"
@@ -113,22 +114,6 @@ __global__ __launch_bounds__(kBlock) void k_penalty_part(Problem pb, Layout L, B
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_penalty_trace(Problem pb, Buffers B) {
-  __shared__ double red[2][kBlock / 64];
-  const double *part = B.scratch + (int64_t)pb.P * pb.K + (int64_t)pb.K * kZChunks;
-  double v[2] = {0.0, 0.0};
-  for (int f = threadIdx.x; f < pb.P; f += kBlock) {
-    v[0] += part[2 * f];
-    v[1] += part[2 * f + 1];
-  }
-  block_sum_vec<2>(v, red);
-  if (threadIdx.x == 0) {
-    const int iter = B.iter[0];
-    B.trace[4 * iter] = v[0];
-    B.trace[4 * iter + 1] = v[0] + v[1];
-  }
-}
-
 __global__ __launch_bounds__(kBlock) void k_subband_cost(Problem pb, Layout L, Buffers B, double *out) {
   __shared__ double red[1][kBlock / 64];
   const int f = blockIdx.x;
@@ -201,45 +186,76 @@ __global__ __launch_bounds__(kBlock) void k_gpa(Problem pb, Layout L, Buffers B,
 }
 
 // grid (K, kZChunks) of one wavefront each: Z_k = W_k (J + Y/rho) for 64 of the direction's 8N
-// real Jones parameters (N <= 128), one per lane, the subbands taken in order with sixteen
-// subbands' J and Y requested before the first is used; the chunk's part of ||Z_new - Z_old||^2
-// to the dual-residual partials (chunks past 8N write zero)
+// real Jones parameters (N <= 128), one per lane, the subbands taken in order. Per block of 64
+// subbands the block's fit weights go to LDS with one coalesced load per basis term and the
+// subbands carrying the direction to a wave-uniform bit mask (per-subband scalar loads would
+// each wait on their own); then sixteen subbands' J and Y are requested before the first is used.
+// The chunk's part of ||Z_new - Z_old||^2 goes to the dual-residual partials (chunks past 8N
+// write zero).
 __global__ __launch_bounds__(64) void k_z_fit(Problem pb, Layout L, Buffers B) {
+  __shared__ __align__(16) double sw[64][8];   // [subband of the block][basis term]
   if (B.rank_fail && *B.rank_fail) return;
-  const int k = blockIdx.x, c = blockIdx.y, N = pb.N, P = pb.P, Q = pb.Q;
-  const int e = c * 64 + threadIdx.x;
+  const int k = blockIdx.x, c = blockIdx.y, N = pb.N, P = pb.P, Q = pb.Q, t = threadIdx.x;
+  double *dz_out = B.scratch + (int64_t)pb.P * pb.K + (int64_t)k * kZChunks + c;
+  if (c * 64 >= 8 * N) {
+    if (t == 0) *dz_out = 0.0;
+    return;
+  }
+  const int e = c * 64 + t;
+  const bool live = e < 8 * N;
   const double rho = B.rho[k];
   const double *W = B.fitw + (int64_t)k * Q * P;
   constexpr int kF = 16;
-  double dz = 0.0;
-  if (e < 8 * N) {
-    double z[8];
-    for (int l = 0; l < Q; ++l) z[l] = 0.0;
-    for (int f0 = 0; f0 < P; f0 += kF) {
+  static_assert(64 % kF == 0, "a batch of subbands stays inside its block");
+  double z[8];
+#pragma unroll
+  for (int l = 0; l < 8; ++l) z[l] = 0.0;
+  for (int fb = 0; fb < P; fb += 64) {
+    const int fl = fb + t, fc = min(fl, P - 1);
+    const bool carried = fl < P && L.ndir[fc] > k;
+    double wl[8];
+#pragma unroll
+    for (int l = 0; l < 8; ++l) {   // every load issued before the first is used; terms past Q
+      const double w = W[min(l, Q - 1) * P + fc];   // repeat the last one and are never stored
+      wl[l] = carried ? w : 0.0;
+    }
+    __syncthreads();   // the previous block's weights have been read
+#pragma unroll
+    for (int l = 0; l < 8; ++l) sw[t][l] = wl[l];
+    const uint64_t mask = __ballot(carried);
+    __syncthreads();
+    const int nf = min(64, P - fb);
+    if (!live) continue;
+    for (int f0 = 0; f0 < nf; f0 += kF) {
       double jv[kF], yv[kF];
 #pragma unroll
       for (int u = 0; u < kF; ++u) {
-        const int64_t o = ((int64_t)min(f0 + u, P - 1) * pb.K + k) * N * 8 + e;
+        const int64_t o = ((int64_t)min(fb + f0 + u, P - 1) * pb.K + k) * N * 8 + e;
         jv[u] = B.J[o];
         yv[u] = B.Y[o];
       }
 #pragma unroll
-      for (int u = 0; u < kF; ++u) {
+      for (int u = 0; u < kF; ++u) {   // f0 + u < 64: kF divides 64
         const int f = f0 + u;
-        if (f >= P || L.ndir[f] <= k) continue;
-        const double x = (rho > 0.0) ? jv[u] + yv[u] / rho : jv[u];
-        for (int l = 0; l < Q; ++l) z[l] += W[l * P + f] * x;
+        const double x0 = (rho > 0.0) ? jv[u] + yv[u] / rho : jv[u];
+        const double x = ((mask >> f) & 1) ? x0 : 0.0;   // past the last subband or not carrying k
+#pragma unroll
+        for (int l = 0; l < 8; ++l) z[l] += sw[f][l] * x;
       }
     }
-    for (int l = 0; l < Q; ++l) {
-      const int64_t o = ((int64_t)k * Q + l) * N * 8 + e;
-      const double d = z[l] - B.Z[o];
-      dz += d * d;
-      B.Z[o] = z[l];
-    }
   }
+  double dz = 0.0;
+  if (live)
+#pragma unroll
+    for (int l = 0; l < 8; ++l)
+      if (l < Q) {
+        const int64_t o = ((int64_t)k * Q + l) * N * 8 + e;
+        const double d = z[l] - B.Z[o];
+        dz += d * d;
+        B.Z[o] = z[l];
+      }
   dz = wave_sum(dz);
-  if (threadIdx.x == 0) B.scratch[(int64_t)pb.P * pb.K + (int64_t)k * kZChunks + c] = dz;
+  if (t == 0) *dz_out = dz;
 }
 
 // grid (P, K): B_f Z_k, dual ascent, primal partial ||J - BZ||^2
@@ -268,15 +284,38 @@ __global__ __launch_bounds__(kBlock) void k_y_update(Problem pb, Layout L, Buffe
   if (threadIdx.x == 0) B.scratch[slot] = v[0];
 }
 
-// averages the residual partials into the trace row of the current iteration and advances the
-// iteration counter (so that a replayed graph writes the next row)
-// Primal and dual residual norms of the trace row from the per-(subband, direction) and
-// per-direction partials: 64 threads take strided shares, summed in a fixed order.
-__global__ __launch_bounds__(64) void k_residuals(Problem pb, Buffers B) {
+// Trace row of the current iteration: primal and dual residual norms from the per-(subband,
+// direction) and per-direction partials, and (with_penalty) the data cost and augmented Lagrangian
+// from the per-subband partials of k_penalty_part; 64 threads take strided shares, summed in a
+// fixed order. Advances the iteration counter, so that a replayed graph writes the next row.
+__global__ __launch_bounds__(64) void k_residuals(Problem pb, Buffers B, int with_penalty) {
   __shared__ double sps[64];
+  __shared__ double spen[2][64];
   __shared__ int spc[64];
-  if (B.rank_fail && *B.rank_fail) return;
   const int t = threadIdx.x;
+  if (with_penalty) {
+    const double *part = B.scratch + (int64_t)pb.P * pb.K + (int64_t)pb.K * kZChunks;
+    double g = 0.0, a = 0.0;
+    for (int f = t; f < pb.P; f += 64) {
+      g += part[2 * f];
+      a += part[2 * f + 1];
+    }
+    spen[0][t] = g;
+    spen[1][t] = a;
+    __syncthreads();
+    if (t == 0) {
+      g = 0.0;
+      a = 0.0;
+      for (int i = 0; i < 64; ++i) {
+        g += spen[0][i];
+        a += spen[1][i];
+      }
+      const int iter = B.iter[0];
+      B.trace[4 * iter] = g;
+      B.trace[4 * iter + 1] = g + a;
+    }
+  }
+  if (B.rank_fail && *B.rank_fail) return;
   double ps = 0.0;
   int pc = 0;
   const double pn = sqrt(4.0 * pb.N);
@@ -347,11 +386,8 @@ hipError_t launch_set_iter(const Buffers &B, int iter, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_penalty_trace(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
+hipError_t launch_penalty_part(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
   hipLaunchKernelGGL(k_penalty_part, dim3(pb.P), dim3(kBlock), 0, s, pb, L, B);
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_penalty_trace, dim3(1), dim3(kBlock), 0, s, pb, B);
   return hipGetLastError();
 }
 
@@ -367,7 +403,8 @@ hipError_t launch_gpa(const Problem &pb, const Layout &L, const Buffers &B, int 
   return hipGetLastError();
 }
 
-hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
+hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, bool with_penalty,
+                             hipStream_t s) {
   if (pb.N > kMaxStations) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_z_fit, dim3(pb.K, kZChunks), dim3(64), 0, s, pb, L, B);
   hipError_t e = hipGetLastError();
@@ -375,7 +412,7 @@ hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B
   hipLaunchKernelGGL(k_y_update, dim3(pb.P, pb.K), dim3(kBlock), 0, s, pb, L, B);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_residuals, dim3(1), dim3(64), 0, s, pb, B);
+  hipLaunchKernelGGL(k_residuals, dim3(1), dim3(64), 0, s, pb, B, with_penalty ? 1 : 0);
   return hipGetLastError();
 }
 
