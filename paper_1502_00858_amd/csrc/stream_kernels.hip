@@ -158,121 +158,109 @@ __global__ __launch_bounds__(64 * kStatTiles) void k_trial_stats(Problem pb, Lay
   lmd::trial_tile(pb, L, B, f, k, tile, lane);
 }
 
-// Every direction's D_l at the current point from the coherency statistics (grid: tile x block of
-// kDallL directions, one lane per baseline: M_m = J_p J_q^H of every direction m is formed once per
-// lane and block and applied to the block's D_l = U_l - sum_m X_lm M_m); direction 0's D also
-// becomes the accepted and start point of the next LM run.
+// Every direction's D_l at the current point from the coherency statistics, one workgroup per tile
+// and four lanes per baseline: lane h of a baseline's four holds the entry (h>>1, h&1) of its 2x2
+// matrices, so that a wavefront's loads and stores of the per-baseline tables are contiguous.
+// The entry of M_m = J_p J_q^H of every direction m is formed once, then each direction's
+// D_l = U_l - sum_m X_lm M_m is streamed (U_l and the row X_l. read, D_l written); direction 0's D
+// also becomes the accepted and start point of the next LM run.  kL >= K directions are unrolled;
+// the loads of a row X_l. take every m < kL at a clamped index (in bounds, never used past K_f),
+// so that they are issued together.
 // With kEnergy, also the residual's energy from the statistics, with R = V - sum_m c_m M_m:
 //   sum_s ||R_s||^2 = sum_s ||V_s||^2 - 2 Re sum_m <M_m, U_m> + sum_lm X_lm <M_l, M_m>
 //                   = Ev - Re sum_l <M_l, U_l + D_l>     (<A, B> = tr(A^H B), D_l = U_l - sum_m X_lm M_m)
-// each wavefront (one tile) summing its baselines' terms of direction l (direction 0 with Ev) into
-// Epl[l][tile] (zero for the directions l >= K_f of its subband).  In FP64 the expansion cancels by
-// about the ratio of the data's energy to the residual's (~SNR), far inside the double's
-// precision; at a perfect fit it leaves an absolute error of order eps * sum ||V||^2.
-constexpr int kDallL = 4;   // directions per lane
-template <bool kEnergy>
-__global__ __launch_bounds__(64 * kStatTiles) void k_dall(Problem pb, Layout L, Buffers B) {
-  const int tile = kStatTiles * blockIdx.x + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int l0 = kDallL * blockIdx.y;
-  if (tile >= pb.ntiles) return;   // uniform per wavefront
+// the tile's terms of direction l (direction 0 with Ev) summed in a fixed order into Epl[l][tile]
+// (zero for the directions l >= K_f of its subband).  In FP64 the expansion cancels by about the
+// ratio of the data's energy to the residual's (~SNR), far inside the double's precision; at a
+// perfect fit it leaves an absolute error of order eps * sum ||V||^2.
+constexpr int kDallThreads = 256;   // one tile of up to 64 baselines, four lanes each
+template <bool kEnergy, int kL>
+__global__ __launch_bounds__(kDallThreads) void k_dall(Problem pb, Layout L, Buffers B) {
+  __shared__ double red[kL][kDallThreads / 64];
+  const int tile = blockIdx.x, tid = threadIdx.x, w = tid >> 6;
+  const int h = tid & 3, ei = h >> 1, ej = h & 1, bl = tid >> 2;
   const int f = L.tile_f[tile];
   const int Kf = L.ndir[f], nb = L.nb[f], K = pb.K;
-  const int bi = L.tile_b0[tile] + lane;
-  const bool live = l0 < Kf && lane < pb.bpt && bi < nb;
-  double part[kDallL];
+  const int bi = L.tile_b0[tile] + bl;
+  const bool live = bl < pb.bpt && bi < nb;
+  double part[kL];
 #pragma unroll
-  for (int j = 0; j < kDallL; ++j) part[j] = 0.0;
+  for (int l = 0; l < kL; ++l) part[l] = 0.0;
   if (live) {
     const int N = pb.N;
-    const int64_t gb = (int64_t)L.bl_off[f] + bi;
+    const int64_t gb = (int64_t)L.bl_off[f] + bi, nbt = pb.nbt;
     const int p = L.bl_p[gb], q = L.bl_q[gb];
-    const int64_t nbt = pb.nbt;
-    double d[kDallL][8], ml[kDallL][8];
+    // entry (ei, ej) of J_p J_q^H = sum_t J_p[ei][t] conj(J_q[ej][t]) per direction
+    double2 M[kL];
 #pragma unroll
-    for (int j = 0; j < kDallL; ++j) {
-      const int l = l0 + j;
-      if (l < Kf) {
-        const double2 *U2 = reinterpret_cast<const double2 *>(B.Ucoh + ((int64_t)l * nbt + gb) * 8);
+    for (int m = 0; m < kL; ++m) {
+      const int mc = min(m, Kf - 1);
+      const double2 *a = reinterpret_cast<const double2 *>(B.J + (((int64_t)f * K + mc) * N + p) * 8 + 4 * ei);
+      const double2 *b = reinterpret_cast<const double2 *>(B.J + (((int64_t)f * K + mc) * N + q) * 8 + 4 * ej);
+      const double2 a0 = a[0], a1 = a[1], b0 = b[0], b1 = b[1];
+      double re = 0.0, im = 0.0;
+      re += a0.x * b0.x + a0.y * b0.y;
+      im += a0.y * b0.x - a0.x * b0.y;
+      re += a1.x * b1.x + a1.y * b1.y;
+      im += a1.y * b1.x - a1.x * b1.y;
+      M[m] = make_double2(re, im);
+    }
+    const double2 *U2 = reinterpret_cast<const double2 *>(B.Ucoh);
+    const double2 *X2 = reinterpret_cast<const double2 *>(B.Xcoh);
+    double2 *D2 = reinterpret_cast<double2 *>(B.Dall);
+    const double ev = (kEnergy && h == 0) ? B.Ev[gb] : 0.0;
 #pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          const double2 u = U2[h];
-          d[j][2 * h] = u.x;
-          d[j][2 * h + 1] = u.y;
+    for (int l = 0; l < kL; ++l) {
+      if (l >= Kf) continue;   // uniform per workgroup
+      const double2 u = U2[((int64_t)l * nbt + gb) * 4 + h];
+      double2 x[kL];
+#pragma unroll
+      for (int m = 0; m < kL; ++m) x[m] = X2[((int64_t)l * K + min(m, Kf - 1)) * nbt + gb];
+      double2 d = u;
+#pragma unroll
+      for (int m = 0; m < kL; ++m) {
+        if (m < Kf) {
+          d.x -= x[m].x * M[m].x - x[m].y * M[m].y;
+          d.y -= x[m].x * M[m].y + x[m].y * M[m].x;
         }
       }
-    }
-    // direction m's J_p and J_q, requested one direction ahead of their use
-    auto fetch = [&](int m, double *jp, double *jq) {
-      const double2 *P2 = reinterpret_cast<const double2 *>(B.J + (((int64_t)f * K + m) * N + p) * 8);
-      const double2 *Q2 = reinterpret_cast<const double2 *>(B.J + (((int64_t)f * K + m) * N + q) * 8);
-#pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        const double2 a = P2[h], b = Q2[h];
-        jp[2 * h] = a.x; jp[2 * h + 1] = a.y;
-        jq[2 * h] = b.x; jq[2 * h + 1] = b.y;
-      }
-    };
-    auto use = [&](int m, const double *jp, const double *jq) {
-      double x[kDallL][2];
-#pragma unroll
-      for (int j = 0; j < kDallL; ++j)
-        if (l0 + j < Kf) {
-          const double2 xv =
-              *reinterpret_cast<const double2 *>(B.Xcoh + (((int64_t)(l0 + j) * K + m) * nbt + gb) * 2);
-          x[j][0] = xv.x;
-          x[j][1] = xv.y;
-        }
-      double mm[8];
-      jjh(jp, jq, mm);
-#pragma unroll
-      for (int j = 0; j < kDallL; ++j)
-        if (l0 + j < Kf) {
-          sub_scaled(d[j], x[j][0], x[j][1], mm);
-          if (kEnergy && m == l0 + j) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) ml[j][e] = mm[e];
-          }
-        }
-    };
-    double jpa[8], jqa[8], jpb[8], jqb[8];
-    fetch(0, jpa, jqa);
-    for (int m = 0; m < Kf; m += 2) {
-      if (m + 1 < Kf) fetch(m + 1, jpb, jqb);
-      use(m, jpa, jqa);
-      if (m + 2 < Kf) fetch(m + 2, jpa, jqa);
-      if (m + 1 < Kf) use(m + 1, jpb, jqb);
-    }
-#pragma unroll
-    for (int j = 0; j < kDallL; ++j) {
-      const int l = l0 + j;
-      if (l >= Kf) continue;
-      double *D = B.Dall + ((int64_t)l * nbt + gb) * 8;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) D[e] = d[j][e];
+      D2[((int64_t)l * nbt + gb) * 4 + h] = d;
       if (l == 0) {
-        double *Da = d_accepted(B, f) + 8 * gb;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          Da[e] = d[j][e];
-          B.Dstart[8 * gb + e] = d[j][e];
-        }
+        reinterpret_cast<double2 *>(d_accepted(B, f))[4 * gb + h] = d;
+        reinterpret_cast<double2 *>(B.Dstart)[4 * gb + h] = d;
       }
-      if (kEnergy) {
-        const double *U = B.Ucoh + ((int64_t)l * nbt + gb) * 8;
-        double t = 0.0;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) t = fma(ml[j][e], U[e] + d[j][e], t);   // Re <M_l, U_l + D_l>
-        part[j] = (l == 0 ? B.Ev[gb] : 0.0) - t;
-      }
+      if (kEnergy)   // Re <M_l, U_l + D_l> over this lane's entry
+        part[l] = (l == 0 ? ev : 0.0) - fma(M[l].x, u.x + d.x, M[l].y * (u.y + d.y));
     }
   }
   if (kEnergy) {
-    wave_sum_vec<kDallL>(part);
-    if (lane == 0)
+    wave_sum_vec<kL>(part);
+    if ((tid & 63) == 0)
 #pragma unroll
-      for (int j = 0; j < kDallL; ++j)
-        if (l0 + j < K) B.Epl[(int64_t)(l0 + j) * pb.ntiles + tile] = part[j];
+      for (int l = 0; l < kL; ++l) red[l][w] = part[l];
+    __syncthreads();
+    if (tid < K) {
+      double v = 0.0;
+#pragma unroll
+      for (int i = 0; i < kDallThreads / 64; ++i) v += red[tid][i];
+      B.Epl[(int64_t)tid * pb.ntiles + tile] = v;
+    }
   }
+}
+
+template <bool kEnergy>
+hipError_t launch_dall(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
+  if (pb.bpt > 64 || pb.K < 1 || pb.K > kMaxDirs) return hipErrorInvalidValue;
+  const dim3 grid(pb.ntiles), block(kDallThreads);
+  if (pb.K <= 4)
+    hipLaunchKernelGGL((k_dall<kEnergy, 4>), grid, block, 0, s, pb, L, B);
+  else if (pb.K <= 8)
+    hipLaunchKernelGGL((k_dall<kEnergy, 8>), grid, block, 0, s, pb, L, B);
+  else if (pb.K <= 12)
+    hipLaunchKernelGGL((k_dall<kEnergy, 12>), grid, block, 0, s, pb, L, B);
+  else
+    hipLaunchKernelGGL((k_dall<kEnergy, 16>), grid, block, 0, s, pb, L, B);
+  return hipGetLastError();
 }
 
 // The tiles' energies (Epart, cost_part) from the statistics' per-(direction, tile) terms, for the
@@ -551,18 +539,13 @@ template <typename T>
 hipError_t launch_refresh(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s) {
   const hipError_t e = launch_energy<T>(pb, L, B, s);
   if (e != hipSuccess || pb.ntiles == 0) return e;
-  if (pb.bpt > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dall<false>, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles, (pb.K + kDallL - 1) / kDallL),
-                     dim3(64 * kStatTiles), 0, s, pb, L, B);
-  return hipGetLastError();
+  return launch_dall<false>(pb, L, B, s);
 }
 hipError_t launch_refresh_stats(const Problem &pb, const Layout &L, const Buffers &B, bool fold,
                                 hipStream_t s) {
   if (pb.ntiles == 0) return hipSuccess;
-  if (pb.bpt > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dall<true>, dim3((pb.ntiles + kStatTiles - 1) / kStatTiles, (pb.K + kDallL - 1) / kDallL),
-                     dim3(64 * kStatTiles), 0, s, pb, L, B);
-  if (!fold) return hipGetLastError();
+  hipError_t e = launch_dall<true>(pb, L, B, s);
+  if (e != hipSuccess || !fold) return e;
   hipLaunchKernelGGL(k_fold_energy, dim3((pb.ntiles + kBlock - 1) / kBlock), dim3(kBlock), 0, s, pb, B);
   return hipGetLastError();
 }
