@@ -269,10 +269,15 @@ __global__ __launch_bounds__(kBlock) void k_y_update(Problem pb, Layout L, Buffe
     return;
   }
   const double rho = B.rho[k];
+  double bf[8];   // the subband's basis row, read once (the stores below could alias it)
+#pragma unroll
+  for (int l = 0; l < 8; ++l) bf[l] = l < Q ? B.basis[f * Q + l] : 0.0;
   double pr = 0.0;
   for (int e = threadIdx.x; e < 8 * N; e += kBlock) {
     double bz = 0.0;
-    for (int l = 0; l < Q; ++l) bz += B.basis[f * Q + l] * B.Z[((int64_t)k * Q + l) * N * 8 + e];
+#pragma unroll
+    for (int l = 0; l < 8; ++l)
+      if (l < Q) bz += bf[l] * B.Z[((int64_t)k * Q + l) * N * 8 + e];
     const int64_t o = slot * N * 8 + e;
     B.BZ[o] = bz;
     const double t = B.J[o] - bz;
