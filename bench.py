@@ -62,8 +62,8 @@ MEASURED_TRAFFIC = {
         ("paper_1502_00858_amd/csrc/pcg_kernel.hip", "paper_1502_00858_amd/csrc/lm_device.h",
          "paper_1502_00858_amd/csrc/calib_internal.h", "paper_1502_00858_amd/csrc/wave_reduce.h",
          "paper_1502_00858_amd/csrc/calib_host.cpp"),
-        "ac3f6ef1c0d31462db05b2ab3bb9b8e8b41eac642f4057cdce68d51580777776",
-        (57.56 + 84.43) * 1e6),
+        "dbe15939b19eb39585f40e0b4e1bf8668c2c1620d6378fcc9e4b5bda7bd530f0",
+        (64.95 + 84.40) * 1e6),
 }
 
 
