@@ -332,7 +332,10 @@ hipError_t launch_energy(const Problem &pb, const Layout &L, const Buffers &B, h
 // the chunk issued before the first is used, into LDS and into the packed arrays; then lane l
 // accumulates direction l's sums from LDS (the group's lanes read the same words: broadcasts).
 // Only the group's own lanes exchange data through LDS, so the wavefronts never wait for each
-// other.  Rows are padded by 16 bytes so that the groups of a wavefront hit different LDS banks.
+// other.  V rows are padded by 16 bytes so that the groups of a wavefront hit different LDS banks;
+// a baseline's coherencies are stored [sample][direction], so that the group's lanes, each reading
+// its own direction at one sample, read consecutive words (stored direction-major, at a direction
+// stride that is a multiple of the bank count, every such read was a K_f-way bank conflict).
 // A non-finite input sets *bad (when given) and the subband's status word.
 template <typename T>
 struct Cplx;
@@ -360,12 +363,15 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
   constexpr int TB = kBlock / G;                   // baselines per workgroup
   constexpr int SC = 32 / (int)sizeof(T);          // samples per chunk
   constexpr int PAD = 16 / (int)sizeof(T);
-  constexpr int VR = SC * 8 + PAD, CR = SC * 2 + PAD;   // padded LDS rows (elements)
+  constexpr int VR = SC * 8 + PAD;                 // padded LDS row of V (elements)
+  // a baseline's chunk of coherencies, [sample][direction] (lanes reading different directions at
+  // one sample hit consecutive banks), padded by 128 bytes between the group's baselines
+  constexpr int CJ = SC * G * 2 + 128 / (int)sizeof(T);
   constexpr int NV = 4 * SC / G;                   // V values per lane per chunk
   constexpr int NC = SC;                           // coherency values per lane per chunk (G*SC >= K_f*SC)
   static_assert(NV >= 1 && 4 * SC == NV * G, "chunk of V split evenly over the group");
   __shared__ __align__(16) T Vs[TB * VR];
-  __shared__ __align__(16) T Cs[G * TB * CR];
+  __shared__ __align__(16) T Cs[TB * CJ];
   const int f = blockIdx.y;
   const int nb = L.nb[f];
   const int bi0 = blockIdx.x * TB;
@@ -431,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
       if (m < Kf && t < n) {
         finite &= isfinite(c[i].x) && isfinite(c[i].y);
         if (keep) cdst[m * cd + s0 + t] = c[i];
-        T *cl = Cs + (m * TB + j) * CR + 2 * t;
+        T *cl = Cs + j * CJ + (t * G + m) * 2;
         cl[0] = c[i].x;
         cl[1] = c[i].y;
       }
@@ -447,8 +453,8 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
 #pragma unroll
           for (int e = 0; e < 8; ++e) ev = fma(vv[e], vv[e], ev);   // sum_s ||V_s||^2
         }
-        const T *ct = Cs + j * CR + 2 * t;         // direction m's value at ct[m * TB * CR]
-        const double cr = (double)ct[l * TB * CR], ci = (double)ct[l * TB * CR + 1];
+        const T *ct = Cs + j * CJ + t * G * 2;     // direction m's value at ct[2 m]
+        const double cr = (double)ct[2 * l], ci = (double)ct[2 * l + 1];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           u[2 * e] = fma(cr, vv[2 * e], fma(ci, vv[2 * e + 1], u[2 * e]));
@@ -458,7 +464,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
         for (int d = 0; d < kD; ++d) {
           if (d <= dmax) {                         // uniform over the workgroup
             const int m = l + d < Kf ? l + d : l + d - Kf;
-            const double mr = (double)ct[m * TB * CR], mi = (double)ct[m * TB * CR + 1];
+            const double mr = (double)ct[2 * m], mi = (double)ct[2 * m + 1];
             x[2 * d] = fma(cr, mr, fma(ci, mi, x[2 * d]));
             x[2 * d + 1] = fma(cr, mi, fma(-ci, mr, x[2 * d + 1]));
           }
