@@ -254,8 +254,14 @@ hipError_t launch_dall(const Problem &pb, const Layout &L, const Buffers &B, hip
   const dim3 grid(pb.ntiles), block(kDallThreads);
   if (pb.K <= 4)
     hipLaunchKernelGGL((k_dall<kEnergy, 4>), grid, block, 0, s, pb, L, B);
+  else if (pb.K <= 5)
+    hipLaunchKernelGGL((k_dall<kEnergy, 5>), grid, block, 0, s, pb, L, B);
+  else if (pb.K <= 6)
+    hipLaunchKernelGGL((k_dall<kEnergy, 6>), grid, block, 0, s, pb, L, B);
   else if (pb.K <= 8)
     hipLaunchKernelGGL((k_dall<kEnergy, 8>), grid, block, 0, s, pb, L, B);
+  else if (pb.K <= 10)
+    hipLaunchKernelGGL((k_dall<kEnergy, 10>), grid, block, 0, s, pb, L, B);
   else if (pb.K <= 12)
     hipLaunchKernelGGL((k_dall<kEnergy, 12>), grid, block, 0, s, pb, L, B);
   else
