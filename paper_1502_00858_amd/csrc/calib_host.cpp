@@ -301,9 +301,13 @@ calib_status local_step_stopping_on(calib_ctx *c, int admm_iter, hipStream_t s) 
 // the device iteration counter, which the last kernel advances
 calib_status consensus_on(calib_ctx *c, bool gpa, hipStream_t s) {
   HIPCHK(c, timed(c, CALIB_KERNEL_CONSENSUS, [&] {
-    hipError_t e = launch_penalty_part(c->pb, c->L, c->B, s);
-    if (e == hipSuccess && gpa) e = launch_gpa(c->pb, c->L, c->B, 3, s);
-    if (e == hipSuccess) e = launch_consensus(c->pb, c->L, c->B, true, s);
+    hipError_t e = hipSuccess;
+    if (gpa) {   // the trace row's penalty at the local step's J, before the alignment rotates it
+      e = launch_penalty_part(c->pb, c->L, c->B, s);
+      if (e == hipSuccess) e = launch_gpa(c->pb, c->L, c->B, 3, s);
+    }
+    if (e == hipSuccess)
+      e = launch_consensus(c->pb, c->L, c->B, gpa ? kPenaltyTaken : kPenaltyInYUpdate, s);
     return e;
   }));
   return CALIB_OK;
@@ -567,7 +571,7 @@ calib_status calib_init(const calib_config *cfg, const void *vis, const void *co
   DALLOC(basis, (size_t)P * Q * 8);
   DALLOC(fitw, (size_t)K * Q * P * 8);
   DALLOC(B.trace, (size_t)kMaxTrace * 4 * 8);
-  DALLOC(B.scratch, ((size_t)P * K + (size_t)K * kZChunks + 2 * P) * 8);   // residual partials, then cost/penalty per subband
+  DALLOC(B.scratch, (2 * (size_t)P * K + (size_t)K * kZChunks + P) * 8);   // residual partials, then the trace row's cost and penalty partials
   DALLOC(B.iter, sizeof(int));
   B.chol_fail = nullptr;
   B.chol_ld = nullptr;

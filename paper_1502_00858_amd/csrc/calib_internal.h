@@ -108,7 +108,7 @@ struct Buffers {
   const double *basis;                  // [P][Q] b_l(f)
   const double *fitw;                   // [K][Q][P] least-squares operator per direction
   double *trace;                        // [iters][4]
-  double *scratch;                      // [P*K + K*kZChunks] residual partials, [2P] cost/penalty partials
+  double *scratch;                      // [P*K + K*kZChunks] residual partials, [P] cost, [P*K] penalty partials
   int *iter;                            // ADMM iteration whose trace row is being written
   int *chol_fail;                       // [P] blocked solver: a pivot failed in this solve
   double *chol_ld;                      // [P][panels][64*64] blocked solver: diagonal blocks' L
@@ -186,11 +186,14 @@ hipError_t launch_dir_reset(const Problem &pb, const Buffers &B, hipStream_t s);
 hipError_t launch_basis_setup(const Problem &pb, const double *freq, double f0, const int32_t *ndir,
                               double *basis, double *fitw, int *rank_fail, hipStream_t s);
 hipError_t launch_set_iter(const Buffers &B, int iter, hipStream_t s);
-// per-subband data cost and penalty partials of the trace row, taken before the alignment and the
-// Y update; launch_consensus(with_penalty) folds them into the row
+// the trace row's data cost and penalty partials (per subband, per subband and direction), taken
+// before the alignment on its iteration; launch_consensus(kPenaltyTaken) folds them into the row,
+// launch_consensus(kPenaltyInYUpdate) takes them in the Y update, kPenaltyNone leaves the row's
+// cost and Lagrangian unwritten
 hipError_t launch_penalty_part(const Problem &pb, const Layout &L, const Buffers &B, hipStream_t s);
+constexpr int kPenaltyNone = 0, kPenaltyTaken = 1, kPenaltyInYUpdate = 2;
 hipError_t launch_gpa(const Problem &pb, const Layout &L, const Buffers &B, int rounds, hipStream_t s);
-hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, bool with_penalty,
+hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, int penalty,
                              hipStream_t s);
 hipError_t launch_subband_cost(const Problem &pb, const Layout &L, const Buffers &B, double *out,
                                hipStream_t s);

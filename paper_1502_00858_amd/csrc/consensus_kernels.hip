@@ -9,7 +9,8 @@
 //   gpa         : first-iteration alignment of the unitary ambiguity (Section 3,
 //                 initialisation): generalised Procrustes to the mean over subbands.
 //   z_fit       : Z_k per direction and the dual-residual partials.
-//   y_update    : B_f Z_k, Y_fk += rho_k (J_fk - B_f Z_k) (minimisation M3) and primal partials.
+//   y_update    : B_f Z_k, Y_fk += rho_k (J_fk - B_f Z_k) (minimisation M3) and primal partials
+//                 (and, except on the alignment's iteration, the trace row's penalty partials).
 //   residuals   : primal and dual residuals of Section 4.1 averaged over (f, k) and k, and the
 //                 trace row's data cost and augmented Lagrangian.
 #include "calib_internal.h"
@@ -90,27 +91,41 @@ __global__ void k_basis_setup(int P, int Q, int K, const double *freq, double f0
   }
 }
 
-// data cost sum_f g_f (from the tile partials of the final residual) and the augmented
-// Lagrangian sum_f [g_f + sum_k Re tr(Y^H (J - BZ)) + rho_k/2 ||J - BZ||^2]
-// Data cost and augmented Lagrangian for the trace row: per-subband partials (one workgroup per
-// subband), then one workgroup adds them in subband order (run-to-run deterministic).
+// Trace row's data cost sum_f g_f (from the tile partials of the final residual) and augmented
+// Lagrangian sum_f [g_f + sum_k Re tr(Y^H (J - BZ)) + rho_k/2 ||J - BZ||^2]: per-subband cost and
+// per-(subband, direction) penalty partials, which k_residuals adds in a fixed order.  Taken here
+// when the first iteration's alignment runs between the local step and the Y update; otherwise
+// k_y_update takes them from the J, Y and B_f Z it reads anyway.
+__device__ inline double *cost_partials(const Problem &pb, const Buffers &B) {
+  return B.scratch + (int64_t)pb.P * pb.K + (int64_t)pb.K * kZChunks;
+}
+__device__ inline double *penalty_partials(const Problem &pb, const Buffers &B) {
+  return cost_partials(pb, B) + pb.P;
+}
+
+__device__ inline double subband_cost_sum(const Layout &L, const Buffers &B, int f) {
+  double v = 0.0;
+  for (int t = L.tile_off[f] + threadIdx.x; t < L.tile_off[f + 1]; t += kBlock) v += B.cost_part[t];
+  return v;
+}
+
+// one workgroup per subband
 __global__ __launch_bounds__(kBlock) void k_penalty_part(Problem pb, Layout L, Buffers B) {
-  __shared__ double red[2][kBlock / 64];
-  const int f = blockIdx.x;
-  double v[2] = {0.0, 0.0};
-  for (int t = L.tile_off[f] + threadIdx.x; t < L.tile_off[f + 1]; t += kBlock) v[0] += B.cost_part[t];
-  const int n8 = 8 * pb.N;
-  const int64_t o = (int64_t)f * pb.K * n8;
-  for (int e = threadIdx.x; e < L.ndir[f] * n8; e += kBlock) {   // the directions f carries
-    const int k = e / n8;
-    const double d = B.J[o + e] - B.BZ[o + e];
-    v[1] += B.Y[o + e] * d + 0.5 * B.rho[k] * d * d;
-  }
-  block_sum_vec<2>(v, red);
-  if (threadIdx.x == 0) {
-    double *part = B.scratch + (int64_t)pb.P * pb.K + (int64_t)pb.K * kZChunks;
-    part[2 * f] = v[0];
-    part[2 * f + 1] = v[1];
+  __shared__ double red[1][kBlock / 64];
+  const int f = blockIdx.x, n8 = 8 * pb.N, Kf = L.ndir[f];
+  double v[1] = {subband_cost_sum(L, B, f)};
+  block_sum_vec<1>(v, red);
+  if (threadIdx.x == 0) cost_partials(pb, B)[f] = v[0];
+  for (int k = 0; k < pb.K; ++k) {   // the directions f carries; zero for the others
+    const int64_t o = ((int64_t)f * pb.K + k) * n8;
+    double pen[1] = {0.0};
+    if (k < Kf)
+      for (int e = threadIdx.x; e < n8; e += kBlock) {
+        const double d = B.J[o + e] - B.BZ[o + e];
+        pen[0] += B.Y[o + e] * d + 0.5 * B.rho[k] * d * d;
+      }
+    block_sum_vec<1>(pen, red);
+    if (threadIdx.x == 0) penalty_partials(pb, B)[(int64_t)f * pb.K + k] = pen[0];
   }
 }
 
@@ -258,40 +273,58 @@ __global__ __launch_bounds__(64) void k_z_fit(Problem pb, Layout L, Buffers B) {
   if (t == 0) *dz_out = dz;
 }
 
-// grid (P, K): B_f Z_k, dual ascent, primal partial ||J - BZ||^2
-__global__ __launch_bounds__(kBlock) void k_y_update(Problem pb, Layout L, Buffers B) {
-  __shared__ double red[1][kBlock / 64];
+// grid (P, K): B_f Z_k, dual ascent, primal partial ||J - BZ||^2; with with_penalty also the
+// trace row's partials of k_penalty_part, from J and the old Y and B_f Z before they are replaced
+__global__ __launch_bounds__(kBlock) void k_y_update(Problem pb, Layout L, Buffers B, int with_penalty) {
+  __shared__ double red[3][kBlock / 64];
   if (B.rank_fail && *B.rank_fail) return;
   const int f = blockIdx.x, k = blockIdx.y, N = pb.N, Q = pb.Q;
   const int64_t slot = (int64_t)f * pb.K + k;
+  if (with_penalty && k == 0) {   // every subband carries direction 0
+    double v[1] = {subband_cost_sum(L, B, f)};
+    block_sum_vec<1>(v, red);
+    if (threadIdx.x == 0) cost_partials(pb, B)[f] = v[0];
+  }
   if (k >= L.ndir[f]) {
-    if (threadIdx.x == 0) B.scratch[slot] = -1.0;
+    if (threadIdx.x == 0) {
+      B.scratch[slot] = -1.0;
+      if (with_penalty) penalty_partials(pb, B)[slot] = 0.0;
+    }
     return;
   }
   const double rho = B.rho[k];
   double bf[8];   // the subband's basis row, read once (the stores below could alias it)
 #pragma unroll
   for (int l = 0; l < 8; ++l) bf[l] = l < Q ? B.basis[f * Q + l] : 0.0;
-  double pr = 0.0;
+  double pr = 0.0, pen = 0.0;
   for (int e = threadIdx.x; e < 8 * N; e += kBlock) {
     double bz = 0.0;
 #pragma unroll
     for (int l = 0; l < 8; ++l)
       if (l < Q) bz += bf[l] * B.Z[((int64_t)k * Q + l) * N * 8 + e];
     const int64_t o = slot * N * 8 + e;
+    const double j = B.J[o], y = B.Y[o];
+    if (with_penalty) {
+      const double d = j - B.BZ[o];
+      pen += y * d + 0.5 * rho * d * d;
+    }
     B.BZ[o] = bz;
-    const double t = B.J[o] - bz;
-    B.Y[o] += rho * t;
+    const double t = j - bz;
+    B.Y[o] = y + rho * t;
     pr += t * t;
   }
-  double v[1] = {pr};
-  block_sum_vec<1>(v, red);
-  if (threadIdx.x == 0) B.scratch[slot] = v[0];
+  double v[2] = {pr, pen};
+  block_sum_vec<2>(v, red);
+  if (threadIdx.x == 0) {
+    B.scratch[slot] = v[0];
+    if (with_penalty) penalty_partials(pb, B)[slot] = v[1];
+  }
 }
 
 // Trace row of the current iteration: primal and dual residual norms from the per-(subband,
 // direction) and per-direction partials, and (with_penalty) the data cost and augmented Lagrangian
-// from the per-subband partials of k_penalty_part; 64 threads take strided shares, summed in a
+// from the per-subband cost and per-(subband, direction) penalty partials; 64 threads take strided
+// shares, summed in a
 // fixed order. Advances the iteration counter, so that a replayed graph writes the next row.
 __global__ __launch_bounds__(64) void k_residuals(Problem pb, Buffers B, int with_penalty) {
   __shared__ double sps[64];
@@ -299,12 +332,10 @@ __global__ __launch_bounds__(64) void k_residuals(Problem pb, Buffers B, int wit
   __shared__ int spc[64];
   const int t = threadIdx.x;
   if (with_penalty) {
-    const double *part = B.scratch + (int64_t)pb.P * pb.K + (int64_t)pb.K * kZChunks;
+    const double *cost = cost_partials(pb, B), *pen = penalty_partials(pb, B);
     double g = 0.0, a = 0.0;
-    for (int f = t; f < pb.P; f += 64) {
-      g += part[2 * f];
-      a += part[2 * f + 1];
-    }
+    for (int f = t; f < pb.P; f += 64) g += cost[f];
+    for (int64_t i = t; i < (int64_t)pb.P * pb.K; i += 64) a += pen[i];
     spen[0][t] = g;
     spen[1][t] = a;
     __syncthreads();
@@ -408,16 +439,17 @@ hipError_t launch_gpa(const Problem &pb, const Layout &L, const Buffers &B, int 
   return hipGetLastError();
 }
 
-hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, bool with_penalty,
+hipError_t launch_consensus(const Problem &pb, const Layout &L, const Buffers &B, int penalty,
                              hipStream_t s) {
   if (pb.N > kMaxStations) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_z_fit, dim3(pb.K, kZChunks), dim3(64), 0, s, pb, L, B);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_y_update, dim3(pb.P, pb.K), dim3(kBlock), 0, s, pb, L, B);
+  hipLaunchKernelGGL(k_y_update, dim3(pb.P, pb.K), dim3(kBlock), 0, s, pb, L, B,
+                     penalty == kPenaltyInYUpdate ? 1 : 0);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_residuals, dim3(1), dim3(64), 0, s, pb, B, with_penalty ? 1 : 0);
+  hipLaunchKernelGGL(k_residuals, dim3(1), dim3(64), 0, s, pb, B, penalty != kPenaltyNone ? 1 : 0);
   return hipGetLastError();
 }
 

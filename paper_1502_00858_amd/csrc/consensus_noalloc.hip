@@ -131,7 +131,7 @@ extern "C" calib_status calib_consensus_noalloc(int32_t n_stations, int32_t n_su
   hipLaunchKernelGGL(k_noalloc_begin, dim3(blocks), dim3(threads), 0, s, ints, n_dirs, P, K);
   e = hipGetLastError();
   if (e == hipSuccess) e = launch_basis_setup(pb, freq_hz, f0_hz, ndir, basis, fitw, rank_fail, s);
-  if (e == hipSuccess) e = launch_consensus(pb, L, B, false, s);
+  if (e == hipSuccess) e = launch_consensus(pb, L, B, kPenaltyNone, s);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_noalloc_end, dim3(1), dim3(64), 0, s, trace, rank_fail, residuals, status);
     e = hipGetLastError();
