@@ -201,12 +201,13 @@ __global__ __launch_bounds__(kBlock) void k_gpa(Problem pb, Layout L, Buffers B,
 }
 
 // grid (K, kZChunks) of one wavefront each: Z_k = W_k (J + Y/rho) for 64 of the direction's 8N
-// real Jones parameters (N <= 128), one per lane, the subbands taken in order. Per block of 64
-// subbands the block's fit weights go to LDS with one coalesced load per basis term and the
-// subbands carrying the direction to a wave-uniform bit mask (per-subband scalar loads would
-// each wait on their own); then sixteen subbands' J and Y are requested before the first is used.
-// The chunk's part of ||Z_new - Z_old||^2 goes to the dual-residual partials (chunks past 8N
-// write zero).
+// real Jones parameters (N <= 128), one per lane, the subbands taken in order in batches of kF.
+// Per block of 64 subbands the block's fit weights go to LDS with one coalesced load per basis
+// term and the subbands carrying the direction to a wave-uniform bit mask (per-subband scalar loads
+// would each wait on their own).  The next batch's J and Y are requested before the current one
+// is summed, and the old Z before anything (the workgroup is one wavefront, whose LDS accesses
+// are ordered without a barrier that would wait for those loads).  The chunk's part of
+// ||Z_new - Z_old||^2 goes to the dual-residual partials (chunks past 8N write zero).
 __global__ __launch_bounds__(64) void k_z_fit(Problem pb, Layout L, Buffers B) {
   __shared__ __align__(16) double sw[64][8];   // [subband of the block][basis term]
   if (B.rank_fail && *B.rank_fail) return;
@@ -218,45 +219,59 @@ __global__ __launch_bounds__(64) void k_z_fit(Problem pb, Layout L, Buffers B) {
   }
   const int e = c * 64 + t;
   const bool live = e < 8 * N;
+  const int ec = min(e, 8 * N - 1);   // lanes past 8N load in bounds and store nothing
   const double rho = B.rho[k];
   const double *W = B.fitw + (int64_t)k * Q * P;
   constexpr int kF = 16;
   static_assert(64 % kF == 0, "a batch of subbands stays inside its block");
-  double z[8];
+  double zo[8], z[8];
 #pragma unroll
-  for (int l = 0; l < 8; ++l) z[l] = 0.0;
-  for (int fb = 0; fb < P; fb += 64) {
-    const int fl = fb + t, fc = min(fl, P - 1);
-    const bool carried = fl < P && L.ndir[fc] > k;
-    double wl[8];
+  for (int l = 0; l < 8; ++l) {
+    zo[l] = B.Z[((int64_t)k * Q + min(l, Q - 1)) * N * 8 + ec];
+    z[l] = 0.0;
+  }
+  auto fetch = [&](int b, double *jj, double *yy) {
 #pragma unroll
-    for (int l = 0; l < 8; ++l) {   // every load issued before the first is used; terms past Q
-      const double w = W[min(l, Q - 1) * P + fc];   // repeat the last one and are never stored
-      wl[l] = carried ? w : 0.0;
+    for (int u = 0; u < kF; ++u) {
+      const int64_t o = ((int64_t)min(b * kF + u, P - 1) * pb.K + k) * N * 8 + ec;
+      jj[u] = B.J[o];
+      yy[u] = B.Y[o];
     }
-    __syncthreads();   // the previous block's weights have been read
+  };
+  const int nbatch = (P + kF - 1) / kF;
+  double jv[kF], yv[kF], jn[kF], yn[kF];
+  uint64_t mask = 0;
+  fetch(0, jv, yv);
+  for (int b = 0; b < nbatch; ++b) {
+    const int fb = (b * kF) & ~63, f0 = b * kF - fb;
+    if (f0 == 0) {   // a new block of 64 subbands: its weights and carrying mask
+      const int fl = fb + t, fc = min(fl, P - 1);
+      const bool carried = fl < P && L.ndir[fc] > k;
+      double wl[8];
 #pragma unroll
-    for (int l = 0; l < 8; ++l) sw[t][l] = wl[l];
-    const uint64_t mask = __ballot(carried);
-    __syncthreads();
-    const int nf = min(64, P - fb);
-    if (!live) continue;
-    for (int f0 = 0; f0 < nf; f0 += kF) {
-      double jv[kF], yv[kF];
-#pragma unroll
-      for (int u = 0; u < kF; ++u) {
-        const int64_t o = ((int64_t)min(fb + f0 + u, P - 1) * pb.K + k) * N * 8 + e;
-        jv[u] = B.J[o];
-        yv[u] = B.Y[o];
+      for (int l = 0; l < 8; ++l) {   // terms past Q repeat the last one and are never stored
+        const double w = W[min(l, Q - 1) * P + fc];
+        wl[l] = carried ? w : 0.0;
       }
+      wave_lds_sync();   // the previous block's weights have been read
 #pragma unroll
-      for (int u = 0; u < kF; ++u) {   // f0 + u < 64: kF divides 64
-        const int f = f0 + u;
-        const double x0 = (rho > 0.0) ? jv[u] + yv[u] / rho : jv[u];
-        const double x = ((mask >> f) & 1) ? x0 : 0.0;   // past the last subband or not carrying k
+      for (int l = 0; l < 8; ++l) sw[t][l] = wl[l];
+      mask = __ballot(carried);
+      wave_lds_sync();
+    }
+    if (b + 1 < nbatch) fetch(b + 1, jn, yn);
 #pragma unroll
-        for (int l = 0; l < 8; ++l) z[l] += sw[f][l] * x;
-      }
+    for (int u = 0; u < kF; ++u) {   // f0 + u < 64: kF divides 64
+      const int f = f0 + u;
+      const double x0 = (rho > 0.0) ? jv[u] + yv[u] / rho : jv[u];
+      const double x = ((mask >> f) & 1) ? x0 : 0.0;   // past the last subband or not carrying k
+#pragma unroll
+      for (int l = 0; l < 8; ++l) z[l] += sw[f][l] * x;
+    }
+#pragma unroll
+    for (int u = 0; u < kF; ++u) {
+      jv[u] = jn[u];
+      yv[u] = yn[u];
     }
   }
   double dz = 0.0;
@@ -264,10 +279,9 @@ __global__ __launch_bounds__(64) void k_z_fit(Problem pb, Layout L, Buffers B) {
 #pragma unroll
     for (int l = 0; l < 8; ++l)
       if (l < Q) {
-        const int64_t o = ((int64_t)k * Q + l) * N * 8 + e;
-        const double d = z[l] - B.Z[o];
+        const double d = z[l] - zo[l];
         dz += d * d;
-        B.Z[o] = z[l];
+        B.Z[((int64_t)k * Q + l) * N * 8 + e] = z[l];
       }
   dz = wave_sum(dz);
   if (t == 0) *dz_out = dz;
@@ -327,62 +341,59 @@ __global__ __launch_bounds__(kBlock) void k_y_update(Problem pb, Layout L, Buffe
 // shares, summed in a
 // fixed order. Advances the iteration counter, so that a replayed graph writes the next row.
 __global__ __launch_bounds__(64) void k_residuals(Problem pb, Buffers B, int with_penalty) {
-  __shared__ double sps[64];
-  __shared__ double spen[2][64];
+  __shared__ double sg[64], sa[64], sps[64], sdz[kMaxDirs];
   __shared__ int spc[64];
   const int t = threadIdx.x;
+  const int64_t PK = (int64_t)pb.P * pb.K;
+  double g = 0.0, a = 0.0;
   if (with_penalty) {
     const double *cost = cost_partials(pb, B), *pen = penalty_partials(pb, B);
-    double g = 0.0, a = 0.0;
     for (int f = t; f < pb.P; f += 64) g += cost[f];
-    for (int64_t i = t; i < (int64_t)pb.P * pb.K; i += 64) a += pen[i];
-    spen[0][t] = g;
-    spen[1][t] = a;
-    __syncthreads();
-    if (t == 0) {
-      g = 0.0;
-      a = 0.0;
-      for (int i = 0; i < 64; ++i) {
-        g += spen[0][i];
-        a += spen[1][i];
-      }
-      const int iter = B.iter[0];
-      B.trace[4 * iter] = g;
-      B.trace[4 * iter + 1] = g + a;
-    }
+    for (int64_t i = t; i < PK; i += 64) a += pen[i];
   }
-  if (B.rank_fail && *B.rank_fail) return;
   double ps = 0.0;
   int pc = 0;
   const double pn = sqrt(4.0 * pb.N);
-  for (int64_t i = t; i < (int64_t)pb.P * pb.K; i += 64) {
+  for (int64_t i = t; i < PK; i += 64) {
     const double x = B.scratch[i];
     if (x >= 0.0) {
       ps += sqrt(x) / pn;
       ++pc;
     }
   }
+  if (t < pb.K) {   // direction t's dual-residual partials, in chunk order
+    double dz = 0.0;
+    for (int c = 0; c < kZChunks; ++c) dz += B.scratch[PK + (int64_t)t * kZChunks + c];
+    sdz[t] = sqrt(dz) / sqrt(4.0 * pb.Q * pb.N);
+  }
+  sg[t] = g;
+  sa[t] = a;
   sps[t] = ps;
   spc[t] = pc;
   __syncthreads();
   if (t != 0) return;
+  const int iter = B.iter[0];
+  if (with_penalty) {
+    g = 0.0;
+    a = 0.0;
+    for (int i = 0; i < 64; ++i) {
+      g += sg[i];
+      a += sa[i];
+    }
+    B.trace[4 * iter] = g;
+    B.trace[4 * iter + 1] = g + a;
+  }
+  if (B.rank_fail && *B.rank_fail) return;
   ps = 0.0;
   pc = 0;
   for (int i = 0; i < 64; ++i) {
     ps += sps[i];
     pc += spc[i];
   }
-  const int iter = B.iter[0];
   double ds = 0.0;
-  int dc = 0;
-  for (int k = 0; k < pb.K; ++k) {
-    double dz = 0.0;
-    for (int c = 0; c < kZChunks; ++c) dz += B.scratch[(int64_t)pb.P * pb.K + (int64_t)k * kZChunks + c];
-    ds += sqrt(dz) / sqrt(4.0 * pb.Q * pb.N);
-    ++dc;
-  }
+  for (int k = 0; k < pb.K; ++k) ds += sdz[k];
   B.trace[4 * iter + 2] = pc ? ps / pc : 0.0;
-  B.trace[4 * iter + 3] = dc ? ds / dc : 0.0;
+  B.trace[4 * iter + 3] = pb.K ? ds / pb.K : 0.0;
   B.iter[0] = iter + 1;
 }
 

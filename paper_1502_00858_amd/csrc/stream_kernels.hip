@@ -350,14 +350,6 @@ struct Cplx<float> { using type = float2; };
 template <>
 struct Cplx<double> { using type = double2; };
 
-// ordering of LDS writes and reads among the lanes of one wavefront (in-order within a wavefront;
-// the fences keep the compiler from moving accesses across)
-__device__ inline void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <typename T, int G>
 __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buffers B, const T *vis,
                                                        const T *coh, T *Vp, T *Cp, double *Sb,

@@ -7,6 +7,15 @@
 #include <hip/hip_runtime.h>
 
 namespace calib {
+
+// ordering of LDS writes and reads among the lanes of one wavefront (in-order within a wavefront;
+// the fences keep the compiler from moving accesses across); unlike a workgroup barrier it does
+// not wait for the wavefront's outstanding global loads
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 namespace wred {
 
 template <int CTRL>
