@@ -62,8 +62,8 @@ MEASURED_TRAFFIC = {
         ("paper_1502_00858_amd/csrc/pcg_kernel.hip", "paper_1502_00858_amd/csrc/lm_device.h",
          "paper_1502_00858_amd/csrc/calib_internal.h", "paper_1502_00858_amd/csrc/wave_reduce.h",
          "paper_1502_00858_amd/csrc/calib_host.cpp"),
-        "dbe15939b19eb39585f40e0b4e1bf8668c2c1620d6378fcc9e4b5bda7bd530f0",
-        (64.95 + 84.40) * 1e6),
+        "20367c5b123922c41c7535018d9d94100e69524e5284fbd87c0a7314abc01324",
+        (63.47 + 86.80) * 1e6),
 }
 
 
