@@ -23,6 +23,8 @@
 // consecutive lanes read consecutive 32-byte (float) or 64-byte (double) samples; the per-tile
 // energy is reduced into one FP64 partial per tile, summed later in a fixed order (run-to-run
 // deterministic).  The per-baseline kernels run one wavefront per tile, one lane per baseline.
+#include <type_traits>
+
 #include "calib_internal.h"
 #include "lm_device.h"
 #include "wave_reduce.h"
@@ -360,16 +362,19 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
   using C2 = typename Cplx<T>::type;
   constexpr int TB = kBlock / G;                   // baselines per workgroup
   constexpr int SC = 32 / (int)sizeof(T);          // samples per chunk
-  constexpr int PAD = 16 / (int)sizeof(T);
-  constexpr int VR = SC * 8 + PAD;                 // padded LDS row of V (elements)
+  // LDS element: the 16-lane groups (up to 16 directions, K_f/2 + 1 coherency products per sample
+  // and lane) keep their rows in FP64, converted once when staged rather than at every read; the
+  // 8-lane groups keep the input type (FP64 rows would halve their occupancy)
+  using LT = typename std::conditional<G == 16, double, T>::type;
+  constexpr int VR = SC * 8 + 16 / (int)sizeof(LT);   // padded LDS row of V (elements)
   // a baseline's chunk of coherencies, [sample][direction] (lanes reading different directions at
   // one sample hit consecutive banks), padded by 128 bytes between the group's baselines
-  constexpr int CJ = SC * G * 2 + 128 / (int)sizeof(T);
+  constexpr int CJ = SC * G * 2 + 128 / (int)sizeof(LT);
   constexpr int NV = 4 * SC / G;                   // V values per lane per chunk
   constexpr int NC = SC;                           // coherency values per lane per chunk (G*SC >= K_f*SC)
   static_assert(NV >= 1 && 4 * SC == NV * G, "chunk of V split evenly over the group");
-  __shared__ __align__(16) T Vs[TB * VR];
-  __shared__ __align__(16) T Cs[TB * CJ];
+  __shared__ __align__(16) LT Vs[TB * VR];
+  __shared__ __align__(16) LT Cs[TB * CJ];
   const int f = blockIdx.y;
   const int nb = L.nb[f];
   const int bi0 = blockIdx.x * TB;
@@ -390,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
   C2 *vdst = keep ? reinterpret_cast<C2 *>(Vp + 8 * (L.samp_off[f] + (int64_t)bi * spb)) : nullptr;
   C2 *cdst = keep ? reinterpret_cast<C2 *>(Cp + 2 * (L.coh_off[f] + (int64_t)bi * spb)) : nullptr;
   const int64_t cs = Bfull * spb, cd = (int64_t)nb * spb;   // between directions (complex values)
-  T *vl = Vs + j * VR;
+  LT *vl = Vs + j * VR;
   // X is Hermitian (X_ml = conj X_lm): lane l sums X_lm for m = (l + d) mod K_f at distances
   // d = 0 .. K_f/2 (at d = K_f/2 for even K_f only lanes l < K_f/2), so every pair is summed once
   constexpr int kD = G / 2 + 1;
@@ -425,8 +430,8 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
       if (e < 4 * n) {
         finite &= isfinite(v[i].x) && isfinite(v[i].y);
         if (keep) vdst[4 * s0 + e] = v[i];
-        vl[2 * e] = v[i].x;
-        vl[2 * e + 1] = v[i].y;
+        vl[2 * e] = (LT)v[i].x;
+        vl[2 * e + 1] = (LT)v[i].y;
       }
     }
 #pragma unroll
@@ -435,9 +440,9 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
       if (m < Kf && t < n) {
         finite &= isfinite(c[i].x) && isfinite(c[i].y);
         if (keep) cdst[m * cd + s0 + t] = c[i];
-        T *cl = Cs + j * CJ + (t * G + m) * 2;
-        cl[0] = c[i].x;
-        cl[1] = c[i].y;
+        LT *cl = Cs + j * CJ + (t * G + m) * 2;
+        cl[0] = (LT)c[i].x;
+        cl[1] = (LT)c[i].y;
       }
     }
     wave_lds_sync();
@@ -451,7 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_stats(Problem pb, Layout L, Buf
 #pragma unroll
           for (int e = 0; e < 8; ++e) ev = fma(vv[e], vv[e], ev);   // sum_s ||V_s||^2
         }
-        const T *ct = Cs + j * CJ + t * G * 2;     // direction m's value at ct[2 m]
+        const LT *ct = Cs + j * CJ + t * G * 2;    // direction m's value at ct[2 m]
         const double cr = (double)ct[2 * l], ci = (double)ct[2 * l + 1];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
