@@ -24,22 +24,28 @@ namespace calib {
 namespace {
 
 
+// One wavefront per row (f, k, p), four rows per workgroup: the lanes stride over station p's
+// baselines (at most N - 1 <= 127) for Q_p and the data gradient G_p, a wavefront sum leaves the
+// twelve sums in every lane, and lane e < 8 writes features e, 8 + e, 16 + e and 24 + e.
 __global__ __launch_bounds__(kBlock) void k_ws_features(Problem pb, Layout L, Buffers B,
                                                         const double *J2, const double *BZp,
                                                         float *feat) {
-  __shared__ double red[12][kBlock / 64];
-  const int f = blockIdx.x, p = blockIdx.y, k = blockIdx.z, N = pb.N;
-  const int64_t row = ((int64_t)f * pb.K + k) * N + p;
+  const int lane = threadIdx.x & 63, N = pb.N;
+  const int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  if (row >= (int64_t)pb.P * pb.K * N) return;   // uniform per wavefront
+  const int p = (int)(row % N);
+  const int64_t fk = row / N;
+  const int k = (int)(fk % pb.K), f = (int)(fk / pb.K);
   float *o = feat + row * kWsFeatures;
   if (k >= L.ndir[f]) {
-    if (threadIdx.x < kWsFeatures) o[threadIdx.x] = 0.f;
+    if (lane < kWsFeatures) o[lane] = 0.f;
     return;
   }
   const double *J = B.J + ((int64_t)f * pb.K + k) * N * 8;
   const int nb = L.nb[f];
   const double *Sb = B.Sb + L.sb_off[f] + (int64_t)k * nb - L.bl_off[f];
   double v[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int a = L.adj_off[f * N + p] + threadIdx.x; a < L.adj_off[f * N + p + 1]; a += kBlock) {
+  for (int a = L.adj_off[f * N + p] + lane; a < L.adj_off[f * N + p + 1]; a += 64) {
     const int gb = L.adj_b[a];
     const bool first = L.adj_o[a] >= 0;
     const int q = first ? L.adj_o[a] : -1 - L.adj_o[a];
@@ -65,42 +71,30 @@ __global__ __launch_bounds__(kBlock) void k_ws_features(Problem pb, Layout L, Bu
         v[4 + (i * 2 + j) * 2 + 1] += -2.0 * im;
       }
   }
-  const int w = threadIdx.x >> 6;
-  wave_sum_vec<12>(v);
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int i = 0; i < 12; ++i) red[i][w] = v[i];
-  }
-  __syncthreads();
-  if (threadIdx.x != 0) return;
-  double t[12];
-  for (int i = 0; i < 12; ++i) t[i] = red[i][0] + red[i][1] + red[i][2] + red[i][3];
-  const double q00 = t[0], q11 = t[1], qr = t[2], qi = t[3];
+  wave_sum_vec<12>(v);   // every lane holds the sums
+  if (lane >= 8) return;
+  const double q00 = v[0], q11 = v[1], qr = v[2], qi = v[3];
   const double det = q00 * q11 - (qr * qr + qi * qi);
   // Q^-1 = [[q11, -q01], [-conj(q01), q00]] / det
   double inv[8] = {q11, 0.0, -qr, -qi, -qr, qi, q00, 0.0};
   const double sc = (det > 0.0) ? 1.0 / det : 0.0;
   for (int e = 0; e < 8; ++e) inv[e] *= sc;
-  const double *G = t + 4;
+  const double *G = v + 4;
   const double *Jp = J + 8 * p;
   const double ws = kWsScale;
-  for (int e = 0; e < 8; ++e) {
-    o[e] = (float)Jp[e];
-    o[8 + e] = J2 ? (float)(ws * (Jp[e] - J2[row * 8 + e])) : 0.f;
-    o[24 + e] = BZp ? (float)(ws * (BZp[row * 8 + e] - Jp[e])) : 0.f;
+  const int e = lane;
+  o[e] = (float)Jp[e];
+  o[8 + e] = J2 ? (float)(ws * (Jp[e] - J2[row * 8 + e])) : 0.f;
+  o[24 + e] = BZp ? (float)(ws * (BZp[row * 8 + e] - Jp[e])) : 0.f;
+  const int i = e >> 2, j = (e >> 1) & 1;
+  double re = 0.0, im = 0.0;   // (G Q^-1)[i][j]
+  for (int m = 0; m < 2; ++m) {
+    const double gr = G[(i * 2 + m) * 2], gi = G[(i * 2 + m) * 2 + 1];
+    const double ir = inv[(m * 2 + j) * 2], ii = inv[(m * 2 + j) * 2 + 1];
+    re += gr * ir - gi * ii;
+    im += gr * ii + gi * ir;
   }
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) {
-      double re = 0.0, im = 0.0;   // (G Q^-1)[i][j]
-      for (int m = 0; m < 2; ++m) {
-        const double gr = G[(i * 2 + m) * 2], gi = G[(i * 2 + m) * 2 + 1];
-        const double ir = inv[(m * 2 + j) * 2], ii = inv[(m * 2 + j) * 2 + 1];
-        re += gr * ir - gi * ii;
-        im += gr * ii + gi * ir;
-      }
-      o[16 + (i * 2 + j) * 2] = (float)(-0.5 * ws * re);
-      o[16 + (i * 2 + j) * 2 + 1] = (float)(-0.5 * ws * im);
-    }
+  o[16 + e] = (float)(-0.5 * ws * ((e & 1) ? im : re));
 }
 
 // J <- J + delta / s for the directions each subband carries; the previous J is kept in Jsave
@@ -190,7 +184,10 @@ hipError_t launch_ws_target(const Problem &pb, const Layout &L, const Buffers &B
 
 hipError_t launch_ws_features(const Problem &pb, const Layout &L, const Buffers &B,
                               const double *J2, const double *BZp, float *feat, hipStream_t s) {
-  hipLaunchKernelGGL(k_ws_features, dim3(pb.P, pb.N, pb.K), dim3(kBlock), 0, s, pb, L, B, J2, BZp, feat);
+  const int64_t rows = (int64_t)pb.P * pb.K * pb.N, per = kBlock / 64;
+  if (rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ws_features, dim3((unsigned)((rows + per - 1) / per)), dim3(kBlock), 0, s, pb, L, B, J2,
+                     BZp, feat);
   return hipGetLastError();
 }
 
