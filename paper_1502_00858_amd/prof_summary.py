@@ -41,12 +41,7 @@ def _one(dirname: str, suffix: str) -> str:
 def trace(dirname: str, between: str | None = None):
     rows = list(csv.DictReader(open(_one(dirname, "kernel_trace.csv"))))
     if between:
-        marks = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows
-                       if between in r["Kernel_Name"])
-        if len(marks) < 2:
-            raise SystemExit(f"fewer than two dispatches of {between}")
-        lo, hi = marks[0][1], marks[1][0]
-        rows = [r for r in rows if int(r["Start_Timestamp"]) >= lo and int(r["End_Timestamp"]) <= hi]
+        rows, (lo, hi) = _window(rows, between, bounds=True)
         print(f"Window: {len(rows)} dispatches over {(hi - lo) / 1e6:.2f} ms between the first two "
               f"dispatches of {between}.\n")
     per = collections.defaultdict(list)
@@ -85,17 +80,19 @@ def trace(dirname: str, between: str | None = None):
               f"{sum(solves) / len(solves):.1f} us, median {solves[len(solves) // 2]:.1f} us")
 
 
-def _window(rows, between):
+def _window(rows, between, bounds=False):
     """The rows of dispatches that start after the first dispatch of a kernel named like `between`
-    ends and end before its second one starts (all rows when between is None)."""
+    ends and end before its second one starts (all rows when between is None); with bounds, also
+    the window's (start, end) timestamps."""
     if not between:
-        return rows
+        return (rows, None) if bounds else rows
     marks = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows
                    if between in r["Kernel_Name"])
     if len(marks) < 2:
         raise SystemExit(f"fewer than two dispatches of {between}")
     lo, hi = marks[0][1], marks[1][0]
-    return [r for r in rows if int(r["Start_Timestamp"]) >= lo and int(r["End_Timestamp"]) <= hi]
+    inside = [r for r in rows if int(r["Start_Timestamp"]) >= lo and int(r["End_Timestamp"]) <= hi]
+    return (inside, (lo, hi)) if bounds else inside
 
 
 def _pmc(dirname: str, between=None):
